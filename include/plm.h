@@ -1,0 +1,189 @@
+/*
+ * plm.h - C ABI of libplm: the local-moving sweep and the coarsening of the
+ * Parallel Louvain Method (PLM) for modularity-based community detection
+ * (Staudt & Meyerhenke, "Engineering Parallel Algorithms for Community
+ * Detection in Massive Networks", section III-B, Algorithms 2 and 3), on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * ---------------------------------------------------------------- graph input
+ * An undirected graph G = (V, E) with positive integer weights (section III
+ * opening paragraph takes real positive weights; this library takes integers so
+ * that every gain is exact) as a symmetric CSR:
+ *   offsets[n+1] int64, offsets[0] = 0, offsets[n] = nnz, non-decreasing;
+ *   cols[nnz]    int32, each row strictly ascending (so no duplicates);
+ *   weights[nnz] int32 > 0, or NULL for unit weights.
+ * Every non-loop edge {u,v} appears as (u,v,w) and (v,u,w) with equal w.  A
+ * self-loop is given once, as (u,u,w(u,u)); the library counts it twice in
+ * vol(u) as section III-B defines the node volume.
+ * n < 2^31.  The total weight S = sum of volumes = 2 w(E) must stay below 2^62.
+ *
+ * ---------------------------------------------------------------- schedule
+ * The paper moves nodes asynchronously in parallel (section III-B, discussion of
+ * Algorithm 3).  This library fixes the order so that every result is
+ * reproducible bit for bit:
+ *   - priority of node u at level l: (H(seed ^ (l << 40) ^ u), u), H = SplitMix64
+ *     (Steele, Lea & Flood 2014), compared lexicographically;
+ *   - colour of u = smallest colour not used by a higher-priority neighbour
+ *     (Jones-Plassmann = greedy colouring in descending priority);
+ *   - a sweep visits the colour classes in ascending order; all nodes of one
+ *     class decide against the community volumes at the start of the class and
+ *     their moves are applied together (classes are independent sets, so no
+ *     decision sees a neighbour's move within the class);
+ *   - node u in community D scores each neighbouring community X != D by
+ *       gain(X) = S (w(u,X) - w(u,D\u)) - vol(u) (vol(X) - vol(D\u)),
+ *     which is 2 w(E)^2 times the paper's Delta-mod (section III-B); it moves to
+ *     the highest gain if that gain is > 0, ties going to the lowest X;
+ *   - a level ends after a sweep with no move or after max_sweeps sweeps; the
+ *     run descends iff the number of communities dropped below the node count;
+ *     coarse node ids are the community ids in ascending order.
+ * Output labels are canonical: numbered by first occurrence in node order.
+ *
+ * ---------------------------------------------------------------- conventions
+ * Every call returns a plm_status (0 = OK, < 0 = error) and never throws.  On
+ * error, plm_last_error(ctx) describes it (plm_last_error(NULL) after a failed
+ * plm_create).  Pointers tagged mem_kind are host memory (PLM_MEM_HOST) or
+ * device memory of the current HIP device (PLM_MEM_DEVICE).  Device work runs
+ * on the stream given at plm_create (NULL = the null stream); every call
+ * returns after that work is complete.  A context is used by one host thread at
+ * a time; several contexts may share a device.
+ */
+#ifndef PLM_H
+#define PLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct plm_ctx plm_ctx;
+typedef int32_t plm_status;
+
+enum {
+    PLM_OK = 0,
+    PLM_E_ARG = -1,     /* bad argument or option */
+    PLM_E_GRAPH = -2,   /* input is not a valid symmetric CSR (validate = 1) */
+    PLM_E_NOMEM = -3,   /* device or host allocation failed */
+    PLM_E_DEVICE = -4,  /* a HIP call failed */
+    PLM_E_BUDGET = -5,  /* reserved for admission control */
+    PLM_E_STATE = -6    /* call not valid in the context's current state */
+};
+
+enum { PLM_MEM_HOST = 0, PLM_MEM_DEVICE = 1 };
+enum { PLM_SCHEDULE_COLOUR = 0, PLM_SCHEDULE_SEQUENTIAL = 1 };
+enum { PLM_INT_AUTO = 0, PLM_INT_64 = 1, PLM_INT_128 = 2 };
+
+typedef struct {
+    int32_t max_sweeps;   /* sweeps per level, >= 1; default 32 */
+    int32_t max_levels;   /* move phases per run; 0 = until no community merges */
+    int32_t schedule;     /* PLM_SCHEDULE_COLOUR (default) or PLM_SCHEDULE_SEQUENTIAL:
+                             one node per class in priority order, which is the
+                             sequential local moving of Blondel et al. */
+    int32_t validate;     /* 1 (default): check the CSR at plm_create */
+    uint64_t colour_seed; /* seed of the priority hash; default 0 */
+    int32_t int_mode;     /* PLM_INT_AUTO: 64-bit gains where S*vol(u) < 2^62, else
+                             128-bit; PLM_INT_128: always 128-bit (same results);
+                             PLM_INT_64: 64-bit only, PLM_E_STATE if unsafe */
+    int32_t bin_lane;     /* rows up to this length: one lane per node (0 = 16) */
+    int32_t bin_wave;     /* rows up to this length: one wavefront per node (0 = 512) */
+    int32_t bin_block;    /* rows up to this length: one workgroup per node, longer
+                             rows: several workgroups per node (0 = 4096) */
+    int32_t timing;       /* 1: time every move-decide launch with HIP events */
+    int32_t reserved[7];
+} plm_options;
+
+/* Fills *opt with the defaults above. */
+void plm_default_options(plm_options *opt);
+
+/* Creates a context holding a private copy of the graph (inputs may be freed
+ * as soon as the call returns) and the level-0 state: vol(u) (section III-B),
+ * singleton communities, colour classes.  offsets/cols/weights are host or
+ * device pointers per mem_kind.  hip_stream is a hipStream_t or NULL.
+ * opt NULL = defaults.  Errors: PLM_E_ARG (null pointers, n < 0, n >= 2^31,
+ * bad options), PLM_E_GRAPH (invalid CSR, checked when opt->validate),
+ * PLM_E_NOMEM, PLM_E_DEVICE.  On error *out is NULL. */
+plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                      const int32_t *weights, int32_t mem_kind, void *hip_stream, const plm_options *opt);
+
+/* One sweep of Algorithm 2 (move) over all colour classes of the current
+ * level; *moves_out = nodes moved.  Errors: PLM_E_STATE (int-mode overflow). */
+plm_status plm_move_sweep(plm_ctx *ctx, int64_t *moves_out);
+
+/* One class step of the current level (class c in [0, colours)). */
+plm_status plm_move_class(plm_ctx *ctx, int32_t c, int64_t *moves_out);
+
+/* Coarsening (section III-B, implementation): contracts each community of the
+ * current level into one node (inter-community weights summed, intra-community
+ * weight kept as a self-loop) and makes the coarse graph the current level with
+ * singleton communities.  *n_coarse_out = number of coarse nodes. */
+plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out);
+
+/* Full PLM (Algorithm 3) from level 0: move, coarsen while communities merge,
+ * prolong.  labels[n] (mem_kind of the context's input) receives canonical
+ * labels; *q_out their modularity; *levels_out the number of move phases.  Any
+ * output pointer may be NULL. */
+plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out);
+
+/* Modularity, Equation (3.1), of labels[n] (values in [0, n), host or device
+ * per mem_kind) on the input graph, computed as (S*I2 - sum vol(C)^2) / S^2
+ * with exact 128-bit numerator and denominator converted once to double and
+ * divided.  PLM_E_ARG for labels out of range. */
+plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind, double *q_out);
+
+/* Resets the context to level 0 with singleton communities. */
+plm_status plm_reset(plm_ctx *ctx);
+
+void plm_destroy(plm_ctx *ctx);
+
+/* Message of the last error on ctx (thread-local create error when ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char *plm_last_error(const plm_ctx *ctx);
+
+/* ---------------------------------------------------------------- inspection */
+typedef struct {
+    int32_t level;        /* current level, 0 = input graph */
+    int32_t colours;      /* colour classes of the current level (0 before built) */
+    int64_t n, nnz;       /* current level */
+    int64_t S;            /* total volume 2 w(E), level invariant */
+    int32_t sweeps;       /* sweeps done at the current level */
+    int32_t weight_kind;  /* 0 unit, 1 int32 (input level), 2 int64 (coarse) */
+    int64_t communities;  /* distinct communities at the current level */
+    int64_t max_vol;      /* largest node volume at the current level */
+} plm_level_info_t;
+
+plm_status plm_level_info(plm_ctx *ctx, plm_level_info_t *out);
+
+/* Copies the current level's community ids (int32[n]), community volumes
+ * (int64[n]) and colours (int32[n]); NULL skips an output. */
+plm_status plm_get_state(plm_ctx *ctx, int32_t *zeta, int64_t *volc, int32_t *colour, int32_t mem_kind);
+
+/* Copies the current level's CSR: offsets int64[n+1], cols int32[nnz] and
+ * weights int64[nnz] with every self-loop entry carrying twice the self-loop
+ * weight (so vol(u) is the row sum).  NULL skips an output. */
+plm_status plm_get_graph(plm_ctx *ctx, int64_t *offsets, int32_t *cols, int64_t *weights, int32_t mem_kind);
+
+/* Per-run counters of the last plm_run (or of the sweeps since plm_reset). */
+#define PLM_MAX_LEVELS 64
+typedef struct {
+    int32_t levels;
+    int32_t pad;
+    int64_t n[PLM_MAX_LEVELS], nnz[PLM_MAX_LEVELS], colours[PLM_MAX_LEVELS];
+    int64_t sweeps[PLM_MAX_LEVELS], communities[PLM_MAX_LEVELS];
+    int64_t moves[PLM_MAX_LEVELS];        /* summed over the level's sweeps */
+    double schedule_ms[PLM_MAX_LEVELS];   /* colouring + class bucketing (host clock) */
+    double sweep_ms[PLM_MAX_LEVELS];      /* all sweeps of the level (host clock) */
+    double coarsen_ms[PLM_MAX_LEVELS];    /* relabel + contraction (host clock) */
+    /* with opt.timing: device time of the move-decide launches (HIP events) and
+     * their count, and the algorithmic bytes those launches had to move. */
+    double decide_ms[PLM_MAX_LEVELS];
+    int64_t decide_launches[PLM_MAX_LEVELS];
+    double decide_bytes[PLM_MAX_LEVELS];
+} plm_stats_t;
+
+plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLM_H */

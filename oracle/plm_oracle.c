@@ -1,0 +1,479 @@
+/*
+ * plm_oracle.c - plain, slow, single-threaded reference of the Parallel Louvain
+ * Method (PLM) under a deterministic colour-class schedule.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline of the benchmark call it to check the GPU library; the library never
+ * links, loads or calls it, and the two share no code.
+ *
+ * What is computed (Staudt & Meyerhenke, "Engineering Parallel Algorithms for
+ * Community Detection in Massive Networks", section III-B):
+ *   - the graph is undirected with positive weights; node volume vol(u) is the
+ *     sum of incident weights with a self-loop counted twice (section III-B,
+ *     definition of vol).  Internally every self-loop entry therefore carries
+ *     twice its weight ("doubled diagonal"), so vol(u) is a plain row sum and
+ *     S = sum of all volumes = 2 w(E).
+ *   - modularity, Equation (3.1), written with integers:
+ *       mod = (S * I2 - sum_C vol(C)^2) / S^2,
+ *     I2 = sum of doubled-diagonal entries inside communities = 2 sum_C w(C).
+ *   - the gain of moving u from D = zeta(u) to a neighbouring community X is the
+ *     paper's Delta-mod (section III-B, the formula after Equation (3.1)) times
+ *     2 w(E)^2:
+ *       gain = S (w(u,X) - w(u,D\u)) - vol(u) (vol(X) - vol(D\u)),
+ *     computed exactly in 128-bit integers.
+ *   - move (Algorithm 2): u takes the best neighbouring community if the gain is
+ *     strictly positive; ties go to the lowest community id.
+ *   - PLM (Algorithm 3): singletons, move until stable, coarsen if the
+ *     partition changed, recurse on the coarse graph, prolong.
+ *   - coarsen (section III-B, implementation): one coarse node per community,
+ *     inter-community weights summed, intra-community weight kept as a
+ *     self-loop; prolongation composes the fine-to-coarse maps.
+ *
+ * Where the paper leaves the order of moves to asynchronous threads, this
+ * oracle fixes it: nodes are coloured greedily in descending priority
+ * (H(seed, level, u), u) with H = SplitMix64, which equals the Jones-Plassmann
+ * colouring; a sweep visits the colour classes in ascending order, and all nodes
+ * of one class decide against the community volumes at the start of the class
+ * (they are pairwise non-adjacent, so no decision sees another's move), then
+ * all their moves are applied.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __int128 i128;
+
+/* ------------------------------------------------------------------ hashing */
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): one step from state x. */
+uint64_t orc_splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Priority hash of node u at a level. */
+uint64_t orc_priority(uint64_t seed, int32_t level, int64_t u) {
+    return orc_splitmix64(seed ^ ((uint64_t)(uint32_t)level << 40) ^ (uint64_t)u);
+}
+
+/* ------------------------------------------------------------------ graph prep */
+/* w2[e] = w[e], doubled on the diagonal; w == NULL means unit weights. */
+void orc_double_diagonal(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, int64_t *w2) {
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            int64_t x = w ? w[e] : 1;
+            w2[e] = (col[e] == u) ? 2 * x : x;
+        }
+}
+
+/* vol[u] = row sum of the doubled-diagonal weights; returns S = sum vol. */
+int64_t orc_volumes(int64_t n, const int64_t *off, const int64_t *w2, int64_t *vol) {
+    int64_t S = 0;
+    for (int64_t u = 0; u < n; ++u) {
+        int64_t s = 0;
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) s += w2[e];
+        vol[u] = s;
+        S += s;
+    }
+    return S;
+}
+
+/* ------------------------------------------------------------------ colouring */
+typedef struct { uint64_t h; int64_t u; } orc_key;
+
+/* descending priority: larger hash first, equal hashes -> larger id first */
+static int orc_key_cmp(const void *a, const void *b) {
+    const orc_key *x = (const orc_key *)a, *y = (const orc_key *)b;
+    if (x->h != y->h) return x->h > y->h ? -1 : 1;
+    if (x->u != y->u) return x->u > y->u ? -1 : 1;
+    return 0;
+}
+
+/* Nodes in descending priority order. */
+void orc_priority_order(int64_t n, uint64_t seed, int32_t level, int32_t *order) {
+    orc_key *k = (orc_key *)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_key));
+    for (int64_t u = 0; u < n; ++u) { k[u].h = orc_priority(seed, level, u); k[u].u = u; }
+    qsort(k, (size_t)n, sizeof(orc_key), orc_key_cmp);
+    for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)k[i].u;
+    free(k);
+}
+
+/* schedule 0: greedy first-fit colouring in descending priority order; the
+ *             colour of u is the smallest one not taken by an already coloured
+ *             (that is: higher-priority) neighbour; self-loops are ignored.
+ * schedule 1: one class per node, class = position in the priority order
+ *             (sequential local moving).
+ * Returns the number of classes. */
+int64_t orc_colour(int64_t n, const int64_t *off, const int32_t *col, uint64_t seed, int32_t level,
+                   int32_t schedule, int32_t *colour) {
+    if (n == 0) return 0;
+    int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    orc_priority_order(n, seed, level, order);
+    if (schedule == 1) {
+        for (int64_t i = 0; i < n; ++i) colour[order[i]] = (int32_t)i;
+        free(order);
+        return n;
+    }
+    int64_t maxdeg = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (off[u + 1] - off[u] > maxdeg) maxdeg = off[u + 1] - off[u];
+    int64_t *stamp = (int64_t *)malloc((size_t)(maxdeg + 2) * sizeof(int64_t));
+    for (int64_t c = 0; c < maxdeg + 2; ++c) stamp[c] = -1;
+    for (int64_t u = 0; u < n; ++u) colour[u] = -1;
+    int64_t ncol = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t u = order[i];
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            int64_t v = col[e];
+            if (v != u && colour[v] >= 0 && colour[v] <= maxdeg) stamp[colour[v]] = u;
+        }
+        int64_t c = 0;
+        while (stamp[c] == u) ++c;
+        colour[u] = (int32_t)c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(stamp);
+    free(order);
+    return ncol;
+}
+
+/* ------------------------------------------------------------------ move */
+/* Scratch for the per-node map community -> summed weight (a dense array with
+ * a list of touched keys, as the paper's per-thread vector). */
+typedef struct {
+    int64_t n;
+    int64_t *acc;
+    uint8_t *seen;
+    int32_t *touched;
+} orc_map;
+
+static void orc_map_init(orc_map *m, int64_t n) {
+    m->n = n;
+    m->acc = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    m->seen = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    m->touched = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+}
+static void orc_map_free(orc_map *m) { free(m->acc); free(m->seen); free(m->touched); }
+
+static int orc_i32_cmp(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Best move of u: the target community, or -1 to stay.  *gain_out gets the
+ * winning gain (0 when staying). */
+static int32_t orc_decide_m(int64_t u, const int64_t *off, const int32_t *col, const int64_t *w2,
+                            const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S,
+                            orc_map *m, i128 *gain_out) {
+    int64_t nt = 0;
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+        int64_t v = col[e];
+        if (v == u) continue;          /* w(u, X) excludes the self-loop */
+        int32_t X = zeta[v];
+        if (!m->seen[X]) { m->seen[X] = 1; m->acc[X] = 0; m->touched[nt++] = X; }
+        m->acc[X] += w2[e];
+    }
+    int32_t D = zeta[u];
+    int32_t best = -1;
+    i128 best_gain = 0;
+    if (nt > 0) {
+        qsort(m->touched, (size_t)nt, sizeof(int32_t), orc_i32_cmp);
+        int64_t wD = m->seen[D] ? m->acc[D] : 0;
+        int64_t base = volC[D] - vol[u];           /* vol(D \ u) */
+        for (int64_t i = 0; i < nt; ++i) {
+            int32_t X = m->touched[i];
+            if (X == D) continue;
+            i128 g = (i128)S * (i128)(m->acc[X] - wD) - (i128)vol[u] * (i128)(volC[X] - base);
+            if (g > best_gain) { best_gain = g; best = X; }  /* ascending X: ties keep the lowest id */
+        }
+    }
+    for (int64_t i = 0; i < nt; ++i) m->seen[m->touched[i]] = 0;
+    *gain_out = best_gain;
+    return best;
+}
+
+/* Single-node decision (exported for sampled checks).  gain_hi/gain_lo receive
+ * the 128-bit winning gain. */
+int32_t orc_decide(int64_t n, int64_t u, const int64_t *off, const int32_t *col, const int64_t *w2,
+                   const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S, int64_t *gain_hi,
+                   uint64_t *gain_lo) {
+    orc_map m;
+    orc_map_init(&m, n);
+    i128 g;
+    int32_t x = orc_decide_m(u, off, col, w2, zeta, volC, vol, S, &m, &g);
+    orc_map_free(&m);
+    if (gain_hi) *gain_hi = (int64_t)(g >> 64);
+    if (gain_lo) *gain_lo = (uint64_t)g;
+    return x;
+}
+
+/* Sampled decisions: for each listed node, its decision against (zeta, volC). */
+void orc_decide_many(int64_t n, int64_t count, const int32_t *nodes, const int64_t *off, const int32_t *col,
+                     const int64_t *w2, const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S,
+                     int32_t *out) {
+    orc_map m;
+    orc_map_init(&m, n);
+    for (int64_t i = 0; i < count; ++i) {
+        i128 g;
+        out[i] = orc_decide_m(nodes[i], off, col, w2, zeta, volC, vol, S, &m, &g);
+    }
+    orc_map_free(&m);
+}
+
+/* One class step: every node of class c decides against the volumes at the
+ * start of the class, then all moves are applied.  Returns the move count.
+ * `members`/`count` list the class; decisions[] is scratch of size count. */
+static int64_t orc_class_step_m(const int32_t *members, int64_t count, const int64_t *off, const int32_t *col,
+                                const int64_t *w2, const int64_t *vol, int64_t S, int32_t *zeta, int64_t *volC,
+                                int32_t *decisions, orc_map *m) {
+    for (int64_t i = 0; i < count; ++i) {
+        i128 g;
+        decisions[i] = orc_decide_m(members[i], off, col, w2, zeta, volC, vol, S, m, &g);
+    }
+    int64_t moves = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        int32_t X = decisions[i];
+        if (X < 0) continue;
+        int32_t u = members[i], D = zeta[u];
+        zeta[u] = X;
+        volC[D] -= vol[u];
+        volC[X] += vol[u];
+        ++moves;
+    }
+    return moves;
+}
+
+/* Class lists: members of class c are cls_nodes[cls_off[c] .. cls_off[c+1]),
+ * ascending node ids.  cls_off has ncol+1 entries. */
+static void orc_classes(int64_t n, const int32_t *colour, int64_t ncol, int64_t *cls_off, int32_t *cls_nodes) {
+    memset(cls_off, 0, (size_t)(ncol + 1) * sizeof(int64_t));
+    for (int64_t u = 0; u < n; ++u) cls_off[colour[u] + 1]++;
+    for (int64_t c = 0; c < ncol; ++c) cls_off[c + 1] += cls_off[c];
+    int64_t *fill = (int64_t *)malloc((size_t)(ncol + 1) * sizeof(int64_t));
+    memcpy(fill, cls_off, (size_t)(ncol + 1) * sizeof(int64_t));
+    for (int64_t u = 0; u < n; ++u) cls_nodes[fill[colour[u]]++] = (int32_t)u;
+    free(fill);
+}
+
+/* One class step by class index (exported). */
+int64_t orc_class_step(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int64_t *vol,
+                       int64_t S, const int32_t *colour, int32_t c, int32_t *zeta, int64_t *volC) {
+    int64_t count = 0;
+    for (int64_t u = 0; u < n; ++u) count += (colour[u] == c);
+    int32_t *members = (int32_t *)malloc((size_t)(count > 0 ? count : 1) * sizeof(int32_t));
+    int32_t *dec = (int32_t *)malloc((size_t)(count > 0 ? count : 1) * sizeof(int32_t));
+    int64_t k = 0;
+    for (int64_t u = 0; u < n; ++u)
+        if (colour[u] == c) members[k++] = (int32_t)u;
+    orc_map m;
+    orc_map_init(&m, n);
+    int64_t moves = orc_class_step_m(members, count, off, col, w2, vol, S, zeta, volC, dec, &m);
+    orc_map_free(&m);
+    free(members);
+    free(dec);
+    return moves;
+}
+
+/* One sweep: all classes in ascending colour order.  Returns the move count. */
+int64_t orc_sweep(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int64_t *vol,
+                  int64_t S, const int32_t *colour, int64_t ncol, int32_t *zeta, int64_t *volC) {
+    int64_t *cls_off = (int64_t *)malloc((size_t)(ncol + 1) * sizeof(int64_t));
+    int32_t *cls_nodes = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *dec = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_classes(n, colour, ncol, cls_off, cls_nodes);
+    orc_map m;
+    orc_map_init(&m, n);
+    int64_t moves = 0;
+    for (int64_t c = 0; c < ncol; ++c)
+        moves += orc_class_step_m(cls_nodes + cls_off[c], cls_off[c + 1] - cls_off[c], off, col, w2, vol, S, zeta,
+                                  volC, dec, &m);
+    orc_map_free(&m);
+    free(cls_off); free(cls_nodes); free(dec);
+    return moves;
+}
+
+/* ------------------------------------------------------------------ coarsen */
+/* pi[u] = rank of zeta[u] among the non-empty community ids (ascending).
+ * Returns the number of communities. */
+int64_t orc_relabel(int64_t n, const int32_t *zeta, int32_t *pi) {
+    int32_t *newid = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t x = 0; x < n; ++x) newid[x] = 0;
+    for (int64_t u = 0; u < n; ++u) newid[zeta[u]] = 1;
+    int64_t k = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        int32_t present = newid[x];
+        newid[x] = (int32_t)k;
+        k += present;
+    }
+    for (int64_t u = 0; u < n; ++u) pi[u] = newid[zeta[u]];
+    free(newid);
+    return k;
+}
+
+/* Coarse graph: W'[pi(u)][pi(v)] = sum of w2 over entries (u, v).  The fine
+ * graph's diagonal is doubled and every intra-community edge appears in both
+ * directions, so the coarse diagonal is again doubled.  Rows ascending.
+ * coff[k+1], ccol[], cw[] must hold up to nnz entries.  Returns nnz'. */
+int64_t orc_contract(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int32_t *pi,
+                     int64_t k, int64_t *coff, int32_t *ccol, int64_t *cw) {
+    /* members of each coarse node, ascending fine id */
+    int64_t *moff = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));
+    int32_t *mem = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t u = 0; u < n; ++u) moff[pi[u] + 1]++;
+    for (int64_t c = 0; c < k; ++c) moff[c + 1] += moff[c];
+    int64_t *fill = (int64_t *)malloc(((size_t)k + 1) * sizeof(int64_t));
+    memcpy(fill, moff, ((size_t)k + 1) * sizeof(int64_t));
+    for (int64_t u = 0; u < n; ++u) mem[fill[pi[u]]++] = (int32_t)u;
+    free(fill);
+    orc_map m;
+    orc_map_init(&m, k);
+    int64_t p = 0;
+    coff[0] = 0;
+    for (int64_t c = 0; c < k; ++c) {
+        int64_t nt = 0;
+        for (int64_t i = moff[c]; i < moff[c + 1]; ++i) {
+            int64_t u = mem[i];
+            for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+                int32_t t = pi[col[e]];
+                if (!m.seen[t]) { m.seen[t] = 1; m.acc[t] = 0; m.touched[nt++] = t; }
+                m.acc[t] += w2[e];
+            }
+        }
+        qsort(m.touched, (size_t)nt, sizeof(int32_t), orc_i32_cmp);
+        for (int64_t i = 0; i < nt; ++i) {
+            int32_t t = m.touched[i];
+            ccol[p] = t;
+            cw[p] = m.acc[t];
+            ++p;
+            m.seen[t] = 0;
+        }
+        coff[c + 1] = p;
+    }
+    orc_map_free(&m);
+    free(moff); free(mem);
+    return p;
+}
+
+/* ------------------------------------------------------------------ modularity */
+/* Equation (3.1) with integers: N = S*I2 - sum_C vol(C)^2 and D = S^2 (both
+ * 128-bit), Q = (double)N / (double)D.  labels in [0, n). */
+double orc_modularity(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int32_t *labels,
+                      int64_t *num_hi, uint64_t *num_lo, int64_t *den_hi, uint64_t *den_lo) {
+    int64_t *vC = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t S = 0, I2 = 0;
+    for (int64_t u = 0; u < n; ++u)
+        for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+            S += w2[e];
+            vC[labels[u]] += w2[e];
+            if (labels[col[e]] == labels[u]) I2 += w2[e];
+        }
+    i128 sq = 0;
+    for (int64_t x = 0; x < n; ++x) sq += (i128)vC[x] * (i128)vC[x];
+    free(vC);
+    i128 N = (i128)S * (i128)I2 - sq, D = (i128)S * (i128)S;
+    if (num_hi) *num_hi = (int64_t)(N >> 64);
+    if (num_lo) *num_lo = (uint64_t)N;
+    if (den_hi) *den_hi = (int64_t)(D >> 64);
+    if (den_lo) *den_lo = (uint64_t)D;
+    if (S == 0) return 0.0;
+    return (double)N / (double)D;
+}
+
+/* ------------------------------------------------------------------ full run */
+typedef struct {
+    int32_t max_sweeps;   /* per level, >= 1 */
+    int32_t max_levels;   /* 0 = unlimited */
+    int32_t schedule;     /* 0 colour classes, 1 sequential */
+    int32_t pad;
+    uint64_t seed;
+} orc_options;
+
+#define ORC_MAX_LEVELS 64
+#define ORC_MAX_SWEEPS 64
+typedef struct {
+    int32_t levels;
+    int32_t pad;
+    int64_t n[ORC_MAX_LEVELS], nnz[ORC_MAX_LEVELS], colours[ORC_MAX_LEVELS], sweeps[ORC_MAX_LEVELS];
+    int64_t communities[ORC_MAX_LEVELS];
+    int64_t moves[ORC_MAX_LEVELS][ORC_MAX_SWEEPS];
+    int64_t S;
+} orc_trace;
+
+/* Canonical labels: renumber by first occurrence in node order. */
+void orc_canonical(int64_t n, const int32_t *lab, int32_t *out) {
+    int32_t *map = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t x = 0; x < n; ++x) map[x] = -1;
+    int32_t next = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (map[lab[v]] < 0) map[lab[v]] = next++;
+        out[v] = map[lab[v]];
+    }
+    free(map);
+}
+
+/* Algorithm 3 under the colour-class schedule.  w: input weights (self-loops
+ * given once) or NULL for unit weights.  labels[n] receives canonical labels.
+ * Returns 0 on success, -1 on bad options or allocation failure. */
+int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, const orc_options *opt,
+            int32_t *labels, double *q_out, orc_trace *tr) {
+    if (opt->max_sweeps < 1 || opt->max_sweeps > ORC_MAX_SWEEPS) return -1;
+    memset(tr, 0, sizeof(*tr));
+    int64_t nnz = off[n];
+    int64_t *w2_0 = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    orc_double_diagonal(n, off, col, w, w2_0);
+    /* current level graph (level 0 aliases the input) */
+    int64_t ln = n, lnnz = nnz;
+    const int64_t *loff = off;
+    const int32_t *lcol = col;
+    const int64_t *lw = w2_0;
+    int64_t *own_off = NULL; int32_t *own_col = NULL; int64_t *own_w = NULL;
+    int32_t *lab = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < n; ++v) lab[v] = (int32_t)v;   /* fine node -> current level node */
+    int64_t S = 0;
+    int32_t level = 0;
+    for (;;) {
+        int64_t *vol = (int64_t *)malloc((size_t)(ln > 0 ? ln : 1) * sizeof(int64_t));
+        int64_t *volC = (int64_t *)malloc((size_t)(ln > 0 ? ln : 1) * sizeof(int64_t));
+        int32_t *zeta = (int32_t *)malloc((size_t)(ln > 0 ? ln : 1) * sizeof(int32_t));
+        int32_t *colour = (int32_t *)malloc((size_t)(ln > 0 ? ln : 1) * sizeof(int32_t));
+        S = orc_volumes(ln, loff, lw, vol);
+        for (int64_t u = 0; u < ln; ++u) { zeta[u] = (int32_t)u; volC[u] = vol[u]; }
+        int64_t ncol = orc_colour(ln, loff, lcol, opt->seed, level, opt->schedule, colour);
+        int64_t sweeps = 0;
+        if (level < ORC_MAX_LEVELS) { tr->n[level] = ln; tr->nnz[level] = lnnz; tr->colours[level] = ncol; }
+        for (int32_t s = 0; s < opt->max_sweeps; ++s) {
+            int64_t mv = orc_sweep(ln, loff, lcol, lw, vol, S, colour, ncol, zeta, volC);
+            if (level < ORC_MAX_LEVELS) tr->moves[level][s] = mv;
+            ++sweeps;
+            if (mv == 0) break;
+        }
+        int32_t *pi = (int32_t *)malloc((size_t)(ln > 0 ? ln : 1) * sizeof(int32_t));
+        int64_t k = orc_relabel(ln, zeta, pi);
+        if (level < ORC_MAX_LEVELS) { tr->sweeps[level] = sweeps; tr->communities[level] = k; }
+        ++level;
+        int stop = (k == ln) || (opt->max_levels > 0 && level >= opt->max_levels);
+        if (stop) {
+            for (int64_t v = 0; v < n; ++v) lab[v] = zeta[lab[v]];
+            free(pi); free(vol); free(volC); free(zeta); free(colour);
+            break;
+        }
+        /* coarsen and descend: fine node -> coarse node */
+        int64_t *coff = (int64_t *)malloc(((size_t)k + 1) * sizeof(int64_t));
+        int32_t *ccol = (int32_t *)malloc((size_t)(lnnz > 0 ? lnnz : 1) * sizeof(int32_t));
+        int64_t *cw = (int64_t *)malloc((size_t)(lnnz > 0 ? lnnz : 1) * sizeof(int64_t));
+        int64_t cnnz = orc_contract(ln, loff, lcol, lw, pi, k, coff, ccol, cw);
+        for (int64_t v = 0; v < n; ++v) lab[v] = pi[lab[v]];
+        free(own_off); free(own_col); free(own_w);
+        own_off = coff; own_col = ccol; own_w = cw;
+        loff = coff; lcol = ccol; lw = cw; ln = k; lnnz = cnnz;
+        free(pi); free(vol); free(volC); free(zeta); free(colour);
+    }
+    tr->levels = level;
+    tr->S = S;
+    orc_canonical(n, lab, labels);
+    *q_out = orc_modularity(n, off, col, w2_0, labels, NULL, NULL, NULL, NULL);
+    free(lab); free(w2_0);
+    free(own_off); free(own_col); free(own_w);
+    return 0;
+}

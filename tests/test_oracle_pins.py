@@ -1,0 +1,368 @@
+"""Pins of the oracle against facts fixed outside it: closed forms, networkx,
+brute force, the published SplitMix64 outputs, an exact-fraction sequential
+Louvain written from the paper's Delta-mod, and invariants of each step.
+
+CPU only.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import refs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    oracle.build(force=False)
+    graphgen.build(force=False)
+
+
+def _state_after_random_moves(g, rng, moves=0.6):
+    """A random partition (via random labels) with consistent volC."""
+    n = g.n
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    k = max(1, n // 3)
+    zeta = rng.integers(0, k, n).astype(np.int32)
+    keep = rng.random(n) > moves
+    zeta[keep] = np.arange(n, dtype=np.int32)[keep]
+    volC = np.zeros(n, np.int64)
+    np.add.at(volC, zeta, vol)
+    return w2, vol, S, zeta, volC
+
+
+def _N(g, w2, labels):
+    return oracle.modularity_parts(g.off, g.col, w2, labels)[0]
+
+
+# ------------------------------------------------------------------ hashing
+def test_splitmix64_published_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64.txt")) if l.startswith("0x")]
+    gamma = 0x9E3779B97F4A7C15
+    for i, v in enumerate(vals):
+        assert oracle.splitmix64((i * gamma) & refs.MASK64) == v
+        assert refs.splitmix64((i * gamma) & refs.MASK64) == v
+
+
+def test_priority_order_matches_reference():
+    for seed, level in [(0, 0), (7, 3), (2**63 + 5, 1)]:
+        assert list(oracle.priority_order(300, seed, level)) == refs.priority_order(300, seed, level)
+
+
+# ------------------------------------------------------------------ modularity (Equation 3.1)
+@pytest.mark.parametrize("k", [3, 5, 8])
+def test_two_cliques_half(k):
+    g = graphgen.disjoint_cliques(2, k)
+    labels = np.repeat(np.arange(2), k).astype(np.int32)
+    assert oracle.modularity(g.off, g.col, None, labels) == 0.5
+
+
+@pytest.mark.parametrize("c,k", [(10, 5), (6, 4), (3, 3), (30, 5)])
+def test_ring_of_cliques_closed_form(c, k):
+    g = graphgen.ring_of_cliques(c, k)
+    labels = np.repeat(np.arange(c), k).astype(np.int32)
+    a = k * (k - 1)
+    want = float(Fraction(a, a + 2) - Fraction(1, c))
+    assert oracle.modularity(g.off, g.col, None, labels) == want
+    if (c, k) == (10, 5):
+        assert want == 89 / 110
+
+
+@pytest.mark.parametrize("c", [1, 2, 7, 50])
+def test_disjoint_edges(c):
+    g = graphgen.disjoint_edges(c)
+    labels = np.repeat(np.arange(c), 2).astype(np.int32)
+    assert oracle.modularity(g.off, g.col, None, labels) == float(Fraction(c - 1, c))
+
+
+def test_one_community_and_singletons():
+    g = graphgen.random_graph(30, 0.2, seed=3, weighted=True, loops=0.2)
+    assert oracle.modularity(g.off, g.col, g.w, np.zeros(30, np.int32)) == 0.0
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    # singletons: only self-loops are intra
+    rows = np.repeat(np.arange(30), np.diff(g.off))
+    I2 = int(w2[rows == g.col].sum())
+    want = Fraction(S * I2 - int((vol.astype(object) ** 2).sum()), S * S)
+    assert oracle.modularity(g.off, g.col, g.w, np.arange(30, dtype=np.int32)) == float(want)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_modularity_matches_networkx(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 60))
+    g = graphgen.random_graph(n, float(rng.uniform(0.05, 0.5)), seed=seed, weighted=True, loops=0.3)
+    for _ in range(3):
+        labels = rng.integers(0, max(1, n // 4), n).astype(np.int32)
+        q = oracle.modularity(g.off, g.col, g.w, labels)
+        assert abs(q - refs.nx_modularity(g.off, g.col, g.w, labels)) < 1e-12
+        ex = refs.modularity_fraction(n, refs.edges_of(g.off, g.col, g.w), labels)
+        assert abs(q - float(ex)) <= 1e-15
+
+
+# ------------------------------------------------------------------ gain (Delta-mod)
+@pytest.mark.parametrize("seed", range(20))
+def test_gain_is_half_the_numerator_change_and_best(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3, 40))
+    g = graphgen.random_graph(n, float(rng.uniform(0.1, 0.6)), seed=1000 + seed, weighted=True, loops=0.25)
+    w2, vol, S, zeta, volC = _state_after_random_moves(g, rng)
+    N0 = _N(g, w2, zeta)
+    for u in range(n):
+        x, gain = oracle.decide(u, g.off, g.col, w2, zeta, volC, vol, S)
+        # brute force every neighbouring community by full recomputation
+        cands = sorted({int(zeta[v]) for v in g.col[g.off[u]:g.off[u + 1]] if v != u} - {int(zeta[u])})
+        best, bestX = 0, -1
+        for X in cands:
+            z2 = zeta.copy(); z2[u] = X
+            d = _N(g, w2, z2) - N0
+            if d > best:
+                best, bestX = d, X
+        assert x == bestX
+        assert 2 * gain == best
+
+
+def test_gain_ties_go_to_lowest_id():
+    # star centre 0 joined to leaves 1..4 with equal weights; leaf 1 sees only 0.
+    g = graphgen.from_edges(5, [(0, 1), (0, 2), (0, 3), (0, 4)])
+    w2 = oracle.double_diagonal(g.off, g.col, None)
+    vol, S = oracle.volumes(g.off, w2)
+    zeta = np.arange(5, dtype=np.int32)
+    x, gain = oracle.decide(0, g.off, g.col, w2, zeta, vol.copy(), vol, S)
+    assert gain > 0 and x == 1
+
+
+def test_no_move_without_positive_gain():
+    g = graphgen.from_edges(2, [(0, 1)], loops={0: 5, 1: 5})
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    zeta = np.arange(2, dtype=np.int32)
+    x, gain = oracle.decide(0, g.off, g.col, w2, zeta, vol.copy(), vol, S)
+    assert x == -1 and gain == 0
+    # isolated and loop-only nodes never move
+    g = graphgen.from_edges(3, [(0, 1)], loops={2: 3})
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    assert oracle.decide(2, g.off, g.col, w2, np.arange(3, dtype=np.int32), vol.copy(), vol, S)[0] == -1
+
+
+# ------------------------------------------------------------------ colouring
+@pytest.mark.parametrize("seed", range(6))
+def test_colouring_is_greedy_in_priority_order(seed):
+    g = graphgen.random_graph(80, 0.08 + 0.04 * seed, seed=seed, weighted=False, loops=0.1)
+    for level in (0, 2):
+        col, C = oracle.colour(g.off, g.col, seed=seed, level=level)
+        order = refs.priority_order(g.n, seed, level)
+        assert np.array_equal(col, refs.nx_greedy_colouring(g.off, g.col, order))
+        rows = np.repeat(np.arange(g.n), np.diff(g.off))
+        nl = rows != g.col
+        assert not np.any(col[rows[nl]] == col[g.col[nl]])      # proper colouring
+        assert C == col.max() + 1
+
+
+def test_sequential_schedule_classes_are_priority_ranks():
+    g = graphgen.random_graph(40, 0.2, seed=1, weighted=False)
+    col, C = oracle.colour(g.off, g.col, seed=9, level=1, schedule=1)
+    order = refs.priority_order(40, 9, 1)
+    assert C == 40 and [int(col[u]) for u in order] == list(range(40))
+
+
+def test_jones_plassmann_rounds_equal_greedy():
+    """Jones-Plassmann (colour a node once all higher-priority neighbours are
+    coloured, with the smallest free colour) computed round by round here gives
+    the oracle's greedy colouring."""
+    g = graphgen.rmat(10, 8, seed=4)
+    col, _ = oracle.colour(g.off, g.col, seed=3, level=0)
+    n = g.n
+    pr = {u: (refs.splitmix64(3 ^ u), u) for u in range(n)}
+    jp = [-1] * n
+    left = set(range(n))
+    while left:
+        ready = [u for u in left if all(jp[v] >= 0 for v in g.col[g.off[u]:g.off[u + 1]]
+                                         if v != u and pr[int(v)] > pr[u])]
+        for u in ready:
+            used = {jp[v] for v in g.col[g.off[u]:g.off[u + 1]] if v != u and pr[int(v)] > pr[u]}
+            c = 0
+            while c in used:
+                c += 1
+            jp[u] = c
+        left -= set(ready)
+    assert list(col) == jp
+
+
+# ------------------------------------------------------------------ class step / sweep
+@pytest.mark.parametrize("seed", range(6))
+def test_class_step_invariants_and_bruteforce(seed):
+    rng = np.random.default_rng(seed)
+    g = graphgen.random_graph(50, 0.15, seed=50 + seed, weighted=True, loops=0.2)
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    colours, C = oracle.colour(g.off, g.col, seed=seed)
+    zeta = np.arange(g.n, dtype=np.int32)
+    volC = vol.copy()
+    for c in range(C):
+        members = np.nonzero(colours == c)[0]
+        # each member's decision against the class-start state, by brute force
+        want = oracle.decide_many(members, g.off, g.col, w2, zeta, volC, vol, S)
+        z0 = zeta.copy()
+        mv = oracle.class_step(g.off, g.col, w2, vol, S, colours, c, zeta, volC)
+        assert mv == int(np.count_nonzero(want >= 0))
+        exp = z0.copy()
+        exp[members[want >= 0]] = want[want >= 0]
+        assert np.array_equal(zeta, exp)
+        assert int(volC.sum()) == S
+        vc = np.zeros(g.n, np.int64); np.add.at(vc, zeta, vol)
+        assert np.array_equal(vc, volC)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_converged_sweep_is_locally_optimal(seed):
+    g = graphgen.random_graph(60, 0.1, seed=70 + seed, weighted=True, loops=0.1)
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    colours, C = oracle.colour(g.off, g.col, seed=seed)
+    zeta = np.arange(g.n, dtype=np.int32); volC = vol.copy()
+    for _ in range(200):
+        if oracle.sweep(g.off, g.col, w2, vol, S, colours, C, zeta, volC) == 0:
+            break
+    else:
+        pytest.skip("did not converge in 200 sweeps")
+    N0 = _N(g, w2, zeta)
+    for u in range(g.n):
+        for X in {int(zeta[v]) for v in g.col[g.off[u]:g.off[u + 1]] if v != u}:
+            z2 = zeta.copy(); z2[u] = X
+            assert _N(g, w2, z2) - N0 <= 0
+
+
+# ------------------------------------------------------------------ coarsening
+@pytest.mark.parametrize("seed", range(8))
+def test_contraction_invariants(seed):
+    rng = np.random.default_rng(seed)
+    g = graphgen.random_graph(70, 0.1, seed=90 + seed, weighted=True, loops=0.2)
+    w2, vol, S, zeta, volC = _state_after_random_moves(g, rng)
+    pi, k = oracle.relabel(zeta)
+    assert sorted(set(pi.tolist())) == list(range(k))
+    # ids ascend with the old community ids
+    firsts = {int(zeta[u]): int(pi[u]) for u in range(g.n)}
+    ks = sorted(firsts)
+    assert [firsts[x] for x in ks] == list(range(k))
+    coff, ccol, cw = oracle.contract(g.off, g.col, w2, pi, k)
+    assert int(cw.sum()) == S and np.all(cw > 0)
+    # rows ascending, symmetric
+    ent = {}
+    for c in range(k):
+        row = ccol[coff[c]:coff[c + 1]]
+        assert np.all(np.diff(row) > 0)
+        for e in range(coff[c], coff[c + 1]):
+            ent[(c, int(ccol[e]))] = int(cw[e])
+    assert all(ent.get((b, a)) == wt for (a, b), wt in ent.items())
+    # coarse volumes are the community volumes
+    cvol, S2 = oracle.volumes(coff, cw)
+    assert S2 == S
+    assert np.array_equal(cvol, np.array([volC[x] for x in ks]))
+    # modularity of the projected partition is preserved exactly
+    assert _N(g, w2, zeta) == oracle.modularity_parts(coff, ccol, cw, np.arange(k, dtype=np.int32))[0]
+    for _ in range(3):
+        zc = rng.integers(0, max(1, k // 2), k).astype(np.int32)
+        assert _N(g, w2, zc[pi]) == oracle.modularity_parts(coff, ccol, cw, zc)[0]
+
+
+# ------------------------------------------------------------------ full run (Algorithm 3)
+def _q_opt(g):
+    best = None
+    for p in refs.set_partitions(g.n):
+        q = refs.modularity_fraction(g.n, refs.edges_of(g.off, g.col, g.w), p)
+        best = q if best is None or q > best else best
+    return best
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_run_never_beats_bruteforce_optimum(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(4, 9))
+    g = graphgen.random_graph(n, float(rng.uniform(0.2, 0.7)), seed=200 + seed, weighted=True, loops=0.2)
+    r = oracle.run(g.off, g.col, g.w, seed=seed)
+    assert r.q <= float(_q_opt(g)) + 1e-12
+
+
+@pytest.mark.parametrize("g,opt", [
+    (graphgen.disjoint_cliques(2, 4), Fraction(1, 2)),
+    (graphgen.disjoint_edges(5), Fraction(4, 5)),
+    (graphgen.ring_of_cliques(3, 3), Fraction(6, 8) - Fraction(1, 3)),
+])
+def test_run_reaches_optimum_on_small_structured(g, opt):
+    assert _q_opt(g) == opt
+    assert oracle.run(g.off, g.col, g.w).q == float(opt)
+
+
+@pytest.mark.parametrize("c,k", [(10, 5), (6, 4), (20, 6)])
+def test_ring_of_cliques_found(c, k):
+    g = graphgen.ring_of_cliques(c, k)
+    r = oracle.run(g.off, g.col, None)
+    a = k * (k - 1)
+    assert c < a + 2
+    assert np.array_equal(r.labels, np.repeat(np.arange(c), k).astype(np.int32))
+    assert r.q == float(Fraction(a, a + 2) - Fraction(1, c))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sequential_schedule_equals_fraction_louvain(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 70))
+    g = graphgen.random_graph(n, float(rng.uniform(0.05, 0.3)), seed=300 + seed, weighted=True, loops=0.15)
+    r = oracle.run(g.off, g.col, g.w, seed=seed, schedule=1)
+    ref = refs.seq_louvain(n, refs.edges_of(g.off, g.col, g.w), seed=seed)
+    assert np.array_equal(r.labels, ref)
+
+
+def test_sequential_schedule_on_planted_partition_matches_reference():
+    g = graphgen.sbm(200, 4, 0.2, 0.01, seed=11)
+    r = oracle.run(g.off, g.col, None, seed=5, schedule=1)
+    assert np.array_equal(r.labels, refs.seq_louvain(g.n, refs.edges_of(g.off, g.col, None), seed=5))
+
+
+def test_canonical_labels_and_trace_consistency():
+    g = graphgen.planted_partition_1000()
+    r = oracle.run(g.off, g.col, None)
+    # canonical: first occurrence order
+    seen = []
+    for x in r.labels:
+        if x not in seen:
+            assert x == len(seen)
+            seen.append(x)
+    assert r.n[0] == 1000 and r.communities[-1] == r.n[-1]
+    assert all(r.communities[i] == r.n[i + 1] for i in range(r.levels - 1))
+    assert abs(r.q - refs.nx_modularity(g.off, g.col, None, r.labels)) < 1e-12
+
+
+def test_planted_partition_statistics():
+    """Statistical expectation only: the 10 planted blocks are (nearly) recovered."""
+    g = graphgen.planted_partition_1000()
+    r = oracle.run(g.off, g.col, None)
+    blocks = np.arange(1000) // 100
+    assert len(set(r.labels.tolist())) == 10
+    for b in range(10):
+        assert np.bincount(r.labels[blocks == b]).max() >= 90
+    assert 0.55 < r.q < 0.65
+
+
+def test_max_levels_and_sweeps_respected():
+    g = graphgen.planted_partition_1000()
+    r = oracle.run(g.off, g.col, None, max_levels=1, max_sweeps=2)
+    assert r.levels == 1 and r.sweeps == [2]
+
+
+def test_empty_and_edgeless():
+    r = oracle.run(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert r.levels == 1 and r.q == 0.0
+    g = graphgen.from_edges(5, [])
+    r = oracle.run(g.off, g.col, None)
+    assert np.array_equal(r.labels, np.arange(5)) and r.q == 0.0
