@@ -1,0 +1,250 @@
+"""paper_1304_4453_amd: PLM (Parallel Louvain Method) move sweep and coarsening
+on AMD Instinct MI355X, behind the C ABI of ``include/plm.h``.
+
+This module is argument marshalling only: every step of the method runs in the
+HIP kernels of ``libplm.so``.  There is no CPU fallback; importing the binding
+without a built library raises.
+
+Low level: ``plm_create``, ``plm_move_sweep``, ``plm_move_class``,
+``plm_coarsen``, ``plm_run``, ``plm_modularity``, ``plm_reset``,
+``plm_destroy``, ``plm_last_error``, ``plm_level_info``, ``plm_get_state``,
+``plm_get_graph``, ``plm_get_stats``, ``plm_default_options`` (ctypes functions
+with the C signatures).  ``Context`` wraps them for numpy (host) and torch
+(device) arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplm.so")
+
+PLM_OK, PLM_E_ARG, PLM_E_GRAPH, PLM_E_NOMEM, PLM_E_DEVICE, PLM_E_BUDGET, PLM_E_STATE = 0, -1, -2, -3, -4, -5, -6
+PLM_MEM_HOST, PLM_MEM_DEVICE = 0, 1
+PLM_SCHEDULE_COLOUR, PLM_SCHEDULE_SEQUENTIAL = 0, 1
+PLM_INT_AUTO, PLM_INT_64, PLM_INT_128 = 0, 1, 2
+PLM_MAX_LEVELS = 64
+
+_STATUS_NAMES = {0: "PLM_OK", -1: "PLM_E_ARG", -2: "PLM_E_GRAPH", -3: "PLM_E_NOMEM", -4: "PLM_E_DEVICE",
+                 -5: "PLM_E_BUDGET", -6: "PLM_E_STATE"}
+
+
+class plm_options(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("colour_seed", ctypes.c_uint64), ("int_mode", ctypes.c_int32),
+                ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class plm_level_info_t(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("colours", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("S", ctypes.c_int64), ("sweeps", ctypes.c_int32),
+                ("weight_kind", ctypes.c_int32), ("communities", ctypes.c_int64), ("max_vol", ctypes.c_int64)]
+
+
+_L = PLM_MAX_LEVELS
+
+
+class plm_stats_t(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n", ctypes.c_int64 * _L), ("nnz", ctypes.c_int64 * _L), ("colours", ctypes.c_int64 * _L),
+                ("sweeps", ctypes.c_int64 * _L), ("communities", ctypes.c_int64 * _L),
+                ("moves", ctypes.c_int64 * _L), ("schedule_ms", ctypes.c_double * _L),
+                ("sweep_ms", ctypes.c_double * _L), ("coarsen_ms", ctypes.c_double * _L),
+                ("decide_ms", ctypes.c_double * _L), ("decide_launches", ctypes.c_int64 * _L),
+                ("decide_bytes", ctypes.c_double * _L)]
+
+
+class PLMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libplm.so not built ({LIB_PATH}); run paper_1304_4453_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.plm_default_options.argtypes = [P(plm_options)]
+    lib.plm_default_options.restype = None
+    lib.plm_create.argtypes = [P(vp), i64, i64, vp, vp, vp, i32, vp, P(plm_options)]
+    lib.plm_move_sweep.argtypes = [vp, P(i64)]
+    lib.plm_move_class.argtypes = [vp, i32, P(i64)]
+    lib.plm_coarsen.argtypes = [vp, P(i64)]
+    lib.plm_run.argtypes = [vp, vp, P(dbl), P(i32)]
+    lib.plm_modularity.argtypes = [vp, vp, i32, P(dbl)]
+    lib.plm_reset.argtypes = [vp]
+    lib.plm_destroy.argtypes = [vp]
+    lib.plm_destroy.restype = None
+    lib.plm_last_error.argtypes = [vp]
+    lib.plm_last_error.restype = ctypes.c_char_p
+    lib.plm_level_info.argtypes = [vp, P(plm_level_info_t)]
+    lib.plm_get_state.argtypes = [vp, vp, vp, vp, i32]
+    lib.plm_get_graph.argtypes = [vp, vp, vp, vp, i32]
+    lib.plm_get_stats.argtypes = [vp, P(plm_stats_t)]
+    for f in ("plm_create", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
+              "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
+        getattr(lib, f).restype = i32
+    return lib
+
+
+_lib = _load()
+
+plm_default_options = _lib.plm_default_options
+plm_create = _lib.plm_create
+plm_move_sweep = _lib.plm_move_sweep
+plm_move_class = _lib.plm_move_class
+plm_coarsen = _lib.plm_coarsen
+plm_run = _lib.plm_run
+plm_modularity = _lib.plm_modularity
+plm_reset = _lib.plm_reset
+plm_destroy = _lib.plm_destroy
+plm_last_error = _lib.plm_last_error
+plm_level_info = _lib.plm_level_info
+plm_get_state = _lib.plm_get_state
+plm_get_graph = _lib.plm_get_graph
+plm_get_stats = _lib.plm_get_stats
+
+
+def default_options(**kw) -> plm_options:
+    o = plm_options()
+    plm_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a) -> int:
+    """Address of a numpy array, a torch tensor, an int address or None."""
+    if a is None:
+        return 0
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+class Context:
+    """Owns one plm_ctx.  Host inputs: numpy arrays (mem_kind host).  Device
+    inputs: torch tensors on the current HIP device or raw device addresses
+    (mem_kind device).  stream: torch stream object, raw hipStream_t int, or None."""
+
+    def __init__(self, off, col, w=None, mem_kind: int | None = None, stream=None, n: int | None = None,
+                 nnz: int | None = None, **options):
+        self._c = ctypes.c_void_p()
+        if mem_kind is None:
+            mem_kind = PLM_MEM_HOST if isinstance(off, np.ndarray) else PLM_MEM_DEVICE
+        if mem_kind == PLM_MEM_HOST:
+            off = np.ascontiguousarray(off, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            if w is not None:
+                w = np.ascontiguousarray(w, dtype=np.int32)
+        if n is None:
+            n = int(off.shape[0]) - 1
+        if nnz is None:
+            nnz = int(col.shape[0])
+        self._keep = (off, col, w)
+        self.n, self.nnz, self.mem_kind = n, nnz, mem_kind
+        sp = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
+        self.opt = default_options(**options)
+        rc = plm_create(ctypes.byref(self._c), n, nnz, _ptr(off), _ptr(col), _ptr(w), mem_kind, sp or 0,
+                        ctypes.byref(self.opt))
+        self._keep = None
+        if rc != 0:
+            raise PLMError(rc, plm_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PLMError(rc, plm_last_error(self._c).decode())
+
+    def close(self):
+        if self._c:
+            plm_destroy(self._c)
+            self._c = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- method
+    def move_sweep(self) -> int:
+        mv = ctypes.c_int64()
+        self._check(plm_move_sweep(self._c, ctypes.byref(mv)))
+        return mv.value
+
+    def move_class(self, c: int) -> int:
+        mv = ctypes.c_int64()
+        self._check(plm_move_class(self._c, c, ctypes.byref(mv)))
+        return mv.value
+
+    def coarsen(self) -> int:
+        k = ctypes.c_int64()
+        self._check(plm_coarsen(self._c, ctypes.byref(k)))
+        return k.value
+
+    def run(self, labels=None):
+        """Full run.  labels: output buffer (numpy int32 for host contexts,
+        torch int32 tensor / address for device contexts) or None for a new
+        numpy array (host contexts).  Returns (labels, q, levels)."""
+        if labels is None and self.mem_kind == PLM_MEM_HOST:
+            labels = np.zeros(self.n, np.int32)
+        q, lv = ctypes.c_double(), ctypes.c_int32()
+        self._check(plm_run(self._c, _ptr(labels), ctypes.byref(q), ctypes.byref(lv)))
+        return labels, q.value, lv.value
+
+    def modularity(self, labels, mem_kind: int | None = None) -> float:
+        if mem_kind is None:
+            mem_kind = PLM_MEM_HOST if isinstance(labels, np.ndarray) else PLM_MEM_DEVICE
+        if isinstance(labels, np.ndarray):
+            labels = np.ascontiguousarray(labels, dtype=np.int32)
+        q = ctypes.c_double()
+        self._check(plm_modularity(self._c, _ptr(labels), mem_kind, ctypes.byref(q)))
+        return q.value
+
+    def reset(self):
+        self._check(plm_reset(self._c))
+
+    # ---- inspection
+    def level_info(self) -> plm_level_info_t:
+        li = plm_level_info_t()
+        self._check(plm_level_info(self._c, ctypes.byref(li)))
+        return li
+
+    def state(self):
+        """(zeta, volC, colour) of the current level as numpy arrays."""
+        n = self.level_info().n
+        z = np.zeros(max(n, 1), np.int32); v = np.zeros(max(n, 1), np.int64); c = np.zeros(max(n, 1), np.int32)
+        self._check(plm_get_state(self._c, z.ctypes.data, v.ctypes.data, c.ctypes.data, PLM_MEM_HOST))
+        return z[:n], v[:n], c[:n]
+
+    def graph(self):
+        """(off, col, w with doubled diagonal) of the current level as numpy arrays."""
+        li = self.level_info()
+        off = np.zeros(li.n + 1, np.int64)
+        col = np.zeros(max(li.nnz, 1), np.int32)
+        w = np.zeros(max(li.nnz, 1), np.int64)
+        self._check(plm_get_graph(self._c, off.ctypes.data, col.ctypes.data, w.ctypes.data, PLM_MEM_HOST))
+        return off, col[: li.nnz], w[: li.nnz]
+
+    def stats(self) -> dict:
+        s = plm_stats_t()
+        self._check(plm_get_stats(self._c, ctypes.byref(s)))
+        L = s.levels
+        out = {"levels": L}
+        for f, _ in plm_stats_t._fields_[2:]:
+            out[f] = list(getattr(s, f))[:L]
+        return out

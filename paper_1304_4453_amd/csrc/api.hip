@@ -1,0 +1,715 @@
+// api.hip - the C ABI of libplm (include/plm.h) and the level engine behind it:
+// level set-up, schedule, sweeps, coarsening and the multilevel run of
+// Algorithm 3 with prolongation.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/plm.h"
+#include "level.h"
+
+using namespace plm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+T *dev_alloc(int64_t count) {
+    T *p = nullptr;
+    size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{PLM_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    return p;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+struct LevelData {
+    int64_t n = 0, nnz = 0;
+    int64_t *off = nullptr;
+    int32_t *col = nullptr;
+    void *w = nullptr;
+    int wkind = 0;
+    int diag_mult = 1;
+    int32_t *pi = nullptr;  // fine -> coarse map, set when this level is coarsened
+
+    GraphView view() const {
+        GraphView g;
+        g.n = n; g.nnz = nnz; g.off = off; g.col = col; g.w = w; g.wkind = wkind; g.diag_mult = diag_mult;
+        return g;
+    }
+    void release() {
+        dev_free(off); dev_free(col); dev_free(w); dev_free(pi);
+    }
+};
+
+__global__ void k_export_w(GraphView g, int64_t *out) {
+    int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (e0 >= g.nnz) return;
+    int64_t e1 = e0 + 16 < g.nnz ? e0 + 16 : g.nnz;
+    int64_t r = row_of(g.off, g.n, e0);
+    int64_t rend = g.off[r + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+        while (e >= rend) { ++r; rend = g.off[r + 1]; }
+        int64_t x = g.wkind == 0 ? 1 : (g.wkind == 1 ? (int64_t)((const int32_t *)g.w)[e] : ((const int64_t *)g.w)[e]);
+        if (g.col[e] == r) x *= g.diag_mult;
+        out[e] = x;
+    }
+}
+
+__global__ void k_count_loop_only(GraphView g, unsigned long long *cnt) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c = 0;
+    if (u < g.n) {
+        int64_t d = g.off[u + 1] - g.off[u];
+        c = (d == 1 && g.col[g.off[u]] == u) ? 1 : 0;
+    }
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
+    if (lane_id() == 0 && c) atomicAdd(cnt, (unsigned long long)c);
+}
+
+}  // namespace
+
+struct plm_ctx {
+    hipStream_t st = nullptr;
+    plm_options opt;
+    int mem_kind = PLM_MEM_HOST;
+    std::string err;
+    std::vector<LevelData> levels;  // [0] = private copy of the input
+    int cur = 0;
+    int64_t n0 = 0, S = 0;
+    // state of the current level (capacity n0)
+    int64_t *vol0 = nullptr, *vol = nullptr, *volC = nullptr;
+    int32_t *zeta = nullptr, *colour = nullptr, *class_nodes = nullptr, *move_to = nullptr, *lab = nullptr;
+    int64_t *bstart_dev = nullptr;
+    int64_t max_vol = 0, wide_lim = 0;
+    bool sched = false;
+    int32_t ncol = 0, jp_rounds = 0;
+    std::vector<int64_t> bstart;
+    std::vector<ClassRange> classes;
+    int64_t active_nodes = 0, active_entries = 0;
+    // hub arrays of the current level
+    int32_t *hub_pos = nullptr, *tab_bits = nullptr, *tab_key = nullptr, *done = nullptr;
+    int64_t *tab_off = nullptr, *ins_first = nullptr, *eval_first = nullptr, *eval_cnt = nullptr, *tab_val = nullptr,
+            *hub_wD = nullptr;
+    unsigned long long *part = nullptr;
+    int64_t hub_cap_slots = 0, hub_cap_part = 0, hub_cap_hubs = 0;
+    int32_t sweeps = 0;
+    unsigned long long *dcnt = nullptr;  // [moves, cand, S, maxvol, loop-only]
+    int64_t *hbuf = nullptr;             // pinned host scratch (64 int64)
+    Scratch scr;
+    plm_stats_t stats;
+    std::vector<hipEvent_t> events;
+
+    ~plm_ctx() {
+        for (auto &l : levels) l.release();
+        dev_free(vol0); dev_free(vol); dev_free(volC); dev_free(zeta); dev_free(colour); dev_free(class_nodes);
+        dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
+        free_hubs();
+        if (hbuf) (void)hipHostFree(hbuf);
+        for (auto e : events) (void)hipEventDestroy(e);
+    }
+    void free_hubs() {
+        dev_free(hub_pos); dev_free(tab_bits); dev_free(tab_key); dev_free(done); dev_free(tab_off);
+        dev_free(ins_first); dev_free(eval_first); dev_free(eval_cnt); dev_free(tab_val); dev_free(hub_wD);
+        dev_free(part);
+        hub_cap_slots = hub_cap_part = hub_cap_hubs = 0;
+    }
+
+    LevelData &L() { return levels[cur]; }
+
+    int64_t bin_lane() const { return opt.bin_lane > 0 ? opt.bin_lane : 16; }
+    int64_t bin_wave() const { return opt.bin_wave > 0 ? opt.bin_wave : 512; }
+    int64_t bin_block() const { return opt.bin_block > 0 ? opt.bin_block : 4096; }
+
+    // ---------------------------------------------------------------- level set-up
+    void init_level() {
+        LevelData &l = L();
+        GraphView g = l.view();
+        launch_volumes(g, vol, dcnt + 2, dcnt + 3, st);
+        HIPCHK(hipMemcpyAsync(hbuf, dcnt + 2, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        uint64_t s = (uint64_t)hbuf[0];
+        if (cur == 0) {
+            if (s >= (1ULL << 62)) throw Error{PLM_E_GRAPH, "total weight S = 2 w(E) must be below 2^62"};
+            S = (int64_t)s;
+            HIPCHK(hipMemcpyAsync(vol0, vol, l.n * 8, hipMemcpyDeviceToDevice, st));
+        } else if ((int64_t)s != S) {
+            throw Error{PLM_E_STATE, "internal: coarse graph changed the total weight"};
+        }
+        max_vol = hbuf[1];
+        wide_lim = S > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)S) : INT64_MAX;
+        if (opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
+            throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
+        launch_iota(zeta, l.n, st);
+        launch_copy_vol(volC, vol, l.n, st);
+        sched = false;
+        ncol = 0;
+        sweeps = 0;
+    }
+
+    void ensure_hub_capacity(int64_t hubs, int64_t slots, int64_t parts) {
+        if (hubs > hub_cap_hubs) {
+            dev_free(hub_pos); dev_free(tab_bits); dev_free(done); dev_free(tab_off); dev_free(ins_first);
+            dev_free(eval_first); dev_free(eval_cnt); dev_free(hub_wD);
+            hub_pos = dev_alloc<int32_t>(hubs); tab_bits = dev_alloc<int32_t>(hubs); done = dev_alloc<int32_t>(hubs);
+            tab_off = dev_alloc<int64_t>(hubs); ins_first = dev_alloc<int64_t>(hubs);
+            eval_first = dev_alloc<int64_t>(hubs); eval_cnt = dev_alloc<int64_t>(hubs); hub_wD = dev_alloc<int64_t>(hubs);
+            hub_cap_hubs = hubs;
+        }
+        if (slots > hub_cap_slots) {
+            dev_free(tab_key); dev_free(tab_val);
+            tab_key = dev_alloc<int32_t>(slots); tab_val = dev_alloc<int64_t>(slots);
+            HIPCHK(hipMemsetAsync(tab_key, 0xff, slots * 4, st));
+            HIPCHK(hipMemsetAsync(tab_val, 0, slots * 8, st));
+            hub_cap_slots = slots;
+        }
+        if (parts > hub_cap_part) {
+            dev_free(part);
+            part = dev_alloc<unsigned long long>(4 * parts);
+            hub_cap_part = parts;
+        }
+    }
+
+    void build_schedule() {
+        LevelData &l = L();
+        GraphView g = l.view();
+        ncol = build_colouring(g, opt.colour_seed, cur, opt.schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st);
+        int64_t nkeys = (int64_t)ncol * 4 + 1;
+        dev_free(bstart_dev);
+        bstart_dev = dev_alloc<int64_t>(nkeys + 1);
+        build_buckets(g, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, scr, st);
+        bstart.assign(nkeys + 1, 0);
+        if (l.n > 0) HIPCHK(hipMemcpyAsync(bstart.data(), bstart_dev, (nkeys + 1) * 8, hipMemcpyDeviceToHost, st));
+        // active entries = nnz minus rows made of a single self-loop
+        HIPCHK(hipMemsetAsync(dcnt + 4, 0, 8, st));
+        if (l.n > 0)
+            hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 4);
+        HIPCHK(hipMemcpyAsync(hbuf + 8, dcnt + 4, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        active_nodes = l.n > 0 ? bstart[(size_t)ncol * 4] : 0;
+        active_entries = l.nnz - hbuf[8];
+        // hubs: degrees to the host, then per-hub table and block layout
+        classes.assign(ncol, ClassRange());
+        int64_t H = 0;
+        for (int32_t c = 0; c < ncol; ++c) H += bstart[4 * c + 4] - bstart[4 * c + 3];
+        std::vector<int64_t> deg(H > 0 ? H : 1), pos;
+        pos.reserve(H);
+        if (H > 0) {
+            scr.reserve(align_up(H * 8));
+            int64_t *ddeg = (int64_t *)scr.get(H * 8);
+            int64_t o = 0;
+            for (int32_t c = 0; c < ncol; ++c) {
+                int64_t b = bstart[4 * c + 3], cnt = bstart[4 * c + 4] - b;
+                if (cnt > 0) launch_hub_degrees(g, class_nodes, b, cnt, ddeg + o, st);
+                for (int64_t i = 0; i < cnt; ++i) pos.push_back(b + i);
+                o += cnt;
+            }
+            HIPCHK(hipMemcpyAsync(deg.data(), ddeg, H * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        std::vector<int32_t> hpos(H > 0 ? H : 1), hbits(H > 0 ? H : 1);
+        std::vector<int64_t> toff(H > 0 ? H : 1), ifirst(H > 0 ? H : 1), efirst(H > 0 ? H : 1), ecnt(H > 0 ? H : 1);
+        int64_t max_slots = 0, max_parts = 0, hg = 0;
+        for (int32_t c = 0; c < ncol; ++c) {
+            ClassRange &cr = classes[c];
+            for (int b = 0; b < 4; ++b) {
+                cr.begin[b] = bstart[4 * c + b];
+                cr.count[b] = bstart[4 * c + b + 1] - bstart[4 * c + b];
+            }
+            cr.hub_first = hg;
+            cr.hub_count = cr.count[3];
+            int64_t slots = 0, ib = 0, eb = 0;
+            for (int64_t i = 0; i < cr.hub_count; ++i, ++hg) {
+                int bits = ceil_log2((uint64_t)(2 * deg[hg]));
+                if (bits < kHubMinBits) bits = kHubMinBits;
+                int64_t ts = 1LL << bits;
+                hpos[hg] = (int32_t)pos[hg];
+                hbits[hg] = bits;
+                toff[hg] = slots;
+                ifirst[hg] = ib;
+                efirst[hg] = eb;
+                ecnt[hg] = cdiv(ts, kHubEvalChunk);
+                slots += ts;
+                ib += cdiv(deg[hg], kHubInsChunk);
+                eb += ecnt[hg];
+            }
+            cr.ins_blocks = ib;
+            cr.eval_blocks = eb;
+            max_slots = slots > max_slots ? slots : max_slots;
+            max_parts = eb > max_parts ? eb : max_parts;
+        }
+        if (H > 0) {
+            ensure_hub_capacity(H, max_slots, max_parts);
+            HIPCHK(hipMemcpyAsync(hub_pos, hpos.data(), H * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(tab_bits, hbits.data(), H * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(tab_off, toff.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(ins_first, ifirst.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(eval_first, efirst.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(eval_cnt, ecnt.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(done, 0, H * 4, st));
+            HIPCHK(hipMemsetAsync(hub_wD, 0, H * 8, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        sched = true;
+        if (opt.timing && events.size() < 2 * (size_t)ncol) {
+            size_t old = events.size();
+            events.resize(2 * (size_t)ncol);
+            for (size_t i = old; i < events.size(); ++i) HIPCHK(hipEventCreate(&events[i]));
+        }
+    }
+
+    MoveState move_state(bool count_cand) {
+        MoveState ms;
+        ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
+        ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
+        return ms;
+    }
+    HubArrays hub_arrays() {
+        HubArrays ha;
+        ha.hub_pos = hub_pos; ha.tab_off = tab_off; ha.tab_bits = tab_bits; ha.ins_first = ins_first;
+        ha.eval_first = eval_first; ha.eval_cnt = eval_cnt; ha.tab_key = tab_key; ha.tab_val = tab_val;
+        ha.part = part; ha.done = done; ha.hub_wD = hub_wD;
+        return ha;
+    }
+
+    // ---------------------------------------------------------------- sweeps
+    int64_t run_classes(int32_t c0, int32_t c1) {
+        if (!sched) build_schedule();
+        HIPCHK(hipMemsetAsync(dcnt, 0, 16, st));
+        bool timing = opt.timing != 0;
+        MoveState ms = move_state(timing);
+        HubArrays ha = hub_arrays();
+        GraphView g = L().view();
+        bool fw = opt.int_mode == PLM_INT_128;
+        for (int32_t c = c0; c < c1; ++c) {
+            const ClassRange &cr = classes[c];
+            hipEvent_t e0 = timing ? events[2 * c] : nullptr, e1 = timing ? events[2 * c + 1] : nullptr;
+            launch_class_step(g, ms, cr, ha, fw, e0, e1, st);
+            launch_apply(ms, cr.begin[0], cr.begin[3] + cr.count[3] - cr.begin[0], st);
+        }
+        HIPCHK(hipMemcpyAsync(hbuf, dcnt, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t moves = hbuf[0];
+        if (timing && cur < PLM_MAX_LEVELS) {
+            double ms_sum = 0;
+            for (int32_t c = c0; c < c1; ++c) {
+                float t = 0;
+                HIPCHK(hipEventElapsedTime(&t, events[2 * c], events[2 * c + 1]));
+                ms_sum += t;
+            }
+            int wb = L().wkind == 0 ? 0 : (L().wkind == 1 ? 4 : 8);
+            double bytes = 0;
+            if (c0 == 0 && c1 == ncol)  // whole sweep: every active node once
+                bytes = (double)active_entries * (8.0 + wb) + 8.0 * (double)hbuf[1] + 32.0 * (double)active_nodes;
+            stats.decide_ms[cur] += ms_sum;
+            stats.decide_launches[cur] += (c1 - c0);
+            stats.decide_bytes[cur] += bytes;
+        }
+        return moves;
+    }
+
+    int64_t sweep() {
+        int64_t mv = run_classes(0, ncol_or_build());
+        ++sweeps;
+        return mv;
+    }
+    int32_t ncol_or_build() {
+        if (!sched) build_schedule();
+        return ncol;
+    }
+
+    // ---------------------------------------------------------------- coarsening
+    int64_t coarsen() {
+        LevelData &l = L();
+        dev_free(l.pi);
+        l.pi = dev_alloc<int32_t>(l.n);
+        int64_t k = build_relabel(zeta, l.n, l.pi, scr, hbuf, st);
+        LevelData nl;
+        nl.n = k;
+        nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st);
+        nl.wkind = 2;
+        nl.diag_mult = 1;
+        // drop any deeper levels left from an earlier run
+        while ((int)levels.size() > cur + 1) {
+            levels.back().release();
+            levels.pop_back();
+        }
+        levels.push_back(nl);
+        ++cur;
+        init_level();
+        return k;
+    }
+
+    void reset() {
+        while (levels.size() > 1) {
+            levels.back().release();
+            levels.pop_back();
+        }
+        dev_free(levels[0].pi);
+        cur = 0;
+        std::memset(&stats, 0, sizeof(stats));
+        init_level();
+    }
+
+    void record_level(int64_t communities, double t_sched, double t_sweep, double t_coarsen, int64_t moves) {
+        if (cur >= PLM_MAX_LEVELS) return;
+        stats.levels = cur + 1;
+        stats.n[cur] = L().n;
+        stats.nnz[cur] = L().nnz;
+        stats.colours[cur] = ncol;
+        stats.sweeps[cur] = sweeps;
+        stats.communities[cur] = communities;
+        stats.moves[cur] = moves;
+        stats.schedule_ms[cur] = t_sched;
+        stats.sweep_ms[cur] = t_sweep;
+        stats.coarsen_ms[cur] += t_coarsen;
+    }
+
+    // Algorithm 3 from level 0; leaves canonical labels in lab_out (device)
+    int32_t run(int32_t *lab_out) {
+        reset();
+        int32_t done_levels = 0;
+        for (;;) {
+            double t0 = now_ms();
+            build_schedule();
+            double t1 = now_ms();
+            int64_t moves = 0;
+            for (int32_t s = 0; s < opt.max_sweeps; ++s) {
+                int64_t mv = sweep();
+                moves += mv;
+                if (mv == 0) break;
+            }
+            double t2 = now_ms();
+            ++done_levels;
+            bool last_allowed = opt.max_levels > 0 && done_levels >= opt.max_levels;
+            int64_t k = count_communities(zeta, L().n, scr, hbuf, st);
+            if (k == L().n || last_allowed) {
+                record_level(k, t1 - t0, t2 - t1, 0, moves);
+                break;
+            }
+            record_level(k, t1 - t0, t2 - t1, 0, moves);
+            double t3 = now_ms();
+            int prev = cur;
+            coarsen();
+            if (prev < PLM_MAX_LEVELS) stats.coarsen_ms[prev] = now_ms() - t3;
+        }
+        // prolong: input node -> current level node -> community
+        int64_t n = n0;
+        if (n > 0) {
+            if (cur == 0) {
+                HIPCHK(hipMemcpyAsync(lab, zeta, n * 4, hipMemcpyDeviceToDevice, st));
+            } else {
+                HIPCHK(hipMemcpyAsync(lab, levels[0].pi, n * 4, hipMemcpyDeviceToDevice, st));
+                for (int l = 1; l < cur; ++l) launch_compose(lab, levels[l].pi, n, st);
+                launch_compose(lab, zeta, n, st);
+            }
+            build_canonical(lab, n, lab_out, scr, st);
+        }
+        return done_levels;
+    }
+
+    double modularity_of(const int32_t *labels_dev) {
+        __int128 num, den;
+        if (modularity_parts(levels[0].view(), vol0, labels_dev, S, scr, hbuf, &num, &den, st) != 0)
+            throw Error{PLM_E_ARG, "labels must lie in [0, n)"};
+        if (S == 0) return 0.0;
+        return (double)num / (double)den;
+    }
+};
+
+// ------------------------------------------------------------------ C ABI
+namespace {
+
+int check_options(const plm_options &o, std::string &msg) {
+    if (o.max_sweeps < 1) { msg = "max_sweeps must be >= 1"; return PLM_E_ARG; }
+    if (o.max_levels < 0) { msg = "max_levels must be >= 0"; return PLM_E_ARG; }
+    if (o.schedule != PLM_SCHEDULE_COLOUR && o.schedule != PLM_SCHEDULE_SEQUENTIAL) { msg = "bad schedule"; return PLM_E_ARG; }
+    if (o.int_mode < 0 || o.int_mode > 2) { msg = "bad int_mode"; return PLM_E_ARG; }
+    int64_t a = o.bin_lane > 0 ? o.bin_lane : 16, b = o.bin_wave > 0 ? o.bin_wave : 512,
+            c = o.bin_block > 0 ? o.bin_block : 4096;
+    if (a > 16 || b > 512 || c > 4096 || a > b || b > c) {
+        msg = "bins must satisfy bin_lane <= 16, bin_lane <= bin_wave <= 512, bin_wave <= bin_block <= 4096";
+        return PLM_E_ARG;
+    }
+    return PLM_OK;
+}
+
+template <typename F>
+plm_status guarded(plm_ctx *ctx, F f) {
+    if (!ctx) return PLM_E_ARG;
+    try {
+        ctx->err.clear();
+        f();
+        return PLM_OK;
+    } catch (const Error &e) {
+        ctx->err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        ctx->err = e.what();
+        return PLM_E_NOMEM;
+    }
+}
+
+void copy_in(void *dst, const void *src, size_t bytes, int mem_kind, hipStream_t st) {
+    if (bytes == 0) return;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          st));
+}
+void copy_out(void *dst, const void *src, size_t bytes, int mem_kind, hipStream_t st) {
+    if (bytes == 0) return;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          st));
+}
+
+}  // namespace
+
+extern "C" {
+
+void plm_default_options(plm_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_sweeps = 32;
+    o->max_levels = 0;
+    o->schedule = PLM_SCHEDULE_COLOUR;
+    o->validate = 1;
+    o->colour_seed = 0;
+    o->int_mode = PLM_INT_AUTO;
+    o->bin_lane = 16;
+    o->bin_wave = 512;
+    o->bin_block = 4096;
+    o->timing = 0;
+}
+
+plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                      const int32_t *weights, int32_t mem_kind, void *hip_stream, const plm_options *opt) {
+    g_create_error.clear();
+    if (out) *out = nullptr;
+    auto fail = [&](int code, const std::string &m) {
+        g_create_error = m;
+        return code;
+    };
+    if (!out) return fail(PLM_E_ARG, "out is NULL");
+    if (n < 0 || n >= (1LL << 31)) return fail(PLM_E_ARG, "n must lie in [0, 2^31)");
+    if (nnz < 0 || nnz >= (1LL << 40)) return fail(PLM_E_ARG, "nnz must lie in [0, 2^40)");
+    if (!offsets) return fail(PLM_E_ARG, "offsets is NULL");
+    if (nnz > 0 && !cols) return fail(PLM_E_ARG, "cols is NULL");
+    if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) return fail(PLM_E_ARG, "bad mem_kind");
+    plm_options o;
+    plm_default_options(&o);
+    if (opt) o = *opt;
+    std::string m;
+    int rc = check_options(o, m);
+    if (rc) return fail(rc, m);
+    if (mem_kind == PLM_MEM_HOST) {
+        if (offsets[0] != 0 || offsets[n] != nnz) return fail(PLM_E_GRAPH, "offsets[0] must be 0 and offsets[n] = nnz");
+    }
+    plm_ctx *c = nullptr;
+    try {
+        c = new plm_ctx();
+        std::memset(&c->stats, 0, sizeof(c->stats));
+        c->st = (hipStream_t)hip_stream;
+        c->opt = o;
+        c->mem_kind = mem_kind;
+        c->n0 = n;
+        HIPCHK(hipHostMalloc((void **)&c->hbuf, 64 * sizeof(int64_t), hipHostMallocDefault));
+        LevelData l0;
+        l0.n = n;
+        l0.nnz = nnz;
+        l0.off = dev_alloc<int64_t>(n + 1);
+        l0.col = dev_alloc<int32_t>(nnz);
+        l0.wkind = weights ? 1 : 0;
+        l0.diag_mult = 2;
+        if (weights) l0.w = dev_alloc<int32_t>(nnz);
+        c->levels.push_back(l0);
+        copy_in(l0.off, offsets, (size_t)(n + 1) * 8, mem_kind, c->st);
+        copy_in(l0.col, cols, (size_t)nnz * 4, mem_kind, c->st);
+        if (weights) copy_in(l0.w, weights, (size_t)nnz * 4, mem_kind, c->st);
+        HIPCHK(hipStreamSynchronize(c->st));
+        if (o.validate) {
+            uint32_t bad = validate_graph(l0.view(), c->scr, c->hbuf, c->st);
+            if (bad) {
+                std::string why;
+                if (bad & 16u) why += " offsets not monotone or not spanning [0, nnz];";
+                if (bad & 1u) why += " column index out of range;";
+                if (bad & 2u) why += " non-positive weight;";
+                if (bad & 4u) why += " row not strictly ascending (duplicate or unsorted);";
+                if (bad & 8u) why += " not symmetric (missing or unequal mirror entry);";
+                throw Error{PLM_E_GRAPH, "invalid graph:" + why};
+            }
+        }
+        c->vol0 = dev_alloc<int64_t>(n);
+        c->vol = dev_alloc<int64_t>(n);
+        c->volC = dev_alloc<int64_t>(n);
+        c->zeta = dev_alloc<int32_t>(n);
+        c->colour = dev_alloc<int32_t>(n);
+        c->class_nodes = dev_alloc<int32_t>(n);
+        c->move_to = dev_alloc<int32_t>(n);
+        c->lab = dev_alloc<int32_t>(n);
+        c->dcnt = dev_alloc<unsigned long long>(8);
+        HIPCHK(hipMemsetAsync(c->dcnt, 0, 64, c->st));
+        c->init_level();
+    } catch (const Error &e) {
+        delete c;
+        return fail(e.code, e.msg);
+    } catch (const std::exception &e) {
+        delete c;
+        return fail(PLM_E_NOMEM, e.what());
+    }
+    *out = c;
+    return PLM_OK;
+}
+
+plm_status plm_move_sweep(plm_ctx *ctx, int64_t *moves_out) {
+    return guarded(ctx, [&] {
+        int64_t mv = ctx->sweep();
+        if (moves_out) *moves_out = mv;
+    });
+}
+
+plm_status plm_move_class(plm_ctx *ctx, int32_t c, int64_t *moves_out) {
+    return guarded(ctx, [&] {
+        int32_t nc = ctx->ncol_or_build();
+        if (c < 0 || c >= nc) throw Error{PLM_E_ARG, "class index out of range"};
+        int64_t mv = ctx->run_classes(c, c + 1);
+        if (moves_out) *moves_out = mv;
+    });
+}
+
+plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out) {
+    return guarded(ctx, [&] {
+        int64_t k = ctx->coarsen();
+        if (n_coarse_out) *n_coarse_out = k;
+    });
+}
+
+plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out) {
+    return guarded(ctx, [&] {
+        int64_t n = ctx->n0;
+        int32_t *canon = dev_alloc<int32_t>(n);
+        try {
+            int32_t lv = ctx->run(canon);
+            double q = 0.0;
+            if (q_out) q = ctx->modularity_of(canon);
+            if (labels) copy_out(labels, canon, (size_t)n * 4, ctx->mem_kind, ctx->st);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            if (q_out) *q_out = q;
+            if (levels_out) *levels_out = lv;
+        } catch (...) {
+            dev_free(canon);
+            throw;
+        }
+        dev_free(canon);
+    });
+}
+
+plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind, double *q_out) {
+    return guarded(ctx, [&] {
+        if (!labels && ctx->n0 > 0) throw Error{PLM_E_ARG, "labels is NULL"};
+        if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) throw Error{PLM_E_ARG, "bad mem_kind"};
+        int64_t n = ctx->n0;
+        const int32_t *dl = labels;
+        int32_t *tmp = nullptr;
+        if (mem_kind == PLM_MEM_HOST && n > 0) {
+            tmp = dev_alloc<int32_t>(n);
+            HIPCHK(hipMemcpyAsync(tmp, labels, n * 4, hipMemcpyHostToDevice, ctx->st));
+            dl = tmp;
+        }
+        try {
+            double q = ctx->modularity_of(dl);
+            if (q_out) *q_out = q;
+        } catch (...) {
+            dev_free(tmp);
+            throw;
+        }
+        dev_free(tmp);
+    });
+}
+
+plm_status plm_reset(plm_ctx *ctx) {
+    return guarded(ctx, [&] { ctx->reset(); });
+}
+
+void plm_destroy(plm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->st);
+    delete ctx;
+}
+
+const char *plm_last_error(const plm_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+plm_status plm_level_info(plm_ctx *ctx, plm_level_info_t *out) {
+    return guarded(ctx, [&] {
+        if (!out) throw Error{PLM_E_ARG, "out is NULL"};
+        LevelData &l = ctx->L();
+        out->level = ctx->cur;
+        out->colours = ctx->sched ? ctx->ncol : 0;
+        out->n = l.n;
+        out->nnz = l.nnz;
+        out->S = ctx->S;
+        out->sweeps = ctx->sweeps;
+        out->weight_kind = l.wkind;
+        out->communities = count_communities(ctx->zeta, l.n, ctx->scr, ctx->hbuf, ctx->st);
+        out->max_vol = ctx->max_vol;
+    });
+}
+
+plm_status plm_get_state(plm_ctx *ctx, int32_t *zeta, int64_t *volc, int32_t *colour, int32_t mem_kind) {
+    return guarded(ctx, [&] {
+        if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) throw Error{PLM_E_ARG, "bad mem_kind"};
+        int64_t n = ctx->L().n;
+        if (colour && !ctx->sched) ctx->build_schedule();
+        if (zeta) copy_out(zeta, ctx->zeta, n * 4, mem_kind, ctx->st);
+        if (volc) copy_out(volc, ctx->volC, n * 8, mem_kind, ctx->st);
+        if (colour) copy_out(colour, ctx->colour, n * 4, mem_kind, ctx->st);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    });
+}
+
+plm_status plm_get_graph(plm_ctx *ctx, int64_t *offsets, int32_t *cols, int64_t *weights, int32_t mem_kind) {
+    return guarded(ctx, [&] {
+        if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) throw Error{PLM_E_ARG, "bad mem_kind"};
+        LevelData &l = ctx->L();
+        if (offsets) copy_out(offsets, l.off, (l.n + 1) * 8, mem_kind, ctx->st);
+        if (cols) copy_out(cols, l.col, l.nnz * 4, mem_kind, ctx->st);
+        if (weights && l.nnz > 0) {
+            if (l.wkind == 2 && l.diag_mult == 1) {
+                copy_out(weights, l.w, l.nnz * 8, mem_kind, ctx->st);
+            } else {
+                int64_t *tmp = dev_alloc<int64_t>(l.nnz);
+                hipLaunchKernelGGL(k_export_w, dim3((unsigned)cdiv(cdiv(l.nnz, 16), 256)), dim3(256), 0, ctx->st,
+                                   l.view(), tmp);
+                copy_out(weights, tmp, l.nnz * 8, mem_kind, ctx->st);
+                HIPCHK(hipStreamSynchronize(ctx->st));
+                dev_free(tmp);
+            }
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    });
+}
+
+plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out) {
+    return guarded(ctx, [&] {
+        if (!out) throw Error{PLM_E_ARG, "out is NULL"};
+        *out = ctx->stats;
+    });
+}
+
+}  // extern "C"

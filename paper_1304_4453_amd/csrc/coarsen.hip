@@ -1,0 +1,413 @@
+// coarsen.hip - contraction of communities into a coarse graph (section III-B,
+// implementation of coarsen), prolongation, canonical labels, modularity
+// (Equation (3.1)) and input validation.
+#include <hip/hip_runtime.h>
+
+#include "level.h"
+
+namespace plm {
+
+constexpr int kT = 256;
+constexpr int kChunk = 16;
+
+// ------------------------------------------------------------------ relabel
+__global__ void k_flag_present(const int32_t *zeta, int64_t n, int32_t *flag) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) flag[zeta[u]] = 1;
+}
+__global__ void k_apply_map(const int32_t *zeta, const int64_t *newid, int64_t n, int32_t *pi) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) pi[u] = (int32_t)newid[zeta[u]];
+}
+
+// Coarse ids ascend with the community ids: newid = exclusive prefix sum of
+// the "community is non-empty" flags.
+int64_t build_relabel(const int32_t *zeta, int64_t n, int32_t *pi, Scratch &scr, int64_t *host_i64,
+                      hipStream_t st) {
+    if (n == 0) return 0;
+    scr.reserve(align_up(n * 4) + align_up(n * 8) + 256 + scan_scratch_bytes(n));
+    int32_t *flag = (int32_t *)scr.get(n * 4);
+    int64_t *newid = (int64_t *)scr.get(n * 8);
+    int64_t *total = (int64_t *)scr.get(8);
+    void *ss = scr.get(scan_scratch_bytes(n));
+    HIPCHK(hipMemsetAsync(flag, 0, n * 4, st));
+    hipLaunchKernelGGL(k_flag_present, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, zeta, n, flag);
+    exclusive_scan_i32(flag, newid, n, total, ss, st);
+    hipLaunchKernelGGL(k_apply_map, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, zeta, newid, n, pi);
+    HIPCHK(hipMemcpyAsync(host_i64, total, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return host_i64[0];
+}
+
+int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t *host_i64, hipStream_t st) {
+    if (n == 0) return 0;
+    scr.reserve(align_up(n * 4) + align_up(n * 8) + 256 + scan_scratch_bytes(n));
+    int32_t *flag = (int32_t *)scr.get(n * 4);
+    int64_t *tmp = (int64_t *)scr.get(n * 8);
+    int64_t *total = (int64_t *)scr.get(8);
+    void *ss = scr.get(scan_scratch_bytes(n));
+    HIPCHK(hipMemsetAsync(flag, 0, n * 4, st));
+    hipLaunchKernelGGL(k_flag_present, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, zeta, n, flag);
+    exclusive_scan_i32(flag, tmp, n, total, ss, st);
+    HIPCHK(hipMemcpyAsync(host_i64, total, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return host_i64[0];
+}
+
+// ------------------------------------------------------------------ contraction
+// key = (pi(u) << b) | pi(v), value = entry weight (self-loops times diag_mult,
+// so the coarse diagonal is again "doubled").
+template <int WK>
+__global__ __launch_bounds__(kT) void k_contract_keys(GraphView g, const int32_t *pi, int b, uint64_t *keys,
+                                                      int64_t *vals) {
+    int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * kChunk;
+    if (e0 >= g.nnz) return;
+    int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
+    int64_t r = row_of(g.off, g.n, e0);
+    int64_t rend = g.off[r + 1];
+    uint64_t pr = (uint64_t)pi[r];
+    for (int64_t e = e0; e < e1; ++e) {
+        while (e >= rend) {
+            ++r;
+            rend = g.off[r + 1];
+            pr = (uint64_t)pi[r];
+        }
+        int32_t v = g.col[e];
+        int64_t x = wload<WK>(g.w, e);
+        if (v == r) x *= g.diag_mult;
+        keys[e] = (pr << b) | (uint64_t)pi[v];
+        vals[e] = x;
+    }
+}
+
+__global__ void k_head_flags(const uint64_t *keys, int64_t n, int32_t *head) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+// Reduce-by-key over sorted keys.  Run id of item i = incl_scan(head)[i] - 1 =
+// excl[i] + head[i] - 1.  Each thread folds its kChunk consecutive items into
+// per-run partial sums; partials are combined per block in LDS; a run that lies
+// wholly inside the block is stored, a run crossing a block edge is added
+// atomically (out_w zeroed first).
+constexpr int kRbkItems = kT * kChunk;
+__global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, const int64_t *vals, const int32_t *head,
+                                                      const int64_t *excl, int64_t n, uint64_t *out_k,
+                                                      int64_t *out_w) {
+    __shared__ int64_t acc[kRbkItems];
+    int64_t blk0 = (int64_t)blockIdx.x * kRbkItems;
+    int64_t blk1 = blk0 + kRbkItems < n ? blk0 + kRbkItems : n;
+    int64_t run0 = excl[blk0] + head[blk0] - 1;  // run id of the block's first item
+    for (int i = threadIdx.x; i < kRbkItems; i += kT) acc[i] = 0;
+    __syncthreads();
+    int64_t i0 = blk0 + (int64_t)threadIdx.x * kChunk;
+    if (i0 < blk1) {
+        int64_t i1 = i0 + kChunk < blk1 ? i0 + kChunk : blk1;
+        int64_t cur = excl[i0] + head[i0] - 1;
+        int64_t s = 0;
+        for (int64_t i = i0; i < i1; ++i) {
+            int64_t r = excl[i] + head[i] - 1;
+            if (r != cur) {
+                atomicAdd((unsigned long long *)&acc[cur - run0], (unsigned long long)s);
+                s = 0;
+                cur = r;
+            }
+            if (head[i]) out_k[r] = keys[i];
+            s += vals[i];
+        }
+        atomicAdd((unsigned long long *)&acc[cur - run0], (unsigned long long)s);
+    }
+    __syncthreads();
+    int64_t last_run = excl[blk1 - 1] + head[blk1 - 1] - 1;
+    int64_t nruns = last_run - run0 + 1;
+    bool first_complete = head[blk0] != 0;
+    bool last_complete = (blk1 == n) || head[blk1] != 0;
+    for (int64_t j = threadIdx.x; j < nruns; j += kT) {
+        bool whole = (j > 0 || first_complete) && (j < nruns - 1 || last_complete);
+        if (whole) out_w[run0 + j] = acc[j];
+        else atomicAdd((unsigned long long *)&out_w[run0 + j], (unsigned long long)acc[j]);
+    }
+}
+
+// coarse offsets: coff[r] = first unique entry with row >= r
+__global__ void k_coarse_csr(const uint64_t *ukeys, int64_t m, int b, int64_t k, int64_t *coff, int32_t *ccol) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > m) return;
+    uint64_t mask = (b >= 64) ? ~0ULL : ((1ULL << b) - 1);
+    int64_t prev = (i == 0) ? -1 : (int64_t)(ukeys[i - 1] >> b);
+    int64_t cur = (i == m) ? k : (int64_t)(ukeys[i] >> b);
+    if (i < m) ccol[i] = (int32_t)(ukeys[i] & mask);
+    for (int64_t r = prev + 1; r <= cur && r <= k; ++r) coff[r] = i;
+}
+
+int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff_out, int32_t **ccol_out,
+                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st) {
+    int64_t nnz = g.nnz;
+    int b = ceil_log2((uint64_t)(k > 1 ? k : 2));
+    int64_t nb = nnz > 0 ? nnz : 1;
+    scr.reserve(4 * align_up(nb * 8) + align_up(nb * 4) + align_up(nb * 8) + 256 +
+                (radix_scratch_bytes(nb) > scan_scratch_bytes(nb) ? radix_scratch_bytes(nb) : scan_scratch_bytes(nb)));
+    uint64_t *ka = (uint64_t *)scr.get(nb * 8), *kb = (uint64_t *)scr.get(nb * 8);
+    int64_t *va = (int64_t *)scr.get(nb * 8), *vb = (int64_t *)scr.get(nb * 8);
+    int32_t *head = (int32_t *)scr.get(nb * 4);
+    int64_t *excl = (int64_t *)scr.get(nb * 8);
+    int64_t *total = (int64_t *)scr.get(8);
+    size_t tmpb = radix_scratch_bytes(nb) > scan_scratch_bytes(nb) ? radix_scratch_bytes(nb) : scan_scratch_bytes(nb);
+    void *tmp = scr.get(tmpb);
+    int64_t *coff = nullptr;
+    int32_t *ccol = nullptr;
+    int64_t *cw = nullptr;
+    auto fail = [&](hipError_t e) {
+        if (coff) (void)hipFree(coff);
+        if (ccol) (void)hipFree(ccol);
+        if (cw) (void)hipFree(cw);
+        (void)hipGetLastError();
+        throw Error{-3, std::string("coarse graph allocation failed: ") + hipGetErrorString(e)};
+    };
+    hipError_t e = hipMalloc(&coff, (k + 1) * 8);
+    if (e != hipSuccess) fail(e);
+    if (nnz == 0) {
+        HIPCHK(hipMemsetAsync(coff, 0, (k + 1) * 8, st));
+        e = hipMalloc(&ccol, 4);
+        if (e != hipSuccess) fail(e);
+        e = hipMalloc(&cw, 8);
+        if (e != hipSuccess) fail(e);
+        *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
+        return 0;
+    }
+    dim3 grid((unsigned)cdiv(cdiv(nnz, kChunk), kT));
+    switch (g.wkind) {
+        case 0: hipLaunchKernelGGL(k_contract_keys<0>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
+        case 1: hipLaunchKernelGGL(k_contract_keys<1>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
+        default: hipLaunchKernelGGL(k_contract_keys<2>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
+    }
+    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b, tmp, st);
+    hipLaunchKernelGGL(k_head_flags, dim3((unsigned)cdiv(nnz, kT)), dim3(kT), 0, st, ka, nnz, head);
+    exclusive_scan_i32(head, excl, nnz, total, tmp, st);
+    HIPCHK(hipMemcpyAsync(host_i64, total, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t m = host_i64[0];
+    e = hipMalloc(&ccol, (m > 0 ? m : 1) * 4);
+    if (e != hipSuccess) fail(e);
+    e = hipMalloc(&cw, (m > 0 ? m : 1) * 8);
+    if (e != hipSuccess) fail(e);
+    // unique keys go to kb (free after the sort), summed weights to cw
+    HIPCHK(hipMemsetAsync(cw, 0, m * 8, st));
+    hipLaunchKernelGGL(k_reduce_by_key, dim3((unsigned)cdiv(nnz, kRbkItems)), dim3(kT), 0, st, ka, va, head, excl,
+                       nnz, kb, cw);
+    hipLaunchKernelGGL(k_coarse_csr, dim3((unsigned)cdiv(m + 1, kT)), dim3(kT), 0, st, kb, m, b, k, coff, ccol);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
+    return m;
+}
+
+// ------------------------------------------------------------------ prolongation / labels
+__global__ void k_compose(int32_t *lab, const int32_t *map, int64_t n) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) lab[v] = map[lab[v]];
+}
+void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_compose, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, lab, map, n);
+    HIPCHK(hipGetLastError());
+}
+__global__ void k_iota(int32_t *a, int64_t n) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) a[v] = (int32_t)v;
+}
+void launch_iota(int32_t *a, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, a, n);
+    HIPCHK(hipGetLastError());
+}
+void launch_copy_vol(int64_t *dst, const int64_t *src, int64_t n, hipStream_t st) {
+    if (n > 0) HIPCHK(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToDevice, st));
+}
+
+// canonical label of v = number of distinct labels whose first node precedes
+// the first node of v's label
+__global__ void k_first_min(const int32_t *lab, int64_t n, int32_t *first) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) atomicMin(&first[lab[v]], (int32_t)v);
+}
+__global__ void k_is_first(const int32_t *lab, const int32_t *first, int64_t n, int32_t *isf) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) isf[v] = first[lab[v]] == (int32_t)v ? 1 : 0;
+}
+__global__ void k_canon(const int32_t *lab, const int32_t *first, const int64_t *rank, int64_t n, int32_t *out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) out[v] = (int32_t)rank[first[lab[v]]];
+}
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t x) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) a[v] = x;
+}
+
+void build_canonical(const int32_t *lab, int64_t n, int32_t *out, Scratch &scr, hipStream_t st) {
+    if (n == 0) return;
+    scr.reserve(2 * align_up(n * 4) + align_up(n * 8) + scan_scratch_bytes(n));
+    int32_t *first = (int32_t *)scr.get(n * 4);
+    int32_t *isf = (int32_t *)scr.get(n * 4);
+    int64_t *rank = (int64_t *)scr.get(n * 8);
+    void *ss = scr.get(scan_scratch_bytes(n));
+    dim3 grid((unsigned)cdiv(n, kT));
+    hipLaunchKernelGGL(k_fill_i32, grid, dim3(kT), 0, st, first, n, (int32_t)0x7fffffff);
+    hipLaunchKernelGGL(k_first_min, grid, dim3(kT), 0, st, lab, n, first);
+    hipLaunchKernelGGL(k_is_first, grid, dim3(kT), 0, st, lab, first, n, isf);
+    exclusive_scan_i32(isf, rank, n, nullptr, ss, st);
+    hipLaunchKernelGGL(k_canon, grid, dim3(kT), 0, st, lab, first, rank, n, out);
+    HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ modularity
+__global__ void k_label_check(const int32_t *lab, int64_t n, int32_t *bad) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && (lab[v] < 0 || lab[v] >= n)) atomicOr(bad, 1);
+}
+__global__ void k_label_vol(const int32_t *lab, const int64_t *vol, int64_t n, int64_t *volL) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && vol[v]) atomicAdd((unsigned long long *)&volL[lab[v]], (unsigned long long)vol[v]);
+}
+// I2 = sum of intra-label entries with self-loops times diag_mult
+template <int WK>
+__global__ __launch_bounds__(kT) void k_intra(GraphView g, const int32_t *lab, unsigned long long *I2) {
+    int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * kChunk;
+    int64_t s = 0;
+    if (e0 < g.nnz) {
+        int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
+        int64_t r = row_of(g.off, g.n, e0);
+        int64_t rend = g.off[r + 1];
+        int32_t lr = lab[r];
+        for (int64_t e = e0; e < e1; ++e) {
+            while (e >= rend) {
+                ++r;
+                rend = g.off[r + 1];
+                lr = lab[r];
+            }
+            int32_t v = g.col[e];
+            if (lab[v] == lr) {
+                int64_t x = wload<WK>(g.w, e);
+                if (v == r) x *= g.diag_mult;
+                s += x;
+            }
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane_id() == 0 && s) atomicAdd(I2, (unsigned long long)s);
+}
+// sum of volL^2 as 128-bit: per-thread squares, wave sums, two-word atomic add
+__global__ __launch_bounds__(kT) void k_sum_sq(const int64_t *volL, int64_t n, unsigned long long *acc2) {
+    unsigned __int128 s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        unsigned __int128 x = (unsigned __int128)(uint64_t)volL[i];
+        s += x * x;
+    }
+    uint64_t lo = (uint64_t)s, hi = (uint64_t)(s >> 64);
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t olo = __shfl_xor(lo, d), ohi = __shfl_xor(hi, d);
+        uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1 : 0);
+        lo = nlo;
+    }
+    if (lane_id() == 0 && (lo || hi)) {
+        unsigned long long old = atomicAdd(&acc2[0], (unsigned long long)lo);
+        uint64_t carry = (old + lo < old) ? 1 : 0;
+        if (hi + carry) atomicAdd(&acc2[1], (unsigned long long)(hi + carry));
+    }
+}
+
+int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, Scratch &scr,
+                     int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st) {
+    int64_t n = g0.n;
+    *den = (__int128)S * (__int128)S;
+    if (n == 0) { *num = 0; return 0; }
+    scr.reserve(align_up(n * 8) + 4 * 256);
+    int64_t *volL = (int64_t *)scr.get(n * 8);
+    unsigned long long *cnt = (unsigned long long *)scr.get(4 * 8);  // [I2, sq lo, sq hi, bad]
+    HIPCHK(hipMemsetAsync(cnt, 0, 4 * 8, st));
+    HIPCHK(hipMemsetAsync(volL, 0, n * 8, st));
+    dim3 grid((unsigned)cdiv(n, kT));
+    hipLaunchKernelGGL(k_label_check, grid, dim3(kT), 0, st, labels, n, (int32_t *)(cnt + 3));
+    HIPCHK(hipMemcpyAsync(host_i64, cnt + 3, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (host_i64[0] != 0) return -1;
+    hipLaunchKernelGGL(k_label_vol, grid, dim3(kT), 0, st, labels, vol0, n, volL);
+    if (g0.nnz > 0) {
+        dim3 eg((unsigned)cdiv(cdiv(g0.nnz, kChunk), kT));
+        switch (g0.wkind) {
+            case 0: hipLaunchKernelGGL(k_intra<0>, eg, dim3(kT), 0, st, g0, labels, cnt); break;
+            case 1: hipLaunchKernelGGL(k_intra<1>, eg, dim3(kT), 0, st, g0, labels, cnt); break;
+            default: hipLaunchKernelGGL(k_intra<2>, eg, dim3(kT), 0, st, g0, labels, cnt); break;
+        }
+    }
+    int64_t nb = cdiv(n, kT);
+    hipLaunchKernelGGL(k_sum_sq, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(kT), 0, st, volL, n, cnt + 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host_i64, cnt, 3 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    unsigned __int128 sq = ((unsigned __int128)(uint64_t)host_i64[2] << 64) | (uint64_t)host_i64[1];
+    *num = (__int128)S * (__int128)host_i64[0] - (__int128)sq;
+    return 0;
+}
+
+// ------------------------------------------------------------------ validation
+// bit 1: col out of range; 2: non-positive weight; 4: row not strictly
+// ascending; 8: missing or unequal mirror entry; 16: offsets not monotone
+template <int WK>
+__global__ __launch_bounds__(kT) void k_validate(GraphView g, uint32_t *bad) {
+    int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= g.nnz) return;
+    int64_t r = row_of(g.off, g.n, e);
+    int32_t v = g.col[e];
+    uint32_t f = 0;
+    if (v < 0 || v >= g.n) {
+        atomicOr(bad, 1u);
+        return;
+    }
+    int64_t x = wload<WK>(g.w, e);
+    if (x <= 0) f |= 2u;
+    if (e > g.off[r] && g.col[e - 1] >= v) f |= 4u;
+    if (v != r) {
+        // binary search for r in row v
+        int64_t lo = g.off[v], hi = g.off[v + 1];
+        bool found = false;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int32_t c = g.col[mid];
+            if (c == r) { found = true; lo = mid; break; }
+            if (c < r) lo = mid + 1; else hi = mid;
+        }
+        if (!found || wload<WK>(g.w, lo) != x) f |= 8u;
+    }
+    if (f) atomicOr(bad, f);
+}
+__global__ void k_validate_off(const int64_t *off, int64_t n, int64_t nnz, uint32_t *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && off[i + 1] < off[i]) atomicOr(bad, 16u);
+    if (i == 0 && (off[0] != 0 || off[n] != nnz)) atomicOr(bad, 16u);
+}
+
+uint32_t validate_graph(const GraphView &g, Scratch &scr, int64_t *host_i64, hipStream_t st) {
+    scr.reserve(256);
+    uint32_t *bad = (uint32_t *)scr.get(8);
+    HIPCHK(hipMemsetAsync(bad, 0, 8, st));
+    hipLaunchKernelGGL(k_validate_off, dim3((unsigned)cdiv(g.n + 1, kT)), dim3(kT), 0, st, g.off, g.n, g.nnz, bad);
+    HIPCHK(hipMemcpyAsync(host_i64, bad, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (host_i64[0] & 0xffffffff) return (uint32_t)host_i64[0];
+    if (g.nnz > 0) {
+        dim3 grid((unsigned)cdiv(g.nnz, kT));
+        switch (g.wkind) {
+            case 0: hipLaunchKernelGGL(k_validate<0>, grid, dim3(kT), 0, st, g, bad); break;
+            case 1: hipLaunchKernelGGL(k_validate<1>, grid, dim3(kT), 0, st, g, bad); break;
+            default: hipLaunchKernelGGL(k_validate<2>, grid, dim3(kT), 0, st, g, bad); break;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host_i64, bad, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return (uint32_t)(host_i64[0] & 0xffffffff);
+}
+
+}  // namespace plm

@@ -1,0 +1,90 @@
+// level.h - launchers of the per-level kernels, the move sweep and coarsening.
+#pragma once
+
+#include "plm_internal.h"
+
+namespace plm {
+
+// ---- level.hip
+void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev, unsigned long long *maxvol_dev,
+                    hipStream_t st);
+// Colours the level (schedule 0: Jones-Plassmann; 1: priority rank) into
+// colour[n]; returns the number of classes.  host_counters: 8 pinned int32.
+int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int schedule, int32_t *colour,
+                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st);
+// Sorts nodes by (colour, degree bin) into class_nodes; bstart_dev[4*ncol+2]
+// receives bucket starts (bucket 4c+b = bin b of class c; bucket 4*ncol holds
+// nodes that cannot move).
+void build_buckets(const GraphView &g, const int32_t *colour, int32_t ncol, int64_t b0, int64_t b1, int64_t b2,
+                   int32_t *class_nodes, int64_t *bstart_dev, Scratch &scr, hipStream_t st);
+
+// ---- move.hip
+struct MoveState {
+    int32_t *zeta;         // community of each node
+    int64_t *volC;         // community volumes
+    const int64_t *vol;    // node volumes
+    const int32_t *class_nodes;
+    int32_t *move_to;      // per class position: target community or -1
+    int64_t S;
+    int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
+    unsigned long long *moves_dev;  // move counter
+    unsigned long long *cand_dev;   // distinct candidates evaluated (may be null)
+};
+
+// One class step: decide (per bin) then apply.  Counts (bin sizes) come from
+// the host copy of the bucket starts.
+struct ClassRange {
+    int64_t begin[4], count[4];  // per bin
+    // hubs of this class in the level's hub arrays
+    int64_t hub_first = 0, hub_count = 0;
+    int64_t ins_blocks = 0, eval_blocks = 0;
+};
+
+struct HubArrays {
+    const int32_t *hub_pos;    // class position
+    const int64_t *tab_off;    // slot offset within the class area
+    const int32_t *tab_bits;
+    const int64_t *ins_first;  // first insert block (class-relative), per hub, +1 sentinel per class
+    const int64_t *eval_first;
+    const int64_t *eval_cnt;   // eval blocks of each hub
+    int32_t *tab_key;          // class area (keys, -1 = empty)
+    int64_t *tab_val;
+    unsigned long long *part;  // per eval block: 4 words (score hi, score lo, X, pad)
+    int32_t *done;             // per hub completion counter (zero between uses)
+    int64_t *hub_wD;           // per hub w(u, D \ u) found by the eval blocks (zero between uses)
+};
+
+constexpr int64_t kHubInsChunk = 4096;   // entries per hub insert workgroup
+constexpr int64_t kHubEvalChunk = 4096;  // table slots per hub eval workgroup
+constexpr int kHubMinBits = 12;
+
+void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
+                       bool force_wide, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
+void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
+void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, int64_t begin, int64_t count,
+                        int64_t *deg_out, hipStream_t st);
+
+// ---- coarsen.hip
+// pi[u] = rank of zeta[u] among non-empty communities; returns k.
+int64_t build_relabel(const int32_t *zeta, int64_t n, int32_t *pi, Scratch &scr, int64_t *host_i64,
+                      hipStream_t st);
+// Contracts g by pi into a coarse CSR (doubled diagonal, int64 weights, rows
+// ascending).  Allocates *coff/*ccol/*cw with hipMalloc.  Returns nnz'.
+int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff, int32_t **ccol,
+                          int64_t **cw, Scratch &scr, int64_t *host_i64, hipStream_t st);
+// lab[v] = map[lab[v]] for v < n
+void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st);
+void launch_iota(int32_t *a, int64_t n, hipStream_t st);
+void launch_copy_vol(int64_t *dst, const int64_t *src, int64_t n, hipStream_t st);
+// canonical relabel by first occurrence, into out
+void build_canonical(const int32_t *lab, int64_t n, int32_t *out, Scratch &scr, hipStream_t st);
+// numerator/denominator of Equation (3.1) on level 0 for labels; returns
+// status 0, or -1 when a label is out of range
+int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, Scratch &scr,
+                     int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st);
+// counts distinct values of zeta
+int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t *host_i64, hipStream_t st);
+// validation of an input CSR; returns 0 or an error code bit set
+uint32_t validate_graph(const GraphView &g, Scratch &scr, int64_t *host_i64, hipStream_t st);
+
+}  // namespace plm

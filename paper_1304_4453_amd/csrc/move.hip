@@ -1,0 +1,522 @@
+// move.hip - the move-decide and apply kernels of one colour class
+// (Algorithm 2 under the colour-class schedule).
+//
+// For node u in community D every neighbouring community X != D is scored by
+//   gain(X) = S (w(u,X) - w(u,D\u)) - vol(u) (vol(X) - vol(D\u))
+// (2 w(E)^2 times Delta-mod of section III-B).  The kernels rank candidates by
+//   s(X) = S w(u,X) - vol(u) vol(X)
+// which differs from gain(X) by the constant K = S w(u,D\u) - vol(u) vol(D\u),
+// so the best candidate is the same and the move happens iff s_best > K.
+// |s|, |K| <= S vol(u): 64-bit arithmetic is exact while S vol(u) < 2^62,
+// otherwise the node takes the 128-bit path.  Ties go to the lowest X.
+//
+// Degree bins: rows up to 16 entries are handled one lane per node (register
+// arrays), up to the wave limit one wavefront per node (LDS hash table), up to
+// the block limit one workgroup per node (LDS hash table), and longer rows
+// ("hubs") by several workgroups per node through a global hash table.
+#include <hip/hip_runtime.h>
+
+#include "level.h"
+
+namespace plm {
+
+typedef __int128 i128;
+constexpr int32_t kNone = 0x7fffffff;
+
+__device__ __forceinline__ uint32_t slot_hash(int32_t x, int bits) {
+    return ((uint32_t)x * 2654435769u) >> (32 - bits);
+}
+
+template <typename G>
+__device__ __forceinline__ G neg_inf();
+template <>
+__device__ __forceinline__ int64_t neg_inf<int64_t>() { return INT64_MIN; }
+template <>
+__device__ __forceinline__ i128 neg_inf<i128>() { return -(((i128)1) << 126); }
+
+template <typename G>
+__device__ __forceinline__ G shfl_xor_g(G x, int d);
+template <>
+__device__ __forceinline__ int64_t shfl_xor_g<int64_t>(int64_t x, int d) { return __shfl_xor(x, d); }
+template <>
+__device__ __forceinline__ i128 shfl_xor_g<i128>(i128 x, int d) {
+    int64_t hi = (int64_t)(x >> 64);
+    uint64_t lo = (uint64_t)x;
+    hi = __shfl_xor(hi, d);
+    lo = __shfl_xor(lo, d);
+    return (i128)(((unsigned __int128)(uint64_t)hi << 64) | lo);
+}
+
+// (s desc, X asc) argmax over the wavefront
+template <typename G>
+__device__ __forceinline__ void wave_argmax(G &s, int32_t &x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        G os = shfl_xor_g<G>(s, d);
+        int32_t ox = __shfl_xor(x, d);
+        if (os > s || (os == s && ox < x)) { s = os; x = ox; }
+    }
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+__device__ __forceinline__ void count_candidates(unsigned long long *cand, int64_t c) {
+    if (!cand) return;
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(cand, (unsigned long long)c);
+}
+
+// ------------------------------------------------------------------ lane per node
+constexpr int kLaneMax = 16;
+
+template <int WK, typename G>
+__device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const int64_t (&W)[kLaneMax], int32_t D,
+                                             int64_t wD, int64_t vu, int64_t base, int64_t S, const int64_t *volC) {
+    G bg = 0;
+    int32_t bx = kNone;
+#pragma unroll
+    for (int j = 0; j < kLaneMax; ++j) {
+        if (X[j] >= 0 && X[j] != D) {
+            G g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
+            if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
+        }
+    }
+    return bx;
+}
+
+template <int WK>
+__global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, int64_t begin, int64_t count,
+                                                     int force_wide) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t ncand = 0;
+    if (i < count) {
+        int64_t pos = begin + i;
+        int32_t u = ms.class_nodes[pos];
+        int64_t e0 = g.off[u];
+        int64_t d = g.off[u + 1] - e0;
+        int32_t X[kLaneMax];
+        int64_t W[kLaneMax];
+#pragma unroll
+        for (int j = 0; j < kLaneMax; ++j) {
+            X[j] = -1;
+            W[j] = 0;
+            if (j < d) {
+                int32_t v = g.col[e0 + j];
+                if (v != u) {
+                    X[j] = ms.zeta[v];
+                    W[j] = wload<WK>(g.w, e0 + j);
+                }
+            }
+        }
+        // merge equal communities into their first occurrence
+#pragma unroll
+        for (int a = 0; a < kLaneMax; ++a)
+#pragma unroll
+            for (int b = a + 1; b < kLaneMax; ++b)
+                if (X[b] >= 0 && X[b] == X[a]) { W[a] += W[b]; X[b] = -1; }
+        int32_t D = ms.zeta[u];
+        int64_t wD = 0;
+#pragma unroll
+        for (int j = 0; j < kLaneMax; ++j) {
+            if (X[j] == D) wD = W[j];
+            ncand += (X[j] >= 0 && X[j] != D);
+        }
+        int64_t vu = ms.vol[u];
+        int64_t base = ms.volC[D] - vu;
+        int32_t bx = (force_wide || vu > ms.wide_lim) ? lane_pick<WK, i128>(X, W, D, wD, vu, base, ms.S, ms.volC)
+                                                      : lane_pick<WK, int64_t>(X, W, D, wD, vu, base, ms.S, ms.volC);
+        ms.move_to[pos] = (bx == kNone) ? -1 : bx;
+    }
+    count_candidates(ms.cand_dev, ncand);
+}
+
+// ------------------------------------------------------------------ wavefront per node
+constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
+
+template <typename G>
+__device__ __forceinline__ void wave_eval(const int32_t *tk, const int64_t *tv, int32_t *tkw, int64_t *tvw, int tsize,
+                                          int32_t D, int64_t vu, int64_t base, int64_t S, const int64_t *volC,
+                                          int32_t &best_x, bool &move, int64_t &ncand) {
+    G bs = neg_inf<G>();
+    int32_t bx = kNone;
+    int64_t wD = 0;
+    for (int s = lane_id(); s < tsize; s += kWave) {
+        int32_t X = tk[s];
+        if (X >= 0) {
+            int64_t a = tv[s];
+            tkw[s] = kEmpty;
+            tvw[s] = 0;
+            if (X == D) {
+                wD = a;
+            } else {
+                ++ncand;
+                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
+            }
+        }
+    }
+    wD = wave_sum(wD);
+    wave_argmax<G>(bs, bx);
+    G K = (G)S * (G)wD - (G)vu * (G)base;
+    best_x = bx;
+    move = bx != kNone && bs > K;
+}
+
+template <int WK>
+__global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, int64_t begin, int64_t count,
+                                                     int force_wide) {
+    __shared__ int32_t tk[4][kWaveCap];
+    __shared__ int64_t tv[4][kWaveCap];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    for (int s = lane; s < kWaveCap; s += kWave) { tk[w][s] = kEmpty; tv[w][s] = 0; }
+    wave_sync();
+    int64_t ncand = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < count; i += (int64_t)gridDim.x * 4) {
+        int64_t pos = begin + i;
+        int32_t u = ms.class_nodes[pos];
+        int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        int bits = ceil_log2_dev(2 * (e1 - e0));
+        bits = bits < 6 ? 6 : bits;
+        int tsize = 1 << bits;
+        uint32_t mask = (uint32_t)tsize - 1;
+        int32_t D = ms.zeta[u];
+        for (int64_t e = e0 + lane; e < e1; e += kWave) {
+            int32_t v = g.col[e];
+            if (v == u) continue;
+            int32_t X = ms.zeta[v];
+            int64_t wt = wload<WK>(g.w, e);
+            uint32_t h = slot_hash(X, bits);
+            for (;;) {
+                int32_t k = atomicCAS(&tk[w][h], kEmpty, X);
+                if (k == kEmpty || k == X) {
+                    atomicAdd((unsigned long long *)&tv[w][h], (unsigned long long)wt);
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
+        }
+        wave_sync();
+        int64_t vu = ms.vol[u];
+        int64_t base = ms.volC[D] - vu;
+        int32_t bx;
+        bool mv;
+        if (force_wide || vu > ms.wide_lim)
+            wave_eval<i128>(tk[w], tv[w], tk[w], tv[w], tsize, D, vu, base, ms.S, ms.volC, bx, mv, ncand);
+        else
+            wave_eval<int64_t>(tk[w], tv[w], tk[w], tv[w], tsize, D, vu, base, ms.S, ms.volC, bx, mv, ncand);
+        if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
+        wave_sync();
+    }
+    count_candidates(ms.cand_dev, ncand);
+}
+
+// ------------------------------------------------------------------ workgroup per node
+constexpr int kBlockThreads = 512;
+constexpr int kBlockCap = 8192;  // rows up to 4096 entries
+
+template <typename G>
+__device__ __forceinline__ void block_eval(int32_t *tk, int64_t *tv, int tsize, int32_t D, int64_t vu, int64_t base,
+                                           int64_t S, const int64_t *volC, int32_t *out, int64_t &ncand) {
+    __shared__ int64_t red_w[kBlockThreads / kWave];
+    __shared__ G red_s[kBlockThreads / kWave];
+    __shared__ int32_t red_x[kBlockThreads / kWave];
+    G bs = neg_inf<G>();
+    int32_t bx = kNone;
+    int64_t wD = 0;
+    for (int s = threadIdx.x; s < tsize; s += kBlockThreads) {
+        int32_t X = tk[s];
+        if (X >= 0) {
+            int64_t a = tv[s];
+            tk[s] = kEmpty;
+            tv[s] = 0;
+            if (X == D) {
+                wD = a;
+            } else {
+                ++ncand;
+                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
+            }
+        }
+    }
+    wD = wave_sum(wD);
+    wave_argmax<G>(bs, bx);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { red_w[w] = wD; red_s[w] = bs; red_x[w] = bx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 1; j < kBlockThreads / kWave; ++j) {
+            wD += red_w[j];
+            if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
+        }
+        G K = (G)S * (G)wD - (G)vu * (G)base;
+        *out = (bx != kNone && bs > K) ? bx : -1;
+    }
+}
+
+template <int WK>
+__global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, MoveState ms, int64_t begin,
+                                                                int64_t count, int force_wide) {
+    __shared__ int32_t tk[kBlockCap];
+    __shared__ int64_t tv[kBlockCap];
+    for (int s = threadIdx.x; s < kBlockCap; s += kBlockThreads) { tk[s] = kEmpty; tv[s] = 0; }
+    __syncthreads();
+    int64_t ncand = 0;
+    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        int64_t pos = begin + i;
+        int32_t u = ms.class_nodes[pos];
+        int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        int bits = ceil_log2_dev(2 * (e1 - e0));
+        bits = bits < 6 ? 6 : bits;
+        int tsize = 1 << bits;
+        uint32_t mask = (uint32_t)tsize - 1;
+        int32_t D = ms.zeta[u];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlockThreads) {
+            int32_t v = g.col[e];
+            if (v == u) continue;
+            int32_t X = ms.zeta[v];
+            int64_t wt = wload<WK>(g.w, e);
+            uint32_t h = slot_hash(X, bits);
+            for (;;) {
+                int32_t k = atomicCAS(&tk[h], kEmpty, X);
+                if (k == kEmpty || k == X) {
+                    atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt);
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
+        }
+        __syncthreads();
+        int64_t vu = ms.vol[u];
+        int64_t base = ms.volC[D] - vu;
+        if (force_wide || vu > ms.wide_lim)
+            block_eval<i128>(tk, tv, tsize, D, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+        else
+            block_eval<int64_t>(tk, tv, tsize, D, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+        __syncthreads();
+    }
+    count_candidates(ms.cand_dev, ncand);
+}
+
+// ------------------------------------------------------------------ hubs: several workgroups per node
+constexpr int kHubThreads = 256;
+
+// hub h of a class owning class-relative block b: last h with first[h] <= b
+__device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
+    int64_t lo = 0, hi = nh;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int WK>
+__global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
+                                                            int64_t nh) {
+    int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
+    int64_t hg = hub0 + h;
+    int64_t chunk = blockIdx.x - ha.ins_first[hg];
+    int32_t u = ms.class_nodes[ha.hub_pos[hg]];
+    int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    int bits = ha.tab_bits[hg];
+    uint32_t mask = (1u << bits) - 1;
+    int32_t *tk = ha.tab_key + ha.tab_off[hg];
+    int64_t *tv = ha.tab_val + ha.tab_off[hg];
+    int64_t c0 = e0 + chunk * kHubInsChunk;
+    int64_t c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kHubThreads) {
+        int32_t v = g.col[e];
+        if (v == u) continue;
+        int32_t X = ms.zeta[v];
+        int64_t wt = wload<WK>(g.w, e);
+        uint32_t s = slot_hash(X, bits);
+        for (;;) {
+            int32_t k = atomicCAS(&tk[s], kEmpty, X);
+            if (k == kEmpty || k == X) {
+                atomicAdd((unsigned long long *)&tv[s], (unsigned long long)wt);
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+    }
+}
+
+template <typename G>
+__device__ __forceinline__ void hub_block_best(int32_t *tk, int64_t *tv, int64_t s0, int64_t s1, int32_t D,
+                                               int64_t vu, int64_t S, const int64_t *volC, int64_t *wD_slot,
+                                               G &bs, int32_t &bx, int64_t &ncand) {
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += kHubThreads) {
+        int32_t X = tk[s];
+        if (X >= 0) {
+            int64_t a = tv[s];
+            tk[s] = kEmpty;
+            tv[s] = 0;
+            if (X == D) {
+                *wD_slot = a;  // exactly one slot holds D
+            } else {
+                ++ncand;
+                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
+            }
+        }
+    }
+    wave_argmax<G>(bs, bx);
+    __shared__ G red_s[kHubThreads / kWave];
+    __shared__ int32_t red_x[kHubThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int j = 0; j < kHubThreads / kWave; ++j)
+            if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
+}
+
+template <int WK>
+__global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
+                                                          int64_t nh, int64_t *hub_wD, int force_wide) {
+    int64_t h = hub_of_block(ha.eval_first + hub0, nh, blockIdx.x);
+    int64_t hg = hub0 + h;
+    int64_t chunk = blockIdx.x - ha.eval_first[hg];
+    int64_t nblk = ha.eval_cnt[hg];
+    int64_t pos = ha.hub_pos[hg];
+    int32_t u = ms.class_nodes[pos];
+    int32_t D = ms.zeta[u];
+    int64_t vu = ms.vol[u];
+    bool wide = force_wide || vu > ms.wide_lim;
+    int64_t tsize = 1LL << ha.tab_bits[hg];
+    int32_t *tk = ha.tab_key + ha.tab_off[hg];
+    int64_t *tv = ha.tab_val + ha.tab_off[hg];
+    int64_t s0 = chunk * kHubEvalChunk, s1 = s0 + kHubEvalChunk < tsize ? s0 + kHubEvalChunk : tsize;
+    int64_t ncand = 0;
+    unsigned long long *part = ha.part + 4 * (size_t)blockIdx.x;
+    if (wide) {
+        i128 bs = neg_inf<i128>();
+        int32_t bx = kNone;
+        hub_block_best<i128>(tk, tv, s0, s1, D, vu, ms.S, ms.volC, &hub_wD[hg], bs, bx, ncand);
+        if (threadIdx.x == 0) {
+            part[0] = (unsigned long long)(uint64_t)(bs >> 64);
+            part[1] = (unsigned long long)(uint64_t)bs;
+            part[2] = (unsigned long long)(uint32_t)bx;
+        }
+    } else {
+        int64_t bs = neg_inf<int64_t>();
+        int32_t bx = kNone;
+        hub_block_best<int64_t>(tk, tv, s0, s1, D, vu, ms.S, ms.volC, &hub_wD[hg], bs, bx, ncand);
+        if (threadIdx.x == 0) {
+            part[0] = (unsigned long long)(bs < 0 ? -1LL : 0LL);
+            part[1] = (unsigned long long)bs;
+            part[2] = (unsigned long long)(uint32_t)bx;
+        }
+    }
+    count_candidates(ms.cand_dev, ncand);
+    // the last block of this hub combines the partial bests
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&ha.done[hg], 1) == (int)(nblk - 1);
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    i128 bs = neg_inf<i128>();
+    int32_t bx = kNone;
+    unsigned long long *p0 = ha.part + 4 * (size_t)ha.eval_first[hg];
+    for (int64_t j = 0; j < nblk; ++j) {
+        unsigned long long hi = __hip_atomic_load(&p0[4 * j + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long lo = __hip_atomic_load(&p0[4 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t x = (int32_t)__hip_atomic_load(&p0[4 * j + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        i128 s = (i128)(((unsigned __int128)hi << 64) | lo);
+        if (x != kNone && (s > bs || (s == bs && x < bx))) { bs = s; bx = x; }
+    }
+    int64_t wD = __hip_atomic_load((unsigned long long *)&hub_wD[hg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t base = ms.volC[D] - vu;
+    i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
+    ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
+    hub_wD[hg] = 0;
+    ha.done[hg] = 0;
+}
+
+// ------------------------------------------------------------------ apply
+__global__ __launch_bounds__(256) void k_apply(MoveState ms, int64_t begin, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t moved = 0;
+    if (i < count) {
+        int64_t pos = begin + i;
+        int32_t X = ms.move_to[pos];
+        if (X >= 0) {
+            int32_t u = ms.class_nodes[pos];
+            int32_t D = ms.zeta[u];
+            int64_t vu = ms.vol[u];
+            ms.zeta[u] = X;
+            atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
+            atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+            moved = 1;
+        }
+    }
+    moved = wave_sum(moved);
+    if (lane_id() == 0 && moved) atomicAdd(ms.moves_dev, (unsigned long long)moved);
+}
+
+__global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, int64_t begin, int64_t count, int64_t *deg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int32_t u = class_nodes[begin + i];
+    deg[i] = g.off[u + 1] - g.off[u];
+}
+
+// ------------------------------------------------------------------ launchers
+template <int WK>
+static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
+                          int fw, hipStream_t st) {
+    if (cr.count[0] > 0)
+        hipLaunchKernelGGL(k_decide_lane<WK>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, g, ms,
+                           cr.begin[0], cr.count[0], fw);
+    if (cr.count[1] > 0) {
+        int64_t blocks = cdiv(cr.count[1], 4);
+        hipLaunchKernelGGL(k_decide_wave<WK>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, g,
+                           ms, cr.begin[1], cr.count[1], fw);
+    }
+    if (cr.count[2] > 0) {
+        int64_t blocks = cr.count[2];
+        hipLaunchKernelGGL(k_decide_block<WK>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(kBlockThreads),
+                           0, st, g, ms, cr.begin[2], cr.count[2], fw);
+    }
+    if (cr.hub_count > 0) {
+        hipLaunchKernelGGL(k_hub_insert<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                           cr.hub_first, cr.hub_count);
+        hipLaunchKernelGGL(k_hub_eval<WK>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                           cr.hub_first, cr.hub_count, ha.hub_wD, fw);
+    }
+}
+
+void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
+                       bool force_wide, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
+    if (ev0) HIPCHK(hipEventRecord(ev0, st));
+    int fw = force_wide ? 1 : 0;
+    switch (g.wkind) {
+        case 0: class_step_wk<0>(g, ms, cr, ha, fw, st); break;
+        case 1: class_step_wk<1>(g, ms, cr, ha, fw, st); break;
+        default: class_step_wk<2>(g, ms, cr, ha, fw, st); break;
+    }
+    if (ev1) HIPCHK(hipEventRecord(ev1, st));
+    HIPCHK(hipGetLastError());
+}
+
+void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_apply, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, ms, begin, count);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, int64_t begin, int64_t count,
+                        int64_t *deg_out, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_hub_degrees, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, g, class_nodes, begin,
+                       count, deg_out);
+    HIPCHK(hipGetLastError());
+}
+
+}  // namespace plm

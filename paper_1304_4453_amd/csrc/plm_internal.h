@@ -1,0 +1,132 @@
+// plm_internal.h - shared declarations of the libplm HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace plm {
+
+constexpr int kWave = 64;
+constexpr int32_t kEmpty = -1;  // empty hash slot / "stay" decision
+
+// ------------------------------------------------------------------ device helpers
+// SplitMix64 step (Steele, Lea & Flood 2014) from state x.
+__device__ __host__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Hash part of the priority of node u at a level; full priority is (hash, u).
+__device__ __host__ __forceinline__ uint64_t prio_hash(uint64_t seed, int32_t level, int64_t u) {
+    return splitmix64(seed ^ ((uint64_t)(uint32_t)level << 40) ^ (uint64_t)u);
+}
+
+// true iff (ha, a) > (hb, b)
+__device__ __host__ __forceinline__ bool prio_greater(uint64_t ha, int64_t a, uint64_t hb, int64_t b) {
+    return ha > hb || (ha == hb && a > b);
+}
+
+// Entry weight: WK = 0 unit, 1 int32, 2 int64.
+template <int WK>
+__device__ __forceinline__ int64_t wload(const void *w, int64_t e) {
+    if constexpr (WK == 0) {
+        return 1;
+    } else if constexpr (WK == 1) {
+        return (int64_t)((const int32_t *)w)[e];
+    } else {
+        return ((const int64_t *)w)[e];
+    }
+}
+
+// Last row r with off[r] <= e (rows may be empty): binary search on off[0..n].
+__device__ __forceinline__ int64_t row_of(const int64_t *off, int64_t n, int64_t e) {
+    int64_t lo = 0, hi = n;  // invariant off[lo] <= e < off[hi]
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// smallest b with 2^b >= x (x >= 1)
+__device__ __forceinline__ int ceil_log2_dev(int64_t x) {
+    return x <= 1 ? 0 : 64 - __clzll((unsigned long long)(x - 1));
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// ------------------------------------------------------------------ graph of one level
+struct GraphView {
+    int64_t n = 0, nnz = 0;
+    const int64_t *off = nullptr;
+    const int32_t *col = nullptr;
+    const void *w = nullptr;  // nullptr when wkind == 0
+    int wkind = 0;            // 0 unit, 1 int32, 2 int64
+    int diag_mult = 1;        // 2: self-loop entries hold w(u,u) (input level); 1: they hold 2 w(u,u)
+};
+
+// ------------------------------------------------------------------ error type
+struct Error {
+    int code;
+    std::string msg;
+};
+
+// throws Error(PLM_E_DEVICE) on failure
+void hip_check(hipError_t e, const char *what);
+#define HIPCHK(x) ::plm::hip_check((x), #x)
+
+// ------------------------------------------------------------------ scratch allocator
+// Grow-only device scratch handed out as aligned slices; reset per use site.
+class Scratch {
+  public:
+    ~Scratch();
+    void reserve(size_t bytes);
+    void *get(size_t bytes);  // next aligned slice (reserve() first)
+    void reset() { used_ = 0; }
+    size_t capacity() const { return cap_; }
+
+  private:
+    char *base_ = nullptr;
+    size_t cap_ = 0, used_ = 0;
+};
+
+size_t align_up(size_t x, size_t a = 256);
+
+// ------------------------------------------------------------------ primitives (prims.hip)
+// Exclusive scan of n values into out (int64); the total goes to *total_dev.
+// Needs scan_scratch_bytes(n) of scratch.
+size_t scan_scratch_bytes(int64_t n);
+void exclusive_scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *scratch,
+                        hipStream_t st);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total_dev, void *scratch,
+                        hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the key.
+// Sorted data ends up in *keys / *vals (which may be swapped with the alt
+// buffers).  Needs radix_scratch_bytes(n) of scratch.
+size_t radix_scratch_bytes(int64_t n);
+void radix_sort_u32_i32(uint32_t **keys, int32_t **vals, uint32_t **keys_alt, int32_t **vals_alt, int64_t n,
+                        int bits, void *scratch, hipStream_t st);
+void radix_sort_u64_i32(uint64_t **keys, int32_t **vals, uint64_t **keys_alt, int32_t **vals_alt, int64_t n,
+                        int bits, void *scratch, hipStream_t st);
+void radix_sort_u64_i64(uint64_t **keys, int64_t **vals, uint64_t **keys_alt, int64_t **vals_alt, int64_t n,
+                        int bits, void *scratch, hipStream_t st);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int ceil_log2(uint64_t x) {  // smallest b with 2^b >= x
+    int b = 0;
+    while (b < 64 && (1ULL << b) < x) ++b;
+    return b;
+}
+
+}  // namespace plm

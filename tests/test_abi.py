@@ -1,0 +1,108 @@
+"""The C ABI: libplm.so loads, exports every entry point include/plm.h declares,
+and the Python binding's struct layouts match the header.  CPU only: no call
+here reaches the GPU (argument errors return before any HIP call)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "plm.h")
+LIB = os.path.join(ROOT, "paper_1304_4453_amd", "libplm.so")
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(LIB):
+        subprocess.run(["python", os.path.join(ROOT, "paper_1304_4453_amd", "build.py")], check=True)
+    assert os.path.exists(LIB), "libplm.so missing: run __graft_entry__.build()"
+    return LIB
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(plm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["plm_create", "plm_move_sweep", "plm_coarsen", "plm_run", "plm_modularity", "plm_destroy",
+                 "plm_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(built):
+    out = subprocess.run(["nm", "-D", "--defined-only", built], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (plm_[a-z_]+)\b", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(built)
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_struct_layouts_match_header(tmp_path, built):
+    import paper_1304_4453_amd as P
+    src = tmp_path / "probe.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "plm.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(plm_options), sizeof(plm_level_info_t),"
+        " sizeof(plm_stats_t), offsetof(plm_options, colour_seed), offsetof(plm_stats_t, decide_bytes),"
+        " offsetof(plm_level_info_t, max_vol)); return 0;}\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(P.plm_options), ctypes.sizeof(P.plm_level_info_t), ctypes.sizeof(P.plm_stats_t),
+                    P.plm_options.colour_seed.offset, P.plm_stats_t.decide_bytes.offset,
+                    P.plm_level_info_t.max_vol.offset]
+
+
+def test_default_options(built):
+    import paper_1304_4453_amd as P
+    o = P.default_options()
+    assert (o.max_sweeps, o.max_levels, o.schedule, o.validate, o.int_mode) == (32, 0, 0, 1, 0)
+    assert (o.bin_lane, o.bin_wave, o.bin_block, o.timing) == (16, 512, 4096, 0)
+
+
+def test_argument_errors_need_no_gpu(built):
+    import numpy as np
+    import paper_1304_4453_amd as P
+    c = ctypes.c_void_p()
+    off = np.zeros(2, np.int64)
+    col = np.zeros(0, np.int32)
+    assert P.plm_create(None, 1, 0, off.ctypes.data, col.ctypes.data, None, 0, None, None) == P.PLM_E_ARG
+    assert P.plm_create(ctypes.byref(c), -1, 0, off.ctypes.data, col.ctypes.data, None, 0, None, None) == P.PLM_E_ARG
+    assert b"n must" in P.plm_last_error(None)
+    assert P.plm_create(ctypes.byref(c), 1, 0, None, col.ctypes.data, None, 0, None, None) == P.PLM_E_ARG
+    assert P.plm_create(ctypes.byref(c), 1, 0, off.ctypes.data, col.ctypes.data, None, 7, None, None) == P.PLM_E_ARG
+    bad = P.default_options(bin_wave=9999)
+    assert P.plm_create(ctypes.byref(c), 1, 0, off.ctypes.data, col.ctypes.data, None, 0, None,
+                        ctypes.byref(bad)) == P.PLM_E_ARG
+    bad = P.default_options(max_sweeps=0)
+    assert P.plm_create(ctypes.byref(c), 1, 0, off.ctypes.data, col.ctypes.data, None, 0, None,
+                        ctypes.byref(bad)) == P.PLM_E_ARG
+    off_bad = np.array([0, 3], np.int64)   # offsets[n] != nnz
+    assert P.plm_create(ctypes.byref(c), 1, 0, off_bad.ctypes.data, col.ctypes.data, None, 0, None,
+                        None) == P.PLM_E_GRAPH
+    assert not c.value
+    # every ctx entry point rejects a NULL context
+    assert P.plm_move_sweep(None, None) == P.PLM_E_ARG
+    assert P.plm_coarsen(None, None) == P.PLM_E_ARG
+    assert P.plm_run(None, None, None, None) == P.PLM_E_ARG
+    assert P.plm_modularity(None, None, 0, None) == P.PLM_E_ARG
+    P.plm_destroy(None)
+
+
+def test_product_has_no_oracle_dependency():
+    """The library sources and the binding never reference the oracle."""
+    pkg = os.path.join(ROOT, "paper_1304_4453_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.lower(), f

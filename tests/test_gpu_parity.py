@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, element by
+element: colouring, every class step, every sweep, every coarse CSR, full-run
+labels, modularity.  Integer results must match bit for bit; modularity is
+compared for exact equality (both sides divide the same two correctly rounded
+128-bit integers), which is inside the 1e-12 tolerance the method allows.
+"""
+from __future__ import annotations
+
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1304_4453_amd as P  # fails loudly without the built library
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def stepwise(P, g, seed=0, schedule=0, per_class=True, max_sweeps=32, max_levels=8, **opts):
+    """Walks the GPU context and the oracle level by level in lock step."""
+    ctx = P.Context(g.off, g.col, g.w, colour_seed=seed, schedule=schedule, **opts)
+    off, col = g.off.astype(np.int64), g.col.astype(np.int32)
+    w2 = oracle.double_diagonal(off, col, g.w)
+    level = 0
+    try:
+        while True:
+            goff, gcol, gw = ctx.graph()
+            assert np.array_equal(goff, off) and np.array_equal(gcol, col) and np.array_equal(gw, w2), level
+            vol, S = oracle.volumes(off, w2)
+            colours, C = oracle.colour(off, col, seed, level, schedule)
+            z, v, c = ctx.state()
+            assert np.array_equal(c, colours), f"colouring differs at level {level}"
+            assert np.array_equal(z, np.arange(len(z))) and np.array_equal(v, vol)
+            li = ctx.level_info()
+            assert li.colours == C and li.S == S and li.level == level
+            zeta = np.arange(len(vol), dtype=np.int32)
+            volC = vol.copy()
+            for s in range(max_sweeps):
+                if per_class:
+                    mv = 0
+                    for cls in range(C):
+                        mo = oracle.class_step(off, col, w2, vol, S, colours, cls, zeta, volC)
+                        mg = ctx.move_class(cls)
+                        assert mg == mo, (level, s, cls)
+                        mv += mo
+                else:
+                    mv = oracle.sweep(off, col, w2, vol, S, colours, C, zeta, volC)
+                    assert ctx.move_sweep() == mv, (level, s)
+                z, v, _ = ctx.state()
+                assert np.array_equal(z, zeta) and np.array_equal(v, volC), (level, s)
+                if mv == 0:
+                    break
+            pi, k = oracle.relabel(zeta)
+            if k == len(vol) or level + 1 >= max_levels:
+                return level + 1
+            coff, ccol, cw = oracle.contract(off, col, w2, pi, k)
+            assert ctx.coarsen() == k
+            off, col, w2 = coff, ccol, cw
+            level += 1
+    finally:
+        ctx.close()
+
+
+def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, **opts):
+    r = oracle.run(g.off, g.col, g.w, max_sweeps=max_sweeps, max_levels=max_levels, seed=seed, schedule=schedule)
+    with P.Context(g.off, g.col, g.w, colour_seed=seed, schedule=schedule, max_sweeps=max_sweeps,
+                   max_levels=max_levels, **opts) as ctx:
+        labels, q, lv = ctx.run()
+        st = ctx.stats()
+    assert lv == r.levels
+    assert np.array_equal(labels, r.labels)
+    assert q == r.q
+    assert st["n"] == r.n and st["nnz"] == r.nnz and st["colours"] == r.colours
+    assert st["sweeps"] == r.sweeps and st["communities"] == r.communities
+    assert st["moves"] == [sum(m) for m in r.moves]
+    return r
+
+
+SMALL_BINS = dict(bin_lane=1, bin_wave=2, bin_block=3)   # every path on small graphs
+MID_BINS = dict(bin_lane=4, bin_wave=16, bin_block=64)
+
+
+# ------------------------------------------------------------------ class / sweep / level parity
+@pytest.mark.parametrize("seed", range(3))
+def test_stepwise_random_weighted_with_loops(P, seed):
+    _say("stepwise random", seed)
+    g = graphgen.random_graph(120, 0.06, seed=10 + seed, weighted=True, loops=0.2)
+    stepwise(P, g, seed=seed)
+
+
+@pytest.mark.parametrize("bins", [SMALL_BINS, MID_BINS], ids=["small", "mid"])
+def test_stepwise_all_bins(P, bins):
+    _say("stepwise bins", bins)
+    g = graphgen.random_graph(150, 0.12, seed=5, weighted=True, loops=0.1)
+    stepwise(P, g, seed=3, **bins)
+
+
+def test_stepwise_planted_partition(P):
+    _say("stepwise planted partition 1000")
+    stepwise(P, graphgen.planted_partition_1000(), per_class=False)
+
+
+def test_stepwise_rmat_small_hubs(P):
+    _say("stepwise rmat 12")
+    g = graphgen.rmat(12, 16, seed=7, weighted=True)
+    stepwise(P, g, seed=1, per_class=False, bin_lane=8, bin_wave=32, bin_block=128)
+
+
+def test_stepwise_sequential_schedule(P):
+    _say("stepwise sequential")
+    g = graphgen.random_graph(60, 0.1, seed=2, weighted=True, loops=0.2)
+    stepwise(P, g, seed=4, schedule=1)
+
+
+# ------------------------------------------------------------------ full runs
+def test_full_run_planted_partition(P):
+    _say("full planted partition 1000")
+    r = full_run(P, graphgen.planted_partition_1000())
+    assert len(set(r.labels.tolist())) == 10
+
+
+@pytest.mark.parametrize("bins", [{}, SMALL_BINS, MID_BINS], ids=["default", "small", "mid"])
+@pytest.mark.parametrize("scale", [10, 14])
+def test_full_run_rmat(P, scale, bins):
+    _say("full rmat", scale, bins)
+    g = graphgen.rmat(scale, 16, seed=scale, weighted=(scale == 14))
+    full_run(P, g, seed=scale, **bins)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_full_run_random(P, seed):
+    _say("full random", seed)
+    g = graphgen.random_graph(300, 0.02, seed=40 + seed, weighted=bool(seed % 2), loops=0.1 * seed)
+    full_run(P, g, seed=seed, max_sweeps=1 + 10 * seed)
+
+
+def test_full_run_forced_int128_same(P):
+    _say("full int128")
+    g = graphgen.rmat(12, 16, seed=3, weighted=True)
+    full_run(P, g, int_mode=P.PLM_INT_128)
+    full_run(P, g, int_mode=P.PLM_INT_128, **SMALL_BINS)
+
+
+def test_int64_mode_rejects_overflow(P):
+    # S * vol(u) >= 2^62: one heavy edge
+    big = 2**31 - 1
+    g = graphgen.from_edges(3, [(0, 1), (1, 2)], [big, big], loops={0: big})
+    with pytest.raises(P.PLMError) as ei:
+        P.Context(g.off, g.col, g.w, int_mode=P.PLM_INT_64)
+    assert ei.value.status == P.PLM_E_STATE
+    full_run(P, g)   # auto mode takes the 128-bit path
+
+
+def test_hub_multi_workgroup(P):
+    """A star with 20000 weighted leaves plus a ring among the leaves: one hub
+    whose table spans many eval workgroups."""
+    _say("hub star")
+    n = 20001
+    edges = [(0, i) for i in range(1, n)] + [(i, i + 1) for i in range(1, n - 1)]
+    rng = np.random.default_rng(1)
+    g = graphgen.from_edges(n, edges, rng.integers(1, 50, len(edges)))
+    full_run(P, g)
+    full_run(P, g, bin_block=64)
+
+
+def test_sequential_schedule_full(P):
+    _say("full sequential")
+    g = graphgen.random_graph(200, 0.03, seed=9, weighted=True, loops=0.1)
+    full_run(P, g, seed=2, schedule=1)
+
+
+def test_ring_of_cliques_and_two_cliques(P):
+    g = graphgen.ring_of_cliques(10, 5)
+    with P.Context(g.off, g.col) as ctx:
+        labels, q, _ = ctx.run()
+    assert q == 89 / 110 and np.array_equal(labels, np.repeat(np.arange(10), 5))
+    g = graphgen.disjoint_cliques(2, 8)
+    with P.Context(g.off, g.col) as ctx:
+        assert ctx.run()[1] == 0.5
+
+
+# ------------------------------------------------------------------ modularity
+@pytest.mark.parametrize("seed", range(3))
+def test_modularity_api(P, seed):
+    rng = np.random.default_rng(seed)
+    g = graphgen.random_graph(200, 0.05, seed=seed, weighted=True, loops=0.2)
+    with P.Context(g.off, g.col, g.w) as ctx:
+        for _ in range(4):
+            lab = rng.integers(0, 30, 200).astype(np.int32)
+            assert ctx.modularity(lab) == oracle.modularity(g.off, g.col, g.w, lab)
+        with pytest.raises(P.PLMError):
+            ctx.modularity(np.full(200, 500, np.int32))
+
+
+# ------------------------------------------------------------------ device inputs, streams, repeatability
+def test_device_inputs_and_stream(P):
+    import torch
+    _say("device inputs")
+    g = graphgen.rmat(13, 16, seed=11, weighted=True)
+    r = oracle.run(g.off, g.col, g.w)
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    off = torch.from_numpy(g.off).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    torch.cuda.synchronize()
+    with P.Context(off, col, w, stream=s) as ctx:
+        lab = torch.empty(g.n, dtype=torch.int32, device=dev)
+        _, q, lv = ctx.run(lab)
+        assert q == r.q and lv == r.levels
+        assert np.array_equal(lab.cpu().numpy(), r.labels)
+        assert ctx.modularity(lab) == r.q
+        # repeat: identical
+        lab2 = torch.empty_like(lab)
+        ctx.run(lab2)
+        assert torch.equal(lab, lab2)
+
+
+def test_repeat_runs_identical(P):
+    g = graphgen.rmat(14, 16, seed=1)
+    with P.Context(g.off, g.col) as ctx:
+        a = ctx.run()[0].copy()
+        for _ in range(3):
+            assert np.array_equal(ctx.run()[0], a)
+
+
+# ------------------------------------------------------------------ edge cases and validation
+def test_empty_and_degenerate(P):
+    with P.Context(np.zeros(1, np.int64), np.zeros(0, np.int32)) as ctx:
+        labels, q, lv = ctx.run()
+        assert labels.shape == (0,) and q == 0.0 and lv == 1
+    g = graphgen.from_edges(5, [])
+    with P.Context(g.off, g.col) as ctx:
+        labels, q, _ = ctx.run()
+        assert np.array_equal(labels, np.arange(5)) and q == 0.0
+    g = graphgen.from_edges(3, [(0, 1)], [4], loops={2: 7})
+    full_run(P, g)
+    g = graphgen.from_edges(1, [], loops={0: 3})
+    full_run(P, g)
+
+
+@pytest.mark.parametrize("case", ["asym", "range", "unsorted", "zero_w", "dup"])
+def test_validation_rejects(P, case):
+    g = graphgen.from_edges(4, [(0, 1), (1, 2), (2, 3)], [1, 2, 3])
+    off, col, w = g.off.copy(), g.col.copy(), g.w.copy()
+    if case == "asym":
+        w[0] = 9
+    elif case == "range":
+        col[0] = 7
+    elif case == "unsorted":
+        col[[1, 2]] = col[[2, 1]]
+        w[[1, 2]] = w[[2, 1]]
+    elif case == "zero_w":
+        w[:] = 0
+    elif case == "dup":
+        col[2] = col[1]
+    with pytest.raises(P.PLMError) as ei:
+        P.Context(off, col, w)
+    assert ei.value.status == P.PLM_E_GRAPH
+
+
+def test_coarsen_api_and_state_errors(P):
+    g = graphgen.planted_partition_1000()
+    with P.Context(g.off, g.col) as ctx:
+        while ctx.move_sweep():
+            pass
+        z, _, _ = ctx.state()
+        k = ctx.coarsen()
+        assert k == len(set(z.tolist()))
+        li = ctx.level_info()
+        assert li.level == 1 and li.n == k and li.weight_kind == 2
+        with pytest.raises(P.PLMError):
+            ctx.move_class(10**6)
+        ctx.reset()
+        assert ctx.level_info().level == 0
