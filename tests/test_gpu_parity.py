@@ -173,7 +173,7 @@ def test_hub_multi_workgroup(P):
     rng = np.random.default_rng(1)
     g = graphgen.from_edges(n, edges, rng.integers(1, 50, len(edges)))
     full_run(P, g)
-    full_run(P, g, bin_block=64)
+    full_run(P, g, bin_wave=32, bin_block=64)
 
 
 def test_sequential_schedule_full(P):
