@@ -1,0 +1,207 @@
+"""Benchmark: PLM move-sweep edges/s on one MI355X, with the HBM roofline of the
+dominant move-decide kernel and the oracle's CPU rate on a bounded sample.
+
+One step = one full multilevel PLM run (plm_run: level set-up, colouring, class
+bucketing, move sweeps, coarsening, prolongation, canonical labels) on a graph
+already resident in HBM.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BIN_KERNELS = ["k_decide_lane", "k_decide_wave", "k_decide_block", "k_hub_insert+k_hub_eval"]
+
+WORKLOADS = {
+    "rmat26": dict(desc="R-MAT scale 26, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised, loops and "
+                        "duplicates removed, integer weights uniform in [1,100], seed 3",
+                   scale=26, seed=3, weighted=True),
+    "rmat20": dict(desc="R-MAT scale 20, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised, loops and "
+                        "duplicates removed, unit weights, seed 2", scale=20, seed=2, weighted=False),
+    "pp1000": dict(desc="planted partition n=1000, 10 blocks of 100, p_in=0.1, p_out=0.005, unit weights, seed 1"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_graph(name):
+    """(device off, col, w pointers or tensors, n, nnz, m, keepalive, host_rows_fn)."""
+    import torch
+    import graphgen
+    if name == "pp1000":
+        g = graphgen.planted_partition_1000(seed=1)
+        dev = torch.device("cuda:0")
+        off = torch.from_numpy(g.off).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        torch.cuda.synchronize()
+        return dict(off=off, col=col, w=None, n=g.n, nnz=g.nnz, m=g.undirected_edges(), host=g, dg=None)
+    wl = WORKLOADS[name]
+    dg = graphgen.rmat_gpu(wl["scale"], 16, seed=wl["seed"], weighted=wl["weighted"])
+    return dict(off=dg.off_ptr, col=dg.col_ptr, w=dg.w_ptr or None, n=dg.n, nnz=dg.nnz, m=dg.nnz // 2, host=None,
+                dg=dg)
+
+
+def cpu_baseline(gr, ctx_state, budget_s=12.0):
+    """The oracle, single-threaded, on a bounded sample of the same workload:
+    level-0, sweep-1 move decisions (singleton communities) of uniformly sampled
+    movable nodes; rate = sampled undirected edges (entries / 2) per second."""
+    import ctypes
+    import numpy as np
+    import graphgen
+    import oracle
+    n = gr["n"]
+    zeta, volc, _ = ctx_state
+    if gr["host"] is not None:
+        g = gr["host"]
+        off = g.off
+        get_row = lambda u: (g.col[off[u]:off[u + 1]], None if g.w is None else g.w[off[u]:off[u + 1]])
+    else:
+        dg = gr["dg"]
+        off = np.zeros(n + 1, np.int64)
+        lib = graphgen._gpu_lib()
+        lib.ggpu_copy_to_host(off.ctypes.data, ctypes.c_void_p(dg.off_ptr), off.nbytes)
+
+        def get_row(u):
+            a, b = int(off[u]), int(off[u + 1])
+            c = np.zeros(b - a, np.int32)
+            lib.ggpu_copy_to_host(c.ctypes.data, ctypes.c_void_p(dg.col_ptr + 4 * a), c.nbytes)
+            w = None
+            if dg.w_ptr:
+                w = np.zeros(b - a, np.int32)
+                lib.ggpu_copy_to_host(w.ctypes.data, ctypes.c_void_p(dg.w_ptr + 4 * a), w.nbytes)
+            return c, w
+    deg = np.diff(off)
+    movable = np.nonzero(deg > 0)[0]
+    rng = np.random.default_rng(12345)
+    vol = volc.astype(np.int64)
+    S = int(vol.sum())
+
+    def timed(count):
+        nodes = np.sort(rng.choice(movable, size=min(count, len(movable)), replace=False)).astype(np.int32)
+        rows = [get_row(int(u)) for u in nodes]
+        soff = np.zeros(n + 1, np.int64)
+        soff[nodes.astype(np.int64) + 1] = deg[nodes]
+        soff = np.cumsum(soff)
+        scol = np.concatenate([r[0] for r in rows]).astype(np.int32)
+        sw = np.concatenate([np.ones(len(r[0]), np.int64) if r[1] is None else r[1].astype(np.int64)
+                             for r in rows])
+        w2 = oracle.double_diagonal(soff, scol, sw)
+        t = time.perf_counter()
+        oracle.decide_many(nodes, soff, scol, w2, zeta, volc, vol, S)
+        dt = time.perf_counter() - t
+        return len(nodes), int(deg[nodes].sum()), dt
+
+    k, e, dt = timed(2000)
+    if dt < budget_s / 4:
+        want = int(2000 * budget_s / max(dt, 1e-3))
+        k, e, dt = timed(min(want, len(movable), 4_000_000))
+    return {"value": (e / 2) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"level-0 sweep-1 move decisions (singleton communities) of {k} uniformly sampled movable "
+                      f"nodes ({e} CSR entries) of the same graph, oracle single-threaded on {platform.processor() or platform.machine()}",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1304_4453_amd as P
+
+    torch.cuda.set_device(0)
+    t = time.time()
+    gr = make_graph(args.workload)
+    log(f"graph {args.workload}: n={gr['n']} nnz={gr['nnz']} built in {time.time() - t:.1f}s")
+    ctx = P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"], timing=1)
+    state0 = ctx.state()  # level-0 singleton state, for the CPU sample
+    lab = torch.empty(max(gr["n"], 1), dtype=torch.int32, device="cuda:0")
+    for i in range(args.warmup):
+        t = time.time()
+        ctx.run(lab)
+        log(f"warmup {i}: {time.time() - t:.2f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q = lv = None
+    for i in range(args.steps):
+        _, q, lv = ctx.run(lab)
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = ctx.stats()  # of the last step
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    L = st["levels"]
+    m_l = [(st["nnz"][l] - st["loops"][l]) // 2 + st["loops"][l] for l in range(L)]
+    sweep_edges = sum(st["sweeps"][l] * m_l[l] for l in range(L))
+    value = sweep_edges / (ms_per_step / 1e3)
+    sweep_ms = sum(st["sweep_ms"])
+    # dominant move-decide kernel (degree bin) at level 0, timed with HIP events on the library's stream
+    bms = st["bin_ms"][0]
+    b = int(np.argmax(bms))
+    launches = st["decide_launches"][0]
+    achieved = st["bin_bytes"][0][b] / (bms[b] * 1e6) if bms[b] > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": BIN_KERNELS[b], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_sweep": st["bin_bytes"][0][b] / max(st["sweeps"][0], 1),
+            "kernel_ms_per_sweep": bms[b] / max(st["sweeps"][0], 1),
+            "all_decide_bins_GBs": st["decide_bytes"][0] / (st["decide_ms"][0] * 1e6) if st["decide_ms"][0] else 0.0,
+            "bin_ms_level0": bms, "bin_bytes_level0": st["bin_bytes"][0]}
+    out = {
+        "metric": "PLM move-sweep edges/s",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload]["desc"], "n": gr["n"], "nnz": gr["nnz"], "m": m_l[0],
+                   "schedule": "Jones-Plassmann colour classes, <=32 sweeps per level", "parallelism": "single-gpu"},
+        "roofline": roof,
+        "sweep_only_edges_per_s": sweep_edges / (sweep_ms / 1e3) if sweep_ms else None,
+        "full_run_edges_per_s": m_l[0] / (ms_per_step / 1e3),
+        "q": q,
+        "levels": lv,
+        "per_level": {k: st[k] for k in ("n", "nnz", "colours", "sweeps", "moves", "schedule_ms", "colour_ms",
+                                         "schedule_rounds", "sweep_ms", "coarsen_ms", "decide_ms")},
+        "paper_context": "PLM full run >21M edges/s (uk-2007-05, 3.3e9 edges, 2x Xeon E5-2680, 32 threads)",
+    }
+    if not args.no_cpu_baseline:
+        t = time.time()
+        out["cpu_baseline"] = cpu_baseline(gr, state0, args.cpu_budget)
+        log(f"cpu baseline {time.time() - t:.1f}s")
+    ctx.close()
+    if gr["dg"] is not None:
+        gr["dg"].free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

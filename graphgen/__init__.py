@@ -212,6 +212,7 @@ class DeviceGraph:
 def _gpu_lib():
     global _gpu
     if _gpu is None:
+        import torch  # noqa: F401  (share torch's HIP runtime, loaded first)
         if not os.path.exists(_GPU_SO):
             build(force=False)
         lib = ctypes.CDLL(_GPU_SO)

@@ -178,6 +178,14 @@ typedef struct {
     double decide_ms[PLM_MAX_LEVELS];
     int64_t decide_launches[PLM_MAX_LEVELS];
     double decide_bytes[PLM_MAX_LEVELS];
+    int64_t schedule_rounds[PLM_MAX_LEVELS];  /* Jones-Plassmann rounds */
+    double colour_ms[PLM_MAX_LEVELS];         /* colouring part of schedule_ms */
+    /* with opt.timing, per degree bin (lane, wavefront, workgroup, hub) */
+    double bin_ms[PLM_MAX_LEVELS][4];
+    double bin_bytes[PLM_MAX_LEVELS][4];
+    int64_t bin_nodes[PLM_MAX_LEVELS][4];     /* nodes of the level in each bin */
+    int64_t bin_entries[PLM_MAX_LEVELS][4];   /* their CSR entries */
+    int64_t loops[PLM_MAX_LEVELS];            /* self-loop entries of the level */
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

@@ -18,6 +18,9 @@ import ctypes
 import os
 
 import numpy as np
+# torch ships its own HIP runtime; loading it before libplm.so makes the library
+# bind to that same runtime, so one process never holds two HIP runtimes.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplm.so")
@@ -55,7 +58,10 @@ class plm_stats_t(ctypes.Structure):
                 ("moves", ctypes.c_int64 * _L), ("schedule_ms", ctypes.c_double * _L),
                 ("sweep_ms", ctypes.c_double * _L), ("coarsen_ms", ctypes.c_double * _L),
                 ("decide_ms", ctypes.c_double * _L), ("decide_launches", ctypes.c_int64 * _L),
-                ("decide_bytes", ctypes.c_double * _L)]
+                ("decide_bytes", ctypes.c_double * _L), ("schedule_rounds", ctypes.c_int64 * _L),
+                ("colour_ms", ctypes.c_double * _L), ("bin_ms", (ctypes.c_double * 4) * _L),
+                ("bin_bytes", (ctypes.c_double * 4) * _L), ("bin_nodes", (ctypes.c_int64 * 4) * _L),
+                ("bin_entries", (ctypes.c_int64 * 4) * _L), ("loops", ctypes.c_int64 * _L)]
 
 
 class PLMError(RuntimeError):
@@ -246,5 +252,6 @@ class Context:
         L = s.levels
         out = {"levels": L}
         for f, _ in plm_stats_t._fields_[2:]:
-            out[f] = list(getattr(s, f))[:L]
+            v = list(getattr(s, f))[:L]
+            out[f] = [list(x) if not isinstance(x, (int, float)) else x for x in v]
         return out

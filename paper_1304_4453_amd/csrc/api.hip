@@ -72,6 +72,23 @@ __global__ void k_export_w(GraphView g, int64_t *out) {
     }
 }
 
+// rows holding a self-loop entry (rows are strictly ascending: binary search)
+__global__ void k_count_loops(GraphView g, unsigned long long *cnt) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c = 0;
+    if (u < g.n) {
+        int64_t lo = g.off[u], hi = g.off[u + 1];
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            int32_t x = g.col[mid];
+            if (x == u) { c = 1; break; }
+            if (x < u) lo = mid + 1; else hi = mid;
+        }
+    }
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
+    if (lane_id() == 0 && c) atomicAdd(cnt, (unsigned long long)c);
+}
+
 __global__ void k_count_loop_only(GraphView g, unsigned long long *cnt) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t c = 0;
@@ -110,7 +127,11 @@ struct plm_ctx {
     unsigned long long *part = nullptr;
     int64_t hub_cap_slots = 0, hub_cap_part = 0, hub_cap_hubs = 0;
     int32_t sweeps = 0;
-    unsigned long long *dcnt = nullptr;  // [moves, cand, S, maxvol, loop-only]
+    // device counters: [0] moves, [1..4] candidates per bin, [5] S, [6] max vol,
+    // [7] loop-only rows, [8..11] entries per bin
+    unsigned long long *dcnt = nullptr;
+    int64_t bin_nodes[4] = {0, 0, 0, 0}, bin_entries[4] = {0, 0, 0, 0};
+    int64_t loops = 0;  // self-loop entries of the current level
     int64_t *hbuf = nullptr;             // pinned host scratch (64 int64)
     Scratch scr;
     plm_stats_t stats;
@@ -141,9 +162,13 @@ struct plm_ctx {
     void init_level() {
         LevelData &l = L();
         GraphView g = l.view();
-        launch_volumes(g, vol, dcnt + 2, dcnt + 3, st);
-        HIPCHK(hipMemcpyAsync(hbuf, dcnt + 2, 16, hipMemcpyDeviceToHost, st));
+        launch_volumes(g, vol, dcnt + 5, dcnt + 6, st);
+        HIPCHK(hipMemsetAsync(dcnt + 12, 0, 8, st));
+        if (l.n > 0) hipLaunchKernelGGL(k_count_loops, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 12);
+        HIPCHK(hipMemcpyAsync(hbuf, dcnt + 5, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hbuf + 2, dcnt + 12, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        loops = hbuf[2];
         uint64_t s = (uint64_t)hbuf[0];
         if (cur == 0) {
             if (s >= (1ULL << 62)) throw Error{PLM_E_GRAPH, "total weight S = 2 w(E) must be below 2^62"};
@@ -189,21 +214,32 @@ struct plm_ctx {
     void build_schedule() {
         LevelData &l = L();
         GraphView g = l.view();
+        double t0 = now_ms();
         ncol = build_colouring(g, opt.colour_seed, cur, opt.schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st);
+        if (cur < PLM_MAX_LEVELS) {
+            stats.colour_ms[cur] = now_ms() - t0;
+            stats.schedule_rounds[cur] = jp_rounds;
+        }
         int64_t nkeys = (int64_t)ncol * 4 + 1;
         dev_free(bstart_dev);
         bstart_dev = dev_alloc<int64_t>(nkeys + 1);
-        build_buckets(g, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, scr, st);
+        HIPCHK(hipMemsetAsync(dcnt + 7, 0, 5 * 8, st));
+        build_buckets(g, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, dcnt + 8, scr,
+                      st);
         bstart.assign(nkeys + 1, 0);
         if (l.n > 0) HIPCHK(hipMemcpyAsync(bstart.data(), bstart_dev, (nkeys + 1) * 8, hipMemcpyDeviceToHost, st));
         // active entries = nnz minus rows made of a single self-loop
-        HIPCHK(hipMemsetAsync(dcnt + 4, 0, 8, st));
         if (l.n > 0)
-            hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 4);
-        HIPCHK(hipMemcpyAsync(hbuf + 8, dcnt + 4, 8, hipMemcpyDeviceToHost, st));
+            hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 7);
+        HIPCHK(hipMemcpyAsync(hbuf + 8, dcnt + 7, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         active_nodes = l.n > 0 ? bstart[(size_t)ncol * 4] : 0;
         active_entries = l.nnz - hbuf[8];
+        for (int b = 0; b < 4; ++b) {
+            bin_entries[b] = hbuf[9 + b];
+            bin_nodes[b] = 0;
+            for (int32_t c = 0; c < ncol; ++c) bin_nodes[b] += bstart[4 * c + b + 1] - bstart[4 * c + b];
+        }
         // hubs: degrees to the host, then per-hub table and block layout
         classes.assign(ncol, ClassRange());
         int64_t H = 0;
@@ -267,9 +303,9 @@ struct plm_ctx {
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
-        if (opt.timing && events.size() < 2 * (size_t)ncol) {
+        if (opt.timing && events.size() < 5 * (size_t)ncol) {
             size_t old = events.size();
-            events.resize(2 * (size_t)ncol);
+            events.resize(5 * (size_t)ncol);
             for (size_t i = old; i < events.size(); ++i) HIPCHK(hipEventCreate(&events[i]));
         }
     }
@@ -291,7 +327,7 @@ struct plm_ctx {
     // ---------------------------------------------------------------- sweeps
     int64_t run_classes(int32_t c0, int32_t c1) {
         if (!sched) build_schedule();
-        HIPCHK(hipMemsetAsync(dcnt, 0, 16, st));
+        HIPCHK(hipMemsetAsync(dcnt, 0, 5 * 8, st));
         bool timing = opt.timing != 0;
         MoveState ms = move_state(timing);
         HubArrays ha = hub_arrays();
@@ -299,27 +335,39 @@ struct plm_ctx {
         bool fw = opt.int_mode == PLM_INT_128;
         for (int32_t c = c0; c < c1; ++c) {
             const ClassRange &cr = classes[c];
-            hipEvent_t e0 = timing ? events[2 * c] : nullptr, e1 = timing ? events[2 * c + 1] : nullptr;
-            launch_class_step(g, ms, cr, ha, fw, e0, e1, st);
+            launch_class_step(g, ms, cr, ha, fw, timing ? &events[5 * (size_t)c] : nullptr, st);
             launch_apply(ms, cr.begin[0], cr.begin[3] + cr.count[3] - cr.begin[0], st);
         }
-        HIPCHK(hipMemcpyAsync(hbuf, dcnt, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hbuf, dcnt, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t moves = hbuf[0];
         if (timing && cur < PLM_MAX_LEVELS) {
-            double ms_sum = 0;
+            double bin_t[4] = {0, 0, 0, 0};
+            int64_t launches = 0;
             for (int32_t c = c0; c < c1; ++c) {
-                float t = 0;
-                HIPCHK(hipEventElapsedTime(&t, events[2 * c], events[2 * c + 1]));
-                ms_sum += t;
+                for (int b = 0; b < 4; ++b) {
+                    float t = 0;
+                    HIPCHK(hipEventElapsedTime(&t, events[5 * (size_t)c + b], events[5 * (size_t)c + b + 1]));
+                    bin_t[b] += t;
+                    launches += classes[c].count[b] > 0 ? (b == 3 ? 2 : 1) : 0;
+                }
             }
+            // algorithmic bytes (whole sweeps only): per entry the column, the
+            // weight and the community of the neighbour; per distinct candidate
+            // its community volume; per node offsets, own community, vol(u),
+            // vol(D) and the class list entry
             int wb = L().wkind == 0 ? 0 : (L().wkind == 1 ? 4 : 8);
-            double bytes = 0;
-            if (c0 == 0 && c1 == ncol)  // whole sweep: every active node once
-                bytes = (double)active_entries * (8.0 + wb) + 8.0 * (double)hbuf[1] + 32.0 * (double)active_nodes;
-            stats.decide_ms[cur] += ms_sum;
-            stats.decide_launches[cur] += (c1 - c0);
-            stats.decide_bytes[cur] += bytes;
+            bool whole = c0 == 0 && c1 == ncol;
+            for (int b = 0; b < 4; ++b) {
+                double bytes = whole ? (double)bin_entries[b] * (8.0 + wb) + 8.0 * (double)hbuf[1 + b] +
+                                           32.0 * (double)bin_nodes[b]
+                                     : 0.0;
+                stats.bin_ms[cur][b] += bin_t[b];
+                stats.bin_bytes[cur][b] += bytes;
+                stats.decide_ms[cur] += bin_t[b];
+                stats.decide_bytes[cur] += bytes;
+            }
+            stats.decide_launches[cur] += launches;
         }
         return moves;
     }
@@ -372,12 +420,17 @@ struct plm_ctx {
         stats.levels = cur + 1;
         stats.n[cur] = L().n;
         stats.nnz[cur] = L().nnz;
+        stats.loops[cur] = loops;
         stats.colours[cur] = ncol;
         stats.sweeps[cur] = sweeps;
         stats.communities[cur] = communities;
         stats.moves[cur] = moves;
         stats.schedule_ms[cur] = t_sched;
         stats.sweep_ms[cur] = t_sweep;
+        for (int b = 0; b < 4; ++b) {
+            stats.bin_nodes[cur][b] = bin_nodes[b];
+            stats.bin_entries[cur][b] = bin_entries[b];
+        }
         stats.coarsen_ms[cur] += t_coarsen;
     }
 
@@ -561,8 +614,8 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
         c->class_nodes = dev_alloc<int32_t>(n);
         c->move_to = dev_alloc<int32_t>(n);
         c->lab = dev_alloc<int32_t>(n);
-        c->dcnt = dev_alloc<unsigned long long>(8);
-        HIPCHK(hipMemsetAsync(c->dcnt, 0, 64, c->st));
+        c->dcnt = dev_alloc<unsigned long long>(16);
+        HIPCHK(hipMemsetAsync(c->dcnt, 0, 16 * 8, c->st));
         c->init_level();
     } catch (const Error &e) {
         delete c;

@@ -15,8 +15,10 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
 // Sorts nodes by (colour, degree bin) into class_nodes; bstart_dev[4*ncol+2]
 // receives bucket starts (bucket 4c+b = bin b of class c; bucket 4*ncol holds
 // nodes that cannot move).
+// bin_entries[4]: CSR entries of the movable nodes of each bin (added to).
 void build_buckets(const GraphView &g, const int32_t *colour, int32_t ncol, int64_t b0, int64_t b1, int64_t b2,
-                   int32_t *class_nodes, int64_t *bstart_dev, Scratch &scr, hipStream_t st);
+                   int32_t *class_nodes, int64_t *bstart_dev, unsigned long long *bin_entries, Scratch &scr,
+                   hipStream_t st);
 
 // ---- move.hip
 struct MoveState {
@@ -28,7 +30,7 @@ struct MoveState {
     int64_t S;
     int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
     unsigned long long *moves_dev;  // move counter
-    unsigned long long *cand_dev;   // distinct candidates evaluated (may be null)
+    unsigned long long *cand_dev;   // distinct candidates evaluated per bin [4] (may be null)
 };
 
 // One class step: decide (per bin) then apply.  Counts (bin sizes) come from
@@ -58,8 +60,9 @@ constexpr int64_t kHubInsChunk = 4096;   // entries per hub insert workgroup
 constexpr int64_t kHubEvalChunk = 4096;  // table slots per hub eval workgroup
 constexpr int kHubMinBits = 12;
 
+// ev: null, or 5 events recorded before bin 0 and after bins 0..3
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st);
+                       bool force_wide, const hipEvent_t *ev, hipStream_t st);
 void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
 void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, int64_t begin, int64_t count,
                         int64_t *deg_out, hipStream_t st);

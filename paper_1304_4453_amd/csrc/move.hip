@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
                                                       : lane_pick<WK, int64_t>(X, W, D, wD, vu, base, ms.S, ms.volC);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
     }
-    count_candidates(ms.cand_dev, ncand);
+    count_candidates(ms.cand_dev ? ms.cand_dev + 0 : nullptr, ncand);
 }
 
 // ------------------------------------------------------------------ wavefront per node
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
         wave_sync();
     }
-    count_candidates(ms.cand_dev, ncand);
+    count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
 }
 
 // ------------------------------------------------------------------ workgroup per node
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
             block_eval<int64_t>(tk, tv, tsize, D, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
         __syncthreads();
     }
-    count_candidates(ms.cand_dev, ncand);
+    count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
 }
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
             part[2] = (unsigned long long)(uint32_t)bx;
         }
     }
-    count_candidates(ms.cand_dev, ncand);
+    count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
     // the last block of this hub combines the partial bests
     __shared__ int last;
     __threadfence();
@@ -470,38 +470,44 @@ __global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, int64_t b
 // ------------------------------------------------------------------ launchers
 template <int WK>
 static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                          int fw, hipStream_t st) {
+                          int fw, const hipEvent_t *ev, hipStream_t st) {
+    auto mark = [&](int i) {
+        if (ev) HIPCHK(hipEventRecord(ev[i], st));
+    };
+    mark(0);
     if (cr.count[0] > 0)
         hipLaunchKernelGGL(k_decide_lane<WK>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, g, ms,
                            cr.begin[0], cr.count[0], fw);
+    mark(1);
     if (cr.count[1] > 0) {
         int64_t blocks = cdiv(cr.count[1], 4);
         hipLaunchKernelGGL(k_decide_wave<WK>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, g,
                            ms, cr.begin[1], cr.count[1], fw);
     }
+    mark(2);
     if (cr.count[2] > 0) {
         int64_t blocks = cr.count[2];
         hipLaunchKernelGGL(k_decide_block<WK>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(kBlockThreads),
                            0, st, g, ms, cr.begin[2], cr.count[2], fw);
     }
+    mark(3);
     if (cr.hub_count > 0) {
         hipLaunchKernelGGL(k_hub_insert<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
                            cr.hub_first, cr.hub_count);
         hipLaunchKernelGGL(k_hub_eval<WK>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
                            cr.hub_first, cr.hub_count, ha.hub_wD, fw);
     }
+    mark(4);
 }
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, hipEvent_t ev0, hipEvent_t ev1, hipStream_t st) {
-    if (ev0) HIPCHK(hipEventRecord(ev0, st));
+                       bool force_wide, const hipEvent_t *ev, hipStream_t st) {
     int fw = force_wide ? 1 : 0;
     switch (g.wkind) {
-        case 0: class_step_wk<0>(g, ms, cr, ha, fw, st); break;
-        case 1: class_step_wk<1>(g, ms, cr, ha, fw, st); break;
-        default: class_step_wk<2>(g, ms, cr, ha, fw, st); break;
+        case 0: class_step_wk<0>(g, ms, cr, ha, fw, ev, st); break;
+        case 1: class_step_wk<1>(g, ms, cr, ha, fw, ev, st); break;
+        default: class_step_wk<2>(g, ms, cr, ha, fw, ev, st); break;
     }
-    if (ev1) HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(hipGetLastError());
 }
 
