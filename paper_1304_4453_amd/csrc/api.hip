@@ -72,6 +72,11 @@ __global__ void k_export_w(GraphView g, int64_t *out) {
     }
 }
 
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // rows holding a self-loop entry (rows are strictly ascending: binary search)
 __global__ void k_count_loops(GraphView g, unsigned long long *cnt) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,6 +131,8 @@ struct plm_ctx {
             *hub_wD = nullptr;
     unsigned long long *part = nullptr;
     int64_t hub_cap_slots = 0, hub_cap_part = 0, hub_cap_hubs = 0;
+    int hub_tab_mode = -1;  // table contents: -1 unset, 0 key/value arrays, 1 packed words
+    bool hub_packed = false;
     int32_t sweeps = 0;
     // device counters: [0] moves, [1..4] candidates per bin, [5] S, [6] max vol,
     // [7] loop-only rows, [8..11] entries per bin
@@ -200,9 +207,20 @@ struct plm_ctx {
         if (slots > hub_cap_slots) {
             dev_free(tab_key); dev_free(tab_val);
             tab_key = dev_alloc<int32_t>(slots); tab_val = dev_alloc<int64_t>(slots);
-            HIPCHK(hipMemsetAsync(tab_key, 0xff, slots * 4, st));
-            HIPCHK(hipMemsetAsync(tab_val, 0, slots * 8, st));
             hub_cap_slots = slots;
+            hub_tab_mode = -1;
+        }
+        int mode = hub_packed ? 1 : 0;
+        if (mode != hub_tab_mode) {  // empty tables in the layout this level uses
+            if (mode == 1) {
+                hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)cdiv(hub_cap_slots, 256)), dim3(256), 0, st,
+                                   (unsigned long long *)tab_val, hub_cap_slots, 0xFFFFFFFF00000000ULL);
+            } else {
+                HIPCHK(hipMemsetAsync(tab_key, 0xff, hub_cap_slots * 4, st));
+                HIPCHK(hipMemsetAsync(tab_val, 0, hub_cap_slots * 8, st));
+            }
+            HIPCHK(hipGetLastError());
+            hub_tab_mode = mode;
         }
         if (parts > hub_cap_part) {
             dev_free(part);
@@ -290,6 +308,7 @@ struct plm_ctx {
             max_slots = slots > max_slots ? slots : max_slots;
             max_parts = eb > max_parts ? eb : max_parts;
         }
+        hub_packed = max_vol < (1LL << 32);  // every partial w(u, X) fits 32 bits
         if (H > 0) {
             ensure_hub_capacity(H, max_slots, max_parts);
             HIPCHK(hipMemcpyAsync(hub_pos, hpos.data(), H * 4, hipMemcpyHostToDevice, st));
@@ -320,7 +339,7 @@ struct plm_ctx {
         HubArrays ha;
         ha.hub_pos = hub_pos; ha.tab_off = tab_off; ha.tab_bits = tab_bits; ha.ins_first = ins_first;
         ha.eval_first = eval_first; ha.eval_cnt = eval_cnt; ha.tab_key = tab_key; ha.tab_val = tab_val;
-        ha.part = part; ha.done = done; ha.hub_wD = hub_wD;
+        ha.part = part; ha.done = done; ha.hub_wD = hub_wD; ha.packed = hub_packed ? 1 : 0;
         return ha;
     }
 

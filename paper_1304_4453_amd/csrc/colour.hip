@@ -1,0 +1,339 @@
+// colour.hip - the priority colouring that fixes the move schedule.
+//
+// Colour of u = smallest colour not used by a higher-priority non-loop
+// neighbour, priorities (H(seed, level, u), u).  Computed as Jones-Plassmann:
+// pending(u) = number of higher-priority neighbours; a node whose count drops
+// to 0 joins the next frontier; a frontier node takes the smallest free colour
+// among its (all already coloured) higher-priority neighbours and decrements
+// its lower-priority neighbours.  This is exactly the greedy colouring in
+// descending priority order.
+//
+// Rounds run back to back on the device: each round is one launch over
+// triple-buffered queues (round r reads set r%3, pushes into set (r+1)%3 and
+// clears set (r+2)%3), so the host only checks for an empty frontier every few
+// rounds.  Frontier nodes are split by row length: one lane per node (<= 32
+// entries), one wavefront per node (<= 1024), and several workgroups per node
+// above that; the latter OR the colours they see into a block-local LDS bitmap,
+// merge it into a per-node global bitmap, and a second launch per round picks
+// the smallest free colour.
+#include <hip/hip_runtime.h>
+
+#include "level.h"
+
+namespace plm {
+
+constexpr int kCT = 256;                  // threads per workgroup
+constexpr int kCChunk = 16;               // entries per thread (pending counts)
+constexpr int64_t kLaneRow = 32;          // row length handled by one lane
+constexpr int64_t kWaveRow = 1024;        // row length handled by one wavefront
+constexpr int kWin = 4096;                // colour window of a bitmap (bits)
+constexpr int kWinWords = kWin / 32;
+constexpr int kRoundGrid = 2048;          // workgroups of a round launch
+constexpr int kRoundsPerCheck = 16;       // rounds launched between host checks
+
+struct JpQ {
+    int32_t *q[3][3];  // [set][kind]: 0 lane, 1 wavefront, 2 multi-workgroup
+    int32_t *cnt;      // [set * 4 + kind]; [12] = ncol, [13] = nodes coloured
+    uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
+};
+
+__global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, int32_t level, int32_t *pending) {
+    int64_t e0 = ((int64_t)blockIdx.x * kCT + threadIdx.x) * kCChunk;
+    if (e0 >= g.nnz) return;
+    int64_t e1 = e0 + kCChunk < g.nnz ? e0 + kCChunk : g.nnz;
+    int64_t r = row_of(g.off, g.n, e0);
+    int64_t rend = g.off[r + 1];
+    uint64_t hr = prio_hash(seed, level, r);
+    int32_t cnt = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        while (e >= rend) {
+            if (cnt) atomicAdd(&pending[r], cnt);
+            cnt = 0;
+            ++r;
+            rend = g.off[r + 1];
+            hr = prio_hash(seed, level, r);
+        }
+        int64_t v = g.col[e];
+        if (v != r && prio_greater(prio_hash(seed, level, v), v, hr, r)) ++cnt;
+    }
+    if (cnt) atomicAdd(&pending[r], cnt);
+}
+
+__device__ __forceinline__ int row_kind(const int64_t *off, int32_t v) {
+    int64_t d = off[v + 1] - off[v];
+    return d <= kLaneRow ? 0 : (d <= kWaveRow ? 1 : 2);
+}
+
+// Queue push, aggregated over the active lanes of the wavefront: one counter
+// atomic per (wavefront, queue kind).
+__device__ __forceinline__ void jp_push(const JpQ &Q, int set, int32_t v, const int64_t *off) {
+    const int k = row_kind(off, v);
+    const int lane = lane_id();
+    const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        uint64_t m = __ballot(k == kk);
+        if (k == kk) {
+            int leader = __ffsll((unsigned long long)m) - 1;
+            int32_t base = 0;
+            if (lane == leader) base = atomicAdd(&Q.cnt[set * 4 + kk], (int32_t)__popcll(m));
+            base = __shfl(base, leader);
+            Q.q[set][kk][base + (int32_t)__popcll(m & lt)] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_max_colour(const JpQ &Q, int32_t c) {
+    for (int s = 32; s >= 1; s >>= 1) {
+        int32_t o = __shfl_xor(c, s);
+        c = o > c ? o : c;
+    }
+    if (lane_id() == 0 && c > 0) atomicMax(&Q.cnt[12], c);
+}
+
+__global__ void k_jp_seed(GraphView g, const int32_t *pending, int32_t *colour, JpQ Q) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= g.n) return;
+    colour[u] = -1;
+    if (pending[u] == 0) jp_push(Q, 0, (int32_t)u, g.off);
+}
+
+__device__ __forceinline__ void jp_release(const JpQ &Q, int nxt, int32_t v, int32_t *pending, const int64_t *off) {
+    if (atomicSub(&pending[v], 1) == 1) jp_push(Q, nxt, v, off);
+}
+
+__device__ __forceinline__ void count_coloured(const JpQ &Q, int64_t c) {
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
+    if (lane_id() == 0 && c) atomicAdd(&Q.cnt[13], (int32_t)c);
+}
+
+// smallest colour >= base not set in an LDS window bitmap, or -1 (wave-wide)
+__device__ __forceinline__ int32_t wave_first_free(const uint32_t *bm, int32_t base) {
+    int32_t best = 0x7fffffff;
+    for (int j = lane_id(); j < kWinWords; j += kWave) {
+        uint32_t f = ~bm[j];
+        if (f) {
+            int32_t c = j * 32 + __builtin_ctz(f);
+            best = c < best ? c : best;
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        int32_t o = __shfl_xor(best, d);
+        best = o < best ? o : best;
+    }
+    return best == 0x7fffffff ? -1 : base + best;
+}
+
+// Wavefront colours node u by scanning its row in colour windows (used for
+// rows up to kWaveRow, and as the rare fallback when a hub's first window is
+// full).
+__device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t seed, int32_t level, int32_t u,
+                                                    uint64_t hu, const int32_t *colour, uint32_t *bm,
+                                                    int32_t base0) {
+    int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    for (int32_t base = base0;; base += kWin) {
+        for (int j = lane_id(); j < kWinWords; j += kWave) bm[j] = 0;
+        wave_sync();
+        for (int64_t e = e0 + lane_id(); e < e1; e += kWave) {
+            int32_t v = g.col[e];
+            if (v == u) continue;
+            if (prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+                int32_t c = colour[v] - base;
+                if (c >= 0 && c < kWin) atomicOr(&bm[c >> 5], 1u << (c & 31));
+            }
+        }
+        wave_sync();
+        int32_t f = wave_first_free(bm, base);
+        wave_sync();
+        if (f >= 0) return f;
+    }
+}
+
+__global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, int32_t level, int32_t r,
+                                                  int32_t *colour, int32_t *pending, JpQ Q) {
+    __shared__ uint32_t wbm[kCT / kWave][kWinWords];
+    __shared__ uint32_t bbm[kWinWords];
+    const int set = r % 3, nxt = (r + 1) % 3, old = (r + 2) % 3;
+    if (blockIdx.x == 0 && threadIdx.x < 3) Q.cnt[old * 4 + threadIdx.x] = 0;
+    const int32_t ns = Q.cnt[set * 4 + 0], nm = Q.cnt[set * 4 + 1], nh = Q.cnt[set * 4 + 2];
+    const int64_t gthreads = (int64_t)gridDim.x * kCT;
+    const int64_t gtid = (int64_t)blockIdx.x * kCT + threadIdx.x;
+    int64_t coloured = 0;
+    int32_t maxc = 0;  // 1 + largest colour given by this thread
+    // one lane per node
+    for (int64_t i = gtid; i < ns; i += gthreads) {
+        int32_t u = Q.q[set][0][i];
+        uint64_t hu = prio_hash(seed, level, u);
+        int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        uint64_t used = 0;  // row length <= 32 bounds the answer below 33
+        for (int64_t e = e0; e < e1; ++e) {
+            int32_t v = g.col[e];
+            if (v != u && prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+                int32_t c = colour[v];
+                if (c < 64) used |= 1ULL << c;
+            }
+        }
+        int32_t c = __builtin_ctzll(~used);
+        colour[u] = c;
+        maxc = c + 1 > maxc ? c + 1 : maxc;
+        ++coloured;
+        for (int64_t e = e0; e < e1; ++e) {
+            int32_t v = g.col[e];
+            if (v != u && !prio_greater(prio_hash(seed, level, v), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
+        }
+    }
+    count_coloured(Q, coloured);
+    wave_max_colour(Q, maxc);
+    // one wavefront per node
+    const int w = threadIdx.x / kWave;
+    for (int64_t i = (int64_t)blockIdx.x * (kCT / kWave) + w; i < nm; i += (int64_t)gridDim.x * (kCT / kWave)) {
+        int32_t u = Q.q[set][1][i];
+        uint64_t hu = prio_hash(seed, level, u);
+        int32_t c = wave_colour_scan(g, seed, level, u, hu, colour, wbm[w], 0);
+        if (lane_id() == 0) {
+            colour[u] = c;
+            atomicMax(&Q.cnt[12], c + 1);
+            atomicAdd(&Q.cnt[13], 1);
+        }
+        for (int64_t e = g.off[u] + lane_id(); e < g.off[u + 1]; e += kWave) {
+            int32_t v = g.col[e];
+            if (v != u && !prio_greater(prio_hash(seed, level, v), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
+        }
+    }
+    // several workgroups per node.  nh <= grid: hub j takes the workgroups
+    // b = j, j + nh, j + 2 nh, ... (part k of nk); nh > grid: workgroup b takes
+    // hubs b, b + grid, ... alone.
+    if (nh > 0) {
+        const int64_t G = gridDim.x;
+        const bool spread = nh <= G;
+        for (int64_t j = spread ? (int64_t)blockIdx.x % nh : (int64_t)blockIdx.x; j < nh; j += spread ? nh : G) {
+            const int64_t k = spread ? (int64_t)blockIdx.x / nh : 0;
+            const int64_t nk = spread ? (G - j + nh - 1) / nh : 1;
+            int32_t u = Q.q[set][2][j];
+            uint64_t hu = prio_hash(seed, level, u);
+            int64_t e0 = g.off[u], e1 = g.off[u + 1];
+            for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
+            __syncthreads();
+            for (int64_t e = e0 + k * kCT + threadIdx.x; e < e1; e += nk * kCT) {
+                int32_t v = g.col[e];
+                if (v == u) continue;
+                if (prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+                    int32_t c = colour[v];
+                    if (c < kWin) atomicOr(&bbm[c >> 5], 1u << (c & 31));
+                } else {
+                    jp_release(Q, nxt, v, pending, g.off);
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < kWinWords; i += kCT)
+                if (bbm[i]) atomicOr(&Q.bitmap[j * kWinWords + i], bbm[i]);
+            __syncthreads();
+            if (spread) break;
+        }
+    }
+}
+
+// smallest free colour of each multi-workgroup node of round r
+__global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, int32_t level, int32_t r,
+                                                   int32_t *colour, JpQ Q) {
+    __shared__ uint32_t wbm[kCT / kWave][kWinWords];
+    const int set = r % 3, w = threadIdx.x / kWave;
+    const int32_t nh = Q.cnt[set * 4 + 2];
+    for (int64_t j = (int64_t)blockIdx.x * (kCT / kWave) + w; j < nh; j += (int64_t)gridDim.x * (kCT / kWave)) {
+        uint32_t *bm = Q.bitmap + j * kWinWords;
+        for (int i = lane_id(); i < kWinWords; i += kWave) wbm[w][i] = bm[i];
+        wave_sync();
+        int32_t c = wave_first_free(wbm[w], 0);
+        wave_sync();
+        for (int i = lane_id(); i < kWinWords; i += kWave) bm[i] = 0;
+        int32_t u = Q.q[set][2][j];
+        if (c < 0) c = wave_colour_scan(g, seed, level, u, prio_hash(seed, level, u), colour, wbm[w], kWin);
+        if (lane_id() == 0) {
+            colour[u] = c;
+            atomicMax(&Q.cnt[12], c + 1);
+            atomicAdd(&Q.cnt[13], 1);
+        }
+    }
+}
+
+__global__ void k_count_hubs(const int64_t *off, int64_t n, int32_t *cnt) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c = (u < n && off[u + 1] - off[u] > kWaveRow) ? 1 : 0;
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
+    if (lane_id() == 0 && c) atomicAdd(cnt, (int32_t)c);
+}
+
+// Sequential schedule: class = rank in descending priority.  Keys are the
+// complemented hash; the value array starts in descending id order so that the
+// stable sort puts the larger id first among equal hashes.
+__global__ void k_seq_keys(int64_t n, uint64_t seed, int32_t level, uint64_t *keys, int32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t u = n - 1 - i;
+    keys[i] = ~prio_hash(seed, level, u);
+    vals[i] = (int32_t)u;
+}
+__global__ void k_seq_rank(int64_t n, const int32_t *order, int32_t *colour) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) colour[order[i]] = (int32_t)i;
+}
+
+int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int schedule, int32_t *colour,
+                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st) {
+    int64_t n = g.n;
+    *jp_rounds = 0;
+    if (n == 0) return 0;
+    if (schedule == 1) {
+        scr.reserve(2 * align_up(n * 8) + 2 * align_up(n * 4) + radix_scratch_bytes(n));
+        uint64_t *k = (uint64_t *)scr.get(n * 8), *ka = (uint64_t *)scr.get(n * 8);
+        int32_t *v = (int32_t *)scr.get(n * 4), *va = (int32_t *)scr.get(n * 4);
+        void *rs = scr.get(radix_scratch_bytes(n));
+        hipLaunchKernelGGL(k_seq_keys, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, n, seed, level, k, v);
+        radix_sort_u64_i32(&k, &v, &ka, &va, n, 64, rs, st);
+        hipLaunchKernelGGL(k_seq_rank, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, n, v, colour);
+        HIPCHK(hipGetLastError());
+        return (int32_t)n;
+    }
+    // count rows longer than kWaveRow to size the hub bitmaps
+    scr.reserve(4096);
+    int32_t *hc = (int32_t *)scr.get(8);
+    HIPCHK(hipMemsetAsync(hc, 0, 8, st));
+    hipLaunchKernelGGL(k_count_hubs, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, g.off, n, hc);
+    HIPCHK(hipMemcpyAsync(host_counters, hc, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t nhub = host_counters[0];
+    // pending counts, 9 queues, counters, hub bitmaps
+    scr.reserve(align_up(n * 4) * 10 + 256 + align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4));
+    int32_t *pending = (int32_t *)scr.get(n * 4);
+    JpQ Q;
+    for (int s = 0; s < 3; ++s)
+        for (int k = 0; k < 3; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
+    Q.cnt = (int32_t *)scr.get(16 * sizeof(int32_t));
+    Q.bitmap = (uint32_t *)scr.get((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4);
+    HIPCHK(hipMemsetAsync(pending, 0, n * 4, st));
+    HIPCHK(hipMemsetAsync(Q.cnt, 0, 16 * sizeof(int32_t), st));
+    HIPCHK(hipMemsetAsync(Q.bitmap, 0, (size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4, st));
+    if (g.nnz > 0)
+        hipLaunchKernelGGL(k_jp_pending, dim3((unsigned)cdiv(cdiv(g.nnz, kCChunk), kCT)), dim3(kCT), 0, st, g, seed,
+                           level, pending);
+    hipLaunchKernelGGL(k_jp_seed, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, g, pending, colour, Q);
+    HIPCHK(hipGetLastError());
+    int32_t r = 0;
+    for (;;) {
+        for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
+            hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour, pending, Q);
+            hipLaunchKernelGGL(k_jp_finish, dim3(256), dim3(kCT), 0, st, g, seed, level, r, colour, Q);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int s = r % 3;
+        if (host_counters[s * 4] == 0 && host_counters[s * 4 + 1] == 0 && host_counters[s * 4 + 2] == 0) break;
+        if (r > n + 2 * kRoundsPerCheck) throw Error{-6, "internal: colouring did not converge"};
+    }
+    if (host_counters[13] != n) throw Error{-6, "internal: colouring did not reach every node"};
+    *jp_rounds = r;
+    return host_counters[12];
+}
+
+}  // namespace plm

@@ -54,10 +54,11 @@ struct HubArrays {
     unsigned long long *part;  // per eval block: 4 words (score hi, score lo, X, pad)
     int32_t *done;             // per hub completion counter (zero between uses)
     int64_t *hub_wD;           // per hub w(u, D \ u) found by the eval blocks (zero between uses)
+    int packed;                // slots are single 64-bit words (community << 32 | weight)
 };
 
-constexpr int64_t kHubInsChunk = 4096;   // entries per hub insert workgroup
-constexpr int64_t kHubEvalChunk = 4096;  // table slots per hub eval workgroup
+constexpr int64_t kHubInsChunk = 256;    // entries per hub insert workgroup (one per thread)
+constexpr int64_t kHubEvalChunk = 1024;  // table slots per hub eval workgroup
 constexpr int kHubMinBits = 12;
 
 // ev: null, or 5 events recorded before bin 0 and after bins 0..3

@@ -302,7 +302,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 }
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
+// Rows longer than the workgroup limit accumulate w(u, X) in a per-node hash
+// table in global memory: first an insert launch (one entry per thread over
+// all hubs of the class), then an eval launch (kHubEvalPerThread slots per
+// thread) whose workgroups each leave a partial best; the last workgroup to
+// finish a hub combines its partials.  When every partial sum of the level fits
+// 32 bits (max vol(u) < 2^32) a slot is one 64-bit word (community << 32 |
+// weight), so an insert is a single atomic; otherwise keys and 64-bit values
+// sit in two arrays.  Eval clears every slot it reads, leaving the tables empty
+// for the next class.
 constexpr int kHubThreads = 256;
+constexpr uint64_t kEmptyWord = 0xFFFFFFFF00000000ULL;
 
 // hub h of a class owning class-relative block b: last h with first[h] <= b
 __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
@@ -314,7 +324,7 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
     return lo;
 }
 
-template <int WK>
+template <int WK, bool PACKED>
 __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
                                                             int64_t nh) {
     int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
@@ -322,18 +332,34 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveSta
     int64_t chunk = blockIdx.x - ha.ins_first[hg];
     int32_t u = ms.class_nodes[ha.hub_pos[hg]];
     int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    int64_t e = e0 + chunk * kHubInsChunk + threadIdx.x;
+    if (e >= e1) return;
+    int32_t v = g.col[e];
+    if (v == u) return;
+    int32_t X = ms.zeta[v];
+    int64_t wt = wload<WK>(g.w, e);
     int bits = ha.tab_bits[hg];
     uint32_t mask = (1u << bits) - 1;
-    int32_t *tk = ha.tab_key + ha.tab_off[hg];
-    int64_t *tv = ha.tab_val + ha.tab_off[hg];
-    int64_t c0 = e0 + chunk * kHubInsChunk;
-    int64_t c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += kHubThreads) {
-        int32_t v = g.col[e];
-        if (v == u) continue;
-        int32_t X = ms.zeta[v];
-        int64_t wt = wload<WK>(g.w, e);
-        uint32_t s = slot_hash(X, bits);
+    uint32_t s = slot_hash(X, bits);
+    if constexpr (PACKED) {
+        unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
+        const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)wt;
+        for (;;) {
+            unsigned long long cur = tw[s];  // a stale "empty" is caught by the CAS
+            if (cur == kEmptyWord) {
+                unsigned long long old = atomicCAS(&tw[s], kEmptyWord, want);
+                if (old == kEmptyWord) break;
+                cur = old;
+            }
+            if ((uint32_t)(cur >> 32) == (uint32_t)X) {
+                atomicAdd(&tw[s], (unsigned long long)wt);
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+    } else {
+        int32_t *tk = ha.tab_key + ha.tab_off[hg];
+        int64_t *tv = ha.tab_val + ha.tab_off[hg];
         for (;;) {
             int32_t k = atomicCAS(&tk[s], kEmpty, X);
             if (k == kEmpty || k == X) {
@@ -345,29 +371,14 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveSta
     }
 }
 
+// block-wide (s desc, X asc) argmax; result valid in thread 0
 template <typename G>
-__device__ __forceinline__ void hub_block_best(int32_t *tk, int64_t *tv, int64_t s0, int64_t s1, int32_t D,
-                                               int64_t vu, int64_t S, const int64_t *volC, int64_t *wD_slot,
-                                               G &bs, int32_t &bx, int64_t &ncand) {
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += kHubThreads) {
-        int32_t X = tk[s];
-        if (X >= 0) {
-            int64_t a = tv[s];
-            tk[s] = kEmpty;
-            tv[s] = 0;
-            if (X == D) {
-                *wD_slot = a;  // exactly one slot holds D
-            } else {
-                ++ncand;
-                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-            }
-        }
-    }
-    wave_argmax<G>(bs, bx);
+__device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
     __shared__ G red_s[kHubThreads / kWave];
     __shared__ int32_t red_x[kHubThreads / kWave];
+    wave_argmax<G>(bs, bx);
     const int w = threadIdx.x / kWave;
+    __syncthreads();
     if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; }
     __syncthreads();
     if (threadIdx.x == 0)
@@ -375,9 +386,42 @@ __device__ __forceinline__ void hub_block_best(int32_t *tk, int64_t *tv, int64_t
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
 }
 
-template <int WK>
+template <typename G, bool PACKED>
+__device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, int64_t s0, int64_t s1, int32_t D,
+                                               int64_t vu, int64_t S, const int64_t *volC, int64_t *wD_slot,
+                                               G &bs, int32_t &bx, int64_t &ncand) {
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += kHubThreads) {
+        int32_t X;
+        int64_t a;
+        if constexpr (PACKED) {
+            unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
+            unsigned long long word = tw[s];
+            if (word == kEmptyWord) continue;
+            tw[s] = kEmptyWord;
+            X = (int32_t)(word >> 32);
+            a = (int64_t)(word & 0xffffffffULL);
+        } else {
+            int32_t *tk = ha.tab_key + ha.tab_off[hg];
+            int64_t *tv = ha.tab_val + ha.tab_off[hg];
+            X = tk[s];
+            if (X < 0) continue;
+            a = tv[s];
+            tk[s] = kEmpty;
+            tv[s] = 0;
+        }
+        if (X == D) {
+            *wD_slot = a;  // exactly one slot holds D
+        } else {
+            ++ncand;
+            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
+        }
+    }
+}
+
+template <bool PACKED>
 __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
-                                                          int64_t nh, int64_t *hub_wD, int force_wide) {
+                                                          int64_t nh, int force_wide) {
     int64_t h = hub_of_block(ha.eval_first + hub0, nh, blockIdx.x);
     int64_t hg = hub0 + h;
     int64_t chunk = blockIdx.x - ha.eval_first[hg];
@@ -388,55 +432,54 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
     int64_t vu = ms.vol[u];
     bool wide = force_wide || vu > ms.wide_lim;
     int64_t tsize = 1LL << ha.tab_bits[hg];
-    int32_t *tk = ha.tab_key + ha.tab_off[hg];
-    int64_t *tv = ha.tab_val + ha.tab_off[hg];
     int64_t s0 = chunk * kHubEvalChunk, s1 = s0 + kHubEvalChunk < tsize ? s0 + kHubEvalChunk : tsize;
     int64_t ncand = 0;
     unsigned long long *part = ha.part + 4 * (size_t)blockIdx.x;
+    i128 bs = neg_inf<i128>();
+    int32_t bx = kNone;
     if (wide) {
-        i128 bs = neg_inf<i128>();
-        int32_t bx = kNone;
-        hub_block_best<i128>(tk, tv, s0, s1, D, vu, ms.S, ms.volC, &hub_wD[hg], bs, bx, ncand);
-        if (threadIdx.x == 0) {
-            part[0] = (unsigned long long)(uint64_t)(bs >> 64);
-            part[1] = (unsigned long long)(uint64_t)bs;
-            part[2] = (unsigned long long)(uint32_t)bx;
-        }
+        hub_slots_best<i128, PACKED>(ha, hg, s0, s1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], bs, bx, ncand);
+        block_argmax<i128>(bs, bx);
     } else {
-        int64_t bs = neg_inf<int64_t>();
-        int32_t bx = kNone;
-        hub_block_best<int64_t>(tk, tv, s0, s1, D, vu, ms.S, ms.volC, &hub_wD[hg], bs, bx, ncand);
-        if (threadIdx.x == 0) {
-            part[0] = (unsigned long long)(bs < 0 ? -1LL : 0LL);
-            part[1] = (unsigned long long)bs;
-            part[2] = (unsigned long long)(uint32_t)bx;
-        }
+        int64_t b64 = neg_inf<int64_t>();
+        hub_slots_best<int64_t, PACKED>(ha, hg, s0, s1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], b64, bx, ncand);
+        block_argmax<int64_t>(b64, bx);
+        bs = (i128)b64;
+    }
+    if (threadIdx.x == 0) {
+        part[0] = (unsigned long long)(uint64_t)(bs >> 64);
+        part[1] = (unsigned long long)(uint64_t)bs;
+        part[2] = (unsigned long long)(uint32_t)bx;
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
-    // the last block of this hub combines the partial bests
+    // the last workgroup of this hub combines the partial bests
     __shared__ int last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) last = atomicAdd(&ha.done[hg], 1) == (int)(nblk - 1);
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
+    if (!last) return;
     __threadfence();
-    i128 bs = neg_inf<i128>();
-    int32_t bx = kNone;
     unsigned long long *p0 = ha.part + 4 * (size_t)ha.eval_first[hg];
-    for (int64_t j = 0; j < nblk; ++j) {
+    bs = neg_inf<i128>();
+    bx = kNone;
+    for (int64_t j = threadIdx.x; j < nblk; j += kHubThreads) {
         unsigned long long hi = __hip_atomic_load(&p0[4 * j + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long lo = __hip_atomic_load(&p0[4 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int32_t x = (int32_t)__hip_atomic_load(&p0[4 * j + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         i128 s = (i128)(((unsigned __int128)hi << 64) | lo);
         if (x != kNone && (s > bs || (s == bs && x < bx))) { bs = s; bx = x; }
     }
-    int64_t wD = __hip_atomic_load((unsigned long long *)&hub_wD[hg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int64_t base = ms.volC[D] - vu;
-    i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
-    ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
-    hub_wD[hg] = 0;
-    ha.done[hg] = 0;
+    block_argmax<i128>(bs, bx);
+    if (threadIdx.x == 0) {
+        int64_t wD = (int64_t)__hip_atomic_load((unsigned long long *)&ha.hub_wD[hg], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        int64_t base = ms.volC[D] - vu;
+        i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
+        ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
+        ha.hub_wD[hg] = 0;
+        ha.done[hg] = 0;
+    }
 }
 
 // ------------------------------------------------------------------ apply
@@ -492,10 +535,17 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
     }
     mark(3);
     if (cr.hub_count > 0) {
-        hipLaunchKernelGGL(k_hub_insert<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
-                           cr.hub_first, cr.hub_count);
-        hipLaunchKernelGGL(k_hub_eval<WK>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
-                           cr.hub_first, cr.hub_count, ha.hub_wD, fw);
+        if (ha.packed) {
+            hipLaunchKernelGGL((k_hub_insert<WK, true>), dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g,
+                               ms, ha, cr.hub_first, cr.hub_count);
+            hipLaunchKernelGGL(k_hub_eval<true>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                               cr.hub_first, cr.hub_count, fw);
+        } else {
+            hipLaunchKernelGGL((k_hub_insert<WK, false>), dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g,
+                               ms, ha, cr.hub_first, cr.hub_count);
+            hipLaunchKernelGGL(k_hub_eval<false>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms,
+                               ha, cr.hub_first, cr.hub_count, fw);
+        }
     }
     mark(4);
 }
