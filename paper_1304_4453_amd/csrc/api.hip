@@ -130,6 +130,7 @@ struct plm_ctx {
     int64_t *tab_off = nullptr, *ins_first = nullptr, *eval_first = nullptr, *eval_cnt = nullptr, *tab_val = nullptr,
             *hub_wD = nullptr;
     unsigned long long *part = nullptr;
+    int32_t *occ = nullptr, *occ_cnt = nullptr;
     int64_t hub_cap_slots = 0, hub_cap_part = 0, hub_cap_hubs = 0;
     int hub_tab_mode = -1;  // table contents: -1 unset, 0 key/value arrays, 1 packed words
     bool hub_packed = false;
@@ -155,7 +156,7 @@ struct plm_ctx {
     void free_hubs() {
         dev_free(hub_pos); dev_free(tab_bits); dev_free(tab_key); dev_free(done); dev_free(tab_off);
         dev_free(ins_first); dev_free(eval_first); dev_free(eval_cnt); dev_free(tab_val); dev_free(hub_wD);
-        dev_free(part);
+        dev_free(part); dev_free(occ); dev_free(occ_cnt);
         hub_cap_slots = hub_cap_part = hub_cap_hubs = 0;
     }
 
@@ -198,6 +199,8 @@ struct plm_ctx {
     void ensure_hub_capacity(int64_t hubs, int64_t slots, int64_t parts) {
         if (hubs > hub_cap_hubs) {
             dev_free(hub_pos); dev_free(tab_bits); dev_free(done); dev_free(tab_off); dev_free(ins_first);
+            dev_free(occ_cnt);
+            occ_cnt = dev_alloc<int32_t>(hubs);
             dev_free(eval_first); dev_free(eval_cnt); dev_free(hub_wD);
             hub_pos = dev_alloc<int32_t>(hubs); tab_bits = dev_alloc<int32_t>(hubs); done = dev_alloc<int32_t>(hubs);
             tab_off = dev_alloc<int64_t>(hubs); ins_first = dev_alloc<int64_t>(hubs);
@@ -205,8 +208,9 @@ struct plm_ctx {
             hub_cap_hubs = hubs;
         }
         if (slots > hub_cap_slots) {
-            dev_free(tab_key); dev_free(tab_val);
+            dev_free(tab_key); dev_free(tab_val); dev_free(occ);
             tab_key = dev_alloc<int32_t>(slots); tab_val = dev_alloc<int64_t>(slots);
+            occ = dev_alloc<int32_t>(slots / 2 + 1);
             hub_cap_slots = slots;
             hub_tab_mode = -1;
         }
@@ -298,7 +302,7 @@ struct plm_ctx {
                 toff[hg] = slots;
                 ifirst[hg] = ib;
                 efirst[hg] = eb;
-                ecnt[hg] = cdiv(ts, kHubEvalChunk);
+                ecnt[hg] = cdiv(deg[hg], kHubEvalChunk);  // distinct communities <= row length
                 slots += ts;
                 ib += cdiv(deg[hg], kHubInsChunk);
                 eb += ecnt[hg];
@@ -318,6 +322,7 @@ struct plm_ctx {
             HIPCHK(hipMemcpyAsync(eval_first, efirst.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(eval_cnt, ecnt.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemsetAsync(done, 0, H * 4, st));
+            HIPCHK(hipMemsetAsync(occ_cnt, 0, H * 4, st));
             HIPCHK(hipMemsetAsync(hub_wD, 0, H * 8, st));
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -340,6 +345,7 @@ struct plm_ctx {
         ha.hub_pos = hub_pos; ha.tab_off = tab_off; ha.tab_bits = tab_bits; ha.ins_first = ins_first;
         ha.eval_first = eval_first; ha.eval_cnt = eval_cnt; ha.tab_key = tab_key; ha.tab_val = tab_val;
         ha.part = part; ha.done = done; ha.hub_wD = hub_wD; ha.packed = hub_packed ? 1 : 0;
+        ha.occ = occ; ha.occ_cnt = occ_cnt;
         return ha;
     }
 

@@ -55,10 +55,12 @@ struct HubArrays {
     int32_t *done;             // per hub completion counter (zero between uses)
     int64_t *hub_wD;           // per hub w(u, D \ u) found by the eval blocks (zero between uses)
     int packed;                // slots are single 64-bit words (community << 32 | weight)
+    int32_t *occ;              // occupied-slot list of each hub at tab_off / 2 (capacity tsize / 2)
+    int32_t *occ_cnt;          // per hub length of that list (zero between uses)
 };
 
-constexpr int64_t kHubInsChunk = 256;    // entries per hub insert workgroup (one per thread)
-constexpr int64_t kHubEvalChunk = 1024;  // table slots per hub eval workgroup
+constexpr int64_t kHubInsChunk = 2048;   // entries per hub insert workgroup
+constexpr int64_t kHubEvalChunk = 1024;  // occupied slots per hub eval workgroup
 constexpr int kHubMinBits = 12;
 
 // ev: null, or 5 events recorded before bin 0 and after bins 0..3

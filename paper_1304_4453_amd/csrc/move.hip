@@ -303,15 +303,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
 // Rows longer than the workgroup limit accumulate w(u, X) in a per-node hash
-// table in global memory: first an insert launch (one entry per thread over
-// all hubs of the class), then an eval launch (kHubEvalPerThread slots per
-// thread) whose workgroups each leave a partial best; the last workgroup to
-// finish a hub combines its partials.  When every partial sum of the level fits
-// 32 bits (max vol(u) < 2^32) a slot is one 64-bit word (community << 32 |
-// weight), so an insert is a single atomic; otherwise keys and 64-bit values
-// sit in two arrays.  Eval clears every slot it reads, leaving the tables empty
-// for the next class.
+// table in global memory.  Insert: each workgroup first folds a chunk of
+// kHubInsChunk entries into an LDS table, then adds its distinct communities
+// to the node's global table; a key that a workgroup creates is appended to the
+// node's list of occupied slots.  Eval: workgroups walk the occupied list
+// (clearing the slots), each leaves a partial best, and the last one to finish
+// combines them.  When every partial sum of the level fits 32 bits (max
+// vol(u) < 2^32) a global slot is one 64-bit word (community << 32 | weight);
+// otherwise keys and 64-bit values sit in two arrays.
 constexpr int kHubThreads = 256;
+constexpr int kHubLdsSlots = 4096;  // LDS table of an insert workgroup (2 x kHubInsChunk)
 constexpr uint64_t kEmptyWord = 0xFFFFFFFF00000000ULL;
 
 // hub h of a class owning class-relative block b: last h with first[h] <= b
@@ -324,36 +325,26 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
     return lo;
 }
 
-template <int WK, bool PACKED>
-__global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
-                                                            int64_t nh) {
-    int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
-    int64_t hg = hub0 + h;
-    int64_t chunk = blockIdx.x - ha.ins_first[hg];
-    int32_t u = ms.class_nodes[ha.hub_pos[hg]];
-    int64_t e0 = g.off[u], e1 = g.off[u + 1];
-    int64_t e = e0 + chunk * kHubInsChunk + threadIdx.x;
-    if (e >= e1) return;
-    int32_t v = g.col[e];
-    if (v == u) return;
-    int32_t X = ms.zeta[v];
-    int64_t wt = wload<WK>(g.w, e);
-    int bits = ha.tab_bits[hg];
-    uint32_t mask = (1u << bits) - 1;
+// adds (X, a) to a node's global table; true if this call created the key;
+// *slot_out = the key's slot
+template <bool PACKED>
+__device__ __forceinline__ bool global_insert(const HubArrays &ha, int64_t hg, int32_t X, int64_t a, uint32_t mask,
+                                              int bits, uint32_t *slot_out) {
     uint32_t s = slot_hash(X, bits);
     if constexpr (PACKED) {
         unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
-        const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)wt;
+        const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)a;
         for (;;) {
             unsigned long long cur = tw[s];  // a stale "empty" is caught by the CAS
             if (cur == kEmptyWord) {
                 unsigned long long old = atomicCAS(&tw[s], kEmptyWord, want);
-                if (old == kEmptyWord) break;
+                if (old == kEmptyWord) { *slot_out = s; return true; }
                 cur = old;
             }
             if ((uint32_t)(cur >> 32) == (uint32_t)X) {
-                atomicAdd(&tw[s], (unsigned long long)wt);
-                break;
+                atomicAdd(&tw[s], (unsigned long long)a);
+                *slot_out = s;
+                return false;
             }
             s = (s + 1) & mask;
         }
@@ -363,10 +354,62 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveSta
         for (;;) {
             int32_t k = atomicCAS(&tk[s], kEmpty, X);
             if (k == kEmpty || k == X) {
-                atomicAdd((unsigned long long *)&tv[s], (unsigned long long)wt);
-                break;
+                atomicAdd((unsigned long long *)&tv[s], (unsigned long long)a);
+                *slot_out = s;
+                return k == kEmpty;
             }
             s = (s + 1) & mask;
+        }
+    }
+}
+
+template <int WK, bool PACKED>
+__global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
+                                                            int64_t nh) {
+    __shared__ int32_t lk[kHubLdsSlots];
+    __shared__ int64_t lv[kHubLdsSlots];
+    for (int s = threadIdx.x; s < kHubLdsSlots; s += kHubThreads) { lk[s] = kEmpty; lv[s] = 0; }
+    int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
+    int64_t hg = hub0 + h;
+    int64_t chunk = blockIdx.x - ha.ins_first[hg];
+    int32_t u = ms.class_nodes[ha.hub_pos[hg]];
+    int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    int64_t c0 = e0 + chunk * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
+    __syncthreads();
+    constexpr int kLdsBits = 12;
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += kHubThreads) {
+        int32_t v = g.col[e];
+        if (v == u) continue;
+        int32_t X = ms.zeta[v];
+        int64_t wt = wload<WK>(g.w, e);
+        uint32_t s = slot_hash(X, kLdsBits);
+        for (;;) {
+            int32_t k = atomicCAS(&lk[s], kEmpty, X);
+            if (k == kEmpty || k == X) {
+                atomicAdd((unsigned long long *)&lv[s], (unsigned long long)wt);
+                break;
+            }
+            s = (s + 1) & (kHubLdsSlots - 1);
+        }
+    }
+    __syncthreads();
+    const int bits = ha.tab_bits[hg];
+    const uint32_t mask = (1u << bits) - 1;
+    int32_t *occ = ha.occ + (ha.tab_off[hg] >> 1);
+    const int lane = lane_id();
+    const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    for (int s0 = 0; s0 < kHubLdsSlots; s0 += kHubThreads) {
+        int32_t X = lk[s0 + threadIdx.x];
+        bool created = false;
+        uint32_t slot = 0;
+        if (X >= 0) created = global_insert<PACKED>(ha, hg, X, lv[s0 + threadIdx.x], mask, bits, &slot);
+        uint64_t m = __ballot(created);
+        if (m) {
+            int leader = __ffsll((unsigned long long)m) - 1;
+            int32_t base = 0;
+            if (lane == leader) base = atomicAdd(&ha.occ_cnt[hg], (int32_t)__popcll(m));
+            base = __shfl(base, leader);
+            if (created) occ[base + (int32_t)__popcll(m & lt)] = (int32_t)slot;
         }
     }
 }
@@ -387,16 +430,16 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
 }
 
 template <typename G, bool PACKED>
-__device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, int64_t s0, int64_t s1, int32_t D,
-                                               int64_t vu, int64_t S, const int64_t *volC, int64_t *wD_slot,
-                                               G &bs, int32_t &bx, int64_t &ncand) {
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += kHubThreads) {
+__device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, const int32_t *occ, int64_t i0,
+                                               int64_t i1, int32_t D, int64_t vu, int64_t S, const int64_t *volC,
+                                               int64_t *wD_slot, G &bs, int32_t &bx, int64_t &ncand) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kHubThreads) {
+        int32_t s = occ[i];
         int32_t X;
         int64_t a;
         if constexpr (PACKED) {
             unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
             unsigned long long word = tw[s];
-            if (word == kEmptyWord) continue;
             tw[s] = kEmptyWord;
             X = (int32_t)(word >> 32);
             a = (int64_t)(word & 0xffffffffULL);
@@ -404,7 +447,6 @@ __device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, 
             int32_t *tk = ha.tab_key + ha.tab_off[hg];
             int64_t *tv = ha.tab_val + ha.tab_off[hg];
             X = tk[s];
-            if (X < 0) continue;
             a = tv[s];
             tk[s] = kEmpty;
             tv[s] = 0;
@@ -431,18 +473,19 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
     int32_t D = ms.zeta[u];
     int64_t vu = ms.vol[u];
     bool wide = force_wide || vu > ms.wide_lim;
-    int64_t tsize = 1LL << ha.tab_bits[hg];
-    int64_t s0 = chunk * kHubEvalChunk, s1 = s0 + kHubEvalChunk < tsize ? s0 + kHubEvalChunk : tsize;
+    const int32_t *occ = ha.occ + (ha.tab_off[hg] >> 1);
+    int64_t nocc = ha.occ_cnt[hg];
+    int64_t i0 = chunk * kHubEvalChunk, i1 = i0 + kHubEvalChunk < nocc ? i0 + kHubEvalChunk : nocc;
     int64_t ncand = 0;
     unsigned long long *part = ha.part + 4 * (size_t)blockIdx.x;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
     if (wide) {
-        hub_slots_best<i128, PACKED>(ha, hg, s0, s1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], bs, bx, ncand);
+        hub_slots_best<i128, PACKED>(ha, hg, occ, i0, i1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], bs, bx, ncand);
         block_argmax<i128>(bs, bx);
     } else {
         int64_t b64 = neg_inf<int64_t>();
-        hub_slots_best<int64_t, PACKED>(ha, hg, s0, s1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], b64, bx, ncand);
+        hub_slots_best<int64_t, PACKED>(ha, hg, occ, i0, i1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], b64, bx, ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
     }
@@ -479,6 +522,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
         ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
         ha.hub_wD[hg] = 0;
         ha.done[hg] = 0;
+        ha.occ_cnt[hg] = 0;
     }
 }
 
