@@ -307,8 +307,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 // kHubInsChunk entries into an LDS table, then adds its distinct communities
 // to the node's global table; a key that a workgroup creates is appended to the
 // node's list of occupied slots.  Eval: workgroups walk the occupied list
-// (clearing the slots), each leaves a partial best, and the last one to finish
-// combines them.  When every partial sum of the level fits 32 bits (max
+// (clearing the slots), each leaves a partial best, and a third launch (one
+// workgroup per node) combines them.  When every partial sum of the level fits 32 bits (max
 // vol(u) < 2^32) a global slot is one 64-bit word (community << 32 | weight);
 // otherwise keys and 64-bit values sit in two arrays.
 constexpr int kHubThreads = 256;
@@ -467,7 +467,6 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
     int64_t h = hub_of_block(ha.eval_first + hub0, nh, blockIdx.x);
     int64_t hg = hub0 + h;
     int64_t chunk = blockIdx.x - ha.eval_first[hg];
-    int64_t nblk = ha.eval_cnt[hg];
     int64_t pos = ha.hub_pos[hg];
     int32_t u = ms.class_nodes[pos];
     int32_t D = ms.zeta[u];
@@ -495,33 +494,32 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
         part[2] = (unsigned long long)(uint32_t)bx;
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
-    // the last workgroup of this hub combines the partial bests
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&ha.done[hg], 1) == (int)(nblk - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    unsigned long long *p0 = ha.part + 4 * (size_t)ha.eval_first[hg];
-    bs = neg_inf<i128>();
-    bx = kNone;
+}
+
+// One workgroup per hub of the class combines the eval partials (written by
+// the previous launch, so no fence is needed) and decides the move.
+__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArrays ha, int64_t hub0) {
+    int64_t hg = hub0 + blockIdx.x;
+    int64_t nblk = ha.eval_cnt[hg];
+    const unsigned long long *p0 = ha.part + 4 * (size_t)ha.eval_first[hg];
+    i128 bs = neg_inf<i128>();
+    int32_t bx = kNone;
     for (int64_t j = threadIdx.x; j < nblk; j += kHubThreads) {
-        unsigned long long hi = __hip_atomic_load(&p0[4 * j + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long lo = __hip_atomic_load(&p0[4 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int32_t x = (int32_t)__hip_atomic_load(&p0[4 * j + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        i128 s = (i128)(((unsigned __int128)hi << 64) | lo);
+        int32_t x = (int32_t)p0[4 * j + 2];
+        i128 s = (i128)(((unsigned __int128)p0[4 * j + 0] << 64) | p0[4 * j + 1]);
         if (x != kNone && (s > bs || (s == bs && x < bx))) { bs = s; bx = x; }
     }
     block_argmax<i128>(bs, bx);
     if (threadIdx.x == 0) {
-        int64_t wD = (int64_t)__hip_atomic_load((unsigned long long *)&ha.hub_wD[hg], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
+        int64_t pos = ha.hub_pos[hg];
+        int32_t u = ms.class_nodes[pos];
+        int32_t D = ms.zeta[u];
+        int64_t vu = ms.vol[u];
+        int64_t wD = ha.hub_wD[hg];
         int64_t base = ms.volC[D] - vu;
         i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
         ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
         ha.hub_wD[hg] = 0;
-        ha.done[hg] = 0;
         ha.occ_cnt[hg] = 0;
     }
 }
@@ -584,11 +582,15 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
                                ms, ha, cr.hub_first, cr.hub_count);
             hipLaunchKernelGGL(k_hub_eval<true>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
                                cr.hub_first, cr.hub_count, fw);
+            hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
+                               cr.hub_first);
         } else {
             hipLaunchKernelGGL((k_hub_insert<WK, false>), dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g,
                                ms, ha, cr.hub_first, cr.hub_count);
             hipLaunchKernelGGL(k_hub_eval<false>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms,
                                ha, cr.hub_first, cr.hub_count, fw);
+            hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
+                               cr.hub_first);
         }
     }
     mark(4);
