@@ -135,35 +135,63 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
 }
 
 // ------------------------------------------------------------------ wavefront per node
+// Entries whose neighbour is already in u's own community D are summed in
+// registers (w(u, D\u) is needed on its own anyway) and never enter the hash
+// table: on graphs where many neighbours have joined u, the table would
+// otherwise serialise on that one key.
 constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 
 template <typename G>
-__device__ __forceinline__ void wave_eval(const int32_t *tk, const int64_t *tv, int32_t *tkw, int64_t *tvw, int tsize,
-                                          int32_t D, int64_t vu, int64_t base, int64_t S, const int64_t *volC,
-                                          int32_t &best_x, bool &move, int64_t &ncand) {
+__device__ __forceinline__ void wave_eval(int32_t *tk, int64_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
+                                          int64_t S, const int64_t *volC, int32_t &best_x, bool &move,
+                                          int64_t &ncand) {
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    int64_t wD = 0;
     for (int s = lane_id(); s < tsize; s += kWave) {
         int32_t X = tk[s];
         if (X >= 0) {
             int64_t a = tv[s];
-            tkw[s] = kEmpty;
-            tvw[s] = 0;
-            if (X == D) {
-                wD = a;
-            } else {
-                ++ncand;
-                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-            }
+            tk[s] = kEmpty;
+            tv[s] = 0;
+            ++ncand;
+            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
         }
     }
-    wD = wave_sum(wD);
     wave_argmax<G>(bs, bx);
     G K = (G)S * (G)wD - (G)vu * (G)base;
     best_x = bx;
     move = bx != kNone && bs > K;
+}
+
+// folds the (X, w) entries of u into a hash table (LDS) except X == D; returns
+// this thread's share of w(u, D \ u)
+template <int WK>
+__device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *zeta, int32_t u, int32_t D, int64_t e0,
+                                            int64_t e1, int64_t first, int64_t step, int32_t *tk, int64_t *tv,
+                                            int bits) {
+    const uint32_t mask = (1u << bits) - 1;
+    int64_t myD = 0;
+    for (int64_t e = e0 + first; e < e1; e += step) {
+        int32_t v = g.col[e];
+        if (v == u) continue;
+        int32_t X = zeta[v];
+        int64_t wt = wload<WK>(g.w, e);
+        if (X == D) {
+            myD += wt;
+            continue;
+        }
+        uint32_t h = slot_hash(X, bits);
+        for (;;) {
+            int32_t k = atomicCAS(&tk[h], kEmpty, X);
+            if (k == kEmpty || k == X) {
+                atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt);
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+    return myD;
 }
 
 template <int WK>
@@ -181,33 +209,18 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
-        int tsize = 1 << bits;
-        uint32_t mask = (uint32_t)tsize - 1;
         int32_t D = ms.zeta[u];
-        for (int64_t e = e0 + lane; e < e1; e += kWave) {
-            int32_t v = g.col[e];
-            if (v == u) continue;
-            int32_t X = ms.zeta[v];
-            int64_t wt = wload<WK>(g.w, e);
-            uint32_t h = slot_hash(X, bits);
-            for (;;) {
-                int32_t k = atomicCAS(&tk[w][h], kEmpty, X);
-                if (k == kEmpty || k == X) {
-                    atomicAdd((unsigned long long *)&tv[w][h], (unsigned long long)wt);
-                    break;
-                }
-                h = (h + 1) & mask;
-            }
-        }
+        int64_t wD = fold_row<WK>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
+        wD = wave_sum(wD);
         wave_sync();
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
         int32_t bx;
         bool mv;
         if (force_wide || vu > ms.wide_lim)
-            wave_eval<i128>(tk[w], tv[w], tk[w], tv[w], tsize, D, vu, base, ms.S, ms.volC, bx, mv, ncand);
+            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, vu, base, ms.S, ms.volC, bx, mv, ncand);
         else
-            wave_eval<int64_t>(tk[w], tv[w], tk[w], tv[w], tsize, D, vu, base, ms.S, ms.volC, bx, mv, ncand);
+            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu, base, ms.S, ms.volC, bx, mv, ncand);
         if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
         wave_sync();
     }
@@ -219,30 +232,25 @@ constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
 
 template <typename G>
-__device__ __forceinline__ void block_eval(int32_t *tk, int64_t *tv, int tsize, int32_t D, int64_t vu, int64_t base,
+__device__ __forceinline__ void block_eval(int32_t *tk, int64_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
                                            int64_t S, const int64_t *volC, int32_t *out, int64_t &ncand) {
     __shared__ int64_t red_w[kBlockThreads / kWave];
     __shared__ G red_s[kBlockThreads / kWave];
     __shared__ int32_t red_x[kBlockThreads / kWave];
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    int64_t wD = 0;
     for (int s = threadIdx.x; s < tsize; s += kBlockThreads) {
         int32_t X = tk[s];
         if (X >= 0) {
             int64_t a = tv[s];
             tk[s] = kEmpty;
             tv[s] = 0;
-            if (X == D) {
-                wD = a;
-            } else {
-                ++ncand;
-                G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-                if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-            }
+            ++ncand;
+            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
         }
     }
-    wD = wave_sum(wD);
+    wD = wave_sum(wD);  // wD enters as this thread's share
     wave_argmax<G>(bs, bx);
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) { red_w[w] = wD; red_s[w] = bs; red_x[w] = bx; }
@@ -271,31 +279,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
-        int tsize = 1 << bits;
-        uint32_t mask = (uint32_t)tsize - 1;
         int32_t D = ms.zeta[u];
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlockThreads) {
-            int32_t v = g.col[e];
-            if (v == u) continue;
-            int32_t X = ms.zeta[v];
-            int64_t wt = wload<WK>(g.w, e);
-            uint32_t h = slot_hash(X, bits);
-            for (;;) {
-                int32_t k = atomicCAS(&tk[h], kEmpty, X);
-                if (k == kEmpty || k == X) {
-                    atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt);
-                    break;
-                }
-                h = (h + 1) & mask;
-            }
-        }
+        int64_t myD = fold_row<WK>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
         if (force_wide || vu > ms.wide_lim)
-            block_eval<i128>(tk, tv, tsize, D, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<i128>(tk, tv, 1 << bits, myD, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
         else
-            block_eval<int64_t>(tk, tv, tsize, D, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<int64_t>(tk, tv, 1 << bits, myD, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
         __syncthreads();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
@@ -377,21 +369,10 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveSta
     int64_t c0 = e0 + chunk * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
     __syncthreads();
     constexpr int kLdsBits = 12;
-    for (int64_t e = c0 + threadIdx.x; e < c1; e += kHubThreads) {
-        int32_t v = g.col[e];
-        if (v == u) continue;
-        int32_t X = ms.zeta[v];
-        int64_t wt = wload<WK>(g.w, e);
-        uint32_t s = slot_hash(X, kLdsBits);
-        for (;;) {
-            int32_t k = atomicCAS(&lk[s], kEmpty, X);
-            if (k == kEmpty || k == X) {
-                atomicAdd((unsigned long long *)&lv[s], (unsigned long long)wt);
-                break;
-            }
-            s = (s + 1) & (kHubLdsSlots - 1);
-        }
-    }
+    const int32_t D = ms.zeta[u];
+    int64_t myD = fold_row<WK>(g, ms.zeta, u, D, c0, c1, threadIdx.x, kHubThreads, lk, lv, kLdsBits);
+    myD = wave_sum(myD);
+    if (lane_id() == 0 && myD) atomicAdd((unsigned long long *)&ha.hub_wD[hg], (unsigned long long)myD);
     __syncthreads();
     const int bits = ha.tab_bits[hg];
     const uint32_t mask = (1u << bits) - 1;
@@ -451,13 +432,9 @@ __device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, 
             tk[s] = kEmpty;
             tv[s] = 0;
         }
-        if (X == D) {
-            *wD_slot = a;  // exactly one slot holds D
-        } else {
-            ++ncand;
-            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-        }
+        ++ncand;  // the tables never hold D (summed into hub_wD by the insert launch)
+        G sc = (G)S * (G)a - (G)vu * (G)volC[X];
+        if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
     }
 }
 
