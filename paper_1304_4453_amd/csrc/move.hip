@@ -165,30 +165,43 @@ __device__ __forceinline__ void wave_eval(int32_t *tk, int64_t *tv, int tsize, i
 }
 
 // folds the (X, w) entries of u into a hash table (LDS) except X == D; returns
-// this thread's share of w(u, D \ u)
-template <int WK>
+// this thread's share of w(u, D \ u).  Entries are taken B at a time: B column
+// loads, then B community gathers, then B inserts, so that the memory
+// latencies of a batch overlap.
+template <int WK, int B>
 __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *zeta, int32_t u, int32_t D, int64_t e0,
                                             int64_t e1, int64_t first, int64_t step, int32_t *tk, int64_t *tv,
                                             int bits) {
     const uint32_t mask = (1u << bits) - 1;
     int64_t myD = 0;
-    for (int64_t e = e0 + first; e < e1; e += step) {
-        int32_t v = g.col[e];
-        if (v == u) continue;
-        int32_t X = zeta[v];
-        int64_t wt = wload<WK>(g.w, e);
-        if (X == D) {
-            myD += wt;
-            continue;
+    for (int64_t base = e0 + first; base < e1; base += step * B) {
+        int32_t v[B], X[B];
+        int64_t wt[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            int64_t e = base + b * step;
+            bool ok = e < e1;
+            v[b] = ok ? g.col[e] : u;
+            wt[b] = ok ? wload<WK>(g.w, e) : 0;
         }
-        uint32_t h = slot_hash(X, bits);
-        for (;;) {
-            int32_t k = atomicCAS(&tk[h], kEmpty, X);
-            if (k == kEmpty || k == X) {
-                atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt);
-                break;
+#pragma unroll
+        for (int b = 0; b < B; ++b) X[b] = v[b] != u ? zeta[v[b]] : -1;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (X[b] < 0) continue;
+            if (X[b] == D) {
+                myD += wt[b];
+                continue;
             }
-            h = (h + 1) & mask;
+            uint32_t h = slot_hash(X[b], bits);
+            for (;;) {
+                int32_t k = atomicCAS(&tk[h], kEmpty, X[b]);
+                if (k == kEmpty || k == X[b]) {
+                    atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt[b]);
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
         }
     }
     return myD;
@@ -210,7 +223,7 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
-        int64_t wD = fold_row<WK>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
+        int64_t wD = fold_row<WK, 4>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
         wD = wave_sum(wD);
         wave_sync();
         int64_t vu = ms.vol[u];
@@ -280,7 +293,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
-        int64_t myD = fold_row<WK>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
+        int64_t myD = fold_row<WK, 4>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
@@ -317,40 +330,32 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
     return lo;
 }
 
-// adds (X, a) to a node's global table; true if this call created the key;
-// *slot_out = the key's slot
+// continues the linear probe for key X from slot s + 1 (slot s held another
+// key); true if this call created the key; *slot_out = the key's slot
 template <bool PACKED>
-__device__ __forceinline__ bool global_insert(const HubArrays &ha, int64_t hg, int32_t X, int64_t a, uint32_t mask,
-                                              int bits, uint32_t *slot_out) {
-    uint32_t s = slot_hash(X, bits);
-    if constexpr (PACKED) {
-        unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
-        const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)a;
-        for (;;) {
-            unsigned long long cur = tw[s];  // a stale "empty" is caught by the CAS
-            if (cur == kEmptyWord) {
-                unsigned long long old = atomicCAS(&tw[s], kEmptyWord, want);
-                if (old == kEmptyWord) { *slot_out = s; return true; }
-                cur = old;
-            }
-            if ((uint32_t)(cur >> 32) == (uint32_t)X) {
+__device__ __noinline__ bool global_probe(const HubArrays &ha, int64_t hg, int32_t X, int64_t a, uint32_t mask,
+                                          uint32_t s, uint32_t *slot_out) {
+    for (;;) {
+        s = (s + 1) & mask;
+        if constexpr (PACKED) {
+            unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
+            const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)a;
+            unsigned long long old = atomicCAS(&tw[s], kEmptyWord, want);
+            if (old == kEmptyWord) { *slot_out = s; return true; }
+            if ((uint32_t)(old >> 32) == (uint32_t)X) {
                 atomicAdd(&tw[s], (unsigned long long)a);
                 *slot_out = s;
                 return false;
             }
-            s = (s + 1) & mask;
-        }
-    } else {
-        int32_t *tk = ha.tab_key + ha.tab_off[hg];
-        int64_t *tv = ha.tab_val + ha.tab_off[hg];
-        for (;;) {
+        } else {
+            int32_t *tk = ha.tab_key + ha.tab_off[hg];
+            int64_t *tv = ha.tab_val + ha.tab_off[hg];
             int32_t k = atomicCAS(&tk[s], kEmpty, X);
             if (k == kEmpty || k == X) {
                 atomicAdd((unsigned long long *)&tv[s], (unsigned long long)a);
                 *slot_out = s;
                 return k == kEmpty;
             }
-            s = (s + 1) & mask;
         }
     }
 }
@@ -370,27 +375,71 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveSta
     __syncthreads();
     constexpr int kLdsBits = 12;
     const int32_t D = ms.zeta[u];
-    int64_t myD = fold_row<WK>(g, ms.zeta, u, D, c0, c1, threadIdx.x, kHubThreads, lk, lv, kLdsBits);
+    int64_t myD = fold_row<WK, 8>(g, ms.zeta, u, D, c0, c1, threadIdx.x, kHubThreads, lk, lv, kLdsBits);
     myD = wave_sum(myD);
     if (lane_id() == 0 && myD) atomicAdd((unsigned long long *)&ha.hub_wD[hg], (unsigned long long)myD);
     __syncthreads();
+    // flush: every thread takes kFlush LDS slots, issues the CAS of each non-empty
+    // one on its home slot at once, then resolves the (rare) collisions
     const int bits = ha.tab_bits[hg];
     const uint32_t mask = (1u << bits) - 1;
     int32_t *occ = ha.occ + (ha.tab_off[hg] >> 1);
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    for (int s0 = 0; s0 < kHubLdsSlots; s0 += kHubThreads) {
-        int32_t X = lk[s0 + threadIdx.x];
-        bool created = false;
-        uint32_t slot = 0;
-        if (X >= 0) created = global_insert<PACKED>(ha, hg, X, lv[s0 + threadIdx.x], mask, bits, &slot);
-        uint64_t m = __ballot(created);
+    constexpr int kFlush = kHubLdsSlots / kHubThreads;
+    int32_t X[kFlush];
+    int64_t a[kFlush];
+    uint32_t slot[kFlush];
+    bool created[kFlush];
+#pragma unroll
+    for (int j = 0; j < kFlush; ++j) {
+        X[j] = lk[j * kHubThreads + threadIdx.x];
+        a[j] = lv[j * kHubThreads + threadIdx.x];
+        slot[j] = X[j] >= 0 ? slot_hash(X[j], bits) : 0;
+        created[j] = false;
+    }
+    if constexpr (PACKED) {
+        unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
+        unsigned long long old[kFlush];
+#pragma unroll
+        for (int j = 0; j < kFlush; ++j)
+            if (X[j] >= 0)
+                old[j] = atomicCAS(&tw[slot[j]], kEmptyWord,
+                                   ((unsigned long long)(uint32_t)X[j] << 32) | (unsigned long long)a[j]);
+#pragma unroll
+        for (int j = 0; j < kFlush; ++j) {
+            if (X[j] < 0) continue;
+            if (old[j] == kEmptyWord) created[j] = true;
+            else if ((uint32_t)(old[j] >> 32) == (uint32_t)X[j]) atomicAdd(&tw[slot[j]], (unsigned long long)a[j]);
+            else created[j] = global_probe<true>(ha, hg, X[j], a[j], mask, slot[j], &slot[j]);
+        }
+    } else {
+        int32_t *tk = ha.tab_key + ha.tab_off[hg];
+        int64_t *tv = ha.tab_val + ha.tab_off[hg];
+        int32_t old[kFlush];
+#pragma unroll
+        for (int j = 0; j < kFlush; ++j)
+            if (X[j] >= 0) old[j] = atomicCAS(&tk[slot[j]], kEmpty, X[j]);
+#pragma unroll
+        for (int j = 0; j < kFlush; ++j) {
+            if (X[j] < 0) continue;
+            if (old[j] == kEmpty || old[j] == X[j]) {
+                atomicAdd((unsigned long long *)&tv[slot[j]], (unsigned long long)a[j]);
+                created[j] = old[j] == kEmpty;
+            } else {
+                created[j] = global_probe<false>(ha, hg, X[j], a[j], mask, slot[j], &slot[j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kFlush; ++j) {
+        uint64_t m = __ballot(created[j]);
         if (m) {
             int leader = __ffsll((unsigned long long)m) - 1;
             int32_t base = 0;
             if (lane == leader) base = atomicAdd(&ha.occ_cnt[hg], (int32_t)__popcll(m));
             base = __shfl(base, leader);
-            if (created) occ[base + (int32_t)__popcll(m & lt)] = (int32_t)slot;
+            if (created[j]) occ[base + (int32_t)__popcll(m & lt)] = (int32_t)slot[j];
         }
     }
 }
