@@ -164,70 +164,22 @@ __device__ __forceinline__ void wave_eval(int32_t *tk, int64_t *tv, int tsize, i
     move = bx != kNone && bs > K;
 }
 
-// LDS hash insert of (X, w): linear probing, key by CAS, weight by atomic add
-__device__ __forceinline__ void lds_insert(int32_t *tk, int64_t *tv, int32_t X, int64_t w, int bits) {
-    const uint32_t mask = (1u << bits) - 1;
-    uint32_t h = slot_hash(X, bits);
-    for (;;) {
-        int32_t k = atomicCAS(&tk[h], kEmpty, X);
-        if (k == kEmpty || k == X) {
-            atomicAdd((unsigned long long *)&tv[h], (unsigned long long)w);
-            return;
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-// Inserts the wavefront's 64 (X, w) pairs (X < 0: none) with one table update
-// per distinct X: the pairs are sorted by X with a bitonic network over the
-// lanes, equal keys are summed by a segmented scan, and the last lane of each
-// run inserts the sum.  Must be called by all lanes of the wavefront.
-__device__ __forceinline__ void wave_sorted_insert(int32_t X, int64_t w, int32_t *tk, int64_t *tv, int bits) {
-    const int lane = lane_id();
-    uint32_t key = X < 0 ? 0xffffffffu : (uint32_t)X;
-    int64_t val = X < 0 ? 0 : w;
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            uint32_t pk = __shfl_xor(key, j);
-            int64_t pv = __shfl_xor(val, j);
-            bool asc = (lane & k) == 0, lower = (lane & j) == 0;
-            bool take = (lower == asc) ? pk < key : pk > key;
-            if (take) { key = pk; val = pv; }
-        }
-    }
-    uint32_t prev = __shfl_up(key, 1);
-    uint64_t heads = __ballot(lane == 0 || prev != key);
-    uint64_t le = lane == kWave - 1 ? ~0ULL : ((2ULL << lane) - 1);
-    int start = 63 - __clzll((unsigned long long)(heads & le));
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int64_t y = __shfl_up(val, d);
-        if (lane - d >= start) val += y;
-    }
-    bool tail = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
-    if (tail && key != 0xffffffffu) lds_insert(tk, tv, (int32_t)key, val, bits);
-}
-
-// Folds the (X, w) entries of row u into an LDS hash table, except X == D;
-// returns this thread's share of w(u, D \ u).  Lane `first - lane_id() + l` of
-// a wavefront starts at entry e0 + first, threads step by `step`; entries are
-// taken B per thread at a time (B column loads, then B community gathers, then
-// B wavefront-sorted inserts) so that memory latencies overlap.  The loop trip
-// count is uniform over the wavefront (the sorted insert needs every lane).
+// folds the (X, w) entries of u into a hash table (LDS) except X == D; returns
+// this thread's share of w(u, D \ u).  Entries are taken B at a time: B column
+// loads, then B community gathers, then B inserts, so that the memory
+// latencies of a batch overlap.
 template <int WK, int B>
 __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *zeta, int32_t u, int32_t D, int64_t e0,
                                             int64_t e1, int64_t first, int64_t step, int32_t *tk, int64_t *tv,
                                             int bits) {
-    const int64_t lane = lane_id();
+    const uint32_t mask = (1u << bits) - 1;
     int64_t myD = 0;
-    for (int64_t wb = e0 + first - lane; wb < e1; wb += step * B) {
+    for (int64_t base = e0 + first; base < e1; base += step * B) {
         int32_t v[B], X[B];
         int64_t wt[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            int64_t e = wb + lane + b * step;
+            int64_t e = base + b * step;
             bool ok = e < e1;
             v[b] = ok ? g.col[e] : u;
             wt[b] = ok ? wload<WK>(g.w, e) : 0;
@@ -236,11 +188,20 @@ __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *z
         for (int b = 0; b < B; ++b) X[b] = v[b] != u ? zeta[v[b]] : -1;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
+            if (X[b] < 0) continue;
             if (X[b] == D) {
                 myD += wt[b];
-                X[b] = -1;
+                continue;
             }
-            wave_sorted_insert(X[b], wt[b], tk, tv, bits);
+            uint32_t h = slot_hash(X[b], bits);
+            for (;;) {
+                int32_t k = atomicCAS(&tk[h], kEmpty, X[b]);
+                if (k == kEmpty || k == X[b]) {
+                    atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt[b]);
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
         }
     }
     return myD;
