@@ -72,11 +72,6 @@ __global__ void k_export_w(GraphView g, int64_t *out) {
     }
 }
 
-__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // rows holding a self-loop entry (rows are strictly ascending: binary search)
 __global__ void k_count_loops(GraphView g, unsigned long long *cnt) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -125,15 +120,13 @@ struct plm_ctx {
     std::vector<int64_t> bstart;
     std::vector<ClassRange> classes;
     int64_t active_nodes = 0, active_entries = 0;
-    // hub arrays of the current level
-    int32_t *hub_pos = nullptr, *tab_bits = nullptr, *tab_key = nullptr, *done = nullptr;
-    int64_t *tab_off = nullptr, *ins_first = nullptr, *eval_first = nullptr, *eval_cnt = nullptr, *tab_val = nullptr,
-            *hub_wD = nullptr;
+    // hub arrays of the current level (see the hub kernels in move.hip)
+    int32_t *hub_pos = nullptr, *nchunk = nullptr, *pbits = nullptr, *stg_x = nullptr;
+    int64_t *ins_first = nullptr, *agg_first = nullptr, *stg_off = nullptr, *bkt_off = nullptr, *stg_w = nullptr,
+            *wd_part = nullptr;
+    uint32_t *bkt = nullptr;
     unsigned long long *part = nullptr;
-    int32_t *occ = nullptr, *occ_cnt = nullptr;
-    int64_t hub_cap_slots = 0, hub_cap_part = 0, hub_cap_hubs = 0;
-    int hub_tab_mode = -1;  // table contents: -1 unset, 0 key/value arrays, 1 packed words
-    bool hub_packed = false;
+    int64_t cap_hubs = 0, cap_stg = 0, cap_bkt = 0, cap_ins = 0, cap_agg = 0;
     int32_t sweeps = 0;
     // device counters: [0] moves, [1..4] candidates per bin, [5] S, [6] max vol,
     // [7] loop-only rows, [8..11] entries per bin
@@ -154,10 +147,10 @@ struct plm_ctx {
         for (auto e : events) (void)hipEventDestroy(e);
     }
     void free_hubs() {
-        dev_free(hub_pos); dev_free(tab_bits); dev_free(tab_key); dev_free(done); dev_free(tab_off);
-        dev_free(ins_first); dev_free(eval_first); dev_free(eval_cnt); dev_free(tab_val); dev_free(hub_wD);
-        dev_free(part); dev_free(occ); dev_free(occ_cnt);
-        hub_cap_slots = hub_cap_part = hub_cap_hubs = 0;
+        dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(stg_x); dev_free(ins_first);
+        dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part);
+        dev_free(bkt); dev_free(part);
+        cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = 0;
     }
 
     LevelData &L() { return levels[cur]; }
@@ -196,41 +189,24 @@ struct plm_ctx {
         sweeps = 0;
     }
 
-    void ensure_hub_capacity(int64_t hubs, int64_t slots, int64_t parts) {
-        if (hubs > hub_cap_hubs) {
-            dev_free(hub_pos); dev_free(tab_bits); dev_free(done); dev_free(tab_off); dev_free(ins_first);
-            dev_free(occ_cnt);
-            occ_cnt = dev_alloc<int32_t>(hubs);
-            dev_free(eval_first); dev_free(eval_cnt); dev_free(hub_wD);
-            hub_pos = dev_alloc<int32_t>(hubs); tab_bits = dev_alloc<int32_t>(hubs); done = dev_alloc<int32_t>(hubs);
-            tab_off = dev_alloc<int64_t>(hubs); ins_first = dev_alloc<int64_t>(hubs);
-            eval_first = dev_alloc<int64_t>(hubs); eval_cnt = dev_alloc<int64_t>(hubs); hub_wD = dev_alloc<int64_t>(hubs);
-            hub_cap_hubs = hubs;
+    // grow-only device arrays of the hub plan
+    void ensure_hub_capacity(int64_t hubs, int64_t stg, int64_t bk, int64_t ins, int64_t agg) {
+        if (hubs > cap_hubs) {
+            dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
+            dev_free(stg_off); dev_free(bkt_off);
+            hub_pos = dev_alloc<int32_t>(hubs); nchunk = dev_alloc<int32_t>(hubs); pbits = dev_alloc<int32_t>(hubs);
+            ins_first = dev_alloc<int64_t>(hubs); agg_first = dev_alloc<int64_t>(hubs);
+            stg_off = dev_alloc<int64_t>(hubs); bkt_off = dev_alloc<int64_t>(hubs);
+            cap_hubs = hubs;
         }
-        if (slots > hub_cap_slots) {
-            dev_free(tab_key); dev_free(tab_val); dev_free(occ);
-            tab_key = dev_alloc<int32_t>(slots); tab_val = dev_alloc<int64_t>(slots);
-            occ = dev_alloc<int32_t>(slots / 2 + 1);
-            hub_cap_slots = slots;
-            hub_tab_mode = -1;
+        if (stg > cap_stg) {
+            dev_free(stg_x); dev_free(stg_w);
+            stg_x = dev_alloc<int32_t>(stg); stg_w = dev_alloc<int64_t>(stg);
+            cap_stg = stg;
         }
-        int mode = hub_packed ? 1 : 0;
-        if (mode != hub_tab_mode) {  // empty tables in the layout this level uses
-            if (mode == 1) {
-                hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)cdiv(hub_cap_slots, 256)), dim3(256), 0, st,
-                                   (unsigned long long *)tab_val, hub_cap_slots, 0xFFFFFFFF00000000ULL);
-            } else {
-                HIPCHK(hipMemsetAsync(tab_key, 0xff, hub_cap_slots * 4, st));
-                HIPCHK(hipMemsetAsync(tab_val, 0, hub_cap_slots * 8, st));
-            }
-            HIPCHK(hipGetLastError());
-            hub_tab_mode = mode;
-        }
-        if (parts > hub_cap_part) {
-            dev_free(part);
-            part = dev_alloc<unsigned long long>(4 * parts);
-            hub_cap_part = parts;
-        }
+        if (bk > cap_bkt) { dev_free(bkt); bkt = dev_alloc<uint32_t>(bk); cap_bkt = bk; }
+        if (ins > cap_ins) { dev_free(wd_part); wd_part = dev_alloc<int64_t>(ins); cap_ins = ins; }
+        if (agg > cap_agg) { dev_free(part); part = dev_alloc<unsigned long long>(4 * agg); cap_agg = agg; }
     }
 
     void build_schedule() {
@@ -281,9 +257,11 @@ struct plm_ctx {
             HIPCHK(hipMemcpyAsync(deg.data(), ddeg, H * 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        std::vector<int32_t> hpos(H > 0 ? H : 1), hbits(H > 0 ? H : 1);
-        std::vector<int64_t> toff(H > 0 ? H : 1), ifirst(H > 0 ? H : 1), efirst(H > 0 ? H : 1), ecnt(H > 0 ? H : 1);
-        int64_t max_slots = 0, max_parts = 0, hg = 0;
+        // per hub: chunks of kHubInsChunk entries, 2^pbits buckets of ~kHubBucketTarget
+        // entries, staging and (bucket, chunk) table offsets within its class
+        std::vector<int32_t> hpos(H > 0 ? H : 1), hch(H > 0 ? H : 1), hpb(H > 0 ? H : 1);
+        std::vector<int64_t> hins(H > 0 ? H : 1), hagg(H > 0 ? H : 1), hstg(H > 0 ? H : 1), hbk(H > 0 ? H : 1);
+        int64_t max_stg = 0, max_bk = 0, max_ins = 0, max_agg = 0, hg = 0;
         for (int32_t c = 0; c < ncol; ++c) {
             ClassRange &cr = classes[c];
             for (int b = 0; b < 4; ++b) {
@@ -292,38 +270,39 @@ struct plm_ctx {
             }
             cr.hub_first = hg;
             cr.hub_count = cr.count[3];
-            int64_t slots = 0, ib = 0, eb = 0;
+            int64_t stg = 0, bk = 0, ins = 0, agg = 0;
             for (int64_t i = 0; i < cr.hub_count; ++i, ++hg) {
-                int bits = ceil_log2((uint64_t)(2 * deg[hg]));
-                if (bits < kHubMinBits) bits = kHubMinBits;
-                int64_t ts = 1LL << bits;
+                int64_t ch = cdiv(deg[hg], kHubInsChunk);
+                int pb = ceil_log2((uint64_t)cdiv(deg[hg], kHubBucketTarget));
+                if (pb > kHubMaxPBits) pb = kHubMaxPBits;
                 hpos[hg] = (int32_t)pos[hg];
-                hbits[hg] = bits;
-                toff[hg] = slots;
-                ifirst[hg] = ib;
-                efirst[hg] = eb;
-                ecnt[hg] = cdiv(deg[hg], kHubEvalChunk);  // distinct communities <= row length
-                slots += ts;
-                ib += cdiv(deg[hg], kHubInsChunk);
-                eb += ecnt[hg];
+                hch[hg] = (int32_t)ch;
+                hpb[hg] = pb;
+                hins[hg] = ins;
+                hagg[hg] = agg;
+                hstg[hg] = stg;
+                hbk[hg] = bk;
+                ins += ch;
+                agg += 1LL << pb;
+                stg += ch * kHubInsChunk;
+                bk += ch << pb;
             }
-            cr.ins_blocks = ib;
-            cr.eval_blocks = eb;
-            max_slots = slots > max_slots ? slots : max_slots;
-            max_parts = eb > max_parts ? eb : max_parts;
+            cr.ins_blocks = ins;
+            cr.agg_blocks = agg;
+            max_stg = stg > max_stg ? stg : max_stg;
+            max_bk = bk > max_bk ? bk : max_bk;
+            max_ins = ins > max_ins ? ins : max_ins;
+            max_agg = agg > max_agg ? agg : max_agg;
         }
-        hub_packed = max_vol < (1LL << 32);  // every partial w(u, X) fits 32 bits
         if (H > 0) {
-            ensure_hub_capacity(H, max_slots, max_parts);
+            ensure_hub_capacity(H, max_stg, max_bk, max_ins, max_agg);
             HIPCHK(hipMemcpyAsync(hub_pos, hpos.data(), H * 4, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(tab_bits, hbits.data(), H * 4, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(tab_off, toff.data(), H * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(ins_first, ifirst.data(), H * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(eval_first, efirst.data(), H * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(eval_cnt, ecnt.data(), H * 8, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemsetAsync(done, 0, H * 4, st));
-            HIPCHK(hipMemsetAsync(occ_cnt, 0, H * 4, st));
-            HIPCHK(hipMemsetAsync(hub_wD, 0, H * 8, st));
+            HIPCHK(hipMemcpyAsync(nchunk, hch.data(), H * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(pbits, hpb.data(), H * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(ins_first, hins.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(agg_first, hagg.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(stg_off, hstg.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(bkt_off, hbk.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
@@ -342,10 +321,9 @@ struct plm_ctx {
     }
     HubArrays hub_arrays() {
         HubArrays ha;
-        ha.hub_pos = hub_pos; ha.tab_off = tab_off; ha.tab_bits = tab_bits; ha.ins_first = ins_first;
-        ha.eval_first = eval_first; ha.eval_cnt = eval_cnt; ha.tab_key = tab_key; ha.tab_val = tab_val;
-        ha.part = part; ha.done = done; ha.hub_wD = hub_wD; ha.packed = hub_packed ? 1 : 0;
-        ha.occ = occ; ha.occ_cnt = occ_cnt;
+        ha.hub_pos = hub_pos; ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
+        ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
+        ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part;
         return ha;
     }
 

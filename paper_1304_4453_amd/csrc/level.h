@@ -39,31 +39,28 @@ struct ClassRange {
     int64_t begin[4], count[4];  // per bin
     // hubs of this class in the level's hub arrays
     int64_t hub_first = 0, hub_count = 0;
-    int64_t ins_blocks = 0, eval_blocks = 0;
+    int64_t ins_blocks = 0, agg_blocks = 0;
 };
 
 struct HubArrays {
-    const int32_t *hub_pos;    // class position
-    const int64_t *tab_off;    // slot offset within the class area
-    const int32_t *tab_bits;
-    const int64_t *ins_first;  // first insert block (class-relative), per hub, +1 sentinel per class
-    const int64_t *eval_first;
-    const int64_t *eval_cnt;   // eval blocks of each hub
-    int32_t *tab_key;          // class area (keys, -1 = empty)
-    int64_t *tab_val;
-    unsigned long long *part;  // per eval block: 4 words (score hi, score lo, X, pad)
-    int32_t *done;             // per hub completion counter (zero between uses)
-    int64_t *hub_wD;           // per hub w(u, D \ u) found by the eval blocks (zero between uses)
-    int packed;                // slots are single 64-bit words (community << 32 | weight)
-    int32_t *occ;              // occupied-slot list of each hub at tab_off / 2 (capacity tsize / 2)
-    int32_t *occ_cnt;          // per hub length of that list (zero between uses)
+    const int32_t *hub_pos;    // class position of each hub
+    const int64_t *ins_first;  // first chunk workgroup of each hub (class-relative prefix)
+    const int64_t *agg_first;  // first bucket workgroup of each hub (class-relative prefix)
+    const int32_t *nchunk;     // chunks of each hub
+    const int32_t *pbits;      // log2 of the bucket count of each hub
+    const int64_t *stg_off;    // staging offset (entries) of each hub within the class area
+    const int64_t *bkt_off;    // offset of each hub's (bucket, chunk) words within the class area
+    int32_t *stg_x;            // staging: community of each entry
+    int64_t *stg_w;            // staging: weight of each entry
+    uint32_t *bkt;             // (start << 16 | count) per (bucket, chunk), bucket-major
+    int64_t *wd_part;          // per chunk workgroup: its share of w(u, D \ u)
+    unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, pad
 };
 
-constexpr int64_t kHubInsChunk = 2048;   // entries per hub insert workgroup
-constexpr int64_t kHubEvalChunk = 1024;  // occupied slots per hub eval workgroup
-constexpr int kHubMinBits = 12;
+constexpr int64_t kHubInsChunk = 2048;  // entries per hub chunk workgroup
+constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
+constexpr int64_t kHubBucketTarget = 1024;
 
-// ev: null, or 5 events recorded before bin 0 and after bins 0..3
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                        bool force_wide, const hipEvent_t *ev, hipStream_t st);
 void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);

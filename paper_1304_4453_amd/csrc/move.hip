@@ -307,22 +307,26 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 }
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
-// Rows longer than the workgroup limit accumulate w(u, X) in a per-node hash
-// table in global memory.  Insert: each workgroup first folds a chunk of
-// kHubInsChunk entries into an LDS table, then adds its distinct communities
-// to the node's global table; a key that a workgroup creates is appended to the
-// node's list of occupied slots.  Eval: workgroups walk the occupied list
-// (clearing the slots), each leaves a partial best, and a third launch (one
-// workgroup per node) combines them.  When every partial sum of the level fits 32 bits (max
-// vol(u) < 2^32) a global slot is one 64-bit word (community << 32 | weight);
-// otherwise keys and 64-bit values sit in two arrays.
+// Rows longer than the workgroup limit are aggregated without global atomics.
+//  1. part: a workgroup per chunk of kHubInsChunk entries counting-sorts its
+//     (X, w) pairs into P = 2^pbits hash buckets of X (P ~ row length / 1024)
+//     and writes them to a staging area, with a (start, count) word per
+//     (bucket, chunk); entries of u's own community D only add to a per-chunk
+//     share of w(u, D \ u).
+//  2. agg: a workgroup per (node, bucket) gathers that bucket from all chunks
+//     into an LDS hash table, scores its communities and leaves a partial best.
+//     A bucket with more than kAggMaxKeys distinct communities (not expected
+//     for hashed ids, but possible) is redone in 2, 4, ... passes, each over a
+//     sub-partition of its keys, so any input stays exact.
+//  3. reduce: a workgroup per node combines the partial bests and the w(u, D)
+//     shares and decides the move.
 constexpr int kHubThreads = 256;
-constexpr int kHubLdsSlots = 4096;  // LDS table of an insert workgroup (2 x kHubInsChunk)
-constexpr uint64_t kEmptyWord = 0xFFFFFFFF00000000ULL;
+constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
+constexpr int kAggSlots = 4096;
+constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
 
-// hub h of a class owning class-relative block b: last h with first[h] <= b
 __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
-    int64_t lo = 0, hi = nh;
+    int64_t lo = 0, hi = nh;  // last h with first[h] <= b
     while (hi - lo > 1) {
         int64_t mid = (lo + hi) >> 1;
         if (first[mid] <= b) lo = mid; else hi = mid;
@@ -330,117 +334,101 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
     return lo;
 }
 
-// continues the linear probe for key X from slot s + 1 (slot s held another
-// key); true if this call created the key; *slot_out = the key's slot
-template <bool PACKED>
-__device__ __noinline__ bool global_probe(const HubArrays &ha, int64_t hg, int32_t X, int64_t a, uint32_t mask,
-                                          uint32_t s, uint32_t *slot_out) {
-    for (;;) {
-        s = (s + 1) & mask;
-        if constexpr (PACKED) {
-            unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
-            const unsigned long long want = ((unsigned long long)(uint32_t)X << 32) | (unsigned long long)a;
-            unsigned long long old = atomicCAS(&tw[s], kEmptyWord, want);
-            if (old == kEmptyWord) { *slot_out = s; return true; }
-            if ((uint32_t)(old >> 32) == (uint32_t)X) {
-                atomicAdd(&tw[s], (unsigned long long)a);
-                *slot_out = s;
-                return false;
-            }
-        } else {
-            int32_t *tk = ha.tab_key + ha.tab_off[hg];
-            int64_t *tv = ha.tab_val + ha.tab_off[hg];
-            int32_t k = atomicCAS(&tk[s], kEmpty, X);
-            if (k == kEmpty || k == X) {
-                atomicAdd((unsigned long long *)&tv[s], (unsigned long long)a);
-                *slot_out = s;
-                return k == kEmpty;
-            }
-        }
-    }
+__device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
+    return pbits == 0 ? 0u : ((uint32_t)x * 2654435769u) >> (32 - pbits);
+}
+__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 12); }
+__device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
+    return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
 
-template <int WK, bool PACKED>
-__global__ __launch_bounds__(kHubThreads) void k_hub_insert(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
-                                                            int64_t nh) {
-    __shared__ int32_t lk[kHubLdsSlots];
-    __shared__ int64_t lv[kHubLdsSlots];
-    for (int s = threadIdx.x; s < kHubLdsSlots; s += kHubThreads) { lk[s] = kEmpty; lv[s] = 0; }
-    int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
-    int64_t hg = hub0 + h;
-    int64_t chunk = blockIdx.x - ha.ins_first[hg];
-    int32_t u = ms.class_nodes[ha.hub_pos[hg]];
-    int64_t e0 = g.off[u], e1 = g.off[u + 1];
-    int64_t c0 = e0 + chunk * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
-    __syncthreads();
-    constexpr int kLdsBits = 12;
+template <int WK>
+__global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
+                                                          int64_t nh) {
+    __shared__ int32_t start[kAggSlots];
+    __shared__ int32_t fill[kAggSlots];
+    __shared__ int64_t wsum[kHubThreads / kWave];
+    const int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
+    const int64_t hg = hub0 + h;
+    const int64_t k = blockIdx.x - ha.ins_first[hg];
+    const int32_t u = ms.class_nodes[ha.hub_pos[hg]];
     const int32_t D = ms.zeta[u];
-    int64_t myD = fold_row<WK, 8>(g, ms.zeta, u, D, c0, c1, threadIdx.x, kHubThreads, lk, lv, kLdsBits);
-    myD = wave_sum(myD);
-    if (lane_id() == 0 && myD) atomicAdd((unsigned long long *)&ha.hub_wD[hg], (unsigned long long)myD);
+    const int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
+    const int pb = ha.pbits[hg];
+    const int P = 1 << pb;
+    for (int i = threadIdx.x; i < P; i += kHubThreads) { start[i] = 0; fill[i] = 0; }
     __syncthreads();
-    // flush: every thread takes kFlush LDS slots, issues the CAS of each non-empty
-    // one on its home slot at once, then resolves the (rare) collisions
-    const int bits = ha.tab_bits[hg];
-    const uint32_t mask = (1u << bits) - 1;
-    int32_t *occ = ha.occ + (ha.tab_off[hg] >> 1);
-    const int lane = lane_id();
-    const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    constexpr int kFlush = kHubLdsSlots / kHubThreads;
-    int32_t X[kFlush];
-    int64_t a[kFlush];
-    uint32_t slot[kFlush];
-    bool created[kFlush];
+    int32_t v[kHubPerThread], X[kHubPerThread], bk[kHubPerThread];
+    int64_t W[kHubPerThread];
 #pragma unroll
-    for (int j = 0; j < kFlush; ++j) {
-        X[j] = lk[j * kHubThreads + threadIdx.x];
-        a[j] = lv[j * kHubThreads + threadIdx.x];
-        slot[j] = X[j] >= 0 ? slot_hash(X[j], bits) : 0;
-        created[j] = false;
-    }
-    if constexpr (PACKED) {
-        unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
-        unsigned long long old[kFlush];
-#pragma unroll
-        for (int j = 0; j < kFlush; ++j)
-            if (X[j] >= 0)
-                old[j] = atomicCAS(&tw[slot[j]], kEmptyWord,
-                                   ((unsigned long long)(uint32_t)X[j] << 32) | (unsigned long long)a[j]);
-#pragma unroll
-        for (int j = 0; j < kFlush; ++j) {
-            if (X[j] < 0) continue;
-            if (old[j] == kEmptyWord) created[j] = true;
-            else if ((uint32_t)(old[j] >> 32) == (uint32_t)X[j]) atomicAdd(&tw[slot[j]], (unsigned long long)a[j]);
-            else created[j] = global_probe<true>(ha, hg, X[j], a[j], mask, slot[j], &slot[j]);
-        }
-    } else {
-        int32_t *tk = ha.tab_key + ha.tab_off[hg];
-        int64_t *tv = ha.tab_val + ha.tab_off[hg];
-        int32_t old[kFlush];
-#pragma unroll
-        for (int j = 0; j < kFlush; ++j)
-            if (X[j] >= 0) old[j] = atomicCAS(&tk[slot[j]], kEmpty, X[j]);
-#pragma unroll
-        for (int j = 0; j < kFlush; ++j) {
-            if (X[j] < 0) continue;
-            if (old[j] == kEmpty || old[j] == X[j]) {
-                atomicAdd((unsigned long long *)&tv[slot[j]], (unsigned long long)a[j]);
-                created[j] = old[j] == kEmpty;
-            } else {
-                created[j] = global_probe<false>(ha, hg, X[j], a[j], mask, slot[j], &slot[j]);
-            }
-        }
+    for (int j = 0; j < kHubPerThread; ++j) {
+        int64_t e = c0 + j * kHubThreads + threadIdx.x;
+        bool ok = e < c1;
+        v[j] = ok ? g.col[e] : u;
+        W[j] = ok ? wload<WK>(g.w, e) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < kFlush; ++j) {
-        uint64_t m = __ballot(created[j]);
-        if (m) {
-            int leader = __ffsll((unsigned long long)m) - 1;
-            int32_t base = 0;
-            if (lane == leader) base = atomicAdd(&ha.occ_cnt[hg], (int32_t)__popcll(m));
-            base = __shfl(base, leader);
-            if (created[j]) occ[base + (int32_t)__popcll(m & lt)] = (int32_t)slot[j];
+    for (int j = 0; j < kHubPerThread; ++j) X[j] = v[j] != u ? ms.zeta[v[j]] : -1;
+    int64_t myD = 0;
+#pragma unroll
+    for (int j = 0; j < kHubPerThread; ++j) {
+        if (X[j] == D) {
+            myD += W[j];
+            X[j] = -1;
         }
+        bk[j] = X[j] >= 0 ? (int32_t)hub_bucket(X[j], pb) : -1;
+        if (bk[j] >= 0) atomicAdd(&start[bk[j]], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the P bucket counts: thread t owns buckets [t*per, (t+1)*per)
+    const int per = (P + kHubThreads - 1) / kHubThreads;
+    int32_t cnts[kAggSlots / kHubThreads];
+    int32_t local = 0;
+#pragma unroll
+    for (int i = 0; i < kAggSlots / kHubThreads; ++i) {
+        int b = threadIdx.x * per + i;
+        cnts[i] = (i < per && b < P) ? start[b] : 0;
+        local += cnts[i];
+    }
+    int32_t inc = local;
+    for (int d = 1; d < kWave; d <<= 1) {
+        int32_t y = __shfl_up(inc, d);
+        if (lane_id() >= d) inc += y;
+    }
+    __shared__ int32_t wtot[kHubThreads / kWave];
+    if (lane_id() == kWave - 1) wtot[threadIdx.x / kWave] = inc;
+    __syncthreads();
+    int32_t run = inc - local;
+    for (int i = 0; i < threadIdx.x / kWave; ++i) run += wtot[i];
+    const int32_t nch = ha.nchunk[hg];
+    uint32_t *bkt = ha.bkt + ha.bkt_off[hg];
+#pragma unroll
+    for (int i = 0; i < kAggSlots / kHubThreads; ++i) {
+        int b = threadIdx.x * per + i;
+        if (i < per && b < P) {
+            start[b] = run;
+            bkt[(int64_t)b * nch + k] = ((uint32_t)run << 16) | (uint32_t)cnts[i];
+            run += cnts[i];
+        }
+    }
+    __syncthreads();
+    int32_t *sx = ha.stg_x + ha.stg_off[hg] + k * kHubInsChunk;
+    int64_t *sw = ha.stg_w + ha.stg_off[hg] + k * kHubInsChunk;
+#pragma unroll
+    for (int j = 0; j < kHubPerThread; ++j) {
+        if (bk[j] < 0) continue;
+        int32_t pos = start[bk[j]] + atomicAdd(&fill[bk[j]], 1);
+        sx[pos] = X[j];
+        sw[pos] = W[j];
+    }
+    myD = wave_sum(myD);
+    if (lane_id() == 0) wsum[threadIdx.x / kWave] = myD;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int i = 0; i < kHubThreads / kWave; ++i) s += wsum[i];
+        ha.wd_part[blockIdx.x] = s;
     }
 }
 
@@ -459,62 +447,96 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
 }
 
-template <typename G, bool PACKED>
-__device__ __forceinline__ void hub_slots_best(const HubArrays &ha, int64_t hg, const int32_t *occ, int64_t i0,
-                                               int64_t i1, int32_t D, int64_t vu, int64_t S, const int64_t *volC,
-                                               int64_t *wD_slot, G &bs, int32_t &bx, int64_t &ncand) {
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kHubThreads) {
-        int32_t s = occ[i];
-        int32_t X;
-        int64_t a;
-        if constexpr (PACKED) {
-            unsigned long long *tw = (unsigned long long *)ha.tab_val + ha.tab_off[hg];
-            unsigned long long word = tw[s];
-            tw[s] = kEmptyWord;
-            X = (int32_t)(word >> 32);
-            a = (int64_t)(word & 0xffffffffULL);
-        } else {
-            int32_t *tk = ha.tab_key + ha.tab_off[hg];
-            int64_t *tv = ha.tab_val + ha.tab_off[hg];
-            X = tk[s];
-            a = tv[s];
-            tk[s] = kEmpty;
-            tv[s] = 0;
+template <typename G>
+__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, int64_t vu, int64_t S,
+                                           const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *nkeys,
+                                           int32_t *overflow, G &bs, int32_t &bx, int64_t &ncand) {
+    const int32_t nch = ha.nchunk[hg];
+    const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
+    const int32_t *sx = ha.stg_x + ha.stg_off[hg];
+    const int64_t *sw = ha.stg_w + ha.stg_off[hg];
+    for (int qbits = 0;; ++qbits) {
+        G pbs = neg_inf<G>();
+        int32_t pbx = kNone;
+        int64_t pc = 0;
+        bool ok = true;
+        for (int q = 0; q < (1 << qbits); ++q) {
+            for (int s = threadIdx.x; s < kAggSlots; s += kHubThreads) { tk[s] = kEmpty; tv[s] = 0; }
+            if (threadIdx.x == 0) { *nkeys = 0; *overflow = 0; }
+            __syncthreads();
+            bool stop = false;
+            for (int32_t c = threadIdx.x; c < nch && !stop; c += kHubThreads) {
+                uint32_t word = bkt[c];
+                int64_t base = (int64_t)c * kHubInsChunk + (word >> 16);
+                int32_t cnt = (int32_t)(word & 0xffffu);
+                for (int32_t i = 0; i < cnt && !stop; ++i) {
+                    int32_t X = sx[base + i];
+                    if (agg_subpart(X, qbits) != (uint32_t)q) continue;
+                    int64_t w = sw[base + i];
+                    uint32_t h = agg_slot(X);
+                    for (;;) {
+                        int32_t kk = atomicCAS(&tk[h], kEmpty, X);
+                        if (kk == kEmpty && atomicAdd(nkeys, 1) >= kAggMaxKeys) {
+                            *overflow = 1;
+                            stop = true;
+                            break;
+                        }
+                        if (kk == kEmpty || kk == X) {
+                            atomicAdd((unsigned long long *)&tv[h], (unsigned long long)w);
+                            break;
+                        }
+                        h = (h + 1) & (kAggSlots - 1);
+                    }
+                }
+            }
+            __syncthreads();
+            if (*overflow) {
+                ok = false;
+                __syncthreads();
+                break;
+            }
+            for (int s = threadIdx.x; s < kAggSlots; s += kHubThreads) {
+                int32_t X = tk[s];
+                if (X < 0) continue;
+                ++pc;
+                G sc = (G)S * (G)tv[s] - (G)vu * (G)volC[X];
+                if (sc > pbs || (sc == pbs && X < pbx)) { pbs = sc; pbx = X; }
+            }
+            __syncthreads();
         }
-        ++ncand;  // the tables never hold D (summed into hub_wD by the insert launch)
-        G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-        if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
+        if (ok) {
+            bs = pbs;
+            bx = pbx;
+            ncand += pc;
+            return;
+        }
     }
 }
 
-template <bool PACKED>
-__global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
-                                                          int64_t nh, int force_wide) {
-    int64_t h = hub_of_block(ha.eval_first + hub0, nh, blockIdx.x);
-    int64_t hg = hub0 + h;
-    int64_t chunk = blockIdx.x - ha.eval_first[hg];
-    int64_t pos = ha.hub_pos[hg];
-    int32_t u = ms.class_nodes[pos];
-    int32_t D = ms.zeta[u];
-    int64_t vu = ms.vol[u];
-    bool wide = force_wide || vu > ms.wide_lim;
-    const int32_t *occ = ha.occ + (ha.tab_off[hg] >> 1);
-    int64_t nocc = ha.occ_cnt[hg];
-    int64_t i0 = chunk * kHubEvalChunk, i1 = i0 + kHubEvalChunk < nocc ? i0 + kHubEvalChunk : nocc;
+__global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays ha, int64_t hub0, int64_t nh,
+                                                         int force_wide) {
+    __shared__ int32_t tk[kAggSlots];
+    __shared__ int64_t tv[kAggSlots];
+    __shared__ int32_t nkeys, overflow;
+    const int64_t h = hub_of_block(ha.agg_first + hub0, nh, blockIdx.x);
+    const int64_t hg = hub0 + h;
+    const int64_t p = blockIdx.x - ha.agg_first[hg];
+    const int32_t u = ms.class_nodes[ha.hub_pos[hg]];
+    const int64_t vu = ms.vol[u];
     int64_t ncand = 0;
-    unsigned long long *part = ha.part + 4 * (size_t)blockIdx.x;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
-    if (wide) {
-        hub_slots_best<i128, PACKED>(ha, hg, occ, i0, i1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], bs, bx, ncand);
+    if (force_wide || vu > ms.wide_lim) {
+        agg_bucket<i128>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, &nkeys, &overflow, bs, bx, ncand);
         block_argmax<i128>(bs, bx);
     } else {
         int64_t b64 = neg_inf<int64_t>();
-        hub_slots_best<int64_t, PACKED>(ha, hg, occ, i0, i1, D, vu, ms.S, ms.volC, &ha.hub_wD[hg], b64, bx, ncand);
+        agg_bucket<int64_t>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, &nkeys, &overflow, b64, bx, ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
     }
     if (threadIdx.x == 0) {
+        unsigned long long *part = ha.part + 4 * (size_t)blockIdx.x;
         part[0] = (unsigned long long)(uint64_t)(bs >> 64);
         part[1] = (unsigned long long)(uint64_t)bs;
         part[2] = (unsigned long long)(uint32_t)bx;
@@ -522,31 +544,35 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_eval(GraphView g, MoveState
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
 }
 
-// One workgroup per hub of the class combines the eval partials (written by
-// the previous launch, so no fence is needed) and decides the move.
+// One workgroup per hub of the class combines the bucket partials and the
+// w(u, D) shares (written by earlier launches) and decides the move.
 __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArrays ha, int64_t hub0) {
-    int64_t hg = hub0 + blockIdx.x;
-    int64_t nblk = ha.eval_cnt[hg];
-    const unsigned long long *p0 = ha.part + 4 * (size_t)ha.eval_first[hg];
+    __shared__ int64_t wsum[kHubThreads / kWave];
+    const int64_t hg = hub0 + blockIdx.x;
+    const int64_t nagg = (int64_t)1 << ha.pbits[hg];
+    const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
-    for (int64_t j = threadIdx.x; j < nblk; j += kHubThreads) {
+    for (int64_t j = threadIdx.x; j < nagg; j += kHubThreads) {
         int32_t x = (int32_t)p0[4 * j + 2];
         i128 s = (i128)(((unsigned __int128)p0[4 * j + 0] << 64) | p0[4 * j + 1]);
         if (x != kNone && (s > bs || (s == bs && x < bx))) { bs = s; bx = x; }
     }
+    int64_t wD = 0;
+    for (int64_t j = threadIdx.x; j < ha.nchunk[hg]; j += kHubThreads) wD += ha.wd_part[ha.ins_first[hg] + j];
+    wD = wave_sum(wD);
+    if (lane_id() == 0) wsum[threadIdx.x / kWave] = wD;
     block_argmax<i128>(bs, bx);
     if (threadIdx.x == 0) {
+        wD = 0;
+        for (int i = 0; i < kHubThreads / kWave; ++i) wD += wsum[i];
         int64_t pos = ha.hub_pos[hg];
         int32_t u = ms.class_nodes[pos];
         int32_t D = ms.zeta[u];
         int64_t vu = ms.vol[u];
-        int64_t wD = ha.hub_wD[hg];
         int64_t base = ms.volC[D] - vu;
         i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
         ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
-        ha.hub_wD[hg] = 0;
-        ha.occ_cnt[hg] = 0;
     }
 }
 
@@ -603,21 +629,12 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
     }
     mark(3);
     if (cr.hub_count > 0) {
-        if (ha.packed) {
-            hipLaunchKernelGGL((k_hub_insert<WK, true>), dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g,
-                               ms, ha, cr.hub_first, cr.hub_count);
-            hipLaunchKernelGGL(k_hub_eval<true>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
-                               cr.hub_first, cr.hub_count, fw);
-            hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
-                               cr.hub_first);
-        } else {
-            hipLaunchKernelGGL((k_hub_insert<WK, false>), dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g,
-                               ms, ha, cr.hub_first, cr.hub_count);
-            hipLaunchKernelGGL(k_hub_eval<false>, dim3((unsigned)cr.eval_blocks), dim3(kHubThreads), 0, st, g, ms,
-                               ha, cr.hub_first, cr.hub_count, fw);
-            hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
-                               cr.hub_first);
-        }
+        hipLaunchKernelGGL(k_hub_part<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                           cr.hub_first, cr.hub_count);
+        hipLaunchKernelGGL(k_hub_agg, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha, cr.hub_first,
+                           cr.hub_count, fw);
+        hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
+                           cr.hub_first);
     }
     mark(4);
 }
