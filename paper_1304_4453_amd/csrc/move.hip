@@ -322,8 +322,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 //     shares and decides the move.
 constexpr int kHubThreads = 256;
 constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
-constexpr int kAggSlots = 4096;
-constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
+constexpr int kAggSlots = 2048;    // LDS table of a bucket workgroup (~512 entries expected)
+constexpr int kAggMaxKeys = 1536;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
+constexpr int kAggTile = 2048;     // chunks whose segments are flattened at once
 
 __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
     int64_t lo = 0, hi = nh;  // last h with first[h] <= b
@@ -337,7 +338,7 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
 __device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
     return pbits == 0 ? 0u : ((uint32_t)x * 2654435769u) >> (32 - pbits);
 }
-__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 12); }
+__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 11); }
 __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
@@ -345,8 +346,8 @@ __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
 template <int WK>
 __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
                                                           int64_t nh) {
-    __shared__ int32_t start[kAggSlots];
-    __shared__ int32_t fill[kAggSlots];
+    __shared__ int32_t start[1 << kHubMaxPBits];
+    __shared__ int32_t fill[1 << kHubMaxPBits];
     __shared__ int64_t wsum[kHubThreads / kWave];
     const int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
     const int64_t hg = hub0 + h;
@@ -383,10 +384,10 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     __syncthreads();
     // exclusive scan of the P bucket counts: thread t owns buckets [t*per, (t+1)*per)
     const int per = (P + kHubThreads - 1) / kHubThreads;
-    int32_t cnts[kAggSlots / kHubThreads];
+    int32_t cnts[(1 << kHubMaxPBits) / kHubThreads];
     int32_t local = 0;
 #pragma unroll
-    for (int i = 0; i < kAggSlots / kHubThreads; ++i) {
+    for (int i = 0; i < (1 << kHubMaxPBits) / kHubThreads; ++i) {
         int b = threadIdx.x * per + i;
         cnts[i] = (i < per && b < P) ? start[b] : 0;
         local += cnts[i];
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     const int32_t nch = ha.nchunk[hg];
     uint32_t *bkt = ha.bkt + ha.bkt_off[hg];
 #pragma unroll
-    for (int i = 0; i < kAggSlots / kHubThreads; ++i) {
+    for (int i = 0; i < (1 << kHubMaxPBits) / kHubThreads; ++i) {
         int b = threadIdx.x * per + i;
         if (i < per && b < P) {
             start[b] = run;
@@ -447,14 +448,20 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
 }
 
+// Entries of bucket p of a hub, over all its chunks, processed kAggTile chunks
+// at a time: an LDS prefix sum over the chunks' segment lengths turns the
+// bucket into one flat index space that every thread strides over (a binary
+// search finds the chunk of an index).
 template <typename G>
 __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, int64_t vu, int64_t S,
-                                           const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *nkeys,
-                                           int32_t *overflow, G &bs, int32_t &bx, int64_t &ncand) {
+                                           const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
+                                           int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
+                                           int32_t &bx, int64_t &ncand) {
     const int32_t nch = ha.nchunk[hg];
     const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
     const int32_t *sx = ha.stg_x + ha.stg_off[hg];
     const int64_t *sw = ha.stg_w + ha.stg_off[hg];
+    constexpr int kPer = kAggTile / kHubThreads;
     for (int qbits = 0;; ++qbits) {
         G pbs = neg_inf<G>();
         int32_t pbx = kNone;
@@ -465,14 +472,46 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
             if (threadIdx.x == 0) { *nkeys = 0; *overflow = 0; }
             __syncthreads();
             bool stop = false;
-            for (int32_t c = threadIdx.x; c < nch && !stop; c += kHubThreads) {
-                uint32_t word = bkt[c];
-                int64_t base = (int64_t)c * kHubInsChunk + (word >> 16);
-                int32_t cnt = (int32_t)(word & 0xffffu);
-                for (int32_t i = 0; i < cnt && !stop; ++i) {
-                    int32_t X = sx[base + i];
+            for (int32_t t0 = 0; t0 < nch; t0 += kAggTile) {
+                const int32_t tn = nch - t0 < kAggTile ? nch - t0 : kAggTile;
+                // segment lengths of this tile's chunks, exclusive prefix into cpre
+                int32_t cnt[kPer], loc = 0;
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    int32_t c = threadIdx.x * kPer + i;
+                    uint32_t word = c < tn ? bkt[t0 + c] : 0u;
+                    cnt[i] = (int32_t)(word & 0xffffu);
+                    if (c < tn) cbase[c] = (t0 + c) * (int32_t)kHubInsChunk + (int32_t)(word >> 16);
+                    loc += cnt[i];
+                }
+                int32_t inc = loc;
+                for (int d = 1; d < kWave; d <<= 1) {
+                    int32_t y = __shfl_up(inc, d);
+                    if (lane_id() >= d) inc += y;
+                }
+                if (lane_id() == kWave - 1) wtot[threadIdx.x / kWave] = inc;
+                __syncthreads();
+                int32_t run = inc - loc, total = 0;
+                for (int i = 0; i < kHubThreads / kWave; ++i) {
+                    if (i < (int)(threadIdx.x / kWave)) run += wtot[i];
+                    total += wtot[i];
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    cpre[threadIdx.x * kPer + i] = run;
+                    run += cnt[i];
+                }
+                __syncthreads();
+                for (int32_t i = threadIdx.x; i < total && !stop; i += kHubThreads) {
+                    int32_t lo = 0, hi = tn;  // last chunk c with cpre[c] <= i
+                    while (hi - lo > 1) {
+                        int32_t mid = (lo + hi) >> 1;
+                        if (cpre[mid] <= i) lo = mid; else hi = mid;
+                    }
+                    int64_t idx = (int64_t)cbase[lo] + (i - cpre[lo]);
+                    int32_t X = sx[idx];
                     if (agg_subpart(X, qbits) != (uint32_t)q) continue;
-                    int64_t w = sw[base + i];
+                    int64_t w = sw[idx];
                     uint32_t h = agg_slot(X);
                     for (;;) {
                         int32_t kk = atomicCAS(&tk[h], kEmpty, X);
@@ -488,8 +527,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                         h = (h + 1) & (kAggSlots - 1);
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
             if (*overflow) {
                 ok = false;
                 __syncthreads();
@@ -517,6 +556,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
                                                          int force_wide) {
     __shared__ int32_t tk[kAggSlots];
     __shared__ int64_t tv[kAggSlots];
+    __shared__ int32_t cpre[kAggTile], cbase[kAggTile], wtot[kHubThreads / kWave];
     __shared__ int32_t nkeys, overflow;
     const int64_t h = hub_of_block(ha.agg_first + hub0, nh, blockIdx.x);
     const int64_t hg = hub0 + h;
@@ -527,11 +567,12 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
     if (force_wide || vu > ms.wide_lim) {
-        agg_bucket<i128>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, &nkeys, &overflow, bs, bx, ncand);
+        agg_bucket<i128>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ncand);
         block_argmax<i128>(bs, bx);
     } else {
         int64_t b64 = neg_inf<int64_t>();
-        agg_bucket<int64_t>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, &nkeys, &overflow, b64, bx, ncand);
+        agg_bucket<int64_t>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
+                            ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
     }
