@@ -59,7 +59,7 @@ struct HubArrays {
 
 constexpr int64_t kHubInsChunk = 2048;  // entries per hub chunk workgroup
 constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
-constexpr int64_t kHubBucketTarget = 512;
+constexpr int64_t kHubBucketTarget = 2048;
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                        bool force_wide, const hipEvent_t *ev, hipStream_t st);

@@ -322,8 +322,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
 //     shares and decides the move.
 constexpr int kHubThreads = 256;
 constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
-constexpr int kAggSlots = 2048;    // LDS table of a bucket workgroup (~512 entries expected)
-constexpr int kAggMaxKeys = 1536;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
+constexpr int kAggSlots = 4096;    // LDS table of a bucket workgroup (~2048 entries expected)
+constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
 constexpr int kAggTile = 2048;     // chunks whose segments are flattened at once
 
 __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
@@ -338,7 +338,7 @@ __device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh
 __device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
     return pbits == 0 ? 0u : ((uint32_t)x * 2654435769u) >> (32 - pbits);
 }
-__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 11); }
+__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 12); }
 __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
