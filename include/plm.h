@@ -130,6 +130,34 @@ plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels
  * divided.  PLM_E_ARG for labels out of range. */
 plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind, double *q_out);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent graphs run Algorithm 3 together, each with the result of a
+ * separate plm_run on it (same labels, modularity and number of levels): the
+ * move phases of all graphs share launches, and a graph whose communities stop
+ * merging leaves the later levels.
+ *
+ * plm_batch_create: num_graphs >= 1 graphs, graph g owning the nodes
+ * node_base[g] .. node_base[g+1]-1 (node_base: host array of num_graphs + 1
+ * non-decreasing values, node_base[0] = 0; empty graphs allowed).  The CSR
+ * (offsets[node_base[num_graphs] + 1], cols, weights as for plm_create) is the
+ * disjoint union with global node ids; with opt->validate an entry joining two
+ * graphs is PLM_E_GRAPH.  Batched contexts take the colour schedule and
+ * int_mode auto or 128 (else PLM_E_ARG); the sum of all graphs' S = 2 w(E)
+ * must stay below 2^62.  plm_move_sweep, plm_move_class, plm_reset and the
+ * inspection calls apply; plm_coarsen, plm_run and plm_modularity return
+ * PLM_E_STATE. */
+plm_status plm_batch_create(plm_ctx **out, int64_t num_graphs, const int64_t *node_base, int64_t nnz,
+                            const int64_t *offsets, const int32_t *cols, const int32_t *weights, int32_t mem_kind,
+                            void *hip_stream, const plm_options *opt);
+
+/* Algorithm 3 on every graph of a batched context.  labels[n] (mem_kind of the
+ * input) receives each graph's canonical labels, numbered from 0 within the
+ * graph; q_out[num_graphs] (host) each graph's modularity, Equation (3.1)
+ * computed as in plm_modularity (0 for a graph without edges);
+ * levels_out[num_graphs] (host) each graph's number of move phases.  Any
+ * output may be NULL.  PLM_E_STATE on a context from plm_create. */
+plm_status plm_batch_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out);
+
 /* Resets the context to level 0 with singleton communities. */
 plm_status plm_reset(plm_ctx *ctx);
 

@@ -93,7 +93,9 @@ def _load():
     lib.plm_get_state.argtypes = [vp, vp, vp, vp, i32]
     lib.plm_get_graph.argtypes = [vp, vp, vp, vp, i32]
     lib.plm_get_stats.argtypes = [vp, P(plm_stats_t)]
-    for f in ("plm_create", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
+    lib.plm_batch_create.argtypes = [P(vp), i64, vp, i64, vp, vp, vp, i32, vp, P(plm_options)]
+    lib.plm_batch_run.argtypes = [vp, vp, vp, vp]
+    for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
               "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
         getattr(lib, f).restype = i32
     return lib
@@ -115,6 +117,8 @@ plm_level_info = _lib.plm_level_info
 plm_get_state = _lib.plm_get_state
 plm_get_graph = _lib.plm_get_graph
 plm_get_stats = _lib.plm_get_stats
+plm_batch_create = _lib.plm_batch_create
+plm_batch_run = _lib.plm_batch_run
 
 
 def default_options(**kw) -> plm_options:
@@ -255,3 +259,67 @@ class Context:
             v = list(getattr(s, f))[:L]
             out[f] = [list(x) if not isinstance(x, (int, float)) else x for x in v]
         return out
+
+
+def pack_batch(graphs):
+    """Disjoint union of host CSR graphs (objects with off, col, w or tuples
+    (off, col, w)): returns (node_base, off, col, w) with global node ids; w is
+    None when no graph carries weights (unit weights), else every graph's
+    weights (unit weights filled in for unweighted members)."""
+    parts = [(g.off, g.col, g.w) if hasattr(g, "off") else tuple(g) for g in graphs]
+    ns = np.array([len(o) - 1 for o, _, _ in parts], np.int64)
+    node_base = np.zeros(len(parts) + 1, np.int64)
+    node_base[1:] = np.cumsum(ns)
+    ms = np.array([len(c) for _, c, _ in parts], np.int64)
+    ebase = np.zeros(len(parts) + 1, np.int64)
+    ebase[1:] = np.cumsum(ms)
+    off = np.zeros(int(node_base[-1]) + 1, np.int64)
+    col = np.zeros(int(ebase[-1]), np.int32)
+    weighted = any(w is not None for _, _, w in parts)
+    w = np.ones(int(ebase[-1]), np.int32) if weighted else None
+    for i, (o, c, ww) in enumerate(parts):
+        a, b = int(node_base[i]), int(node_base[i + 1])
+        off[a:b] = np.asarray(o[:-1], np.int64) + ebase[i]
+        col[ebase[i]:ebase[i + 1]] = np.asarray(c, np.int64) + a
+        if weighted and ww is not None:
+            w[ebase[i]:ebase[i + 1]] = ww
+    off[-1] = ebase[-1]
+    return node_base, off, col, w
+
+
+class BatchContext(Context):
+    """Owns one batched plm_ctx (plm_batch_create): graph g holds the nodes
+    node_base[g] .. node_base[g+1]-1 of the union CSR (off, col, w)."""
+
+    def __init__(self, node_base, off, col, w=None, mem_kind: int | None = None, stream=None,
+                 nnz: int | None = None, **options):
+        self._c = ctypes.c_void_p()
+        node_base = np.ascontiguousarray(node_base, dtype=np.int64)
+        if mem_kind is None:
+            mem_kind = PLM_MEM_HOST if isinstance(off, np.ndarray) else PLM_MEM_DEVICE
+        if mem_kind == PLM_MEM_HOST:
+            off = np.ascontiguousarray(off, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            if w is not None:
+                w = np.ascontiguousarray(w, dtype=np.int32)
+        if nnz is None:
+            nnz = int(col.shape[0])
+        self.G = int(node_base.shape[0]) - 1
+        self.node_base = node_base
+        self.n, self.nnz, self.mem_kind = int(node_base[-1]), nnz, mem_kind
+        sp = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
+        self.opt = default_options(**options)
+        rc = plm_batch_create(ctypes.byref(self._c), self.G, node_base.ctypes.data, nnz, _ptr(off), _ptr(col),
+                              _ptr(w), mem_kind, sp or 0, ctypes.byref(self.opt))
+        if rc != 0:
+            raise PLMError(rc, plm_last_error(None).decode())
+
+    def run_batch(self, labels=None):
+        """Runs every graph.  Returns (labels, q[G], levels[G]); labels are
+        numbered from 0 within each graph."""
+        if labels is None and self.mem_kind == PLM_MEM_HOST:
+            labels = np.zeros(self.n, np.int32)
+        q = np.zeros(max(self.G, 1), np.float64)
+        lv = np.zeros(max(self.G, 1), np.int32)
+        self._check(plm_batch_run(self._c, _ptr(labels), q.ctypes.data, lv.ctypes.data))
+        return labels, q[: self.G], lv[: self.G]

@@ -47,14 +47,19 @@ struct LevelData {
     int wkind = 0;
     int diag_mult = 1;
     int32_t *pi = nullptr;  // fine -> coarse map, set when this level is coarsened
+    // batched runs: graph (index among this level's graphs) of each node, and
+    // the first node of each graph (count + 1 entries)
+    int32_t *gid = nullptr;
+    int64_t *gbase = nullptr;
 
     GraphView view() const {
         GraphView g;
         g.n = n; g.nnz = nnz; g.off = off; g.col = col; g.w = w; g.wkind = wkind; g.diag_mult = diag_mult;
+        g.gid = gid; g.gbase = gbase;
         return g;
     }
     void release() {
-        dev_free(off); dev_free(col); dev_free(w); dev_free(pi);
+        dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase);
     }
 };
 
@@ -138,10 +143,27 @@ struct plm_ctx {
     plm_stats_t stats;
     std::vector<hipEvent_t> events;
 
+    // batched runs (plm_batch_create): G graphs side by side on node ranges
+    // gbase0_h[g] .. gbase0_h[g+1]; levels[0].gid / .gbase hold the input ranges
+    bool batch = false;
+    int64_t G = 0;
+    std::vector<int64_t> gbase0_h;
+    int64_t *gS0 = nullptr, *gwl0 = nullptr;   // per input graph: S and 64-bit limit
+    std::vector<int64_t> act_h;                // graphs of the current level (input ids)
+    int64_t *act = nullptr, *gS = nullptr, *gwl = nullptr;  // the same, per current graph
+    int32_t *bflag = nullptr, *bout = nullptr;
+    int64_t *bnewid = nullptr, *bgath = nullptr;
+    void *bscan = nullptr;
+    uint8_t *bstatus = nullptr, *bkeep = nullptr;
+    unsigned long long *bI2 = nullptr, *bsq = nullptr;
+
     ~plm_ctx() {
         for (auto &l : levels) l.release();
         dev_free(vol0); dev_free(vol); dev_free(volC); dev_free(zeta); dev_free(colour); dev_free(class_nodes);
         dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
+        dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
+        dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
+        dev_free(bsq);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
@@ -172,15 +194,26 @@ struct plm_ctx {
         loops = hbuf[2];
         uint64_t s = (uint64_t)hbuf[0];
         if (cur == 0) {
-            if (s >= (1ULL << 62)) throw Error{PLM_E_GRAPH, "total weight S = 2 w(E) must be below 2^62"};
+            if (s >= (1ULL << 62))
+                throw Error{PLM_E_GRAPH, batch ? "total weight of the batch must be below 2^62"
+                                               : "total weight S = 2 w(E) must be below 2^62"};
             S = (int64_t)s;
             HIPCHK(hipMemcpyAsync(vol0, vol, l.n * 8, hipMemcpyDeviceToDevice, st));
+            if (batch) {
+                launch_graph_S(vol, l.gbase, G, gS0, gwl0, st);
+                HIPCHK(hipMemcpyAsync(gS, gS0, G * 8, hipMemcpyDeviceToDevice, st));
+                HIPCHK(hipMemcpyAsync(gwl, gwl0, G * 8, hipMemcpyDeviceToDevice, st));
+            }
+        } else if (batch) {
+            // the graphs of this level keep their input S (contraction preserves it)
+            launch_gather_i64(gS0, act, (int64_t)act_h.size(), gS, st);
+            launch_gather_i64(gwl0, act, (int64_t)act_h.size(), gwl, st);
         } else if ((int64_t)s != S) {
             throw Error{PLM_E_STATE, "internal: coarse graph changed the total weight"};
         }
         max_vol = hbuf[1];
         wide_lim = S > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)S) : INT64_MAX;
-        if (opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
+        if (!batch && opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
             throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
         launch_iota(zeta, l.n, st);
         launch_copy_vol(volC, vol, l.n, st);
@@ -317,6 +350,7 @@ struct plm_ctx {
         MoveState ms;
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
+        if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; }
         return ms;
     }
     HubArrays hub_arrays() {
@@ -415,7 +449,14 @@ struct plm_ctx {
         dev_free(levels[0].pi);
         cur = 0;
         std::memset(&stats, 0, sizeof(stats));
+        if (batch) set_active_all();
         init_level();
+    }
+    void set_active_all() {
+        act_h.resize(G);
+        for (int64_t g = 0; g < G; ++g) act_h[g] = g;
+        HIPCHK(hipMemcpyAsync(act, act_h.data(), G * 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
     }
 
     void record_level(int64_t communities, double t_sched, double t_sweep, double t_coarsen, int64_t moves) {
@@ -487,6 +528,130 @@ struct plm_ctx {
         if (S == 0) return 0.0;
         return (double)num / (double)den;
     }
+
+    // Algorithm 3 on every graph of a batch at once.  All graphs still active
+    // are at the same level; a graph whose communities stop merging (or that
+    // reached max_levels) gets its labels at that level and leaves the next.
+    // Results per graph equal those of a separate run: priorities, gains and
+    // coarse ids are all local to each graph, and once a graph's sweep makes
+    // no move, further sweeps of the batch leave it unchanged.
+    // canon_out (device, n0): labels canonical within each graph.
+    void run_batch(int32_t *canon_out, double *q_out, int32_t *levels_out) {
+        reset();
+        int64_t n0v = n0;
+        std::vector<uint8_t> status(G, 0), keep;
+        std::vector<int64_t> gath, nbase, nact;
+        std::vector<int32_t> glev(G, 0);
+        launch_iota(lab, n0v, st);
+        for (int32_t depth = 1;; ++depth) {
+            double t0 = now_ms();
+            build_schedule();
+            double t1 = now_ms();
+            int64_t moves = 0;
+            for (int32_t s = 0; s < opt.max_sweeps; ++s) {
+                int64_t mv = sweep();
+                moves += mv;
+                if (mv == 0) break;
+            }
+            double t2 = now_ms();
+            LevelData &l = L();
+            int64_t A = (int64_t)act_h.size();
+            // communities of each graph: ranks of community ids at the graph bounds
+            batch_relabel(zeta, l.n, l.gid, nullptr, bflag, bnewid, nullptr, bscan, st);
+            launch_gather_i64(bnewid, l.gbase, A + 1, bgath, st);
+            launch_gather_i64(l.off, l.gbase, A + 1, bgath + A + 1, st);
+            gath.resize(2 * (A + 1));
+            HIPCHK(hipMemcpyAsync(gath.data(), bgath, 2 * (A + 1) * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int64_t *nid = gath.data(), *eoff = gath.data() + A + 1;
+            std::vector<int64_t> abase(A + 1);
+            HIPCHK(hipMemcpyAsync(abase.data(), l.gbase, (A + 1) * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool last = opt.max_levels > 0 && depth >= opt.max_levels;
+            keep.assign(A, 0);
+            nbase.assign(1, 0);
+            nact.clear();
+            int64_t nnz_kept = 0;
+            for (int64_t a = 0; a < A; ++a) {
+                int64_t ka = nid[a + 1] - nid[a], na = abase[a + 1] - abase[a];
+                int64_t g = act_h[a];
+                glev[g] = depth;
+                if (ka == na || last) {
+                    status[g] = 1;
+                } else {
+                    status[g] = 0;
+                    keep[a] = 1;
+                    nact.push_back(g);
+                    nbase.push_back(nbase.back() + ka);
+                    nnz_kept += eoff[a + 1] - eoff[a];
+                }
+            }
+            record_level(nid[A] - nid[0], t1 - t0, t2 - t1, 0, moves);
+            double t3 = now_ms();
+            HIPCHK(hipMemcpyAsync(bstatus, status.data(), G, hipMemcpyHostToDevice, st));
+            if (A > 0) HIPCHK(hipMemcpyAsync(bkeep, keep.data(), A, hipMemcpyHostToDevice, st));
+            int64_t A2 = (int64_t)nact.size();
+            if (A2 > 0) {
+                dev_free(l.pi);
+                l.pi = dev_alloc<int32_t>(l.n);
+                batch_relabel(zeta, l.n, l.gid, bkeep, bflag, bnewid, l.pi, bscan, st);
+            }
+            launch_batch_step(n0v, levels[0].gid, bstatus, l.gid, l.gbase, zeta, l.pi, lab, bout, st);
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t a = 0; a < A; ++a)
+                if (!keep[a]) status[act_h[a]] = 2;
+            if (A2 == 0) break;
+            int64_t k = nbase.back();
+            LevelData nl;
+            nl.n = k;
+            try {
+                nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, bkeep,
+                                           nnz_kept);
+                nl.wkind = 2;
+                nl.diag_mult = 1;
+                nl.gbase = dev_alloc<int64_t>(A2 + 1);
+                nl.gid = dev_alloc<int32_t>(k);
+                HIPCHK(hipMemcpyAsync(nl.gbase, nbase.data(), (A2 + 1) * 8, hipMemcpyHostToDevice, st));
+                launch_fill_gid(nl.gbase, A2, k, nl.gid, st);
+                act_h = nact;
+                HIPCHK(hipMemcpyAsync(act, act_h.data(), A2 * 8, hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+            } catch (...) {
+                nl.release();
+                throw;
+            }
+            while ((int)levels.size() > cur + 1) {
+                levels.back().release();
+                levels.pop_back();
+            }
+            levels.push_back(nl);
+            int prev = cur++;
+            init_level();
+            if (prev < PLM_MAX_LEVELS) stats.coarsen_ms[prev] = now_ms() - t3;
+        }
+        // labels canonical within each graph; per-graph modularity on the input
+        const GraphView g0 = levels[0].view();
+        if (n0v > 0) batch_canonical(n0v, g0.gid, g0.gbase, bout, bflag, move_to, canon_out, scr, st);
+        if (q_out) {
+            // keys (bflag) = first input node of the graph + local label
+            batch_modularity_parts(g0, g0.gid, bflag, vol0, G, bnewid, bI2, bsq, st);
+            std::vector<uint64_t> I2(G), sq(2 * G);
+            std::vector<int64_t> Sg(G);
+            HIPCHK(hipMemcpyAsync(I2.data(), bI2, G * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(sq.data(), bsq, G * 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(Sg.data(), gS0, G * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t g = 0; g < G; ++g) {
+                if (Sg[g] == 0) { q_out[g] = 0.0; continue; }
+                unsigned __int128 s2 = ((unsigned __int128)sq[2 * g + 1] << 64) | sq[2 * g];
+                __int128 num = (__int128)Sg[g] * (__int128)(int64_t)I2[g] - (__int128)s2;
+                __int128 den = (__int128)Sg[g] * (__int128)Sg[g];
+                q_out[g] = (double)num / (double)den;
+            }
+        }
+        if (levels_out)
+            for (int64_t g = 0; g < G; ++g) levels_out[g] = glev[g];
+    }
 };
 
 // ------------------------------------------------------------------ C ABI
@@ -552,8 +717,15 @@ void plm_default_options(plm_options *o) {
     o->timing = 0;
 }
 
-plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
-                      const int32_t *weights, int32_t mem_kind, void *hip_stream, const plm_options *opt) {
+}  // extern "C"
+
+namespace {
+
+// Shared by plm_create (G = 0) and plm_batch_create (G >= 1 graphs on the node
+// ranges node_base[0..G]).
+plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t n, int64_t nnz,
+                       const int64_t *offsets, const int32_t *cols, const int32_t *weights, int32_t mem_kind,
+                       void *hip_stream, const plm_options *opt) {
     g_create_error.clear();
     if (out) *out = nullptr;
     auto fail = [&](int code, const std::string &m) {
@@ -572,6 +744,13 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
     std::string m;
     int rc = check_options(o, m);
     if (rc) return fail(rc, m);
+    if (G > 0) {
+        if (o.schedule != PLM_SCHEDULE_COLOUR) return fail(PLM_E_ARG, "batched runs use the colour schedule");
+        if (o.int_mode == PLM_INT_64) return fail(PLM_E_ARG, "batched runs take int_mode auto or 128");
+        if (node_base[0] != 0) return fail(PLM_E_ARG, "node_base[0] must be 0");
+        for (int64_t g = 0; g < G; ++g)
+            if (node_base[g + 1] < node_base[g]) return fail(PLM_E_ARG, "node_base must be non-decreasing");
+    }
     if (mem_kind == PLM_MEM_HOST) {
         if (offsets[0] != 0 || offsets[n] != nnz) return fail(PLM_E_GRAPH, "offsets[0] must be 0 and offsets[n] = nnz");
     }
@@ -597,8 +776,29 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
         copy_in(l0.col, cols, (size_t)nnz * 4, mem_kind, c->st);
         if (weights) copy_in(l0.w, weights, (size_t)nnz * 4, mem_kind, c->st);
         HIPCHK(hipStreamSynchronize(c->st));
+        if (G > 0) {
+            c->batch = true;
+            c->G = G;
+            c->gbase0_h.assign(node_base, node_base + G + 1);
+            LevelData &b0 = c->levels[0];
+            b0.gbase = dev_alloc<int64_t>(G + 1);
+            b0.gid = dev_alloc<int32_t>(n);
+            HIPCHK(hipMemcpyAsync(b0.gbase, node_base, (G + 1) * 8, hipMemcpyHostToDevice, c->st));
+            launch_fill_gid(b0.gbase, G, n, b0.gid, c->st);
+            c->gS0 = dev_alloc<int64_t>(G); c->gwl0 = dev_alloc<int64_t>(G);
+            c->act = dev_alloc<int64_t>(G); c->gS = dev_alloc<int64_t>(G); c->gwl = dev_alloc<int64_t>(G);
+            c->bflag = dev_alloc<int32_t>(n); c->bout = dev_alloc<int32_t>(n);
+            c->bnewid = dev_alloc<int64_t>(n + 1); c->bgath = dev_alloc<int64_t>(2 * (G + 1));
+            c->bscan = dev_alloc<uint8_t>((int64_t)scan_scratch_bytes(n > 0 ? n : 1));
+            c->bstatus = dev_alloc<uint8_t>(G); c->bkeep = dev_alloc<uint8_t>(G);
+            c->bI2 = dev_alloc<unsigned long long>(G); c->bsq = dev_alloc<unsigned long long>(2 * G);
+            HIPCHK(hipStreamSynchronize(c->st));
+        }
         if (o.validate) {
-            uint32_t bad = validate_graph(l0.view(), c->scr, c->hbuf, c->st);
+            uint32_t bad = validate_graph(c->levels[0].view(), c->scr, c->hbuf, c->st);
+            if (!bad && G > 0)
+                bad = batch_validate(c->levels[0].view(), c->levels[0].gid, c->levels[0].gbase, c->scr, c->hbuf,
+                                     c->st);
             if (bad) {
                 std::string why;
                 if (bad & 16u) why += " offsets not monotone or not spanning [0, nnz];";
@@ -606,6 +806,7 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
                 if (bad & 2u) why += " non-positive weight;";
                 if (bad & 4u) why += " row not strictly ascending (duplicate or unsorted);";
                 if (bad & 8u) why += " not symmetric (missing or unequal mirror entry);";
+                if (bad & 32u) why += " edge between two graphs of the batch;";
                 throw Error{PLM_E_GRAPH, "invalid graph:" + why};
             }
         }
@@ -619,6 +820,7 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
         c->lab = dev_alloc<int32_t>(n);
         c->dcnt = dev_alloc<unsigned long long>(16);
         HIPCHK(hipMemsetAsync(c->dcnt, 0, 16 * 8, c->st));
+        if (c->batch) c->set_active_all();
         c->init_level();
     } catch (const Error &e) {
         delete c;
@@ -629,6 +831,48 @@ plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offs
     }
     *out = c;
     return PLM_OK;
+}
+
+void reject_batch(plm_ctx *ctx, const char *what) {
+    if (ctx->batch) throw Error{PLM_E_STATE, std::string(what) + " does not apply to a batched context"};
+}
+
+}  // namespace
+
+extern "C" {
+
+plm_status plm_create(plm_ctx **out, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                      const int32_t *weights, int32_t mem_kind, void *hip_stream, const plm_options *opt) {
+    return create_impl(out, 0, nullptr, n, nnz, offsets, cols, weights, mem_kind, hip_stream, opt);
+}
+
+plm_status plm_batch_create(plm_ctx **out, int64_t num_graphs, const int64_t *node_base, int64_t nnz,
+                            const int64_t *offsets, const int32_t *cols, const int32_t *weights, int32_t mem_kind,
+                            void *hip_stream, const plm_options *opt) {
+    if (num_graphs < 1 || num_graphs >= (1LL << 31) || !node_base) {
+        g_create_error = "num_graphs must lie in [1, 2^31) and node_base must not be NULL";
+        if (out) *out = nullptr;
+        return PLM_E_ARG;
+    }
+    return create_impl(out, num_graphs, node_base, node_base[num_graphs], nnz, offsets, cols, weights, mem_kind,
+                       hip_stream, opt);
+}
+
+plm_status plm_batch_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out) {
+    return guarded(ctx, [&] {
+        if (!ctx->batch) throw Error{PLM_E_STATE, "plm_batch_run needs a context from plm_batch_create"};
+        int64_t n = ctx->n0;
+        int32_t *canon = dev_alloc<int32_t>(n);
+        try {
+            ctx->run_batch(canon, q_out, levels_out);
+            if (labels) copy_out(labels, canon, (size_t)n * 4, ctx->mem_kind, ctx->st);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+        } catch (...) {
+            dev_free(canon);
+            throw;
+        }
+        dev_free(canon);
+    });
 }
 
 plm_status plm_move_sweep(plm_ctx *ctx, int64_t *moves_out) {
@@ -649,6 +893,7 @@ plm_status plm_move_class(plm_ctx *ctx, int32_t c, int64_t *moves_out) {
 
 plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out) {
     return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_coarsen");
         int64_t k = ctx->coarsen();
         if (n_coarse_out) *n_coarse_out = k;
     });
@@ -656,6 +901,7 @@ plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out) {
 
 plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out) {
     return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_run");
         int64_t n = ctx->n0;
         int32_t *canon = dev_alloc<int32_t>(n);
         try {
@@ -676,6 +922,7 @@ plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels
 
 plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind, double *q_out) {
     return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_modularity");
         if (!labels && ctx->n0 > 0) throw Error{PLM_E_ARG, "labels is NULL"};
         if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) throw Error{PLM_E_ARG, "bad mem_kind"};
         int64_t n = ctx->n0;

@@ -1,0 +1,232 @@
+// batch.hip - kernels of batched runs: many independent graphs side by side in
+// one level, each following Algorithm 3 on its own.
+//
+// The graphs of a level occupy contiguous node ranges.  Priorities hash ids
+// local to each graph and gains use each graph's own S, so colour classes,
+// decisions, coarse ids and levels are exactly those of separate runs.  A
+// graph whose communities stop merging is finished: its input nodes receive
+// their labels and it leaves the next level.
+#include <hip/hip_runtime.h>
+
+#include "level.h"
+
+namespace plm {
+
+constexpr int kBT = 256;
+
+// out[i] = a[idx[i]]
+__global__ void k_gather_i64(const int64_t *a, const int64_t *idx, int64_t count, int64_t *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = a[idx[i]];
+}
+void launch_gather_i64(const int64_t *a, const int64_t *idx, int64_t count, int64_t *out, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_gather_i64, dim3((unsigned)cdiv(count, kBT)), dim3(kBT), 0, st, a, idx, count, out);
+    HIPCHK(hipGetLastError());
+}
+
+// flag[zeta[u]] = 1 for the nodes of kept graphs (keep == null: all nodes)
+__global__ void k_flag_kept(const int32_t *zeta, int64_t n, const int32_t *gid, const uint8_t *keep, int32_t *flag) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n && (!keep || keep[gid[u]])) flag[zeta[u]] = 1;
+}
+__global__ void k_map_kept(const int32_t *zeta, const int64_t *newid, int64_t n, const int32_t *gid,
+                           const uint8_t *keep, int32_t *pi) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) pi[u] = (!keep || keep[gid[u]]) ? (int32_t)newid[zeta[u]] : -1;
+}
+
+// Community flags of the kept graphs' nodes, their exclusive prefix sum
+// (newid[0..n], newid[n] = total) and, if pi is not null, the fine-to-coarse map.
+void batch_relabel(const int32_t *zeta, int64_t n, const int32_t *gid, const uint8_t *keep, int32_t *flag,
+                   int64_t *newid, int32_t *pi, void *scan_scratch, hipStream_t st) {
+    if (n == 0) {
+        HIPCHK(hipMemsetAsync(newid, 0, 8, st));
+        return;
+    }
+    HIPCHK(hipMemsetAsync(flag, 0, n * 4, st));
+    hipLaunchKernelGGL(k_flag_kept, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, zeta, n, gid, keep, flag);
+    exclusive_scan_i32(flag, newid, n, newid + n, scan_scratch, st);
+    if (pi) hipLaunchKernelGGL(k_map_kept, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, zeta, newid, n, gid, keep, pi);
+    HIPCHK(hipGetLastError());
+}
+
+// gid[u] = last a with base[a] <= u
+__global__ void k_fill_gid(const int64_t *base, int64_t A, int64_t n, int32_t *gid) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int64_t lo = 0, hi = A;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (base[mid] <= u) lo = mid; else hi = mid;
+    }
+    gid[u] = (int32_t)lo;
+}
+void launch_fill_gid(const int64_t *base, int64_t A, int64_t n, int32_t *gid, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_gid, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, base, A, n, gid);
+    HIPCHK(hipGetLastError());
+}
+
+// For every input node v of graph g = gid0[v], whose node at this level is
+// x = lab[v] (of active graph gid[x], first node base[gid[x]]):
+//   status[g] == 1 (finishing at this level): out[v] = zeta[x] - base[gid[x]]
+//   status[g] == 0 (continuing):              lab[v] = pi[x]
+__global__ void k_batch_step(int64_t n0, const int32_t *gid0, const uint8_t *status, const int32_t *gid,
+                             const int64_t *base, const int32_t *zeta, const int32_t *pi, int32_t *lab, int32_t *out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n0) return;
+    uint8_t s = status[gid0[v]];
+    if (s > 1) return;
+    int32_t x = lab[v];
+    if (s == 1) out[v] = (int32_t)((int64_t)zeta[x] - base[gid[x]]);
+    else lab[v] = pi[x];
+}
+void launch_batch_step(int64_t n0, const int32_t *gid0, const uint8_t *status, const int32_t *gid,
+                       const int64_t *base, const int32_t *zeta, const int32_t *pi, int32_t *lab, int32_t *out,
+                       hipStream_t st) {
+    if (n0 <= 0) return;
+    hipLaunchKernelGGL(k_batch_step, dim3((unsigned)cdiv(n0, kBT)), dim3(kBT), 0, st, n0, gid0, status, gid, base,
+                       zeta, pi, lab, out);
+    HIPCHK(hipGetLastError());
+}
+
+// Per graph a: S[a] = sum of vol over its node range and the 64-bit limit
+// wl[a] = (2^62 - 1) / S[a] of the gain arithmetic (no limit when S[a] = 0).
+__global__ __launch_bounds__(kBT) void k_graph_S(const int64_t *vol, const int64_t *base, int64_t *S, int64_t *wl) {
+    __shared__ int64_t part[kBT / 64];
+    int64_t a = blockIdx.x;
+    int64_t lo = base[a], hi = base[a + 1];
+    int64_t s = 0;
+    for (int64_t u = lo + threadIdx.x; u < hi; u += kBT) s += vol[u];
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (lane_id() == 0) part[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int i = 0; i < kBT / 64; ++i) t += part[i];
+        S[a] = t;
+        wl[a] = t > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)t) : INT64_MAX;
+    }
+}
+void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t *S, int64_t *wl, hipStream_t st) {
+    if (A <= 0) return;
+    hipLaunchKernelGGL(k_graph_S, dim3((unsigned)A), dim3(kBT), 0, st, vol, base, S, wl);
+    HIPCHK(hipGetLastError());
+}
+
+// key[v] = first input node of v's graph + local label
+__global__ void k_batch_keys(int64_t n0, const int32_t *gid0, const int64_t *gbase0, const int32_t *local,
+                             int32_t *key) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0) key[v] = (int32_t)(gbase0[gid0[v]] + local[v]);
+}
+// canonical label within the graph = global rank - rank of the graph's first node
+__global__ void k_batch_canon(int64_t n0, const int32_t *gid0, const int64_t *gbase0, const int32_t *rank,
+                              int32_t *out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0) out[v] = rank[v] - rank[gbase0[gid0[v]]];
+}
+void batch_canonical(int64_t n0, const int32_t *gid0, const int64_t *gbase0, const int32_t *local, int32_t *keys,
+                     int32_t *rank, int32_t *out, Scratch &scr, hipStream_t st) {
+    if (n0 <= 0) return;
+    hipLaunchKernelGGL(k_batch_keys, dim3((unsigned)cdiv(n0, kBT)), dim3(kBT), 0, st, n0, gid0, gbase0, local, keys);
+    build_canonical(keys, n0, rank, scr, st);
+    hipLaunchKernelGGL(k_batch_canon, dim3((unsigned)cdiv(n0, kBT)), dim3(kBT), 0, st, n0, gid0, gbase0, rank, out);
+    HIPCHK(hipGetLastError());
+}
+
+// Per-graph modularity parts on the input level: I2[g] and sum of vol(C)^2 of
+// graph g (two words, carry handled), with labels given as global keys.
+template <int WK>
+__global__ __launch_bounds__(kBT) void k_batch_intra(GraphView g, const int32_t *gid0, const int32_t *key,
+                                                      unsigned long long *I2) {
+    constexpr int kC = 16;
+    int64_t e0 = ((int64_t)blockIdx.x * kBT + threadIdx.x) * kC;
+    if (e0 >= g.nnz) return;
+    int64_t e1 = e0 + kC < g.nnz ? e0 + kC : g.nnz;
+    int64_t r = row_of(g.off, g.n, e0);
+    int64_t rend = g.off[r + 1];
+    int32_t kr = key[r];
+    int64_t s = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        while (e >= rend) {
+            if (s) atomicAdd(&I2[gid0[r]], (unsigned long long)s);
+            s = 0;
+            ++r;
+            rend = g.off[r + 1];
+            kr = key[r];
+        }
+        int32_t v = g.col[e];
+        if (key[v] == kr) {
+            int64_t x = wload<WK>(g.w, e);
+            if (v == r) x *= g.diag_mult;
+            s += x;
+        }
+    }
+    if (s) atomicAdd(&I2[gid0[r]], (unsigned long long)s);
+}
+__global__ void k_batch_vol(int64_t n0, const int32_t *key, const int64_t *vol0, int64_t *volL) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n0 && vol0[v]) atomicAdd((unsigned long long *)&volL[key[v]], (unsigned long long)vol0[v]);
+}
+__global__ void k_batch_sq(int64_t n0, const int32_t *gid0, const int64_t *volL, unsigned long long *sq) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n0 || volL[x] == 0) return;
+    unsigned __int128 q = (unsigned __int128)(uint64_t)volL[x] * (unsigned __int128)(uint64_t)volL[x];
+    uint64_t lo = (uint64_t)q, hi = (uint64_t)(q >> 64);
+    int32_t g = gid0[x];
+    unsigned long long old = atomicAdd(&sq[2 * g], (unsigned long long)lo);
+    uint64_t carry = (old + lo < old) ? 1 : 0;
+    if (hi + carry) atomicAdd(&sq[2 * g + 1], (unsigned long long)(hi + carry));
+}
+
+void batch_modularity_parts(const GraphView &g0, const int32_t *gid0, const int32_t *key, const int64_t *vol0,
+                            int64_t G, int64_t *volL, unsigned long long *I2, unsigned long long *sq,
+                            hipStream_t st) {
+    int64_t n0 = g0.n;
+    HIPCHK(hipMemsetAsync(I2, 0, (size_t)(G > 0 ? G : 1) * 8, st));
+    HIPCHK(hipMemsetAsync(sq, 0, (size_t)(G > 0 ? G : 1) * 16, st));
+    if (n0 <= 0) return;
+    HIPCHK(hipMemsetAsync(volL, 0, n0 * 8, st));
+    if (g0.nnz > 0) {
+        dim3 eg((unsigned)cdiv(cdiv(g0.nnz, 16), kBT));
+        switch (g0.wkind) {
+            case 0: hipLaunchKernelGGL(k_batch_intra<0>, eg, dim3(kBT), 0, st, g0, gid0, key, I2); break;
+            case 1: hipLaunchKernelGGL(k_batch_intra<1>, eg, dim3(kBT), 0, st, g0, gid0, key, I2); break;
+            default: hipLaunchKernelGGL(k_batch_intra<2>, eg, dim3(kBT), 0, st, g0, gid0, key, I2); break;
+        }
+    }
+    hipLaunchKernelGGL(k_batch_vol, dim3((unsigned)cdiv(n0, kBT)), dim3(kBT), 0, st, n0, key, vol0, volL);
+    hipLaunchKernelGGL(k_batch_sq, dim3((unsigned)cdiv(n0, kBT)), dim3(kBT), 0, st, n0, gid0, volL, sq);
+    HIPCHK(hipGetLastError());
+}
+
+// batched validation: every column lies in its row's graph
+__global__ void k_batch_validate(const int64_t *off, const int32_t *col, int64_t n, const int32_t *gid0,
+                                 const int64_t *gbase0, uint32_t *bad) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    int32_t g = gid0[u];
+    int64_t lo = gbase0[g], hi = gbase0[g + 1];
+    for (int64_t e = off[u]; e < off[u + 1]; ++e)
+        if (col[e] < lo || col[e] >= hi) {
+            atomicOr(bad, 32u);
+            return;
+        }
+}
+uint32_t batch_validate(const GraphView &g, const int32_t *gid0, const int64_t *gbase0, Scratch &scr,
+                        int64_t *host_i64, hipStream_t st) {
+    scr.reserve(256);
+    uint32_t *bad = (uint32_t *)scr.get(8);
+    HIPCHK(hipMemsetAsync(bad, 0, 8, st));
+    if (g.n > 0)
+        hipLaunchKernelGGL(k_batch_validate, dim3((unsigned)cdiv(g.n, kBT)), dim3(kBT), 0, st, g.off, g.col, g.n,
+                           gid0, gbase0, bad);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host_i64, bad, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return (uint32_t)(host_i64[0] & 0xffffffff);
+}
+
+}  // namespace plm

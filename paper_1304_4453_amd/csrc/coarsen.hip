@@ -57,20 +57,29 @@ int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t 
 // ------------------------------------------------------------------ contraction
 // key = (pi(u) << b) | pi(v), value = entry weight (self-loops times diag_mult,
 // so the coarse diagonal is again "doubled").
+// Rows of graphs that are not kept (batched runs) get the key 1 << 2b, which
+// sorts after every real key.
 template <int WK>
-__global__ __launch_bounds__(kT) void k_contract_keys(GraphView g, const int32_t *pi, int b, uint64_t *keys,
-                                                      int64_t *vals) {
+__global__ __launch_bounds__(kT) void k_contract_keys(GraphView g, const int32_t *pi, int b, const uint8_t *keep,
+                                                      uint64_t *keys, int64_t *vals) {
     int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * kChunk;
     if (e0 >= g.nnz) return;
     int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
     int64_t r = row_of(g.off, g.n, e0);
     int64_t rend = g.off[r + 1];
-    uint64_t pr = (uint64_t)pi[r];
+    bool kept = !keep || keep[g.gid[r]];
+    uint64_t pr = kept ? (uint64_t)pi[r] : 0;
     for (int64_t e = e0; e < e1; ++e) {
         while (e >= rend) {
             ++r;
             rend = g.off[r + 1];
-            pr = (uint64_t)pi[r];
+            kept = !keep || keep[g.gid[r]];
+            pr = kept ? (uint64_t)pi[r] : 0;
+        }
+        if (!kept) {
+            keys[e] = 1ULL << (2 * b);
+            vals[e] = 0;
+            continue;
         }
         int32_t v = g.col[e];
         int64_t x = wload<WK>(g.w, e);
@@ -141,7 +150,8 @@ __global__ void k_coarse_csr(const uint64_t *ukeys, int64_t m, int b, int64_t k,
 }
 
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff_out, int32_t **ccol_out,
-                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st) {
+                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st, const uint8_t *keep,
+                          int64_t nnz_kept) {
     int64_t nnz = g.nnz;
     int b = ceil_log2((uint64_t)(k > 1 ? k : 2));
     int64_t nb = nnz > 0 ? nnz : 1;
@@ -177,11 +187,21 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
     }
     dim3 grid((unsigned)cdiv(cdiv(nnz, kChunk), kT));
     switch (g.wkind) {
-        case 0: hipLaunchKernelGGL(k_contract_keys<0>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
-        case 1: hipLaunchKernelGGL(k_contract_keys<1>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
-        default: hipLaunchKernelGGL(k_contract_keys<2>, grid, dim3(kT), 0, st, g, pi, b, ka, va); break;
+        case 0: hipLaunchKernelGGL(k_contract_keys<0>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
+        case 1: hipLaunchKernelGGL(k_contract_keys<1>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
+        default: hipLaunchKernelGGL(k_contract_keys<2>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
     }
-    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b, tmp, st);
+    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b + (keep ? 1 : 0), tmp, st);
+    if (keep) nnz = nnz_kept;  // the dropped rows' entries sorted last
+    if (nnz == 0) {
+        HIPCHK(hipMemsetAsync(coff, 0, (k + 1) * 8, st));
+        e = hipMalloc(&ccol, 4);
+        if (e != hipSuccess) fail(e);
+        e = hipMalloc(&cw, 8);
+        if (e != hipSuccess) fail(e);
+        *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
+        return 0;
+    }
     hipLaunchKernelGGL(k_head_flags, dim3((unsigned)cdiv(nnz, kT)), dim3(kT), 0, st, ka, nnz, head);
     exclusive_scan_i32(head, excl, nnz, total, tmp, st);
     HIPCHK(hipMemcpyAsync(host_i64, total, 8, hipMemcpyDeviceToHost, st));

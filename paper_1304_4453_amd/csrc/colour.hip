@@ -43,7 +43,8 @@ __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, 
     int64_t e1 = e0 + kCChunk < g.nnz ? e0 + kCChunk : g.nnz;
     int64_t r = row_of(g.off, g.n, e0);
     int64_t rend = g.off[r + 1];
-    uint64_t hr = prio_hash(seed, level, r);
+    int64_t br = node_base(g, r);
+    uint64_t hr = prio_hash(seed, level, r - br);
     int32_t cnt = 0;
     for (int64_t e = e0; e < e1; ++e) {
         while (e >= rend) {
@@ -51,10 +52,11 @@ __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, 
             cnt = 0;
             ++r;
             rend = g.off[r + 1];
-            hr = prio_hash(seed, level, r);
+            br = node_base(g, r);
+            hr = prio_hash(seed, level, r - br);
         }
         int64_t v = g.col[e];
-        if (v != r && prio_greater(prio_hash(seed, level, v), v, hr, r)) ++cnt;
+        if (v != r && prio_greater(prio_hash(seed, level, v - br), v, hr, r)) ++cnt;
     }
     if (cnt) atomicAdd(&pending[r], cnt);
 }
@@ -131,13 +133,14 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
                                                     uint64_t hu, const int32_t *colour, uint32_t *bm,
                                                     int32_t base0) {
     int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    const int64_t bu = node_base(g, u);
     for (int32_t base = base0;; base += kWin) {
         for (int j = lane_id(); j < kWinWords; j += kWave) bm[j] = 0;
         wave_sync();
         for (int64_t e = e0 + lane_id(); e < e1; e += kWave) {
             int32_t v = g.col[e];
             if (v == u) continue;
-            if (prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+            if (prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
                 int32_t c = colour[v] - base;
                 if (c >= 0 && c < kWin) atomicOr(&bm[c >> 5], 1u << (c & 31));
             }
@@ -163,12 +166,13 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
     // one lane per node
     for (int64_t i = gtid; i < ns; i += gthreads) {
         int32_t u = Q.q[set][0][i];
-        uint64_t hu = prio_hash(seed, level, u);
+        const int64_t bu = node_base(g, u);
+        uint64_t hu = prio_hash(seed, level, u - bu);
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         uint64_t used = 0;  // row length <= 32 bounds the answer below 33
         for (int64_t e = e0; e < e1; ++e) {
             int32_t v = g.col[e];
-            if (v != u && prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+            if (v != u && prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
                 int32_t c = colour[v];
                 if (c < 64) used |= 1ULL << c;
             }
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
         ++coloured;
         for (int64_t e = e0; e < e1; ++e) {
             int32_t v = g.col[e];
-            if (v != u && !prio_greater(prio_hash(seed, level, v), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
+            if (v != u && !prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
         }
     }
     count_coloured(Q, coloured);
@@ -188,7 +192,8 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
     const int w = threadIdx.x / kWave;
     for (int64_t i = (int64_t)blockIdx.x * (kCT / kWave) + w; i < nm; i += (int64_t)gridDim.x * (kCT / kWave)) {
         int32_t u = Q.q[set][1][i];
-        uint64_t hu = prio_hash(seed, level, u);
+        const int64_t bu = node_base(g, u);
+        uint64_t hu = prio_hash(seed, level, u - bu);
         int32_t c = wave_colour_scan(g, seed, level, u, hu, colour, wbm[w], 0);
         if (lane_id() == 0) {
             colour[u] = c;
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
         }
         for (int64_t e = g.off[u] + lane_id(); e < g.off[u + 1]; e += kWave) {
             int32_t v = g.col[e];
-            if (v != u && !prio_greater(prio_hash(seed, level, v), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
+            if (v != u && !prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
         }
     }
     // several workgroups per node.  nh <= grid: hub j takes the workgroups
@@ -210,14 +215,15 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             const int64_t k = spread ? (int64_t)blockIdx.x / nh : 0;
             const int64_t nk = spread ? (G - j + nh - 1) / nh : 1;
             int32_t u = Q.q[set][2][j];
-            uint64_t hu = prio_hash(seed, level, u);
+            const int64_t bu = node_base(g, u);
+            uint64_t hu = prio_hash(seed, level, u - bu);
             int64_t e0 = g.off[u], e1 = g.off[u + 1];
             for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
             __syncthreads();
             for (int64_t e = e0 + k * kCT + threadIdx.x; e < e1; e += nk * kCT) {
                 int32_t v = g.col[e];
                 if (v == u) continue;
-                if (prio_greater(prio_hash(seed, level, v), v, hu, u)) {
+                if (prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
                     int32_t c = colour[v];
                     if (c < kWin) atomicOr(&bbm[c >> 5], 1u << (c & 31));
                 } else {
@@ -247,7 +253,8 @@ __global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, i
         wave_sync();
         for (int i = lane_id(); i < kWinWords; i += kWave) bm[i] = 0;
         int32_t u = Q.q[set][2][j];
-        if (c < 0) c = wave_colour_scan(g, seed, level, u, prio_hash(seed, level, u), colour, wbm[w], kWin);
+        if (c < 0)
+            c = wave_colour_scan(g, seed, level, u, prio_hash(seed, level, u - node_base(g, u)), colour, wbm[w], kWin);
         if (lane_id() == 0) {
             colour[u] = c;
             atomicMax(&Q.cnt[12], c + 1);

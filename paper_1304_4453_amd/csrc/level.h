@@ -31,7 +31,16 @@ struct MoveState {
     int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
     unsigned long long *moves_dev;  // move counter
     unsigned long long *cand_dev;   // distinct candidates evaluated per bin [4] (may be null)
+    // batched runs: graph of each node, and per graph S and the 64-bit limit
+    const int32_t *gid = nullptr;
+    const int64_t *gS = nullptr;
+    const int64_t *gwl = nullptr;
 };
+
+__device__ __forceinline__ int64_t node_S(const MoveState &ms, int32_t u) { return ms.gid ? ms.gS[ms.gid[u]] : ms.S; }
+__device__ __forceinline__ int64_t node_wl(const MoveState &ms, int32_t u) {
+    return ms.gid ? ms.gwl[ms.gid[u]] : ms.wide_lim;
+}
 
 // One class step: decide (per bin) then apply.  Counts (bin sizes) come from
 // the host copy of the bucket starts.
@@ -73,8 +82,11 @@ int64_t build_relabel(const int32_t *zeta, int64_t n, int32_t *pi, Scratch &scr,
                       hipStream_t st);
 // Contracts g by pi into a coarse CSR (doubled diagonal, int64 weights, rows
 // ascending).  Allocates *coff/*ccol/*cw with hipMalloc.  Returns nnz'.
+// keep (batched runs, else null): rows of graphs not kept are dropped; they
+// hold all but nnz_kept of the entries.
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff, int32_t **ccol,
-                          int64_t **cw, Scratch &scr, int64_t *host_i64, hipStream_t st);
+                          int64_t **cw, Scratch &scr, int64_t *host_i64, hipStream_t st,
+                          const uint8_t *keep = nullptr, int64_t nnz_kept = 0);
 // lab[v] = map[lab[v]] for v < n
 void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st);
 void launch_iota(int32_t *a, int64_t n, hipStream_t st);
@@ -89,5 +101,21 @@ int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *la
 int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t *host_i64, hipStream_t st);
 // validation of an input CSR; returns 0 or an error code bit set
 uint32_t validate_graph(const GraphView &g, Scratch &scr, int64_t *host_i64, hipStream_t st);
+
+// ---- batch.hip
+void launch_gather_i64(const int64_t *a, const int64_t *idx, int64_t count, int64_t *out, hipStream_t st);
+void batch_relabel(const int32_t *zeta, int64_t n, const int32_t *gid, const uint8_t *keep, int32_t *flag,
+                   int64_t *newid, int32_t *pi, void *scan_scratch, hipStream_t st);
+void launch_fill_gid(const int64_t *base, int64_t A, int64_t n, int32_t *gid, hipStream_t st);
+void launch_batch_step(int64_t n0, const int32_t *gid0, const uint8_t *status, const int32_t *gid,
+                       const int64_t *base, const int32_t *zeta, const int32_t *pi, int32_t *lab, int32_t *out,
+                       hipStream_t st);
+void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t *S, int64_t *wl, hipStream_t st);
+void batch_canonical(int64_t n0, const int32_t *gid0, const int64_t *gbase0, const int32_t *local, int32_t *keys,
+                     int32_t *rank, int32_t *out, Scratch &scr, hipStream_t st);
+void batch_modularity_parts(const GraphView &g0, const int32_t *gid0, const int32_t *key, const int64_t *vol0,
+                            int64_t G, int64_t *volL, unsigned long long *I2, unsigned long long *sq, hipStream_t st);
+uint32_t batch_validate(const GraphView &g, const int32_t *gid0, const int64_t *gbase0, Scratch &scr,
+                        int64_t *host_i64, hipStream_t st);
 
 }  // namespace plm

@@ -127,8 +127,9 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
         }
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
-        int32_t bx = (force_wide || vu > ms.wide_lim) ? lane_pick<WK, i128>(X, W, D, wD, vu, base, ms.S, ms.volC)
-                                                      : lane_pick<WK, int64_t>(X, W, D, wD, vu, base, ms.S, ms.volC);
+        const int64_t S_u = node_S(ms, u);
+        int32_t bx = (force_wide || vu > node_wl(ms, u)) ? lane_pick<WK, i128>(X, W, D, wD, vu, base, S_u, ms.volC)
+                                                         : lane_pick<WK, int64_t>(X, W, D, wD, vu, base, S_u, ms.volC);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 0 : nullptr, ncand);
@@ -230,10 +231,11 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         int64_t base = ms.volC[D] - vu;
         int32_t bx;
         bool mv;
-        if (force_wide || vu > ms.wide_lim)
-            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, vu, base, ms.S, ms.volC, bx, mv, ncand);
+        const int64_t S_u = node_S(ms, u);
+        if (force_wide || vu > node_wl(ms, u))
+            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, vu, base, S_u, ms.volC, bx, mv, ncand);
         else
-            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu, base, ms.S, ms.volC, bx, mv, ncand);
+            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu, base, S_u, ms.volC, bx, mv, ncand);
         if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
         wave_sync();
     }
@@ -297,10 +299,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
         __syncthreads();
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
-        if (force_wide || vu > ms.wide_lim)
-            block_eval<i128>(tk, tv, 1 << bits, myD, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+        const int64_t S_u = node_S(ms, u);
+        if (force_wide || vu > node_wl(ms, u))
+            block_eval<i128>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
         else
-            block_eval<int64_t>(tk, tv, 1 << bits, myD, vu, base, ms.S, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<int64_t>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
         __syncthreads();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
@@ -566,12 +569,13 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
-    if (force_wide || vu > ms.wide_lim) {
-        agg_bucket<i128>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ncand);
+    const int64_t S_u = node_S(ms, u);
+    if (force_wide || vu > node_wl(ms, u)) {
+        agg_bucket<i128>(ha, hg, p, vu, S_u, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ncand);
         block_argmax<i128>(bs, bx);
     } else {
         int64_t b64 = neg_inf<int64_t>();
-        agg_bucket<int64_t>(ha, hg, p, vu, ms.S, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
+        agg_bucket<int64_t>(ha, hg, p, vu, S_u, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
                             ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
@@ -612,7 +616,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArr
         int32_t D = ms.zeta[u];
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
-        i128 K = (i128)ms.S * (i128)wD - (i128)vu * (i128)base;
+        i128 K = (i128)node_S(ms, u) * (i128)wD - (i128)vu * (i128)base;
         ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
     }
 }

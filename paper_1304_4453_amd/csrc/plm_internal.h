@@ -73,7 +73,14 @@ struct GraphView {
     const void *w = nullptr;  // nullptr when wkind == 0
     int wkind = 0;            // 0 unit, 1 int32, 2 int64
     int diag_mult = 1;        // 2: self-loop entries hold w(u,u) (input level); 1: they hold 2 w(u,u)
+    // several graphs side by side (batched runs): graph of each node and the
+    // first node of each graph; null for a single graph
+    const int32_t *gid = nullptr;
+    const int64_t *gbase = nullptr;
 };
+
+// first node of u's graph (priorities hash the id local to the graph)
+__device__ __forceinline__ int64_t node_base(const GraphView &g, int64_t u) { return g.gid ? g.gbase[g.gid[u]] : 0; }
 
 // ------------------------------------------------------------------ error type
 struct Error {

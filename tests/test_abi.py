@@ -95,7 +95,41 @@ def test_argument_errors_need_no_gpu(built):
     assert P.plm_coarsen(None, None) == P.PLM_E_ARG
     assert P.plm_run(None, None, None, None) == P.PLM_E_ARG
     assert P.plm_modularity(None, None, 0, None) == P.PLM_E_ARG
+    assert P.plm_batch_run(None, None, None, None) == P.PLM_E_ARG
     P.plm_destroy(None)
+    # batched contexts: graph ranges and options are checked before any HIP call
+    nb = np.array([0, 1], np.int64)
+    assert P.plm_batch_create(ctypes.byref(c), 0, nb.ctypes.data, 0, off.ctypes.data, col.ctypes.data, None, 0,
+                              None, None) == P.PLM_E_ARG
+    assert P.plm_batch_create(ctypes.byref(c), 1, None, 0, off.ctypes.data, col.ctypes.data, None, 0, None,
+                              None) == P.PLM_E_ARG
+    nb_bad = np.array([1, 1], np.int64)
+    assert P.plm_batch_create(ctypes.byref(c), 1, nb_bad.ctypes.data, 0, off.ctypes.data, col.ctypes.data, None,
+                              0, None, None) == P.PLM_E_ARG
+    seq = P.default_options(schedule=P.PLM_SCHEDULE_SEQUENTIAL)
+    assert P.plm_batch_create(ctypes.byref(c), 1, nb.ctypes.data, 0, off.ctypes.data, col.ctypes.data, None, 0,
+                              None, ctypes.byref(seq)) == P.PLM_E_ARG
+    i64 = P.default_options(int_mode=P.PLM_INT_64)
+    assert P.plm_batch_create(ctypes.byref(c), 1, nb.ctypes.data, 0, off.ctypes.data, col.ctypes.data, None, 0,
+                              None, ctypes.byref(i64)) == P.PLM_E_ARG
+    assert not c.value
+
+
+def test_pack_batch_is_the_disjoint_union(built):
+    import numpy as np
+    import graphgen
+    import paper_1304_4453_amd as P
+    gs = [graphgen.disjoint_cliques(2, 3), graphgen.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32), None),
+          graphgen.random_graph(10, 0.3, seed=1), graphgen.from_edges(3, [])]
+    nb, off, col, w = P.pack_batch(gs)
+    assert nb.tolist() == [0, 6, 6, 16, 19] and off[0] == 0 and off[-1] == sum(g.nnz for g in gs)
+    for i, g in enumerate(gs):
+        a, b = int(nb[i]), int(nb[i + 1])
+        assert np.array_equal(off[a:b + 1] - off[a], g.off)
+        assert np.array_equal(col[off[a]:off[b]] - a, g.col)
+        assert np.array_equal(w[off[a]:off[b]], np.ones(g.nnz) if g.w is None else g.w)
+    nb, off, col, w = P.pack_batch([graphgen.disjoint_cliques(1, 3)] * 2)
+    assert w is None and col.tolist() == [1, 2, 0, 2, 0, 1, 4, 5, 3, 5, 3, 4]
 
 
 def test_product_has_no_oracle_dependency():
