@@ -131,7 +131,9 @@ struct plm_ctx {
             *wd_part = nullptr;
     uint32_t *bkt = nullptr;
     unsigned long long *part = nullptr;
-    int64_t cap_hubs = 0, cap_stg = 0, cap_bkt = 0, cap_ins = 0, cap_agg = 0;
+    int32_t *hub_u = nullptr, *ins_hub = nullptr, *agg_hub = nullptr, *sgl_hub = nullptr, *red_hub = nullptr;
+    int64_t cap_hubs = 0, cap_stg = 0, cap_bkt = 0, cap_ins = 0, cap_agg = 0, cap_hubu = 0, cap_ihub = 0,
+            cap_ahub = 0, cap_shub = 0, cap_rhub = 0;
     int32_t sweeps = 0;
     // device counters: [0] moves, [1..4] candidates per bin, [5] S, [6] max vol,
     // [7] loop-only rows, [8..11] entries per bin
@@ -171,8 +173,9 @@ struct plm_ctx {
     void free_hubs() {
         dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(stg_x); dev_free(ins_first);
         dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part);
-        dev_free(bkt); dev_free(part);
-        cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = 0;
+        dev_free(bkt); dev_free(part); dev_free(hub_u); dev_free(ins_hub); dev_free(agg_hub); dev_free(sgl_hub);
+        dev_free(red_hub);
+        cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = cap_hubu = cap_ihub = cap_ahub = cap_shub = cap_rhub = 0;
     }
 
     LevelData &L() { return levels[cur]; }
@@ -223,7 +226,11 @@ struct plm_ctx {
     }
 
     // grow-only device arrays of the hub plan
-    void ensure_hub_capacity(int64_t hubs, int64_t stg, int64_t bk, int64_t ins, int64_t agg) {
+    void ensure_hub_nodes(int64_t hubs) {
+        if (hubs > cap_hubu) { dev_free(hub_u); hub_u = dev_alloc<int32_t>(hubs); cap_hubu = hubs; }
+    }
+    void ensure_hub_capacity(int64_t hubs, int64_t stg, int64_t bk, int64_t ins, int64_t agg, int64_t ins_tot,
+                             int64_t agg_tot, int64_t sgl_tot, int64_t red_tot) {
         if (hubs > cap_hubs) {
             dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
             dev_free(stg_off); dev_free(bkt_off);
@@ -240,6 +247,10 @@ struct plm_ctx {
         if (bk > cap_bkt) { dev_free(bkt); bkt = dev_alloc<uint32_t>(bk); cap_bkt = bk; }
         if (ins > cap_ins) { dev_free(wd_part); wd_part = dev_alloc<int64_t>(ins); cap_ins = ins; }
         if (agg > cap_agg) { dev_free(part); part = dev_alloc<unsigned long long>(4 * agg); cap_agg = agg; }
+        if (ins_tot > cap_ihub) { dev_free(ins_hub); ins_hub = dev_alloc<int32_t>(ins_tot); cap_ihub = ins_tot; }
+        if (agg_tot > cap_ahub) { dev_free(agg_hub); agg_hub = dev_alloc<int32_t>(agg_tot); cap_ahub = agg_tot; }
+        if (sgl_tot > cap_shub) { dev_free(sgl_hub); sgl_hub = dev_alloc<int32_t>(sgl_tot); cap_shub = sgl_tot; }
+        if (red_tot > cap_rhub) { dev_free(red_hub); red_hub = dev_alloc<int32_t>(red_tot); cap_rhub = red_tot; }
     }
 
     void build_schedule() {
@@ -255,8 +266,8 @@ struct plm_ctx {
         dev_free(bstart_dev);
         bstart_dev = dev_alloc<int64_t>(nkeys + 1);
         HIPCHK(hipMemsetAsync(dcnt + 7, 0, 5 * 8, st));
-        build_buckets(g, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, dcnt + 8, scr,
-                      st);
+        build_buckets(g, vol, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, dcnt + 8,
+                      scr, st);
         bstart.assign(nkeys + 1, 0);
         if (l.n > 0) HIPCHK(hipMemcpyAsync(bstart.data(), bstart_dev, (nkeys + 1) * 8, hipMemcpyDeviceToHost, st));
         // active entries = nnz minus rows made of a single self-loop
@@ -278,22 +289,27 @@ struct plm_ctx {
         std::vector<int64_t> deg(H > 0 ? H : 1), pos;
         pos.reserve(H);
         if (H > 0) {
+            ensure_hub_nodes(H);
             scr.reserve(align_up(H * 8));
             int64_t *ddeg = (int64_t *)scr.get(H * 8);
             int64_t o = 0;
             for (int32_t c = 0; c < ncol; ++c) {
                 int64_t b = bstart[4 * c + 3], cnt = bstart[4 * c + 4] - b;
-                if (cnt > 0) launch_hub_degrees(g, class_nodes, b, cnt, ddeg + o, st);
+                if (cnt > 0) launch_hub_degrees(g, class_nodes, vol, b, cnt, ddeg + o, hub_u + o, st);
                 for (int64_t i = 0; i < cnt; ++i) pos.push_back(b + i);
                 o += cnt;
             }
             HIPCHK(hipMemcpyAsync(deg.data(), ddeg, H * 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
         }
-        // per hub: chunks of kHubInsChunk entries, 2^pbits buckets of ~kHubBucketTarget
-        // entries, staging and (bucket, chunk) table offsets within its class
-        std::vector<int32_t> hpos(H > 0 ? H : 1), hch(H > 0 ? H : 1), hpb(H > 0 ? H : 1);
-        std::vector<int64_t> hins(H > 0 ? H : 1), hagg(H > 0 ? H : 1), hstg(H > 0 ? H : 1), hbk(H > 0 ? H : 1);
+        // per hub: one workgroup (rows up to kSingleMaxRow with vol(u) < 2^31), or
+        // chunks of kHubInsChunk entries and 2^pbits buckets of ~kHubBucketTarget
+        // entries with staging and (bucket, chunk) table offsets within its class;
+        // per workgroup of each launch: its hub
+        std::vector<int32_t> hpos(H > 0 ? H : 1), hch(H > 0 ? H : 1, 0), hpb(H > 0 ? H : 1, 0), shub, rhub, ihub,
+            ahub;
+        std::vector<int64_t> hins(H > 0 ? H : 1, 0), hagg(H > 0 ? H : 1, 0), hstg(H > 0 ? H : 1, 0),
+            hbk(H > 0 ? H : 1, 0);
         int64_t max_stg = 0, max_bk = 0, max_ins = 0, max_agg = 0, hg = 0;
         for (int32_t c = 0; c < ncol; ++c) {
             ClassRange &cr = classes[c];
@@ -303,23 +319,37 @@ struct plm_ctx {
             }
             cr.hub_first = hg;
             cr.hub_count = cr.count[3];
+            cr.sgl_base = (int64_t)shub.size();
+            cr.red_base = (int64_t)rhub.size();
+            cr.ins_base = (int64_t)ihub.size();
+            cr.agg_base = (int64_t)ahub.size();
             int64_t stg = 0, bk = 0, ins = 0, agg = 0;
             for (int64_t i = 0; i < cr.hub_count; ++i, ++hg) {
-                int64_t ch = cdiv(deg[hg], kHubInsChunk);
-                int pb = ceil_log2((uint64_t)cdiv(deg[hg], kHubBucketTarget));
-                if (pb > kHubMaxPBits) pb = kHubMaxPBits;
                 hpos[hg] = (int32_t)pos[hg];
+                int64_t d = deg[hg] < 0 ? -deg[hg] : deg[hg];
+                if (deg[hg] > 0 && d <= kSingleMaxRow) {
+                    shub.push_back((int32_t)hg);
+                    continue;
+                }
+                rhub.push_back((int32_t)hg);
+                int64_t ch = cdiv(d, kHubInsChunk);
+                int pb = ceil_log2((uint64_t)cdiv(d, kHubBucketTarget));
+                if (pb > kHubMaxPBits) pb = kHubMaxPBits;
                 hch[hg] = (int32_t)ch;
                 hpb[hg] = pb;
                 hins[hg] = ins;
                 hagg[hg] = agg;
                 hstg[hg] = stg;
                 hbk[hg] = bk;
+                ihub.insert(ihub.end(), (size_t)ch, (int32_t)hg);
+                ahub.insert(ahub.end(), (size_t)1 << pb, (int32_t)hg);
                 ins += ch;
                 agg += 1LL << pb;
                 stg += ch * kHubInsChunk;
                 bk += ch << pb;
             }
+            cr.sgl_count = (int64_t)shub.size() - cr.sgl_base;
+            cr.red_count = (int64_t)rhub.size() - cr.red_base;
             cr.ins_blocks = ins;
             cr.agg_blocks = agg;
             max_stg = stg > max_stg ? stg : max_stg;
@@ -328,7 +358,8 @@ struct plm_ctx {
             max_agg = agg > max_agg ? agg : max_agg;
         }
         if (H > 0) {
-            ensure_hub_capacity(H, max_stg, max_bk, max_ins, max_agg);
+            ensure_hub_capacity(H, max_stg, max_bk, max_ins, max_agg, (int64_t)ihub.size(), (int64_t)ahub.size(),
+                                (int64_t)shub.size(), (int64_t)rhub.size());
             HIPCHK(hipMemcpyAsync(hub_pos, hpos.data(), H * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(nchunk, hch.data(), H * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(pbits, hpb.data(), H * 4, hipMemcpyHostToDevice, st));
@@ -336,6 +367,10 @@ struct plm_ctx {
             HIPCHK(hipMemcpyAsync(agg_first, hagg.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(stg_off, hstg.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(bkt_off, hbk.data(), H * 8, hipMemcpyHostToDevice, st));
+            if (!ihub.empty()) HIPCHK(hipMemcpyAsync(ins_hub, ihub.data(), ihub.size() * 4, hipMemcpyHostToDevice, st));
+            if (!ahub.empty()) HIPCHK(hipMemcpyAsync(agg_hub, ahub.data(), ahub.size() * 4, hipMemcpyHostToDevice, st));
+            if (!shub.empty()) HIPCHK(hipMemcpyAsync(sgl_hub, shub.data(), shub.size() * 4, hipMemcpyHostToDevice, st));
+            if (!rhub.empty()) HIPCHK(hipMemcpyAsync(red_hub, rhub.data(), rhub.size() * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
@@ -355,7 +390,9 @@ struct plm_ctx {
     }
     HubArrays hub_arrays() {
         HubArrays ha;
-        ha.hub_pos = hub_pos; ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
+        ha.hub_pos = hub_pos; ha.hub_u = hub_u; ha.sgl_hub = sgl_hub; ha.red_hub = red_hub; ha.ins_hub = ins_hub;
+        ha.agg_hub = agg_hub;
+        ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
         ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
         ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part;
         return ha;
@@ -386,7 +423,8 @@ struct plm_ctx {
                     float t = 0;
                     HIPCHK(hipEventElapsedTime(&t, events[5 * (size_t)c + b], events[5 * (size_t)c + b + 1]));
                     bin_t[b] += t;
-                    launches += classes[c].count[b] > 0 ? (b == 3 ? 2 : 1) : 0;
+                    if (b < 3) launches += classes[c].count[b] > 0 ? 1 : 0;
+                    else launches += (classes[c].sgl_count > 0 ? 1 : 0) + (classes[c].red_count > 0 ? 3 : 0);
                 }
             }
             // algorithmic bytes (whole sweeps only): per entry the column, the

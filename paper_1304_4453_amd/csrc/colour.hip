@@ -11,11 +11,13 @@
 // Rounds run back to back on the device: each round is one launch over
 // triple-buffered queues (round r reads set r%3, pushes into set (r+1)%3 and
 // clears set (r+2)%3), so the host only checks for an empty frontier every few
-// rounds.  Frontier nodes are split by row length: one lane per node (<= 32
+// rounds.  Frontier nodes are split by row length: eight lanes per node (<= 32
 // entries), one wavefront per node (<= 1024), and several workgroups per node
 // above that; the latter OR the colours they see into a block-local LDS bitmap,
 // merge it into a per-node global bitmap, and a second launch per round picks
-// the smallest free colour.
+// the smallest free colour.  A round is bound by latency (its frontier is
+// often small), so every lane loads a batch of entries before it gathers their
+// colours, instead of walking a row one dependent load after another.
 #include <hip/hip_runtime.h>
 
 #include "level.h"
@@ -24,7 +26,7 @@ namespace plm {
 
 constexpr int kCT = 256;                  // threads per workgroup
 constexpr int kCChunk = 16;               // entries per thread (pending counts)
-constexpr int64_t kLaneRow = 32;          // row length handled by one lane
+constexpr int64_t kLaneRow = 32;          // row length handled by eight lanes
 constexpr int64_t kWaveRow = 1024;        // row length handled by one wavefront
 constexpr int kWin = 4096;                // colour window of a bitmap (bits)
 constexpr int kWinWords = kWin / 32;
@@ -137,12 +139,19 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
     for (int32_t base = base0;; base += kWin) {
         for (int j = lane_id(); j < kWinWords; j += kWave) bm[j] = 0;
         wave_sync();
-        for (int64_t e = e0 + lane_id(); e < e1; e += kWave) {
-            int32_t v = g.col[e];
-            if (v == u) continue;
-            if (prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
-                int32_t c = colour[v] - base;
-                if (c >= 0 && c < kWin) atomicOr(&bm[c >> 5], 1u << (c & 31));
+        // four entries per lane at a time: the column loads, then the colour
+        // gathers of a batch are in flight together
+        for (int64_t e = e0 + lane_id(); e < e1; e += 4 * kWave) {
+            int32_t v[4], c[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = e + j * kWave < e1 ? g.col[e + j * kWave] : u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                c[j] = (v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u)) ? colour[v[j]] : -1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int32_t x = c[j] - base;
+                if (c[j] >= 0 && x >= 0 && x < kWin) atomicOr(&bm[x >> 5], 1u << (x & 31));
             }
         }
         wave_sync();
@@ -163,47 +172,87 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
     const int64_t gtid = (int64_t)blockIdx.x * kCT + threadIdx.x;
     int64_t coloured = 0;
     int32_t maxc = 0;  // 1 + largest colour given by this thread
-    // one lane per node
-    for (int64_t i = gtid; i < ns; i += gthreads) {
+    // eight lanes per node (rows of at most 32 entries: four per lane, loaded
+    // together); the colours seen are OR-ed over the eight lanes
+    const int sub = (int)(threadIdx.x & 7);
+    for (int64_t i = gtid >> 3; i < ns; i += gthreads >> 3) {
         int32_t u = Q.q[set][0][i];
         const int64_t bu = node_base(g, u);
         uint64_t hu = prio_hash(seed, level, u - bu);
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
-        uint64_t used = 0;  // row length <= 32 bounds the answer below 33
-        for (int64_t e = e0; e < e1; ++e) {
-            int32_t v = g.col[e];
-            if (v != u && prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
-                int32_t c = colour[v];
-                if (c < 64) used |= 1ULL << c;
-            }
+        int32_t v[4];
+        bool hi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t e = e0 + sub + 8 * j;
+            v[j] = e < e1 ? g.col[e] : u;
         }
-        int32_t c = __builtin_ctzll(~used);
-        colour[u] = c;
-        maxc = c + 1 > maxc ? c + 1 : maxc;
-        ++coloured;
-        for (int64_t e = e0; e < e1; ++e) {
-            int32_t v = g.col[e];
-            if (v != u && !prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hi[j] = v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u);
+        int32_t c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = hi[j] ? colour[v[j]] : 64;
+        uint64_t used = 0;  // at most 32 higher neighbours: the answer is below 33
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (c[j] < 64) used |= 1ULL << c[j];
+#pragma unroll
+        for (int d = 1; d < 8; d <<= 1) used |= __shfl_xor(used, d);
+        int32_t cu = __builtin_ctzll(~used);
+        if (sub == 0) {
+            colour[u] = cu;
+            maxc = cu + 1 > maxc ? cu + 1 : maxc;
+            ++coloured;
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (v[j] != u && !hi[j]) jp_release(Q, nxt, v[j], pending, g.off);
     }
     count_coloured(Q, coloured);
     wave_max_colour(Q, maxc);
-    // one wavefront per node
+    // one wavefront per node: a row of up to kWaveRow entries is held in
+    // registers (kWaveRow / 64 per lane), its colours gathered in one batch and
+    // its lower-priority neighbours released from the same registers
     const int w = threadIdx.x / kWave;
     for (int64_t i = (int64_t)blockIdx.x * (kCT / kWave) + w; i < nm; i += (int64_t)gridDim.x * (kCT / kWave)) {
         int32_t u = Q.q[set][1][i];
         const int64_t bu = node_base(g, u);
         uint64_t hu = prio_hash(seed, level, u - bu);
-        int32_t c = wave_colour_scan(g, seed, level, u, hu, colour, wbm[w], 0);
+        const int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        constexpr int kPer = (int)(kWaveRow / kWave);
+        int32_t v[kPer], c[kPer];
+        uint32_t hi = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            int64_t e = e0 + lane_id() + (int64_t)j * kWave;
+            v[j] = e < e1 ? g.col[e] : u;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u)) hi |= 1u << j;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) c[j] = (hi >> j) & 1u ? colour[v[j]] : -1;
+        int32_t f = -1;
+        for (int32_t base = 0; f < 0; base += kWin) {
+            for (int j = lane_id(); j < kWinWords; j += kWave) wbm[w][j] = 0;
+            wave_sync();
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                int32_t x = c[j] - base;
+                if (c[j] >= 0 && x >= 0 && x < kWin) atomicOr(&wbm[w][x >> 5], 1u << (x & 31));
+            }
+            wave_sync();
+            f = wave_first_free(wbm[w], base);
+            wave_sync();
+        }
         if (lane_id() == 0) {
-            colour[u] = c;
-            atomicMax(&Q.cnt[12], c + 1);
+            colour[u] = f;
+            atomicMax(&Q.cnt[12], f + 1);
             atomicAdd(&Q.cnt[13], 1);
         }
-        for (int64_t e = g.off[u] + lane_id(); e < g.off[u + 1]; e += kWave) {
-            int32_t v = g.col[e];
-            if (v != u && !prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) jp_release(Q, nxt, v, pending, g.off);
-        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (v[j] != u && !((hi >> j) & 1u)) jp_release(Q, nxt, v[j], pending, g.off);
     }
     // several workgroups per node.  nh <= grid: hub j takes the workgroups
     // b = j, j + nh, j + 2 nh, ... (part k of nk); nh > grid: workgroup b takes

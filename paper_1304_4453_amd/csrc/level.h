@@ -16,9 +16,11 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
 // receives bucket starts (bucket 4c+b = bin b of class c; bucket 4*ncol holds
 // nodes that cannot move).
 // bin_entries[4]: CSR entries of the movable nodes of each bin (added to).
-void build_buckets(const GraphView &g, const int32_t *colour, int32_t ncol, int64_t b0, int64_t b1, int64_t b2,
-                   int32_t *class_nodes, int64_t *bstart_dev, unsigned long long *bin_entries, Scratch &scr,
-                   hipStream_t st);
+// Nodes of the wave and block bins whose vol(u) does not fit 32 bits go to the
+// hub bin (the tables of those bins sum in 32 bits).
+void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
+                   int64_t b1, int64_t b2, int32_t *class_nodes, int64_t *bstart_dev,
+                   unsigned long long *bin_entries, Scratch &scr, hipStream_t st);
 
 // ---- move.hip
 struct MoveState {
@@ -49,10 +51,19 @@ struct ClassRange {
     // hubs of this class in the level's hub arrays
     int64_t hub_first = 0, hub_count = 0;
     int64_t ins_blocks = 0, agg_blocks = 0;
+    // first entries of this class in the level's per-workgroup hub lists:
+    // single-workgroup hubs, partitioned hubs (reduce), their chunk and bucket
+    // workgroups
+    int64_t sgl_base = 0, sgl_count = 0, red_base = 0, red_count = 0, ins_base = 0, agg_base = 0;
 };
 
 struct HubArrays {
     const int32_t *hub_pos;    // class position of each hub
+    const int32_t *hub_u;      // node of each hub
+    const int32_t *sgl_hub;    // hubs taken by one workgroup (level-wide list)
+    const int32_t *red_hub;    // partitioned hubs (level-wide list)
+    const int32_t *ins_hub;    // hub of each chunk workgroup (level-wide list)
+    const int32_t *agg_hub;    // hub of each bucket workgroup (level-wide list)
     const int64_t *ins_first;  // first chunk workgroup of each hub (class-relative prefix)
     const int64_t *agg_first;  // first bucket workgroup of each hub (class-relative prefix)
     const int32_t *nchunk;     // chunks of each hub
@@ -69,12 +80,15 @@ struct HubArrays {
 constexpr int64_t kHubInsChunk = 2048;  // entries per hub chunk workgroup
 constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
 constexpr int64_t kHubBucketTarget = 2048;
+constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol < 2^31) take one workgroup
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                        bool force_wide, const hipEvent_t *ev, hipStream_t st);
 void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
-void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, int64_t begin, int64_t count,
-                        int64_t *deg_out, hipStream_t st);
+// row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
+// positions [begin, begin + count)
+void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
+                        int64_t count, int64_t *deg_out, int32_t *u_out, hipStream_t st);
 
 // ---- coarsen.hip
 // pi[u] = rank of zeta[u] among non-empty communities; returns k.

@@ -13,7 +13,11 @@
 // Degree bins: rows up to 16 entries are handled one lane per node (register
 // arrays), up to the wave limit one wavefront per node (LDS hash table), up to
 // the block limit one workgroup per node (LDS hash table), and longer rows
-// ("hubs") by several workgroups per node through a global hash table.
+// ("hubs") by one 1024-thread workgroup with a 16384-slot LDS table when the
+// row has at most kSingleMaxRow entries, else by several workgroups per node
+// through hash-partitioned staging.  The LDS tables sum weights in 32 bits:
+// the bucketing sends a node whose vol(u) (an upper bound of every w(u, X))
+// does not fit to the partitioned hub path, whose sums are 64-bit.
 #include <hip/hip_runtime.h>
 
 #include "level.h"
@@ -142,23 +146,47 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
 // otherwise serialise on that one key.
 constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 
+// Scores the occupied slots of a table (and empties them).  Slots are taken
+// kEvalBatch per thread at a time, so that their community-volume gathers are
+// in flight together.
+constexpr int kEvalBatch = 8;
+
+template <typename G, typename V>
+__device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, int64_t vu,
+                                           int64_t S, const int64_t *volC, bool clear, G &bs, int32_t &bx,
+                                           int64_t &ncand) {
+    for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
+        int32_t X[kEvalBatch];
+        int64_t a[kEvalBatch], vc[kEvalBatch];
+#pragma unroll
+        for (int j = 0; j < kEvalBatch; ++j) {
+            int s = s0 + j * step;
+            X[j] = s < tsize ? tk[s] : kEmpty;
+            a[j] = 0;
+            if (X[j] >= 0) {
+                a[j] = (int64_t)tv[s];
+                if (clear) { tk[s] = kEmpty; tv[s] = 0; }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kEvalBatch; ++j) vc[j] = X[j] >= 0 ? volC[X[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kEvalBatch; ++j) {
+            if (X[j] < 0) continue;
+            ++ncand;
+            G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
+            if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
+        }
+    }
+}
+
 template <typename G>
-__device__ __forceinline__ void wave_eval(int32_t *tk, int64_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
+__device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
                                           int64_t S, const int64_t *volC, int32_t &best_x, bool &move,
                                           int64_t &ncand) {
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    for (int s = lane_id(); s < tsize; s += kWave) {
-        int32_t X = tk[s];
-        if (X >= 0) {
-            int64_t a = tv[s];
-            tk[s] = kEmpty;
-            tv[s] = 0;
-            ++ncand;
-            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-        }
-    }
+    eval_slots<G, int32_t>(tk, tv, tsize, lane_id(), kWave, vu, S, volC, true, bs, bx, ncand);
     wave_argmax<G>(bs, bx);
     G K = (G)S * (G)wD - (G)vu * (G)base;
     best_x = bx;
@@ -169,10 +197,14 @@ __device__ __forceinline__ void wave_eval(int32_t *tk, int64_t *tv, int tsize, i
 // this thread's share of w(u, D \ u).  Entries are taken B at a time: B column
 // loads, then B community gathers, then B inserts, so that the memory
 // latencies of a batch overlap.
-template <int WK, int B>
+__device__ __forceinline__ void lds_add(int32_t *p, int64_t x) { atomicAdd(p, (int32_t)x); }
+__device__ __forceinline__ void lds_add(int64_t *p, int64_t x) {
+    atomicAdd((unsigned long long *)p, (unsigned long long)x);
+}
+
+template <int WK, int B, typename V>
 __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *zeta, int32_t u, int32_t D, int64_t e0,
-                                            int64_t e1, int64_t first, int64_t step, int32_t *tk, int64_t *tv,
-                                            int bits) {
+                                            int64_t e1, int64_t first, int64_t step, int32_t *tk, V *tv, int bits) {
     const uint32_t mask = (1u << bits) - 1;
     int64_t myD = 0;
     for (int64_t base = e0 + first; base < e1; base += step * B) {
@@ -198,7 +230,7 @@ __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *z
             for (;;) {
                 int32_t k = atomicCAS(&tk[h], kEmpty, X[b]);
                 if (k == kEmpty || k == X[b]) {
-                    atomicAdd((unsigned long long *)&tv[h], (unsigned long long)wt[b]);
+                    lds_add(&tv[h], wt[b]);
                     break;
                 }
                 h = (h + 1) & mask;
@@ -212,7 +244,7 @@ template <int WK>
 __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, int64_t begin, int64_t count,
                                                      int force_wide) {
     __shared__ int32_t tk[4][kWaveCap];
-    __shared__ int64_t tv[4][kWaveCap];
+    __shared__ int32_t tv[4][kWaveCap];
     const int w = threadIdx.x / kWave, lane = lane_id();
     for (int s = lane; s < kWaveCap; s += kWave) { tk[w][s] = kEmpty; tv[w][s] = 0; }
     wave_sync();
@@ -224,7 +256,7 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
-        int64_t wD = fold_row<WK, 4>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
+        int64_t wD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
         wD = wave_sum(wD);
         wave_sync();
         int64_t vu = ms.vol[u];
@@ -246,32 +278,22 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
 constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
 
-template <typename G>
-__device__ __forceinline__ void block_eval(int32_t *tk, int64_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
+template <typename G, int NT>
+__device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
                                            int64_t S, const int64_t *volC, int32_t *out, int64_t &ncand) {
-    __shared__ int64_t red_w[kBlockThreads / kWave];
-    __shared__ G red_s[kBlockThreads / kWave];
-    __shared__ int32_t red_x[kBlockThreads / kWave];
+    __shared__ int64_t red_w[NT / kWave];
+    __shared__ G red_s[NT / kWave];
+    __shared__ int32_t red_x[NT / kWave];
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    for (int s = threadIdx.x; s < tsize; s += kBlockThreads) {
-        int32_t X = tk[s];
-        if (X >= 0) {
-            int64_t a = tv[s];
-            tk[s] = kEmpty;
-            tv[s] = 0;
-            ++ncand;
-            G sc = (G)S * (G)a - (G)vu * (G)volC[X];
-            if (sc > bs || (sc == bs && X < bx)) { bs = sc; bx = X; }
-        }
-    }
+    eval_slots<G, int32_t>(tk, tv, tsize, threadIdx.x, NT, vu, S, volC, true, bs, bx, ncand);
     wD = wave_sum(wD);  // wD enters as this thread's share
     wave_argmax<G>(bs, bx);
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) { red_w[w] = wD; red_s[w] = bs; red_x[w] = bx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int j = 1; j < kBlockThreads / kWave; ++j) {
+        for (int j = 1; j < NT / kWave; ++j) {
             wD += red_w[j];
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
         }
@@ -280,11 +302,12 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int64_t *tv, int tsize, 
     }
 }
 
+// (two workgroups per CU: 64 KB of LDS each, at most 128 VGPRs)
 template <int WK>
-__global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, MoveState ms, int64_t begin,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_block(GraphView g, MoveState ms, int64_t begin,
                                                                 int64_t count, int force_wide) {
     __shared__ int32_t tk[kBlockCap];
-    __shared__ int64_t tv[kBlockCap];
+    __shared__ int32_t tv[kBlockCap];
     for (int s = threadIdx.x; s < kBlockCap; s += kBlockThreads) { tk[s] = kEmpty; tv[s] = 0; }
     __syncthreads();
     int64_t ncand = 0;
@@ -295,18 +318,51 @@ __global__ __launch_bounds__(kBlockThreads) void k_decide_block(GraphView g, Mov
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
-        int64_t myD = fold_row<WK, 4>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
+        int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         if (force_wide || vu > node_wl(ms, u))
-            block_eval<i128>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<i128, kBlockThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
         else
-            block_eval<int64_t>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<int64_t, kBlockThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos],
+                                               ncand);
         __syncthreads();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
+}
+
+// ------------------------------------------------------------------ hubs: one large workgroup per node
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleBits = 14;  // 16384 slots of int32 key + int32 sum: 128 KB of LDS
+
+template <int WK>
+__global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, MoveState ms, HubArrays ha, int64_t blk0,
+                                                               int force_wide) {
+    __shared__ int32_t tk[1 << kSingleBits];
+    __shared__ int32_t tv[1 << kSingleBits];
+    const int64_t hg = ha.sgl_hub[blk0 + blockIdx.x];
+    const int32_t u = ha.hub_u[hg];
+    const int64_t pos = ha.hub_pos[hg];
+    const int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    // rows of at most kSingleMaxRow entries: load factor <= 0.75
+    int bits = ceil_log2_dev(2 * (e1 - e0));
+    bits = bits < 6 ? 6 : (bits > kSingleBits ? kSingleBits : bits);
+    for (int s = threadIdx.x; s < (1 << bits); s += kSingleThreads) { tk[s] = kEmpty; tv[s] = 0; }
+    __syncthreads();
+    const int32_t D = ms.zeta[u];
+    int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kSingleThreads, tk, tv, bits);
+    __syncthreads();
+    const int64_t vu = ms.vol[u];
+    const int64_t base = ms.volC[D] - vu;
+    const int64_t S_u = node_S(ms, u);
+    int64_t ncand = 0;
+    if (force_wide || vu > node_wl(ms, u))
+        block_eval<i128, kSingleThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+    else
+        block_eval<int64_t, kSingleThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+    count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
 }
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
@@ -328,15 +384,7 @@ constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
 constexpr int kAggSlots = 4096;    // LDS table of a bucket workgroup (~2048 entries expected)
 constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
 constexpr int kAggTile = 2048;     // chunks whose segments are flattened at once
-
-__device__ __forceinline__ int64_t hub_of_block(const int64_t *first, int64_t nh, int64_t b) {
-    int64_t lo = 0, hi = nh;  // last h with first[h] <= b
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (first[mid] <= b) lo = mid; else hi = mid;
-    }
-    return lo;
-}
+constexpr int kAggBatch = 4;       // staged entries per thread loaded together
 
 __device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
     return pbits == 0 ? 0u : ((uint32_t)x * 2654435769u) >> (32 - pbits);
@@ -347,15 +395,13 @@ __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
 }
 
 template <int WK>
-__global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t hub0,
-                                                          int64_t nh) {
+__global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t blk0) {
     __shared__ int32_t start[1 << kHubMaxPBits];
     __shared__ int32_t fill[1 << kHubMaxPBits];
     __shared__ int64_t wsum[kHubThreads / kWave];
-    const int64_t h = hub_of_block(ha.ins_first + hub0, nh, blockIdx.x);
-    const int64_t hg = hub0 + h;
+    const int64_t hg = ha.ins_hub[blk0 + blockIdx.x];
     const int64_t k = blockIdx.x - ha.ins_first[hg];
-    const int32_t u = ms.class_nodes[ha.hub_pos[hg]];
+    const int32_t u = ha.hub_u[hg];
     const int32_t D = ms.zeta[u];
     const int64_t e0 = g.off[u], e1 = g.off[u + 1];
     const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
@@ -505,29 +551,43 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                     run += cnt[i];
                 }
                 __syncthreads();
-                for (int32_t i = threadIdx.x; i < total && !stop; i += kHubThreads) {
-                    int32_t lo = 0, hi = tn;  // last chunk c with cpre[c] <= i
-                    while (hi - lo > 1) {
-                        int32_t mid = (lo + hi) >> 1;
-                        if (cpre[mid] <= i) lo = mid; else hi = mid;
+                // kAggBatch entries per thread at a time: staging loads in flight together
+                for (int32_t i0 = threadIdx.x; i0 < total && !stop; i0 += kAggBatch * kHubThreads) {
+                    int32_t X[kAggBatch];
+                    int64_t w[kAggBatch];
+#pragma unroll
+                    for (int b = 0; b < kAggBatch; ++b) {
+                        int32_t i = i0 + b * kHubThreads;
+                        X[b] = kEmpty;
+                        w[b] = 0;
+                        if (i < total) {
+                            int32_t lo = 0, hi = tn;  // last chunk c with cpre[c] <= i
+                            while (hi - lo > 1) {
+                                int32_t mid = (lo + hi) >> 1;
+                                if (cpre[mid] <= i) lo = mid; else hi = mid;
+                            }
+                            int64_t idx = (int64_t)cbase[lo] + (i - cpre[lo]);
+                            X[b] = sx[idx];
+                            w[b] = sw[idx];
+                        }
                     }
-                    int64_t idx = (int64_t)cbase[lo] + (i - cpre[lo]);
-                    int32_t X = sx[idx];
-                    if (agg_subpart(X, qbits) != (uint32_t)q) continue;
-                    int64_t w = sw[idx];
-                    uint32_t h = agg_slot(X);
-                    for (;;) {
-                        int32_t kk = atomicCAS(&tk[h], kEmpty, X);
-                        if (kk == kEmpty && atomicAdd(nkeys, 1) >= kAggMaxKeys) {
-                            *overflow = 1;
-                            stop = true;
-                            break;
+#pragma unroll
+                    for (int b = 0; b < kAggBatch; ++b) {
+                        if (stop || X[b] < 0 || agg_subpart(X[b], qbits) != (uint32_t)q) continue;
+                        uint32_t h = agg_slot(X[b]);
+                        for (;;) {
+                            int32_t kk = atomicCAS(&tk[h], kEmpty, X[b]);
+                            if (kk == kEmpty && atomicAdd(nkeys, 1) >= kAggMaxKeys) {
+                                *overflow = 1;
+                                stop = true;
+                                break;
+                            }
+                            if (kk == kEmpty || kk == X[b]) {
+                                atomicAdd((unsigned long long *)&tv[h], (unsigned long long)w[b]);
+                                break;
+                            }
+                            h = (h + 1) & (kAggSlots - 1);
                         }
-                        if (kk == kEmpty || kk == X) {
-                            atomicAdd((unsigned long long *)&tv[h], (unsigned long long)w);
-                            break;
-                        }
-                        h = (h + 1) & (kAggSlots - 1);
                     }
                 }
                 __syncthreads();
@@ -537,13 +597,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                 __syncthreads();
                 break;
             }
-            for (int s = threadIdx.x; s < kAggSlots; s += kHubThreads) {
-                int32_t X = tk[s];
-                if (X < 0) continue;
-                ++pc;
-                G sc = (G)S * (G)tv[s] - (G)vu * (G)volC[X];
-                if (sc > pbs || (sc == pbs && X < pbx)) { pbs = sc; pbx = X; }
-            }
+            eval_slots<G, int64_t>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, volC, false, pbs, pbx, pc);
             __syncthreads();
         }
         if (ok) {
@@ -555,16 +609,14 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     }
 }
 
-__global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays ha, int64_t hub0, int64_t nh,
-                                                         int force_wide) {
+__global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays ha, int64_t blk0, int force_wide) {
     __shared__ int32_t tk[kAggSlots];
     __shared__ int64_t tv[kAggSlots];
     __shared__ int32_t cpre[kAggTile], cbase[kAggTile], wtot[kHubThreads / kWave];
     __shared__ int32_t nkeys, overflow;
-    const int64_t h = hub_of_block(ha.agg_first + hub0, nh, blockIdx.x);
-    const int64_t hg = hub0 + h;
+    const int64_t hg = ha.agg_hub[blk0 + blockIdx.x];
     const int64_t p = blockIdx.x - ha.agg_first[hg];
-    const int32_t u = ms.class_nodes[ha.hub_pos[hg]];
+    const int32_t u = ha.hub_u[hg];
     const int64_t vu = ms.vol[u];
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
@@ -591,9 +643,9 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
 
 // One workgroup per hub of the class combines the bucket partials and the
 // w(u, D) shares (written by earlier launches) and decides the move.
-__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArrays ha, int64_t hub0) {
+__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArrays ha, int64_t blk0) {
     __shared__ int64_t wsum[kHubThreads / kWave];
-    const int64_t hg = hub0 + blockIdx.x;
+    const int64_t hg = ha.red_hub[blk0 + blockIdx.x];
     const int64_t nagg = (int64_t)1 << ha.pbits[hg];
     const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
     i128 bs = neg_inf<i128>();
@@ -612,7 +664,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArr
         wD = 0;
         for (int i = 0; i < kHubThreads / kWave; ++i) wD += wsum[i];
         int64_t pos = ha.hub_pos[hg];
-        int32_t u = ms.class_nodes[pos];
+        int32_t u = ha.hub_u[hg];
         int32_t D = ms.zeta[u];
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
@@ -642,11 +694,15 @@ __global__ __launch_bounds__(256) void k_apply(MoveState ms, int64_t begin, int6
     if (lane_id() == 0 && moved) atomicAdd(ms.moves_dev, (unsigned long long)moved);
 }
 
-__global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, int64_t begin, int64_t count, int64_t *deg) {
+// row length of each hub, negated when vol(u) does not fit 32 bits
+__global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
+                              int64_t count, int64_t *deg, int32_t *uo) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     int32_t u = class_nodes[begin + i];
-    deg[i] = g.off[u + 1] - g.off[u];
+    int64_t d = g.off[u + 1] - g.off[u];
+    deg[i] = vol[u] > (int64_t)INT32_MAX ? -d : d;
+    uo[i] = u;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -673,13 +729,16 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
                            0, st, g, ms, cr.begin[2], cr.count[2], fw);
     }
     mark(3);
-    if (cr.hub_count > 0) {
+    if (cr.sgl_count > 0)
+        hipLaunchKernelGGL(k_hub_single<WK>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, g, ms, ha,
+                           cr.sgl_base, fw);
+    if (cr.red_count > 0) {
         hipLaunchKernelGGL(k_hub_part<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
-                           cr.hub_first, cr.hub_count);
-        hipLaunchKernelGGL(k_hub_agg, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha, cr.hub_first,
-                           cr.hub_count, fw);
-        hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.hub_count), dim3(kHubThreads), 0, st, ms, ha,
-                           cr.hub_first);
+                           cr.ins_base);
+        hipLaunchKernelGGL(k_hub_agg, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha, cr.agg_base,
+                           fw);
+        hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st, ms, ha,
+                           cr.red_base);
     }
     mark(4);
 }
@@ -701,11 +760,11 @@ void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t
     HIPCHK(hipGetLastError());
 }
 
-void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, int64_t begin, int64_t count,
-                        int64_t *deg_out, hipStream_t st) {
+void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
+                        int64_t count, int64_t *deg_out, int32_t *u_out, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_hub_degrees, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, g, class_nodes, begin,
-                       count, deg_out);
+    hipLaunchKernelGGL(k_hub_degrees, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, g, class_nodes, vol, begin,
+                       count, deg_out, u_out);
     HIPCHK(hipGetLastError());
 }
 
