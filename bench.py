@@ -5,7 +5,10 @@ One step = one full multilevel PLM run (plm_run: level set-up, colouring, class
 bucketing, move sweeps, coarsening, prolongation, canonical labels) on a graph
 already resident in HBM.  Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000] [--no-batch]
+
+The line also carries "batched": the batched engine (plm_batch_run) on 4,096
+uneven SBM graphs against a per-graph plm_run loop on the same GPU.
 """
 from __future__ import annotations
 
@@ -20,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-BIN_KERNELS = ["k_decide_lane", "k_decide_wave", "k_decide_block", "k_hub_part+k_hub_agg+k_hub_reduce"]
+KERNELS = ["k_decide_lane", "k_decide_wave", "k_decide_block", "k_hub_single", "k_hub_part+k_hub_agg+k_hub_reduce"]
 
 WORKLOADS = {
     "rmat26": dict(desc="R-MAT scale 26, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised, loops and "
@@ -30,6 +33,28 @@ WORKLOADS = {
                         "duplicates removed, unit weights, seed 2", scale=20, seed=2, weighted=False),
     "pp1000": dict(desc="planted partition n=1000, 10 blocks of 100, p_in=0.1, p_out=0.005, unit weights, seed 1"),
 }
+
+
+def roofline(st, level=0):
+    """Roofline of the move-decide kernel with the most device time at a level:
+    algorithmic bytes (section 8(d) of the design: per entry column, weight and
+    neighbour community; per distinct candidate its volume; per node 32 bytes)
+    over the kernel's event-timed duration, against the HBM peak."""
+    bm, bb = st["bin_ms"][level], st["bin_bytes"][level]
+    ms = [bm[0], bm[1], bm[2], st["hub_single_ms"][level], bm[3] - st["hub_single_ms"][level]]
+    by = [bb[0], bb[1], bb[2], st["hub_single_bytes"][level], bb[3] - st["hub_single_bytes"][level]]
+    k = max(range(5), key=lambda i: ms[i])
+    launches = st["kernel_launches"][level][k]
+    achieved = by[k] / (ms[k] * 1e6) if ms[k] > 0 else 0.0
+    sweeps = max(st["sweeps"][level], 1)
+    return {"bound": "hbm", "kernel": KERNELS[k], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "level": level, "launches": launches, "avg_launch_us": ms[k] * 1e3 / max(launches, 1),
+            "algorithmic_bytes_per_launch": by[k] / max(launches, 1),
+            "algorithmic_bytes_per_sweep": by[k] / sweeps, "kernel_ms_per_sweep": ms[k] / sweeps,
+            "all_decide_GBs": st["decide_bytes"][level] / (st["decide_ms"][level] * 1e6)
+            if st["decide_ms"][level] else 0.0,
+            "kernels": KERNELS, "kernel_ms": ms, "kernel_bytes": by}
 
 
 def log(*a):
@@ -118,6 +143,95 @@ def cpu_baseline(gr, ctx_state, budget_s=15.0):
             "seconds": dt}
 
 
+BATCH_DESC = ("4,096 SBM graphs, n log-uniform in [100, 100000], k = max(2, n/100) near-equal blocks, "
+              "p_in = 20/blocksize, p_out = 1/n, unit weights, seed 4")
+
+
+def batch_bench(args, P, torch, np):
+    """Batched PLM: graphs/s of plm_batch_run over the whole batch, against a
+    loop of plm_run over a random sample of the same graphs (contexts created
+    beforehand, inputs resident in HBM for both); partitions, Q and levels of
+    the sample must be identical.  The oracle's rate (plain C, one graph per
+    host thread) is timed on a bounded sample."""
+    from concurrent.futures import ThreadPoolExecutor
+    import graphgen
+    import oracle
+    count = args.batch_graphs
+    t = time.time()
+    n, k, pin, pout, gs = graphgen.batch_params(4, count)
+    workers = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(workers) as ex:
+        graphs = list(ex.map(lambda i: graphgen.sbm(int(n[i]), int(k[i]), float(pin[i]), float(pout[i]), int(gs[i])),
+                             range(count)))
+    nb, off, col, w = P.pack_batch(graphs)
+    log(f"batch: {count} graphs, n={nb[-1]} nnz={len(col)} built in {time.time() - t:.1f}s")
+    ctx = P.BatchContext(nb, off, col, w, timing=1)  # instrumented step (see main)
+    lab = torch.empty(int(nb[-1]), dtype=torch.int32, device="cuda:0")
+    ctx.run_batch(lab)
+    roof = roofline(ctx.stats())
+    ctx.close()
+    ctx = P.BatchContext(nb, off, col, w)
+    for i in range(args.warmup):
+        ctx.run_batch(lab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, q, lv = ctx.run_batch(lab)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    st = ctx.stats()
+    labels = lab.cpu().numpy()
+    ctx.close()
+    log(f"batch run {tb * 1e3:.1f} ms")
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(count, min(args.plain_sample, count), replace=False))
+    ctxs = [P.Context(graphs[i].off, graphs[i].col, graphs[i].w) for i in idx]
+    outs = [torch.empty(max(graphs[i].n, 1), dtype=torch.int32, device="cuda:0") for i in idx]
+    res = [c.run(o) for c, o in zip(ctxs, outs)]  # warm-up pass
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [c.run(o) for c, o in zip(ctxs, outs)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = 0
+    for j, i in enumerate(idx):
+        a, b = int(nb[i]), int(nb[i + 1])
+        same += int(np.array_equal(outs[j].cpu().numpy()[: b - a], labels[a:b]) and res[j][1] == q[i]
+                    and res[j][2] == lv[i])
+    for c in ctxs:
+        c.close()
+    log(f"plain loop over {len(idx)} graphs {tp * 1e3:.1f} ms")
+    out = {"workload": BATCH_DESC, "graphs": count, "n": int(nb[-1]), "nnz": int(len(col)),
+           "graphs_per_s": count / tb, "ms_per_run": tb * 1e3,
+           "plain_graphs_per_s": len(idx) / tp, "plain_sample": int(len(idx)),
+           "speedup_vs_plain": (count / tb) / (len(idx) / tp),
+           "identical_partitions": f"{same}/{len(idx)}", "levels_max": int(lv.max()),
+           "roofline": roof,
+           "per_level": {k: st[k] for k in ("n", "nnz", "colours", "sweeps", "sweep_ms", "colour_ms",
+                                            "coarsen_ms")}}
+    if not args.no_cpu_baseline:
+        order = rng.permutation(count)
+        done, ge, t0 = 0, 0, time.perf_counter()
+
+        def one(i):
+            g = graphs[i]
+            oracle.run(g.off, g.col, g.w)
+            return g.nnz
+
+        with ThreadPoolExecutor(workers) as ex:
+            for s0 in range(0, count, workers):
+                ge += sum(ex.map(one, order[s0:s0 + workers]))
+                done += len(order[s0:s0 + workers])
+                if time.perf_counter() - t0 > args.cpu_budget:
+                    break
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done / dt, "unit": "graphs/s", "cores": workers, "kind": "oracle",
+                               "sample": f"full oracle runs of {done} randomly chosen graphs of the batch "
+                                         f"({ge} CSR entries), one graph per host thread",
+                               "seconds": dt}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +240,9 @@ def main():
     ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -140,9 +257,23 @@ def main():
     t = time.time()
     gr = make_graph(args.workload)
     log(f"graph {args.workload}: n={gr['n']} nnz={gr['nnz']} built in {time.time() - t:.1f}s")
-    ctx = P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"], timing=1)
+    # Instrumented step: every move-decide kernel carries start/stop HIP events
+    # on its dispatch (the library's stream); it gives the dominant kernel and
+    # its average launch duration.  Events slow the timed kernels on this
+    # stack (up to ~2x), so the timed steps below run without them and the
+    # roofline from the instrumented step is a lower bound.
+    mk = lambda **kw: P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"],
+                                **kw)
+    ctx = mk(timing=1)
     state0 = ctx.state()  # level-0 singleton state, for the CPU sample
     lab = torch.empty(max(gr["n"], 1), dtype=torch.int32, device="cuda:0")
+    t = time.time()
+    ctx.run(lab)
+    st_probe = ctx.stats()
+    roof = roofline(st_probe)
+    log(f"instrumented step {time.time() - t:.2f}s: dominant {roof['kernel']}")
+    ctx.close()
+    ctx = mk(timing=0)
     for i in range(args.warmup):
         t = time.time()
         ctx.run(lab)
@@ -163,17 +294,8 @@ def main():
     sweep_edges = sum(st["sweeps"][l] * m_l[l] for l in range(L))
     value = sweep_edges / (ms_per_step / 1e3)
     sweep_ms = sum(st["sweep_ms"])
-    # dominant move-decide kernel (degree bin) at level 0, timed with HIP events on the library's stream
-    bms = st["bin_ms"][0]
-    b = int(np.argmax(bms))
-    launches = st["decide_launches"][0]
-    achieved = st["bin_bytes"][0][b] / (bms[b] * 1e6) if bms[b] > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": BIN_KERNELS[b], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "algorithmic_bytes_per_sweep": st["bin_bytes"][0][b] / max(st["sweeps"][0], 1),
-            "kernel_ms_per_sweep": bms[b] / max(st["sweeps"][0], 1),
-            "all_decide_bins_GBs": st["decide_bytes"][0] / (st["decide_ms"][0] * 1e6) if st["decide_ms"][0] else 0.0,
-            "bin_ms_level0": bms, "bin_bytes_level0": st["bin_bytes"][0]}
+    roof["timing"] = ("HIP events attached to each move-decide dispatch (hipExtLaunchKernelGGL) on the library's "
+                      "stream, in one instrumented step before the timed steps; the timed steps run without events")
     out = {
         "metric": "PLM move-sweep edges/s",
         "value": value,
@@ -195,7 +317,7 @@ def main():
         "q": q,
         "levels": lv,
         "per_level": {k: st[k] for k in ("n", "nnz", "colours", "sweeps", "moves", "schedule_ms", "colour_ms",
-                                         "schedule_rounds", "sweep_ms", "coarsen_ms", "decide_ms")},
+                                         "schedule_rounds", "sweep_ms", "coarsen_ms")},
         "paper_context": "PLM full run >21M edges/s (uk-2007-05, 3.3e9 edges, 2x Xeon E5-2680, 32 threads)",
     }
     if not args.no_cpu_baseline:
@@ -205,6 +327,8 @@ def main():
     ctx.close()
     if gr["dg"] is not None:
         gr["dg"].free()
+    if not args.no_batch:
+        out["batched"] = batch_bench(args, P, torch, np)
     print(json.dumps(out), flush=True)
 
 

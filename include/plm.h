@@ -86,10 +86,17 @@ typedef struct {
                              PLM_INT_64: 64-bit only, PLM_E_STATE if unsafe */
     int32_t bin_lane;     /* rows up to this length: one lane per node (0 = 16) */
     int32_t bin_wave;     /* rows up to this length: one wavefront per node (0 = 512) */
-    int32_t bin_block;    /* rows up to this length: one workgroup per node, longer
-                             rows: several workgroups per node (0 = 4096) */
-    int32_t timing;       /* 1: time every move-decide launch with HIP events */
-    int32_t reserved[7];
+    int32_t bin_block;    /* rows up to this length: one workgroup per node (0 = 4096);
+                             longer rows ("hubs"): one 1024-thread workgroup up to
+                             12288 entries, else several workgroups per node.
+                             Rows of the wavefront and workgroup bins whose vol(u)
+                             reaches 2^31 also take the hub path. */
+    int32_t timing;       /* 1: time the move-decide launches with HIP events */
+    int32_t timing_kernel; /* with timing: 0 = every kernel of every class step (six
+                              events per step); k = 1..5 = only kernel k (lane,
+                              wavefront, workgroup, one-workgroup hub, partitioned
+                              hub): two events per step, so timing costs less */
+    int32_t reserved[6];
 } plm_options;
 
 /* Fills *opt with the defaults above. */
@@ -214,6 +221,15 @@ typedef struct {
     int64_t bin_nodes[PLM_MAX_LEVELS][4];     /* nodes of the level in each bin */
     int64_t bin_entries[PLM_MAX_LEVELS][4];   /* their CSR entries */
     int64_t loops[PLM_MAX_LEVELS];            /* self-loop entries of the level */
+    /* the part of the hub bin taken by one workgroup per hub (rows of at most
+     * 12288 entries with vol(u) < 2^31); the rest of the bin is partitioned */
+    double hub_single_ms[PLM_MAX_LEVELS];
+    double hub_single_bytes[PLM_MAX_LEVELS];
+    int64_t hub_single_nodes[PLM_MAX_LEVELS];
+    int64_t hub_single_entries[PLM_MAX_LEVELS];
+    /* with opt.timing: class steps that launched each kernel (lane, wavefront,
+     * workgroup, one-workgroup hub, partitioned hub) */
+    int64_t kernel_launches[PLM_MAX_LEVELS][5];
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

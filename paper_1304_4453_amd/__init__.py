@@ -39,7 +39,7 @@ class plm_options(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("colour_seed", ctypes.c_uint64), ("int_mode", ctypes.c_int32),
                 ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class plm_level_info_t(ctypes.Structure):
@@ -61,7 +61,10 @@ class plm_stats_t(ctypes.Structure):
                 ("decide_bytes", ctypes.c_double * _L), ("schedule_rounds", ctypes.c_int64 * _L),
                 ("colour_ms", ctypes.c_double * _L), ("bin_ms", (ctypes.c_double * 4) * _L),
                 ("bin_bytes", (ctypes.c_double * 4) * _L), ("bin_nodes", (ctypes.c_int64 * 4) * _L),
-                ("bin_entries", (ctypes.c_int64 * 4) * _L), ("loops", ctypes.c_int64 * _L)]
+                ("bin_entries", (ctypes.c_int64 * 4) * _L), ("loops", ctypes.c_int64 * _L),
+                ("hub_single_ms", ctypes.c_double * _L), ("hub_single_bytes", ctypes.c_double * _L),
+                ("hub_single_nodes", ctypes.c_int64 * _L), ("hub_single_entries", ctypes.c_int64 * _L),
+                ("kernel_launches", (ctypes.c_int64 * 5) * _L)]
 
 
 class PLMError(RuntimeError):

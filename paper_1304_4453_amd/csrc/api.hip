@@ -17,6 +17,11 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// batched runs: rebuild the class buckets when the graphs still sweeping hold
+// less than this fraction of the planned entries
+constexpr double kReplanFraction = 0.7;
+constexpr size_t kEv = 10;  // timing events per class step: start and stop of 5 kernel groups
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -136,9 +141,11 @@ struct plm_ctx {
             cap_ahub = 0, cap_shub = 0, cap_rhub = 0;
     int32_t sweeps = 0;
     // device counters: [0] moves, [1..4] candidates per bin, [5] S, [6] max vol,
-    // [7] loop-only rows, [8..11] entries per bin
+    // [7] loop-only rows, [8..11] entries per bin, [12] self-loops, [13]
+    // candidates of the one-workgroup hubs
     unsigned long long *dcnt = nullptr;
     int64_t bin_nodes[4] = {0, 0, 0, 0}, bin_entries[4] = {0, 0, 0, 0};
+    int64_t sgl_nodes = 0, sgl_entries = 0;  // hubs of the one-workgroup path
     int64_t loops = 0;  // self-loop entries of the current level
     int64_t *hbuf = nullptr;             // pinned host scratch (64 int64)
     Scratch scr;
@@ -156,7 +163,8 @@ struct plm_ctx {
     int32_t *bflag = nullptr, *bout = nullptr;
     int64_t *bnewid = nullptr, *bgath = nullptr;
     void *bscan = nullptr;
-    uint8_t *bstatus = nullptr, *bkeep = nullptr;
+    uint8_t *bstatus = nullptr, *bkeep = nullptr, *bsweep = nullptr;
+    int32_t *bgmoved = nullptr;  // per graph of the level: moved in the current sweep
     unsigned long long *bI2 = nullptr, *bsq = nullptr;
 
     ~plm_ctx() {
@@ -165,7 +173,7 @@ struct plm_ctx {
         dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
-        dev_free(bsq);
+        dev_free(bsq); dev_free(bsweep); dev_free(bgmoved);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
@@ -262,12 +270,21 @@ struct plm_ctx {
             stats.colour_ms[cur] = now_ms() - t0;
             stats.schedule_rounds[cur] = jp_rounds;
         }
+        build_plan(nullptr);
+    }
+
+    // Class buckets and hub plan of the current colouring.  keep (batched runs,
+    // device, one flag per graph of the level, else null): only the nodes of
+    // kept graphs enter the buckets.
+    void build_plan(const uint8_t *keep) {
+        LevelData &l = L();
+        GraphView g = l.view();
         int64_t nkeys = (int64_t)ncol * 4 + 1;
         dev_free(bstart_dev);
         bstart_dev = dev_alloc<int64_t>(nkeys + 1);
         HIPCHK(hipMemsetAsync(dcnt + 7, 0, 5 * 8, st));
         build_buckets(g, vol, colour, ncol, bin_lane(), bin_wave(), bin_block(), class_nodes, bstart_dev, dcnt + 8,
-                      scr, st);
+                      scr, st, keep);
         bstart.assign(nkeys + 1, 0);
         if (l.n > 0) HIPCHK(hipMemcpyAsync(bstart.data(), bstart_dev, (nkeys + 1) * 8, hipMemcpyDeviceToHost, st));
         // active entries = nnz minus rows made of a single self-loop
@@ -311,6 +328,7 @@ struct plm_ctx {
         std::vector<int64_t> hins(H > 0 ? H : 1, 0), hagg(H > 0 ? H : 1, 0), hstg(H > 0 ? H : 1, 0),
             hbk(H > 0 ? H : 1, 0);
         int64_t max_stg = 0, max_bk = 0, max_ins = 0, max_agg = 0, hg = 0;
+        sgl_nodes = sgl_entries = 0;
         for (int32_t c = 0; c < ncol; ++c) {
             ClassRange &cr = classes[c];
             for (int b = 0; b < 4; ++b) {
@@ -329,6 +347,8 @@ struct plm_ctx {
                 int64_t d = deg[hg] < 0 ? -deg[hg] : deg[hg];
                 if (deg[hg] > 0 && d <= kSingleMaxRow) {
                     shub.push_back((int32_t)hg);
+                    ++sgl_nodes;
+                    sgl_entries += d;
                     continue;
                 }
                 rhub.push_back((int32_t)hg);
@@ -374,10 +394,13 @@ struct plm_ctx {
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
-        if (opt.timing && events.size() < 5 * (size_t)ncol) {
+        if (opt.timing && events.size() < kEv * (size_t)ncol) {
             size_t old = events.size();
-            events.resize(5 * (size_t)ncol);
-            for (size_t i = old; i < events.size(); ++i) HIPCHK(hipEventCreate(&events[i]));
+            events.resize(kEv * (size_t)ncol);
+            // timing-only events (read after a stream synchronisation): no
+            // system-scope fence
+            for (size_t i = old; i < events.size(); ++i)
+                HIPCHK(hipEventCreateWithFlags(&events[i], hipEventDisableSystemFence));
         }
     }
 
@@ -385,7 +408,8 @@ struct plm_ctx {
         MoveState ms;
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
-        if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; }
+        ms.cand_sgl = count_cand ? dcnt + 13 : nullptr;
+        if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; ms.gmoved = bgmoved; }
         return ms;
     }
     HubArrays hub_arrays() {
@@ -402,30 +426,47 @@ struct plm_ctx {
     int64_t run_classes(int32_t c0, int32_t c1) {
         if (!sched) build_schedule();
         HIPCHK(hipMemsetAsync(dcnt, 0, 5 * 8, st));
+        HIPCHK(hipMemsetAsync(dcnt + 13, 0, 8, st));
         bool timing = opt.timing != 0;
         MoveState ms = move_state(timing);
         HubArrays ha = hub_arrays();
         GraphView g = L().view();
         bool fw = opt.int_mode == PLM_INT_128;
+        // timing_kernel k in 1..5: only kernel group k - 1
+        const int tk = opt.timing_kernel;
+        const unsigned mask = tk == 0 ? 0x1fu : (1u << (tk - 1));
         for (int32_t c = c0; c < c1; ++c) {
             const ClassRange &cr = classes[c];
-            launch_class_step(g, ms, cr, ha, fw, timing ? &events[5 * (size_t)c] : nullptr, st);
+            launch_class_step(g, ms, cr, ha, fw, timing ? &events[kEv * (size_t)c] : nullptr, mask, st);
             launch_apply(ms, cr.begin[0], cr.begin[3] + cr.count[3] - cr.begin[0], st);
         }
         HIPCHK(hipMemcpyAsync(hbuf, dcnt, 5 * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hbuf + 5, dcnt + 13, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t moves = hbuf[0];
         if (timing && cur < PLM_MAX_LEVELS) {
-            double bin_t[4] = {0, 0, 0, 0};
+            // per bin: lane, wavefront, workgroup, hub (one-workgroup + partitioned)
+            double bin_t[4] = {0, 0, 0, 0}, sgl_t = 0;
             int64_t launches = 0;
             for (int32_t c = c0; c < c1; ++c) {
-                for (int b = 0; b < 4; ++b) {
-                    float t = 0;
-                    HIPCHK(hipEventElapsedTime(&t, events[5 * (size_t)c + b], events[5 * (size_t)c + b + 1]));
-                    bin_t[b] += t;
-                    if (b < 3) launches += classes[c].count[b] > 0 ? 1 : 0;
-                    else launches += (classes[c].sgl_count > 0 ? 1 : 0) + (classes[c].red_count > 0 ? 3 : 0);
+                const ClassRange &cr = classes[c];
+                const bool ran[5] = {cr.count[0] > 0, cr.count[1] > 0, cr.count[2] > 0, cr.sgl_count > 0,
+                                     cr.red_count > 0};
+                float t[5] = {0, 0, 0, 0, 0};
+                for (int b = 0; b < 5; ++b)
+                    if (((mask >> b) & 1u) && ran[b])
+                        HIPCHK(hipEventElapsedTime(&t[b], events[kEv * (size_t)c + 2 * b],
+                                                   events[kEv * (size_t)c + 2 * b + 1]));
+                for (int b = 0; b < 3; ++b) bin_t[b] += t[b];
+                bin_t[3] += t[3] + t[4];
+                sgl_t += t[3];
+                for (int b = 0; b < 3; ++b) {
+                    launches += cr.count[b] > 0 ? 1 : 0;
+                    stats.kernel_launches[cur][b] += cr.count[b] > 0 ? 1 : 0;
                 }
+                launches += (cr.sgl_count > 0 ? 1 : 0) + (cr.red_count > 0 ? 3 : 0);
+                stats.kernel_launches[cur][3] += cr.sgl_count > 0 ? 1 : 0;
+                stats.kernel_launches[cur][4] += cr.red_count > 0 ? 1 : 0;
             }
             // algorithmic bytes (whole sweeps only): per entry the column, the
             // weight and the community of the neighbour; per distinct candidate
@@ -442,6 +483,10 @@ struct plm_ctx {
                 stats.decide_ms[cur] += bin_t[b];
                 stats.decide_bytes[cur] += bytes;
             }
+            stats.hub_single_ms[cur] += sgl_t;
+            if (whole)
+                stats.hub_single_bytes[cur] += (double)sgl_entries * (8.0 + wb) + 8.0 * (double)hbuf[5] +
+                                               32.0 * (double)sgl_nodes;
             stats.decide_launches[cur] += launches;
         }
         return moves;
@@ -513,6 +558,8 @@ struct plm_ctx {
             stats.bin_nodes[cur][b] = bin_nodes[b];
             stats.bin_entries[cur][b] = bin_entries[b];
         }
+        stats.hub_single_nodes[cur] = sgl_nodes;
+        stats.hub_single_entries[cur] = sgl_entries;
         stats.coarsen_ms[cur] += t_coarsen;
     }
 
@@ -581,19 +628,47 @@ struct plm_ctx {
         std::vector<int64_t> gath, nbase, nact;
         std::vector<int32_t> glev(G, 0);
         launch_iota(lab, n0v, st);
+        std::vector<int32_t> gmoved;
+        std::vector<uint8_t> sweeping;
+        std::vector<int64_t> ebound;
         for (int32_t depth = 1;; ++depth) {
             double t0 = now_ms();
             build_schedule();
             double t1 = now_ms();
+            LevelData &l = L();
+            int64_t A = (int64_t)act_h.size();
+            // entries of each graph of the level (row ranges are contiguous)
+            ebound.resize(A + 1);
+            launch_gather_i64(l.off, l.gbase, A + 1, bgath, st);
+            HIPCHK(hipMemcpyAsync(ebound.data(), bgath, (A + 1) * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemsetAsync(bgmoved, 0, A * 4, st));
+            HIPCHK(hipStreamSynchronize(st));
+            sweeping.assign(A, 1);
+            int64_t planned = ebound[A] - ebound[0];
             int64_t moves = 0;
             for (int32_t s = 0; s < opt.max_sweeps; ++s) {
                 int64_t mv = sweep();
                 moves += mv;
                 if (mv == 0) break;
+                // a graph whose sweep moved nothing is done at this level (a
+                // further sweep would repeat the same decisions): its nodes
+                // leave the class buckets once the live entries have shrunk
+                gmoved.resize(A);
+                HIPCHK(hipMemcpyAsync(gmoved.data(), bgmoved, A * 4, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemsetAsync(bgmoved, 0, A * 4, st));
+                HIPCHK(hipStreamSynchronize(st));
+                int64_t live = 0;
+                for (int64_t a = 0; a < A; ++a) {
+                    if (!gmoved[a]) sweeping[a] = 0;
+                    if (sweeping[a]) live += ebound[a + 1] - ebound[a];
+                }
+                if (s + 1 < opt.max_sweeps && (double)live < kReplanFraction * (double)planned) {
+                    HIPCHK(hipMemcpyAsync(bsweep, sweeping.data(), A, hipMemcpyHostToDevice, st));
+                    build_plan(bsweep);
+                    planned = live;
+                }
             }
             double t2 = now_ms();
-            LevelData &l = L();
-            int64_t A = (int64_t)act_h.size();
             // communities of each graph: ranks of community ids at the graph bounds
             batch_relabel(zeta, l.n, l.gid, nullptr, bflag, bnewid, nullptr, bscan, st);
             launch_gather_i64(bnewid, l.gbase, A + 1, bgath, st);
@@ -700,6 +775,7 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.max_levels < 0) { msg = "max_levels must be >= 0"; return PLM_E_ARG; }
     if (o.schedule != PLM_SCHEDULE_COLOUR && o.schedule != PLM_SCHEDULE_SEQUENTIAL) { msg = "bad schedule"; return PLM_E_ARG; }
     if (o.int_mode < 0 || o.int_mode > 2) { msg = "bad int_mode"; return PLM_E_ARG; }
+    if (o.timing_kernel < 0 || o.timing_kernel > 5) { msg = "timing_kernel must lie in [0, 5]"; return PLM_E_ARG; }
     int64_t a = o.bin_lane > 0 ? o.bin_lane : 16, b = o.bin_wave > 0 ? o.bin_wave : 512,
             c = o.bin_block > 0 ? o.bin_block : 4096;
     if (a > 16 || b > 512 || c > 4096 || a > b || b > c) {
@@ -830,6 +906,8 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
             c->bscan = dev_alloc<uint8_t>((int64_t)scan_scratch_bytes(n > 0 ? n : 1));
             c->bstatus = dev_alloc<uint8_t>(G); c->bkeep = dev_alloc<uint8_t>(G);
             c->bI2 = dev_alloc<unsigned long long>(G); c->bsq = dev_alloc<unsigned long long>(2 * G);
+            c->bsweep = dev_alloc<uint8_t>(G); c->bgmoved = dev_alloc<int32_t>(G);
+            HIPCHK(hipMemsetAsync(c->bgmoved, 0, G * 4, c->st));
             HIPCHK(hipStreamSynchronize(c->st));
         }
         if (o.validate) {

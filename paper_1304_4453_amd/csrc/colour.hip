@@ -32,10 +32,12 @@ constexpr int kWin = 4096;                // colour window of a bitmap (bits)
 constexpr int kWinWords = kWin / 32;
 constexpr int kRoundGrid = 2048;          // workgroups of a round launch
 constexpr int kRoundsPerCheck = 16;       // rounds launched between host checks
+constexpr int64_t kHubChunk = 4 * 256;    // entries of a long row per work item (4 per thread)
 
 struct JpQ {
     int32_t *q[3][3];  // [set][kind]: 0 lane, 1 wavefront, 2 multi-workgroup
-    int32_t *cnt;      // [set * 4 + kind]; [12] = ncol, [13] = nodes coloured
+    int64_t *cq[3];    // [set]: chunks of the multi-workgroup rows, (slot << 32) | chunk
+    int32_t *cnt;      // [set * 4 + kind], [set * 4 + 3] = chunks; [12] = ncol, [13] = nodes coloured
     uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
 };
 
@@ -75,7 +77,7 @@ __device__ __forceinline__ void jp_push(const JpQ &Q, int set, int32_t v, const 
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
 #pragma unroll
-    for (int kk = 0; kk < 3; ++kk) {
+    for (int kk = 0; kk < 2; ++kk) {
         uint64_t m = __ballot(k == kk);
         if (k == kk) {
             int leader = __ffsll((unsigned long long)m) - 1;
@@ -84,6 +86,14 @@ __device__ __forceinline__ void jp_push(const JpQ &Q, int set, int32_t v, const 
             base = __shfl(base, leader);
             Q.q[set][kk][base + (int32_t)__popcll(m & lt)] = v;
         }
+    }
+    // long rows (rare): a queue slot, and one work item per kHubChunk entries
+    if (k == 2) {
+        int32_t slot = atomicAdd(&Q.cnt[set * 4 + 2], 1);
+        Q.q[set][2][slot] = v;
+        int32_t nc = (int32_t)((off[v + 1] - off[v] + kHubChunk - 1) / kHubChunk);
+        int32_t c0 = atomicAdd(&Q.cnt[set * 4 + 3], nc);
+        for (int32_t c = 0; c < nc; ++c) Q.cq[set][c0 + c] = ((int64_t)slot << 32) | c;
     }
 }
 
@@ -100,10 +110,6 @@ __global__ void k_jp_seed(GraphView g, const int32_t *pending, int32_t *colour, 
     if (u >= g.n) return;
     colour[u] = -1;
     if (pending[u] == 0) jp_push(Q, 0, (int32_t)u, g.off);
-}
-
-__device__ __forceinline__ void jp_release(const JpQ &Q, int nxt, int32_t v, int32_t *pending, const int64_t *off) {
-    if (atomicSub(&pending[v], 1) == 1) jp_push(Q, nxt, v, off);
 }
 
 __device__ __forceinline__ void count_coloured(const JpQ &Q, int64_t c) {
@@ -166,8 +172,8 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
     __shared__ uint32_t wbm[kCT / kWave][kWinWords];
     __shared__ uint32_t bbm[kWinWords];
     const int set = r % 3, nxt = (r + 1) % 3, old = (r + 2) % 3;
-    if (blockIdx.x == 0 && threadIdx.x < 3) Q.cnt[old * 4 + threadIdx.x] = 0;
-    const int32_t ns = Q.cnt[set * 4 + 0], nm = Q.cnt[set * 4 + 1], nh = Q.cnt[set * 4 + 2];
+    if (blockIdx.x == 0 && threadIdx.x < 4) Q.cnt[old * 4 + threadIdx.x] = 0;
+    const int32_t ns = Q.cnt[set * 4 + 0], nm = Q.cnt[set * 4 + 1], nc = Q.cnt[set * 4 + 3];
     const int64_t gthreads = (int64_t)gridDim.x * kCT;
     const int64_t gtid = (int64_t)blockIdx.x * kCT + threadIdx.x;
     int64_t coloured = 0;
@@ -204,9 +210,12 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             maxc = cu + 1 > maxc ? cu + 1 : maxc;
             ++coloured;
         }
+        int32_t left[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) left[j] = (v[j] != u && !hi[j]) ? atomicSub(&pending[v[j]], 1) : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (v[j] != u && !hi[j]) jp_release(Q, nxt, v[j], pending, g.off);
+            if (left[j] == 1) jp_push(Q, nxt, v[j], g.off);
     }
     count_coloured(Q, coloured);
     wave_max_colour(Q, maxc);
@@ -250,41 +259,51 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             atomicMax(&Q.cnt[12], f + 1);
             atomicAdd(&Q.cnt[13], 1);
         }
+        int32_t left[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
-            if (v[j] != u && !((hi >> j) & 1u)) jp_release(Q, nxt, v[j], pending, g.off);
+            left[j] = (v[j] != u && !((hi >> j) & 1u)) ? atomicSub(&pending[v[j]], 1) : 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (left[j] == 1) jp_push(Q, nxt, v[j], g.off);
     }
-    // several workgroups per node.  nh <= grid: hub j takes the workgroups
-    // b = j, j + nh, j + 2 nh, ... (part k of nk); nh > grid: workgroup b takes
-    // hubs b, b + grid, ... alone.
-    if (nh > 0) {
-        const int64_t G = gridDim.x;
-        const bool spread = nh <= G;
-        for (int64_t j = spread ? (int64_t)blockIdx.x % nh : (int64_t)blockIdx.x; j < nh; j += spread ? nh : G) {
-            const int64_t k = spread ? (int64_t)blockIdx.x / nh : 0;
-            const int64_t nk = spread ? (G - j + nh - 1) / nh : 1;
-            int32_t u = Q.q[set][2][j];
-            const int64_t bu = node_base(g, u);
-            uint64_t hu = prio_hash(seed, level, u - bu);
-            int64_t e0 = g.off[u], e1 = g.off[u + 1];
-            for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
-            __syncthreads();
-            for (int64_t e = e0 + k * kCT + threadIdx.x; e < e1; e += nk * kCT) {
-                int32_t v = g.col[e];
-                if (v == u) continue;
-                if (prio_greater(prio_hash(seed, level, v - bu), v, hu, u)) {
-                    int32_t c = colour[v];
-                    if (c < kWin) atomicOr(&bbm[c >> 5], 1u << (c & 31));
-                } else {
-                    jp_release(Q, nxt, v, pending, g.off);
-                }
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < kWinWords; i += kCT)
-                if (bbm[i]) atomicOr(&Q.bitmap[j * kWinWords + i], bbm[i]);
-            __syncthreads();
-            if (spread) break;
+    // several workgroups per node: each work item is kHubChunk entries of one
+    // long row; its colours go into an LDS bitmap that is OR-ed into the row's
+    // global bitmap (the finishing launch picks the smallest free colour)
+    for (int64_t it = blockIdx.x; it < nc; it += gridDim.x) {
+        const int64_t item = Q.cq[set][it];
+        const int32_t j = (int32_t)(item >> 32);
+        const int64_t k = item & 0xffffffffLL;
+        int32_t u = Q.q[set][2][j];
+        const int64_t bu = node_base(g, u);
+        uint64_t hu = prio_hash(seed, level, u - bu);
+        const int64_t c0 = g.off[u] + k * kHubChunk, e1 = g.off[u + 1];
+        const int64_t c1 = c0 + kHubChunk < e1 ? c0 + kHubChunk : e1;
+        for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
+        __syncthreads();
+        int32_t v[4], c[4], left[4];
+        bool hi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int64_t e = c0 + q * kCT + threadIdx.x;
+            v[q] = e < c1 ? g.col[e] : u;
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hi[q] = v[q] != u && prio_greater(prio_hash(seed, level, v[q] - bu), v[q], hu, u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = hi[q] ? colour[v[q]] : kWin;
+            left[q] = (v[q] != u && !hi[q]) ? atomicSub(&pending[v[q]], 1) : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (c[q] < kWin) atomicOr(&bbm[c[q] >> 5], 1u << (c[q] & 31));
+            if (left[q] == 1) jp_push(Q, nxt, v[q], g.off);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < kWinWords; i += kCT)
+            if (bbm[i]) atomicOr(&Q.bitmap[(int64_t)j * kWinWords + i], bbm[i]);
+        __syncthreads();
     }
 }
 
@@ -359,13 +378,17 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     HIPCHK(hipStreamSynchronize(st));
     int64_t nhub = host_counters[0];
     // pending counts, 9 queues, counters, hub bitmaps
-    scr.reserve(align_up(n * 4) * 10 + 256 + align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4));
+    // work items of long rows in one set: at most nnz / kHubChunk + nhub
+    const int64_t ncap = g.nnz / kHubChunk + nhub + 1;
+    scr.reserve(align_up(n * 4) * 10 + 256 + align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4) +
+                3 * align_up(ncap * 8));
     int32_t *pending = (int32_t *)scr.get(n * 4);
     JpQ Q;
     for (int s = 0; s < 3; ++s)
         for (int k = 0; k < 3; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
     Q.cnt = (int32_t *)scr.get(16 * sizeof(int32_t));
     Q.bitmap = (uint32_t *)scr.get((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4);
+    for (int s = 0; s < 3; ++s) Q.cq[s] = (int64_t *)scr.get(ncap * 8);
     HIPCHK(hipMemsetAsync(pending, 0, n * 4, st));
     HIPCHK(hipMemsetAsync(Q.cnt, 0, 16 * sizeof(int32_t), st));
     HIPCHK(hipMemsetAsync(Q.bitmap, 0, (size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4, st));

@@ -17,10 +17,11 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
 // nodes that cannot move).
 // bin_entries[4]: CSR entries of the movable nodes of each bin (added to).
 // Nodes of the wave and block bins whose vol(u) does not fit 32 bits go to the
-// hub bin (the tables of those bins sum in 32 bits).
+// hub bin (the tables of those bins sum in 32 bits).  keep (batched runs, else
+// null): nodes of graphs g with keep[g.gid[u]] == 0 are left out (sentinel key).
 void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
                    int64_t b1, int64_t b2, int32_t *class_nodes, int64_t *bstart_dev,
-                   unsigned long long *bin_entries, Scratch &scr, hipStream_t st);
+                   unsigned long long *bin_entries, Scratch &scr, hipStream_t st, const uint8_t *keep = nullptr);
 
 // ---- move.hip
 struct MoveState {
@@ -33,10 +34,12 @@ struct MoveState {
     int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
     unsigned long long *moves_dev;  // move counter
     unsigned long long *cand_dev;   // distinct candidates evaluated per bin [4] (may be null)
+    unsigned long long *cand_sgl;   // of those in the hub bin, the one-workgroup hubs' (may be null)
     // batched runs: graph of each node, and per graph S and the 64-bit limit
     const int32_t *gid = nullptr;
     const int64_t *gS = nullptr;
     const int64_t *gwl = nullptr;
+    int32_t *gmoved = nullptr;  // set to 1 for the graph of every node that moves
 };
 
 __device__ __forceinline__ int64_t node_S(const MoveState &ms, int32_t u) { return ms.gid ? ms.gS[ms.gid[u]] : ms.S; }
@@ -82,8 +85,11 @@ constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
 constexpr int64_t kHubBucketTarget = 2048;
 constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol < 2^31) take one workgroup
 
+// ev (may be null): per kernel group (lane, wavefront, workgroup, one-workgroup
+// hub, partitioned hub) a start and a stop event, taken by the group's first
+// and last dispatch, for the groups whose bit is set in ev_mask and that launch
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, const hipEvent_t *ev, hipStream_t st);
+                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st);
 void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
 // row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
 // positions [begin, begin + count)

@@ -89,13 +89,13 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
 // key(u) = colour(u) * 4 + bin(u); nodes without a non-loop neighbour get the
 // sentinel key ncol * 4 (they can never move).
 __global__ void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
-                              int64_t b1, int64_t b2, uint32_t *keys, int32_t *vals,
+                              int64_t b1, int64_t b2, const uint8_t *keep, uint32_t *keys, int32_t *vals,
                               unsigned long long *bin_entries) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t cnt[4] = {0, 0, 0, 0};
     if (u < g.n) {
         int64_t e0 = g.off[u], d = g.off[u + 1] - e0;
-        bool active = d > 1 || (d == 1 && g.col[e0] != u);
+        bool active = (d > 1 || (d == 1 && g.col[e0] != u)) && (!keep || keep[g.gid[u]]);
         uint32_t bin = d <= b0 ? 0u : (d <= b1 ? 1u : (d <= b2 ? 2u : 3u));
         if ((bin == 1u || bin == 2u) && vol[u] > (int64_t)INT32_MAX) bin = 3u;
         keys[u] = active ? (uint32_t)colour[u] * 4u + bin : (uint32_t)ncol * 4u;
@@ -121,7 +121,7 @@ __global__ void k_bucket_bounds(const uint32_t *keys, int64_t n, int64_t nkeys, 
 
 void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
                    int64_t b1, int64_t b2, int32_t *class_nodes, int64_t *bstart_dev,
-                   unsigned long long *bin_entries, Scratch &scr, hipStream_t st) {
+                   unsigned long long *bin_entries, Scratch &scr, hipStream_t st, const uint8_t *keep) {
     int64_t n = g.n;
     if (n == 0) return;
     scr.reserve(2 * align_up(n * 4) * 2 + radix_scratch_bytes(n));
@@ -129,7 +129,7 @@ void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour
     int32_t *v = (int32_t *)scr.get(n * 4), *va = (int32_t *)scr.get(n * 4);
     void *rs = scr.get(radix_scratch_bytes(n));
     hipLaunchKernelGGL(k_bucket_keys, dim3((unsigned)cdiv(n, kThreads)), dim3(kThreads), 0, st, g, vol, colour, ncol,
-                       b0, b1, b2, k, v, bin_entries);
+                       b0, b1, b2, keep, k, v, bin_entries);
     int64_t nkeys = (int64_t)ncol * 4 + 1;  // including the sentinel
     radix_sort_u32_i32(&k, &v, &ka, &va, n, ceil_log2((uint64_t)nkeys), rs, st);
     hipLaunchKernelGGL(k_bucket_bounds, dim3((unsigned)cdiv(n + 1, kThreads)), dim3(kThreads), 0, st, k, n, nkeys,

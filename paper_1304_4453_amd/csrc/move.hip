@@ -18,6 +18,7 @@
 // through hash-partitioned staging.  The LDS tables sum weights in 32 bits:
 // the bucketing sends a node whose vol(u) (an upper bound of every w(u, X))
 // does not fit to the partitioned hub path, whose sums are 64-bit.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "level.h"
@@ -82,9 +83,12 @@ __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const
                                              int64_t wD, int64_t vu, int64_t base, int64_t S, const int64_t *volC) {
     G bg = 0;
     int32_t bx = kNone;
+    const G vb = (G)vu * (G)base;
 #pragma unroll
     for (int j = 0; j < kLaneMax; ++j) {
-        if (X[j] >= 0 && X[j] != D) {
+        // vol(X) >= 0 bounds the gain by S (w(u,X) - w(u,D\u)) + vol(u) vol(D\u):
+        // a candidate that cannot reach a positive gain is not gathered
+        if (X[j] >= 0 && X[j] != D && (G)S * (G)(W[j] - wD) + vb > 0) {
             G g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
             if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
         }
@@ -148,16 +152,20 @@ constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 
 // Scores the occupied slots of a table (and empties them).  Slots are taken
 // kEvalBatch per thread at a time, so that their community-volume gathers are
-// in flight together.
+// in flight together.  s(X) = S w(u,X) - vol(u) vol(X) <= S w(u,X) since
+// vol(X) >= 0, so a slot with S w(u,X) <= K (the score of staying) can never
+// be chosen and its volume is not gathered; the best of the remaining slots,
+// and whether it beats K, are exactly those of a full scan.
 constexpr int kEvalBatch = 8;
 
 template <typename G, typename V>
 __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, int64_t vu,
-                                           int64_t S, const int64_t *volC, bool clear, G &bs, int32_t &bx,
+                                           int64_t S, G K, const int64_t *volC, bool clear, G &bs, int32_t &bx,
                                            int64_t &ncand) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
         int64_t a[kEvalBatch], vc[kEvalBatch];
+        bool c[kEvalBatch];
 #pragma unroll
         for (int j = 0; j < kEvalBatch; ++j) {
             int s = s0 + j * step;
@@ -167,13 +175,14 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
                 a[j] = (int64_t)tv[s];
                 if (clear) { tk[s] = kEmpty; tv[s] = 0; }
             }
+            c[j] = X[j] >= 0 && (G)S * (G)a[j] > K;
         }
 #pragma unroll
-        for (int j = 0; j < kEvalBatch; ++j) vc[j] = X[j] >= 0 ? volC[X[j]] : 0;
+        for (int j = 0; j < kEvalBatch; ++j) vc[j] = c[j] ? volC[X[j]] : 0;
 #pragma unroll
         for (int j = 0; j < kEvalBatch; ++j) {
-            if (X[j] < 0) continue;
-            ++ncand;
+            ncand += X[j] >= 0;
+            if (!c[j]) continue;
             G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
             if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
         }
@@ -186,9 +195,9 @@ __device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, i
                                           int64_t &ncand) {
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    eval_slots<G, int32_t>(tk, tv, tsize, lane_id(), kWave, vu, S, volC, true, bs, bx, ncand);
+    const G K = (G)S * (G)wD - (G)vu * (G)base;
+    eval_slots<G, int32_t>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ncand);
     wave_argmax<G>(bs, bx);
-    G K = (G)S * (G)wD - (G)vu * (G)base;
     best_x = bx;
     move = bx != kNone && bs > K;
 }
@@ -284,20 +293,24 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
     __shared__ int32_t red_x[NT / kWave];
+    // w(u, D \ u) first (wD enters as this thread's share): the score of staying
+    // bounds which slots need their community volume
+    wD = wave_sum(wD);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) red_w[w] = wD;
+    __syncthreads();
+    wD = 0;
+    for (int j = 0; j < NT / kWave; ++j) wD += red_w[j];
+    const G K = (G)S * (G)wD - (G)vu * (G)base;
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    eval_slots<G, int32_t>(tk, tv, tsize, threadIdx.x, NT, vu, S, volC, true, bs, bx, ncand);
-    wD = wave_sum(wD);  // wD enters as this thread's share
+    eval_slots<G, int32_t>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ncand);
     wave_argmax<G>(bs, bx);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) { red_w[w] = wD; red_s[w] = bs; red_x[w] = bx; }
+    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int j = 1; j < NT / kWave; ++j) {
-            wD += red_w[j];
+        for (int j = 1; j < NT / kWave; ++j)
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
-        }
-        G K = (G)S * (G)wD - (G)vu * (G)base;
         *out = (bx != kNone && bs > K) ? bx : -1;
     }
 }
@@ -363,6 +376,7 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     else
         block_eval<int64_t, kSingleThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
+    count_candidates(ms.cand_sgl, ncand);
 }
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
@@ -502,7 +516,7 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
 // bucket into one flat index space that every thread strides over (a binary
 // search finds the chunk of an index).
 template <typename G>
-__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, int64_t vu, int64_t S,
+__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, int64_t vu, int64_t S, G K,
                                            const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
                                            int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
                                            int32_t &bx, int64_t &ncand) {
@@ -597,7 +611,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                 __syncthreads();
                 break;
             }
-            eval_slots<G, int64_t>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, volC, false, pbs, pbx, pc);
+            eval_slots<G, int64_t>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx, pc);
             __syncthreads();
         }
         if (ok) {
@@ -614,20 +628,35 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     __shared__ int64_t tv[kAggSlots];
     __shared__ int32_t cpre[kAggTile], cbase[kAggTile], wtot[kHubThreads / kWave];
     __shared__ int32_t nkeys, overflow;
+    __shared__ int64_t wred[kHubThreads / kWave];
     const int64_t hg = ha.agg_hub[blk0 + blockIdx.x];
     const int64_t p = blockIdx.x - ha.agg_first[hg];
     const int32_t u = ha.hub_u[hg];
     const int64_t vu = ms.vol[u];
+    // w(u, D \ u) from the chunk shares (written by the chunk launch) and the
+    // score of staying, which bounds the slots worth a volume gather
+    int64_t wD = 0;
+    for (int64_t j = threadIdx.x; j < ha.nchunk[hg]; j += kHubThreads) wD += ha.wd_part[ha.ins_first[hg] + j];
+    wD = wave_sum(wD);
+    if (lane_id() == 0) wred[threadIdx.x / kWave] = wD;
+    __syncthreads();
+    wD = 0;
+    for (int i = 0; i < kHubThreads / kWave; ++i) wD += wred[i];
+    const int32_t D = ms.zeta[u];
+    const int64_t base = ms.volC[D] - vu;
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
     const int64_t S_u = node_S(ms, u);
     if (force_wide || vu > node_wl(ms, u)) {
-        agg_bucket<i128>(ha, hg, p, vu, S_u, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ncand);
+        const i128 K = (i128)S_u * (i128)wD - (i128)vu * (i128)base;
+        agg_bucket<i128>(ha, hg, p, vu, S_u, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
+                         ncand);
         block_argmax<i128>(bs, bx);
     } else {
+        const int64_t K = S_u * wD - vu * base;
         int64_t b64 = neg_inf<int64_t>();
-        agg_bucket<int64_t>(ha, hg, p, vu, S_u, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
+        agg_bucket<int64_t>(ha, hg, p, vu, S_u, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
                             ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
@@ -687,6 +716,7 @@ __global__ __launch_bounds__(256) void k_apply(MoveState ms, int64_t begin, int6
             ms.zeta[u] = X;
             atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
             atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+            if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
             moved = 1;
         }
     }
@@ -708,48 +738,43 @@ __global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, const int
 // ------------------------------------------------------------------ launchers
 template <int WK>
 static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                          int fw, const hipEvent_t *ev, hipStream_t st) {
-    auto mark = [&](int i) {
-        if (ev) HIPCHK(hipEventRecord(ev[i], st));
-    };
-    mark(0);
+                          int fw, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
+    // start / stop events of kernel group i (taken by the dispatch itself)
+    auto t0 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i] : (hipEvent_t) nullptr; };
+    auto t1 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i + 1] : (hipEvent_t) nullptr; };
     if (cr.count[0] > 0)
-        hipLaunchKernelGGL(k_decide_lane<WK>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, g, ms,
-                           cr.begin[0], cr.count[0], fw);
-    mark(1);
+        hipExtLaunchKernelGGL(k_decide_lane<WK>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, t0(0),
+                              t1(0), 0, g, ms, cr.begin[0], cr.count[0], fw);
     if (cr.count[1] > 0) {
         int64_t blocks = cdiv(cr.count[1], 4);
-        hipLaunchKernelGGL(k_decide_wave<WK>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, g,
-                           ms, cr.begin[1], cr.count[1], fw);
+        hipExtLaunchKernelGGL(k_decide_wave<WK>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st,
+                              t0(1), t1(1), 0, g, ms, cr.begin[1], cr.count[1], fw);
     }
-    mark(2);
     if (cr.count[2] > 0) {
         int64_t blocks = cr.count[2];
-        hipLaunchKernelGGL(k_decide_block<WK>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(kBlockThreads),
-                           0, st, g, ms, cr.begin[2], cr.count[2], fw);
+        hipExtLaunchKernelGGL(k_decide_block<WK>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
+                              dim3(kBlockThreads), 0, st, t0(2), t1(2), 0, g, ms, cr.begin[2], cr.count[2], fw);
     }
-    mark(3);
     if (cr.sgl_count > 0)
-        hipLaunchKernelGGL(k_hub_single<WK>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, g, ms, ha,
-                           cr.sgl_base, fw);
+        hipExtLaunchKernelGGL(k_hub_single<WK>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, t0(3),
+                              t1(3), 0, g, ms, ha, cr.sgl_base, fw);
     if (cr.red_count > 0) {
-        hipLaunchKernelGGL(k_hub_part<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, g, ms, ha,
-                           cr.ins_base);
+        hipExtLaunchKernelGGL(k_hub_part<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, t0(4),
+                              (hipEvent_t) nullptr, 0, g, ms, ha, cr.ins_base);
         hipLaunchKernelGGL(k_hub_agg, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha, cr.agg_base,
                            fw);
-        hipLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st, ms, ha,
-                           cr.red_base);
+        hipExtLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st,
+                              (hipEvent_t) nullptr, t1(4), 0, ms, ha, cr.red_base);
     }
-    mark(4);
 }
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, const hipEvent_t *ev, hipStream_t st) {
+                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
     int fw = force_wide ? 1 : 0;
     switch (g.wkind) {
-        case 0: class_step_wk<0>(g, ms, cr, ha, fw, ev, st); break;
-        case 1: class_step_wk<1>(g, ms, cr, ha, fw, ev, st); break;
-        default: class_step_wk<2>(g, ms, cr, ha, fw, ev, st); break;
+        case 0: class_step_wk<0>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
+        case 1: class_step_wk<1>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
+        default: class_step_wk<2>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
     }
     HIPCHK(hipGetLastError());
 }
