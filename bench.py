@@ -57,6 +57,29 @@ def roofline(st, level=0):
             "kernels": KERNELS, "kernel_ms": ms, "kernel_bytes": by}
 
 
+def counter_traffic(kernel):
+    """Per-launch HBM traffic of a move-decide kernel group from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or
+    None when the kernels' source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "decide_traffic_rmat26.md")
+    src = os.path.join(ROOT, "paper_1304_4453_amd", "csrc", "move.hip")
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if blob["move_hip_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        for k in blob["kernels"]:
+            if k["kernel"] == kernel:
+                return {"bytes_per_launch": k["traffic_bytes_per_launch"],
+                        "algorithmic_bytes_per_launch_same_sweep": k["algorithmic_bytes_per_launch"],
+                        "fetch_scale": blob["fetch_scale"], "write_scale": blob["write_scale"],
+                        "source": "profiles/decide_traffic_rmat26.md (level-0 sweep 1)"}
+    except (OSError, KeyError, IndexError, ValueError):
+        return None
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -232,6 +255,34 @@ def batch_bench(args, P, torch, np):
     return out
 
 
+def sweep_probe(P, torch):
+    """One level-0 move sweep of the R-MAT 26 workload with every move-decide
+    kernel timed, after a 1 GiB device copy that calibrates the HBM byte
+    counters; for rocprofv3 --pmc runs.  Prints the sweep's per-kernel
+    algorithmic bytes and launch counts as one JSON line."""
+    import ctypes
+    import graphgen
+    wl = WORKLOADS["rmat26"]
+    dg = graphgen.rmat_gpu(wl["scale"], 16, seed=wl["seed"], weighted=wl["weighted"])
+    ctx = P.Context(dg.off_ptr, dg.col_ptr, dg.w_ptr, mem_kind=P.PLM_MEM_DEVICE, n=dg.n, nnz=dg.nnz, timing=1,
+                    validate=0)
+    dg.free()
+    x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")  # 1 GiB
+    y = x.clone()                                                # copy: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    del x, y
+    moves = ctx.move_sweep()
+    st = P.plm_stats_t()
+    P.plm_get_stats(ctx._c, ctypes.byref(st))
+    bb, bm = list(st.bin_bytes[0]), list(st.bin_ms[0])
+    out = {"workload": wl["desc"], "sweep": 1, "moves": moves, "kernels": KERNELS,
+           "kernel_bytes": [bb[0], bb[1], bb[2], st.hub_single_bytes[0], bb[3] - st.hub_single_bytes[0]],
+           "kernel_ms": [bm[0], bm[1], bm[2], st.hub_single_ms[0], bm[3] - st.hub_single_ms[0]],
+           "kernel_launches": list(st.kernel_launches[0]), "calibration_copy_bytes": 1 << 30}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +294,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256)
+    ap.add_argument("--sweep-probe", action="store_true",
+                    help="one instrumented level-0 sweep of R-MAT 26 for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -254,6 +307,9 @@ def main():
     import paper_1304_4453_amd as P
 
     torch.cuda.set_device(0)
+    if args.sweep_probe:
+        sweep_probe(P, torch)
+        return
     t = time.time()
     gr = make_graph(args.workload)
     log(f"graph {args.workload}: n={gr['n']} nnz={gr['nnz']} built in {time.time() - t:.1f}s")
@@ -296,6 +352,11 @@ def main():
     sweep_ms = sum(st["sweep_ms"])
     roof["timing"] = ("HIP events attached to each move-decide dispatch (hipExtLaunchKernelGGL) on the library's "
                       "stream, in one instrumented step before the timed steps; the timed steps run without events")
+    if args.workload == "rmat26":
+        tr = counter_traffic(roof["kernel"])
+        if tr is not None:
+            roof["traffic"] = tr["bytes_per_launch"]
+            roof["traffic_detail"] = tr
     out = {
         "metric": "PLM move-sweep edges/s",
         "value": value,
