@@ -159,6 +159,24 @@ def batch_params(seed: int, count: int, n_lo: float = 100.0, n_hi: float = 10000
     return n, k, pin, pout, gs
 
 
+def serve_params(seed: int, count: int, rate: float, scale_lo: int = 12, scale_hi: int = 22):
+    """Requests of the served workload: Poisson arrivals at `rate` per second
+    (exponential gaps), R-MAT scale uniform in [scale_lo, scale_hi] and a
+    per-request graph seed, all from counter-based draws of `seed`.
+    Returns (arrival times in s, scales, graph seeds)."""
+    arrivals = np.zeros(count, np.float64)
+    scales = np.zeros(count, np.int64)
+    seeds = np.zeros(count, np.uint64)
+    t = 0.0
+    for i in range(count):
+        u = ((draw(seed, 2, i) >> 11) + 1) * (1.0 / 9007199254740993.0)   # (0, 1]
+        t += -np.log(u) / rate
+        arrivals[i] = t
+        scales[i] = scale_lo + draw(seed, 1, i) % (scale_hi - scale_lo + 1)
+        seeds[i] = draw(seed, 3, i) & 0xFFFFFFFF
+    return arrivals, scales, seeds
+
+
 def sbm_batch(seed: int, count: int, n_lo: float = 100.0, n_hi: float = 100000.0) -> list[Graph]:
     n, k, pin, pout, gs = batch_params(seed, count, n_lo, n_hi)
     return [sbm(int(n[i]), int(k[i]), float(pin[i]), float(pout[i]), int(gs[i])) for i in range(count)]

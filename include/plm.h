@@ -165,6 +165,58 @@ plm_status plm_batch_create(plm_ctx **out, int64_t num_graphs, const int64_t *no
  * output may be NULL.  PLM_E_STATE on a context from plm_create. */
 plm_status plm_batch_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out);
 
+/* ---------------------------------------------------------------- serving
+ * A request server over the batched engine: each request is one graph (CSR as
+ * for plm_create); its result equals plm_run on it.  plm_server_step admits
+ * queued requests in submission order while their resident footprint (CSR,
+ * per-node state and contraction buffers: 8(n+1) + 4 nnz (+4 nnz with
+ * weights) + 128 n + 64 nnz bytes) stays within hbm_budget_bytes and their
+ * entries within max_batch_entries (at least one request per step), copies
+ * them side by side into device memory, runs them as one batch
+ * (plm_batch_run) and completes them.  Results stay in device memory until
+ * plm_server_result fetches them.  The options are those of the batches
+ * (colour schedule, int_mode auto or 128, else PLM_E_ARG).  A server is used
+ * by one host thread at a time. */
+typedef struct plm_server plm_server;
+
+typedef struct {
+    int64_t queued;        /* submitted, not yet admitted */
+    int64_t completed;     /* completed since creation */
+    int64_t batches;       /* steps that ran a batch */
+    int64_t held_results;  /* completed or failed, not yet fetched */
+    int64_t budget_bytes;
+} plm_server_info_t;
+
+plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t max_batch_entries,
+                             void *hip_stream, const plm_options *opt);
+
+/* Queues one graph without copying it: offsets/cols/weights (mem_kind) must
+ * stay valid and unchanged until the request is admitted by a step.  Checks
+ * offsets[0] = 0 and offsets[n] = nnz (PLM_E_GRAPH); a request whose footprint
+ * alone exceeds the budget is refused (PLM_E_BUDGET).  *request_id identifies
+ * it in plm_server_result. */
+plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
+                             const int32_t *weights, int32_t mem_kind, int64_t *request_id);
+
+/* Runs one batch of admitted requests (nothing when the queue is empty);
+ * *completed_out = requests completed by it.  A request that fails (invalid
+ * graph, allocation) is completed with its error, reported by
+ * plm_server_result; when validation refuses a batch of several requests,
+ * they are queued again at the front and run one per step, so that only the
+ * invalid ones fail. */
+plm_status plm_server_step(plm_server *s, int32_t *completed_out);
+
+/* *ready_out = 0 while the request waits.  Once it has run: its canonical
+ * labels[n] (mem_kind; NULL to discard), *q_out and *levels_out as plm_run
+ * gives them, *ready_out = 1, and the request is released (its id becomes
+ * unknown, PLM_E_ARG).  A failed request returns its error here, once. */
+plm_status plm_server_result(plm_server *s, int64_t request_id, int32_t *labels, int32_t mem_kind, double *q_out,
+                             int32_t *levels_out, int32_t *ready_out);
+
+plm_status plm_server_info(plm_server *s, plm_server_info_t *out);
+void plm_server_destroy(plm_server *s);
+const char *plm_server_last_error(const plm_server *s);
+
 /* Resets the context to level 0 with singleton communities. */
 plm_status plm_reset(plm_ctx *ctx);
 

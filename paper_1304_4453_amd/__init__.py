@@ -67,6 +67,11 @@ class plm_stats_t(ctypes.Structure):
                 ("kernel_launches", (ctypes.c_int64 * 5) * _L)]
 
 
+class plm_server_info_t(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("held_results", ctypes.c_int64), ("budget_bytes", ctypes.c_int64)]
+
+
 class PLMError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
@@ -98,7 +103,17 @@ def _load():
     lib.plm_get_stats.argtypes = [vp, P(plm_stats_t)]
     lib.plm_batch_create.argtypes = [P(vp), i64, vp, i64, vp, vp, vp, i32, vp, P(plm_options)]
     lib.plm_batch_run.argtypes = [vp, vp, vp, vp]
-    for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
+    lib.plm_server_create.argtypes = [P(vp), i64, i64, vp, P(plm_options)]
+    lib.plm_server_submit.argtypes = [vp, i64, i64, vp, vp, vp, i32, P(i64)]
+    lib.plm_server_step.argtypes = [vp, P(i32)]
+    lib.plm_server_result.argtypes = [vp, i64, vp, i32, P(dbl), P(i32), P(i32)]
+    lib.plm_server_info.argtypes = [vp, P(plm_server_info_t)]
+    lib.plm_server_destroy.argtypes = [vp]
+    lib.plm_server_destroy.restype = None
+    lib.plm_server_last_error.argtypes = [vp]
+    lib.plm_server_last_error.restype = ctypes.c_char_p
+    for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_server_create", "plm_server_submit",
+              "plm_server_step", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
               "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
         getattr(lib, f).restype = i32
     return lib
@@ -122,6 +137,13 @@ plm_get_graph = _lib.plm_get_graph
 plm_get_stats = _lib.plm_get_stats
 plm_batch_create = _lib.plm_batch_create
 plm_batch_run = _lib.plm_batch_run
+plm_server_create = _lib.plm_server_create
+plm_server_submit = _lib.plm_server_submit
+plm_server_step = _lib.plm_server_step
+plm_server_result = _lib.plm_server_result
+plm_server_info = _lib.plm_server_info
+plm_server_destroy = _lib.plm_server_destroy
+plm_server_last_error = _lib.plm_server_last_error
 
 
 def default_options(**kw) -> plm_options:
@@ -326,3 +348,92 @@ class BatchContext(Context):
         lv = np.zeros(max(self.G, 1), np.int32)
         self._check(plm_batch_run(self._c, _ptr(labels), q.ctypes.data, lv.ctypes.data))
         return labels, q[: self.G], lv[: self.G]
+
+
+class Server:
+    """Owns one plm_server.  submit() queues a graph without copying it: the
+    caller keeps the arrays (numpy for host, torch tensors or addresses for
+    device memory) alive until a step has admitted it."""
+
+    def __init__(self, hbm_budget_bytes: int, max_batch_entries: int = 1 << 40, stream=None, **options):
+        self._s = ctypes.c_void_p()
+        sp = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
+        self.opt = default_options(**options)
+        rc = plm_server_create(ctypes.byref(self._s), hbm_budget_bytes, max_batch_entries, sp or 0,
+                               ctypes.byref(self.opt))
+        if rc != 0:
+            raise PLMError(rc, "plm_server_create failed")
+        self._held = {}
+
+    def _check(self, rc):
+        if rc != 0:
+            raise PLMError(rc, plm_server_last_error(self._s).decode())
+
+    def submit(self, off, col, w=None, mem_kind: int | None = None, n: int | None = None,
+               nnz: int | None = None) -> int:
+        if mem_kind is None:
+            mem_kind = PLM_MEM_HOST if isinstance(off, np.ndarray) else PLM_MEM_DEVICE
+        if mem_kind == PLM_MEM_HOST:
+            off = np.ascontiguousarray(off, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            if w is not None:
+                w = np.ascontiguousarray(w, dtype=np.int32)
+        if n is None:
+            n = int(off.shape[0]) - 1
+        if nnz is None:
+            nnz = int(col.shape[0])
+        rid = ctypes.c_int64()
+        self._check(plm_server_submit(self._s, n, nnz, _ptr(off), _ptr(col), _ptr(w), mem_kind, ctypes.byref(rid)))
+        self._held[rid.value] = (off, col, w, n)
+        return rid.value
+
+    def step(self) -> int:
+        c = ctypes.c_int32()
+        self._check(plm_server_step(self._s, ctypes.byref(c)))
+        return c.value
+
+    def result(self, rid: int, labels=None, mem_kind: int | None = None):
+        """(ready, labels, q, levels); labels: output buffer or None for a new
+        numpy array (when the request's inputs were host arrays) or discarded."""
+        held = self._held.get(rid)
+        n = held[3] if held else 0
+        if labels is None and held and isinstance(held[0], np.ndarray):
+            labels = np.zeros(max(n, 1), np.int32)
+        if mem_kind is None:
+            mem_kind = PLM_MEM_HOST if labels is None or isinstance(labels, np.ndarray) else PLM_MEM_DEVICE
+        q, lv, ready = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
+        try:
+            self._check(plm_server_result(self._s, rid, _ptr(labels), mem_kind, ctypes.byref(q), ctypes.byref(lv),
+                                          ctypes.byref(ready)))
+        except PLMError:
+            self._held.pop(rid, None)
+            raise
+        if not ready.value:
+            return False, None, None, None
+        self._held.pop(rid, None)
+        if isinstance(labels, np.ndarray):
+            labels = labels[:n]
+        return True, labels, q.value, lv.value
+
+    def info(self) -> plm_server_info_t:
+        i = plm_server_info_t()
+        self._check(plm_server_info(self._s, ctypes.byref(i)))
+        return i
+
+    def close(self):
+        if self._s:
+            plm_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+        self._held = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -837,36 +837,50 @@ namespace {
 
 // Shared by plm_create (G = 0) and plm_batch_create (G >= 1 graphs on the node
 // ranges node_base[0..G]).
+// adopt: offsets/cols/weights are device buffers from hipMalloc that the new
+// context takes over (freed with it, also when creation fails) instead of copying
 plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t n, int64_t nnz,
                        const int64_t *offsets, const int32_t *cols, const int32_t *weights, int32_t mem_kind,
-                       void *hip_stream, const plm_options *opt) {
+                       void *hip_stream, const plm_options *opt, bool adopt = false) {
     g_create_error.clear();
     if (out) *out = nullptr;
     auto fail = [&](int code, const std::string &m) {
         g_create_error = m;
         return code;
     };
-    if (!out) return fail(PLM_E_ARG, "out is NULL");
-    if (n < 0 || n >= (1LL << 31)) return fail(PLM_E_ARG, "n must lie in [0, 2^31)");
-    if (nnz < 0 || nnz >= (1LL << 40)) return fail(PLM_E_ARG, "nnz must lie in [0, 2^40)");
-    if (!offsets) return fail(PLM_E_ARG, "offsets is NULL");
-    if (nnz > 0 && !cols) return fail(PLM_E_ARG, "cols is NULL");
-    if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) return fail(PLM_E_ARG, "bad mem_kind");
+    // adopted buffers not yet handed to a level are freed on every error path
+    auto release_adopted = [&]() {
+        if (!adopt) return;
+        adopt = false;
+        (void)hipFree(const_cast<int64_t *>(offsets));
+        (void)hipFree(const_cast<int32_t *>(cols));
+        if (weights) (void)hipFree(const_cast<int32_t *>(weights));
+    };
+    auto fail_adopt = [&](int code, const std::string &m) {
+        release_adopted();
+        return fail(code, m);
+    };
+    if (!out) return fail_adopt(PLM_E_ARG, "out is NULL");
+    if (n < 0 || n >= (1LL << 31)) return fail_adopt(PLM_E_ARG, "n must lie in [0, 2^31)");
+    if (nnz < 0 || nnz >= (1LL << 40)) return fail_adopt(PLM_E_ARG, "nnz must lie in [0, 2^40)");
+    if (!offsets) return fail_adopt(PLM_E_ARG, "offsets is NULL");
+    if (nnz > 0 && !cols) return fail_adopt(PLM_E_ARG, "cols is NULL");
+    if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) return fail_adopt(PLM_E_ARG, "bad mem_kind");
     plm_options o;
     plm_default_options(&o);
     if (opt) o = *opt;
     std::string m;
     int rc = check_options(o, m);
-    if (rc) return fail(rc, m);
+    if (rc) return fail_adopt(rc, m);
     if (G > 0) {
-        if (o.schedule != PLM_SCHEDULE_COLOUR) return fail(PLM_E_ARG, "batched runs use the colour schedule");
-        if (o.int_mode == PLM_INT_64) return fail(PLM_E_ARG, "batched runs take int_mode auto or 128");
-        if (node_base[0] != 0) return fail(PLM_E_ARG, "node_base[0] must be 0");
+        if (o.schedule != PLM_SCHEDULE_COLOUR) return fail_adopt(PLM_E_ARG, "batched runs use the colour schedule");
+        if (o.int_mode == PLM_INT_64) return fail_adopt(PLM_E_ARG, "batched runs take int_mode auto or 128");
+        if (node_base[0] != 0) return fail_adopt(PLM_E_ARG, "node_base[0] must be 0");
         for (int64_t g = 0; g < G; ++g)
-            if (node_base[g + 1] < node_base[g]) return fail(PLM_E_ARG, "node_base must be non-decreasing");
+            if (node_base[g + 1] < node_base[g]) return fail_adopt(PLM_E_ARG, "node_base must be non-decreasing");
     }
     if (mem_kind == PLM_MEM_HOST) {
-        if (offsets[0] != 0 || offsets[n] != nnz) return fail(PLM_E_GRAPH, "offsets[0] must be 0 and offsets[n] = nnz");
+        if (offsets[0] != 0 || offsets[n] != nnz) return fail_adopt(PLM_E_GRAPH, "offsets[0] must be 0 and offsets[n] = nnz");
     }
     plm_ctx *c = nullptr;
     try {
@@ -880,15 +894,23 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         LevelData l0;
         l0.n = n;
         l0.nnz = nnz;
-        l0.off = dev_alloc<int64_t>(n + 1);
-        l0.col = dev_alloc<int32_t>(nnz);
         l0.wkind = weights ? 1 : 0;
         l0.diag_mult = 2;
-        if (weights) l0.w = dev_alloc<int32_t>(nnz);
-        c->levels.push_back(l0);
-        copy_in(l0.off, offsets, (size_t)(n + 1) * 8, mem_kind, c->st);
-        copy_in(l0.col, cols, (size_t)nnz * 4, mem_kind, c->st);
-        if (weights) copy_in(l0.w, weights, (size_t)nnz * 4, mem_kind, c->st);
+        if (adopt) {
+            l0.off = const_cast<int64_t *>(offsets);
+            l0.col = const_cast<int32_t *>(cols);
+            l0.w = const_cast<int32_t *>(weights);
+            adopt = false;  // owned by the level from here on
+            c->levels.push_back(l0);
+        } else {
+            l0.off = dev_alloc<int64_t>(n + 1);
+            l0.col = dev_alloc<int32_t>(nnz);
+            if (weights) l0.w = dev_alloc<int32_t>(nnz);
+            c->levels.push_back(l0);
+            copy_in(l0.off, offsets, (size_t)(n + 1) * 8, mem_kind, c->st);
+            copy_in(l0.col, cols, (size_t)nnz * 4, mem_kind, c->st);
+            if (weights) copy_in(l0.w, weights, (size_t)nnz * 4, mem_kind, c->st);
+        }
         HIPCHK(hipStreamSynchronize(c->st));
         if (G > 0) {
             c->batch = true;
@@ -940,14 +962,27 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c->init_level();
     } catch (const Error &e) {
         delete c;
+        release_adopted();
         return fail(e.code, e.msg);
     } catch (const std::exception &e) {
         delete c;
+        release_adopted();
         return fail(PLM_E_NOMEM, e.what());
     }
     *out = c;
     return PLM_OK;
 }
+
+}  // namespace
+
+// Batched context over a disjoint-union CSR already in device memory (hipMalloc
+// buffers the context adopts; used by the request server in serve.hip).
+plm_status plm_internal_batch_adopt(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t nnz, int64_t *off,
+                                    int32_t *col, int32_t *w, void *hip_stream, const plm_options *opt) {
+    return create_impl(out, G, node_base, node_base[G], nnz, off, col, w, PLM_MEM_DEVICE, hip_stream, opt, true);
+}
+
+namespace {
 
 void reject_batch(plm_ctx *ctx, const char *what) {
     if (ctx->batch) throw Error{PLM_E_STATE, std::string(what) + " does not apply to a batched context"};

@@ -115,6 +115,37 @@ def test_argument_errors_need_no_gpu(built):
     assert not c.value
 
 
+def test_server_queue_needs_no_gpu(built):
+    """Creation, submission, queue accounting and argument errors of the
+    request server run on the host only."""
+    import numpy as np
+    import graphgen
+    import paper_1304_4453_amd as P
+    s = ctypes.c_void_p()
+    assert P.plm_server_create(None, 1 << 30, 1 << 20, None, None) == P.PLM_E_ARG
+    assert P.plm_server_create(ctypes.byref(s), 0, 1 << 20, None, None) == P.PLM_E_ARG
+    seq = P.default_options(schedule=P.PLM_SCHEDULE_SEQUENTIAL)
+    assert P.plm_server_create(ctypes.byref(s), 1 << 30, 1 << 20, None, ctypes.byref(seq)) == P.PLM_E_ARG
+    g = graphgen.disjoint_cliques(2, 4)
+    srv = P.Server(1 << 30)
+    a = srv.submit(g.off, g.col, g.w)
+    b = srv.submit(g.off, g.col, g.w)
+    assert (a, b) == (0, 1) and srv.info().queued == 2 and srv.info().budget_bytes == 1 << 30
+    ready, _, _, _ = srv.result(a)
+    assert not ready
+    with pytest.raises(P.PLMError) as e:
+        srv.submit(np.array([0, 3], np.int64), np.zeros(2, np.int32))   # offsets[n] != nnz
+    assert e.value.status == P.PLM_E_GRAPH
+    tiny = P.Server(64)
+    with pytest.raises(P.PLMError) as e:
+        tiny.submit(g.off, g.col, g.w)
+    assert e.value.status == P.PLM_E_BUDGET
+    with pytest.raises(P.PLMError) as e:
+        srv.result(99)
+    assert e.value.status == P.PLM_E_ARG
+    assert P.plm_server_step(None, None) == P.PLM_E_ARG
+
+
 def test_pack_batch_is_the_disjoint_union(built):
     import numpy as np
     import graphgen

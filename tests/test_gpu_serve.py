@@ -1,0 +1,148 @@
+"""The request server (plm_server_*): every completed request carries exactly
+the oracle's run on its graph (labels, Q bit for bit, levels), whatever it was
+batched with; admission keeps submission order under the HBM budget and the
+per-batch entry cap; an invalid graph fails alone."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1304_4453_amd as P
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _graphs():
+    return [
+        graphgen.planted_partition_1000(seed=5),
+        graphgen.rmat(11, 16, seed=21, weighted=False),
+        graphgen.ring_of_cliques(6, 4),
+        graphgen.from_edges(4, []),
+        graphgen.random_graph(90, 0.08, seed=8, weighted=True, loops=0.2),
+        graphgen.rmat(12, 16, seed=22, weighted=True),
+        graphgen.disjoint_edges(5),
+    ]
+
+
+def _check(g, res):
+    ready, labels, q, lv = res
+    r = oracle.run(g.off, g.col, g.w)
+    assert ready
+    assert np.array_equal(labels, r.labels[: g.n]) and q == r.q and lv == r.levels
+
+
+def _drain(srv, ids):
+    out = {}
+    steps = 0
+    while len(out) < len(ids):
+        srv.step()
+        steps += 1
+        for i in ids:
+            if i not in out:
+                res = srv.result(i)
+                if res[0]:
+                    out[i] = res
+        assert steps <= 4 * len(ids)
+    return out, steps
+
+
+def test_server_results_match_oracle(P):
+    _say("server: one batch")
+    gs = _graphs()
+    with P.Server(1 << 34) as srv:
+        ids = [srv.submit(g.off, g.col, g.w) for g in gs]
+        out, steps = _drain(srv, ids)
+        assert steps == 1 and srv.info().completed == len(gs) and srv.info().batches == 1
+    for g, i in zip(gs, ids):
+        _check(g, out[i])
+
+
+def test_server_budget_keeps_order(P):
+    _say("server: tight budget")
+    gs = _graphs()
+    # the budget holds the largest request alone, so the requests take several steps
+    fp = [8 * (g.n + 1) + (8 if g.w is not None else 4) * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
+    with P.Server(max(fp) + 1) as srv:
+        ids = [srv.submit(g.off, g.col, g.w) for g in gs]
+        out, steps = {}, 0
+        while len(out) < len(ids):
+            srv.step()
+            steps += 1
+            assert steps <= len(ids)
+            # submission order: the completed requests are always a prefix
+            first_waiting = None
+            for k, i in enumerate(ids):
+                if i in out:
+                    continue
+                res = srv.result(i)
+                if res[0]:
+                    assert first_waiting is None, f"request {k} completed before an earlier one"
+                    out[i] = res
+                elif first_waiting is None:
+                    first_waiting = k
+        assert steps > 1
+    for g, i in zip(gs, ids):
+        _check(g, out[i])
+
+
+def test_server_entry_cap(P):
+    _say("server: entry cap")
+    gs = [graphgen.rmat(10, 16, seed=s, weighted=False) for s in range(4)]
+    with P.Server(1 << 34, max_batch_entries=max(g.nnz for g in gs)) as srv:
+        ids = [srv.submit(g.off, g.col, g.w) for g in gs]
+        out, steps = _drain(srv, ids)
+        assert steps == len(gs)
+    for g, i in zip(gs, ids):
+        _check(g, out[i])
+
+
+def test_server_device_inputs_and_invalid_request(P):
+    import torch
+    _say("server: device inputs, invalid request")
+    gs = _graphs()[:3]
+    d = torch.device("cuda:0")
+    bad = graphgen.disjoint_cliques(2, 3)
+    bad_col = bad.col.copy()
+    bad_col[0] = 2                      # row 0 becomes [2, 2]: not strictly ascending
+    with P.Server(1 << 34) as srv:
+        keep = []
+        ids = []
+        for k, g in enumerate(gs):
+            if k == 1:
+                ids.append(srv.submit(bad.off, bad_col, bad.w))
+            t = [torch.from_numpy(x).to(d) for x in (g.off, g.col)] + \
+                [None if g.w is None else torch.from_numpy(g.w).to(d)]
+            keep.append(t)
+            ids.append(srv.submit(t[0], t[1], t[2], n=g.n, nnz=g.nnz))
+        for _ in range(8):
+            srv.step()
+            if srv.info().queued == 0:
+                break
+        assert srv.info().queued == 0
+        bad_id = ids.pop(1)
+        with pytest.raises(P.PLMError) as e:
+            srv.result(bad_id)
+        assert e.value.status == P.PLM_E_GRAPH
+        for g, i in zip(gs, ids):
+            lab = torch.empty(max(g.n, 1), dtype=torch.int32, device=d)
+            ready, _, q, lv = srv.result(i, lab)
+            _check(g, (ready, lab.cpu().numpy()[: g.n], q, lv))
+
+
+def test_server_empty_step(P):
+    with P.Server(1 << 30) as srv:
+        assert srv.step() == 0 and srv.info().batches == 0

@@ -64,3 +64,18 @@ def test_small_families():
     assert g.undirected_edges() == 5 * 6 + 5
     g = graphgen.random_graph(30, 0.3, seed=1, loops=0.5)
     _check_csr(g, loops_allowed=True)
+
+
+def test_serve_params_recipe():
+    """Served workload: deterministic, exponential gaps of mean 1/rate, scales
+    uniform over [12, 22], distinct request seeds."""
+    a1, s1, d1 = graphgen.serve_params(5, 4000, 200.0)
+    a2, s2, d2 = graphgen.serve_params(5, 4000, 200.0)
+    assert np.array_equal(a1, a2) and np.array_equal(s1, s2) and np.array_equal(d1, d2)
+    gaps = np.diff(np.concatenate([[0.0], a1]))
+    assert np.all(gaps > 0) and abs(gaps.mean() - 1 / 200.0) < 0.1 / 200.0
+    assert abs(np.median(gaps) - np.log(2) / 200.0) < 0.15 / 200.0      # exponential median
+    assert s1.min() == 12 and s1.max() == 22
+    counts = np.bincount(s1 - 12)
+    assert counts.min() > 4000 / 11 * 0.8
+    assert len(np.unique(d1)) == 4000
