@@ -24,7 +24,7 @@ MAX_SWEEPS = 64
 
 class _Options(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("schedule", ctypes.c_int32), ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class _Trace(ctypes.Structure):
@@ -32,7 +32,9 @@ class _Trace(ctypes.Structure):
                 ("n", ctypes.c_int64 * MAX_LEVELS), ("nnz", ctypes.c_int64 * MAX_LEVELS),
                 ("colours", ctypes.c_int64 * MAX_LEVELS), ("sweeps", ctypes.c_int64 * MAX_LEVELS),
                 ("communities", ctypes.c_int64 * MAX_LEVELS),
-                ("moves", (ctypes.c_int64 * MAX_SWEEPS) * MAX_LEVELS), ("S", ctypes.c_int64)]
+                ("moves", (ctypes.c_int64 * MAX_SWEEPS) * MAX_LEVELS),
+                ("ref_sweeps", ctypes.c_int64 * MAX_LEVELS), ("ref_moves", ctypes.c_int64 * MAX_LEVELS),
+                ("S", ctypes.c_int64)]
 
 
 def build(force: bool = True) -> None:
@@ -237,17 +239,21 @@ class RunResult:
     communities: list = field(default_factory=list)
     moves: list = field(default_factory=list)
     S: int = 0
+    ref_sweeps: list = field(default_factory=list)   # PLMR: sweeps of the move after prolongation, per level
+    ref_moves: list = field(default_factory=list)
 
 
-def run(off, col, w=None, max_sweeps: int = 32, max_levels: int = 0, seed: int = 0, schedule: int = 0) -> RunResult:
-    """Full multilevel PLM (Algorithm 3) with canonical output labels."""
+def run(off, col, w=None, max_sweeps: int = 32, max_levels: int = 0, seed: int = 0, schedule: int = 0,
+        refine: bool = False) -> RunResult:
+    """Full multilevel PLM (Algorithm 3), or PLMR (Algorithm 4) with refine,
+    with canonical output labels."""
     off, col = _i64(off), _i32(col)
     n = off.shape[0] - 1
     wp = None
     if w is not None:
         w = _i64(w)
         wp = _p(w, ctypes.c_int64)
-    opt = _Options(max_sweeps, max_levels, schedule, 0, seed)
+    opt = _Options(max_sweeps, max_levels, schedule, 1 if refine else 0, seed)
     tr = _Trace()
     labels = np.zeros(max(n, 1), np.int32)
     q = ctypes.c_double()
@@ -259,4 +265,5 @@ def run(off, col, w=None, max_sweeps: int = 32, max_levels: int = 0, seed: int =
     return RunResult(labels[:n].copy(), float(q.value), L, [tr.n[i] for i in range(L)],
                      [tr.nnz[i] for i in range(L)], [tr.colours[i] for i in range(L)],
                      [tr.sweeps[i] for i in range(L)], [tr.communities[i] for i in range(L)],
-                     [[tr.moves[i][s] for s in range(tr.sweeps[i])] for i in range(L)], int(tr.S))
+                     [[tr.moves[i][s] for s in range(tr.sweeps[i])] for i in range(L)], int(tr.S),
+                     [tr.ref_sweeps[i] for i in range(L)], [tr.ref_moves[i] for i in range(L)])

@@ -385,7 +385,7 @@ typedef struct {
     int32_t max_sweeps;   /* per level, >= 1 */
     int32_t max_levels;   /* 0 = unlimited */
     int32_t schedule;     /* 0 colour classes, 1 sequential */
-    int32_t pad;
+    int32_t refine;       /* 1: PLMR (Algorithm 4), a move phase after every prolongation */
     uint64_t seed;
 } orc_options;
 
@@ -397,6 +397,8 @@ typedef struct {
     int64_t n[ORC_MAX_LEVELS], nnz[ORC_MAX_LEVELS], colours[ORC_MAX_LEVELS], sweeps[ORC_MAX_LEVELS];
     int64_t communities[ORC_MAX_LEVELS];
     int64_t moves[ORC_MAX_LEVELS][ORC_MAX_SWEEPS];
+    int64_t ref_sweeps[ORC_MAX_LEVELS];   /* refinement (PLMR): sweeps of the move after prolongation */
+    int64_t ref_moves[ORC_MAX_LEVELS];    /* and the nodes moved by it */
     int64_t S;
 } orc_trace;
 
@@ -415,6 +417,60 @@ void orc_canonical(int64_t n, const int32_t *lab, int32_t *out) {
 /* Algorithm 3 under the colour-class schedule.  w: input weights (self-loops
  * given once) or NULL for unit weights.  labels[n] receives canonical labels.
  * Returns 0 on success, -1 on bad options or allocation failure. */
+/* PLMR, Algorithm 4, on the graph (n, off, col, w2) (doubled diagonal) at the
+ * given level: move from singletons; if communities merged (and the level cap
+ * allows), coarsen, recurse, prolong the coarse result (the community of u is
+ * that of its coarse node, named by its coarse id) and move again from it.
+ * Leaves the communities in zeta_out[n]; returns the number of levels below
+ * and including this one. */
+static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, int32_t level,
+                        const orc_options *opt, int32_t *zeta_out, orc_trace *tr) {
+    int64_t nnz = off[n];
+    int64_t *vol = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *volC = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int32_t *colour = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t S = orc_volumes(n, off, w2, vol);
+    int64_t ncol = orc_colour(n, off, col, opt->seed, level, opt->schedule, colour);
+    /* move from singletons */
+    for (int64_t u = 0; u < n; ++u) { zeta_out[u] = (int32_t)u; volC[u] = vol[u]; }
+    int64_t sweeps = 0;
+    if (level < ORC_MAX_LEVELS) { tr->n[level] = n; tr->nnz[level] = nnz; tr->colours[level] = ncol; }
+    for (int32_t s = 0; s < opt->max_sweeps; ++s) {
+        int64_t mv = orc_sweep(n, off, col, w2, vol, S, colour, ncol, zeta_out, volC);
+        if (level < ORC_MAX_LEVELS) tr->moves[level][s] = mv;
+        ++sweeps;
+        if (mv == 0) break;
+    }
+    int32_t *pi = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t k = orc_relabel(n, zeta_out, pi);
+    if (level < ORC_MAX_LEVELS) { tr->sweeps[level] = sweeps; tr->communities[level] = k; }
+    int32_t depth = 1;
+    if (k < n && !(opt->max_levels > 0 && level + 1 >= opt->max_levels)) {
+        /* coarsen, recurse, prolong */
+        int64_t *coff = (int64_t *)malloc(((size_t)k + 1) * sizeof(int64_t));
+        int32_t *ccol = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+        int64_t *cw = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+        orc_contract(n, off, col, w2, pi, k, coff, ccol, cw);
+        int32_t *zc = (int32_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(int32_t));
+        depth += orc_plmr(k, coff, ccol, cw, level + 1, opt, zc, tr);
+        for (int64_t u = 0; u < n; ++u) zeta_out[u] = zc[pi[u]];
+        free(zc); free(coff); free(ccol); free(cw);
+        /* move again, from the prolonged communities */
+        for (int64_t u = 0; u < n; ++u) volC[u] = 0;
+        for (int64_t u = 0; u < n; ++u) volC[zeta_out[u]] += vol[u];
+        int64_t rs = 0, rm = 0;
+        for (int32_t s = 0; s < opt->max_sweeps; ++s) {
+            int64_t mv = orc_sweep(n, off, col, w2, vol, S, colour, ncol, zeta_out, volC);
+            ++rs;
+            rm += mv;
+            if (mv == 0) break;
+        }
+        if (level < ORC_MAX_LEVELS) { tr->ref_sweeps[level] = rs; tr->ref_moves[level] = rm; }
+    }
+    free(pi); free(vol); free(volC); free(colour);
+    return depth;
+}
+
 int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, const orc_options *opt,
             int32_t *labels, double *q_out, orc_trace *tr) {
     if (opt->max_sweeps < 1 || opt->max_sweeps > ORC_MAX_SWEEPS) return -1;
@@ -422,6 +478,16 @@ int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w,
     int64_t nnz = off[n];
     int64_t *w2_0 = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
     orc_double_diagonal(n, off, col, w, w2_0);
+    if (opt->refine) {
+        int32_t *zeta = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+        tr->levels = orc_plmr(n, off, col, w2_0, 0, opt, zeta, tr);
+        tr->S = 0;
+        for (int64_t e = 0; e < nnz; ++e) tr->S += w2_0[e];
+        orc_canonical(n, zeta, labels);
+        *q_out = orc_modularity(n, off, col, w2_0, labels, NULL, NULL, NULL, NULL);
+        free(zeta); free(w2_0);
+        return 0;
+    }
     /* current level graph (level 0 aliases the input) */
     int64_t ln = n, lnnz = nnz;
     const int64_t *loff = off;

@@ -180,3 +180,77 @@ def seq_louvain(n, edges, seed=0, max_sweeps=32, max_levels=0):
         canon.setdefault(x, len(canon))
         out.append(canon[x])
     return np.array(out, dtype=np.int32)
+
+
+def seq_plmr(n, edges, seed=0, max_sweeps=32, max_levels=0):
+    """PLMR (Algorithm 4) with the sequential schedule and the paper's
+    Delta-mod in fractions, written recursively as the algorithm is stated:
+    move from singletons; if communities merged, coarsen, recurse, prolong
+    (u takes the community of its coarse node, named by that node's community
+    id on the coarse level) and move again from the prolonged communities.
+    Moves, ties and coarse ids follow seq_louvain.  Returns canonical labels."""
+
+    def graph(cur_n, cur_edges):
+        adj = [dict() for _ in range(cur_n)]
+        vol = [0] * cur_n
+        for (u, v), wt in cur_edges.items():
+            if u == v:
+                vol[u] += 2 * wt
+            else:
+                adj[u][v] = wt
+                adj[v][u] = wt
+                vol[u] += wt
+                vol[v] += wt
+        return adj, vol, Fraction(sum(cur_edges.values()))
+
+    def move(cur_n, adj, vol, W, zeta, level):
+        volC = [0] * cur_n
+        for u in range(cur_n):
+            volC[zeta[u]] += vol[u]
+        order = priority_order(cur_n, seed, level)
+        for _ in range(max_sweeps):
+            moves = 0
+            for u in order:
+                C = zeta[u]
+                wto = {}
+                for v, wt in adj[u].items():
+                    wto[zeta[v]] = wto.get(zeta[v], 0) + wt
+                best, bestD = None, None
+                for D in sorted(wto):
+                    if D == C:
+                        continue
+                    delta = (Fraction(wto[D] - wto.get(C, 0)) / W
+                             + Fraction((volC[C] - vol[u]) - volC[D]) * vol[u] / (2 * W * W))
+                    if best is None or delta > best:
+                        best, bestD = delta, D
+                if best is not None and best > 0:
+                    volC[C] -= vol[u]
+                    volC[bestD] += vol[u]
+                    zeta[u] = bestD
+                    moves += 1
+            if moves == 0:
+                break
+        return zeta
+
+    def rec(cur_n, cur_edges, level):
+        adj, vol, W = graph(cur_n, cur_edges)
+        zeta = move(cur_n, adj, vol, W, list(range(cur_n)), level)
+        ids = sorted(set(zeta))
+        if len(ids) == cur_n or (max_levels and level + 1 >= max_levels):
+            return zeta
+        newid = {c: i for i, c in enumerate(ids)}
+        pi = [newid[zeta[u]] for u in range(cur_n)]
+        coarse = {}
+        for (u, v), wt in cur_edges.items():
+            a, b = sorted((pi[u], pi[v]))
+            coarse[(a, b)] = coarse.get((a, b), 0) + wt
+        zc = rec(len(ids), coarse, level + 1)
+        zeta = [zc[pi[u]] for u in range(cur_n)]
+        return move(cur_n, adj, vol, W, zeta, level)
+
+    z = rec(n, dict(edges), 0)
+    canon, out = {}, []
+    for x in z:
+        canon.setdefault(x, len(canon))
+        out.append(canon[x])
+    return np.array(out, dtype=np.int32)

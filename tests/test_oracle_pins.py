@@ -366,3 +366,57 @@ def test_empty_and_edgeless():
     g = graphgen.from_edges(5, [])
     r = oracle.run(g.off, g.col, None)
     assert np.array_equal(r.labels, np.arange(5)) and r.q == 0.0
+
+
+# ------------------------------------------------------------------ PLMR (Algorithm 4)
+@pytest.mark.parametrize("seed", range(8))
+def test_plmr_sequential_equals_fraction_reference(seed):
+    """With the sequential schedule, the oracle's PLMR equals an independent
+    recursive implementation of Algorithm 4 in exact fractions."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(8, 80))
+    g = graphgen.random_graph(n, float(rng.uniform(0.04, 0.25)), seed=500 + seed, weighted=True, loops=0.15)
+    r = oracle.run(g.off, g.col, g.w, seed=seed, schedule=1, refine=True)
+    ref = refs.seq_plmr(n, refs.edges_of(g.off, g.col, g.w), seed=seed)
+    assert np.array_equal(r.labels, ref)
+
+
+def test_plmr_sequential_on_planted_partition_and_level_cap():
+    g = graphgen.sbm(300, 6, 0.15, 0.01, seed=12)
+    e = refs.edges_of(g.off, g.col, None)
+    for ml in (0, 2):
+        r = oracle.run(g.off, g.col, None, seed=3, schedule=1, refine=True, max_levels=ml)
+        assert np.array_equal(r.labels, refs.seq_plmr(g.n, e, seed=3, max_levels=ml))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plmr_single_level_is_plm(seed):
+    """With one level there is no prolongation, so PLMR is PLM."""
+    g = graphgen.random_graph(120, 0.06, seed=600 + seed, weighted=True, loops=0.1)
+    a = oracle.run(g.off, g.col, g.w, seed=seed, max_levels=1)
+    b = oracle.run(g.off, g.col, g.w, seed=seed, max_levels=1, refine=True)
+    assert np.array_equal(a.labels, b.labels) and a.q == b.q and b.ref_sweeps == [0]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plmr_final_partition_is_locally_optimal(seed):
+    """When the refinement at level 0 ends on a sweep without moves, no single
+    node move to a neighbouring community raises N (on the input graph)."""
+    g = graphgen.random_graph(70, 0.09, seed=700 + seed, weighted=True, loops=0.1)
+    r = oracle.run(g.off, g.col, g.w, seed=seed, refine=True, max_sweeps=64)
+    if r.levels < 2 or r.ref_sweeps[0] >= 64:
+        pytest.skip("no refinement at level 0, or it did not converge")
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    zeta = r.labels.astype(np.int32)
+    N0 = _N(g, w2, zeta)
+    for u in range(g.n):
+        for X in {int(zeta[v]) for v in g.col[g.off[u]:g.off[u + 1]] if v != u}:
+            z2 = zeta.copy(); z2[u] = X
+            assert _N(g, w2, z2) - N0 <= 0
+
+
+def test_plmr_keeps_the_optimum_of_clear_structures():
+    for g, q in [(graphgen.disjoint_cliques(2, 5), Fraction(1, 2)),
+                 (graphgen.ring_of_cliques(6, 4), Fraction(12, 14) - Fraction(1, 6))]:
+        r = oracle.run(g.off, g.col, g.w, refine=True)
+        assert r.q == float(q)
