@@ -96,7 +96,11 @@ typedef struct {
                               events per step); k = 1..5 = only kernel k (lane,
                               wavefront, workgroup, one-workgroup hub, partitioned
                               hub): two events per step, so timing costs less */
-    int32_t reserved[6];
+    int32_t refine;        /* 1: PLMR (Algorithm 4): after each prolongation, a move
+                              phase on that level starting from the prolonged
+                              communities (same colour classes and sweep rule);
+                              plm_run only (batches and servers: PLM_E_ARG) */
+    int32_t reserved[5];
 } plm_options;
 
 /* Fills *opt with the defaults above. */
@@ -125,8 +129,8 @@ plm_status plm_move_class(plm_ctx *ctx, int32_t c, int64_t *moves_out);
  * singleton communities.  *n_coarse_out = number of coarse nodes. */
 plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out);
 
-/* Full PLM (Algorithm 3) from level 0: move, coarsen while communities merge,
- * prolong.  labels[n] (mem_kind of the context's input) receives canonical
+/* Full PLM (Algorithm 3; with opt.refine, PLMR, Algorithm 4) from level 0:
+ * move, coarsen while communities merge, prolong.  labels[n] (mem_kind of the context's input) receives canonical
  * labels; *q_out their modularity; *levels_out the number of move phases.  Any
  * output pointer may be NULL. */
 plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out);
@@ -282,6 +286,10 @@ typedef struct {
     /* with opt.timing: class steps that launched each kernel (lane, wavefront,
      * workgroup, one-workgroup hub, partitioned hub) */
     int64_t kernel_launches[PLM_MAX_LEVELS][5];
+    /* with opt.refine: the move phase after prolongation at each level */
+    int64_t ref_sweeps[PLM_MAX_LEVELS];
+    int64_t ref_moves[PLM_MAX_LEVELS];
+    double ref_ms[PLM_MAX_LEVELS];            /* prolongation + schedule + sweeps (host clock) */
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

@@ -39,7 +39,8 @@ class plm_options(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("colour_seed", ctypes.c_uint64), ("int_mode", ctypes.c_int32),
                 ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class plm_level_info_t(ctypes.Structure):
@@ -64,7 +65,8 @@ class plm_stats_t(ctypes.Structure):
                 ("bin_entries", (ctypes.c_int64 * 4) * _L), ("loops", ctypes.c_int64 * _L),
                 ("hub_single_ms", ctypes.c_double * _L), ("hub_single_bytes", ctypes.c_double * _L),
                 ("hub_single_nodes", ctypes.c_int64 * _L), ("hub_single_entries", ctypes.c_int64 * _L),
-                ("kernel_launches", (ctypes.c_int64 * 5) * _L)]
+                ("kernel_launches", (ctypes.c_int64 * 5) * _L), ("ref_sweeps", ctypes.c_int64 * _L),
+                ("ref_moves", ctypes.c_int64 * _L), ("ref_ms", ctypes.c_double * _L)]
 
 
 class plm_server_info_t(ctypes.Structure):

@@ -591,6 +591,11 @@ struct plm_ctx {
             coarsen();
             if (prev < PLM_MAX_LEVELS) stats.coarsen_ms[prev] = now_ms() - t3;
         }
+        if (opt.refine && cur > 0) {
+            refine_up();
+            if (n0 > 0) build_canonical(zeta, n0, lab_out, scr, st);
+            return done_levels;
+        }
         // prolong: input node -> current level node -> community
         int64_t n = n0;
         if (n > 0) {
@@ -604,6 +609,48 @@ struct plm_ctx {
             build_canonical(lab, n, lab_out, scr, st);
         }
         return done_levels;
+    }
+
+    // PLMR (Algorithm 4), on the way back up: at each level l below the
+    // deepest, u takes the community of its coarse node pi_l(u) (named by that
+    // community's id on level l + 1, which is below n_l), and a move phase
+    // (same colouring, same sweep rule) starts from there.  Leaves level 0's
+    // communities in zeta.
+    void refine_up() {
+        for (int l = cur - 1; l >= 0; --l) {
+            double t0 = now_ms();
+            const int64_t nl = levels[l].n;
+            if (nl > 0) {
+                HIPCHK(hipMemcpyAsync(move_to, levels[l].pi, nl * 4, hipMemcpyDeviceToDevice, st));
+                launch_compose(move_to, zeta, nl, st);  // move_to[u] = zeta_{l+1}[pi_l[u]]
+                HIPCHK(hipMemcpyAsync(zeta, move_to, nl * 4, hipMemcpyDeviceToDevice, st));
+            }
+            cur = l;
+            LevelData &lv = L();
+            launch_volumes(lv.view(), vol, dcnt + 5, dcnt + 6, st);
+            HIPCHK(hipMemcpyAsync(hbuf, dcnt + 5, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (hbuf[0] != S) throw Error{PLM_E_STATE, "internal: level weight differs during refinement"};
+            max_vol = hbuf[1];
+            wide_lim = S > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)S) : INT64_MAX;
+            if (opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
+                throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
+            launch_comm_vol(zeta, vol, nl, volC, st);
+            sched = false;
+            sweeps = 0;
+            build_schedule();
+            int64_t moves = 0;
+            for (int32_t s = 0; s < opt.max_sweeps; ++s) {
+                int64_t mv = sweep();
+                moves += mv;
+                if (mv == 0) break;
+            }
+            if (l < PLM_MAX_LEVELS) {
+                stats.ref_sweeps[l] = sweeps;
+                stats.ref_moves[l] = moves;
+                stats.ref_ms[l] = now_ms() - t0;
+            }
+        }
     }
 
     double modularity_of(const int32_t *labels_dev) {
@@ -776,6 +823,7 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.schedule != PLM_SCHEDULE_COLOUR && o.schedule != PLM_SCHEDULE_SEQUENTIAL) { msg = "bad schedule"; return PLM_E_ARG; }
     if (o.int_mode < 0 || o.int_mode > 2) { msg = "bad int_mode"; return PLM_E_ARG; }
     if (o.timing_kernel < 0 || o.timing_kernel > 5) { msg = "timing_kernel must lie in [0, 5]"; return PLM_E_ARG; }
+    if (o.refine != 0 && o.refine != 1) { msg = "refine must be 0 or 1"; return PLM_E_ARG; }
     int64_t a = o.bin_lane > 0 ? o.bin_lane : 16, b = o.bin_wave > 0 ? o.bin_wave : 512,
             c = o.bin_block > 0 ? o.bin_block : 4096;
     if (a > 16 || b > 512 || c > 4096 || a > b || b > c) {
@@ -873,6 +921,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
     int rc = check_options(o, m);
     if (rc) return fail_adopt(rc, m);
     if (G > 0) {
+        if (o.refine) return fail_adopt(PLM_E_ARG, "batched runs do not refine");
         if (o.schedule != PLM_SCHEDULE_COLOUR) return fail_adopt(PLM_E_ARG, "batched runs use the colour schedule");
         if (o.int_mode == PLM_INT_64) return fail_adopt(PLM_E_ARG, "batched runs take int_mode auto or 128");
         if (node_base[0] != 0) return fail_adopt(PLM_E_ARG, "node_base[0] must be 0");

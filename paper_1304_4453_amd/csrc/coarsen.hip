@@ -236,6 +236,17 @@ __global__ void k_iota(int32_t *a, int64_t n) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) a[v] = (int32_t)v;
 }
+// volC[x] = sum of vol[u] over the nodes u with zeta[u] = x (volC zeroed first)
+__global__ void k_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t *volC) {
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n && vol[u]) atomicAdd((unsigned long long *)&volC[zeta[u]], (unsigned long long)vol[u]);
+}
+void launch_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t *volC, hipStream_t st) {
+    if (n <= 0) return;
+    HIPCHK(hipMemsetAsync(volC, 0, n * 8, st));
+    hipLaunchKernelGGL(k_comm_vol, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, zeta, vol, n, volC);
+    HIPCHK(hipGetLastError());
+}
 void launch_iota(int32_t *a, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_iota, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, a, n);

@@ -256,7 +256,7 @@ plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t
     plm_options o;
     plm_default_options(&o);
     if (opt) o = *opt;
-    if (o.schedule != PLM_SCHEDULE_COLOUR || o.int_mode == PLM_INT_64) return PLM_E_ARG;
+    if (o.schedule != PLM_SCHEDULE_COLOUR || o.int_mode == PLM_INT_64 || o.refine) return PLM_E_ARG;
     plm_server *s = new (std::nothrow) plm_server();
     if (!s) return PLM_E_NOMEM;
     s->st = (hipStream_t)hip_stream;

@@ -1,4 +1,5 @@
-"""Writes the oracle's full-run results for the named workloads to
+"""Writes the oracle's full-run results (PLM, and PLMR under the "_plmr" keys)
+for the named workloads to
 tests/golden/oracle_runs.json: a SHA-256 of the canonical label array, Q and
 the per-level trace.  Calls only the oracle and the input generators.
 
@@ -30,12 +31,17 @@ def main():
     }
     for name, make in work.items():
         g = make()
-        r = oracle.run(g.off, g.col, None if g.w is None else g.w)
-        out[name] = {"n": g.n, "nnz": g.nnz, "q": r.q, "q_hex": float(r.q).hex(), "levels": r.levels,
-                     "labels_sha256": digest(r.labels), "communities": len(set(r.labels.tolist())),
-                     "trace": {"n": r.n, "nnz": r.nnz, "colours": r.colours, "sweeps": r.sweeps,
-                               "communities": r.communities, "moves": [sum(m) for m in r.moves]}}
-        print(name, out[name]["q"], out[name]["levels"], flush=True)
+        for refine in (False, True):
+            r = oracle.run(g.off, g.col, None if g.w is None else g.w, refine=refine)
+            key = name + ("_plmr" if refine else "")
+            out[key] = {"n": g.n, "nnz": g.nnz, "q": r.q, "q_hex": float(r.q).hex(), "levels": r.levels,
+                        "labels_sha256": digest(r.labels), "communities": len(set(r.labels.tolist())),
+                        "trace": {"n": r.n, "nnz": r.nnz, "colours": r.colours, "sweeps": r.sweeps,
+                                  "communities": r.communities, "moves": [sum(m) for m in r.moves]}}
+            if refine:
+                out[key]["trace"]["ref_sweeps"] = r.ref_sweeps
+                out[key]["trace"]["ref_moves"] = r.ref_moves
+            print(key, out[key]["q"], out[key]["levels"], flush=True)
     with open(os.path.join(HERE, "oracle_runs.json"), "w") as f:
         json.dump(out, f, indent=1)
 

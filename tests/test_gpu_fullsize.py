@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes.
 
-* The 1,000-node planted partition and R-MAT scale 20 (unit weights, seed 2):
-  the whole run is compared with the oracle's stored result
+* The 1,000-node planted partition and R-MAT scale 20 (unit weights, seed 2),
+  PLM and PLMR: the whole run is compared with the oracle's stored result
   (tests/golden/oracle_runs.json, written by tests/golden/make_golden.py from
   the oracle alone): SHA-256 of the canonical labels, Q bit for bit, and the
   per-level trace.
@@ -41,14 +41,15 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _check_golden(P, name, g):
-    gold = json.load(open(GOLDEN))[name]
-    with P.Context(g.off, g.col, g.w) as ctx:
+def _check_golden(P, name, g, refine=False):
+    gold = json.load(open(GOLDEN))[name + ("_plmr" if refine else "")]
+    with P.Context(g.off, g.col, g.w, refine=int(refine)) as ctx:
         labels, q, lv = ctx.run()
         st = ctx.stats()
     assert hashlib.sha256(labels.astype(np.int32).tobytes()).hexdigest() == gold["labels_sha256"]
     assert q == float.fromhex(gold["q_hex"]) and lv == gold["levels"]
-    for k in ("n", "nnz", "colours", "sweeps", "communities", "moves"):
+    keys = ("n", "nnz", "colours", "sweeps", "communities", "moves") + (("ref_sweeps", "ref_moves") if refine else ())
+    for k in keys:
         assert st[k] == gold["trace"][k], k
 
 
@@ -60,6 +61,16 @@ def test_planted_partition_golden(P):
 def test_rmat20_golden(P):
     _say("rmat20 golden")
     _check_golden(P, "rmat20_seed2_unit", graphgen.rmat20(seed=2))
+
+
+def test_planted_partition_golden_plmr(P):
+    _check_golden(P, "planted_partition_1000_seed1", graphgen.planted_partition_1000(seed=1), refine=True)
+
+
+@pytest.mark.timeout(300)
+def test_rmat20_golden_plmr(P):
+    _say("rmat20 golden plmr")
+    _check_golden(P, "rmat20_seed2_unit", graphgen.rmat20(seed=2), refine=True)
 
 
 def test_device_generator_matches_host(P):

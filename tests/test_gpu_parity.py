@@ -74,10 +74,11 @@ def stepwise(P, g, seed=0, schedule=0, per_class=True, max_sweeps=32, max_levels
         ctx.close()
 
 
-def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, **opts):
-    r = oracle.run(g.off, g.col, g.w, max_sweeps=max_sweeps, max_levels=max_levels, seed=seed, schedule=schedule)
+def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, refine=False, **opts):
+    r = oracle.run(g.off, g.col, g.w, max_sweeps=max_sweeps, max_levels=max_levels, seed=seed, schedule=schedule,
+                   refine=refine)
     with P.Context(g.off, g.col, g.w, colour_seed=seed, schedule=schedule, max_sweeps=max_sweeps,
-                   max_levels=max_levels, **opts) as ctx:
+                   max_levels=max_levels, refine=int(refine), **opts) as ctx:
         labels, q, lv = ctx.run()
         st = ctx.stats()
     assert lv == r.levels
@@ -86,6 +87,8 @@ def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, **opts):
     assert st["n"] == r.n and st["nnz"] == r.nnz and st["colours"] == r.colours
     assert st["sweeps"] == r.sweeps and st["communities"] == r.communities
     assert st["moves"] == [sum(m) for m in r.moves]
+    if refine:
+        assert st["ref_sweeps"] == r.ref_sweeps and st["ref_moves"] == r.ref_moves
     return r
 
 
@@ -152,6 +155,38 @@ def test_full_run_forced_int128_same(P):
     g = graphgen.rmat(12, 16, seed=3, weighted=True)
     full_run(P, g, int_mode=P.PLM_INT_128)
     full_run(P, g, int_mode=P.PLM_INT_128, **SMALL_BINS)
+
+
+# ------------------------------------------------------------------ PLMR (Algorithm 4)
+def test_plmr_planted_partition(P):
+    _say("plmr planted partition")
+    full_run(P, graphgen.planted_partition_1000(seed=2), refine=True)
+
+
+@pytest.mark.parametrize("bins", [{}, SMALL_BINS, MID_BINS], ids=["default", "small", "mid"])
+def test_plmr_rmat(P, bins):
+    _say("plmr rmat", bins)
+    full_run(P, graphgen.rmat(13, 16, seed=31, weighted=True), seed=5, refine=True, **bins)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_plmr_random_caps_and_schedules(P, seed):
+    _say("plmr random", seed)
+    g = graphgen.random_graph(250, 0.03, seed=80 + seed, weighted=True, loops=0.1)
+    full_run(P, g, seed=seed, refine=True, max_sweeps=3 + 10 * seed, max_levels=[0, 2, 3][seed])
+    full_run(P, g, seed=seed, refine=True, schedule=1)
+
+
+def test_plmr_forced_int128(P):
+    _say("plmr int128")
+    full_run(P, graphgen.rmat(12, 16, seed=9, weighted=True), refine=True, int_mode=P.PLM_INT_128)
+
+
+def test_plmr_rejected_for_batches(P):
+    g = graphgen.disjoint_cliques(2, 3)
+    with pytest.raises(P.PLMError) as e:
+        P.BatchContext(np.array([0, 3, 6]), g.off, g.col, g.w, refine=1)
+    assert e.value.status == P.PLM_E_ARG
 
 
 def test_int64_mode_rejects_overflow(P):
