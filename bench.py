@@ -7,7 +7,8 @@ already resident in HBM.  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000] [--no-batch]
 
-The line also carries "batched": the batched engine (plm_batch_run) on 4,096
+The line also carries "plmr": one PLMR run (Algorithm 4) on the same graph;
+"batched": the batched engine (plm_batch_run) on 4,096
 uneven SBM graphs against a per-graph plm_run loop on the same GPU; and
 "served": the request server (plm_server_*) under Poisson arrivals, with
 p50/p99 latency and graphs/s.
@@ -344,6 +345,25 @@ def serve_bench(args, P, torch, np):
                     "is bounded (--serve-seconds) so that the run ends within minutes"}
 
 
+def plmr_bench(gr, P, torch, q_plm, st_plm):
+    """PLMR (Algorithm 4) on the same resident graph: one warm-up and one timed
+    full run with refinement; its modularity beside PLM's."""
+    ctx = P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"], refine=1)
+    lab = torch.empty(max(gr["n"], 1), dtype=torch.int32, device="cuda:0")
+    ctx.run(lab)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, q, lv = ctx.run(lab)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    st = ctx.stats()
+    ctx.close()
+    m0 = (st["nnz"][0] - st["loops"][0]) // 2 + st["loops"][0]
+    log(f"plmr step {dt:.2f}s q={q}")
+    return {"ms_per_run": dt * 1e3, "full_run_edges_per_s": m0 / dt, "q": q, "q_plm": q_plm, "levels": lv,
+            "refinement_ms": sum(st["ref_ms"]), "ref_sweeps": st["ref_sweeps"], "ref_moves": st["ref_moves"]}
+
+
 def sweep_probe(P, torch):
     """One level-0 move sweep of the R-MAT 26 workload with every move-decide
     kernel timed, after a 1 GiB device copy that calibrates the HBM byte
@@ -384,6 +404,7 @@ def main():
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plmr", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served workload")
     ap.add_argument("--plain-serve-sample", type=int, default=40)
     ap.add_argument("--sweep-probe", action="store_true",
@@ -478,6 +499,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(gr, state0, args.cpu_budget)
         log(f"cpu baseline {time.time() - t:.1f}s")
     ctx.close()
+    if not args.no_plmr:
+        out["plmr"] = plmr_bench(gr, P, torch, q, st)
     if gr["dg"] is not None:
         gr["dg"].free()
     if not args.no_batch:
