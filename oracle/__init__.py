@@ -24,7 +24,8 @@ MAX_SWEEPS = 64
 
 class _Options(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("schedule", ctypes.c_int32), ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("gamma_num", ctypes.c_int64), ("gamma_den", ctypes.c_int64)]
 
 
 class _Trace(ctypes.Structure):
@@ -64,12 +65,13 @@ def lib():
         L.orc_volumes.argtypes = [i64, P64, P64, P64]; L.orc_volumes.restype = i64
         L.orc_priority_order.argtypes = [i64, u64, i32, P32]
         L.orc_colour.argtypes = [i64, P64, P32, u64, i32, i32, P32]; L.orc_colour.restype = i64
-        L.orc_decide.argtypes = [i64, i64, P64, P32, P64, P32, P64, P64, i64, P64, PU64]
+        L.orc_decide.argtypes = [i64, i64, P64, P32, P64, P32, P64, P64, i64, i64, i64, P64, PU64]
         L.orc_decide.restype = i32
-        L.orc_decide_many.argtypes = [i64, i64, P32, P64, P32, P64, P32, P64, P64, i64, P32]
-        L.orc_class_step.argtypes = [i64, P64, P32, P64, P64, i64, P32, i32, P32, P64]
+        L.orc_decide_many.argtypes = [i64, i64, P32, P64, P32, P64, P32, P64, P64, i64, i64, i64, P32]
+        L.orc_class_step.argtypes = [i64, P64, P32, P64, P64, i64, i64, i64, P32, i32, P32, P64]
         L.orc_class_step.restype = i64
-        L.orc_sweep.argtypes = [i64, P64, P32, P64, P64, i64, P32, i64, P32, P64]; L.orc_sweep.restype = i64
+        L.orc_sweep.argtypes = [i64, P64, P32, P64, P64, i64, i64, i64, P32, i64, P32, P64]
+        L.orc_sweep.restype = i64
         L.orc_relabel.argtypes = [i64, P32, P32]; L.orc_relabel.restype = i64
         L.orc_contract.argtypes = [i64, P64, P32, P64, P32, i64, P64, P32, P64]; L.orc_contract.restype = i64
         L.orc_modularity.argtypes = [i64, P64, P32, P64, P32, P64, PU64, P64, PU64]
@@ -139,45 +141,47 @@ def colour(off, col, seed: int = 0, level: int = 0, schedule: int = 0):
     return out[:n], int(C)
 
 
-def decide(u, off, col, w2, zeta, volC, vol, S):
-    """(target or -1, exact 128-bit gain) of one node."""
+def decide(u, off, col, w2, zeta, volC, vol, S, gamma=(1, 1)):
+    """(target or -1, exact 128-bit gain) of one node; gamma = (num, den)."""
     off, col, w2, zeta, volC, vol = _i64(off), _i32(col), _i64(w2), _i32(zeta), _i64(volC), _i64(vol)
     hi, lo = ctypes.c_int64(), ctypes.c_uint64()
     x = lib().orc_decide(off.shape[0] - 1, u, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32),
                          _p(w2, ctypes.c_int64), _p(zeta, ctypes.c_int32), _p(volC, ctypes.c_int64),
-                         _p(vol, ctypes.c_int64), S, ctypes.byref(hi), ctypes.byref(lo))
+                         _p(vol, ctypes.c_int64), S, gamma[0], gamma[1], ctypes.byref(hi), ctypes.byref(lo))
     g = _u128(hi.value, lo.value)
     if g >= 1 << 127:
         g -= 1 << 128
     return int(x), g
 
 
-def decide_many(nodes, off, col, w2, zeta, volC, vol, S) -> np.ndarray:
+def decide_many(nodes, off, col, w2, zeta, volC, vol, S, gamma=(1, 1)) -> np.ndarray:
     nodes = _i32(nodes)
     off, col, w2, zeta, volC, vol = _i64(off), _i32(col), _i64(w2), _i32(zeta), _i64(volC), _i64(vol)
     out = np.zeros(max(nodes.shape[0], 1), np.int32)
     lib().orc_decide_many(off.shape[0] - 1, nodes.shape[0], _p(nodes, ctypes.c_int32), _p(off, ctypes.c_int64),
                           _p(col, ctypes.c_int32), _p(w2, ctypes.c_int64), _p(zeta, ctypes.c_int32),
-                          _p(volC, ctypes.c_int64), _p(vol, ctypes.c_int64), S, _p(out, ctypes.c_int32))
+                          _p(volC, ctypes.c_int64), _p(vol, ctypes.c_int64), S, gamma[0], gamma[1],
+                          _p(out, ctypes.c_int32))
     return out[: nodes.shape[0]]
 
 
-def class_step(off, col, w2, vol, S, colours, c, zeta, volC) -> int:
+def class_step(off, col, w2, vol, S, colours, c, zeta, volC, gamma=(1, 1)) -> int:
     """In place on zeta (int32) and volC (int64) numpy arrays."""
     off, col, w2, vol, colours = _i64(off), _i32(col), _i64(w2), _i64(vol), _i32(colours)
     assert zeta.dtype == np.int32 and volC.dtype == np.int64
     return int(lib().orc_class_step(off.shape[0] - 1, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32),
-                                    _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S,
+                                    _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S, gamma[0], gamma[1],
                                     _p(colours, ctypes.c_int32), c, _p(zeta, ctypes.c_int32),
                                     _p(volC, ctypes.c_int64)))
 
 
-def sweep(off, col, w2, vol, S, colours, ncol, zeta, volC) -> int:
+def sweep(off, col, w2, vol, S, colours, ncol, zeta, volC, gamma=(1, 1)) -> int:
     """In place on zeta (int32) and volC (int64) numpy arrays."""
     off, col, w2, vol, colours = _i64(off), _i32(col), _i64(w2), _i64(vol), _i32(colours)
     assert zeta.dtype == np.int32 and volC.dtype == np.int64
     return int(lib().orc_sweep(off.shape[0] - 1, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32),
-                               _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S, _p(colours, ctypes.c_int32),
+                               _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S, gamma[0], gamma[1],
+                               _p(colours, ctypes.c_int32),
                                ncol, _p(zeta, ctypes.c_int32), _p(volC, ctypes.c_int64)))
 
 
@@ -244,23 +248,23 @@ class RunResult:
 
 
 def run(off, col, w=None, max_sweeps: int = 32, max_levels: int = 0, seed: int = 0, schedule: int = 0,
-        refine: bool = False) -> RunResult:
+        refine: bool = False, gamma=(1, 1)) -> RunResult:
     """Full multilevel PLM (Algorithm 3), or PLMR (Algorithm 4) with refine,
-    with canonical output labels."""
+    with canonical output labels; gamma = (num, den) is the resolution."""
     off, col = _i64(off), _i32(col)
     n = off.shape[0] - 1
     wp = None
     if w is not None:
         w = _i64(w)
         wp = _p(w, ctypes.c_int64)
-    opt = _Options(max_sweeps, max_levels, schedule, 1 if refine else 0, seed)
+    opt = _Options(max_sweeps, max_levels, schedule, 1 if refine else 0, seed, gamma[0], gamma[1])
     tr = _Trace()
     labels = np.zeros(max(n, 1), np.int32)
     q = ctypes.c_double()
     rc = lib().orc_run(n, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32), wp, ctypes.byref(opt),
                        _p(labels, ctypes.c_int32), ctypes.byref(q), ctypes.byref(tr))
     if rc != 0:
-        raise ValueError("orc_run: bad options")
+        raise ValueError("orc_run: bad options (sweeps, or gamma outside [0, 2^16) / [1, 2^16) or too large for S)")
     L = tr.levels
     return RunResult(labels[:n].copy(), float(q.value), L, [tr.n[i] for i in range(L)],
                      [tr.nnz[i] for i in range(L)], [tr.colours[i] for i in range(L)],

@@ -162,10 +162,13 @@ static int orc_i32_cmp(const void *a, const void *b) {
 }
 
 /* Best move of u: the target community, or -1 to stay.  *gain_out gets the
- * winning gain (0 when staying). */
+ * winning gain (0 when staying).  Resolution gamma = gp / gq (section III-B
+ * names the parameter; gamma = 1 is plain modularity): the gain is scaled by
+ * gq > 0, gq S (w(u,X) - w(u,D\u)) - gp vol(u) (vol(X) - vol(D\u)), which keeps
+ * every comparison exact; callers keep S vol(u) max(gp, gq) below 2^126. */
 static int32_t orc_decide_m(int64_t u, const int64_t *off, const int32_t *col, const int64_t *w2,
                             const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S,
-                            orc_map *m, i128 *gain_out) {
+                            int64_t gp, int64_t gq, orc_map *m, i128 *gain_out) {
     int64_t nt = 0;
     for (int64_t e = off[u]; e < off[u + 1]; ++e) {
         int64_t v = col[e];
@@ -184,7 +187,7 @@ static int32_t orc_decide_m(int64_t u, const int64_t *off, const int32_t *col, c
         for (int64_t i = 0; i < nt; ++i) {
             int32_t X = m->touched[i];
             if (X == D) continue;
-            i128 g = (i128)S * (i128)(m->acc[X] - wD) - (i128)vol[u] * (i128)(volC[X] - base);
+            i128 g = (i128)gq * (i128)S * (i128)(m->acc[X] - wD) - (i128)gp * (i128)vol[u] * (i128)(volC[X] - base);
             if (g > best_gain) { best_gain = g; best = X; }  /* ascending X: ties keep the lowest id */
         }
     }
@@ -196,12 +199,12 @@ static int32_t orc_decide_m(int64_t u, const int64_t *off, const int32_t *col, c
 /* Single-node decision (exported for sampled checks).  gain_hi/gain_lo receive
  * the 128-bit winning gain. */
 int32_t orc_decide(int64_t n, int64_t u, const int64_t *off, const int32_t *col, const int64_t *w2,
-                   const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S, int64_t *gain_hi,
-                   uint64_t *gain_lo) {
+                   const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S, int64_t gp, int64_t gq,
+                   int64_t *gain_hi, uint64_t *gain_lo) {
     orc_map m;
     orc_map_init(&m, n);
     i128 g;
-    int32_t x = orc_decide_m(u, off, col, w2, zeta, volC, vol, S, &m, &g);
+    int32_t x = orc_decide_m(u, off, col, w2, zeta, volC, vol, S, gp, gq, &m, &g);
     orc_map_free(&m);
     if (gain_hi) *gain_hi = (int64_t)(g >> 64);
     if (gain_lo) *gain_lo = (uint64_t)g;
@@ -211,12 +214,12 @@ int32_t orc_decide(int64_t n, int64_t u, const int64_t *off, const int32_t *col,
 /* Sampled decisions: for each listed node, its decision against (zeta, volC). */
 void orc_decide_many(int64_t n, int64_t count, const int32_t *nodes, const int64_t *off, const int32_t *col,
                      const int64_t *w2, const int32_t *zeta, const int64_t *volC, const int64_t *vol, int64_t S,
-                     int32_t *out) {
+                     int64_t gp, int64_t gq, int32_t *out) {
     orc_map m;
     orc_map_init(&m, n);
     for (int64_t i = 0; i < count; ++i) {
         i128 g;
-        out[i] = orc_decide_m(nodes[i], off, col, w2, zeta, volC, vol, S, &m, &g);
+        out[i] = orc_decide_m(nodes[i], off, col, w2, zeta, volC, vol, S, gp, gq, &m, &g);
     }
     orc_map_free(&m);
 }
@@ -225,11 +228,11 @@ void orc_decide_many(int64_t n, int64_t count, const int32_t *nodes, const int64
  * start of the class, then all moves are applied.  Returns the move count.
  * `members`/`count` list the class; decisions[] is scratch of size count. */
 static int64_t orc_class_step_m(const int32_t *members, int64_t count, const int64_t *off, const int32_t *col,
-                                const int64_t *w2, const int64_t *vol, int64_t S, int32_t *zeta, int64_t *volC,
-                                int32_t *decisions, orc_map *m) {
+                                const int64_t *w2, const int64_t *vol, int64_t S, int64_t gp, int64_t gq,
+                                int32_t *zeta, int64_t *volC, int32_t *decisions, orc_map *m) {
     for (int64_t i = 0; i < count; ++i) {
         i128 g;
-        decisions[i] = orc_decide_m(members[i], off, col, w2, zeta, volC, vol, S, m, &g);
+        decisions[i] = orc_decide_m(members[i], off, col, w2, zeta, volC, vol, S, gp, gq, m, &g);
     }
     int64_t moves = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -258,7 +261,8 @@ static void orc_classes(int64_t n, const int32_t *colour, int64_t ncol, int64_t 
 
 /* One class step by class index (exported). */
 int64_t orc_class_step(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int64_t *vol,
-                       int64_t S, const int32_t *colour, int32_t c, int32_t *zeta, int64_t *volC) {
+                       int64_t S, int64_t gp, int64_t gq, const int32_t *colour, int32_t c, int32_t *zeta,
+                       int64_t *volC) {
     int64_t count = 0;
     for (int64_t u = 0; u < n; ++u) count += (colour[u] == c);
     int32_t *members = (int32_t *)malloc((size_t)(count > 0 ? count : 1) * sizeof(int32_t));
@@ -268,7 +272,7 @@ int64_t orc_class_step(int64_t n, const int64_t *off, const int32_t *col, const 
         if (colour[u] == c) members[k++] = (int32_t)u;
     orc_map m;
     orc_map_init(&m, n);
-    int64_t moves = orc_class_step_m(members, count, off, col, w2, vol, S, zeta, volC, dec, &m);
+    int64_t moves = orc_class_step_m(members, count, off, col, w2, vol, S, gp, gq, zeta, volC, dec, &m);
     orc_map_free(&m);
     free(members);
     free(dec);
@@ -277,7 +281,8 @@ int64_t orc_class_step(int64_t n, const int64_t *off, const int32_t *col, const 
 
 /* One sweep: all classes in ascending colour order.  Returns the move count. */
 int64_t orc_sweep(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int64_t *vol,
-                  int64_t S, const int32_t *colour, int64_t ncol, int32_t *zeta, int64_t *volC) {
+                  int64_t S, int64_t gp, int64_t gq, const int32_t *colour, int64_t ncol, int32_t *zeta,
+                  int64_t *volC) {
     int64_t *cls_off = (int64_t *)malloc((size_t)(ncol + 1) * sizeof(int64_t));
     int32_t *cls_nodes = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     int32_t *dec = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
@@ -286,8 +291,8 @@ int64_t orc_sweep(int64_t n, const int64_t *off, const int32_t *col, const int64
     orc_map_init(&m, n);
     int64_t moves = 0;
     for (int64_t c = 0; c < ncol; ++c)
-        moves += orc_class_step_m(cls_nodes + cls_off[c], cls_off[c + 1] - cls_off[c], off, col, w2, vol, S, zeta,
-                                  volC, dec, &m);
+        moves += orc_class_step_m(cls_nodes + cls_off[c], cls_off[c + 1] - cls_off[c], off, col, w2, vol, S, gp, gq,
+                                  zeta, volC, dec, &m);
     orc_map_free(&m);
     free(cls_off); free(cls_nodes); free(dec);
     return moves;
@@ -387,6 +392,8 @@ typedef struct {
     int32_t schedule;     /* 0 colour classes, 1 sequential */
     int32_t refine;       /* 1: PLMR (Algorithm 4), a move phase after every prolongation */
     uint64_t seed;
+    int64_t gamma_num;    /* resolution gamma = gamma_num / gamma_den (0/0 = 1) */
+    int64_t gamma_den;
 } orc_options;
 
 #define ORC_MAX_LEVELS 64
@@ -436,7 +443,8 @@ static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const
     int64_t sweeps = 0;
     if (level < ORC_MAX_LEVELS) { tr->n[level] = n; tr->nnz[level] = nnz; tr->colours[level] = ncol; }
     for (int32_t s = 0; s < opt->max_sweeps; ++s) {
-        int64_t mv = orc_sweep(n, off, col, w2, vol, S, colour, ncol, zeta_out, volC);
+        int64_t mv = orc_sweep(n, off, col, w2, vol, S, opt->gamma_num, opt->gamma_den, colour, ncol, zeta_out,
+                               volC);
         if (level < ORC_MAX_LEVELS) tr->moves[level][s] = mv;
         ++sweeps;
         if (mv == 0) break;
@@ -460,7 +468,8 @@ static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const
         for (int64_t u = 0; u < n; ++u) volC[zeta_out[u]] += vol[u];
         int64_t rs = 0, rm = 0;
         for (int32_t s = 0; s < opt->max_sweeps; ++s) {
-            int64_t mv = orc_sweep(n, off, col, w2, vol, S, colour, ncol, zeta_out, volC);
+            int64_t mv = orc_sweep(n, off, col, w2, vol, S, opt->gamma_num, opt->gamma_den, colour, ncol, zeta_out,
+                                   volC);
             ++rs;
             rm += mv;
             if (mv == 0) break;
@@ -471,13 +480,26 @@ static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const
     return depth;
 }
 
-int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, const orc_options *opt,
+int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, const orc_options *opt_in,
             int32_t *labels, double *q_out, orc_trace *tr) {
-    if (opt->max_sweeps < 1 || opt->max_sweeps > ORC_MAX_SWEEPS) return -1;
+    if (opt_in->max_sweeps < 1 || opt_in->max_sweeps > ORC_MAX_SWEEPS) return -1;
+    /* resolution: 0/0 means 1; 0 <= gamma_num, 1 <= gamma_den, both below 2^16 */
+    orc_options o = *opt_in;
+    const orc_options *opt = &o;
+    if (o.gamma_num == 0 && o.gamma_den == 0) o.gamma_num = o.gamma_den = 1;
+    if (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536) return -1;
     memset(tr, 0, sizeof(*tr));
     int64_t nnz = off[n];
     int64_t *w2_0 = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
     orc_double_diagonal(n, off, col, w, w2_0);
+    if (o.gamma_num != o.gamma_den) {
+        /* every gain stays below 2^126: S^2 max(gamma_num, gamma_den) < 2^126 */
+        int64_t S0 = 0;
+        for (int64_t e = 0; e < nnz; ++e) S0 += w2_0[e];
+        unsigned __int128 b = (unsigned __int128)S0 * (unsigned __int128)S0 *
+                              (unsigned __int128)(o.gamma_num > o.gamma_den ? o.gamma_num : o.gamma_den);
+        if (b >> 126) { free(w2_0); return -1; }
+    }
     if (opt->refine) {
         int32_t *zeta = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
         tr->levels = orc_plmr(n, off, col, w2_0, 0, opt, zeta, tr);
@@ -509,7 +531,8 @@ int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w,
         int64_t sweeps = 0;
         if (level < ORC_MAX_LEVELS) { tr->n[level] = ln; tr->nnz[level] = lnnz; tr->colours[level] = ncol; }
         for (int32_t s = 0; s < opt->max_sweeps; ++s) {
-            int64_t mv = orc_sweep(ln, loff, lcol, lw, vol, S, colour, ncol, zeta, volC);
+            int64_t mv = orc_sweep(ln, loff, lcol, lw, vol, S, opt->gamma_num, opt->gamma_den, colour, ncol, zeta,
+                                   volC);
             if (level < ORC_MAX_LEVELS) tr->moves[level][s] = mv;
             ++sweeps;
             if (mv == 0) break;

@@ -110,14 +110,15 @@ def set_partitions(n):
     yield from rec(1, 1)
 
 
-def seq_louvain(n, edges, seed=0, max_sweeps=32, max_levels=0):
+def seq_louvain(n, edges, seed=0, max_sweeps=32, max_levels=0, gamma=Fraction(1)):
     """Sequential Louvain with the paper's Delta-mod in fractions.
 
     Per level: singletons; sweeps visit nodes in descending priority; node u in
     community C moves to the neighbouring community D maximising
       Delta-mod(u, C -> D) = (w(u,D\\u) - w(u,C\\u)) / w(E)
                              + (vol(C\\u) - vol(D\\u)) vol(u) / (2 w(E)^2)
-    (lowest D among equal values) if that value is > 0.  A level stops after a
+    (lowest D among equal values) if that value is > 0; with a resolution gamma
+    the volume term is multiplied by gamma.  A level stops after a
     sweep without moves or max_sweeps sweeps; the run descends iff communities
     merged; coarse ids ascend with the old community ids; intra-community
     weight becomes a self-loop.  Returns canonical labels of the input nodes.
@@ -152,7 +153,7 @@ def seq_louvain(n, edges, seed=0, max_sweeps=32, max_levels=0):
                     if D == C:
                         continue
                     delta = (Fraction(wto[D] - wto.get(C, 0)) / W
-                             + Fraction((volC[C] - vol[u]) - volC[D]) * vol[u] / (2 * W * W))
+                             + gamma * Fraction((volC[C] - vol[u]) - volC[D]) * vol[u] / (2 * W * W))
                     if best is None or delta > best:
                         best, bestD = delta, D
                 if best is not None and best > 0:

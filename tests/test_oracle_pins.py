@@ -420,3 +420,79 @@ def test_plmr_keeps_the_optimum_of_clear_structures():
                  (graphgen.ring_of_cliques(6, 4), Fraction(12, 14) - Fraction(1, 6))]:
         r = oracle.run(g.off, g.col, g.w, refine=True)
         assert r.q == float(q)
+
+
+# ------------------------------------------------------------------ resolution gamma
+def _Ng(g, w2, zeta, gamma):
+    """q S I2 - p sum vol(C)^2 for gamma = p / q (q S^2 times the gamma-modularity)."""
+    p, q = gamma
+    vol, S = oracle.volumes(g.off, w2)
+    I2 = 0
+    for u in range(g.n):
+        for e in range(g.off[u], g.off[u + 1]):
+            if zeta[g.col[e]] == zeta[u]:
+                I2 += int(w2[e])
+    vc = {}
+    for u in range(g.n):
+        vc[int(zeta[u])] = vc.get(int(zeta[u]), 0) + int(vol[u])
+    return q * S * I2 - p * sum(x * x for x in vc.values())
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (3, 2), (7, 3), (0, 1), (5, 1)])
+def test_gamma_gain_is_half_the_change_of_Ngamma(gamma):
+    """For every node of a random partition: the chosen move's gain is half the
+    exact change of q S I2 - p sum vol(C)^2, no candidate changes it more (ties
+    to the lowest id), and staying means no candidate raises it."""
+    g = graphgen.random_graph(40, 0.15, seed=900 + gamma[0], weighted=True, loops=0.2)
+    w2 = oracle.double_diagonal(g.off, g.col, g.w)
+    vol, S = oracle.volumes(g.off, w2)
+    rng = np.random.default_rng(gamma[0] * 10 + gamma[1])
+    zeta = rng.integers(0, 8, g.n).astype(np.int32)
+    volC = np.zeros(g.n, np.int64)
+    np.add.at(volC, zeta, vol)
+    N0 = _Ng(g, w2, zeta, gamma)
+    for u in range(g.n):
+        x, gain = oracle.decide(u, g.off, g.col, w2, zeta, volC, vol, S, gamma=gamma)
+        best, bestX = 0, -1
+        for X in sorted({int(zeta[v]) for v in g.col[g.off[u]:g.off[u + 1]] if v != u} - {int(zeta[u])}):
+            z2 = zeta.copy(); z2[u] = X
+            d = _Ng(g, w2, z2, gamma) - N0
+            if d > best:
+                best, bestX = d, X
+        assert x == bestX and (x < 0 or 2 * gain == best)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gamma_sequential_equals_fraction_louvain(seed):
+    gammas = [(1, 2), (3, 2), (7, 3), (2, 5), (4, 1), (1, 1)]
+    gm = gammas[seed]
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(8, 70))
+    g = graphgen.random_graph(n, float(rng.uniform(0.05, 0.25)), seed=1100 + seed, weighted=True, loops=0.15)
+    r = oracle.run(g.off, g.col, g.w, seed=seed, schedule=1, gamma=gm)
+    ref = refs.seq_louvain(n, refs.edges_of(g.off, g.col, g.w), seed=seed, gamma=Fraction(*gm))
+    assert np.array_equal(r.labels, ref)
+
+
+def test_gamma_threshold_on_two_cliques():
+    """Two K5 (S = 40, vol = 4): a first move gains 40 q - 16 p, so every gamma
+    below 5/2 finds the cliques and gamma >= 5/2 keeps singletons."""
+    g = graphgen.disjoint_cliques(2, 5)
+    assert oracle.run(g.off, g.col, g.w, gamma=(249, 100)).q == 0.5
+    r = oracle.run(g.off, g.col, g.w, gamma=(5, 2))
+    assert r.q == -0.1 and len(set(r.labels.tolist())) == 10
+
+
+def test_gamma_one_in_any_form_is_plm():
+    g = graphgen.rmat(11, 16, seed=4, weighted=True)
+    a = oracle.run(g.off, g.col, g.w)
+    for gm in [(1, 1), (2, 2), (0, 0), (37, 37)]:
+        b = oracle.run(g.off, g.col, g.w, gamma=gm)
+        assert np.array_equal(a.labels, b.labels) and a.q == b.q
+
+
+def test_gamma_bounds():
+    g = graphgen.disjoint_cliques(2, 3)
+    for gm in [(-1, 1), (1, 0), (1 << 16, 1), (1, 1 << 16)]:
+        with pytest.raises(ValueError):
+            oracle.run(g.off, g.col, g.w, gamma=gm)
