@@ -100,7 +100,15 @@ typedef struct {
                               phase on that level starting from the prolonged
                               communities (same colour classes and sweep rule);
                               plm_run only (batches and servers: PLM_E_ARG) */
-    int32_t reserved[5];
+    /* resolution gamma = gamma_num / gamma_den (the gamma of section III-B;
+     * default 1/1, 0/0 also means 1): the gain becomes S dw - gamma vol(u) dvol,
+     * computed exactly as gamma_den S dw - gamma_num vol(u) dvol.
+     * 0 <= gamma_num, 1 <= gamma_den, both < 2^16; with gamma != 1 the total
+     * weight must satisfy S^2 max(num, den) < 2^126 (PLM_E_ARG at creation).
+     * The reported Q stays the plain modularity (gamma = 1). */
+    int32_t gamma_num;
+    int32_t gamma_den;
+    int32_t reserved[3];
 } plm_options;
 
 /* Fills *opt with the defaults above. */

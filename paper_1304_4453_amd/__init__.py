@@ -40,7 +40,7 @@ class plm_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("colour_seed", ctypes.c_uint64), ("int_mode", ctypes.c_int32),
                 ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class plm_level_info_t(ctypes.Structure):

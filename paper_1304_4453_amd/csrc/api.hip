@@ -188,6 +188,18 @@ struct plm_ctx {
 
     LevelData &L() { return levels[cur]; }
 
+    // resolution gamma = gp / gq (normalised at creation)
+    int64_t gp() const { return opt.gamma_num; }
+    int64_t gq() const { return opt.gamma_den; }
+    int64_t gmax() const { return opt.gamma_num > opt.gamma_den ? opt.gamma_num : opt.gamma_den; }
+    // largest vol(u) whose gains fit 64 bits: S vol(u) max(p, q) < 2^62
+    int64_t wide_limit(int64_t s) const {
+        unsigned __int128 sg = (unsigned __int128)(uint64_t)s * (unsigned __int128)(uint64_t)gmax();
+        if (sg == 0) return INT64_MAX;
+        if (sg >> 62) return 0;
+        return (int64_t)(((1ULL << 62) - 1) / (uint64_t)sg);
+    }
+
     int64_t bin_lane() const { return opt.bin_lane > 0 ? opt.bin_lane : 16; }
     int64_t bin_wave() const { return opt.bin_wave > 0 ? opt.bin_wave : 512; }
     int64_t bin_block() const { return opt.bin_block > 0 ? opt.bin_block : 4096; }
@@ -209,9 +221,13 @@ struct plm_ctx {
                 throw Error{PLM_E_GRAPH, batch ? "total weight of the batch must be below 2^62"
                                                : "total weight S = 2 w(E) must be below 2^62"};
             S = (int64_t)s;
+            if (gp() != gq()) {
+                unsigned __int128 b = (unsigned __int128)s * (unsigned __int128)s * (unsigned __int128)gmax();
+                if (b >> 126) throw Error{PLM_E_ARG, "gamma != 1 needs S^2 max(gamma_num, gamma_den) < 2^126"};
+            }
             HIPCHK(hipMemcpyAsync(vol0, vol, l.n * 8, hipMemcpyDeviceToDevice, st));
             if (batch) {
-                launch_graph_S(vol, l.gbase, G, gS0, gwl0, st);
+                launch_graph_S(vol, l.gbase, G, gmax(), gS0, gwl0, st);
                 HIPCHK(hipMemcpyAsync(gS, gS0, G * 8, hipMemcpyDeviceToDevice, st));
                 HIPCHK(hipMemcpyAsync(gwl, gwl0, G * 8, hipMemcpyDeviceToDevice, st));
             }
@@ -223,7 +239,7 @@ struct plm_ctx {
             throw Error{PLM_E_STATE, "internal: coarse graph changed the total weight"};
         }
         max_vol = hbuf[1];
-        wide_lim = S > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)S) : INT64_MAX;
+        wide_lim = wide_limit(S);
         if (!batch && opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
             throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
         launch_iota(zeta, l.n, st);
@@ -409,6 +425,8 @@ struct plm_ctx {
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
         ms.cand_sgl = count_cand ? dcnt + 13 : nullptr;
+        ms.gp = gp();
+        ms.gq = gq();
         if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; ms.gmoved = bgmoved; }
         return ms;
     }
@@ -632,7 +650,7 @@ struct plm_ctx {
             HIPCHK(hipStreamSynchronize(st));
             if (hbuf[0] != S) throw Error{PLM_E_STATE, "internal: level weight differs during refinement"};
             max_vol = hbuf[1];
-            wide_lim = S > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)S) : INT64_MAX;
+            wide_lim = wide_limit(S);
             if (opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
                 throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
             launch_comm_vol(zeta, vol, nl, volC, st);
@@ -824,6 +842,11 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.int_mode < 0 || o.int_mode > 2) { msg = "bad int_mode"; return PLM_E_ARG; }
     if (o.timing_kernel < 0 || o.timing_kernel > 5) { msg = "timing_kernel must lie in [0, 5]"; return PLM_E_ARG; }
     if (o.refine != 0 && o.refine != 1) { msg = "refine must be 0 or 1"; return PLM_E_ARG; }
+    if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
+        (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
+        msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
+        return PLM_E_ARG;
+    }
     int64_t a = o.bin_lane > 0 ? o.bin_lane : 16, b = o.bin_wave > 0 ? o.bin_wave : 512,
             c = o.bin_block > 0 ? o.bin_block : 4096;
     if (a > 16 || b > 512 || c > 4096 || a > b || b > c) {
@@ -877,6 +900,8 @@ void plm_default_options(plm_options *o) {
     o->bin_wave = 512;
     o->bin_block = 4096;
     o->timing = 0;
+    o->gamma_num = 1;
+    o->gamma_den = 1;
 }
 
 }  // extern "C"
@@ -920,6 +945,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
     std::string m;
     int rc = check_options(o, m);
     if (rc) return fail_adopt(rc, m);
+    if (o.gamma_num == 0 && o.gamma_den == 0) o.gamma_num = o.gamma_den = 1;
     if (G > 0) {
         if (o.refine) return fail_adopt(PLM_E_ARG, "batched runs do not refine");
         if (o.schedule != PLM_SCHEDULE_COLOUR) return fail_adopt(PLM_E_ARG, "batched runs use the colour schedule");

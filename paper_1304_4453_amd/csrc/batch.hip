@@ -92,8 +92,10 @@ void launch_batch_step(int64_t n0, const int32_t *gid0, const uint8_t *status, c
 }
 
 // Per graph a: S[a] = sum of vol over its node range and the 64-bit limit
-// wl[a] = (2^62 - 1) / S[a] of the gain arithmetic (no limit when S[a] = 0).
-__global__ __launch_bounds__(kBT) void k_graph_S(const int64_t *vol, const int64_t *base, int64_t *S, int64_t *wl) {
+// wl[a] = (2^62 - 1) / (S[a] gmax) of the gain arithmetic (gmax = max of the
+// resolution's numerator and denominator; no limit when S[a] = 0).
+__global__ __launch_bounds__(kBT) void k_graph_S(const int64_t *vol, const int64_t *base, int64_t gmax, int64_t *S,
+                                                 int64_t *wl) {
     __shared__ int64_t part[kBT / 64];
     int64_t a = blockIdx.x;
     int64_t lo = base[a], hi = base[a + 1];
@@ -106,12 +108,14 @@ __global__ __launch_bounds__(kBT) void k_graph_S(const int64_t *vol, const int64
         int64_t t = 0;
         for (int i = 0; i < kBT / 64; ++i) t += part[i];
         S[a] = t;
-        wl[a] = t > 0 ? (int64_t)(((1ULL << 62) - 1) / (uint64_t)t) : INT64_MAX;
+        unsigned __int128 sg = (unsigned __int128)(uint64_t)t * (unsigned __int128)(uint64_t)gmax;
+        wl[a] = sg == 0 ? INT64_MAX : ((sg >> 62) ? 0 : (int64_t)(((1ULL << 62) - 1) / (uint64_t)sg));
     }
 }
-void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t *S, int64_t *wl, hipStream_t st) {
+void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t gmax, int64_t *S, int64_t *wl,
+                    hipStream_t st) {
     if (A <= 0) return;
-    hipLaunchKernelGGL(k_graph_S, dim3((unsigned)A), dim3(kBT), 0, st, vol, base, S, wl);
+    hipLaunchKernelGGL(k_graph_S, dim3((unsigned)A), dim3(kBT), 0, st, vol, base, gmax, S, wl);
     HIPCHK(hipGetLastError());
 }
 

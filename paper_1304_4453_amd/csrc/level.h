@@ -40,6 +40,8 @@ struct MoveState {
     const int64_t *gS = nullptr;
     const int64_t *gwl = nullptr;
     int32_t *gmoved = nullptr;  // set to 1 for the graph of every node that moves
+    // resolution gamma = gp / gq: S is scaled by gq, vol(u) multipliers by gp
+    int64_t gp = 1, gq = 1;
 };
 
 __device__ __forceinline__ int64_t node_S(const MoveState &ms, int32_t u) { return ms.gid ? ms.gS[ms.gid[u]] : ms.S; }
@@ -132,7 +134,8 @@ void launch_fill_gid(const int64_t *base, int64_t A, int64_t n, int32_t *gid, hi
 void launch_batch_step(int64_t n0, const int32_t *gid0, const uint8_t *status, const int32_t *gid,
                        const int64_t *base, const int32_t *zeta, const int32_t *pi, int32_t *lab, int32_t *out,
                        hipStream_t st);
-void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t *S, int64_t *wl, hipStream_t st);
+void launch_graph_S(const int64_t *vol, const int64_t *base, int64_t A, int64_t gmax, int64_t *S, int64_t *wl,
+                    hipStream_t st);
 void batch_canonical(int64_t n0, const int32_t *gid0, const int64_t *gbase0, const int32_t *local, int32_t *keys,
                      int32_t *rank, int32_t *out, Scratch &scr, hipStream_t st);
 void batch_modularity_parts(const GraphView &g0, const int32_t *gid0, const int32_t *key, const int64_t *vol0,

@@ -7,7 +7,9 @@
 //   s(X) = S w(u,X) - vol(u) vol(X)
 // which differs from gain(X) by the constant K = S w(u,D\u) - vol(u) vol(D\u),
 // so the best candidate is the same and the move happens iff s_best > K.
-// |s|, |K| <= S vol(u): 64-bit arithmetic is exact while S vol(u) < 2^62,
+// With a resolution gamma = p / q every S is scaled by q and every vol(u)
+// multiplier by p (q times the gamma gain: same ranking, exact).
+// |s|, |K| <= S vol(u) max(p, q): 64-bit arithmetic is exact below 2^62,
 // otherwise the node takes the 128-bit path.  Ties go to the lowest X.
 //
 // Degree bins: rows up to 16 entries are handled one lane per node (register
@@ -80,7 +82,7 @@ constexpr int kLaneMax = 16;
 
 template <int WK, typename G>
 __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const int64_t (&W)[kLaneMax], int32_t D,
-                                             int64_t wD, int64_t vu, int64_t base, int64_t S, const int64_t *volC) {
+                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC) {
     G bg = 0;
     int32_t bx = kNone;
     const G vb = (G)vu * (G)base;
@@ -136,8 +138,9 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
-        int32_t bx = (force_wide || vu > node_wl(ms, u)) ? lane_pick<WK, i128>(X, W, D, wD, vu, base, S_u, ms.volC)
-                                                         : lane_pick<WK, int64_t>(X, W, D, wD, vu, base, S_u, ms.volC);
+        int32_t bx = (force_wide || vu > node_wl(ms, u))
+                         ? lane_pick<WK, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC)
+                         : lane_pick<WK, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 0 : nullptr, ncand);
@@ -159,8 +162,8 @@ constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 constexpr int kEvalBatch = 8;
 
 template <typename G, typename V>
-__device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, int64_t vu,
-                                           int64_t S, G K, const int64_t *volC, bool clear, G &bs, int32_t &bx,
+__device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, G vu, G S, G K,
+                                           const int64_t *volC, bool clear, G &bs, int32_t &bx,
                                            int64_t &ncand) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
@@ -190,8 +193,8 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
 }
 
 template <typename G>
-__device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
-                                          int64_t S, const int64_t *volC, int32_t &best_x, bool &move,
+__device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
+                                          const int64_t *volC, int32_t &best_x, bool &move,
                                           int64_t &ncand) {
     G bs = neg_inf<G>();
     int32_t bx = kNone;
@@ -274,9 +277,10 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         bool mv;
         const int64_t S_u = node_S(ms, u);
         if (force_wide || vu > node_wl(ms, u))
-            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, vu, base, S_u, ms.volC, bx, mv, ncand);
+            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, bx, mv,
+                            ncand);
         else
-            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu, base, S_u, ms.volC, bx, mv, ncand);
+            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv, ncand);
         if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
         wave_sync();
     }
@@ -288,8 +292,8 @@ constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
 
 template <typename G, int NT>
-__device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, int64_t vu, int64_t base,
-                                           int64_t S, const int64_t *volC, int32_t *out, int64_t &ncand) {
+__device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
+                                           const int64_t *volC, int32_t *out, int64_t &ncand) {
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
     __shared__ int32_t red_x[NT / kWave];
@@ -337,10 +341,11 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4
         int64_t base = ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         if (force_wide || vu > node_wl(ms, u))
-            block_eval<i128, kBlockThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+            block_eval<i128, kBlockThreads>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
+                                            ms.volC, &ms.move_to[pos], ncand);
         else
-            block_eval<int64_t, kBlockThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos],
-                                               ncand);
+            block_eval<int64_t, kBlockThreads>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
+                                               &ms.move_to[pos], ncand);
         __syncthreads();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
@@ -372,9 +377,11 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     const int64_t S_u = node_S(ms, u);
     int64_t ncand = 0;
     if (force_wide || vu > node_wl(ms, u))
-        block_eval<i128, kSingleThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+        block_eval<i128, kSingleThreads>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC,
+                                         &ms.move_to[pos], ncand);
     else
-        block_eval<int64_t, kSingleThreads>(tk, tv, 1 << bits, myD, vu, base, S_u, ms.volC, &ms.move_to[pos], ncand);
+        block_eval<int64_t, kSingleThreads>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
+                                            &ms.move_to[pos], ncand);
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
     count_candidates(ms.cand_sgl, ncand);
 }
@@ -516,7 +523,7 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
 // bucket into one flat index space that every thread strides over (a binary
 // search finds the chunk of an index).
 template <typename G>
-__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, int64_t vu, int64_t S, G K,
+__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, G vu, G S, G K,
                                            const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
                                            int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
                                            int32_t &bx, int64_t &ncand) {
@@ -649,14 +656,16 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     int32_t bx = kNone;
     const int64_t S_u = node_S(ms, u);
     if (force_wide || vu > node_wl(ms, u)) {
-        const i128 K = (i128)S_u * (i128)wD - (i128)vu * (i128)base;
-        agg_bucket<i128>(ha, hg, p, vu, S_u, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
+        const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
+        const i128 K = Sg * (i128)wD - vg * (i128)base;
+        agg_bucket<i128>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
                          ncand);
         block_argmax<i128>(bs, bx);
     } else {
-        const int64_t K = S_u * wD - vu * base;
+        const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
+        const int64_t K = Sg * wD - vg * base;
         int64_t b64 = neg_inf<int64_t>();
-        agg_bucket<int64_t>(ha, hg, p, vu, S_u, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
+        agg_bucket<int64_t>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
                             ncand);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
@@ -697,7 +706,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArr
         int32_t D = ms.zeta[u];
         int64_t vu = ms.vol[u];
         int64_t base = ms.volC[D] - vu;
-        i128 K = (i128)node_S(ms, u) * (i128)wD - (i128)vu * (i128)base;
+        i128 K = (i128)node_S(ms, u) * ms.gq * (i128)wD - (i128)vu * ms.gp * (i128)base;
         ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
     }
 }

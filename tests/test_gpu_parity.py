@@ -74,11 +74,12 @@ def stepwise(P, g, seed=0, schedule=0, per_class=True, max_sweeps=32, max_levels
         ctx.close()
 
 
-def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, refine=False, **opts):
+def full_run(P, g, seed=0, schedule=0, max_sweeps=32, max_levels=0, refine=False, gamma=(1, 1), **opts):
     r = oracle.run(g.off, g.col, g.w, max_sweeps=max_sweeps, max_levels=max_levels, seed=seed, schedule=schedule,
-                   refine=refine)
+                   refine=refine, gamma=gamma)
     with P.Context(g.off, g.col, g.w, colour_seed=seed, schedule=schedule, max_sweeps=max_sweeps,
-                   max_levels=max_levels, refine=int(refine), **opts) as ctx:
+                   max_levels=max_levels, refine=int(refine), gamma_num=gamma[0], gamma_den=gamma[1],
+                   **opts) as ctx:
         labels, q, lv = ctx.run()
         st = ctx.stats()
     assert lv == r.levels
@@ -187,6 +188,50 @@ def test_plmr_rejected_for_batches(P):
     with pytest.raises(P.PLMError) as e:
         P.BatchContext(np.array([0, 3, 6]), g.off, g.col, g.w, refine=1)
     assert e.value.status == P.PLM_E_ARG
+
+
+# ------------------------------------------------------------------ resolution gamma
+GAMMAS = [(1, 2), (3, 2), (7, 3), (0, 1), (5, 1)]
+
+
+@pytest.mark.parametrize("gamma", GAMMAS, ids=[f"{a}_{b}" for a, b in GAMMAS])
+@pytest.mark.parametrize("bins", [{}, SMALL_BINS, MID_BINS], ids=["default", "small", "mid"])
+def test_gamma_random_all_bins(P, gamma, bins):
+    _say("gamma random", gamma, bins)
+    g = graphgen.random_graph(200, 0.05, seed=90 + gamma[0], weighted=True, loops=0.1)
+    full_run(P, g, seed=gamma[1], gamma=gamma, **bins)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (7, 3)], ids=["1_2", "7_3"])
+def test_gamma_rmat_plmr_int128(P, gamma):
+    _say("gamma rmat plmr int128", gamma)
+    g = graphgen.rmat(12, 16, seed=14, weighted=True)
+    full_run(P, g, gamma=gamma)
+    full_run(P, g, gamma=gamma, refine=True)
+    full_run(P, g, gamma=gamma, int_mode=P.PLM_INT_128, **SMALL_BINS)
+
+
+def test_gamma_batch_matches_oracle(P):
+    _say("gamma batch")
+    graphs = [graphgen.planted_partition_1000(seed=4), graphgen.ring_of_cliques(6, 4),
+              graphgen.random_graph(150, 0.05, seed=3, weighted=True, loops=0.2), graphgen.rmat(11, 16, seed=2)]
+    nb, off, col, w = P.pack_batch(graphs)
+    with P.BatchContext(nb, off, col, w, gamma_num=3, gamma_den=2) as ctx:
+        labels, q, lv = ctx.run_batch()
+    for i, g in enumerate(graphs):
+        r = oracle.run(g.off, g.col, g.w, gamma=(3, 2))
+        a, b = int(nb[i]), int(nb[i + 1])
+        assert np.array_equal(labels[a:b], r.labels) and q[i] == r.q and lv[i] == r.levels
+
+
+def test_gamma_argument_errors(P):
+    g = graphgen.disjoint_cliques(2, 3)
+    for gm in [(-1, 1), (1, 0), (1 << 16, 1)]:
+        with pytest.raises(P.PLMError) as e:
+            P.Context(g.off, g.col, g.w, gamma_num=gm[0], gamma_den=gm[1])
+        assert e.value.status == P.PLM_E_ARG
+    with P.Context(g.off, g.col, g.w, gamma_num=0, gamma_den=0) as ctx:   # 0/0 means 1
+        assert ctx.run()[1] == oracle.run(g.off, g.col, g.w).q
 
 
 def test_int64_mode_rejects_overflow(P):
