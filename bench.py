@@ -8,6 +8,7 @@ already resident in HBM.  Prints ONE JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000] [--no-batch]
 
 The line also carries "plmr": one PLMR run (Algorithm 4) on the same graph;
+"gamma": R-MAT 20 runs at resolutions 1/2, 1 and 2;
 "batched": the batched engine (plm_batch_run) on 4,096
 uneven SBM graphs against a per-graph plm_run loop on the same GPU; and
 "served": the request server (plm_server_*) under Poisson arrivals, with
@@ -364,6 +365,30 @@ def plmr_bench(gr, P, torch, q_plm, st_plm):
             "refinement_ms": sum(st["ref_ms"]), "ref_sweeps": st["ref_sweeps"], "ref_moves": st["ref_moves"]}
 
 
+def gamma_bench(P, torch):
+    """Resolution gamma on R-MAT 20 (unit weights, seed 2) resident in HBM: one
+    warm-up and one timed full run per gamma; time, Q and communities."""
+    import graphgen
+    dg = graphgen.rmat_gpu(20, 16, seed=2, weighted=False)
+    out = []
+    for num, den in [(1, 2), (1, 1), (2, 1)]:
+        ctx = P.Context(dg.off_ptr, dg.col_ptr, None, mem_kind=P.PLM_MEM_DEVICE, n=dg.n, nnz=dg.nnz,
+                        gamma_num=num, gamma_den=den)
+        lab = torch.empty(dg.n, dtype=torch.int32, device="cuda:0")
+        ctx.run(lab)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, q, lv = ctx.run(lab)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st = ctx.stats()
+        ctx.close()
+        out.append({"gamma": f"{num}/{den}", "ms_per_run": dt * 1e3, "q": q, "levels": lv,
+                    "communities": st["communities"][-1]})
+    dg.free()
+    return {"workload": "R-MAT scale 20, edge factor 16, unit weights, seed 2", "runs": out}
+
+
 def sweep_probe(P, torch):
     """One level-0 move sweep of the R-MAT 26 workload with every move-decide
     kernel timed, after a 1 GiB device copy that calibrates the HBM byte
@@ -405,6 +430,7 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=256)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-plmr", action="store_true")
+    ap.add_argument("--no-gamma", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served workload")
     ap.add_argument("--plain-serve-sample", type=int, default=40)
     ap.add_argument("--sweep-probe", action="store_true",
@@ -501,6 +527,8 @@ def main():
     ctx.close()
     if not args.no_plmr:
         out["plmr"] = plmr_bench(gr, P, torch, q, st)
+    if not args.no_gamma:
+        out["gamma"] = gamma_bench(P, torch)
     if gr["dg"] is not None:
         gr["dg"].free()
     if not args.no_batch:
