@@ -80,6 +80,11 @@ def lib():
         L.orc_run.argtypes = [i64, P64, P32, P64, ctypes.POINTER(_Options), P32, ctypes.POINTER(dbl),
                               ctypes.POINTER(_Trace)]
         L.orc_run.restype = ctypes.c_int
+        L.orc_plp_run.argtypes = [i64, P64, P32, P64, u64, i32, P32, ctypes.POINTER(dbl), P64, P32]
+        L.orc_plp_run.restype = ctypes.c_int
+        L.orc_epp.argtypes = [i64, P64, P32, P64, i32, i32, ctypes.POINTER(_Options), P32, ctypes.POINTER(dbl),
+                              P64, P32, ctypes.POINTER(_Trace)]
+        L.orc_epp.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -271,3 +276,70 @@ def run(off, col, w=None, max_sweeps: int = 32, max_levels: int = 0, seed: int =
                      [tr.sweeps[i] for i in range(L)], [tr.communities[i] for i in range(L)],
                      [[tr.moves[i][s] for s in range(tr.sweeps[i])] for i in range(L)], int(tr.S),
                      [tr.ref_sweeps[i] for i in range(L)], [tr.ref_moves[i] for i in range(L)])
+
+
+@dataclass
+class PLPResult:
+    labels: np.ndarray
+    q: float
+    iterations: int
+    updates: list   # nodes updated in each iteration
+
+
+def plp(off, col, w=None, seed: int = 0, max_iters: int = 64) -> PLPResult:
+    """PLP (Algorithm 1) with the colour-class schedule, active sets and
+    theta = n * 10^-5; canonical labels."""
+    off, col = _i64(off), _i32(col)
+    n = off.shape[0] - 1
+    wp = None
+    if w is not None:
+        w = _i64(w)
+        wp = _p(w, ctypes.c_int64)
+    labels = np.zeros(max(n, 1), np.int32)
+    q = ctypes.c_double()
+    upd = np.zeros(MAX_SWEEPS, np.int64)
+    it = ctypes.c_int32()
+    rc = lib().orc_plp_run(n, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32), wp, seed, max_iters,
+                           _p(labels, ctypes.c_int32), ctypes.byref(q), _p(upd, ctypes.c_int64), ctypes.byref(it))
+    if rc != 0:
+        raise ValueError("orc_plp_run: max_iters must lie in [1, 64]")
+    return PLPResult(labels[:n].copy(), float(q.value), int(it.value), [int(x) for x in upd[: it.value]])
+
+
+@dataclass
+class EPPResult:
+    labels: np.ndarray
+    q: float
+    cores: int      # core groups (nodes of the coarse graph given to PLMR)
+    core_groups: np.ndarray  # coarse node of each input node (ascending with the smallest member)
+    levels: int     # levels of the final PLMR run
+    run: RunResult  # trace of the final PLMR run (its level 0 is the core-group graph)
+
+
+def epp(off, col, w=None, b: int = 4, seed: int = 0, plp_iters: int = 64, max_sweeps: int = 32,
+        max_levels: int = 0, gamma=(1, 1), schedule: int = 0) -> EPPResult:
+    """EPP(b, PLP, PLMR) (Algorithm 5) with exact core groups (Equation (3.2))."""
+    off, col = _i64(off), _i32(col)
+    n = off.shape[0] - 1
+    wp = None
+    if w is not None:
+        w = _i64(w)
+        wp = _p(w, ctypes.c_int64)
+    opt = _Options(max_sweeps, max_levels, schedule, 1, seed, gamma[0], gamma[1])
+    tr = _Trace()
+    labels = np.zeros(max(n, 1), np.int32)
+    q = ctypes.c_double()
+    cores = ctypes.c_int64()
+    cg = np.zeros(max(n, 1), np.int32)
+    rc = lib().orc_epp(n, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32), wp, b, plp_iters, ctypes.byref(opt),
+                       _p(labels, ctypes.c_int32), ctypes.byref(q), ctypes.byref(cores), _p(cg, ctypes.c_int32),
+                       ctypes.byref(tr))
+    if rc != 0:
+        raise ValueError("orc_epp: bad arguments")
+    L = tr.levels
+    run_tr = RunResult(labels[:n].copy(), float(q.value), L, [tr.n[i] for i in range(L)],
+                       [tr.nnz[i] for i in range(L)], [tr.colours[i] for i in range(L)],
+                       [tr.sweeps[i] for i in range(L)], [tr.communities[i] for i in range(L)],
+                       [[tr.moves[i][s] for s in range(tr.sweeps[i])] for i in range(L)], 0,
+                       [tr.ref_sweeps[i] for i in range(L)], [tr.ref_moves[i] for i in range(L)])
+    return EPPResult(labels[:n].copy(), float(q.value), int(cores.value), cg[:n].copy(), L, run_tr)

@@ -431,7 +431,8 @@ void orc_canonical(int64_t n, const int32_t *lab, int32_t *out) {
  * Leaves the communities in zeta_out[n]; returns the number of levels below
  * and including this one. */
 static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, int32_t level,
-                        const orc_options *opt, int32_t *zeta_out, orc_trace *tr) {
+                        int32_t first, const orc_options *opt, int32_t *zeta_out, orc_trace *tr) {
+    const int32_t t = level - first;   /* trace slot and level count relative to the first level */
     int64_t nnz = off[n];
     int64_t *vol = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     int64_t *volC = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
@@ -441,26 +442,26 @@ static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const
     /* move from singletons */
     for (int64_t u = 0; u < n; ++u) { zeta_out[u] = (int32_t)u; volC[u] = vol[u]; }
     int64_t sweeps = 0;
-    if (level < ORC_MAX_LEVELS) { tr->n[level] = n; tr->nnz[level] = nnz; tr->colours[level] = ncol; }
+    if (t < ORC_MAX_LEVELS) { tr->n[t] = n; tr->nnz[t] = nnz; tr->colours[t] = ncol; }
     for (int32_t s = 0; s < opt->max_sweeps; ++s) {
         int64_t mv = orc_sweep(n, off, col, w2, vol, S, opt->gamma_num, opt->gamma_den, colour, ncol, zeta_out,
                                volC);
-        if (level < ORC_MAX_LEVELS) tr->moves[level][s] = mv;
+        if (t < ORC_MAX_LEVELS) tr->moves[t][s] = mv;
         ++sweeps;
         if (mv == 0) break;
     }
     int32_t *pi = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     int64_t k = orc_relabel(n, zeta_out, pi);
-    if (level < ORC_MAX_LEVELS) { tr->sweeps[level] = sweeps; tr->communities[level] = k; }
+    if (t < ORC_MAX_LEVELS) { tr->sweeps[t] = sweeps; tr->communities[t] = k; }
     int32_t depth = 1;
-    if (k < n && !(opt->max_levels > 0 && level + 1 >= opt->max_levels)) {
+    if (k < n && !(opt->max_levels > 0 && t + 1 >= opt->max_levels)) {
         /* coarsen, recurse, prolong */
         int64_t *coff = (int64_t *)malloc(((size_t)k + 1) * sizeof(int64_t));
         int32_t *ccol = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
         int64_t *cw = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
         orc_contract(n, off, col, w2, pi, k, coff, ccol, cw);
         int32_t *zc = (int32_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(int32_t));
-        depth += orc_plmr(k, coff, ccol, cw, level + 1, opt, zc, tr);
+        depth += orc_plmr(k, coff, ccol, cw, level + 1, first, opt, zc, tr);
         for (int64_t u = 0; u < n; ++u) zeta_out[u] = zc[pi[u]];
         free(zc); free(coff); free(ccol); free(cw);
         /* move again, from the prolonged communities */
@@ -474,7 +475,7 @@ static int32_t orc_plmr(int64_t n, const int64_t *off, const int32_t *col, const
             rm += mv;
             if (mv == 0) break;
         }
-        if (level < ORC_MAX_LEVELS) { tr->ref_sweeps[level] = rs; tr->ref_moves[level] = rm; }
+        if (t < ORC_MAX_LEVELS) { tr->ref_sweeps[t] = rs; tr->ref_moves[t] = rm; }
     }
     free(pi); free(vol); free(volC); free(colour);
     return depth;
@@ -502,7 +503,7 @@ int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w,
     }
     if (opt->refine) {
         int32_t *zeta = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-        tr->levels = orc_plmr(n, off, col, w2_0, 0, opt, zeta, tr);
+        tr->levels = orc_plmr(n, off, col, w2_0, 0, 0, opt, zeta, tr);
         tr->S = 0;
         for (int64_t e = 0; e < nnz; ++e) tr->S += w2_0[e];
         orc_canonical(n, zeta, labels);
@@ -564,5 +565,181 @@ int orc_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w,
     *q_out = orc_modularity(n, off, col, w2_0, labels, NULL, NULL, NULL, NULL);
     free(lab); free(w2_0);
     free(own_off); free(own_col); free(own_w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ PLP (Algorithm 1)
+ * Label propagation with the deterministic schedule of this library: the
+ * colour classes of the level (ascending), each class deciding against the
+ * labels at its start and then applying (classes are independent sets).  A node
+ * is visited while active (Algorithm 1: it turns inactive when it keeps its
+ * label, and active again when a neighbour changes label).  The dominant label
+ * of v maximises the weight sum of its non-loop neighbours carrying it; v keeps
+ * its label when that label attains the maximum, else takes, among the labels
+ * l that do, the one with the largest tie key t(v, l) = upper 32 bits of
+ * SplitMix64(H(seed, level, v) ^ l), then the lowest label.  The paper breaks
+ * ties arbitrarily; a key drawn per (node, label) stands in for an independent
+ * random choice at every node (a fixed order of labels would let one label win
+ * every tie and flood the graph).  Iterations (passes over all classes) continue while the number
+ * of updated nodes exceeds theta = n * 10^-5, at most max_iters times.
+ * zeta[n] receives the labels (node ids); returns the number of iterations. */
+static int32_t orc_dominant_label(int64_t v, const int64_t *off, const int32_t *col, const int64_t *w2,
+                                  const int32_t *zeta, uint64_t seed, int32_t level, orc_map *m) {
+    int64_t nt = 0;
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        int64_t u = col[e];
+        if (u == v) continue;
+        int32_t l = zeta[u];
+        if (!m->seen[l]) { m->seen[l] = 1; m->acc[l] = 0; m->touched[nt++] = l; }
+        m->acc[l] += w2[e];
+    }
+    const int32_t own = zeta[v];
+    const int64_t wown = m->seen[own] ? m->acc[own] : 0;
+    const uint64_t hv = orc_priority(seed, level, v);   /* tie keys differ from node to node */
+    int32_t best = -1;
+    int64_t bw = 0;
+    uint32_t bt = 0;
+    if (nt > 0) {
+        qsort(m->touched, (size_t)nt, sizeof(int32_t), orc_i32_cmp);
+        for (int64_t i = 0; i < nt; ++i) {        /* ascending labels: strict comparisons keep the lowest */
+            int32_t l = m->touched[i];
+            if (l == own) continue;
+            uint32_t t = (uint32_t)(orc_splitmix64(hv ^ (uint64_t)(uint32_t)l) >> 32);
+            if (best < 0 || m->acc[l] > bw || (m->acc[l] == bw && t > bt)) { best = l; bw = m->acc[l]; bt = t; }
+        }
+    }
+    for (int64_t i = 0; i < nt; ++i) m->seen[m->touched[i]] = 0;
+    return (best >= 0 && bw > wown) ? best : own;
+}
+
+int32_t orc_plp(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, uint64_t seed, int32_t level,
+                int32_t max_iters, int32_t *zeta, int64_t *updates_out) {
+    int32_t *colour = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t ncol = orc_colour(n, off, col, seed, level, 0, colour);
+    int64_t *cls_off = (int64_t *)malloc((size_t)(ncol + 1) * sizeof(int64_t));
+    int32_t *cls_nodes = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *dec = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    uint8_t *active = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    orc_classes(n, colour, ncol, cls_off, cls_nodes);
+    orc_map m;
+    orc_map_init(&m, n);
+    for (int64_t v = 0; v < n; ++v) {
+        zeta[v] = (int32_t)v;
+        int deg = 0;   /* degree without the self-loop */
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) deg += (col[e] != v);
+        active[v] = deg > 0;
+    }
+    int64_t updated = n;
+    int32_t it = 0;
+    while (updated * 100000 > n && it < max_iters) {    /* updated > theta = n * 10^-5 */
+        updated = 0;
+        for (int64_t c = 0; c < ncol; ++c) {
+            const int32_t *mem = cls_nodes + cls_off[c];
+            int64_t cnt = cls_off[c + 1] - cls_off[c];
+            for (int64_t i = 0; i < cnt; ++i)
+                dec[i] = active[mem[i]] ? orc_dominant_label(mem[i], off, col, w2, zeta, seed, level, &m)
+                                        : zeta[mem[i]];
+            for (int64_t i = 0; i < cnt; ++i) {
+                int32_t v = mem[i];
+                if (!active[v]) continue;
+                if (dec[i] != zeta[v]) {
+                    zeta[v] = dec[i];
+                    ++updated;
+                    for (int64_t e = off[v]; e < off[v + 1]; ++e)
+                        if (col[e] != v) active[col[e]] = 1;
+                } else {
+                    active[v] = 0;
+                }
+            }
+        }
+        if (updates_out && it < ORC_MAX_SWEEPS) updates_out[it] = updated;
+        ++it;
+    }
+    orc_map_free(&m);
+    free(colour); free(cls_off); free(cls_nodes); free(dec); free(active);
+    return it;
+}
+
+/* PLP from the input CSR: canonical labels, modularity, iterations. */
+int orc_plp_run(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, uint64_t seed, int32_t max_iters,
+                int32_t *labels, double *q_out, int64_t *updates_out, int32_t *iters_out) {
+    if (max_iters < 1 || max_iters > ORC_MAX_SWEEPS) return -1;
+    int64_t nnz = off[n];
+    int64_t *w2 = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    int32_t *zeta = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_double_diagonal(n, off, col, w, w2);
+    *iters_out = orc_plp(n, off, col, w2, seed, 0, max_iters, zeta, updates_out);
+    orc_canonical(n, zeta, labels);
+    *q_out = orc_modularity(n, off, col, w2, labels, NULL, NULL, NULL, NULL);
+    free(w2); free(zeta);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ EPP (Algorithm 5)
+ * EPP(b, PLP, PLMR): b PLP runs (colour seeds seed .. seed+b-1), core groups by
+ * Equation (3.2) (same group iff every base solution agrees; exact tuple
+ * comparison instead of a hash), coarsening by the core groups (coarse ids
+ * ascending with the smallest member), PLMR on the coarse graph as level 1, and
+ * prolongation.  Canonical labels and the modularity on the input graph. */
+static const int32_t *orc_epp_base;   /* b base solutions, row-major [b][n], for the tuple sort */
+static int64_t orc_epp_b, orc_epp_n;
+static int orc_tuple_cmp(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    for (int64_t i = 0; i < orc_epp_b; ++i) {
+        int32_t lx = orc_epp_base[i * orc_epp_n + x], ly = orc_epp_base[i * orc_epp_n + y];
+        if (lx != ly) return lx < ly ? -1 : 1;
+    }
+    return x < y ? -1 : (x > y);
+}
+
+int orc_epp(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w, int32_t b, int32_t plp_iters,
+            const orc_options *opt, int32_t *labels, double *q_out, int64_t *cores_out, int32_t *core_groups,
+            orc_trace *tr) {
+    if (b < 1 || plp_iters < 1 || plp_iters > ORC_MAX_SWEEPS || opt->max_sweeps < 1 ||
+        opt->max_sweeps > ORC_MAX_SWEEPS)
+        return -1;
+    memset(tr, 0, sizeof(*tr));
+    orc_options o = *opt;
+    if (o.gamma_num == 0 && o.gamma_den == 0) o.gamma_num = o.gamma_den = 1;
+    o.refine = 1;
+    int64_t nnz = off[n];
+    int64_t *w2 = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    orc_double_diagonal(n, off, col, w, w2);
+    int32_t *base = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * (size_t)b * sizeof(int32_t));
+    for (int32_t i = 0; i < b; ++i)
+        orc_plp(n, off, col, w2, o.seed + (uint64_t)i, 0, plp_iters, base + (size_t)i * (size_t)n, NULL);
+    /* core groups: nodes sorted by their tuple of base labels; a group's id is its smallest member */
+    int32_t *ord = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *core = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < n; ++v) ord[v] = (int32_t)v;
+    orc_epp_base = base; orc_epp_b = b; orc_epp_n = n;
+    qsort(ord, (size_t)n, sizeof(int32_t), orc_tuple_cmp);
+    for (int64_t i = 0; i < n;) {
+        int64_t j = i;
+        while (j < n) {
+            int same = 1;
+            for (int32_t t = 0; t < b && same; ++t)
+                same = base[(size_t)t * n + ord[j]] == base[(size_t)t * n + ord[i]];
+            if (!same) break;
+            ++j;
+        }
+        for (int64_t k = i; k < j; ++k) core[ord[k]] = ord[i];   /* smallest member: the sort breaks ties by id */
+        i = j;
+    }
+    int32_t *pi = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t k = orc_relabel(n, core, pi);
+    *cores_out = k;
+    if (core_groups) memcpy(core_groups, pi, (size_t)n * sizeof(int32_t));   /* coarse node of each node */
+    int64_t *coff = (int64_t *)malloc(((size_t)k + 1) * sizeof(int64_t));
+    int32_t *ccol = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    int64_t *cw = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+    orc_contract(n, off, col, w2, pi, k, coff, ccol, cw);
+    int32_t *zc = (int32_t *)malloc((size_t)(k > 0 ? k : 1) * sizeof(int32_t));
+    tr->levels = orc_plmr(k, coff, ccol, cw, 1, 1, &o, zc, tr);
+    int32_t *zeta = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t v = 0; v < n; ++v) zeta[v] = zc[pi[v]];
+    orc_canonical(n, zeta, labels);
+    *q_out = orc_modularity(n, off, col, w2, labels, NULL, NULL, NULL, NULL);
+    free(w2); free(base); free(ord); free(core); free(pi); free(coff); free(ccol); free(cw); free(zc); free(zeta);
     return 0;
 }

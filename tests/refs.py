@@ -11,6 +11,8 @@ the paper's formulas in their own (rational) form, or delegated to networkx:
   exact fractions, visiting nodes in a given priority order.
 * ``set_partitions``: brute-force enumeration for tiny graphs.
 * ``splitmix64``: the published SplitMix64 step.
+* ``seq_plp``: label propagation (Algorithm 1) over given colour classes, in
+  plain Python dictionaries.
 """
 from __future__ import annotations
 
@@ -183,13 +185,15 @@ def seq_louvain(n, edges, seed=0, max_sweeps=32, max_levels=0, gamma=Fraction(1)
     return np.array(out, dtype=np.int32)
 
 
-def seq_plmr(n, edges, seed=0, max_sweeps=32, max_levels=0):
+def seq_plmr(n, edges, seed=0, max_sweeps=32, max_levels=0, first_level=0):
     """PLMR (Algorithm 4) with the sequential schedule and the paper's
     Delta-mod in fractions, written recursively as the algorithm is stated:
     move from singletons; if communities merged, coarsen, recurse, prolong
     (u takes the community of its coarse node, named by that node's community
     id on the coarse level) and move again from the prolonged communities.
-    Moves, ties and coarse ids follow seq_louvain.  Returns canonical labels."""
+    Moves, ties and coarse ids follow seq_louvain.  The input graph is level
+    first_level (priorities are drawn for that level; max_levels counts from
+    it).  Returns canonical labels."""
 
     def graph(cur_n, cur_edges):
         adj = [dict() for _ in range(cur_n)]
@@ -237,7 +241,7 @@ def seq_plmr(n, edges, seed=0, max_sweeps=32, max_levels=0):
         adj, vol, W = graph(cur_n, cur_edges)
         zeta = move(cur_n, adj, vol, W, list(range(cur_n)), level)
         ids = sorted(set(zeta))
-        if len(ids) == cur_n or (max_levels and level + 1 >= max_levels):
+        if len(ids) == cur_n or (max_levels and level - first_level + 1 >= max_levels):
             return zeta
         newid = {c: i for i, c in enumerate(ids)}
         pi = [newid[zeta[u]] for u in range(cur_n)]
@@ -249,9 +253,57 @@ def seq_plmr(n, edges, seed=0, max_sweeps=32, max_levels=0):
         zeta = [zc[pi[u]] for u in range(cur_n)]
         return move(cur_n, adj, vol, W, zeta, level)
 
-    z = rec(n, dict(edges), 0)
+    z = rec(n, dict(edges), first_level)
     canon, out = {}, []
     for x in z:
         canon.setdefault(x, len(canon))
         out.append(canon[x])
     return np.array(out, dtype=np.int32)
+
+
+def seq_plp(off, col, w, colours, seed=0, level=0, max_iters=64, active_sets=True):
+    """Label propagation (Algorithm 1) over the given colour classes, in plain
+    Python: classes in ascending colour, each deciding against the labels at
+    its start; dominant label by weight over non-loop neighbours, own label
+    kept when it attains the maximum, else the largest tie key
+    t(v, l) = SplitMix64(H(seed, level, v) ^ l) >> 32, then the lowest label;
+    active sets as in the algorithm (or every node every iteration); stop when
+    updated <= n * 10^-5.  Returns (labels as node ids, updates per iteration)."""
+    n = len(off) - 1
+    wts = np.ones(len(col), np.int64) if w is None else np.asarray(w, np.int64)
+    zeta = list(range(n))
+    active = [any(int(c) != v for c in col[off[v]:off[v + 1]]) for v in range(n)]
+    has_nb = list(active)
+    classes = {}
+    for v in range(n):
+        classes.setdefault(int(colours[v]), []).append(v)
+    updates, updated, it = [], n, 0
+    while updated * 100000 > n and it < max_iters:
+        updated = 0
+        for c in sorted(classes):
+            dec = {}
+            for v in classes[c]:
+                if not (active[v] if active_sets else has_nb[v]):
+                    continue
+                acc = {}
+                for e in range(off[v], off[v + 1]):
+                    u = int(col[e])
+                    if u != v:
+                        acc[zeta[u]] = acc.get(zeta[u], 0) + int(wts[e])
+                own = zeta[v]
+                hv = splitmix64(seed ^ (level << 40) ^ v)
+                cands = [(acc[l], splitmix64(hv ^ l) >> 32, -l) for l in acc if l != own]
+                best = max(cands) if cands else None
+                dec[v] = -best[2] if best is not None and best[0] > acc.get(own, 0) else own
+            for v, l in dec.items():
+                if l != zeta[v]:
+                    zeta[v] = l
+                    updated += 1
+                    for e in range(off[v], off[v + 1]):
+                        if int(col[e]) != v:
+                            active[int(col[e])] = True
+                else:
+                    active[v] = False
+        updates.append(updated)
+        it += 1
+    return np.array(zeta, np.int32), updates

@@ -496,3 +496,168 @@ def test_gamma_bounds():
     for gm in [(-1, 1), (1, 0), (1 << 16, 1), (1, 1 << 16)]:
         with pytest.raises(ValueError):
             oracle.run(g.off, g.col, g.w, gamma=gm)
+
+
+# ------------------------------------------------------------------ PLP (Algorithm 1)
+def _canon(lab):
+    m, out = {}, []
+    for x in lab:
+        m.setdefault(int(x), len(m))
+        out.append(m[int(x)])
+    return np.array(out, np.int32)
+
+
+def _seq_plp(g, seed=0, max_iters=64, active_sets=True):
+    colours = refs.nx_greedy_colouring(g.off, g.col, refs.priority_order(g.n, seed, 0))
+    return refs.seq_plp(g.off, g.col, g.w, colours, seed=seed, max_iters=max_iters, active_sets=active_sets)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_plp_equals_python_label_propagation(seed):
+    """Same colour classes (networkx greedy colouring in priority order), same
+    tie key: labels, iterations and updates per iteration agree."""
+    rng = np.random.default_rng(1200 + seed)
+    n = int(rng.integers(20, 160))
+    g = graphgen.random_graph(n, float(rng.uniform(0.03, 0.2)), seed=1300 + seed, weighted=seed % 2 == 1,
+                              loops=0.2 if seed % 3 == 0 else 0.0)
+    r = oracle.plp(g.off, g.col, g.w, seed=seed)
+    lab, upd = _seq_plp(g, seed)
+    assert np.array_equal(r.labels, _canon(lab))
+    assert r.updates == upd and r.iterations == len(upd)
+    assert r.q == pytest.approx(refs.nx_modularity(g.off, g.col, g.w, r.labels), abs=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plp_active_sets_change_nothing(seed):
+    """A node turns inactive only after keeping its label; its neighbourhood's
+    labels are unchanged until a neighbour moves, so evaluating it anyway would
+    keep the label again: the active set is an optimisation only."""
+    g = graphgen.sbm(400, 8, 0.12, 0.01, seed=1400 + seed)
+    r = oracle.plp(g.off, g.col, g.w, seed=seed)
+    lab, upd = _seq_plp(g, seed, active_sets=False)
+    assert np.array_equal(r.labels, _canon(lab)) and r.updates == upd
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_plp_fixed_point_is_dominant(seed):
+    """When the last iteration updated nothing, every node carries a dominant
+    label of its neighbourhood (by brute force over its neighbours)."""
+    g = graphgen.rmat(9, 8, seed=1500 + seed, weighted=seed % 2 == 0)
+    r = oracle.plp(g.off, g.col, g.w, seed=seed)
+    assert r.updates[-1] == 0
+    wts = np.ones(g.nnz, np.int64) if g.w is None else g.w
+    for v in range(g.n):
+        acc = {}
+        for e in range(g.off[v], g.off[v + 1]):
+            u = int(g.col[e])
+            if u != v:
+                acc[int(r.labels[u])] = acc.get(int(r.labels[u]), 0) + int(wts[e])
+        if acc:
+            assert acc.get(int(r.labels[v]), 0) == max(acc.values())
+
+
+@pytest.mark.parametrize("c,k", [(2, 3), (3, 5), (6, 4), (10, 8)])
+def test_plp_disjoint_cliques_one_label_each(c, k):
+    """In K_k the first node to move takes a neighbour's label, which then
+    carries weight 2 against 1 for every other label: one label per clique,
+    Q = 1 - 1/c."""
+    g = graphgen.disjoint_cliques(c, k)
+    r = oracle.plp(g.off, g.col, g.w)
+    assert np.array_equal(r.labels, np.repeat(np.arange(c), k).astype(np.int32))
+    assert r.q == pytest.approx(1 - 1 / c, abs=1e-15)
+
+
+def test_plp_isolated_loops_and_empty():
+    """Nodes without non-loop neighbours keep their own label and are never
+    visited; the empty graph takes no iteration work."""
+    g = graphgen.from_edges(5, [(1, 2)], loops={0: 3})
+    r = oracle.plp(g.off, g.col, g.w)
+    assert r.labels[0] != r.labels[1] and r.labels[1] == r.labels[2]
+    assert len(set(r.labels.tolist())) == 4
+    e = graphgen.from_edges(0, [])
+    assert oracle.plp(e.off, e.col, e.w).labels.shape == (0,)
+
+
+def test_plp_iteration_cap_and_threshold():
+    g = graphgen.rmat(12, 16, seed=7, weighted=False)
+    r1 = oracle.plp(g.off, g.col, g.w, max_iters=1)
+    assert r1.iterations == 1 and r1.updates[0] > 0
+    r = oracle.plp(g.off, g.col, g.w)
+    # theta = n 10^-5 < 1 here: the loop ends on an iteration without updates or at the cap
+    assert r.updates[-1] == 0 or r.iterations == 64
+    assert all(u > 0 for u in r.updates[:-1])
+    for bad in (0, 65):
+        with pytest.raises(ValueError):
+            oracle.plp(g.off, g.col, g.w, max_iters=bad)
+
+
+def test_plp_ring_of_cliques():
+    g = graphgen.ring_of_cliques(12, 6)
+    r = oracle.plp(g.off, g.col, g.w)
+    assert np.array_equal(r.labels, np.repeat(np.arange(12), 6).astype(np.int32))
+
+
+# ------------------------------------------------------------------ EPP (Algorithm 5)
+def _coarse_edges(g, pi):
+    out = {}
+    for (u, v), wt in refs.edges_of(g.off, g.col, g.w).items():
+        a, b = sorted((int(pi[u]), int(pi[v])))
+        out[(a, b)] = out.get((a, b), 0) + wt
+    return out
+
+
+@pytest.mark.parametrize("b", [1, 2, 4])
+def test_epp_core_groups_are_equation_3_2(b):
+    """Two nodes share a core group iff every base PLP solution (seeds
+    seed .. seed+b-1) gives them the same label; coarse ids ascend with the
+    smallest member."""
+    g = graphgen.planted_partition_1000(seed=3)
+    r = oracle.epp(g.off, g.col, g.w, b=b, seed=11)
+    base = [oracle.plp(g.off, g.col, g.w, seed=11 + i).labels for i in range(b)]
+    tuples = {}
+    for v in range(g.n):
+        tuples.setdefault(tuple(int(x[v]) for x in base), len(tuples))
+    expect = np.array([tuples[tuple(int(x[v]) for x in base)] for v in range(g.n)], np.int32)
+    assert np.array_equal(r.core_groups, expect)   # first-occurrence order = ascending smallest member
+    assert r.cores == len(tuples) == r.run.n[0]
+    if b == 1:
+        assert np.array_equal(r.core_groups, base[0])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_epp_equals_fraction_plmr_on_core_graph(seed):
+    """Sequential schedule: EPP's result is the exact-fraction PLMR on the
+    core-group graph (as level 1), prolonged to the input nodes."""
+    rng = np.random.default_rng(1600 + seed)
+    n = int(rng.integers(30, 120))
+    g = graphgen.random_graph(n, float(rng.uniform(0.04, 0.15)), seed=1700 + seed, weighted=seed % 2 == 0,
+                              loops=0.1)
+    r = oracle.epp(g.off, g.col, g.w, b=3, seed=seed, schedule=1)
+    zc = refs.seq_plmr(r.cores, _coarse_edges(g, r.core_groups), seed=seed, first_level=1)
+    assert np.array_equal(r.labels, _canon(zc[r.core_groups]))
+    assert r.q == pytest.approx(refs.nx_modularity(g.off, g.col, g.w, r.labels), abs=1e-12)
+
+
+def test_epp_clear_structures_and_bounds():
+    for g, q in [(graphgen.disjoint_cliques(4, 6), 0.75), (graphgen.ring_of_cliques(8, 5), None)]:
+        r = oracle.epp(g.off, g.col, g.w, b=4)
+        if q is not None:
+            assert r.q == q
+        else:
+            ref = oracle.run(g.off, g.col, g.w, refine=True)
+            assert r.q >= ref.q - 1e-12
+    g = graphgen.disjoint_cliques(2, 3)
+    for kw in [dict(b=0), dict(plp_iters=0), dict(plp_iters=65), dict(max_sweeps=0)]:
+        with pytest.raises(ValueError):
+            oracle.epp(g.off, g.col, g.w, **kw)
+    e = graphgen.from_edges(0, [])
+    assert oracle.epp(e.off, e.col, e.w).labels.shape == (0,)
+
+
+def test_epp_planted_partition_quality():
+    """On the planted partition the ensemble's cores feed PLMR a small graph:
+    no worse than PLP alone."""
+    g = graphgen.planted_partition_1000(seed=1)
+    p = oracle.plp(g.off, g.col, g.w)
+    r = oracle.epp(g.off, g.col, g.w, b=4)
+    assert r.q >= p.q and r.cores < g.n
