@@ -143,6 +143,38 @@ plm_status plm_coarsen(plm_ctx *ctx, int64_t *n_coarse_out);
  * output pointer may be NULL. */
 plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels_out);
 
+/* Label propagation, PLP (Algorithm 1), on the input graph from singleton
+ * labels.  Nodes are visited class by class in the colour classes drawn with
+ * opt.colour_seed (level 0), each class deciding against the labels at its
+ * start; a node takes the label of largest weight among its non-loop
+ * neighbours, keeps its own label when that one attains the maximum, and
+ * otherwise breaks ties by the largest key t(v, l) = upper 32 bits of
+ * SplitMix64(H(v) ^ l) (H: the node's priority hash), then the lowest label.
+ * Only active nodes are visited (Algorithm 1); iterations continue while more
+ * than n * 10^-5 labels changed, at most max_iters (in [1, 64]) times.
+ * labels[n] (mem_kind of the context's input) receives canonical labels,
+ * *q_out their modularity, *iters_out the iterations, updates_out[i] (host,
+ * max_iters entries) the labels changed in iteration i.  Outputs may be NULL.
+ * Leaves the context at level 0.  Errors: PLM_E_ARG, PLM_E_STATE (batched
+ * context), PLM_E_NOMEM, PLM_E_DEVICE. */
+plm_status plm_plp(plm_ctx *ctx, int32_t max_iters, int32_t *labels, double *q_out, int32_t *iters_out,
+                   int64_t *updates_out);
+
+/* Ensemble preprocessing EPP(b, PLP, PLMR) (Algorithm 5): ensemble_size = b
+ * (in [1, 1024]) PLP runs as in plm_plp with colour seeds colour_seed ..
+ * colour_seed + b - 1 and at most plp_iters (in [1, 64]) iterations each; the
+ * core groups of their labels (Equation (3.2): two nodes share a group iff
+ * every run gives them the same label), numbered by ascending smallest
+ * member; the input contracted by the core groups as level 1; PLMR
+ * (Algorithm 4) on it from level 1 (priorities of levels 1, 2, ...;
+ * opt.max_levels counts from level 1; level 0 is not refined) with the
+ * context's gamma; and the communities prolonged to the input nodes.
+ * labels[n] receives canonical labels, *q_out their modularity on the input,
+ * *levels_out the PLMR levels, *cores_out the number of core groups.
+ * Outputs may be NULL.  Errors as plm_plp. */
+plm_status plm_epp(plm_ctx *ctx, int32_t ensemble_size, int32_t plp_iters, int32_t *labels, double *q_out,
+                   int32_t *levels_out, int64_t *cores_out);
+
 /* Modularity, Equation (3.1), of labels[n] (values in [0, n), host or device
  * per mem_kind) on the input graph, computed as (S*I2 - sum vol(C)^2) / S^2
  * with exact 128-bit numerator and denominator converted once to double and
@@ -298,6 +330,16 @@ typedef struct {
     int64_t ref_sweeps[PLM_MAX_LEVELS];
     int64_t ref_moves[PLM_MAX_LEVELS];
     double ref_ms[PLM_MAX_LEVELS];            /* prolongation + schedule + sweeps (host clock) */
+    /* label propagation: plm_plp, and the base solutions of plm_epp */
+    int64_t lp_runs, lp_iterations;
+    int64_t lp_updates;        /* label changes over all iterations */
+    double lp_ms;              /* host clock, colouring included */
+    double lp_decide_ms;       /* with opt.timing: device time of the decide launches */
+    double lp_first_ms;        /* with opt.timing: that time in the first iteration of each run */
+    double lp_first_bytes;     /* algorithmic bytes of those first iterations (every node active) */
+    /* plm_epp: core-group combination (host clock) and the core groups */
+    double ens_ms;
+    int64_t ens_cores;
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

@@ -6,7 +6,7 @@ HIP kernels of ``libplm.so``.  There is no CPU fallback; importing the binding
 without a built library raises.
 
 Low level: ``plm_create``, ``plm_move_sweep``, ``plm_move_class``,
-``plm_coarsen``, ``plm_run``, ``plm_modularity``, ``plm_reset``,
+``plm_coarsen``, ``plm_run``, ``plm_plp``, ``plm_epp``, ``plm_modularity``, ``plm_reset``,
 ``plm_destroy``, ``plm_last_error``, ``plm_level_info``, ``plm_get_state``,
 ``plm_get_graph``, ``plm_get_stats``, ``plm_default_options`` (ctypes functions
 with the C signatures).  ``Context`` wraps them for numpy (host) and torch
@@ -66,7 +66,10 @@ class plm_stats_t(ctypes.Structure):
                 ("hub_single_ms", ctypes.c_double * _L), ("hub_single_bytes", ctypes.c_double * _L),
                 ("hub_single_nodes", ctypes.c_int64 * _L), ("hub_single_entries", ctypes.c_int64 * _L),
                 ("kernel_launches", (ctypes.c_int64 * 5) * _L), ("ref_sweeps", ctypes.c_int64 * _L),
-                ("ref_moves", ctypes.c_int64 * _L), ("ref_ms", ctypes.c_double * _L)]
+                ("ref_moves", ctypes.c_int64 * _L), ("ref_ms", ctypes.c_double * _L),
+                ("lp_runs", ctypes.c_int64), ("lp_iterations", ctypes.c_int64), ("lp_updates", ctypes.c_int64),
+                ("lp_ms", ctypes.c_double), ("lp_decide_ms", ctypes.c_double), ("lp_first_ms", ctypes.c_double),
+                ("lp_first_bytes", ctypes.c_double), ("ens_ms", ctypes.c_double), ("ens_cores", ctypes.c_int64)]
 
 
 class plm_server_info_t(ctypes.Structure):
@@ -93,6 +96,8 @@ def _load():
     lib.plm_move_class.argtypes = [vp, i32, P(i64)]
     lib.plm_coarsen.argtypes = [vp, P(i64)]
     lib.plm_run.argtypes = [vp, vp, P(dbl), P(i32)]
+    lib.plm_plp.argtypes = [vp, i32, vp, P(dbl), P(i32), P(i64)]
+    lib.plm_epp.argtypes = [vp, i32, i32, vp, P(dbl), P(i32), P(i64)]
     lib.plm_modularity.argtypes = [vp, vp, i32, P(dbl)]
     lib.plm_reset.argtypes = [vp]
     lib.plm_destroy.argtypes = [vp]
@@ -115,7 +120,7 @@ def _load():
     lib.plm_server_last_error.argtypes = [vp]
     lib.plm_server_last_error.restype = ctypes.c_char_p
     for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_server_create", "plm_server_submit",
-              "plm_server_step", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_modularity",
+              "plm_server_step", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_plp", "plm_epp", "plm_modularity",
               "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
         getattr(lib, f).restype = i32
     return lib
@@ -129,6 +134,8 @@ plm_move_sweep = _lib.plm_move_sweep
 plm_move_class = _lib.plm_move_class
 plm_coarsen = _lib.plm_coarsen
 plm_run = _lib.plm_run
+plm_plp = _lib.plm_plp
+plm_epp = _lib.plm_epp
 plm_modularity = _lib.plm_modularity
 plm_reset = _lib.plm_reset
 plm_destroy = _lib.plm_destroy
@@ -243,6 +250,25 @@ class Context:
         self._check(plm_run(self._c, _ptr(labels), ctypes.byref(q), ctypes.byref(lv)))
         return labels, q.value, lv.value
 
+    def plp(self, max_iters: int = 64, labels=None):
+        """Label propagation (Algorithm 1) on the input graph.  Returns
+        (labels, q, iterations, updates per iteration)."""
+        if labels is None and self.mem_kind == PLM_MEM_HOST:
+            labels = np.zeros(self.n, np.int32)
+        q, it = ctypes.c_double(), ctypes.c_int32()
+        upd = (ctypes.c_int64 * 64)()
+        self._check(plm_plp(self._c, max_iters, _ptr(labels), ctypes.byref(q), ctypes.byref(it), upd))
+        return labels, q.value, it.value, [int(upd[i]) for i in range(it.value)]
+
+    def epp(self, ensemble_size: int = 4, plp_iters: int = 64, labels=None):
+        """EPP(b, PLP, PLMR) (Algorithm 5).  Returns (labels, q, levels, cores)."""
+        if labels is None and self.mem_kind == PLM_MEM_HOST:
+            labels = np.zeros(self.n, np.int32)
+        q, lv, k = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(plm_epp(self._c, ensemble_size, plp_iters, _ptr(labels), ctypes.byref(q), ctypes.byref(lv),
+                            ctypes.byref(k)))
+        return labels, q.value, lv.value, k.value
+
     def modularity(self, labels, mem_kind: int | None = None) -> float:
         if mem_kind is None:
             mem_kind = PLM_MEM_HOST if isinstance(labels, np.ndarray) else PLM_MEM_DEVICE
@@ -283,8 +309,11 @@ class Context:
         L = s.levels
         out = {"levels": L}
         for f, _ in plm_stats_t._fields_[2:]:
-            v = list(getattr(s, f))[:L]
-            out[f] = [list(x) if not isinstance(x, (int, float)) else x for x in v]
+            v = getattr(s, f)
+            if isinstance(v, (int, float)):
+                out[f] = v
+                continue
+            out[f] = [list(x) if not isinstance(x, (int, float)) else x for x in list(v)[:L]]
         return out
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libplm.so")
-SOURCES = ["prims.hip", "level.hip", "colour.hip", "move.hip", "coarsen.hip", "batch.hip", "api.hip", "serve.hip"]
+SOURCES = ["prims.hip", "level.hip", "colour.hip", "move.hip", "coarsen.hip", "batch.hip", "api.hip", "serve.hip", "ensemble.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

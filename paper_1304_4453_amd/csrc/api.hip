@@ -167,13 +167,21 @@ struct plm_ctx {
     int32_t *bgmoved = nullptr;  // per graph of the level: moved in the current sweep
     unsigned long long *bI2 = nullptr, *bsq = nullptr;
 
+    // label propagation (Algorithm 1): active flag of each node; lp_mode turns
+    // the class steps into label-propagation steps with tie keys of lp_seed
+    uint8_t *active = nullptr;
+    bool lp_mode = false;
+    uint64_t lp_seed = 0;
+    // device time and algorithmic bytes of the last timed run_classes
+    double last_ms = 0, last_bytes = 0;
+
     ~plm_ctx() {
         for (auto &l : levels) l.release();
         dev_free(vol0); dev_free(vol); dev_free(volC); dev_free(zeta); dev_free(colour); dev_free(class_nodes);
         dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
-        dev_free(bsq); dev_free(bsweep); dev_free(bgmoved);
+        dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
@@ -277,11 +285,12 @@ struct plm_ctx {
         if (red_tot > cap_rhub) { dev_free(red_hub); red_hub = dev_alloc<int32_t>(red_tot); cap_rhub = red_tot; }
     }
 
-    void build_schedule() {
+    void build_schedule() { build_schedule(opt.colour_seed, opt.schedule); }
+    void build_schedule(uint64_t seed, int schedule) {
         LevelData &l = L();
         GraphView g = l.view();
         double t0 = now_ms();
-        ncol = build_colouring(g, opt.colour_seed, cur, opt.schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st);
+        ncol = build_colouring(g, seed, cur, schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st);
         if (cur < PLM_MAX_LEVELS) {
             stats.colour_ms[cur] = now_ms() - t0;
             stats.schedule_rounds[cur] = jp_rounds;
@@ -428,6 +437,17 @@ struct plm_ctx {
         ms.gp = gp();
         ms.gq = gq();
         if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; ms.gmoved = bgmoved; }
+        if (lp_mode) {
+            // scores (w(u,X) << 32) + t(u,X): S = 2^32, no vol(u) term, 64-bit
+            // while vol(u) (>= every w(u,X)) is below 2^31
+            ms.active = active;
+            ms.lp_seed = lp_seed;
+            ms.lp_level = cur;
+            ms.S = (int64_t)1 << 32;
+            ms.gp = 0;
+            ms.gq = 1;
+            ms.wide_lim = INT32_MAX;
+        }
         return ms;
     }
     HubArrays hub_arrays() {
@@ -488,24 +508,31 @@ struct plm_ctx {
             }
             // algorithmic bytes (whole sweeps only): per entry the column, the
             // weight and the community of the neighbour; per distinct candidate
-            // its community volume; per node offsets, own community, vol(u),
-            // vol(D) and the class list entry
+            // its community volume (none in label propagation); per node
+            // offsets, own community, vol(u), vol(D) and the class list entry
             int wb = L().wkind == 0 ? 0 : (L().wkind == 1 ? 4 : 8);
             bool whole = c0 == 0 && c1 == ncol;
+            const double per_cand = lp_mode ? 0.0 : 8.0;
+            last_ms = last_bytes = 0;
             for (int b = 0; b < 4; ++b) {
-                double bytes = whole ? (double)bin_entries[b] * (8.0 + wb) + 8.0 * (double)hbuf[1 + b] +
+                double bytes = whole ? (double)bin_entries[b] * (8.0 + wb) + per_cand * (double)hbuf[1 + b] +
                                            32.0 * (double)bin_nodes[b]
                                      : 0.0;
+                last_ms += bin_t[b];
+                last_bytes += bytes;
+                if (lp_mode) continue;
                 stats.bin_ms[cur][b] += bin_t[b];
                 stats.bin_bytes[cur][b] += bytes;
                 stats.decide_ms[cur] += bin_t[b];
                 stats.decide_bytes[cur] += bytes;
             }
-            stats.hub_single_ms[cur] += sgl_t;
-            if (whole)
-                stats.hub_single_bytes[cur] += (double)sgl_entries * (8.0 + wb) + 8.0 * (double)hbuf[5] +
-                                               32.0 * (double)sgl_nodes;
-            stats.decide_launches[cur] += launches;
+            if (!lp_mode) {
+                stats.hub_single_ms[cur] += sgl_t;
+                if (whole)
+                    stats.hub_single_bytes[cur] += (double)sgl_entries * (8.0 + wb) + 8.0 * (double)hbuf[5] +
+                                                   32.0 * (double)sgl_nodes;
+                stats.decide_launches[cur] += launches;
+            }
         }
         return moves;
     }
@@ -581,9 +608,19 @@ struct plm_ctx {
         stats.coarsen_ms[cur] += t_coarsen;
     }
 
-    // Algorithm 3 from level 0; leaves canonical labels in lab_out (device)
+    // Algorithm 3 (Algorithm 4 with opt.refine) from level 0; leaves canonical
+    // labels in lab_out (device)
     int32_t run(int32_t *lab_out) {
         reset();
+        return descend(lab_out, 0, opt.refine != 0);
+    }
+
+    // From the current level `floor` (with its singletons set up): move phases
+    // and coarsening until the communities stop merging (max_levels counts
+    // from floor); with refine, the move phases after prolongation back down
+    // to floor (Algorithm 4); then the communities of the input nodes through
+    // the level maps, as canonical labels in lab_out.  Returns the levels.
+    int32_t descend(int32_t *lab_out, int floor, bool refine) {
         int32_t done_levels = 0;
         for (;;) {
             double t0 = now_ms();
@@ -609,11 +646,7 @@ struct plm_ctx {
             coarsen();
             if (prev < PLM_MAX_LEVELS) stats.coarsen_ms[prev] = now_ms() - t3;
         }
-        if (opt.refine && cur > 0) {
-            refine_up();
-            if (n0 > 0) build_canonical(zeta, n0, lab_out, scr, st);
-            return done_levels;
-        }
+        if (refine && cur > floor) refine_up(floor);
         // prolong: input node -> current level node -> community
         int64_t n = n0;
         if (n > 0) {
@@ -630,12 +663,12 @@ struct plm_ctx {
     }
 
     // PLMR (Algorithm 4), on the way back up: at each level l below the
-    // deepest, u takes the community of its coarse node pi_l(u) (named by that
-    // community's id on level l + 1, which is below n_l), and a move phase
-    // (same colouring, same sweep rule) starts from there.  Leaves level 0's
-    // communities in zeta.
-    void refine_up() {
-        for (int l = cur - 1; l >= 0; --l) {
+    // deepest, down to floor, u takes the community of its coarse node pi_l(u)
+    // (named by that community's id on level l + 1, which is below n_l), and a
+    // move phase (same colouring, same sweep rule) starts from there.  Leaves
+    // level floor's communities in zeta.
+    void refine_up(int floor) {
+        for (int l = cur - 1; l >= floor; --l) {
             double t0 = now_ms();
             const int64_t nl = levels[l].n;
             if (nl > 0) {
@@ -669,6 +702,109 @@ struct plm_ctx {
                 stats.ref_ms[l] = now_ms() - t0;
             }
         }
+    }
+
+    // Label propagation (Algorithm 1) on the current level from singleton
+    // labels: colour classes (Jones-Plassmann, whatever opt.schedule says) and
+    // tie keys drawn with seed, every node with a
+    // non-loop neighbour active at the start, iterations while more than
+    // n * 10^-5 labels changed in the last one (at most max_iters).  Leaves the
+    // labels (node ids) in zeta; upd (host, may be null) receives the changes
+    // per iteration.  Returns the iterations.
+    int32_t plp_level(uint64_t seed, int32_t max_iters, int64_t *upd) {
+        LevelData &l = L();
+        double t0 = now_ms();
+        if (!active) active = dev_alloc<uint8_t>(n0 > 0 ? n0 : 1);
+        launch_iota(zeta, l.n, st);
+        // nodes without non-loop neighbours are outside the class buckets, so
+        // marking every node active is the same as marking those with one
+        if (l.n > 0) HIPCHK(hipMemsetAsync(active, 1, l.n, st));
+        build_schedule(seed, PLM_SCHEDULE_COLOUR);  // label propagation always runs on colour classes
+        lp_mode = true;
+        lp_seed = seed;
+        int64_t updated = l.n;
+        int32_t it = 0;
+        try {
+            while (updated * 100000 > l.n && it < max_iters) {
+                updated = run_classes(0, ncol);
+                if (upd) upd[it] = updated;
+                if (opt.timing) {
+                    stats.lp_decide_ms += last_ms;
+                    if (it == 0) {
+                        stats.lp_first_ms += last_ms;
+                        stats.lp_first_bytes += last_bytes;
+                    }
+                }
+                stats.lp_updates += updated;
+                ++it;
+            }
+        } catch (...) {
+            lp_mode = false;
+            throw;
+        }
+        lp_mode = false;
+        sched = false;  // the move phase draws its own classes
+        stats.lp_runs += 1;
+        stats.lp_iterations += it;
+        stats.lp_ms += now_ms() - t0;
+        return it;
+    }
+
+    // EPP(b, PLP, PLMR) (Algorithm 5): b label-propagation runs with seeds
+    // colour_seed .. colour_seed + b - 1 on the input graph, their core groups
+    // (Equation (3.2), named by their smallest member), the graph contracted
+    // by the core groups as level 1, PLMR from there (max_levels counted from
+    // level 1; level 0 is not refined), and the communities prolonged to the
+    // input nodes (canonical labels in lab_out).  Returns the PLMR levels.
+    int32_t epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *cores_out) {
+        reset();
+        const int64_t n = n0;
+        *cores_out = 0;
+        if (n == 0) return 1;
+        EnsembleWork wk;
+        int32_t *grp = nullptr;
+        auto release = [&]() {
+            dev_free(wk.keys); dev_free(wk.keys_alt); dev_free(wk.vals); dev_free(wk.vals_alt); dev_free(wk.first);
+            dev_free(grp);
+            if (wk.scratch) (void)hipFree(wk.scratch);
+            wk.scratch = nullptr;
+        };
+        double t_ens = 0;
+        int64_t k = 0;
+        try {
+            wk.keys = dev_alloc<uint64_t>(n); wk.keys_alt = dev_alloc<uint64_t>(n);
+            wk.vals = dev_alloc<int32_t>(n); wk.vals_alt = dev_alloc<int32_t>(n); wk.first = dev_alloc<int32_t>(n);
+            wk.scratch = (void *)dev_alloc<uint8_t>((int64_t)ensemble_scratch_bytes(n));
+            grp = dev_alloc<int32_t>(n);
+            for (int32_t i = 0; i < b; ++i) {
+                plp_level(opt.colour_seed + (uint64_t)i, plp_iters, nullptr);
+                double t1 = now_ms();
+                ensemble_refine(grp, zeta, n, i == 0, wk, st);
+                HIPCHK(hipStreamSynchronize(st));
+                t_ens += now_ms() - t1;
+            }
+            double t1 = now_ms();
+            HIPCHK(hipMemcpyAsync(zeta, grp, n * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            release();
+            const int32_t ncol0 = ncol;
+            const int64_t loops0 = loops;
+            k = coarsen();
+            stats.levels = 1;
+            stats.n[0] = n;
+            stats.nnz[0] = levels[0].nnz;
+            stats.loops[0] = loops0;
+            stats.colours[0] = ncol0;
+            stats.communities[0] = k;
+            stats.coarsen_ms[0] = now_ms() - t1;
+            stats.ens_ms = t_ens;
+            stats.ens_cores = k;
+        } catch (...) {
+            release();
+            throw;
+        }
+        *cores_out = k;
+        return descend(lab_out, 1, true);
     }
 
     double modularity_of(const int32_t *labels_dev) {
@@ -1138,6 +1274,60 @@ plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels
             HIPCHK(hipStreamSynchronize(ctx->st));
             if (q_out) *q_out = q;
             if (levels_out) *levels_out = lv;
+        } catch (...) {
+            dev_free(canon);
+            throw;
+        }
+        dev_free(canon);
+    });
+}
+
+plm_status plm_plp(plm_ctx *ctx, int32_t max_iters, int32_t *labels, double *q_out, int32_t *iters_out,
+                   int64_t *updates_out) {
+    return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_plp");
+        if (max_iters < 1 || max_iters > 64) throw Error{PLM_E_ARG, "max_iters must lie in [1, 64]"};
+        int64_t n = ctx->n0;
+        int32_t *canon = dev_alloc<int32_t>(n);
+        try {
+            ctx->reset();
+            int64_t upd[64];
+            int32_t it = ctx->plp_level(ctx->opt.colour_seed, max_iters, upd);
+            if (n > 0) build_canonical(ctx->zeta, n, canon, ctx->scr, ctx->st);
+            double q = 0.0;
+            if (q_out) q = ctx->modularity_of(canon);
+            if (labels) copy_out(labels, canon, (size_t)n * 4, ctx->mem_kind, ctx->st);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            if (q_out) *q_out = q;
+            if (iters_out) *iters_out = it;
+            if (updates_out)
+                for (int32_t i = 0; i < it; ++i) updates_out[i] = upd[i];
+        } catch (...) {
+            dev_free(canon);
+            throw;
+        }
+        dev_free(canon);
+    });
+}
+
+plm_status plm_epp(plm_ctx *ctx, int32_t ensemble_size, int32_t plp_iters, int32_t *labels, double *q_out,
+                   int32_t *levels_out, int64_t *cores_out) {
+    return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_epp");
+        if (ensemble_size < 1 || ensemble_size > 1024) throw Error{PLM_E_ARG, "ensemble_size must lie in [1, 1024]"};
+        if (plp_iters < 1 || plp_iters > 64) throw Error{PLM_E_ARG, "plp_iters must lie in [1, 64]"};
+        int64_t n = ctx->n0;
+        int32_t *canon = dev_alloc<int32_t>(n);
+        try {
+            int64_t cores = 0;
+            int32_t lv = ctx->epp(ensemble_size, plp_iters, canon, &cores);
+            double q = 0.0;
+            if (q_out) q = ctx->modularity_of(canon);
+            if (labels) copy_out(labels, canon, (size_t)n * 4, ctx->mem_kind, ctx->st);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            if (q_out) *q_out = q;
+            if (levels_out) *levels_out = lv;
+            if (cores_out) *cores_out = cores;
         } catch (...) {
             dev_free(canon);
             throw;

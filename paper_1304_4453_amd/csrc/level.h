@@ -42,6 +42,11 @@ struct MoveState {
     int32_t *gmoved = nullptr;  // set to 1 for the graph of every node that moves
     // resolution gamma = gp / gq: S is scaled by gq, vol(u) multipliers by gp
     int64_t gp = 1, gq = 1;
+    // label propagation (Algorithm 1), set for the label-propagation kernels
+    // only: active flag of each node, and seed and level of the tie keys
+    uint8_t *active = nullptr;
+    uint64_t lp_seed = 0;
+    int32_t lp_level = 0;
 };
 
 __device__ __forceinline__ int64_t node_S(const MoveState &ms, int32_t u) { return ms.gid ? ms.gS[ms.gid[u]] : ms.S; }
@@ -90,6 +95,8 @@ constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol
 // ev (may be null): per kernel group (lane, wavefront, workgroup, one-workgroup
 // hub, partitioned hub) a start and a stop event, taken by the group's first
 // and last dispatch, for the groups whose bit is set in ev_mask and that launch
+// ms.active non-null: the label-propagation variant (ms.S = 2^32, ms.gp = 0,
+// ms.gq = 1, ms.wide_lim = INT32_MAX)
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                        bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st);
 void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
@@ -125,6 +132,22 @@ int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *la
 int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t *host_i64, hipStream_t st);
 // validation of an input CSR; returns 0 or an error code bit set
 uint32_t validate_graph(const GraphView &g, Scratch &scr, int64_t *host_i64, hipStream_t st);
+
+// ---- ensemble.hip
+// Work arrays of ensemble_refine for n nodes (device): keys and keys_alt
+// uint64[n], vals, vals_alt and first int32[n], ensemble_scratch_bytes(n) of
+// scratch.
+struct EnsembleWork {
+    uint64_t *keys = nullptr, *keys_alt = nullptr;
+    int32_t *vals = nullptr, *vals_alt = nullptr, *first = nullptr;
+    void *scratch = nullptr;
+};
+size_t ensemble_scratch_bytes(int64_t n);
+// Refines the core groups grp[n] (each node's group named by its smallest
+// member) by the labels lab[n] (ids in [0, n)) of one more base solution;
+// first_solution: grp is not read, the groups become those of lab.
+void ensemble_refine(int32_t *grp, const int32_t *lab, int64_t n, bool first_solution, EnsembleWork &wk,
+                     hipStream_t st);
 
 // ---- batch.hip
 void launch_gather_i64(const int64_t *a, const int64_t *idx, int64_t count, int64_t *out, hipStream_t st);

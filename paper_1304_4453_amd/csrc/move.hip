@@ -20,6 +20,17 @@
 // through hash-partitioned staging.  The LDS tables sum weights in 32 bits:
 // the bucketing sends a node whose vol(u) (an upper bound of every w(u, X))
 // does not fit to the partitioned hub path, whose sums are 64-bit.
+//
+// The same kernels (template flag LP) run label propagation (Algorithm 1):
+// with S = 2^32, a zero vol(u) multiplier and K raised by 2^32 - 1, a label X
+// scores (w(u,X) << 32) + t(u,X) against K = (w(u,D) << 32) + 2^32 - 1, so the
+// best label has the largest weight, then the largest tie key t, then the
+// lowest id, and u keeps its label iff that label's weight is the maximum.
+// No community volumes are read.  w(u,X) <= vol(u) < 2^31 keeps the scores in
+// 64 bits (wide_lim = 2^31 - 1 sends larger nodes to the 128-bit path).  Only
+// active nodes are decided; a node that keeps its label turns inactive and a
+// node that takes a new one activates its neighbours (neighbours are never in
+// the same class, so this cannot disturb the class's own decisions).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -71,6 +82,22 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
     return v;
 }
 
+// tie key of label x for the node with priority hash hv: upper half of
+// SplitMix64(hv ^ x), so that each node breaks ties in its own random order
+__device__ __forceinline__ uint32_t lp_tie(uint64_t hv, int32_t x) {
+    return (uint32_t)(splitmix64(hv ^ (uint64_t)(uint32_t)x) >> 32);
+}
+constexpr uint32_t kLpTieMax = 0xFFFFFFFFu;
+
+// label propagation: u moved, so its non-loop neighbours become active
+__device__ __forceinline__ void lp_activate(const GraphView &g, uint8_t *active, int32_t u, int64_t e0, int64_t e1,
+                                            int64_t first, int64_t step) {
+    for (int64_t e = e0 + first; e < e1; e += step) {
+        int32_t v = g.col[e];
+        if (v != u) active[v] = 1;
+    }
+}
+
 __device__ __forceinline__ void count_candidates(unsigned long long *cand, int64_t c) {
     if (!cand) return;
     c = wave_sum(c);
@@ -80,9 +107,9 @@ __device__ __forceinline__ void count_candidates(unsigned long long *cand, int64
 // ------------------------------------------------------------------ lane per node
 constexpr int kLaneMax = 16;
 
-template <int WK, typename G>
+template <int WK, bool LP, typename G>
 __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const int64_t (&W)[kLaneMax], int32_t D,
-                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC) {
+                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC, uint64_t hv) {
     G bg = 0;
     int32_t bx = kNone;
     const G vb = (G)vu * (G)base;
@@ -91,21 +118,32 @@ __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const
         // vol(X) >= 0 bounds the gain by S (w(u,X) - w(u,D\u)) + vol(u) vol(D\u):
         // a candidate that cannot reach a positive gain is not gathered
         if (X[j] >= 0 && X[j] != D && (G)S * (G)(W[j] - wD) + vb > 0) {
-            G g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
+            G g;
+            if constexpr (LP)
+                g = (G)S * (G)(W[j] - wD) + (G)lp_tie(hv, X[j]) - (G)kLpTieMax;
+            else
+                g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
             if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
         }
     }
     return bx;
 }
 
-template <int WK>
+template <int WK, bool LP>
 __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, int64_t begin, int64_t count,
                                                      int force_wide) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t ncand = 0;
+    int32_t u = 0;
+    if (i < count) {
+        u = ms.class_nodes[(int64_t)begin + i];
+        if (LP && !ms.active[u]) {
+            ms.move_to[begin + i] = -1;
+            i = count;  // inactive: nothing to decide
+        }
+    }
     if (i < count) {
         int64_t pos = begin + i;
-        int32_t u = ms.class_nodes[pos];
         int64_t e0 = g.off[u];
         int64_t d = g.off[u + 1] - e0;
         int32_t X[kLaneMax];
@@ -136,12 +174,17 @@ __global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, 
             ncand += (X[j] >= 0 && X[j] != D);
         }
         int64_t vu = ms.vol[u];
-        int64_t base = ms.volC[D] - vu;
+        int64_t base = LP ? 0 : ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
+        const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         int32_t bx = (force_wide || vu > node_wl(ms, u))
-                         ? lane_pick<WK, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC)
-                         : lane_pick<WK, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC);
+                         ? lane_pick<WK, LP, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, hv)
+                         : lane_pick<WK, LP, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, hv);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
+        if (LP) {
+            if (bx == kNone) ms.active[u] = 0;
+            else lp_activate(g, ms.active, u, e0, e0 + d, 0, 1);
+        }
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 0 : nullptr, ncand);
 }
@@ -161,10 +204,10 @@ constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 // and whether it beats K, are exactly those of a full scan.
 constexpr int kEvalBatch = 8;
 
-template <typename G, typename V>
+template <typename G, typename V, bool LP>
 __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, G vu, G S, G K,
                                            const int64_t *volC, bool clear, G &bs, int32_t &bx,
-                                           int64_t &ncand) {
+                                           int64_t &ncand, uint64_t hv) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
         int64_t a[kEvalBatch], vc[kEvalBatch];
@@ -181,25 +224,26 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
             c[j] = X[j] >= 0 && (G)S * (G)a[j] > K;
         }
 #pragma unroll
-        for (int j = 0; j < kEvalBatch; ++j) vc[j] = c[j] ? volC[X[j]] : 0;
+        for (int j = 0; j < kEvalBatch; ++j) vc[j] = (!LP && c[j]) ? volC[X[j]] : 0;
 #pragma unroll
         for (int j = 0; j < kEvalBatch; ++j) {
             ncand += X[j] >= 0;
             if (!c[j]) continue;
             G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
+            if constexpr (LP) sc += (G)lp_tie(hv, X[j]);
             if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
         }
     }
 }
 
-template <typename G>
+template <typename G, bool LP>
 __device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
                                           const int64_t *volC, int32_t &best_x, bool &move,
-                                          int64_t &ncand) {
+                                          int64_t &ncand, uint64_t hv) {
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    const G K = (G)S * (G)wD - (G)vu * (G)base;
-    eval_slots<G, int32_t>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ncand);
+    const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ncand, hv);
     wave_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
@@ -252,7 +296,7 @@ __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *z
     return myD;
 }
 
-template <int WK>
+template <int WK, bool LP>
 __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, int64_t begin, int64_t count,
                                                      int force_wide) {
     __shared__ int32_t tk[4][kWaveCap];
@@ -264,6 +308,10 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
     for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < count; i += (int64_t)gridDim.x * 4) {
         int64_t pos = begin + i;
         int32_t u = ms.class_nodes[pos];
+        if (LP && !ms.active[u]) {  // wave-uniform
+            if (lane == 0) ms.move_to[pos] = -1;
+            continue;
+        }
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
@@ -272,16 +320,22 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         wD = wave_sum(wD);
         wave_sync();
         int64_t vu = ms.vol[u];
-        int64_t base = ms.volC[D] - vu;
+        int64_t base = LP ? 0 : ms.volC[D] - vu;
         int32_t bx;
         bool mv;
         const int64_t S_u = node_S(ms, u);
+        const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         if (force_wide || vu > node_wl(ms, u))
-            wave_eval<i128>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, bx, mv,
-                            ncand);
+            wave_eval<i128, LP>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, bx,
+                                mv, ncand, hv);
         else
-            wave_eval<int64_t>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv, ncand);
+            wave_eval<int64_t, LP>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv, ncand,
+                                   hv);
         if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
+        if (LP) {
+            if (mv) lp_activate(g, ms.active, u, e0, e1, lane, kWave);
+            else if (lane == 0) ms.active[u] = 0;
+        }
         wave_sync();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
@@ -291,9 +345,10 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
 constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
 
-template <typename G, int NT>
+// leaves the decision (community or -1) in *out (LDS), written by thread 0
+template <typename G, int NT, bool LP>
 __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
-                                           const int64_t *volC, int32_t *out, int64_t &ncand) {
+                                           const int64_t *volC, int32_t *out, int64_t &ncand, uint64_t hv) {
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
     __shared__ int32_t red_x[NT / kWave];
@@ -305,10 +360,10 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     __syncthreads();
     wD = 0;
     for (int j = 0; j < NT / kWave; ++j) wD += red_w[j];
-    const G K = (G)S * (G)wD - (G)vu * (G)base;
+    const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
     G bs = neg_inf<G>();
     int32_t bx = kNone;
-    eval_slots<G, int32_t>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ncand);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ncand, hv);
     wave_argmax<G>(bs, bx);
     if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; }
     __syncthreads();
@@ -320,17 +375,22 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
 }
 
 // (two workgroups per CU: 64 KB of LDS each, at most 128 VGPRs)
-template <int WK>
+template <int WK, bool LP>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_block(GraphView g, MoveState ms, int64_t begin,
                                                                 int64_t count, int force_wide) {
     __shared__ int32_t tk[kBlockCap];
     __shared__ int32_t tv[kBlockCap];
+    __shared__ int32_t dec;
     for (int s = threadIdx.x; s < kBlockCap; s += kBlockThreads) { tk[s] = kEmpty; tv[s] = 0; }
     __syncthreads();
     int64_t ncand = 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         int64_t pos = begin + i;
         int32_t u = ms.class_nodes[pos];
+        if (LP && !ms.active[u]) {  // workgroup-uniform
+            if (threadIdx.x == 0) ms.move_to[pos] = -1;
+            continue;
+        }
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
@@ -338,15 +398,22 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4
         int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
-        int64_t base = ms.volC[D] - vu;
+        int64_t base = LP ? 0 : ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
+        const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         if (force_wide || vu > node_wl(ms, u))
-            block_eval<i128, kBlockThreads>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
-                                            ms.volC, &ms.move_to[pos], ncand);
+            block_eval<i128, kBlockThreads, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
+                                                ms.volC, &dec, ncand, hv);
         else
-            block_eval<int64_t, kBlockThreads>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                               &ms.move_to[pos], ncand);
+            block_eval<int64_t, kBlockThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
+                                                   &dec, ncand, hv);
         __syncthreads();
+        const int32_t x = dec;
+        if (threadIdx.x == 0) ms.move_to[pos] = x;
+        if (LP) {
+            if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, kBlockThreads);
+            else if (threadIdx.x == 0) ms.active[u] = 0;
+        }
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
 }
@@ -355,14 +422,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4
 constexpr int kSingleThreads = 1024;
 constexpr int kSingleBits = 14;  // 16384 slots of int32 key + int32 sum: 128 KB of LDS
 
-template <int WK>
+template <int WK, bool LP>
 __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, MoveState ms, HubArrays ha, int64_t blk0,
                                                                int force_wide) {
     __shared__ int32_t tk[1 << kSingleBits];
     __shared__ int32_t tv[1 << kSingleBits];
+    __shared__ int32_t dec;
     const int64_t hg = ha.sgl_hub[blk0 + blockIdx.x];
     const int32_t u = ha.hub_u[hg];
     const int64_t pos = ha.hub_pos[hg];
+    if (LP && !ms.active[u]) {
+        if (threadIdx.x == 0) ms.move_to[pos] = -1;
+        return;
+    }
     const int64_t e0 = g.off[u], e1 = g.off[u + 1];
     // rows of at most kSingleMaxRow entries: load factor <= 0.75
     int bits = ceil_log2_dev(2 * (e1 - e0));
@@ -373,15 +445,23 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kSingleThreads, tk, tv, bits);
     __syncthreads();
     const int64_t vu = ms.vol[u];
-    const int64_t base = ms.volC[D] - vu;
+    const int64_t base = LP ? 0 : ms.volC[D] - vu;
     const int64_t S_u = node_S(ms, u);
+    const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
     int64_t ncand = 0;
     if (force_wide || vu > node_wl(ms, u))
-        block_eval<i128, kSingleThreads>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC,
-                                         &ms.move_to[pos], ncand);
+        block_eval<i128, kSingleThreads, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
+                                             ms.volC, &dec, ncand, hv);
     else
-        block_eval<int64_t, kSingleThreads>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                            &ms.move_to[pos], ncand);
+        block_eval<int64_t, kSingleThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
+                                                &dec, ncand, hv);
+    __syncthreads();
+    const int32_t x = dec;
+    if (threadIdx.x == 0) ms.move_to[pos] = x;
+    if (LP) {
+        if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, kSingleThreads);
+        else if (threadIdx.x == 0) ms.active[u] = 0;
+    }
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
     count_candidates(ms.cand_sgl, ncand);
 }
@@ -415,7 +495,7 @@ __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
 
-template <int WK>
+template <int WK, bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t blk0) {
     __shared__ int32_t start[1 << kHubMaxPBits];
     __shared__ int32_t fill[1 << kHubMaxPBits];
@@ -423,6 +503,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     const int64_t hg = ha.ins_hub[blk0 + blockIdx.x];
     const int64_t k = blockIdx.x - ha.ins_first[hg];
     const int32_t u = ha.hub_u[hg];
+    if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
     const int32_t D = ms.zeta[u];
     const int64_t e0 = g.off[u], e1 = g.off[u + 1];
     const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
@@ -522,11 +603,11 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
 // at a time: an LDS prefix sum over the chunks' segment lengths turns the
 // bucket into one flat index space that every thread strides over (a binary
 // search finds the chunk of an index).
-template <typename G>
+template <typename G, bool LP>
 __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, G vu, G S, G K,
                                            const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
                                            int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
-                                           int32_t &bx, int64_t &ncand) {
+                                           int32_t &bx, int64_t &ncand, uint64_t hv) {
     const int32_t nch = ha.nchunk[hg];
     const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
     const int32_t *sx = ha.stg_x + ha.stg_off[hg];
@@ -618,7 +699,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                 __syncthreads();
                 break;
             }
-            eval_slots<G, int64_t>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx, pc);
+            eval_slots<G, int64_t, LP>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx,
+                                       pc, hv);
             __syncthreads();
         }
         if (ok) {
@@ -630,6 +712,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     }
 }
 
+template <bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays ha, int64_t blk0, int force_wide) {
     __shared__ int32_t tk[kAggSlots];
     __shared__ int64_t tv[kAggSlots];
@@ -639,6 +722,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     const int64_t hg = ha.agg_hub[blk0 + blockIdx.x];
     const int64_t p = blockIdx.x - ha.agg_first[hg];
     const int32_t u = ha.hub_u[hg];
+    if (LP && !ms.active[u]) return;
     const int64_t vu = ms.vol[u];
     // w(u, D \ u) from the chunk shares (written by the chunk launch) and the
     // score of staying, which bounds the slots worth a volume gather
@@ -650,23 +734,24 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     wD = 0;
     for (int i = 0; i < kHubThreads / kWave; ++i) wD += wred[i];
     const int32_t D = ms.zeta[u];
-    const int64_t base = ms.volC[D] - vu;
+    const int64_t base = LP ? 0 : ms.volC[D] - vu;
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
     const int64_t S_u = node_S(ms, u);
+    const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
     if (force_wide || vu > node_wl(ms, u)) {
         const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
-        const i128 K = Sg * (i128)wD - vg * (i128)base;
-        agg_bucket<i128>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
-                         ncand);
+        const i128 K = Sg * (i128)wD - vg * (i128)base + (LP ? (i128)kLpTieMax : (i128)0);
+        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
+                             ncand, hv);
         block_argmax<i128>(bs, bx);
     } else {
         const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
-        const int64_t K = Sg * wD - vg * base;
+        const int64_t K = Sg * wD - vg * base + (LP ? (int64_t)kLpTieMax : 0);
         int64_t b64 = neg_inf<int64_t>();
-        agg_bucket<int64_t>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
-                            ncand);
+        agg_bucket<int64_t, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
+                                ncand, hv);
         block_argmax<int64_t>(b64, bx);
         bs = (i128)b64;
     }
@@ -681,9 +766,15 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
 
 // One workgroup per hub of the class combines the bucket partials and the
 // w(u, D) shares (written by earlier launches) and decides the move.
-__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArrays ha, int64_t blk0) {
+template <bool LP>
+__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(GraphView g, MoveState ms, HubArrays ha, int64_t blk0) {
     __shared__ int64_t wsum[kHubThreads / kWave];
+    __shared__ int32_t dec;
     const int64_t hg = ha.red_hub[blk0 + blockIdx.x];
+    if (LP && !ms.active[ha.hub_u[hg]]) {
+        if (threadIdx.x == 0) ms.move_to[ha.hub_pos[hg]] = -1;
+        return;
+    }
     const int64_t nagg = (int64_t)1 << ha.pbits[hg];
     const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
     i128 bs = neg_inf<i128>();
@@ -705,9 +796,17 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(MoveState ms, HubArr
         int32_t u = ha.hub_u[hg];
         int32_t D = ms.zeta[u];
         int64_t vu = ms.vol[u];
-        int64_t base = ms.volC[D] - vu;
-        i128 K = (i128)node_S(ms, u) * ms.gq * (i128)wD - (i128)vu * ms.gp * (i128)base;
-        ms.move_to[pos] = (bx != kNone && bs > K) ? bx : -1;
+        int64_t base = LP ? 0 : ms.volC[D] - vu;
+        i128 K = (i128)node_S(ms, u) * ms.gq * (i128)wD - (i128)vu * ms.gp * (i128)base +
+                 (LP ? (i128)kLpTieMax : (i128)0);
+        dec = (bx != kNone && bs > K) ? bx : -1;
+        ms.move_to[pos] = dec;
+    }
+    if (LP) {
+        __syncthreads();
+        const int32_t u = ha.hub_u[hg];
+        if (dec >= 0) lp_activate(g, ms.active, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads);
+        else if (threadIdx.x == 0) ms.active[u] = 0;
     }
 }
 
@@ -723,8 +822,10 @@ __global__ __launch_bounds__(256) void k_apply(MoveState ms, int64_t begin, int6
             int32_t D = ms.zeta[u];
             int64_t vu = ms.vol[u];
             ms.zeta[u] = X;
-            atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
-            atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+            if (!ms.active) {  // label propagation keeps no community volumes
+                atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
+                atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+            }
             if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
             moved = 1;
         }
@@ -745,45 +846,55 @@ __global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, const int
 }
 
 // ------------------------------------------------------------------ launchers
-template <int WK>
+template <int WK, bool LP>
 static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                           int fw, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
     // start / stop events of kernel group i (taken by the dispatch itself)
     auto t0 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i] : (hipEvent_t) nullptr; };
     auto t1 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i + 1] : (hipEvent_t) nullptr; };
     if (cr.count[0] > 0)
-        hipExtLaunchKernelGGL(k_decide_lane<WK>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, t0(0),
+        hipExtLaunchKernelGGL(k_decide_lane<WK, LP>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, t0(0),
                               t1(0), 0, g, ms, cr.begin[0], cr.count[0], fw);
     if (cr.count[1] > 0) {
         int64_t blocks = cdiv(cr.count[1], 4);
-        hipExtLaunchKernelGGL(k_decide_wave<WK>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st,
+        hipExtLaunchKernelGGL(k_decide_wave<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st,
                               t0(1), t1(1), 0, g, ms, cr.begin[1], cr.count[1], fw);
     }
     if (cr.count[2] > 0) {
         int64_t blocks = cr.count[2];
-        hipExtLaunchKernelGGL(k_decide_block<WK>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
+        hipExtLaunchKernelGGL(k_decide_block<WK, LP>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
                               dim3(kBlockThreads), 0, st, t0(2), t1(2), 0, g, ms, cr.begin[2], cr.count[2], fw);
     }
     if (cr.sgl_count > 0)
-        hipExtLaunchKernelGGL(k_hub_single<WK>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, t0(3),
+        hipExtLaunchKernelGGL(k_hub_single<WK, LP>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, t0(3),
                               t1(3), 0, g, ms, ha, cr.sgl_base, fw);
     if (cr.red_count > 0) {
-        hipExtLaunchKernelGGL(k_hub_part<WK>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, t0(4),
+        hipExtLaunchKernelGGL(k_hub_part<WK, LP>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, t0(4),
                               (hipEvent_t) nullptr, 0, g, ms, ha, cr.ins_base);
-        hipLaunchKernelGGL(k_hub_agg, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha, cr.agg_base,
-                           fw);
-        hipExtLaunchKernelGGL(k_hub_reduce, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st,
-                              (hipEvent_t) nullptr, t1(4), 0, ms, ha, cr.red_base);
+        hipLaunchKernelGGL(k_hub_agg<LP>, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha,
+                           cr.agg_base, fw);
+        hipExtLaunchKernelGGL(k_hub_reduce<LP>, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st,
+                              (hipEvent_t) nullptr, t1(4), 0, g, ms, ha, cr.red_base);
     }
 }
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
                        bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
     int fw = force_wide ? 1 : 0;
+    const bool lp = ms.active != nullptr;
     switch (g.wkind) {
-        case 0: class_step_wk<0>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
-        case 1: class_step_wk<1>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
-        default: class_step_wk<2>(g, ms, cr, ha, fw, ev, ev_mask, st); break;
+        case 0:
+            if (lp) class_step_wk<0, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            else class_step_wk<0, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            break;
+        case 1:
+            if (lp) class_step_wk<1, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            else class_step_wk<1, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            break;
+        default:
+            if (lp) class_step_wk<2, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            else class_step_wk<2, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            break;
     }
     HIPCHK(hipGetLastError());
 }
