@@ -8,6 +8,8 @@ already resident in HBM.  Prints ONE JSON line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat26|rmat20|pp1000] [--no-batch]
 
 The line also carries "plmr": one PLMR run (Algorithm 4) on the same graph;
+"plp": label propagation (Algorithm 1) on the same graph, with the roofline of
+its first iteration; "epp": EPP(4, PLP, PLMR) (Algorithm 5) on the same graph;
 "gamma": R-MAT 20 runs at resolutions 1/2, 1 and 2;
 "batched": the batched engine (plm_batch_run) on 4,096
 uneven SBM graphs against a per-graph plm_run loop on the same GPU; and
@@ -365,6 +367,58 @@ def plmr_bench(gr, P, torch, q_plm, st_plm):
             "refinement_ms": sum(st["ref_ms"]), "ref_sweeps": st["ref_sweeps"], "ref_moves": st["ref_moves"]}
 
 
+def plp_bench(gr, P, torch):
+    """Label propagation (Algorithm 1) on the same resident graph: one run with
+    every decide dispatch event-timed (it gives the first iteration's
+    roofline: every node is active there, so its algorithmic bytes are the
+    whole graph's: per entry column, weight and neighbour label, per node 32
+    bytes, no community volumes) and one timed run without events."""
+    mk = lambda **kw: P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"],
+                                validate=0, **kw)
+    lab = torch.empty(max(gr["n"], 1), dtype=torch.int32, device="cuda:0")
+    ctx = mk(timing=1)
+    ctx.plp(64, lab)
+    st = ctx.stats()
+    ctx.close()
+    first_gbs = st["lp_first_bytes"] / (st["lp_first_ms"] * 1e6) if st["lp_first_ms"] else 0.0
+    ctx = mk(timing=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, q, it, upd = ctx.plp(64, lab)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    st2 = ctx.stats()
+    ctx.close()
+    m0 = gr["m"]
+    log(f"plp {dt:.2f}s iterations={it} q={q}")
+    return {"ms_per_run": dt * 1e3, "edges_per_s": m0 / dt, "iterations": it, "updates": upd, "q": q,
+            "colouring_and_iterations_ms_host": st2["lp_ms"],
+            "first_iteration": {"bound": "hbm", "achieved": first_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": first_gbs / HBM_PEAK_GBS, "decide_ms": st["lp_first_ms"],
+                                "algorithmic_bytes": st["lp_first_bytes"],
+                                "timing": "HIP events on every decide dispatch of the instrumented run"},
+            "paper_context": "PLP >53M edges/s (uk-2007-05, 3.3e9 edges, 2x Xeon E5-2680, 32 threads)"}
+
+
+def epp_bench(gr, P, torch, q_plm):
+    """EPP(4, PLP, PLMR) (Algorithm 5) on the same resident graph: one timed run
+    (the kernels are warm from the label-propagation runs before it)."""
+    ctx = P.Context(gr["off"], gr["col"], gr["w"], mem_kind=P.PLM_MEM_DEVICE, n=gr["n"], nnz=gr["nnz"], validate=0)
+    lab = torch.empty(max(gr["n"], 1), dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, q, lv, cores = ctx.epp(4, 64, lab)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    st = ctx.stats()
+    ctx.close()
+    log(f"epp {dt:.2f}s cores={cores} q={q}")
+    return {"ensemble_size": 4, "ms_per_run": dt * 1e3, "edges_per_s": gr["m"] / dt, "q": q, "q_plm": q_plm,
+            "core_groups": cores, "plmr_levels": lv, "plp_iterations": st["lp_iterations"],
+            "plp_ms_host": st["lp_ms"], "core_group_ms_host": st["ens_ms"],
+            "paper_context": "EPP(4,PLP,PLMR) about 219 s on uk-2007-05 (2x Xeon E5-2680, 32 threads)"}
+
+
 def gamma_bench(P, torch):
     """Resolution gamma on R-MAT 20 (unit weights, seed 2) resident in HBM: one
     warm-up and one timed full run per gamma; time, Q and communities."""
@@ -431,6 +485,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-plmr", action="store_true")
     ap.add_argument("--no-gamma", action="store_true")
+    ap.add_argument("--no-plp", action="store_true")
+    ap.add_argument("--no-epp", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served workload")
     ap.add_argument("--plain-serve-sample", type=int, default=40)
     ap.add_argument("--sweep-probe", action="store_true",
@@ -527,6 +583,10 @@ def main():
     ctx.close()
     if not args.no_plmr:
         out["plmr"] = plmr_bench(gr, P, torch, q, st)
+    if not args.no_plp:
+        out["plp"] = plp_bench(gr, P, torch)
+    if not args.no_epp:
+        out["epp"] = epp_bench(gr, P, torch, q)
     if not args.no_gamma:
         out["gamma"] = gamma_bench(P, torch)
     if gr["dg"] is not None:
