@@ -340,6 +340,13 @@ typedef struct {
     /* plm_epp: core-group combination (host clock) and the core groups */
     double ens_ms;
     int64_t ens_cores;
+    /* sweeps counted in sweeps[] (ref_sweeps[]) but not executed: the state
+     * after a sweep equalled the state two sweeps before, so every later sweep
+     * up to max_sweeps alternates between the last two states, and the level
+     * ends in the state its last sweep would leave (the result and the move
+     * counts are those of running them) */
+    int64_t cycle_sweeps[PLM_MAX_LEVELS];
+    int64_t ref_cycle_sweeps[PLM_MAX_LEVELS];
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

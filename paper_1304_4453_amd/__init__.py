@@ -69,7 +69,8 @@ class plm_stats_t(ctypes.Structure):
                 ("ref_moves", ctypes.c_int64 * _L), ("ref_ms", ctypes.c_double * _L),
                 ("lp_runs", ctypes.c_int64), ("lp_iterations", ctypes.c_int64), ("lp_updates", ctypes.c_int64),
                 ("lp_ms", ctypes.c_double), ("lp_decide_ms", ctypes.c_double), ("lp_first_ms", ctypes.c_double),
-                ("lp_first_bytes", ctypes.c_double), ("ens_ms", ctypes.c_double), ("ens_cores", ctypes.c_int64)]
+                ("lp_first_bytes", ctypes.c_double), ("ens_ms", ctypes.c_double), ("ens_cores", ctypes.c_int64),
+                ("cycle_sweeps", ctypes.c_int64 * _L), ("ref_cycle_sweeps", ctypes.c_int64 * _L)]
 
 
 class plm_server_info_t(ctypes.Structure):

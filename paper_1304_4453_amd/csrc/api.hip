@@ -174,6 +174,8 @@ struct plm_ctx {
     uint64_t lp_seed = 0;
     // device time and algorithmic bytes of the last timed run_classes
     double last_ms = 0, last_bytes = 0;
+    // states after the last two sweeps of a move phase (cycle detection)
+    int32_t *snap[2] = {nullptr, nullptr};
 
     ~plm_ctx() {
         for (auto &l : levels) l.release();
@@ -181,7 +183,7 @@ struct plm_ctx {
         dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
-        dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active);
+        dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active); dev_free(snap[0]); dev_free(snap[1]);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
@@ -542,6 +544,54 @@ struct plm_ctx {
         ++sweeps;
         return mv;
     }
+
+    // Move phase of the current level: sweeps until one moves nothing, at
+    // most max_sweeps.  A sweep is a deterministic function of zeta (volumes
+    // follow from it; colouring and class order are fixed), so when the state
+    // after sweep s equals the state after sweep s - 2, sweeps s + 1, s + 2, ...
+    // alternate between the states of sweeps s - 1 and s, moving as many nodes
+    // as those did.  The phase then takes the state the last allowed sweep
+    // would leave, without running the rest; *skipped receives their number.
+    // Returns the moves of all max_sweeps (or fewer) sweeps.
+    int64_t move_phase(int64_t *skipped) {
+        const int64_t n = L().n;
+        *skipped = 0;
+        std::vector<int64_t> mv;
+        int64_t moves = 0;
+        for (int32_t s = 0; s < opt.max_sweeps; ++s) {
+            int64_t m = sweep();
+            mv.push_back(m);
+            moves += m;
+            if (m == 0) break;
+            if (n == 0 || s + 1 == opt.max_sweeps) continue;
+            if (!snap[0]) {
+                snap[0] = dev_alloc<int32_t>(n0);
+                snap[1] = dev_alloc<int32_t>(n0);
+            }
+            int32_t *prev2 = snap[s & 1];  // state after sweep s - 2
+            if (s >= 2 && mv[s] == mv[s - 2]) {
+                int32_t *flag = (int32_t *)(dcnt + 14);
+                HIPCHK(hipMemsetAsync(flag, 0, 4, st));
+                launch_differ(zeta, prev2, n, flag, st);
+                HIPCHK(hipMemcpyAsync(hbuf + 16, flag, 4, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (*(int32_t *)(hbuf + 16) == 0) {
+                    const int64_t rest = opt.max_sweeps - 1 - s;
+                    for (int64_t k = 1; k <= rest; ++k) moves += (k & 1) ? mv[s - 1] : mv[s];
+                    if (rest & 1) {  // the last sweep leaves the state of sweep s - 1
+                        HIPCHK(hipMemcpyAsync(zeta, snap[(s - 1) & 1], n * 4, hipMemcpyDeviceToDevice, st));
+                        launch_comm_vol(zeta, vol, n, volC, st);
+                        HIPCHK(hipStreamSynchronize(st));
+                    }
+                    sweeps += (int32_t)rest;
+                    *skipped = rest;
+                    break;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(prev2, zeta, n * 4, hipMemcpyDeviceToDevice, st));  // now the state after sweep s
+        }
+        return moves;
+    }
     int32_t ncol_or_build() {
         if (!sched) build_schedule();
         return ncol;
@@ -626,12 +676,9 @@ struct plm_ctx {
             double t0 = now_ms();
             build_schedule();
             double t1 = now_ms();
-            int64_t moves = 0;
-            for (int32_t s = 0; s < opt.max_sweeps; ++s) {
-                int64_t mv = sweep();
-                moves += mv;
-                if (mv == 0) break;
-            }
+            int64_t skipped = 0;
+            int64_t moves = move_phase(&skipped);
+            if (cur < PLM_MAX_LEVELS) stats.cycle_sweeps[cur] = skipped;
             double t2 = now_ms();
             ++done_levels;
             bool last_allowed = opt.max_levels > 0 && done_levels >= opt.max_levels;
@@ -690,13 +737,10 @@ struct plm_ctx {
             sched = false;
             sweeps = 0;
             build_schedule();
-            int64_t moves = 0;
-            for (int32_t s = 0; s < opt.max_sweeps; ++s) {
-                int64_t mv = sweep();
-                moves += mv;
-                if (mv == 0) break;
-            }
+            int64_t skipped = 0;
+            int64_t moves = move_phase(&skipped);
             if (l < PLM_MAX_LEVELS) {
+                stats.ref_cycle_sweeps[l] = skipped;
                 stats.ref_sweeps[l] = sweeps;
                 stats.ref_moves[l] = moves;
                 stats.ref_ms[l] = now_ms() - t0;

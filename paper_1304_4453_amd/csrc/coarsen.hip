@@ -247,6 +247,20 @@ void launch_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t
     hipLaunchKernelGGL(k_comm_vol, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, zeta, vol, n, volC);
     HIPCHK(hipGetLastError());
 }
+// *flag = 1 if a and b differ anywhere in [0, n) (flag cleared by the caller)
+__global__ void k_differ(const int32_t *a, const int32_t *b, int64_t n, int32_t *flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (a[i] != b[i]) {
+            *flag = 1;
+            return;
+        }
+}
+void launch_differ(const int32_t *a, const int32_t *b, int64_t n, int32_t *flag, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t blocks = cdiv(n, kT);
+    hipLaunchKernelGGL(k_differ, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kT), 0, st, a, b, n, flag);
+    HIPCHK(hipGetLastError());
+}
 void launch_iota(int32_t *a, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_iota, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, st, a, n);

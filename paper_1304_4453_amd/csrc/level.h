@@ -119,6 +119,8 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
 // lab[v] = map[lab[v]] for v < n
 void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st);
 void launch_iota(int32_t *a, int64_t n, hipStream_t st);
+// *flag = 1 if a[0..n) and b[0..n) differ (the caller clears *flag)
+void launch_differ(const int32_t *a, const int32_t *b, int64_t n, int32_t *flag, hipStream_t st);
 // community volumes of a partition with ids in [0, n)
 void launch_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t *volC, hipStream_t st);
 void launch_copy_vol(int64_t *dst, const int64_t *src, int64_t n, hipStream_t st);

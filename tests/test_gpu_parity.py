@@ -366,3 +366,29 @@ def test_coarsen_api_and_state_errors(P):
             ctx.move_class(10**6)
         ctx.reset()
         assert ctx.level_info().level == 0
+
+
+# ------------------------------------------------------------------ period-2 sweep cycles
+@pytest.mark.parametrize("max_sweeps", [31, 32, 33])
+def test_sweep_cycles_fast_forward(P, max_sweeps):
+    """Graphs whose sweeps settle into a period-2 cycle (a few nodes moving back
+    and forth until the sweep cap).  The library stops sweeping once the state
+    repeats and takes the state the last sweep would leave; labels, Q, sweeps
+    and move counts must still equal the oracle's, for both parities of the
+    remaining sweep count, with and without refinement."""
+    _say(f"cycles max_sweeps={max_sweeps}")
+    skipped = 0
+    for g in (graphgen.rmat(11, 16, seed=5, weighted=False), graphgen.rmat(10, 16, seed=8, weighted=False)):
+        for refine in (False, True):
+            r = full_run(P, g, max_sweeps=max_sweeps, refine=refine)
+            with P.Context(g.off, g.col, g.w, max_sweeps=max_sweeps, refine=int(refine)) as ctx:
+                ctx.run()
+                st = ctx.stats()
+            skipped += sum(st["cycle_sweeps"]) + sum(st["ref_cycle_sweeps"])
+            assert all(c < s for c, s in zip(st["cycle_sweeps"], st["sweeps"]))
+            assert r.sweeps[0] == max_sweeps
+    rng = np.random.default_rng(9)
+    n = int(rng.integers(50, 800))
+    g = graphgen.random_graph(n, float(rng.uniform(0.005, 0.05)), seed=9, weighted=True, loops=0.1)
+    full_run(P, g, max_sweeps=max_sweeps, refine=True)
+    assert skipped > 0
