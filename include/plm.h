@@ -108,7 +108,16 @@ typedef struct {
      * The reported Q stays the plain modularity (gamma = 1). */
     int32_t gamma_num;
     int32_t gamma_den;
-    int32_t reserved[3];
+    int32_t graph_sweeps;  /* 1 (default): from the third sweep of a level (third
+                              iteration of label propagation) on, a sweep's launches
+                              are replayed from a HIP graph captured once per plan;
+                              0: every launch is issued one by one.  Same results.
+                              Timed runs (timing = 1) always launch one by one. */
+    int32_t hub_stream;    /* 1 (default): in a captured sweep, the partitioned-hub
+                              kernels of each class form a branch beside the class's
+                              other decide kernels, joined before its moves apply;
+                              0: one chain.  Same results. */
+    int32_t reserved[1];
 } plm_options;
 
 /* Fills *opt with the defaults above. */

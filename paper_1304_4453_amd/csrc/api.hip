@@ -133,7 +133,7 @@ struct plm_ctx {
     // hub arrays of the current level (see the hub kernels in move.hip)
     int32_t *hub_pos = nullptr, *nchunk = nullptr, *pbits = nullptr, *stg_x = nullptr;
     int64_t *ins_first = nullptr, *agg_first = nullptr, *stg_off = nullptr, *bkt_off = nullptr, *stg_w = nullptr,
-            *wd_part = nullptr;
+            *wd_part = nullptr, *hub_base = nullptr;
     uint32_t *bkt = nullptr;
     unsigned long long *part = nullptr;
     int32_t *hub_u = nullptr, *ins_hub = nullptr, *agg_hub = nullptr, *sgl_hub = nullptr, *red_hub = nullptr;
@@ -176,6 +176,15 @@ struct plm_ctx {
     double last_ms = 0, last_bytes = 0;
     // states after the last two sweeps of a move phase (cycle detection)
     int32_t *snap[2] = {nullptr, nullptr};
+    // a whole sweep's launches captured once per plan (graph_sweeps), on a
+    // private stream (capture cannot use the null stream), replayed on st
+    hipStream_t cap_st = nullptr;
+    hipGraphExec_t sweep_exec = nullptr;
+    // capture stream of the partitioned-hub branch of a captured sweep
+    // (hub_stream), and a ring of fork/join events
+    hipStream_t hub_cap_st = nullptr;
+    static constexpr int kForkRing = 16;
+    hipEvent_t fork_ev[kForkRing] = {}, join_ev[kForkRing] = {};
 
     ~plm_ctx() {
         for (auto &l : levels) l.release();
@@ -187,10 +196,21 @@ struct plm_ctx {
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
+        drop_graph();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
+        if (hub_cap_st) (void)hipStreamDestroy(hub_cap_st);
+        for (int i = 0; i < kForkRing; ++i) {
+            if (fork_ev[i]) (void)hipEventDestroy(fork_ev[i]);
+            if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+        }
+    }
+    void drop_graph() {
+        if (sweep_exec) (void)hipGraphExecDestroy(sweep_exec);
+        sweep_exec = nullptr;
     }
     void free_hubs() {
         dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(stg_x); dev_free(ins_first);
-        dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part);
+        dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part); dev_free(hub_base);
         dev_free(bkt); dev_free(part); dev_free(hub_u); dev_free(ins_hub); dev_free(agg_hub); dev_free(sgl_hub);
         dev_free(red_hub);
         cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = cap_hubu = cap_ihub = cap_ahub = cap_shub = cap_rhub = 0;
@@ -267,7 +287,8 @@ struct plm_ctx {
                              int64_t agg_tot, int64_t sgl_tot, int64_t red_tot) {
         if (hubs > cap_hubs) {
             dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
-            dev_free(stg_off); dev_free(bkt_off);
+            dev_free(stg_off); dev_free(bkt_off); dev_free(hub_base);
+            hub_base = dev_alloc<int64_t>(hubs);
             hub_pos = dev_alloc<int32_t>(hubs); nchunk = dev_alloc<int32_t>(hubs); pbits = dev_alloc<int32_t>(hubs);
             ins_first = dev_alloc<int64_t>(hubs); agg_first = dev_alloc<int64_t>(hubs);
             stg_off = dev_alloc<int64_t>(hubs); bkt_off = dev_alloc<int64_t>(hubs);
@@ -304,6 +325,7 @@ struct plm_ctx {
     // device, one flag per graph of the level, else null): only the nodes of
     // kept graphs enter the buckets.
     void build_plan(const uint8_t *keep) {
+        drop_graph();  // the captured sweep belongs to the previous plan
         LevelData &l = L();
         GraphView g = l.view();
         int64_t nkeys = (int64_t)ncol * 4 + 1;
@@ -458,12 +480,69 @@ struct plm_ctx {
         ha.agg_hub = agg_hub;
         ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
         ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
-        ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part;
+        ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part; ha.hub_base = hub_base;
         return ha;
     }
 
     // ---------------------------------------------------------------- sweeps
-    int64_t run_classes(int32_t c0, int32_t c1) {
+    // The class steps of classes [c0, c1) on stream s (decide launches, apply).
+    // With aux, a class's partitioned-hub kernels go to aux after a fork event
+    // and the apply waits for them through a join event; they only read the
+    // state the class starts from and write their own class positions, like
+    // the other decide kernels.
+    void launch_classes(int32_t c0, int32_t c1, const MoveState &ms, const HubArrays &ha, const GraphView &g,
+                        bool fw, bool timing, unsigned mask, hipStream_t s, hipStream_t aux = nullptr) {
+        for (int32_t c = c0; c < c1; ++c) {
+            const ClassRange &cr = classes[c];
+            const hipEvent_t *ev = timing ? &events[kEv * (size_t)c] : nullptr;
+            if (aux && cr.red_count > 0) {
+                const int k = c % kForkRing;
+                HIPCHK(hipEventRecord(fork_ev[k], s));
+                HIPCHK(hipStreamWaitEvent(aux, fork_ev[k], 0));
+                launch_class_step(g, ms, cr, ha, fw, ev, mask, aux, 16u);
+                HIPCHK(hipEventRecord(join_ev[k], aux));
+                launch_class_step(g, ms, cr, ha, fw, ev, mask, s, 15u);
+                HIPCHK(hipStreamWaitEvent(s, join_ev[k], 0));
+            } else {
+                launch_class_step(g, ms, cr, ha, fw, ev, mask, s);
+            }
+            launch_apply(g, ms, ha, cr, s);
+        }
+    }
+    void ensure_hub_streams() {
+        if (hub_cap_st) return;
+        HIPCHK(hipStreamCreateWithFlags(&hub_cap_st, hipStreamNonBlocking));
+        for (int i = 0; i < kForkRing; ++i) {
+            HIPCHK(hipEventCreateWithFlags(&fork_ev[i], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming));
+        }
+    }
+
+    // Captures the launches of a whole sweep into sweep_exec.  Every kernel
+    // argument is fixed while the plan lives (build_plan drops the graph), and
+    // the counters a sweep reads back are cleared outside the graph.
+    void capture_sweep(const MoveState &ms, const HubArrays &ha, const GraphView &g, bool fw) {
+        if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+        if (opt.hub_stream) ensure_hub_streams();
+        HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal));
+        hipGraph_t gr = nullptr;
+        try {
+            launch_classes(0, ncol, ms, ha, g, fw, false, 0, cap_st, opt.hub_stream ? hub_cap_st : nullptr);
+        } catch (...) {
+            (void)hipStreamEndCapture(cap_st, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(cap_st, &gr));
+        hipError_t e = hipGraphInstantiate(&sweep_exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) sweep_exec = nullptr;
+        HIPCHK(e);
+    }
+
+    // allow_graph: a whole sweep may be replayed from (or captured into) the
+    // sweep graph
+    int64_t run_classes(int32_t c0, int32_t c1, bool allow_graph = false) {
         if (!sched) build_schedule();
         HIPCHK(hipMemsetAsync(dcnt, 0, 5 * 8, st));
         HIPCHK(hipMemsetAsync(dcnt + 13, 0, 8, st));
@@ -475,10 +554,13 @@ struct plm_ctx {
         // timing_kernel k in 1..5: only kernel group k - 1
         const int tk = opt.timing_kernel;
         const unsigned mask = tk == 0 ? 0x1fu : (1u << (tk - 1));
-        for (int32_t c = c0; c < c1; ++c) {
-            const ClassRange &cr = classes[c];
-            launch_class_step(g, ms, cr, ha, fw, timing ? &events[kEv * (size_t)c] : nullptr, mask, st);
-            launch_apply(ms, cr.begin[0], cr.begin[3] + cr.count[3] - cr.begin[0], st);
+        if (allow_graph && opt.graph_sweeps && !timing && c0 == 0 && c1 == ncol && ncol > 0) {
+            if (!sweep_exec) capture_sweep(ms, ha, g, fw);
+            HIPCHK(hipGraphLaunch(sweep_exec, st));
+        } else {
+            // one stream: a fork and a join per class cost more than the overlap
+            // gains when issued one by one (inside a graph they are edges)
+            launch_classes(c0, c1, ms, ha, g, fw, timing, mask, st);
         }
         HIPCHK(hipMemcpyAsync(hbuf, dcnt, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hbuf + 5, dcnt + 13, 8, hipMemcpyDeviceToHost, st));
@@ -504,7 +586,7 @@ struct plm_ctx {
                     launches += cr.count[b] > 0 ? 1 : 0;
                     stats.kernel_launches[cur][b] += cr.count[b] > 0 ? 1 : 0;
                 }
-                launches += (cr.sgl_count > 0 ? 1 : 0) + (cr.red_count > 0 ? 3 : 0);
+                launches += (cr.sgl_count > 0 ? 1 : 0) + (cr.red_count > 0 ? 2 : 0);
                 stats.kernel_launches[cur][3] += cr.sgl_count > 0 ? 1 : 0;
                 stats.kernel_launches[cur][4] += cr.red_count > 0 ? 1 : 0;
             }
@@ -539,8 +621,9 @@ struct plm_ctx {
         return moves;
     }
 
-    int64_t sweep() {
-        int64_t mv = run_classes(0, ncol_or_build());
+    // one sweep; from the third of a move phase on, replayed from the sweep graph
+    int64_t sweep(bool allow_graph = false) {
+        int64_t mv = run_classes(0, ncol_or_build(), allow_graph && sweeps >= 2);
         ++sweeps;
         return mv;
     }
@@ -559,7 +642,7 @@ struct plm_ctx {
         std::vector<int64_t> mv;
         int64_t moves = 0;
         for (int32_t s = 0; s < opt.max_sweeps; ++s) {
-            int64_t m = sweep();
+            int64_t m = sweep(true);
             mv.push_back(m);
             moves += m;
             if (m == 0) break;
@@ -770,7 +853,7 @@ struct plm_ctx {
         int32_t it = 0;
         try {
             while (updated * 100000 > l.n && it < max_iters) {
-                updated = run_classes(0, ncol);
+                updated = run_classes(0, ncol, it >= 2);
                 if (upd) upd[it] = updated;
                 if (opt.timing) {
                     stats.lp_decide_ms += last_ms;
@@ -892,7 +975,7 @@ struct plm_ctx {
             int64_t planned = ebound[A] - ebound[0];
             int64_t moves = 0;
             for (int32_t s = 0; s < opt.max_sweeps; ++s) {
-                int64_t mv = sweep();
+                int64_t mv = sweep(true);
                 moves += mv;
                 if (mv == 0) break;
                 // a graph whose sweep moved nothing is done at this level (a
@@ -1022,6 +1105,8 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.int_mode < 0 || o.int_mode > 2) { msg = "bad int_mode"; return PLM_E_ARG; }
     if (o.timing_kernel < 0 || o.timing_kernel > 5) { msg = "timing_kernel must lie in [0, 5]"; return PLM_E_ARG; }
     if (o.refine != 0 && o.refine != 1) { msg = "refine must be 0 or 1"; return PLM_E_ARG; }
+    if (o.graph_sweeps != 0 && o.graph_sweeps != 1) { msg = "graph_sweeps must be 0 or 1"; return PLM_E_ARG; }
+    if (o.hub_stream != 0 && o.hub_stream != 1) { msg = "hub_stream must be 0 or 1"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
@@ -1082,6 +1167,8 @@ void plm_default_options(plm_options *o) {
     o->timing = 0;
     o->gamma_num = 1;
     o->gamma_den = 1;
+    o->graph_sweeps = 1;
+    o->hub_stream = 1;
 }
 
 }  // extern "C"

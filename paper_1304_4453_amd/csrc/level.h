@@ -84,6 +84,7 @@ struct HubArrays {
     int64_t *stg_w;            // staging: weight of each entry
     uint32_t *bkt;             // (start << 16 | count) per (bucket, chunk), bucket-major
     int64_t *wd_part;          // per chunk workgroup: its share of w(u, D \ u)
+    int64_t *hub_base;         // per hub: vol(D \ u) at the start of its class
     unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, pad
 };
 
@@ -97,9 +98,15 @@ constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol
 // and last dispatch, for the groups whose bit is set in ev_mask and that launch
 // ms.active non-null: the label-propagation variant (ms.S = 2^32, ms.gp = 0,
 // ms.gq = 1, ms.wide_lim = INT32_MAX)
+// groups: bit i launches kernel group i (lane, wavefront, workgroup,
+// one-workgroup hub, partitioned hub)
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st);
-void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st);
+                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st,
+                       unsigned groups = 0x1fu);
+// The moves of a class: reduce and apply of its partitioned hubs, and the
+// apply of every other decided move (all class positions)
+void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, const ClassRange &cr,
+                  hipStream_t st);
 // row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
 // positions [begin, begin + count)
 void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,

@@ -479,12 +479,14 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
 //     for hashed ids, but possible) is redone in 2, 4, ... passes, each over a
 //     sub-partition of its keys, so any input stays exact.
 //  3. reduce: a workgroup per node combines the partial bests and the w(u, D)
-//     shares and decides the move.
+//     shares, decides the move and applies it, within the launch that applies
+//     the class's other moves (k_reduce_apply).
 constexpr int kHubThreads = 256;
 constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
 constexpr int kAggSlots = 4096;    // LDS table of a bucket workgroup (~2048 entries expected)
 constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
-constexpr int kAggTile = 2048;     // chunks whose segments are flattened at once
+constexpr int kAggTile = 512;      // chunks whose segments are flattened at once (52 KB of LDS: 3 per CU)
+constexpr int32_t kHubPending = -2;  // class position of a partitioned hub until its reduce
 constexpr int kAggBatch = 4;       // staged entries per thread loaded together
 
 __device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
@@ -503,6 +505,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     const int64_t hg = ha.ins_hub[blk0 + blockIdx.x];
     const int64_t k = blockIdx.x - ha.ins_first[hg];
     const int32_t u = ha.hub_u[hg];
+    // the apply launch leaves this position to the hub's own reduce
+    if (k == 0 && threadIdx.x == 0) ms.move_to[ha.hub_pos[hg]] = kHubPending;
     if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
     const int32_t D = ms.zeta[u];
     const int64_t e0 = g.off[u], e1 = g.off[u + 1];
@@ -735,6 +739,9 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     for (int i = 0; i < kHubThreads / kWave; ++i) wD += wred[i];
     const int32_t D = ms.zeta[u];
     const int64_t base = LP ? 0 : ms.volC[D] - vu;
+    // vol(D \ u) at the start of the class, for the reduce (which runs while the
+    // class's other moves apply)
+    if (p == 0 && threadIdx.x == 0) ha.hub_base[hg] = base;
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
@@ -764,17 +771,30 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
 }
 
-// One workgroup per hub of the class combines the bucket partials and the
-// w(u, D) shares (written by earlier launches) and decides the move.
+// apply of one decided move (X >= 0) of node u; returns 1
+__device__ __forceinline__ int64_t apply_move(const MoveState &ms, int32_t u, int32_t X) {
+    int32_t D = ms.zeta[u];
+    int64_t vu = ms.vol[u];
+    ms.zeta[u] = X;
+    if (!ms.active) {  // label propagation keeps no community volumes
+        atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
+        atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+    }
+    if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
+    return 1;
+}
+
+// A partitioned hub's reduce: one workgroup combines the bucket partials and
+// the w(u, D) shares (written by earlier launches), decides the move like any
+// other node, and applies it.  vol(D \ u) comes from the bucket launch, taken
+// before any move of the class applied.
 template <bool LP>
-__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(GraphView g, MoveState ms, HubArrays ha, int64_t blk0) {
+__device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha,
+                                                 int64_t hg) {
     __shared__ int64_t wsum[kHubThreads / kWave];
     __shared__ int32_t dec;
-    const int64_t hg = ha.red_hub[blk0 + blockIdx.x];
-    if (LP && !ms.active[ha.hub_u[hg]]) {
-        if (threadIdx.x == 0) ms.move_to[ha.hub_pos[hg]] = -1;
-        return;
-    }
+    const int32_t u = ha.hub_u[hg];
+    if (LP && !ms.active[u]) return;  // nothing decided, nothing to apply
     const int64_t nagg = (int64_t)1 << ha.pbits[hg];
     const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
     i128 bs = neg_inf<i128>();
@@ -792,43 +812,38 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(GraphView g, MoveSta
     if (threadIdx.x == 0) {
         wD = 0;
         for (int i = 0; i < kHubThreads / kWave; ++i) wD += wsum[i];
-        int64_t pos = ha.hub_pos[hg];
-        int32_t u = ha.hub_u[hg];
-        int32_t D = ms.zeta[u];
-        int64_t vu = ms.vol[u];
-        int64_t base = LP ? 0 : ms.volC[D] - vu;
+        const int64_t vu = ms.vol[u];
+        const int64_t base = ha.hub_base[hg];
         i128 K = (i128)node_S(ms, u) * ms.gq * (i128)wD - (i128)vu * ms.gp * (i128)base +
                  (LP ? (i128)kLpTieMax : (i128)0);
         dec = (bx != kNone && bs > K) ? bx : -1;
-        ms.move_to[pos] = dec;
+        if (dec >= 0) atomicAdd(ms.moves_dev, (unsigned long long)apply_move(ms, u, dec));
     }
     if (LP) {
         __syncthreads();
-        const int32_t u = ha.hub_u[hg];
         if (dec >= 0) lp_activate(g, ms.active, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads);
         else if (threadIdx.x == 0) ms.active[u] = 0;
     }
 }
 
 // ------------------------------------------------------------------ apply
-__global__ __launch_bounds__(256) void k_apply(MoveState ms, int64_t begin, int64_t count) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The moves of class positions [begin, begin + count): workgroups [0, nred)
+// reduce and apply the class's partitioned hubs (red_hub[red0 ..]), the rest
+// apply every other decided move.  Partitioned hubs' positions hold
+// kHubPending and are skipped by the latter.
+template <bool LP>
+__global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveState ms, HubArrays ha, int64_t red0,
+                                                              int64_t nred, int64_t begin, int64_t count) {
+    if ((int64_t)blockIdx.x < nred) {  // workgroup-uniform
+        hub_reduce_apply<LP>(g, ms, ha, ha.red_hub[red0 + blockIdx.x]);
+        return;
+    }
+    int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x;
     int64_t moved = 0;
     if (i < count) {
         int64_t pos = begin + i;
         int32_t X = ms.move_to[pos];
-        if (X >= 0) {
-            int32_t u = ms.class_nodes[pos];
-            int32_t D = ms.zeta[u];
-            int64_t vu = ms.vol[u];
-            ms.zeta[u] = X;
-            if (!ms.active) {  // label propagation keeps no community volumes
-                atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
-                atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
-            }
-            if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
-            moved = 1;
-        }
+        if (X >= 0) moved = apply_move(ms, ms.class_nodes[pos], X);
     }
     moved = wave_sum(moved);
     if (lane_id() == 0 && moved) atomicAdd(ms.moves_dev, (unsigned long long)moved);
@@ -846,62 +861,79 @@ __global__ void k_hub_degrees(GraphView g, const int32_t *class_nodes, const int
 }
 
 // ------------------------------------------------------------------ launchers
+// A dispatch with start/stop events attached when either is given, else a plain
+// launch (the form stream capture records).
+template <typename... Params, typename... Args>
+static void dispatch(void (*kernel)(Params...), dim3 grid, dim3 block, hipStream_t st, hipEvent_t start,
+                     hipEvent_t stop, Args... args) {
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, start, stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 template <int WK, bool LP>
 static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                          int fw, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
+                          int fw, const hipEvent_t *ev, unsigned ev_mask, unsigned groups, hipStream_t st) {
     // start / stop events of kernel group i (taken by the dispatch itself)
     auto t0 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i] : (hipEvent_t) nullptr; };
     auto t1 = [&](int i) { return (ev && ((ev_mask >> i) & 1u)) ? ev[2 * i + 1] : (hipEvent_t) nullptr; };
-    if (cr.count[0] > 0)
-        hipExtLaunchKernelGGL(k_decide_lane<WK, LP>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), 0, st, t0(0),
-                              t1(0), 0, g, ms, cr.begin[0], cr.count[0], fw);
-    if (cr.count[1] > 0) {
+    if (cr.count[0] > 0 && (groups & 1u))
+        dispatch(k_decide_lane<WK, LP>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), st, t0(0), t1(0), g, ms,
+                 cr.begin[0], cr.count[0], fw);
+    if (cr.count[1] > 0 && (groups & 2u)) {
         int64_t blocks = cdiv(cr.count[1], 4);
-        hipExtLaunchKernelGGL(k_decide_wave<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st,
-                              t0(1), t1(1), 0, g, ms, cr.begin[1], cr.count[1], fw);
+        dispatch(k_decide_wave<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), st, t0(1), t1(1),
+                 g, ms, cr.begin[1], cr.count[1], fw);
     }
-    if (cr.count[2] > 0) {
+    if (cr.count[2] > 0 && (groups & 4u)) {
         int64_t blocks = cr.count[2];
-        hipExtLaunchKernelGGL(k_decide_block<WK, LP>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
-                              dim3(kBlockThreads), 0, st, t0(2), t1(2), 0, g, ms, cr.begin[2], cr.count[2], fw);
+        dispatch(k_decide_block<WK, LP>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(kBlockThreads), st,
+                 t0(2), t1(2), g, ms, cr.begin[2], cr.count[2], fw);
     }
-    if (cr.sgl_count > 0)
-        hipExtLaunchKernelGGL(k_hub_single<WK, LP>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), 0, st, t0(3),
-                              t1(3), 0, g, ms, ha, cr.sgl_base, fw);
-    if (cr.red_count > 0) {
-        hipExtLaunchKernelGGL(k_hub_part<WK, LP>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), 0, st, t0(4),
-                              (hipEvent_t) nullptr, 0, g, ms, ha, cr.ins_base);
-        hipLaunchKernelGGL(k_hub_agg<LP>, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), 0, st, ms, ha,
-                           cr.agg_base, fw);
-        hipExtLaunchKernelGGL(k_hub_reduce<LP>, dim3((unsigned)cr.red_count), dim3(kHubThreads), 0, st,
-                              (hipEvent_t) nullptr, t1(4), 0, g, ms, ha, cr.red_base);
+    if (cr.sgl_count > 0 && (groups & 8u))
+        dispatch(k_hub_single<WK, LP>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), st, t0(3), t1(3), g, ms,
+                 ha, cr.sgl_base, fw);
+    if (cr.red_count > 0 && (groups & 16u)) {
+        dispatch(k_hub_part<WK, LP>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), st, t0(4), (hipEvent_t) nullptr,
+                 g, ms, ha, cr.ins_base);
+        dispatch(k_hub_agg<LP>, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), st, (hipEvent_t) nullptr, t1(4), ms,
+                 ha, cr.agg_base, fw);
     }
 }
 
 void launch_class_step(const GraphView &g, const MoveState &ms, const ClassRange &cr, const HubArrays &ha,
-                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st) {
+                       bool force_wide, const hipEvent_t *ev, unsigned ev_mask, hipStream_t st, unsigned groups) {
     int fw = force_wide ? 1 : 0;
     const bool lp = ms.active != nullptr;
     switch (g.wkind) {
         case 0:
-            if (lp) class_step_wk<0, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
-            else class_step_wk<0, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            if (lp) class_step_wk<0, true>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
+            else class_step_wk<0, false>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
             break;
         case 1:
-            if (lp) class_step_wk<1, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
-            else class_step_wk<1, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            if (lp) class_step_wk<1, true>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
+            else class_step_wk<1, false>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
             break;
         default:
-            if (lp) class_step_wk<2, true>(g, ms, cr, ha, fw, ev, ev_mask, st);
-            else class_step_wk<2, false>(g, ms, cr, ha, fw, ev, ev_mask, st);
+            if (lp) class_step_wk<2, true>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
+            else class_step_wk<2, false>(g, ms, cr, ha, fw, ev, ev_mask, groups, st);
             break;
     }
     HIPCHK(hipGetLastError());
 }
 
-void launch_apply(const MoveState &ms, int64_t begin, int64_t count, hipStream_t st) {
+void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, const ClassRange &cr,
+                  hipStream_t st) {
+    const int64_t begin = cr.begin[0], count = cr.begin[3] + cr.count[3] - cr.begin[0];
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_apply, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, st, ms, begin, count);
+    const int64_t blocks = cr.red_count + cdiv(count, kHubThreads);
+    if (ms.active)
+        hipLaunchKernelGGL(k_reduce_apply<true>, dim3((unsigned)blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                           cr.red_base, cr.red_count, begin, count);
+    else
+        hipLaunchKernelGGL(k_reduce_apply<false>, dim3((unsigned)blocks), dim3(kHubThreads), 0, st, g, ms, ha,
+                           cr.red_base, cr.red_count, begin, count);
     HIPCHK(hipGetLastError());
 }
 

@@ -392,3 +392,48 @@ def test_sweep_cycles_fast_forward(P, max_sweeps):
     g = graphgen.random_graph(n, float(rng.uniform(0.005, 0.05)), seed=9, weighted=True, loops=0.1)
     full_run(P, g, max_sweeps=max_sweeps, refine=True)
     assert skipped > 0
+
+
+# ------------------------------------------------------------------ sweeps replayed from a HIP graph
+def test_graph_sweeps_equal_eager(P):
+    """graph_sweeps: from the third sweep of a level on, a sweep is replayed
+    from a captured HIP graph; hub_stream: the partitioned-hub kernels run on a
+    second stream (also inside the captured graph, as a forked branch).
+    Replays are interleaved with eager work (counter clears, read-backs,
+    re-planning); every combination must equal the plain one and the oracle."""
+    _say("graph sweeps / hub stream vs eager")
+    cases = [(graphgen.rmat(12, 16, seed=31, weighted=True), {}),
+             (graphgen.rmat(11, 16, seed=5, weighted=False), SMALL_BINS),
+             (graphgen.rmat(11, 16, seed=4, weighted=False), MID_BINS)]
+    for g, bins in cases:
+        res = []
+        for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            with P.Context(g.off, g.col, g.w, graph_sweeps=gs, hub_stream=hs, refine=1, **bins) as ctx:
+                labels, q, lv = ctx.run()
+                st = ctx.stats()
+                lp = ctx.plp()
+                labels2, q2, lv2 = ctx.run()   # a second run re-captures every level
+            res.append((labels, q, lv, st["sweeps"], st["moves"], st["ref_moves"], lp[0], lp[2], lp[3]))
+            assert np.array_equal(labels, labels2) and q == q2 and lv == lv2
+        a = res[0]
+        for b in res[1:]:
+            assert np.array_equal(a[0], b[0]) and a[1:6] == b[1:6]
+            assert np.array_equal(a[6], b[6]) and a[7:] == b[7:]
+        r = oracle.run(g.off, g.col, g.w, refine=True)
+        assert np.array_equal(b[0], r.labels) and b[1] == r.q
+        p = oracle.plp(g.off, g.col, g.w)
+        assert np.array_equal(b[6], p.labels) and b[8] == p.updates
+
+
+def test_graph_sweeps_batch_equal_eager(P):
+    _say("graph sweeps batch")
+    gs = [graphgen.rmat(11, 16, seed=s, weighted=s % 2 == 0) for s in range(3, 9)] + \
+         [graphgen.planted_partition_1000(seed=4)]
+    node_base, off, col, w = P.pack_batch(gs)
+    out = []
+    for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        with P.BatchContext(node_base, off, col, w, graph_sweeps=gs, hub_stream=hs, **SMALL_BINS) as bc:
+            out.append(bc.run_batch())
+    la, qa, lva = out[0]
+    for lb, qb, lvb in out[1:]:
+        assert np.array_equal(la, lb) and list(qa) == list(qb) and list(lva) == list(lvb)
