@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-KERNELS = ["k_decide_lane", "k_decide_wave", "k_decide_block", "k_hub_single", "k_hub_part+k_hub_agg+k_hub_reduce"]
+KERNELS = ["k_decide_lane", "k_decide_wave", "k_decide_block", "k_hub_single", "k_hub_part+k_hub_agg"]
 
 WORKLOADS = {
     "rmat26": dict(desc="R-MAT scale 26, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised, loops and "
