@@ -269,8 +269,10 @@ def serve_bench(args, P, torch, np):
     """Served PLM: the request stream of the arrival window is generated on the
     GPU first (client buffers), then replayed open-loop in real time against
     the native request server (plm_server_*): each request is submitted at its
-    arrival time, every step runs the admitted requests as one batch, and a
-    request's latency is its result-ready time minus its arrival time."""
+    arrival time; a step admits the queued requests that fit beside the batches
+    in flight as one batch and hands it to a free worker of the server (up to
+    --serve-inflight batches share the device); a request's latency is its
+    result-ready time minus its arrival time."""
     import graphgen
     import oracle
     rate = 200.0
@@ -284,7 +286,7 @@ def serve_bench(args, P, torch, np):
     # a few small requests are checked against the oracle afterwards
     check = [i for i in range(count) if scales[i] <= 13][:3]
     check_lab = {i: torch.empty(dgs[i].n, dtype=torch.int32, device="cuda:0") for i in check}
-    srv = P.Server(200 * 10 ** 9)
+    srv = P.Server(200 * 10 ** 9, max_inflight=args.serve_inflight)
     ids, lat, done_q = {}, np.full(count, np.nan), {}
     nxt, t0 = 0, time.perf_counter()
     while len(done_q) < count:
@@ -293,19 +295,24 @@ def serve_bench(args, P, torch, np):
             d = dgs[nxt]
             ids[nxt] = srv.submit(d.off_ptr, d.col_ptr, None, mem_kind=P.PLM_MEM_DEVICE, n=d.n, nnz=d.nnz)
             nxt += 1
-        if len(ids) > len(done_q) and srv.info().queued > 0:
-            srv.step()
-            tdone = time.perf_counter() - t0
-            for i, rid in list(ids.items()):
-                if i in done_q:
-                    continue
-                ready, _, q, lv = srv.result(rid, check_lab.get(i))
-                if ready:
-                    done_q[i] = (q, lv)
-                    lat[i] = tdone - arr[i]
-                    dgs[i].free()
-        elif nxt < count:
-            time.sleep(max(0.0, min(arr[nxt] - now, 0.01)))
+        if srv.info().queued > 0:
+            srv.step()  # one inflight: runs a batch; several: hands one to a free worker
+        tdone = time.perf_counter() - t0
+        progressed = False
+        for i, rid in list(ids.items()):
+            if i in done_q:
+                continue
+            ready, _, q, lv = srv.result(rid, check_lab.get(i))
+            if ready:
+                done_q[i] = (q, lv)
+                lat[i] = tdone - arr[i]
+                dgs[i].free()
+                progressed = True
+        if not progressed:
+            pause = 0.0005
+            if srv.info().inflight == 0 and nxt < count:
+                pause = max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.01))
+            time.sleep(pause)
     makespan = time.perf_counter() - t0
     info = srv.info()
     srv.close()
@@ -340,6 +347,7 @@ def serve_bench(args, P, torch, np):
             "edges_per_s": edges / makespan, "p50_latency_s": float(np.nanpercentile(lat, 50)),
             "p99_latency_s": float(np.nanpercentile(lat, 99)), "max_latency_s": float(np.nanmax(lat)),
             "batches": int(info.batches), "mean_batch": count / max(int(info.batches), 1),
+            "max_inflight": args.serve_inflight,
             "plain_graphs_per_s": len(sample) / tp, "plain_sample": int(len(sample)),
             "speedup_vs_plain": (count / makespan) / (len(sample) / tp),
             "hbm_budget_bytes": 200 * 10 ** 9,
@@ -489,6 +497,7 @@ def main():
     ap.add_argument("--no-epp", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served workload")
     ap.add_argument("--plain-serve-sample", type=int, default=40)
+    ap.add_argument("--serve-inflight", type=int, default=1, help="batches the server may run at once")
     ap.add_argument("--sweep-probe", action="store_true",
                     help="one instrumented level-0 sweep of R-MAT 26 for hardware-counter runs")
     args = ap.parse_args()

@@ -112,7 +112,10 @@ typedef struct {
                               iteration of label propagation) on, a sweep's launches
                               are replayed from a HIP graph captured once per plan;
                               0: every launch is issued one by one.  Same results.
-                              Timed runs (timing = 1) always launch one by one. */
+                              Timed runs (timing = 1) always launch one by one.  While
+                              a capture runs (on private non-blocking streams), HIP
+                              refuses synchronous copies on the legacy default
+                              stream from other host threads of the process. */
     int32_t hub_stream;    /* 1 (default): in a captured sweep, the partitioned-hub
                               kernels of each class form a branch beside the class's
                               other decide kernels, joined before its moves apply;
@@ -220,16 +223,21 @@ plm_status plm_batch_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *
 
 /* ---------------------------------------------------------------- serving
  * A request server over the batched engine: each request is one graph (CSR as
- * for plm_create); its result equals plm_run on it.  plm_server_step admits
- * queued requests in submission order while their resident footprint (CSR,
- * per-node state and contraction buffers: 8(n+1) + 4 nnz (+4 nnz with
- * weights) + 128 n + 64 nnz bytes) stays within hbm_budget_bytes and their
- * entries within max_batch_entries (at least one request per step), copies
+ * for plm_create); its result equals plm_run on it, whatever it is batched
+ * with.  plm_server_step admits queued requests in submission order while
+ * their resident footprint (CSR, per-node state and contraction buffers:
+ * 8(n+1) + 4 nnz (+4 nnz with weights) + 128 n + 64 nnz bytes) fits what
+ * hbm_budget_bytes leaves beside the batches still running and their entries
+ * fit max_batch_entries (with nothing running, at least one request), copies
  * them side by side into device memory, runs them as one batch
- * (plm_batch_run) and completes them.  Results stay in device memory until
+ * (plm_batch_run) and completes them.  max_inflight (1..16) batches may run
+ * at once: with 1, the batch runs inside plm_server_step on hip_stream; with
+ * k >= 2, the server's k worker threads each run batches on a stream of their
+ * own (without sweep graphs), plm_server_step only admits and hands over (when
+ * a worker is free), and the batches' kernels share the device.  Results stay in device memory until
  * plm_server_result fetches them.  The options are those of the batches
- * (colour schedule, int_mode auto or 128, else PLM_E_ARG).  A server is used
- * by one host thread at a time. */
+ * (colour schedule, int_mode auto or 128, else PLM_E_ARG).  The client calls
+ * a server from one host thread at a time. */
 typedef struct plm_server plm_server;
 
 typedef struct {
@@ -238,26 +246,35 @@ typedef struct {
     int64_t batches;       /* steps that ran a batch */
     int64_t held_results;  /* completed or failed, not yet fetched */
     int64_t budget_bytes;
+    int64_t inflight;      /* batches admitted and not finished */
+    int64_t running;       /* requests in those batches */
+    int64_t resident_bytes; /* their footprint, charged against the budget */
 } plm_server_info_t;
 
+/* Errors: PLM_E_ARG (budget or entry cap <= 0, max_inflight outside [1, 16],
+ * options not valid for batches), PLM_E_DEVICE (worker streams). */
 plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t max_batch_entries,
-                             void *hip_stream, const plm_options *opt);
+                             int32_t max_inflight, void *hip_stream, const plm_options *opt);
 
 /* Queues one graph without copying it: offsets/cols/weights (mem_kind) must
- * stay valid and unchanged until the request is admitted by a step.  Checks
+ * stay valid and unchanged until the request's result is ready.  Checks
  * offsets[0] = 0 and offsets[n] = nnz (PLM_E_GRAPH); a request whose footprint
  * alone exceeds the budget is refused (PLM_E_BUDGET).  *request_id identifies
  * it in plm_server_result. */
 plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *cols,
                              const int32_t *weights, int32_t mem_kind, int64_t *request_id);
 
-/* Runs one batch of admitted requests (nothing when the queue is empty);
- * *completed_out = requests completed by it.  A request that fails (invalid
- * graph, allocation) is completed with its error, reported by
- * plm_server_result; when validation refuses a batch of several requests,
- * they are queued again at the front and run one per step, so that only the
- * invalid ones fail. */
+/* Admits one batch (nothing when the queue is empty, every worker is busy, or
+ * the first queued request does not fit beside the running batches) and, with
+ * max_inflight = 1, runs it; *completed_out = requests completed or failed
+ * since the previous step or wait.  A request that fails (invalid graph,
+ * allocation) is completed with its error, reported by plm_server_result;
+ * when validation refuses a batch of several requests, they are queued again
+ * at the front and run one per batch, so that only the invalid ones fail. */
 plm_status plm_server_step(plm_server *s, int32_t *completed_out);
+
+/* Blocks until no batch is in flight; *completed_out as for plm_server_step. */
+plm_status plm_server_wait(plm_server *s, int32_t *completed_out);
 
 /* *ready_out = 0 while the request waits.  Once it has run: its canonical
  * labels[n] (mem_kind; NULL to discard), *q_out and *levels_out as plm_run

@@ -76,7 +76,8 @@ class plm_stats_t(ctypes.Structure):
 
 class plm_server_info_t(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
-                ("held_results", ctypes.c_int64), ("budget_bytes", ctypes.c_int64)]
+                ("held_results", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("inflight", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
 
 
 class PLMError(RuntimeError):
@@ -112,7 +113,8 @@ def _load():
     lib.plm_get_stats.argtypes = [vp, P(plm_stats_t)]
     lib.plm_batch_create.argtypes = [P(vp), i64, vp, i64, vp, vp, vp, i32, vp, P(plm_options)]
     lib.plm_batch_run.argtypes = [vp, vp, vp, vp]
-    lib.plm_server_create.argtypes = [P(vp), i64, i64, vp, P(plm_options)]
+    lib.plm_server_create.argtypes = [P(vp), i64, i64, i32, vp, P(plm_options)]
+    lib.plm_server_wait.argtypes = [vp, P(i32)]
     lib.plm_server_submit.argtypes = [vp, i64, i64, vp, vp, vp, i32, P(i64)]
     lib.plm_server_step.argtypes = [vp, P(i32)]
     lib.plm_server_result.argtypes = [vp, i64, vp, i32, P(dbl), P(i32), P(i32)]
@@ -122,7 +124,7 @@ def _load():
     lib.plm_server_last_error.argtypes = [vp]
     lib.plm_server_last_error.restype = ctypes.c_char_p
     for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_server_create", "plm_server_submit",
-              "plm_server_step", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_plp", "plm_epp", "plm_modularity",
+              "plm_server_step", "plm_server_wait", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_plp", "plm_epp", "plm_modularity",
               "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
         getattr(lib, f).restype = i32
     return lib
@@ -151,6 +153,7 @@ plm_batch_run = _lib.plm_batch_run
 plm_server_create = _lib.plm_server_create
 plm_server_submit = _lib.plm_server_submit
 plm_server_step = _lib.plm_server_step
+plm_server_wait = _lib.plm_server_wait
 plm_server_result = _lib.plm_server_result
 plm_server_info = _lib.plm_server_info
 plm_server_destroy = _lib.plm_server_destroy
@@ -385,14 +388,17 @@ class BatchContext(Context):
 
 class Server:
     """Owns one plm_server.  submit() queues a graph without copying it: the
-    caller keeps the arrays (numpy for host, torch tensors or addresses for
-    device memory) alive until a step has admitted it."""
+    arrays (numpy for host, torch tensors or addresses for device memory) are
+    kept alive here until its result is fetched.  max_inflight >= 2 runs up to
+    that many batches at once on worker threads of the server; step() then
+    returns after handing a batch over, and wait() blocks until none runs."""
 
-    def __init__(self, hbm_budget_bytes: int, max_batch_entries: int = 1 << 40, stream=None, **options):
+    def __init__(self, hbm_budget_bytes: int, max_batch_entries: int = 1 << 40, stream=None, max_inflight: int = 1,
+                 **options):
         self._s = ctypes.c_void_p()
         sp = stream if isinstance(stream, int) or stream is None else stream.cuda_stream
         self.opt = default_options(**options)
-        rc = plm_server_create(ctypes.byref(self._s), hbm_budget_bytes, max_batch_entries, sp or 0,
+        rc = plm_server_create(ctypes.byref(self._s), hbm_budget_bytes, max_batch_entries, max_inflight, sp or 0,
                                ctypes.byref(self.opt))
         if rc != 0:
             raise PLMError(rc, "plm_server_create failed")
@@ -423,6 +429,11 @@ class Server:
     def step(self) -> int:
         c = ctypes.c_int32()
         self._check(plm_server_step(self._s, ctypes.byref(c)))
+        return c.value
+
+    def wait(self) -> int:
+        c = ctypes.c_int32()
+        self._check(plm_server_wait(self._s, ctypes.byref(c)))
         return c.value
 
     def result(self, rid: int, labels=None, mem_kind: int | None = None):

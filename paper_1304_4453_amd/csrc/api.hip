@@ -524,7 +524,7 @@ struct plm_ctx {
     void capture_sweep(const MoveState &ms, const HubArrays &ha, const GraphView &g, bool fw) {
         if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
         if (opt.hub_stream) ensure_hub_streams();
-        HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal));
+        HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
         hipGraph_t gr = nullptr;
         try {
             launch_classes(0, ncol, ms, ha, g, fw, false, 0, cap_st, opt.hub_stream ? hub_cap_st : nullptr);
@@ -1229,6 +1229,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c = new plm_ctx();
         std::memset(&c->stats, 0, sizeof(c->stats));
         c->st = (hipStream_t)hip_stream;
+        c->scr.set_stream(c->st);
         c->opt = o;
         c->mem_kind = mem_kind;
         c->n0 = n;

@@ -94,9 +94,11 @@ void hip_check(hipError_t e, const char *what);
 
 // ------------------------------------------------------------------ scratch allocator
 // Grow-only device scratch handed out as aligned slices; reset per use site.
+// Only work on the owner's stream (set_stream) uses it.
 class Scratch {
   public:
     ~Scratch();
+    void set_stream(hipStream_t s) { stream_ = s; }
     void reserve(size_t bytes);
     void *get(size_t bytes);  // next aligned slice (reserve() first)
     void reset() { used_ = 0; }
@@ -105,6 +107,7 @@ class Scratch {
   private:
     char *base_ = nullptr;
     size_t cap_ = 0, used_ = 0;
+    hipStream_t stream_ = nullptr;
 };
 
 size_t align_up(size_t x, size_t a = 256);

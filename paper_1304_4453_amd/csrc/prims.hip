@@ -243,9 +243,9 @@ Scratch::~Scratch() {
 void Scratch::reserve(size_t bytes) {
     used_ = 0;
     if (bytes <= cap_) return;
-    // work queued on any stream may still use the old buffer
+    // work queued on the owner's stream may still use the old buffer
     if (base_) {
-        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipStreamSynchronize(stream_));
         HIPCHK(hipFree(base_));
     }
     base_ = nullptr;

@@ -2,17 +2,26 @@
 // include/plm.h).
 //
 // Requests (one graph each) wait in a first-in first-out queue.  A step admits
-// queued requests in order while their resident footprint fits the HBM budget
-// (and their entries fit the per-batch cap), lays their CSRs side by side in
-// device memory as one disjoint union, runs Algorithm 3 on all of them at once
-// (run_batch in api.hip: every graph gets exactly the result of its own run),
-// and completes them.  Labels stay in device memory until the client fetches
-// them.
+// queued requests in order while their resident footprint fits what the HBM
+// budget leaves beside the batches still running (and their entries fit the
+// per-batch cap), lays their CSRs side by side in device memory as one
+// disjoint union, runs Algorithm 3 on all of them at once (run_batch in
+// api.hip: every graph gets exactly the result of its own run), and completes
+// them.  Labels stay in device memory until the client fetches them.
+//
+// With max_inflight = 1 the batch runs inside the step, on the server's
+// stream.  With k >= 2, k worker threads of the server each own a stream; a
+// step hands the admitted batch to a free worker and returns, so requests that
+// arrive while batches run are admitted as soon as a worker and budget are
+// free, and the batches' kernels share the device.
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -58,7 +67,7 @@ struct plm_server {
         const int32_t *col = nullptr;
         const int32_t *w = nullptr;
         int mem_kind = PLM_MEM_HOST;
-        int state = 0;  // 0 queued, 1 done, 2 failed
+        int state = 0;  // 0 queued, 3 running, 1 done, 2 failed
         bool solo = false;  // runs in a batch of its own (its batch was refused as a whole)
         int32_t *labels = nullptr;  // device, when done
         double q = 0.0;
@@ -67,55 +76,104 @@ struct plm_server {
         plm_status err = PLM_OK;
         std::string msg;
     };
+    // one admitted batch: the requests (ids and copies of their descriptors)
+    struct Job {
+        std::vector<int64_t> ids;
+        std::vector<Req> in;
+        int64_t bytes = 0;
+    };
     hipStream_t st = nullptr;
     plm_options opt;
     int64_t budget = 0, max_entries = 0;
+    int32_t max_inflight = 1;
     std::string err;
+    // everything below is guarded by mu
+    std::mutex mu;
+    std::condition_variable cv_job, cv_idle;
     std::deque<int64_t> queue;
     std::unordered_map<int64_t, Req> reqs;
-    int64_t next_id = 0, completed = 0, batches = 0, resident = 0;
+    std::deque<Job> jobs;  // admitted, waiting for a worker
+    int64_t next_id = 0, completed = 0, batches = 0, resident = 0, inflight = 0, unreported = 0;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> wstreams;
 
     ~plm_server() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_job.notify_all();
+        for (auto &t : workers) t.join();
+        for (auto s : wstreams) (void)hipStreamDestroy(s);
         for (auto &kv : reqs)
             if (kv.second.labels) (void)hipFree(kv.second.labels);
     }
 
-    // one batch: admission, union, run, completion; returns requests completed
-    int32_t step() {
-        std::vector<int64_t> take;
+    // Admission (mu held): the longest queue prefix whose footprint fits the
+    // budget beside the running batches and whose entries fit the cap; with
+    // nothing running, at least one request.  False when none is admitted.
+    bool admit(Job &job) {
         int64_t bytes = 0, entries = 0;
+        const int64_t room = budget - resident;
         while (!queue.empty()) {
             const Req &r = reqs[queue.front()];
-            if (!take.empty() && (r.solo || bytes + r.bytes > budget || entries + r.nnz > max_entries)) break;
+            if (!job.ids.empty() && (r.solo || bytes + r.bytes > room || entries + r.nnz > max_entries)) break;
+            if (job.ids.empty() && inflight > 0 && r.bytes > room) break;  // waits for memory
             bytes += r.bytes;
             entries += r.nnz;
-            take.push_back(queue.front());
+            job.ids.push_back(queue.front());
             queue.pop_front();
             if (r.solo) break;
         }
-        if (take.empty()) return 0;
-        const int64_t G = (int64_t)take.size();
+        if (job.ids.empty()) return false;
+        for (int64_t id : job.ids) {
+            Req &r = reqs[id];
+            r.state = 3;
+            job.in.push_back(r);
+        }
+        job.bytes = bytes;
+        resident += bytes;
+        ++inflight;
+        return true;
+    }
+
+    // end of a batch (mu held): its memory goes back to the budget
+    void retire(const Job &job) {
+        resident -= job.bytes;
+        --inflight;
+        cv_idle.notify_all();
+    }
+
+    // every request of the job fails with (code, m) (mu held)
+    void fail_job(const Job &job, plm_status code, const std::string &m) {
+        for (int64_t id : job.ids) {
+            Req &r = reqs[id];
+            r.state = 2;
+            r.err = code;
+            r.msg = m;
+        }
+        unreported += (int64_t)job.ids.size();
+        retire(job);
+    }
+
+    // Runs one admitted batch on stream s (mu not held).
+    void run_job(Job &job, hipStream_t s) {
+        const int64_t G = (int64_t)job.ids.size();
         std::vector<int64_t> nbase(G + 1, 0), ebase(G + 1, 0);
         bool weighted = false;
         for (int64_t g = 0; g < G; ++g) {
-            const Req &r = reqs[take[g]];
+            const Req &r = job.in[g];
             nbase[g + 1] = nbase[g] + r.n;
             ebase[g + 1] = ebase[g] + r.nnz;
             weighted = weighted || r.w != nullptr;
         }
         const int64_t N = nbase[G], E = ebase[G];
         auto fail_all = [&](plm_status code, const std::string &m) {
-            for (int64_t id : take) {
-                Req &r = reqs[id];
-                r.state = 2;
-                r.err = code;
-                r.msg = m;
-            }
+            std::lock_guard<std::mutex> lk(mu);
+            fail_job(job, code, m);
         };
-        if (N >= (1LL << 31)) {
-            fail_all(PLM_E_BUDGET, "admitted requests exceed 2^31 nodes");
-            return 0;
-        }
+        if (N >= (1LL << 31)) return fail_all(PLM_E_BUDGET, "admitted requests exceed 2^31 nodes");
         int64_t *off = nullptr;
         int32_t *col = nullptr, *w = nullptr;
         bool ok = hipMalloc(&off, (size_t)(N + 1) * 8) == hipSuccess &&
@@ -126,58 +184,52 @@ struct plm_server {
             if (off) (void)hipFree(off);
             if (col) (void)hipFree(col);
             if (w) (void)hipFree(w);
-            fail_all(PLM_E_NOMEM, "device allocation of the batch failed");
-            return 0;
+            return fail_all(PLM_E_NOMEM, "device allocation of the batch failed");
         }
-        resident = bytes;
         try {
             for (int64_t g = 0; g < G; ++g) {
-                const Req &r = reqs[take[g]];
+                const Req &r = job.in[g];
                 hipMemcpyKind kind = r.mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-                if (r.n > 0) HIPCHK(hipMemcpyAsync(off + nbase[g], r.off, (size_t)r.n * 8, kind, st));
-                if (r.nnz > 0) HIPCHK(hipMemcpyAsync(col + ebase[g], r.col, (size_t)r.nnz * 4, kind, st));
-                if (r.nnz > 0 && r.w) HIPCHK(hipMemcpyAsync(w + ebase[g], r.w, (size_t)r.nnz * 4, kind, st));
+                if (r.n > 0) HIPCHK(hipMemcpyAsync(off + nbase[g], r.off, (size_t)r.n * 8, kind, s));
+                if (r.nnz > 0) HIPCHK(hipMemcpyAsync(col + ebase[g], r.col, (size_t)r.nnz * 4, kind, s));
+                if (r.nnz > 0 && r.w) HIPCHK(hipMemcpyAsync(w + ebase[g], r.w, (size_t)r.nnz * 4, kind, s));
                 int64_t m = r.n > r.nnz ? r.n : r.nnz;
                 if (m > 0)
-                    hipLaunchKernelGGL(k_union_fix, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, st, off + nbase[g],
+                    hipLaunchKernelGGL(k_union_fix, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, off + nbase[g],
                                        r.n, ebase[g], col + ebase[g], r.nnz, (int32_t)nbase[g],
                                        weighted ? w + ebase[g] : nullptr, (weighted && !r.w) ? 1 : 0);
             }
-            hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, off + N, E);
+            hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, off + N, E);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipStreamSynchronize(s));
         } catch (const Error &e) {
             (void)hipFree(off);
             (void)hipFree(col);
             if (w) (void)hipFree(w);
-            fail_all(e.code, e.msg);
-            resident = 0;
-            return 0;
+            return fail_all(e.code, e.msg);
         }
         plm_ctx *ctx = nullptr;
-        plm_status rc = plm_internal_batch_adopt(&ctx, G, nbase.data(), E, off, col, w, st, &opt);
+        plm_status rc = plm_internal_batch_adopt(&ctx, G, nbase.data(), E, off, col, w, s, &opt);
         if (rc == PLM_E_GRAPH && G > 1) {
-            // an invalid graph refuses the whole union: rerun these requests one
-            // per batch, in their order, so that only the invalid ones fail
+            // an invalid graph refuses the whole union: these requests go back to
+            // the front of the queue, in their order, to run one per batch, so
+            // that only the invalid ones fail
+            std::lock_guard<std::mutex> lk(mu);
             for (int64_t g = G - 1; g >= 0; --g) {
-                reqs[take[g]].solo = true;
-                queue.push_front(take[g]);
+                Req &r = reqs[job.ids[g]];
+                r.solo = true;
+                r.state = 0;
+                queue.push_front(job.ids[g]);
             }
-            resident = 0;
-            return 0;
+            retire(job);
+            return;
         }
-        if (rc != PLM_OK) {
-            fail_all(rc, plm_last_error(nullptr));
-            resident = 0;
-            return 0;
-        }
+        if (rc != PLM_OK) return fail_all(rc, plm_last_error(nullptr));
         int32_t *canon = nullptr;
         if (hipMalloc(&canon, (size_t)(N > 0 ? N : 1) * 4) != hipSuccess) {
             (void)hipGetLastError();
             plm_destroy(ctx);
-            fail_all(PLM_E_NOMEM, "device allocation of the labels failed");
-            resident = 0;
-            return 0;
+            return fail_all(PLM_E_NOMEM, "device allocation of the labels failed");
         }
         std::vector<double> q(G);
         std::vector<int32_t> lv(G);
@@ -186,43 +238,107 @@ struct plm_server {
             std::string m = plm_last_error(ctx);
             plm_destroy(ctx);
             (void)hipFree(canon);
-            fail_all(rc, m);
-            resident = 0;
-            return 0;
+            return fail_all(rc, m);
         }
         plm_destroy(ctx);
+        std::vector<int32_t *> lab(G, nullptr);
         for (int64_t g = 0; g < G; ++g) {
-            Req &r = reqs[take[g]];
-            r.q = q[g];
-            r.levels = lv[g];
-            if (hipMalloc(&r.labels, (size_t)(r.n > 0 ? r.n : 1) * 4) != hipSuccess ||
-                (r.n > 0 && hipMemcpyAsync(r.labels, canon + nbase[g], (size_t)r.n * 4, hipMemcpyDeviceToDevice, st) !=
-                                hipSuccess)) {
+            const int64_t n = job.in[g].n;
+            if (hipMalloc(&lab[g], (size_t)(n > 0 ? n : 1) * 4) != hipSuccess ||
+                (n > 0 && hipMemcpyAsync(lab[g], canon + nbase[g], (size_t)n * 4, hipMemcpyDeviceToDevice, s) !=
+                              hipSuccess)) {
                 (void)hipGetLastError();
-                if (r.labels) (void)hipFree(r.labels);
-                r.labels = nullptr;
+                if (lab[g]) (void)hipFree(lab[g]);
+                lab[g] = nullptr;
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(canon);
+        std::lock_guard<std::mutex> lk(mu);
+        for (int64_t g = 0; g < G; ++g) {
+            Req &r = reqs[job.ids[g]];
+            if (!lab[g]) {
                 r.state = 2;
                 r.err = PLM_E_NOMEM;
                 r.msg = "device allocation or copy of the result failed";
+                continue;
             }
+            r.state = 1;
+            r.labels = lab[g];
+            r.q = q[g];
+            r.levels = lv[g];
+            ++completed;
         }
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(canon);
-        int32_t done = 0;
-        for (int64_t id : take) {
-            Req &r = reqs[id];
-            if (r.state == 0) {
-                r.state = 1;
-                ++done;
-            }
-            r.off = nullptr;
-            r.col = nullptr;
-            r.w = nullptr;
-        }
-        completed += done;
+        unreported += G;
         ++batches;
-        resident = 0;
-        return done;
+        retire(job);
+    }
+
+    // run_job, with anything thrown outside its own error paths (host
+    // allocation) failing the batch instead of escaping
+    void run_job_safe(Job &job, hipStream_t s) {
+        try {
+            run_job(job, s);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu);
+            fail_job(job, PLM_E_NOMEM, "host allocation failed while running the batch");
+        }
+    }
+
+    void worker(hipStream_t s) {
+        for (;;) {
+            Job job;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_job.wait(lk, [&] { return stop || !jobs.empty(); });
+                if (jobs.empty()) return;  // stopping, and nothing left to run
+                job = std::move(jobs.front());
+                jobs.pop_front();
+            }
+            run_job_safe(job, s);
+        }
+    }
+
+    void start_workers() {
+        for (int32_t i = 0; i < max_inflight; ++i) {
+            hipStream_t s = nullptr;
+            HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));  // default priority
+            wstreams.push_back(s);
+        }
+        for (int32_t i = 0; i < max_inflight; ++i) {
+            hipStream_t s = wstreams[i];
+            workers.emplace_back([this, s] { worker(s); });
+        }
+    }
+
+    // One step; *reported = requests completed or failed since the last report.
+    void step(int32_t *reported) {
+        if (max_inflight == 1) {
+            Job job;
+            bool got;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                got = admit(job);
+            }
+            if (got) run_job_safe(job, st);
+        } else {
+            std::lock_guard<std::mutex> lk(mu);
+            Job job;
+            if (inflight < max_inflight && admit(job)) {
+                jobs.push_back(std::move(job));
+                cv_job.notify_one();
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        if (reported) *reported = (int32_t)unreported;
+        unreported = 0;
+    }
+
+    void wait_idle(int32_t *reported) {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_idle.wait(lk, [&] { return inflight == 0; });
+        if (reported) *reported = (int32_t)unreported;
+        unreported = 0;
     }
 };
 
@@ -248,11 +364,11 @@ plm_status server_guard(plm_server *s, F f) {
 
 extern "C" {
 
-plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t max_batch_entries, void *hip_stream,
-                             const plm_options *opt) {
+plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t max_batch_entries,
+                             int32_t max_inflight, void *hip_stream, const plm_options *opt) {
     if (!out) return PLM_E_ARG;
     *out = nullptr;
-    if (hbm_budget_bytes <= 0 || max_batch_entries <= 0) return PLM_E_ARG;
+    if (hbm_budget_bytes <= 0 || max_batch_entries <= 0 || max_inflight < 1 || max_inflight > 16) return PLM_E_ARG;
     plm_options o;
     plm_default_options(&o);
     if (opt) o = *opt;
@@ -263,6 +379,18 @@ plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t
     s->opt = o;
     s->budget = hbm_budget_bytes;
     s->max_entries = max_batch_entries;
+    s->max_inflight = max_inflight;
+    // a stream capture in a worker would make the client thread's synchronous
+    // copies on the legacy stream fail: concurrent batches launch one by one
+    if (max_inflight > 1) s->opt.graph_sweeps = 0;
+    if (max_inflight > 1) {
+        try {
+            s->start_workers();
+        } catch (...) {
+            delete s;
+            return PLM_E_DEVICE;
+        }
+    }
     *out = s;
     return PLM_OK;
 }
@@ -291,6 +419,7 @@ plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_
         r.mem_kind = mem_kind;
         r.bytes = footprint(n, nnz, weights != nullptr);
         if (r.bytes > s->budget) throw Error{PLM_E_BUDGET, "the request alone exceeds the HBM budget"};
+        std::lock_guard<std::mutex> lk(s->mu);
         int64_t id = s->next_id++;
         s->reqs[id] = r;
         s->queue.push_back(id);
@@ -299,52 +428,70 @@ plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_
 }
 
 plm_status plm_server_step(plm_server *s, int32_t *completed_out) {
-    return server_guard(s, [&] {
-        int32_t c = s->step();
-        if (completed_out) *completed_out = c;
-    });
+    return server_guard(s, [&] { s->step(completed_out); });
+}
+
+plm_status plm_server_wait(plm_server *s, int32_t *completed_out) {
+    return server_guard(s, [&] { s->wait_idle(completed_out); });
 }
 
 plm_status plm_server_result(plm_server *s, int64_t request_id, int32_t *labels, int32_t mem_kind, double *q_out,
                              int32_t *levels_out, int32_t *ready_out) {
     return server_guard(s, [&] {
-        auto it = s->reqs.find(request_id);
-        if (it == s->reqs.end()) throw Error{PLM_E_ARG, "unknown or already fetched request"};
-        plm_server::Req &r = it->second;
-        if (ready_out) *ready_out = r.state != 0 ? 1 : 0;
-        if (r.state == 0) return;
-        if (r.state == 2) {
-            Error e{r.err, r.msg};
+        plm_server::Req r;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            auto it = s->reqs.find(request_id);
+            if (it == s->reqs.end()) throw Error{PLM_E_ARG, "unknown or already fetched request"};
+            const int state = it->second.state;
+            if (ready_out) *ready_out = (state == 1 || state == 2) ? 1 : 0;
+            if (state == 0 || state == 3) return;
+            if (state == 1 && mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE)
+                throw Error{PLM_E_ARG, "bad mem_kind"};
+            r = it->second;  // done or failed: no worker touches it any more
             s->reqs.erase(it);
-            throw e;
         }
-        if (mem_kind != PLM_MEM_HOST && mem_kind != PLM_MEM_DEVICE) throw Error{PLM_E_ARG, "bad mem_kind"};
-        if (labels && r.n > 0)
-            HIPCHK(hipMemcpyAsync(labels, r.labels, (size_t)r.n * 4,
-                                  mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s->st));
-        HIPCHK(hipStreamSynchronize(s->st));
+        if (r.state == 2) throw Error{r.err, r.msg};
+        plm_status rc = PLM_OK;
+        std::string m;
+        try {
+            if (labels && r.n > 0)
+                HIPCHK(hipMemcpyAsync(labels, r.labels, (size_t)r.n * 4,
+                                      mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                      s->st));
+            HIPCHK(hipStreamSynchronize(s->st));
+        } catch (const Error &e) {
+            rc = e.code;
+            m = e.msg;
+        }
+        (void)hipFree(r.labels);
+        if (rc != PLM_OK) throw Error{rc, m};
         if (q_out) *q_out = r.q;
         if (levels_out) *levels_out = r.levels;
-        (void)hipFree(r.labels);
-        s->reqs.erase(it);
     });
 }
 
 plm_status plm_server_info(plm_server *s, plm_server_info_t *out) {
     return server_guard(s, [&] {
         if (!out) throw Error{PLM_E_ARG, "out is NULL"};
+        std::lock_guard<std::mutex> lk(s->mu);
+        int64_t running = 0;
+        for (const auto &kv : s->reqs) running += kv.second.state == 3 ? 1 : 0;
         out->queued = (int64_t)s->queue.size();
         out->completed = s->completed;
         out->batches = s->batches;
-        out->held_results = (int64_t)s->reqs.size() - (int64_t)s->queue.size();
+        out->held_results = (int64_t)s->reqs.size() - (int64_t)s->queue.size() - running;
         out->budget_bytes = s->budget;
+        out->inflight = s->inflight;
+        out->running = running;
+        out->resident_bytes = s->resident;
     });
 }
 
 void plm_server_destroy(plm_server *s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->st);
-    delete s;
+    delete s;  // the workers finish the batches they hold, then join
 }
 
 const char *plm_server_last_error(const plm_server *s) { return s ? s->err.c_str() : ""; }

@@ -122,10 +122,12 @@ def test_server_queue_needs_no_gpu(built):
     import graphgen
     import paper_1304_4453_amd as P
     s = ctypes.c_void_p()
-    assert P.plm_server_create(None, 1 << 30, 1 << 20, None, None) == P.PLM_E_ARG
-    assert P.plm_server_create(ctypes.byref(s), 0, 1 << 20, None, None) == P.PLM_E_ARG
+    assert P.plm_server_create(None, 1 << 30, 1 << 20, 1, None, None) == P.PLM_E_ARG
+    assert P.plm_server_create(ctypes.byref(s), 0, 1 << 20, 1, None, None) == P.PLM_E_ARG
+    for k in (0, 17):   # max_inflight outside [1, 16]
+        assert P.plm_server_create(ctypes.byref(s), 1 << 30, 1 << 20, k, None, None) == P.PLM_E_ARG
     seq = P.default_options(schedule=P.PLM_SCHEDULE_SEQUENTIAL)
-    assert P.plm_server_create(ctypes.byref(s), 1 << 30, 1 << 20, None, ctypes.byref(seq)) == P.PLM_E_ARG
+    assert P.plm_server_create(ctypes.byref(s), 1 << 30, 1 << 20, 1, None, ctypes.byref(seq)) == P.PLM_E_ARG
     g = graphgen.disjoint_cliques(2, 4)
     srv = P.Server(1 << 30)
     a = srv.submit(g.off, g.col, g.w)
@@ -144,6 +146,9 @@ def test_server_queue_needs_no_gpu(built):
         srv.result(99)
     assert e.value.status == P.PLM_E_ARG
     assert P.plm_server_step(None, None) == P.PLM_E_ARG
+    assert P.plm_server_wait(None, None) == P.PLM_E_ARG
+    i = srv.info()
+    assert i.inflight == 0 and i.running == 0 and i.resident_bytes == 0
 
 
 def test_pack_batch_is_the_disjoint_union(built):

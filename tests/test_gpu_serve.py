@@ -1,10 +1,13 @@
 """The request server (plm_server_*): every completed request carries exactly
 the oracle's run on its graph (labels, Q bit for bit, levels), whatever it was
-batched with; admission keeps submission order under the HBM budget and the
-per-batch entry cap; an invalid graph fails alone."""
+batched with and whatever ran beside it; admission keeps submission order under
+the HBM budget and the per-batch entry cap; an invalid graph fails alone; with
+several batches in flight, requests that arrive while a batch runs start beside
+it, within the budget."""
 from __future__ import annotations
 
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -146,3 +149,90 @@ def test_server_device_inputs_and_invalid_request(P):
 def test_server_empty_step(P):
     with P.Server(1 << 30) as srv:
         assert srv.step() == 0 and srv.info().batches == 0
+
+
+def _drain_async(srv, ids, budget):
+    """Steps and polls until every request is ready; checks the budget and
+    returns (results, most batches seen in flight at once)."""
+    out, most = {}, 0
+    for _ in range(100000):
+        srv.step()
+        info = srv.info()
+        assert info.resident_bytes <= budget
+        most = max(most, info.inflight)
+        for i in ids:
+            if i not in out:
+                res = srv.result(i)
+                if res[0]:
+                    out[i] = res
+        if len(out) == len(ids):
+            break
+        time.sleep(0.001)
+    srv.wait()
+    assert len(out) == len(ids) and srv.info().inflight == 0
+    return out, most
+
+
+def test_server_async_results_match_oracle(P):
+    _say("server: three batches in flight")
+    gs = _graphs() + [graphgen.rmat(13, 16, seed=23, weighted=False)]
+    fp = [8 * (g.n + 1) + (8 if g.w is not None else 4) * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
+    budget = max(fp) + 1   # the largest request fits only alone: several batches, some waiting for memory
+    assert sum(fp) > budget
+    with P.Server(budget, max_inflight=3) as srv:
+        ids = [srv.submit(g.off, g.col, g.w) for g in gs]
+        out, _ = _drain_async(srv, ids, budget)
+        assert srv.info().completed == len(gs) and srv.info().batches >= 2
+    for g, i in zip(gs, ids):
+        _check(g, out[i])
+
+
+def test_server_async_admits_beside_a_running_batch(P):
+    """A large request runs; small ones submitted meanwhile start in batches of
+    their own beside it (a second batch is in flight before the first ends)."""
+    _say("server: arrivals during a running batch")
+    big = graphgen.rmat(18, 16, seed=24, weighted=False)
+    small = [graphgen.planted_partition_1000(seed=s) for s in range(6, 9)] + [graphgen.rmat(10, 16, seed=25)]
+    budget = 1 << 36
+    with P.Server(budget, max_inflight=2) as srv:
+        ids = [srv.submit(big.off, big.col, big.w)]
+        srv.step()
+        ids += [srv.submit(g.off, g.col, g.w) for g in small]
+        srv.step()
+        seen = srv.info().inflight
+        out, most = _drain_async(srv, ids, budget)
+        assert max(seen, most) == 2
+    for g, i in zip([big] + small, ids):
+        _check(g, out[i])
+
+
+def test_server_async_invalid_request_and_device_inputs(P):
+    import torch
+    _say("server: async invalid request")
+    gs = _graphs()[:4]
+    d = torch.device("cuda:0")
+    bad = graphgen.disjoint_cliques(2, 3)
+    bad_col = bad.col.copy()
+    bad_col[0] = 2
+    with P.Server(1 << 34, max_inflight=4) as srv:
+        ids, keep = [], []
+        for k, g in enumerate(gs):
+            if k == 2:
+                bad_id = srv.submit(bad.off, bad_col, bad.w)
+            t = [torch.from_numpy(x).to(d) for x in (g.off, g.col)] + \
+                [None if g.w is None else torch.from_numpy(g.w).to(d)]
+            keep.append(t)
+            ids.append(srv.submit(t[0], t[1], t[2], n=g.n, nnz=g.nnz))
+        for _ in range(100000):
+            srv.step()
+            if srv.info().queued == 0 and srv.info().inflight == 0:
+                break
+            time.sleep(0.001)
+        srv.wait()
+        with pytest.raises(P.PLMError) as e:
+            srv.result(bad_id)
+        assert e.value.status == P.PLM_E_GRAPH
+        for g, i in zip(gs, ids):
+            lab = torch.empty(max(g.n, 1), dtype=torch.int32, device=d)
+            ready, _, q, lv = srv.result(i, lab)
+            _check(g, (ready, lab.cpu().numpy()[: g.n], q, lv))
