@@ -90,7 +90,7 @@ struct HubArrays {
 
 constexpr int64_t kHubInsChunk = 2048;  // entries per hub chunk workgroup
 constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
-constexpr int64_t kHubBucketTarget = 2048;
+constexpr int64_t kHubBucketTarget = 1024;  // entries per hash bucket (one agg workgroup each)
 constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol < 2^31) take one workgroup
 
 // ev (may be null): per kernel group (lane, wavefront, workgroup, one-workgroup

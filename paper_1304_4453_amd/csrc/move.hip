@@ -483,8 +483,13 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
 //     the class's other moves (k_reduce_apply).
 constexpr int kHubThreads = 256;
 constexpr int kHubPerThread = (int)(kHubInsChunk / kHubThreads);
-constexpr int kAggSlots = 4096;    // LDS table of a bucket workgroup (~2048 entries expected)
-constexpr int kAggMaxKeys = 3072;  // new keys allowed per pass (load <= 0.75 + one claim per thread)
+constexpr int kAggBits = 11;
+constexpr int kAggSlots = 1 << kAggBits;  // LDS table of a bucket workgroup (~1024 entries expected)
+// new keys allowed per pass: each thread claims at most one slot past the
+// limit before it stops, so at most kAggMaxKeys + kHubThreads < kAggSlots
+// slots are ever taken and every probe ends
+constexpr int kAggMaxKeys = 1536;
+static_assert(kAggMaxKeys + 256 < kAggSlots, "agg table must never fill");
 constexpr int kAggTile = 512;      // chunks whose segments are flattened at once (52 KB of LDS: 3 per CU)
 constexpr int32_t kHubPending = -2;  // class position of a partitioned hub until its reduce
 constexpr int kAggBatch = 4;       // staged entries per thread loaded together
@@ -492,7 +497,7 @@ constexpr int kAggBatch = 4;       // staged entries per thread loaded together
 __device__ __forceinline__ uint32_t hub_bucket(int32_t x, int pbits) {
     return pbits == 0 ? 0u : ((uint32_t)x * 2654435769u) >> (32 - pbits);
 }
-__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - 12); }
+__device__ __forceinline__ uint32_t agg_slot(int32_t x) { return ((uint32_t)x * 0x85EBCA6Bu) >> (32 - kAggBits); }
 __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }

@@ -83,6 +83,7 @@ struct plm_server {
         int64_t bytes = 0;
     };
     hipStream_t st = nullptr;
+    hipStream_t io_st = nullptr;  // reads of device requests at submission (created on first use)
     plm_options opt;
     int64_t budget = 0, max_entries = 0;
     int32_t max_inflight = 1;
@@ -106,6 +107,7 @@ struct plm_server {
         cv_job.notify_all();
         for (auto &t : workers) t.join();
         for (auto s : wstreams) (void)hipStreamDestroy(s);
+        if (io_st) (void)hipStreamDestroy(io_st);
         for (auto &kv : reqs)
             if (kv.second.labels) (void)hipFree(kv.second.labels);
     }
@@ -406,8 +408,11 @@ plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_
             ends[0] = offsets[0];
             ends[1] = offsets[n];
         } else {
-            HIPCHK(hipMemcpy(&ends[0], offsets, 8, hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(&ends[1], offsets + n, 8, hipMemcpyDeviceToHost));
+            // on a stream of the server's own, not the legacy default stream
+            if (!s->io_st) HIPCHK(hipStreamCreateWithFlags(&s->io_st, hipStreamNonBlocking));
+            HIPCHK(hipMemcpyAsync(&ends[0], offsets, 8, hipMemcpyDeviceToHost, s->io_st));
+            HIPCHK(hipMemcpyAsync(&ends[1], offsets + n, 8, hipMemcpyDeviceToHost, s->io_st));
+            HIPCHK(hipStreamSynchronize(s->io_st));
         }
         if (ends[0] != 0 || ends[1] != nnz) throw Error{PLM_E_GRAPH, "offsets[0] must be 0 and offsets[n] = nnz"};
         plm_server::Req r;
