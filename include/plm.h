@@ -92,10 +92,12 @@ typedef struct {
                              Rows of the wavefront and workgroup bins whose vol(u)
                              reaches 2^31 also take the hub path. */
     int32_t timing;       /* 1: time the move-decide launches with HIP events */
-    int32_t timing_kernel; /* with timing: 0 = every kernel of every class step (six
-                              events per step); k = 1..5 = only kernel k (lane,
-                              wavefront, workgroup, one-workgroup hub, partitioned
-                              hub): two events per step, so timing costs less */
+    int32_t timing_kernel; /* with timing: 0 = every kernel group of every class step;
+                              k = 1..5 = only group k (lane, wavefront, workgroup,
+                              one-workgroup hub, partitioned hub), so timing costs
+                              less.  Each group is timed by events attached to its
+                              launches (the partitioned group's two launches each
+                              by their own pair) */
     int32_t refine;        /* 1: PLMR (Algorithm 4): after each prolongation, a move
                               phase on that level starting from the prolonged
                               communities (same colour classes and sweep rule);

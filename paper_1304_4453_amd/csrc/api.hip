@@ -20,7 +20,9 @@ thread_local std::string g_create_error;
 // batched runs: rebuild the class buckets when the graphs still sweeping hold
 // less than this fraction of the planned entries
 constexpr double kReplanFraction = 0.7;
-constexpr size_t kEv = 10;  // timing events per class step: start and stop of 5 kernel groups
+// timing events per class step: start and stop of the 5 kernel groups (the
+// partitioned group's part launch), then start and stop of the agg launch
+constexpr size_t kEv = 12;
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -579,6 +581,11 @@ struct plm_ctx {
                     if (((mask >> b) & 1u) && ran[b])
                         HIPCHK(hipEventElapsedTime(&t[b], events[kEv * (size_t)c + 2 * b],
                                                    events[kEv * (size_t)c + 2 * b + 1]));
+                if (((mask >> 4) & 1u) && ran[4]) {  // + the agg launch
+                    float ta = 0;
+                    HIPCHK(hipEventElapsedTime(&ta, events[kEv * (size_t)c + 10], events[kEv * (size_t)c + 11]));
+                    t[4] += ta;
+                }
                 for (int b = 0; b < 3; ++b) bin_t[b] += t[b];
                 bin_t[3] += t[3] + t[4];
                 sgl_t += t[3];

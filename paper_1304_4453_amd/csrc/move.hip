@@ -721,7 +721,9 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     }
 }
 
-template <bool LP>
+// (WK only names the instantiation after the level's weight kind, so that
+// profiles tell the input level from the coarse ones)
+template <int WK, bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays ha, int64_t blk0, int force_wide) {
     __shared__ int32_t tk[kAggSlots];
     __shared__ int64_t tv[kAggSlots];
@@ -900,10 +902,13 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
         dispatch(k_hub_single<WK, LP>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), st, t0(3), t1(3), g, ms,
                  ha, cr.sgl_base, fw);
     if (cr.red_count > 0 && (groups & 16u)) {
-        dispatch(k_hub_part<WK, LP>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), st, t0(4), (hipEvent_t) nullptr,
-                 g, ms, ha, cr.ins_base);
-        dispatch(k_hub_agg<LP>, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), st, (hipEvent_t) nullptr, t1(4), ms,
-                 ha, cr.agg_base, fw);
+        // the partitioned group is timed per launch (events 8, 9 and 10, 11), so
+        // that the gap between its two dependent launches is not counted
+        const bool t4 = ev && ((ev_mask >> 4) & 1u);
+        dispatch(k_hub_part<WK, LP>, dim3((unsigned)cr.ins_blocks), dim3(kHubThreads), st, t4 ? ev[8] : nullptr,
+                 t4 ? ev[9] : nullptr, g, ms, ha, cr.ins_base);
+        dispatch(k_hub_agg<WK, LP>, dim3((unsigned)cr.agg_blocks), dim3(kHubThreads), st, t4 ? ev[10] : nullptr,
+                 t4 ? ev[11] : nullptr, ms, ha, cr.agg_base, fw);
     }
 }
 
