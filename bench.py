@@ -60,6 +60,9 @@ def roofline(st, level=0):
             "algorithmic_bytes_per_sweep": by[k] / sweeps, "kernel_ms_per_sweep": ms[k] / sweeps,
             "all_decide_GBs": st["decide_bytes"][level] / (st["decide_ms"][level] * 1e6)
             if st["decide_ms"][level] else 0.0,
+            # every decide kernel of every level and executed sweep together
+            "all_levels_decide_GBs": sum(st["decide_bytes"]) / (sum(st["decide_ms"]) * 1e6)
+            if sum(st["decide_ms"]) else 0.0,
             "kernels": KERNELS, "kernel_ms": ms, "kernel_bytes": by}
 
 
@@ -88,6 +91,43 @@ def counter_traffic(kernel):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_info():
+    """CPU model, logical cores and RAM of the host the benchmark runs on."""
+    model, mem_kb = platform.processor() or platform.machine(), None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem_kb = int(line.split()[1])
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "logical_cores": os.cpu_count(), "ram_gib": None if mem_kb is None else round(mem_kb / 2**20, 1)}
+
+
+def copy_peak(torch):
+    """Device-to-device copy bandwidth (read + write bytes per second) of a
+    4 GiB buffer, median of 5 copies timed with events on torch's stream."""
+    x = torch.empty(1 << 30, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = sorted(ts)[len(ts) // 2]
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * (4 << 30), "GBs": 2 * (4 << 30) / (ms * 1e6)}
 
 
 def make_graph(name):
@@ -167,9 +207,8 @@ def cpu_baseline(gr, ctx_state, budget_s=15.0):
         k, e, dt = timed(int(min(n, 50_000 * budget_s / max(dt, 1e-3))))
     return {"value": (e / 2) / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"level-0 sweep-1 move decisions (singleton communities) of the {k} movable nodes of a random "
-                      f"contiguous node-id range ({e} CSR entries) of the same graph; oracle single-threaded on "
-                      f"{platform.processor() or platform.machine()}",
-            "seconds": dt}
+                      f"contiguous node-id range ({e} CSR entries) of the same graph; oracle single-threaded",
+            "seconds": dt, "host": host_info()}
 
 
 BATCH_DESC = ("4,096 SBM graphs, n log-uniform in [100, 100000], k = max(2, n/100) near-equal blocks, "
@@ -558,6 +597,7 @@ def main():
     sweep_ms = sum(st["sweep_ms"])
     roof["timing"] = ("HIP events attached to each move-decide dispatch (hipExtLaunchKernelGGL) on the library's "
                       "stream, in one instrumented step before the timed steps; the timed steps run without events")
+    roof["measured_copy"] = copy_peak(torch)
     if args.workload == "rmat26":
         tr = counter_traffic(roof["kernel"])
         if tr is not None:
