@@ -70,30 +70,51 @@ __device__ __forceinline__ int row_kind(const int64_t *off, int32_t v) {
     return d <= kLaneRow ? 0 : (d <= kWaveRow ? 1 : 2);
 }
 
-// Queue push, aggregated over the active lanes of the wavefront: one counter
-// atomic per (wavefront, queue kind).
-__device__ __forceinline__ void jp_push(const JpQ &Q, int set, int32_t v, const int64_t *off) {
-    const int k = row_kind(off, v);
+// A long row (rare) enters the multi-workgroup queue: a slot, and one work
+// item per kHubChunk entries.
+__device__ __forceinline__ void push_long(const JpQ &Q, int set, int32_t v, const int64_t *off) {
+    int32_t slot = atomicAdd(&Q.cnt[set * 4 + 2], 1);
+    Q.q[set][2][slot] = v;
+    int32_t nc = (int32_t)((off[v + 1] - off[v] + kHubChunk - 1) / kHubChunk);
+    int32_t c0 = atomicAdd(&Q.cnt[set * 4 + 3], nc);
+    for (int32_t c = 0; c < nc; ++c) Q.cq[set][c0 + c] = ((int64_t)slot << 32) | c;
+}
+
+// Queue pushes of a wavefront: each active lane offers v[j] where want[j].
+// All of the wavefront's pushes of one queue kind are ranked by ballots and
+// take their slots with a single counter atomic (the early rounds push
+// millions of nodes, and per-push atomics on the two counters would
+// serialise).  Order within a frontier does not matter: it is an independent
+// set.  Call with every lane of the loop iteration active.
+template <int NV>
+__device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (&v)[NV], const bool (&want)[NV],
+                                          const int64_t *off) {
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
+    int kind[NV];
+    int32_t rank[NV];
+    int32_t tot0 = 0, tot1 = 0;
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        uint64_t m = __ballot(k == kk);
-        if (k == kk) {
-            int leader = __ffsll((unsigned long long)m) - 1;
-            int32_t base = 0;
-            if (lane == leader) base = atomicAdd(&Q.cnt[set * 4 + kk], (int32_t)__popcll(m));
-            base = __shfl(base, leader);
-            Q.q[set][kk][base + (int32_t)__popcll(m & lt)] = v;
-        }
+    for (int j = 0; j < NV; ++j) {
+        kind[j] = want[j] ? row_kind(off, v[j]) : 3;
+        const uint64_t m0 = __ballot(kind[j] == 0), m1 = __ballot(kind[j] == 1);
+        rank[j] = kind[j] == 0 ? tot0 + (int32_t)__popcll(m0 & lt) : tot1 + (int32_t)__popcll(m1 & lt);
+        tot0 += (int32_t)__popcll(m0);
+        tot1 += (int32_t)__popcll(m1);
+        if (kind[j] == 2) push_long(Q, set, v[j], off);
     }
-    // long rows (rare): a queue slot, and one work item per kHubChunk entries
-    if (k == 2) {
-        int32_t slot = atomicAdd(&Q.cnt[set * 4 + 2], 1);
-        Q.q[set][2][slot] = v;
-        int32_t nc = (int32_t)((off[v + 1] - off[v] + kHubChunk - 1) / kHubChunk);
-        int32_t c0 = atomicAdd(&Q.cnt[set * 4 + 3], nc);
-        for (int32_t c = 0; c < nc; ++c) Q.cq[set][c0 + c] = ((int64_t)slot << 32) | c;
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+    int32_t b0 = 0, b1 = 0;
+    if (lane == leader) {
+        if (tot0) b0 = atomicAdd(&Q.cnt[set * 4 + 0], tot0);
+        if (tot1) b1 = atomicAdd(&Q.cnt[set * 4 + 1], tot1);
+    }
+    b0 = __shfl(b0, leader);
+    b1 = __shfl(b1, leader);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        if (kind[j] == 0) Q.q[set][0][b0 + rank[j]] = v[j];
+        else if (kind[j] == 1) Q.q[set][1][b1 + rank[j]] = v[j];
     }
 }
 
@@ -107,9 +128,10 @@ __device__ __forceinline__ void wave_max_colour(const JpQ &Q, int32_t c) {
 
 __global__ void k_jp_seed(GraphView g, const int32_t *pending, int32_t *colour, JpQ Q) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= g.n) return;
-    colour[u] = -1;
-    if (pending[u] == 0) jp_push(Q, 0, (int32_t)u, g.off);
+    const int32_t v[1] = {(int32_t)(u < g.n ? u : 0)};
+    const bool want[1] = {u < g.n && pending[u] == 0};
+    if (u < g.n) colour[u] = -1;
+    wave_push<1>(Q, 0, v, want, g.off);
 }
 
 __device__ __forceinline__ void count_coloured(const JpQ &Q, int64_t c) {
@@ -210,12 +232,10 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             maxc = cu + 1 > maxc ? cu + 1 : maxc;
             ++coloured;
         }
-        int32_t left[4];
+        bool rel[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) left[j] = (v[j] != u && !hi[j]) ? atomicSub(&pending[v[j]], 1) : 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (left[j] == 1) jp_push(Q, nxt, v[j], g.off);
+        for (int j = 0; j < 4; ++j) rel[j] = (v[j] != u && !hi[j]) && atomicSub(&pending[v[j]], 1) == 1;
+        wave_push<4>(Q, nxt, v, rel, g.off);
     }
     count_coloured(Q, coloured);
     wave_max_colour(Q, maxc);
@@ -259,13 +279,11 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             atomicMax(&Q.cnt[12], f + 1);
             atomicAdd(&Q.cnt[13], 1);
         }
-        int32_t left[kPer];
+        bool rel[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
-            left[j] = (v[j] != u && !((hi >> j) & 1u)) ? atomicSub(&pending[v[j]], 1) : 0;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            if (left[j] == 1) jp_push(Q, nxt, v[j], g.off);
+            rel[j] = (v[j] != u && !((hi >> j) & 1u)) && atomicSub(&pending[v[j]], 1) == 1;
+        wave_push<kPer>(Q, nxt, v, rel, g.off);
     }
     // several workgroups per node: each work item is kHubChunk entries of one
     // long row; its colours go into an LDS bitmap that is OR-ed into the row's
@@ -281,8 +299,8 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
         const int64_t c1 = c0 + kHubChunk < e1 ? c0 + kHubChunk : e1;
         for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
         __syncthreads();
-        int32_t v[4], c[4], left[4];
-        bool hi[4];
+        int32_t v[4], c[4];
+        bool hi[4], rel[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int64_t e = c0 + q * kCT + threadIdx.x;
@@ -293,13 +311,12 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             c[q] = hi[q] ? colour[v[q]] : kWin;
-            left[q] = (v[q] != u && !hi[q]) ? atomicSub(&pending[v[q]], 1) : 0;
+            rel[q] = (v[q] != u && !hi[q]) && atomicSub(&pending[v[q]], 1) == 1;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 4; ++q)
             if (c[q] < kWin) atomicOr(&bbm[c[q] >> 5], 1u << (c[q] & 31));
-            if (left[q] == 1) jp_push(Q, nxt, v[q], g.off);
-        }
+        wave_push<4>(Q, nxt, v, rel, g.off);
         __syncthreads();
         for (int i = threadIdx.x; i < kWinWords; i += kCT)
             if (bbm[i]) atomicOr(&Q.bitmap[(int64_t)j * kWinWords + i], bbm[i]);
