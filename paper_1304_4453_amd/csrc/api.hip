@@ -330,7 +330,7 @@ struct plm_ctx {
         drop_graph();  // the captured sweep belongs to the previous plan
         LevelData &l = L();
         GraphView g = l.view();
-        int64_t nkeys = (int64_t)ncol * 4 + 1;
+        int64_t nkeys = (int64_t)ncol * 8 + 1;
         dev_free(bstart_dev);
         bstart_dev = dev_alloc<int64_t>(nkeys + 1);
         HIPCHK(hipMemsetAsync(dcnt + 7, 0, 5 * 8, st));
@@ -343,17 +343,19 @@ struct plm_ctx {
             hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 7);
         HIPCHK(hipMemcpyAsync(hbuf + 8, dcnt + 7, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        active_nodes = l.n > 0 ? bstart[(size_t)ncol * 4] : 0;
+        // first position of bin b of class c (b = 4: the next class)
+        auto bs = [&](int64_t c, int b) { return bstart[8 * c + 2 * b]; };
+        active_nodes = l.n > 0 ? bstart[(size_t)ncol * 8] : 0;
         active_entries = l.nnz - hbuf[8];
         for (int b = 0; b < 4; ++b) {
             bin_entries[b] = hbuf[9 + b];
             bin_nodes[b] = 0;
-            for (int32_t c = 0; c < ncol; ++c) bin_nodes[b] += bstart[4 * c + b + 1] - bstart[4 * c + b];
+            for (int32_t c = 0; c < ncol; ++c) bin_nodes[b] += bs(c, b + 1) - bs(c, b);
         }
         // hubs: degrees to the host, then per-hub table and block layout
         classes.assign(ncol, ClassRange());
         int64_t H = 0;
-        for (int32_t c = 0; c < ncol; ++c) H += bstart[4 * c + 4] - bstart[4 * c + 3];
+        for (int32_t c = 0; c < ncol; ++c) H += bs(c, 4) - bs(c, 3);
         std::vector<int64_t> deg(H > 0 ? H : 1), pos;
         pos.reserve(H);
         if (H > 0) {
@@ -362,7 +364,7 @@ struct plm_ctx {
             int64_t *ddeg = (int64_t *)scr.get(H * 8);
             int64_t o = 0;
             for (int32_t c = 0; c < ncol; ++c) {
-                int64_t b = bstart[4 * c + 3], cnt = bstart[4 * c + 4] - b;
+                int64_t b = bs(c, 3), cnt = bs(c, 4) - b;
                 if (cnt > 0) launch_hub_degrees(g, class_nodes, vol, b, cnt, ddeg + o, hub_u + o, st);
                 for (int64_t i = 0; i < cnt; ++i) pos.push_back(b + i);
                 o += cnt;
@@ -383,9 +385,10 @@ struct plm_ctx {
         for (int32_t c = 0; c < ncol; ++c) {
             ClassRange &cr = classes[c];
             for (int b = 0; b < 4; ++b) {
-                cr.begin[b] = bstart[4 * c + b];
-                cr.count[b] = bstart[4 * c + b + 1] - bstart[4 * c + b];
+                cr.begin[b] = bs(c, b);
+                cr.count[b] = bs(c, b + 1) - bs(c, b);
             }
+            cr.quad = bstart[8 * c + 3] - bstart[8 * c + 2];
             cr.hub_first = hg;
             cr.hub_count = cr.count[3];
             cr.sgl_base = (int64_t)shub.size();

@@ -12,8 +12,9 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
 // colour[n]; returns the number of classes.  host_counters: 8 pinned int32.
 int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int schedule, int32_t *colour,
                         Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st);
-// Sorts nodes by (colour, degree bin) into class_nodes; bstart_dev[4*ncol+2]
-// receives bucket starts (bucket 4c+b = bin b of class c; bucket 4*ncol holds
+// Sorts nodes by (colour, degree bin, short row first) into class_nodes;
+// bstart_dev[8*ncol+2] receives bucket starts (bucket 8c+2b+s = bin b of class
+// c, s = 1 for the wavefront-bin rows longer than kQuadRow; bucket 8*ncol holds
 // nodes that cannot move).
 // bin_entries[4]: CSR entries of the movable nodes of each bin (added to).
 // Nodes of the wave and block bins whose vol(u) does not fit 32 bits go to the
@@ -22,6 +23,10 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
 void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
                    int64_t b1, int64_t b2, int32_t *class_nodes, int64_t *bstart_dev,
                    unsigned long long *bin_entries, Scratch &scr, hipStream_t st, const uint8_t *keep = nullptr);
+
+// wavefront-bin rows up to this length take 16 lanes per node (four nodes per
+// wavefront) instead of a whole wavefront
+constexpr int64_t kQuadRow = 64;
 
 // ---- move.hip
 struct MoveState {
@@ -58,6 +63,7 @@ __device__ __forceinline__ int64_t node_wl(const MoveState &ms, int32_t u) {
 // the host copy of the bucket starts.
 struct ClassRange {
     int64_t begin[4], count[4];  // per bin
+    int64_t quad = 0;            // the first quad nodes of the wavefront bin have rows of at most kQuadRow
     // hubs of this class in the level's hub arrays
     int64_t hub_first = 0, hub_count = 0;
     int64_t ins_blocks = 0, agg_blocks = 0;

@@ -86,8 +86,10 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
 }
 
 // ------------------------------------------------------------------ bucketing
-// key(u) = colour(u) * 4 + bin(u); nodes without a non-loop neighbour get the
-// sentinel key ncol * 4 (they can never move).
+// key(u) = (colour(u) * 4 + bin(u)) * 2 + sub(u), sub = 1 for wavefront-bin
+// rows longer than kQuadRow (so that the short ones come first in their
+// bucket); nodes without a non-loop neighbour get the sentinel key ncol * 8
+// (they can never move).
 __global__ void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
                               int64_t b1, int64_t b2, const uint8_t *keep, uint32_t *keys, int32_t *vals,
                               unsigned long long *bin_entries) {
@@ -98,7 +100,8 @@ __global__ void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *co
         bool active = (d > 1 || (d == 1 && g.col[e0] != u)) && (!keep || keep[g.gid[u]]);
         uint32_t bin = d <= b0 ? 0u : (d <= b1 ? 1u : (d <= b2 ? 2u : 3u));
         if ((bin == 1u || bin == 2u) && vol[u] > (int64_t)INT32_MAX) bin = 3u;
-        keys[u] = active ? (uint32_t)colour[u] * 4u + bin : (uint32_t)ncol * 4u;
+        const uint32_t sub = (bin == 1u && d > kQuadRow) ? 1u : 0u;
+        keys[u] = active ? ((uint32_t)colour[u] * 4u + bin) * 2u + sub : (uint32_t)ncol * 8u;
         vals[u] = (int32_t)u;
         if (active) cnt[bin] = d;
     }
@@ -130,7 +133,7 @@ void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour
     void *rs = scr.get(radix_scratch_bytes(n));
     hipLaunchKernelGGL(k_bucket_keys, dim3((unsigned)cdiv(n, kThreads)), dim3(kThreads), 0, st, g, vol, colour, ncol,
                        b0, b1, b2, keep, k, v, bin_entries);
-    int64_t nkeys = (int64_t)ncol * 4 + 1;  // including the sentinel
+    int64_t nkeys = (int64_t)ncol * 8 + 1;  // including the sentinel
     radix_sort_u32_i32(&k, &v, &ka, &va, n, ceil_log2((uint64_t)nkeys), rs, st);
     hipLaunchKernelGGL(k_bucket_bounds, dim3((unsigned)cdiv(n + 1, kThreads)), dim3(kThreads), 0, st, k, n, nkeys,
                        bstart_dev);

@@ -341,6 +341,89 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
     count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
 }
 
+// ------------------------------------------------------------------ 16 lanes per node
+// Short rows of the wavefront bin (at most kQuadRow entries): four nodes per
+// wavefront, each with 16 lanes and a table of at most 128 slots, so that a row
+// of ~20 entries no longer leaves most of a wavefront idle.  The body is
+// uniform over the wavefront: a group without a node (past the end, or
+// inactive in label propagation) folds an empty row.
+constexpr int kQuadLanes = 16;
+constexpr int kQuadCap = 2 * (int)kQuadRow;
+
+template <typename G>
+__device__ __forceinline__ void quad_argmax(G &s, int32_t &x) {
+#pragma unroll
+    for (int d = kQuadLanes / 2; d >= 1; d >>= 1) {
+        G os = shfl_xor_g<G>(s, d);
+        int32_t ox = __shfl_xor(x, d);
+        if (os > s || (os == s && ox < x)) { s = os; x = ox; }
+    }
+}
+__device__ __forceinline__ int64_t quad_sum(int64_t v) {
+#pragma unroll
+    for (int d = kQuadLanes / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+template <typename G, bool LP>
+__device__ __forceinline__ void quad_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
+                                          const int64_t *volC, int32_t &best_x, bool &move, int64_t &ncand,
+                                          uint64_t hv) {
+    G bs = neg_inf<G>();
+    int32_t bx = kNone;
+    const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, (int)(threadIdx.x % kQuadLanes), kQuadLanes, vu, S, K, volC, true, bs,
+                               bx, ncand, hv);
+    quad_argmax<G>(bs, bx);
+    best_x = bx;
+    move = bx != kNone && bs > K;
+}
+
+template <int WK, bool LP>
+__global__ __launch_bounds__(256) void k_decide_quad(GraphView g, MoveState ms, int64_t begin, int64_t count,
+                                                     int force_wide) {
+    constexpr int kGroups = 256 / kQuadLanes;
+    __shared__ int32_t tk[kGroups][kQuadCap];
+    __shared__ int32_t tv[kGroups][kQuadCap];
+    const int grp = threadIdx.x / kQuadLanes, l = threadIdx.x % kQuadLanes;
+    for (int s = l; s < kQuadCap; s += kQuadLanes) { tk[grp][s] = kEmpty; tv[grp][s] = 0; }
+    wave_sync();
+    int64_t ncand = 0;
+    for (int64_t b0 = (int64_t)blockIdx.x * kGroups; b0 < count; b0 += (int64_t)gridDim.x * kGroups) {
+        const int64_t i = b0 + grp, pos = begin + i;
+        const bool has = i < count;
+        const int32_t u = has ? ms.class_nodes[pos] : 0;
+        const bool act = has && (!LP || ms.active[u]);
+        if (LP && has && !act && l == 0) ms.move_to[pos] = -1;
+        const int64_t e0 = act ? g.off[u] : 0, e1 = act ? g.off[u + 1] : 0;
+        int bits = ceil_log2_dev(2 * (e1 - e0));
+        bits = bits < 6 ? 6 : bits;  // rows of at most kQuadRow entries: at most kQuadCap slots
+        const int32_t D = act ? ms.zeta[u] : -1;
+        int64_t wD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, l, kQuadLanes, tk[grp], tv[grp], bits);
+        wD = quad_sum(wD);
+        wave_sync();
+        const int64_t vu = act ? ms.vol[u] : 0;
+        const int64_t base = (LP || !act) ? 0 : ms.volC[D] - vu;
+        const int64_t S_u = act ? node_S(ms, u) : 0;
+        const uint64_t hv = (LP && act) ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
+        int32_t bx;
+        bool mv;
+        if (act && (force_wide || vu > node_wl(ms, u)))
+            quad_eval<i128, LP>(tk[grp], tv[grp], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC,
+                                bx, mv, ncand, hv);
+        else
+            quad_eval<int64_t, LP>(tk[grp], tv[grp], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv,
+                                   ncand, hv);
+        if (act && l == 0) ms.move_to[pos] = mv ? bx : -1;
+        if (LP && act) {
+            if (mv) lp_activate(g, ms.active, u, e0, e1, l, kQuadLanes);
+            else if (l == 0) ms.active[u] = 0;
+        }
+        wave_sync();
+    }
+    count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
+}
+
 // ------------------------------------------------------------------ workgroup per node
 constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
@@ -889,9 +972,19 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
         dispatch(k_decide_lane<WK, LP>, dim3((unsigned)cdiv(cr.count[0], 256)), dim3(256), st, t0(0), t1(0), g, ms,
                  cr.begin[0], cr.count[0], fw);
     if (cr.count[1] > 0 && (groups & 2u)) {
-        int64_t blocks = cdiv(cr.count[1], 4);
-        dispatch(k_decide_wave<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), st, t0(1), t1(1),
-                 g, ms, cr.begin[1], cr.count[1], fw);
+        // short rows (16 lanes per node) first, then a wavefront per node; the
+        // group's start event goes on its first launch, the stop on its last
+        const int64_t nq = cr.quad, nw = cr.count[1] - cr.quad;
+        if (nq > 0) {
+            int64_t blocks = cdiv(nq, 256 / kQuadLanes);
+            dispatch(k_decide_quad<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), st, t0(1),
+                     nw > 0 ? (hipEvent_t) nullptr : t1(1), g, ms, cr.begin[1], nq, fw);
+        }
+        if (nw > 0) {
+            int64_t blocks = cdiv(nw, 4);
+            dispatch(k_decide_wave<WK, LP>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), st,
+                     nq > 0 ? (hipEvent_t) nullptr : t0(1), t1(1), g, ms, cr.begin[1] + nq, nw, fw);
+        }
     }
     if (cr.count[2] > 0 && (groups & 4u)) {
         int64_t blocks = cr.count[2];
