@@ -142,33 +142,50 @@ void batch_canonical(int64_t n0, const int32_t *gid0, const int64_t *gbase0, con
 
 // Per-graph modularity parts on the input level: I2[g] and sum of vol(C)^2 of
 // graph g (two words, carry handled), with labels given as global keys.
+// A thread sums its kC entries per graph (rows of a graph are contiguous, so
+// they rarely span two); a wavefront whose lanes all end in one graph adds its
+// total with a single atomic, since a graph's counter would otherwise take an
+// atomic per row of a graph with millions of entries.
 template <int WK>
 __global__ __launch_bounds__(kBT) void k_batch_intra(GraphView g, const int32_t *gid0, const int32_t *key,
                                                       unsigned long long *I2) {
     constexpr int kC = 16;
-    int64_t e0 = ((int64_t)blockIdx.x * kBT + threadIdx.x) * kC;
-    if (e0 >= g.nnz) return;
-    int64_t e1 = e0 + kC < g.nnz ? e0 + kC : g.nnz;
-    int64_t r = row_of(g.off, g.n, e0);
-    int64_t rend = g.off[r + 1];
-    int32_t kr = key[r];
+    const int64_t e0 = ((int64_t)blockIdx.x * kBT + threadIdx.x) * kC;
+    int32_t gcur = -1;
     int64_t s = 0;
-    for (int64_t e = e0; e < e1; ++e) {
-        while (e >= rend) {
-            if (s) atomicAdd(&I2[gid0[r]], (unsigned long long)s);
-            s = 0;
-            ++r;
-            rend = g.off[r + 1];
-            kr = key[r];
-        }
-        int32_t v = g.col[e];
-        if (key[v] == kr) {
-            int64_t x = wload<WK>(g.w, e);
-            if (v == r) x *= g.diag_mult;
-            s += x;
+    if (e0 < g.nnz) {
+        const int64_t e1 = e0 + kC < g.nnz ? e0 + kC : g.nnz;
+        int64_t r = row_of(g.off, g.n, e0);
+        int64_t rend = g.off[r + 1];
+        int32_t kr = key[r];
+        gcur = gid0[r];
+        for (int64_t e = e0; e < e1; ++e) {
+            while (e >= rend) {
+                ++r;
+                rend = g.off[r + 1];
+                kr = key[r];
+                const int32_t gr = gid0[r];
+                if (gr != gcur) {
+                    if (s) atomicAdd(&I2[gcur], (unsigned long long)s);
+                    s = 0;
+                    gcur = gr;
+                }
+            }
+            int32_t v = g.col[e];
+            if (key[v] == kr) {
+                int64_t x = wload<WK>(g.w, e);
+                if (v == r) x *= g.diag_mult;
+                s += x;
+            }
         }
     }
-    if (s) atomicAdd(&I2[gid0[r]], (unsigned long long)s);
+    const int32_t g0 = __shfl(gcur, 0);
+    if (__all(gcur == g0)) {
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        if (lane_id() == 0 && s) atomicAdd(&I2[g0], (unsigned long long)s);
+    } else if (s) {
+        atomicAdd(&I2[gcur], (unsigned long long)s);
+    }
 }
 __global__ void k_batch_vol(int64_t n0, const int32_t *key, const int64_t *vol0, int64_t *volL) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

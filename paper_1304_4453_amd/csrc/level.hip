@@ -90,12 +90,15 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
 // rows longer than kQuadRow (so that the short ones come first in their
 // bucket); nodes without a non-loop neighbour get the sentinel key ncol * 8
 // (they can never move).
-__global__ void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *colour, int32_t ncol, int64_t b0,
-                              int64_t b1, int64_t b2, const uint8_t *keep, uint32_t *keys, int32_t *vals,
-                              unsigned long long *bin_entries) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Grid-stride, with the per-bin entry counts summed per workgroup: one atomic
+// per (workgroup, bin) instead of one per wavefront, on four counters.
+__global__ __launch_bounds__(kThreads) void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *colour,
+                                                          int32_t ncol, int64_t b0, int64_t b1, int64_t b2,
+                                                          const uint8_t *keep, uint32_t *keys, int32_t *vals,
+                                                          unsigned long long *bin_entries) {
+    __shared__ unsigned long long red[kThreads / kWave][4];
     int64_t cnt[4] = {0, 0, 0, 0};
-    if (u < g.n) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
         int64_t e0 = g.off[u], d = g.off[u + 1] - e0;
         bool active = (d > 1 || (d == 1 && g.col[e0] != u)) && (!keep || keep[g.gid[u]]);
         uint32_t bin = d <= b0 ? 0u : (d <= b1 ? 1u : (d <= b2 ? 2u : 3u));
@@ -103,13 +106,19 @@ __global__ void k_bucket_keys(GraphView g, const int64_t *vol, const int32_t *co
         const uint32_t sub = (bin == 1u && d > kQuadRow) ? 1u : 0u;
         keys[u] = active ? ((uint32_t)colour[u] * 4u + bin) * 2u + sub : (uint32_t)ncol * 8u;
         vals[u] = (int32_t)u;
-        if (active) cnt[bin] = d;
+        if (active) cnt[bin] += d;
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         int64_t c = cnt[b];
         for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
-        if (lane_id() == 0 && c) atomicAdd(&bin_entries[b], (unsigned long long)c);
+        if (lane_id() == 0) red[threadIdx.x / kWave][b] = (unsigned long long)c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long c = 0;
+        for (int w = 0; w < kThreads / kWave; ++w) c += red[w][threadIdx.x];
+        if (c) atomicAdd(&bin_entries[threadIdx.x], c);
     }
 }
 
@@ -131,8 +140,9 @@ void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour
     uint32_t *k = (uint32_t *)scr.get(n * 4), *ka = (uint32_t *)scr.get(n * 4);
     int32_t *v = (int32_t *)scr.get(n * 4), *va = (int32_t *)scr.get(n * 4);
     void *rs = scr.get(radix_scratch_bytes(n));
-    hipLaunchKernelGGL(k_bucket_keys, dim3((unsigned)cdiv(n, kThreads)), dim3(kThreads), 0, st, g, vol, colour, ncol,
-                       b0, b1, b2, keep, k, v, bin_entries);
+    const int64_t kb = cdiv(n, kThreads);
+    hipLaunchKernelGGL(k_bucket_keys, dim3((unsigned)(kb < 4096 ? kb : 4096)), dim3(kThreads), 0, st, g, vol, colour,
+                       ncol, b0, b1, b2, keep, k, v, bin_entries);
     int64_t nkeys = (int64_t)ncol * 8 + 1;  // including the sentinel
     radix_sort_u32_i32(&k, &v, &ka, &va, n, ceil_log2((uint64_t)nkeys), rs, st);
     hipLaunchKernelGGL(k_bucket_bounds, dim3((unsigned)cdiv(n + 1, kThreads)), dim3(kThreads), 0, st, k, n, nkeys,

@@ -919,8 +919,9 @@ __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveS
 // ------------------------------------------------------------------ apply
 // The moves of class positions [begin, begin + count): workgroups [0, nred)
 // reduce and apply the class's partitioned hubs (red_hub[red0 ..]), the rest
-// apply every other decided move.  Partitioned hubs' positions hold
-// kHubPending and are skipped by the latter.
+// (grid-stride) apply every other decided move and add their count with one
+// atomic per workgroup.  Partitioned hubs' positions hold kHubPending and are
+// skipped by the latter.
 template <bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveState ms, HubArrays ha, int64_t red0,
                                                               int64_t nred, int64_t begin, int64_t count) {
@@ -928,15 +929,22 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
         hub_reduce_apply<LP>(g, ms, ha, ha.red_hub[red0 + blockIdx.x]);
         return;
     }
-    int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x;
+    __shared__ int64_t red[kHubThreads / kWave];
+    const int64_t nblk = (int64_t)gridDim.x - nred;
     int64_t moved = 0;
-    if (i < count) {
+    for (int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x; i < count; i += nblk * kHubThreads) {
         int64_t pos = begin + i;
         int32_t X = ms.move_to[pos];
-        if (X >= 0) moved = apply_move(ms, ms.class_nodes[pos], X);
+        if (X >= 0) moved += apply_move(ms, ms.class_nodes[pos], X);
     }
     moved = wave_sum(moved);
-    if (lane_id() == 0 && moved) atomicAdd(ms.moves_dev, (unsigned long long)moved);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = moved;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t m = 0;
+        for (int w = 0; w < kHubThreads / kWave; ++w) m += red[w];
+        if (m) atomicAdd(ms.moves_dev, (unsigned long long)m);
+    }
 }
 
 // row length of each hub, negated when vol(u) does not fit 32 bits
@@ -1030,7 +1038,8 @@ void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, 
                   hipStream_t st) {
     const int64_t begin = cr.begin[0], count = cr.begin[3] + cr.count[3] - cr.begin[0];
     if (count <= 0) return;
-    const int64_t blocks = cr.red_count + cdiv(count, kHubThreads);
+    const int64_t ab = cdiv(count, kHubThreads);
+    const int64_t blocks = cr.red_count + (ab < 2048 ? ab : 2048);
     if (ms.active)
         hipLaunchKernelGGL(k_reduce_apply<true>, dim3((unsigned)blocks), dim3(kHubThreads), 0, st, g, ms, ha,
                            cr.red_base, cr.red_count, begin, count);
