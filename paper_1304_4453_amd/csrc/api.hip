@@ -85,31 +85,27 @@ __global__ void k_export_w(GraphView g, int64_t *out) {
 }
 
 // rows holding a self-loop entry (rows are strictly ascending: binary search)
-__global__ void k_count_loops(GraphView g, unsigned long long *cnt) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t c = 0;
-    if (u < g.n) {
+__global__ __launch_bounds__(256) void k_count_loops(GraphView g, unsigned long long *cnt) {
+    unsigned long long c = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
         int64_t lo = g.off[u], hi = g.off[u + 1];
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
             int32_t x = g.col[mid];
-            if (x == u) { c = 1; break; }
+            if (x == u) { ++c; break; }
             if (x < u) lo = mid + 1; else hi = mid;
         }
     }
-    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
-    if (lane_id() == 0 && c) atomicAdd(cnt, (unsigned long long)c);
+    block_count_add(cnt, c);
 }
 
-__global__ void k_count_loop_only(GraphView g, unsigned long long *cnt) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t c = 0;
-    if (u < g.n) {
+__global__ __launch_bounds__(256) void k_count_loop_only(GraphView g, unsigned long long *cnt) {
+    unsigned long long c = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = g.off[u + 1] - g.off[u];
-        c = (d == 1 && g.col[g.off[u]] == u) ? 1 : 0;
+        c += (d == 1 && g.col[g.off[u]] == u) ? 1 : 0;
     }
-    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
-    if (lane_id() == 0 && c) atomicAdd(cnt, (unsigned long long)c);
+    block_count_add(cnt, c);
 }
 
 }  // namespace
@@ -242,7 +238,11 @@ struct plm_ctx {
         GraphView g = l.view();
         launch_volumes(g, vol, dcnt + 5, dcnt + 6, st);
         HIPCHK(hipMemsetAsync(dcnt + 12, 0, 8, st));
-        if (l.n > 0) hipLaunchKernelGGL(k_count_loops, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 12);
+        if (l.n > 0) {
+            const int64_t nb = cdiv(l.n, 256);
+            hipLaunchKernelGGL(k_count_loops, dim3((unsigned)(nb < kCountGrid ? nb : kCountGrid)), dim3(256), 0, st, g,
+                               dcnt + 12);
+        }
         HIPCHK(hipMemcpyAsync(hbuf, dcnt + 5, 16, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hbuf + 2, dcnt + 12, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -340,7 +340,8 @@ struct plm_ctx {
         if (l.n > 0) HIPCHK(hipMemcpyAsync(bstart.data(), bstart_dev, (nkeys + 1) * 8, hipMemcpyDeviceToHost, st));
         // active entries = nnz minus rows made of a single self-loop
         if (l.n > 0)
-            hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)cdiv(l.n, 256)), dim3(256), 0, st, g, dcnt + 7);
+            hipLaunchKernelGGL(k_count_loop_only, dim3((unsigned)(cdiv(l.n, 256) < kCountGrid ? cdiv(l.n, 256) : kCountGrid)),
+                               dim3(256), 0, st, g, dcnt + 7);
         HIPCHK(hipMemcpyAsync(hbuf + 8, dcnt + 7, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         // first position of bin b of class c (b = 4: the next class)

@@ -20,6 +20,8 @@
 // colours, instead of walking a row one dependent load after another.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "level.h"
 
 namespace plm {
@@ -348,11 +350,11 @@ __global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, i
     }
 }
 
-__global__ void k_count_hubs(const int64_t *off, int64_t n, int32_t *cnt) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t c = (u < n && off[u + 1] - off[u] > kWaveRow) ? 1 : 0;
-    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
-    if (lane_id() == 0 && c) atomicAdd(cnt, (int32_t)c);
+__global__ __launch_bounds__(kCT) void k_count_hubs(const int64_t *off, int64_t n, unsigned long long *cnt) {
+    unsigned long long c = 0;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x)
+        c += (off[u + 1] - off[u] > kWaveRow) ? 1 : 0;
+    block_count_add(cnt, c);
 }
 
 // Sequential schedule: class = rank in descending priority.  Keys are the
@@ -388,12 +390,16 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     }
     // count rows longer than kWaveRow to size the hub bitmaps
     scr.reserve(4096);
-    int32_t *hc = (int32_t *)scr.get(8);
+    unsigned long long *hc = (unsigned long long *)scr.get(8);
     HIPCHK(hipMemsetAsync(hc, 0, 8, st));
-    hipLaunchKernelGGL(k_count_hubs, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, g.off, n, hc);
-    HIPCHK(hipMemcpyAsync(host_counters, hc, 4, hipMemcpyDeviceToHost, st));
+    const int64_t hb = cdiv(n, kCT);
+    hipLaunchKernelGGL(k_count_hubs, dim3((unsigned)(hb < kCountGrid ? hb : kCountGrid)), dim3(kCT), 0, st, g.off, n,
+                       hc);
+    HIPCHK(hipMemcpyAsync(host_counters, hc, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int64_t nhub = host_counters[0];
+    uint64_t nhub_u = 0;
+    std::memcpy(&nhub_u, host_counters, 8);
+    int64_t nhub = (int64_t)nhub_u;
     // pending counts, 9 queues, counters, hub bitmaps
     // work items of long rows in one set: at most nnz / kHubChunk + nhub
     const int64_t ncap = g.nnz / kHubChunk + nhub + 1;

@@ -18,9 +18,11 @@ constexpr int kChunk = 16;  // entries per thread in entry-parallel kernels
 template <int WK>
 __global__ __launch_bounds__(kThreads) void k_vol(GraphView g, int64_t *vol, unsigned long long *S,
                                                   unsigned long long *maxvol) {
-    int64_t e0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * kChunk;
     int64_t tot = 0;
-    if (e0 < g.nnz) {
+    const int64_t nchunks = cdiv_dev(g.nnz, kChunk);
+    for (int64_t ch = (int64_t)blockIdx.x * kThreads + threadIdx.x; ch < nchunks;
+         ch += (int64_t)gridDim.x * kThreads) {
+        const int64_t e0 = ch * kChunk;
         int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
         int64_t r = row_of(g.off, g.n, e0);
         int64_t rend = g.off[r + 1];
@@ -43,16 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_vol(GraphView g, int64_t *vol, uns
         else if (acc) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)acc);
         tot += acc;
     }
-    // block sum of tot -> S
-    __shared__ int64_t red[kThreads / kWave];
-    for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d);
-    if (lane_id() == 0) red[threadIdx.x / kWave] = tot;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t s = 0;
-        for (int i = 0; i < kThreads / kWave; ++i) s += red[i];
-        if (s) atomicAdd(S, (unsigned long long)s);
-    }
+    block_count_add(S, (unsigned long long)tot);  // S: one atomic per workgroup
 }
 
 __global__ void k_max_vol(const int64_t *vol, int64_t n, unsigned long long *maxvol) {
@@ -72,7 +65,8 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
     HIPCHK(hipMemsetAsync(S_dev, 0, sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(maxvol_dev, 0, sizeof(unsigned long long), st));
     if (g.nnz > 0) {
-        dim3 grid((unsigned)cdiv(cdiv(g.nnz, kChunk), kThreads));
+        const int64_t vb = cdiv(cdiv(g.nnz, kChunk), kThreads);
+        dim3 grid((unsigned)(vb < 4 * kCountGrid ? vb : 4 * kCountGrid));
         switch (g.wkind) {
             case 0: hipLaunchKernelGGL(k_vol<0>, grid, dim3(kThreads), 0, st, g, vol, S_dev, maxvol_dev); break;
             case 1: hipLaunchKernelGGL(k_vol<1>, grid, dim3(kThreads), 0, st, g, vol, S_dev, maxvol_dev); break;

@@ -58,12 +58,29 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ int64_t cdiv_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 // smallest b with 2^b >= x (x >= 1)
 __device__ __forceinline__ int ceil_log2_dev(int64_t x) {
     return x <= 1 ? 0 : 64 - __clzll((unsigned long long)(x - 1));
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Adds c of every thread of a 256-thread workgroup to *dst with one atomic
+// (counters that every wavefront would otherwise hit one by one).  Call from
+// every thread of the workgroup.
+__device__ __forceinline__ void block_count_add(unsigned long long *dst, unsigned long long c) {
+    __shared__ unsigned long long red[4];
+    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
+    if (lane_id() == 0) red[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = red[0] + red[1] + red[2] + red[3];
+        if (t) atomicAdd(dst, t);
+    }
+}
+constexpr int64_t kCountGrid = 2048;  // workgroups of the grid-stride counting kernels
 
 // ------------------------------------------------------------------ graph of one level
 struct GraphView {
