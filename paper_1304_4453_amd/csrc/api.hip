@@ -1011,11 +1011,10 @@ struct plm_ctx {
             // communities of each graph: ranks of community ids at the graph bounds
             batch_relabel(zeta, l.n, l.gid, nullptr, bflag, bnewid, nullptr, bscan, st);
             launch_gather_i64(bnewid, l.gbase, A + 1, bgath, st);
-            launch_gather_i64(l.off, l.gbase, A + 1, bgath + A + 1, st);
-            gath.resize(2 * (A + 1));
-            HIPCHK(hipMemcpyAsync(gath.data(), bgath, 2 * (A + 1) * 8, hipMemcpyDeviceToHost, st));
+            gath.resize(A + 1);
+            HIPCHK(hipMemcpyAsync(gath.data(), bgath, (A + 1) * 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            const int64_t *nid = gath.data(), *eoff = gath.data() + A + 1;
+            const int64_t *nid = gath.data();
             std::vector<int64_t> abase(A + 1);
             HIPCHK(hipMemcpyAsync(abase.data(), l.gbase, (A + 1) * 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -1023,7 +1022,6 @@ struct plm_ctx {
             keep.assign(A, 0);
             nbase.assign(1, 0);
             nact.clear();
-            int64_t nnz_kept = 0;
             for (int64_t a = 0; a < A; ++a) {
                 int64_t ka = nid[a + 1] - nid[a], na = abase[a + 1] - abase[a];
                 int64_t g = act_h[a];
@@ -1035,7 +1033,6 @@ struct plm_ctx {
                     keep[a] = 1;
                     nact.push_back(g);
                     nbase.push_back(nbase.back() + ka);
-                    nnz_kept += eoff[a + 1] - eoff[a];
                 }
             }
             record_level(nid[A] - nid[0], t1 - t0, t2 - t1, 0, moves);
@@ -1057,8 +1054,7 @@ struct plm_ctx {
             LevelData nl;
             nl.n = k;
             try {
-                nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, bkeep,
-                                           nnz_kept);
+                nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, bkeep);
                 nl.wkind = 2;
                 nl.diag_mult = 1;
                 nl.gbase = dev_alloc<int64_t>(A2 + 1);

@@ -57,35 +57,85 @@ int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t 
 // ------------------------------------------------------------------ contraction
 // key = (pi(u) << b) | pi(v), value = entry weight (self-loops times diag_mult,
 // so the coarse diagonal is again "doubled").
-// Rows of graphs that are not kept (batched runs) get the key 1 << 2b, which
-// sorts after every real key.
+// Merged before the sort: each thread turns its kChunk consecutive entries
+// into keys (pi(u) << b) | pi(v) with weights, merges equal keys in registers
+// (within a row many neighbours fall into the same coarse node), and its
+// workgroup writes the merged entries contiguously after a global cursor (one
+// atomic per workgroup step).  Their order does not matter: the sort that
+// follows orders them completely and equal keys' weights are summed.  Rows of
+// graphs that are not kept (batched runs) are left out.
+constexpr uint64_t kNoKey = ~0ULL;  // keys are below 2^(2b) <= 2^62
 template <int WK>
-__global__ __launch_bounds__(kT) void k_contract_keys(GraphView g, const int32_t *pi, int b, const uint8_t *keep,
-                                                      uint64_t *keys, int64_t *vals) {
-    int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * kChunk;
-    if (e0 >= g.nnz) return;
-    int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
-    int64_t r = row_of(g.off, g.n, e0);
-    int64_t rend = g.off[r + 1];
-    bool kept = !keep || keep[g.gid[r]];
-    uint64_t pr = kept ? (uint64_t)pi[r] : 0;
-    for (int64_t e = e0; e < e1; ++e) {
-        while (e >= rend) {
-            ++r;
-            rend = g.off[r + 1];
-            kept = !keep || keep[g.gid[r]];
-            pr = kept ? (uint64_t)pi[r] : 0;
+__global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_t *pi, int b, const uint8_t *keep,
+                                                       uint64_t *keys, int64_t *vals, unsigned long long *cursor) {
+    __shared__ int32_t wsum[kT / kWave];
+    __shared__ unsigned long long sbase;
+    const int64_t nchunks = cdiv_dev(g.nnz, kChunk);
+    for (int64_t c0 = (int64_t)blockIdx.x * kT; c0 < nchunks; c0 += (int64_t)gridDim.x * kT) {  // workgroup-uniform
+        const int64_t ch = c0 + threadIdx.x;
+        uint64_t K[kChunk];
+        int64_t W[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) { K[j] = kNoKey; W[j] = 0; }
+        if (ch < nchunks) {
+            const int64_t e0 = ch * kChunk, e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
+            int64_t r = row_of(g.off, g.n, e0);
+            int64_t rend = g.off[r + 1];
+            bool kept = !keep || keep[g.gid[r]];
+            uint64_t pr = kept ? (uint64_t)pi[r] : 0;
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j) {
+                const int64_t e = e0 + j;
+                if (e < e1) {
+                    while (e >= rend) {
+                        ++r;
+                        rend = g.off[r + 1];
+                        kept = !keep || keep[g.gid[r]];
+                        pr = kept ? (uint64_t)pi[r] : 0;
+                    }
+                    if (kept) {
+                        int32_t v = g.col[e];
+                        int64_t x = wload<WK>(g.w, e);
+                        if (v == r) x *= g.diag_mult;
+                        K[j] = (pr << b) | (uint64_t)pi[v];
+                        W[j] = x;
+                    }
+                }
+            }
+            // equal keys into their first occurrence
+#pragma unroll
+            for (int a = 0; a < kChunk; ++a)
+#pragma unroll
+                for (int c = a + 1; c < kChunk; ++c)
+                    if (K[c] != kNoKey && K[c] == K[a]) { W[a] += W[c]; K[c] = kNoKey; }
         }
-        if (!kept) {
-            keys[e] = 1ULL << (2 * b);
-            vals[e] = 0;
-            continue;
+        int32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) cnt += K[j] != kNoKey;
+        // workgroup exclusive prefix of cnt
+        int32_t inc = cnt;
+        for (int d = 1; d < kWave; d <<= 1) {
+            int32_t y = __shfl_up(inc, d);
+            if (lane_id() >= d) inc += y;
         }
-        int32_t v = g.col[e];
-        int64_t x = wload<WK>(g.w, e);
-        if (v == r) x *= g.diag_mult;
-        keys[e] = (pr << b) | (uint64_t)pi[v];
-        vals[e] = x;
+        if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = inc;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int w = 0; w < kT / kWave; ++w) {
+            if (w < (int)(threadIdx.x / kWave)) before += wsum[w];
+            total += wsum[w];
+        }
+        if (threadIdx.x == 0) sbase = total ? atomicAdd(cursor, (unsigned long long)total) : 0ULL;
+        __syncthreads();
+        int64_t pos = (int64_t)sbase + before + (inc - cnt);
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j)
+            if (K[j] != kNoKey) {
+                keys[pos] = K[j];
+                vals[pos] = W[j];
+                ++pos;
+            }
+        __syncthreads();  // wsum and sbase are reused by the next step
     }
 }
 
@@ -150,8 +200,7 @@ __global__ void k_coarse_csr(const uint64_t *ukeys, int64_t m, int b, int64_t k,
 }
 
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff_out, int32_t **ccol_out,
-                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st, const uint8_t *keep,
-                          int64_t nnz_kept) {
+                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st, const uint8_t *keep) {
     int64_t nnz = g.nnz;
     int b = ceil_log2((uint64_t)(k > 1 ? k : 2));
     int64_t nb = nnz > 0 ? nnz : 1;
@@ -185,14 +234,19 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
         *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
         return 0;
     }
-    dim3 grid((unsigned)cdiv(cdiv(nnz, kChunk), kT));
+    const int64_t cb = cdiv(cdiv(nnz, kChunk), kT);
+    dim3 grid((unsigned)(cb < 8192 ? cb : 8192));
+    unsigned long long *cursor = (unsigned long long *)total;
+    HIPCHK(hipMemsetAsync(cursor, 0, 8, st));
     switch (g.wkind) {
-        case 0: hipLaunchKernelGGL(k_contract_keys<0>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
-        case 1: hipLaunchKernelGGL(k_contract_keys<1>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
-        default: hipLaunchKernelGGL(k_contract_keys<2>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va); break;
+        case 0: hipLaunchKernelGGL(k_contract_merge<0>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
+        case 1: hipLaunchKernelGGL(k_contract_merge<1>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
+        default: hipLaunchKernelGGL(k_contract_merge<2>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
     }
-    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b + (keep ? 1 : 0), tmp, st);
-    if (keep) nnz = nnz_kept;  // the dropped rows' entries sorted last
+    HIPCHK(hipMemcpyAsync(host_i64, cursor, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    nnz = host_i64[0];  // merged entries (kept rows only)
+    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b, tmp, st);
     if (nnz == 0) {
         HIPCHK(hipMemsetAsync(coff, 0, (k + 1) * 8, st));
         e = hipMalloc(&ccol, 4);

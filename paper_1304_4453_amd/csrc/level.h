@@ -124,11 +124,11 @@ int64_t build_relabel(const int32_t *zeta, int64_t n, int32_t *pi, Scratch &scr,
                       hipStream_t st);
 // Contracts g by pi into a coarse CSR (doubled diagonal, int64 weights, rows
 // ascending).  Allocates *coff/*ccol/*cw with hipMalloc.  Returns nnz'.
-// keep (batched runs, else null): rows of graphs not kept are dropped; they
-// hold all but nnz_kept of the entries.
+// keep (batched runs, else null): rows of graphs g with keep[g.gid[u]] == 0
+// are left out.
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff, int32_t **ccol,
                           int64_t **cw, Scratch &scr, int64_t *host_i64, hipStream_t st,
-                          const uint8_t *keep = nullptr, int64_t nnz_kept = 0);
+                          const uint8_t *keep = nullptr);
 // lab[v] = map[lab[v]] for v < n
 void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st);
 void launch_iota(int32_t *a, int64_t n, hipStream_t st);
