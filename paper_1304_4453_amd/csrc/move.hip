@@ -129,9 +129,12 @@ __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const
     return bx;
 }
 
+// (at most 128 VGPRs, four waves per SIMD, no spills: left alone the compiler
+// hoists the loads of the unrolled row and takes ~250, one wave per SIMD)
 template <int WK, bool LP>
-__global__ __launch_bounds__(256) void k_decide_lane(GraphView g, MoveState ms, int64_t begin, int64_t count,
-                                                     int force_wide) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_lane(GraphView g, MoveState ms,
+                                                                                           int64_t begin, int64_t count,
+                                                                                           int force_wide) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t ncand = 0;
     int32_t u = 0;
