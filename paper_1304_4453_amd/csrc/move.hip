@@ -554,8 +554,9 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
 
 // ------------------------------------------------------------------ hubs: several workgroups per node
 // Rows longer than the workgroup limit are aggregated without global atomics.
-//  1. part: a workgroup per chunk of kHubInsChunk entries counting-sorts its
-//     (X, w) pairs into P = 2^pbits hash buckets of X (P ~ row length / 1024)
+//  1. part: a workgroup per chunk of kHubInsChunk entries merges its entries
+//     of equal X in LDS and counting-sorts the merged (X, w) pairs into
+//     P = 2^pbits hash buckets of X (P ~ row length / 1024)
 //     and writes them to a staging area, with a (start, count) word per
 //     (bucket, chunk); entries of u's own community D only add to a per-chunk
 //     share of w(u, D \ u).
@@ -588,10 +589,29 @@ __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
 
+constexpr int kMergeBits = 12;
+constexpr int kMergeSlots = 1 << kMergeBits;  // a chunk's merge table: at most kHubInsChunk keys, load <= 1/2
+static_assert(2 * kHubInsChunk <= kMergeSlots, "merge table must never fill");
+__device__ __forceinline__ uint32_t merge_slot(int32_t x) {
+    return ((uint32_t)x * 0x27D4EB2Fu) >> (32 - kMergeBits);
+}
+
 template <int WK, bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState ms, HubArrays ha, int64_t blk0) {
-    __shared__ int32_t start[1 << kHubMaxPBits];
-    __shared__ int32_t fill[1 << kHubMaxPBits];
+    // the chunk's merge table, then (once the merged weights are in registers)
+    // the bucket counts and fill cursors
+    __shared__ union {
+        struct {
+            int32_t key[kMergeSlots];
+            int64_t val[kMergeSlots];
+        } m;
+        struct {
+            int32_t start[1 << kHubMaxPBits];
+            int32_t fill[1 << kHubMaxPBits];
+        } b;
+    } lds;
+    int32_t *const start = lds.b.start;
+    int32_t *const fill = lds.b.fill;
     __shared__ int64_t wsum[kHubThreads / kWave];
     const int64_t hg = ha.ins_hub[blk0 + blockIdx.x];
     const int64_t k = blockIdx.x - ha.ins_first[hg];
@@ -604,8 +624,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
     const int pb = ha.pbits[hg];
     const int P = 1 << pb;
-    for (int i = threadIdx.x; i < P; i += kHubThreads) { start[i] = 0; fill[i] = 0; }
-    __syncthreads();
+    for (int i = threadIdx.x; i < kMergeSlots; i += kHubThreads) { lds.m.key[i] = kEmpty; lds.m.val[i] = 0; }
     int32_t v[kHubPerThread], X[kHubPerThread], bk[kHubPerThread];
     int64_t W[kHubPerThread];
 #pragma unroll
@@ -619,11 +638,41 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     for (int j = 0; j < kHubPerThread; ++j) X[j] = v[j] != u ? ms.zeta[v[j]] : -1;
     int64_t myD = 0;
 #pragma unroll
-    for (int j = 0; j < kHubPerThread; ++j) {
+    for (int j = 0; j < kHubPerThread; ++j)
         if (X[j] == D) {
             myD += W[j];
             X[j] = -1;
         }
+    __syncthreads();
+    // merge equal communities of the chunk: the entry that claims a key's slot
+    // carries the key's summed weight, the others drop out, so a bucket holds
+    // at most one entry per (community, chunk) however large the community is
+    int32_t slot[kHubPerThread];
+#pragma unroll
+    for (int j = 0; j < kHubPerThread; ++j) {
+        slot[j] = -1;
+        if (X[j] < 0) continue;
+        uint32_t h = merge_slot(X[j]);
+        for (;;) {
+            int32_t kk = atomicCAS(&lds.m.key[h], kEmpty, X[j]);
+            if (kk == kEmpty || kk == X[j]) {
+                atomicAdd((unsigned long long *)&lds.m.val[h], (unsigned long long)W[j]);
+                if (kk == kEmpty) slot[j] = (int32_t)h;
+                else X[j] = -1;
+                break;
+            }
+            h = (h + 1) & (kMergeSlots - 1);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kHubPerThread; ++j)
+        if (slot[j] >= 0) W[j] = lds.m.val[slot[j]];
+    __syncthreads();
+    for (int i = threadIdx.x; i < P; i += kHubThreads) { start[i] = 0; fill[i] = 0; }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kHubPerThread; ++j) {
         bk[j] = X[j] >= 0 ? (int32_t)hub_bucket(X[j], pb) : -1;
         if (bk[j] >= 0) atomicAdd(&start[bk[j]], 1);
     }
