@@ -189,7 +189,9 @@ __global__ __launch_bounds__(kBT) void k_batch_intra(GraphView g, const int32_t 
 }
 __global__ void k_batch_vol(int64_t n0, const int32_t *key, const int64_t *vol0, int64_t *volL) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n0 && vol0[v]) atomicAdd((unsigned long long *)&volL[key[v]], (unsigned long long)vol0[v]);
+    int64_t x = v < n0 ? vol0[v] : 0;
+    int32_t l = x ? key[v] : 0;
+    if (wave_group_sum(l, x != 0, x)) atomicAdd((unsigned long long *)&volL[l], (unsigned long long)x);
 }
 __global__ void k_batch_sq(int64_t n0, const int32_t *gid0, const int64_t *volL, unsigned long long *sq) {
     int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

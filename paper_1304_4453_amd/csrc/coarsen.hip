@@ -293,7 +293,9 @@ __global__ void k_iota(int32_t *a, int64_t n) {
 // volC[x] = sum of vol[u] over the nodes u with zeta[u] = x (volC zeroed first)
 __global__ void k_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t *volC) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < n && vol[u]) atomicAdd((unsigned long long *)&volC[zeta[u]], (unsigned long long)vol[u]);
+    int64_t x = u < n ? vol[u] : 0;
+    int32_t c = x ? zeta[u] : 0;
+    if (wave_group_sum(c, x != 0, x)) atomicAdd((unsigned long long *)&volC[c], (unsigned long long)x);
 }
 void launch_comm_vol(const int32_t *zeta, const int64_t *vol, int64_t n, int64_t *volC, hipStream_t st) {
     if (n <= 0) return;
@@ -328,7 +330,10 @@ void launch_copy_vol(int64_t *dst, const int64_t *src, int64_t n, hipStream_t st
 // the first node of v's label
 __global__ void k_first_min(const int32_t *lab, int64_t n, int32_t *first) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicMin(&first[lab[v]], (int32_t)v);
+    int32_t l = v < n ? lab[v] : 0;
+    int64_t unused = 0;
+    // a group's leader is its lowest lane, which holds the group's smallest v
+    if (wave_group_sum(l, v < n, unused)) atomicMin(&first[l], (int32_t)v);
 }
 __global__ void k_is_first(const int32_t *lab, const int32_t *first, int64_t n, int32_t *isf) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -366,7 +371,9 @@ __global__ void k_label_check(const int32_t *lab, int64_t n, int32_t *bad) {
 }
 __global__ void k_label_vol(const int32_t *lab, const int64_t *vol, int64_t n, int64_t *volL) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n && vol[v]) atomicAdd((unsigned long long *)&volL[lab[v]], (unsigned long long)vol[v]);
+    int64_t x = v < n ? vol[v] : 0;
+    int32_t l = x ? lab[v] : 0;
+    if (wave_group_sum(l, x != 0, x)) atomicAdd((unsigned long long *)&volL[l], (unsigned long long)x);
 }
 // I2 = sum of intra-label entries with self-loops times diag_mult
 template <int WK>

@@ -984,10 +984,35 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
     __shared__ int64_t red[kHubThreads / kWave];
     const int64_t nblk = (int64_t)gridDim.x - nred;
     int64_t moved = 0;
-    for (int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x; i < count; i += nblk * kHubThreads) {
-        int64_t pos = begin + i;
-        int32_t X = ms.move_to[pos];
-        if (X >= 0) moved += apply_move(ms, ms.class_nodes[pos], X);
+    if (LP) {
+        for (int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x; i < count;
+             i += nblk * kHubThreads) {
+            int64_t pos = begin + i;
+            int32_t X = ms.move_to[pos];
+            if (X >= 0) moved += apply_move(ms, ms.class_nodes[pos], X);
+        }
+    } else {
+        // wavefront-uniform trips: the volume updates of moves that leave or
+        // join the same community are combined per wavefront
+        for (int64_t i0 = ((int64_t)blockIdx.x - nred) * kHubThreads + (threadIdx.x & ~(kWave - 1)); i0 < count;
+             i0 += nblk * kHubThreads) {
+            const int64_t i = i0 + lane_id();
+            const int32_t X = i < count ? ms.move_to[begin + i] : -1;
+            const bool mv = X >= 0;
+            int32_t D = 0;
+            int64_t join = 0, leave = 0;
+            if (mv) {
+                const int32_t u = ms.class_nodes[begin + i];
+                D = ms.zeta[u];
+                join = leave = ms.vol[u];
+                ms.zeta[u] = X;
+                if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
+                ++moved;
+            }
+            if (wave_group_sum(X, mv, join)) atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)join);
+            if (wave_group_sum(D, mv, leave))
+                atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-leave));
+        }
     }
     moved = wave_sum(moved);
     if (lane_id() == 0) red[threadIdx.x / kWave] = moved;

@@ -82,6 +82,34 @@ __device__ __forceinline__ void block_count_add(unsigned long long *dst, unsigne
 }
 constexpr int64_t kCountGrid = 2048;  // workgroups of the grid-stride counting kernels
 
+// Combines the updates of wavefront lanes that target the same key before
+// they reach memory (scatters onto a few large communities otherwise
+// serialise on one address): up to kGroupRounds times, the remaining lanes
+// whose key equals that of the lowest remaining lane form a group whose v sum
+// lands in that lane, the group's leader.  Returns whether this lane still
+// updates memory: a leader (v now its group's sum) or a lane left over after
+// the last round (its own v).  The leader is the group's lowest lane.  live:
+// the lane has an update.  Every lane of the wavefront must call.
+constexpr int kGroupRounds = 4;
+__device__ __forceinline__ bool wave_group_sum(int32_t key, bool live, int64_t &v) {
+    unsigned long long rem = __ballot(live);
+    bool act = live;
+    const int lane = lane_id();
+    for (int r = 0; r < kGroupRounds && rem; ++r) {
+        const int lead = __ffsll(rem) - 1;
+        const int32_t lk = __shfl(key, lead);
+        const bool in = ((rem >> lane) & 1ull) && key == lk;
+        int64_t x = in ? v : 0;
+        for (int s = 32; s >= 1; s >>= 1) x += __shfl_xor(x, s);
+        if (in) {
+            if (lane == lead) v = x;
+            else act = false;
+        }
+        rem &= ~__ballot(in);
+    }
+    return act;
+}
+
 // ------------------------------------------------------------------ graph of one level
 struct GraphView {
     int64_t n = 0, nnz = 0;
