@@ -122,7 +122,10 @@ typedef struct {
                               kernels of each class form a branch beside the class's
                               other decide kernels, joined before its moves apply;
                               0: one chain.  Same results. */
-    int32_t reserved[1];
+    int32_t colour_tail;   /* 1 (default): once a colouring round's frontier is
+                              small, the following rounds run back to back inside
+                              one workgroup (one launch for many rounds); 0: every
+                              round is a grid launch.  Same colours. */
 } plm_options;
 
 /* Fills *opt with the defaults above. */

@@ -41,7 +41,7 @@ class plm_options(ctypes.Structure):
                 ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32),
-                ("hub_stream", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32)]
 
 
 class plm_level_info_t(ctypes.Structure):

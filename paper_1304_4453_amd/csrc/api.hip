@@ -23,6 +23,9 @@ constexpr double kReplanFraction = 0.7;
 // timing events per class step: start and stop of the 5 kernel groups (the
 // partitioned group's part launch), then start and stop of the agg launch
 constexpr size_t kEv = 12;
+// pinned host scratch of a context, in int64 words (the colouring's counter
+// read-back takes 480 int32)
+constexpr size_t kHostWords = 512;
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -145,7 +148,7 @@ struct plm_ctx {
     int64_t bin_nodes[4] = {0, 0, 0, 0}, bin_entries[4] = {0, 0, 0, 0};
     int64_t sgl_nodes = 0, sgl_entries = 0;  // hubs of the one-workgroup path
     int64_t loops = 0;  // self-loop entries of the current level
-    int64_t *hbuf = nullptr;             // pinned host scratch (64 int64)
+    int64_t *hbuf = nullptr;             // pinned host scratch (kHostWords int64)
     Scratch scr;
     plm_stats_t stats;
     std::vector<hipEvent_t> events;
@@ -315,7 +318,8 @@ struct plm_ctx {
         LevelData &l = L();
         GraphView g = l.view();
         double t0 = now_ms();
-        ncol = build_colouring(g, seed, cur, schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st);
+        ncol = build_colouring(g, seed, cur, schedule, colour, scr, (int32_t *)hbuf, &jp_rounds, st,
+                               opt.colour_tail != 0);
         if (cur < PLM_MAX_LEVELS) {
             stats.colour_ms[cur] = now_ms() - t0;
             stats.schedule_rounds[cur] = jp_rounds;
@@ -1114,6 +1118,7 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.refine != 0 && o.refine != 1) { msg = "refine must be 0 or 1"; return PLM_E_ARG; }
     if (o.graph_sweeps != 0 && o.graph_sweeps != 1) { msg = "graph_sweeps must be 0 or 1"; return PLM_E_ARG; }
     if (o.hub_stream != 0 && o.hub_stream != 1) { msg = "hub_stream must be 0 or 1"; return PLM_E_ARG; }
+    if (o.colour_tail != 0 && o.colour_tail != 1) { msg = "colour_tail must be 0 or 1"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
@@ -1176,6 +1181,7 @@ void plm_default_options(plm_options *o) {
     o->gamma_den = 1;
     o->graph_sweeps = 1;
     o->hub_stream = 1;
+    o->colour_tail = 1;
 }
 
 }  // extern "C"
@@ -1240,7 +1246,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c->opt = o;
         c->mem_kind = mem_kind;
         c->n0 = n;
-        HIPCHK(hipHostMalloc((void **)&c->hbuf, 64 * sizeof(int64_t), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void **)&c->hbuf, kHostWords * sizeof(int64_t), hipHostMallocDefault));
         LevelData l0;
         l0.n = n;
         l0.nnz = nnz;

@@ -36,10 +36,20 @@ constexpr int kRoundGrid = 2048;          // workgroups of a round launch
 constexpr int kRoundsPerCheck = 16;       // rounds launched between host checks
 constexpr int64_t kHubChunk = 4 * 256;    // entries of a long row per work item (4 per thread)
 
+// counters, each on a 128-byte line of its own (the pushes of a round hit
+// them from every XCD, and counters that share a line serialise each other):
+// the four of set s (queue kinds 0..2, then chunks), then the number of
+// colours, the uncoloured-node count (both written once, after the last
+// round) and the round a tail launch reached
+constexpr int kCntLine = 32;
+__host__ __device__ __forceinline__ int cidx(int set, int kind) { return (set * 4 + kind) * kCntLine; }
+constexpr int kCntNcol = 12 * kCntLine, kCntUncoloured = 13 * kCntLine, kCntTail = 14 * kCntLine;
+constexpr int kCntWords = 15 * kCntLine;
+
 struct JpQ {
     int32_t *q[3][3];  // [set][kind]: 0 lane, 1 wavefront, 2 multi-workgroup
     int64_t *cq[3];    // [set]: chunks of the multi-workgroup rows, (slot << 32) | chunk
-    int32_t *cnt;      // [set * 4 + kind], [set * 4 + 3] = chunks; [12] = ncol, [13] = nodes coloured
+    int32_t *cnt;      // kCntWords counters (above)
     uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
 };
 
@@ -75,10 +85,10 @@ __device__ __forceinline__ int row_kind(const int64_t *off, int32_t v) {
 // A long row (rare) enters the multi-workgroup queue: a slot, and one work
 // item per kHubChunk entries.
 __device__ __forceinline__ void push_long(const JpQ &Q, int set, int32_t v, const int64_t *off) {
-    int32_t slot = atomicAdd(&Q.cnt[set * 4 + 2], 1);
+    int32_t slot = atomicAdd(&Q.cnt[cidx(set, 2)], 1);
     Q.q[set][2][slot] = v;
     int32_t nc = (int32_t)((off[v + 1] - off[v] + kHubChunk - 1) / kHubChunk);
-    int32_t c0 = atomicAdd(&Q.cnt[set * 4 + 3], nc);
+    int32_t c0 = atomicAdd(&Q.cnt[cidx(set, 3)], nc);
     for (int32_t c = 0; c < nc; ++c) Q.cq[set][c0 + c] = ((int64_t)slot << 32) | c;
 }
 
@@ -108,8 +118,8 @@ __device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (
     const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
     int32_t b0 = 0, b1 = 0;
     if (lane == leader) {
-        if (tot0) b0 = atomicAdd(&Q.cnt[set * 4 + 0], tot0);
-        if (tot1) b1 = atomicAdd(&Q.cnt[set * 4 + 1], tot1);
+        if (tot0) b0 = atomicAdd(&Q.cnt[cidx(set, 0)], tot0);
+        if (tot1) b1 = atomicAdd(&Q.cnt[cidx(set, 1)], tot1);
     }
     b0 = __shfl(b0, leader);
     b1 = __shfl(b1, leader);
@@ -120,25 +130,12 @@ __device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (
     }
 }
 
-__device__ __forceinline__ void wave_max_colour(const JpQ &Q, int32_t c) {
-    for (int s = 32; s >= 1; s >>= 1) {
-        int32_t o = __shfl_xor(c, s);
-        c = o > c ? o : c;
-    }
-    if (lane_id() == 0 && c > 0) atomicMax(&Q.cnt[12], c);
-}
-
 __global__ void k_jp_seed(GraphView g, const int32_t *pending, int32_t *colour, JpQ Q) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t v[1] = {(int32_t)(u < g.n ? u : 0)};
     const bool want[1] = {u < g.n && pending[u] == 0};
     if (u < g.n) colour[u] = -1;
     wave_push<1>(Q, 0, v, want, g.off);
-}
-
-__device__ __forceinline__ void count_coloured(const JpQ &Q, int64_t c) {
-    for (int s = 32; s >= 1; s >>= 1) c += __shfl_xor(c, s);
-    if (lane_id() == 0 && c) atomicAdd(&Q.cnt[13], (int32_t)c);
 }
 
 // smallest colour >= base not set in an LDS window bitmap, or -1 (wave-wide)
@@ -191,17 +188,19 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
     }
 }
 
-__global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, int32_t level, int32_t r,
-                                                  int32_t *colour, int32_t *pending, JpQ Q) {
-    __shared__ uint32_t wbm[kCT / kWave][kWinWords];
+// One round, run by workgroups [bid, bid + nblk) of NT threads: the grid
+// launch passes its own block index and size, the single-workgroup tail 0, 1.
+template <int NT>
+__device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed, int32_t level, int32_t r,
+                                              int32_t *colour, int32_t *pending, const JpQ &Q, int64_t bid,
+                                              int64_t nblk) {
+    __shared__ uint32_t wbm[NT / kWave][kWinWords];
     __shared__ uint32_t bbm[kWinWords];
     const int set = r % 3, nxt = (r + 1) % 3, old = (r + 2) % 3;
-    if (blockIdx.x == 0 && threadIdx.x < 4) Q.cnt[old * 4 + threadIdx.x] = 0;
-    const int32_t ns = Q.cnt[set * 4 + 0], nm = Q.cnt[set * 4 + 1], nc = Q.cnt[set * 4 + 3];
-    const int64_t gthreads = (int64_t)gridDim.x * kCT;
-    const int64_t gtid = (int64_t)blockIdx.x * kCT + threadIdx.x;
-    int64_t coloured = 0;
-    int32_t maxc = 0;  // 1 + largest colour given by this thread
+    if (bid == 0 && threadIdx.x < 4) Q.cnt[cidx(old, (int)threadIdx.x)] = 0;
+    const int32_t ns = Q.cnt[cidx(set, 0)], nm = Q.cnt[cidx(set, 1)], nc = Q.cnt[cidx(set, 3)];
+    const int64_t gthreads = nblk * NT;
+    const int64_t gtid = bid * NT + threadIdx.x;
     // eight lanes per node (rows of at most 32 entries: four per lane, loaded
     // together); the colours seen are OR-ed over the eight lanes
     const int sub = (int)(threadIdx.x & 7);
@@ -229,23 +228,17 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
 #pragma unroll
         for (int d = 1; d < 8; d <<= 1) used |= __shfl_xor(used, d);
         int32_t cu = __builtin_ctzll(~used);
-        if (sub == 0) {
-            colour[u] = cu;
-            maxc = cu + 1 > maxc ? cu + 1 : maxc;
-            ++coloured;
-        }
+        if (sub == 0) colour[u] = cu;
         bool rel[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) rel[j] = (v[j] != u && !hi[j]) && atomicSub(&pending[v[j]], 1) == 1;
         wave_push<4>(Q, nxt, v, rel, g.off);
     }
-    count_coloured(Q, coloured);
-    wave_max_colour(Q, maxc);
     // one wavefront per node: a row of up to kWaveRow entries is held in
     // registers (kWaveRow / 64 per lane), its colours gathered in one batch and
     // its lower-priority neighbours released from the same registers
     const int w = threadIdx.x / kWave;
-    for (int64_t i = (int64_t)blockIdx.x * (kCT / kWave) + w; i < nm; i += (int64_t)gridDim.x * (kCT / kWave)) {
+    for (int64_t i = bid * (NT / kWave) + w; i < nm; i += nblk * (NT / kWave)) {
         int32_t u = Q.q[set][1][i];
         const int64_t bu = node_base(g, u);
         uint64_t hu = prio_hash(seed, level, u - bu);
@@ -276,11 +269,7 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
             f = wave_first_free(wbm[w], base);
             wave_sync();
         }
-        if (lane_id() == 0) {
-            colour[u] = f;
-            atomicMax(&Q.cnt[12], f + 1);
-            atomicAdd(&Q.cnt[13], 1);
-        }
+        if (lane_id() == 0) colour[u] = f;
         bool rel[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
@@ -290,7 +279,7 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
     // several workgroups per node: each work item is kHubChunk entries of one
     // long row; its colours go into an LDS bitmap that is OR-ed into the row's
     // global bitmap (the finishing launch picks the smallest free colour)
-    for (int64_t it = blockIdx.x; it < nc; it += gridDim.x) {
+    for (int64_t it = bid; it < nc; it += nblk) {
         const int64_t item = Q.cq[set][it];
         const int32_t j = (int32_t)(item >> 32);
         const int64_t k = item & 0xffffffffLL;
@@ -299,42 +288,52 @@ __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, in
         uint64_t hu = prio_hash(seed, level, u - bu);
         const int64_t c0 = g.off[u] + k * kHubChunk, e1 = g.off[u + 1];
         const int64_t c1 = c0 + kHubChunk < e1 ? c0 + kHubChunk : e1;
-        for (int i = threadIdx.x; i < kWinWords; i += kCT) bbm[i] = 0;
+        for (int i = threadIdx.x; i < kWinWords; i += NT) bbm[i] = 0;
         __syncthreads();
-        int32_t v[4], c[4];
-        bool hi[4], rel[4];
+        constexpr int kQ = (int)(kHubChunk / NT) > 0 ? (int)(kHubChunk / NT) : 1;
+        int32_t v[kQ], c[kQ];
+        bool hi[kQ], rel[kQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int64_t e = c0 + q * kCT + threadIdx.x;
+        for (int q = 0; q < kQ; ++q) {
+            int64_t e = c0 + q * NT + threadIdx.x;
             v[q] = e < c1 ? g.col[e] : u;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) hi[q] = v[q] != u && prio_greater(prio_hash(seed, level, v[q] - bu), v[q], hu, u);
+        for (int q = 0; q < kQ; ++q)
+            hi[q] = v[q] != u && prio_greater(prio_hash(seed, level, v[q] - bu), v[q], hu, u);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kQ; ++q) {
             c[q] = hi[q] ? colour[v[q]] : kWin;
             rel[q] = (v[q] != u && !hi[q]) && atomicSub(&pending[v[q]], 1) == 1;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < kQ; ++q)
             if (c[q] < kWin) atomicOr(&bbm[c[q] >> 5], 1u << (c[q] & 31));
-        wave_push<4>(Q, nxt, v, rel, g.off);
+        wave_push<kQ>(Q, nxt, v, rel, g.off);
         __syncthreads();
-        for (int i = threadIdx.x; i < kWinWords; i += kCT)
+        for (int i = threadIdx.x; i < kWinWords; i += NT)
             if (bbm[i]) atomicOr(&Q.bitmap[(int64_t)j * kWinWords + i], bbm[i]);
         __syncthreads();
     }
 }
 
-// smallest free colour of each multi-workgroup node of round r
-__global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, int32_t level, int32_t r,
-                                                   int32_t *colour, JpQ Q) {
-    __shared__ uint32_t wbm[kCT / kWave][kWinWords];
+__global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, int32_t level, int32_t r,
+                                                  int32_t *colour, int32_t *pending, JpQ Q) {
+    jp_round_body<kCT>(g, seed, level, r, colour, pending, Q, blockIdx.x, gridDim.x);
+}
+
+// smallest free colour of each multi-workgroup node of round r (the bitmap
+// words were OR-ed at the device's L2 and are read from there)
+template <int NT>
+__device__ __forceinline__ void jp_finish_body(const GraphView &g, uint64_t seed, int32_t level, int32_t r,
+                                               int32_t *colour, const JpQ &Q, int64_t bid, int64_t nblk) {
+    __shared__ uint32_t wbm[NT / kWave][kWinWords];
     const int set = r % 3, w = threadIdx.x / kWave;
-    const int32_t nh = Q.cnt[set * 4 + 2];
-    for (int64_t j = (int64_t)blockIdx.x * (kCT / kWave) + w; j < nh; j += (int64_t)gridDim.x * (kCT / kWave)) {
+    const int32_t nh = Q.cnt[cidx(set, 2)];
+    for (int64_t j = bid * (NT / kWave) + w; j < nh; j += nblk * (NT / kWave)) {
         uint32_t *bm = Q.bitmap + j * kWinWords;
-        for (int i = lane_id(); i < kWinWords; i += kWave) wbm[w][i] = bm[i];
+        for (int i = lane_id(); i < kWinWords; i += kWave)
+            wbm[w][i] = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wave_sync();
         int32_t c = wave_first_free(wbm[w], 0);
         wave_sync();
@@ -342,11 +341,69 @@ __global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, i
         int32_t u = Q.q[set][2][j];
         if (c < 0)
             c = wave_colour_scan(g, seed, level, u, prio_hash(seed, level, u - node_base(g, u)), colour, wbm[w], kWin);
-        if (lane_id() == 0) {
-            colour[u] = c;
-            atomicMax(&Q.cnt[12], c + 1);
-            atomicAdd(&Q.cnt[13], 1);
-        }
+        if (lane_id() == 0) colour[u] = c;
+    }
+}
+
+__global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, int32_t level, int32_t r,
+                                                   int32_t *colour, JpQ Q) {
+    jp_finish_body<kCT>(g, seed, level, r, colour, Q, blockIdx.x, gridDim.x);
+}
+
+// Tail of the colouring: once frontiers are small, rounds [r0, r_end) run back
+// to back in one workgroup (a grid launch per round would cost far more than
+// the round's work), each round's writes made visible to the next by an agent
+// fence around a workgroup barrier (counters, queues and bitmaps are updated
+// by device atomics, which the CU's L1 does not see).  The workgroup stops at
+// an empty frontier, at one whose work exceeds kTailExit passes of the
+// workgroup (the grid takes it back), or at r_end, and leaves the round it
+// reached in cnt[kCntTail].  Every loop is bounded by the counters of its round.
+constexpr int kTailThreads = 1024;
+constexpr int32_t kTailEnter = 8;   // frontier work (workgroup passes) at which the host starts the tail
+constexpr int32_t kTailExit = 32;   // ... above which the tail hands the rounds back
+constexpr int32_t kTailRounds = 1 << 16;  // rounds per tail launch at most
+__host__ __device__ __forceinline__ int64_t tail_passes(int64_t ns, int64_t nm, int64_t nc) {
+    return ns / (kTailThreads / 8) + nm / (kTailThreads / kWave) + nc + 1;
+}
+__device__ __forceinline__ void tail_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__global__ __launch_bounds__(kTailThreads) void k_jp_tail(GraphView g, uint64_t seed, int32_t level, int32_t r0,
+                                                          int32_t r_end, int32_t *colour, int32_t *pending, JpQ Q) {
+    int32_t r = r0;
+    tail_barrier();
+    for (; r < r_end; ++r) {
+        const int set = r % 3;
+        const int32_t ns = Q.cnt[cidx(set, 0)], nm = Q.cnt[cidx(set, 1)], nh = Q.cnt[cidx(set, 2)],
+                      nc = Q.cnt[cidx(set, 3)];
+        // uniform: set r's counters do not change during round r
+        if (ns + nm + nh == 0 || tail_passes(ns, nm, nc) > kTailExit) break;
+        jp_round_body<kTailThreads>(g, seed, level, r, colour, pending, Q, 0, 1);
+        tail_barrier();
+        jp_finish_body<kTailThreads>(g, seed, level, r, colour, Q, 0, 1);
+        tail_barrier();
+    }
+    if (threadIdx.x == 0) Q.cnt[kCntTail] = r;
+}
+
+// number of colours (1 + the largest) and uncoloured nodes, once at the end
+__global__ __launch_bounds__(kCT) void k_colour_stats(const int32_t *colour, int64_t n, int32_t *cnt) {
+    int32_t mx = -1, bad = 0;
+    for (int64_t u = (int64_t)blockIdx.x * kCT + threadIdx.x; u < n; u += (int64_t)gridDim.x * kCT) {
+        const int32_t c = colour[u];
+        mx = c > mx ? c : mx;
+        bad += c < 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        const int32_t o = __shfl_xor(mx, d);
+        mx = o > mx ? o : mx;
+        bad += __shfl_xor(bad, d);
+    }
+    if (lane_id() == 0) {
+        if (mx >= 0) atomicMax(&cnt[kCntNcol], mx + 1);
+        if (bad) atomicAdd(&cnt[kCntUncoloured], bad);
     }
 }
 
@@ -373,7 +430,7 @@ __global__ void k_seq_rank(int64_t n, const int32_t *order, int32_t *colour) {
 }
 
 int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int schedule, int32_t *colour,
-                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st) {
+                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st, bool use_tail) {
     int64_t n = g.n;
     *jp_rounds = 0;
     if (n == 0) return 0;
@@ -403,39 +460,60 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     // pending counts, 9 queues, counters, hub bitmaps
     // work items of long rows in one set: at most nnz / kHubChunk + nhub
     const int64_t ncap = g.nnz / kHubChunk + nhub + 1;
-    scr.reserve(align_up(n * 4) * 10 + 256 + align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4) +
+    scr.reserve(align_up(n * 4) * 10 + align_up(kCntWords * sizeof(int32_t)) +
+                align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4) +
                 3 * align_up(ncap * 8));
     int32_t *pending = (int32_t *)scr.get(n * 4);
     JpQ Q;
     for (int s = 0; s < 3; ++s)
         for (int k = 0; k < 3; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
-    Q.cnt = (int32_t *)scr.get(16 * sizeof(int32_t));
+    Q.cnt = (int32_t *)scr.get(kCntWords * sizeof(int32_t));
     Q.bitmap = (uint32_t *)scr.get((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4);
     for (int s = 0; s < 3; ++s) Q.cq[s] = (int64_t *)scr.get(ncap * 8);
     HIPCHK(hipMemsetAsync(pending, 0, n * 4, st));
-    HIPCHK(hipMemsetAsync(Q.cnt, 0, 16 * sizeof(int32_t), st));
+    HIPCHK(hipMemsetAsync(Q.cnt, 0, kCntWords * sizeof(int32_t), st));
     HIPCHK(hipMemsetAsync(Q.bitmap, 0, (size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4, st));
     if (g.nnz > 0)
         hipLaunchKernelGGL(k_jp_pending, dim3((unsigned)cdiv(cdiv(g.nnz, kCChunk), kCT)), dim3(kCT), 0, st, g, seed,
                            level, pending);
     hipLaunchKernelGGL(k_jp_seed, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, g, pending, colour, Q);
     HIPCHK(hipGetLastError());
+    // grid rounds while frontiers are large, the one-workgroup tail once the
+    // frontier the host last saw is small (the seed frontier is known without
+    // a copy only for its size, so the first check decides)
     int32_t r = 0;
+    bool tail = false;
     for (;;) {
-        for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
-            hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour, pending, Q);
-            hipLaunchKernelGGL(k_jp_finish, dim3(256), dim3(kCT), 0, st, g, seed, level, r, colour, Q);
+        if (tail) {
+            const int32_t r_end = r < INT32_MAX - kTailRounds ? r + kTailRounds : INT32_MAX;
+            hipLaunchKernelGGL(k_jp_tail, dim3(1), dim3(kTailThreads), 0, st, g, seed, level, r, r_end, colour,
+                               pending, Q);
+        } else {
+            for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
+                hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour,
+                                   pending, Q);
+                hipLaunchKernelGGL(k_jp_finish, dim3(256), dim3(kCT), 0, st, g, seed, level, r, colour, Q);
+            }
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (tail) r = host_counters[kCntTail];
         int s = r % 3;
-        if (host_counters[s * 4] == 0 && host_counters[s * 4 + 1] == 0 && host_counters[s * 4 + 2] == 0) break;
+        const int32_t ns = host_counters[cidx(s, 0)], nm = host_counters[cidx(s, 1)],
+                      nh = host_counters[cidx(s, 2)], nc = host_counters[cidx(s, 3)];
+        if (ns == 0 && nm == 0 && nh == 0) break;
         if (r > n + 2 * kRoundsPerCheck) throw Error{-6, "internal: colouring did not converge"};
+        tail = use_tail && tail_passes(ns, nm, nc) <= kTailEnter;
     }
-    if (host_counters[13] != n) throw Error{-6, "internal: colouring did not reach every node"};
+    hipLaunchKernelGGL(k_colour_stats, dim3((unsigned)(hb < kCountGrid ? hb : kCountGrid)), dim3(kCT), 0, st, colour,
+                       n, Q.cnt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (host_counters[kCntUncoloured] != 0) throw Error{-6, "internal: colouring did not reach every node"};
     *jp_rounds = r;
-    return host_counters[12];
+    return host_counters[kCntNcol];
 }
 
 }  // namespace plm

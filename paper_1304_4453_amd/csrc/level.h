@@ -9,9 +9,10 @@ namespace plm {
 void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev, unsigned long long *maxvol_dev,
                     hipStream_t st);
 // Colours the level (schedule 0: Jones-Plassmann; 1: priority rank) into
-// colour[n]; returns the number of classes.  host_counters: 8 pinned int32.
+// colour[n]; returns the number of classes.  host_counters: 480 pinned int32.
+// use_tail: small frontiers run as one workgroup's back-to-back rounds.
 int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int schedule, int32_t *colour,
-                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st);
+                        Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st, bool use_tail);
 // Sorts nodes by (colour, degree bin, short row first) into class_nodes;
 // bstart_dev[8*ncol+2] receives bucket starts (bucket 8c+2b+s = bin b of class
 // c, s = 1 for the wavefront-bin rows longer than kQuadRow; bucket 8*ncol holds

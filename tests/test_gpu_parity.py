@@ -437,3 +437,36 @@ def test_graph_sweeps_batch_equal_eager(P):
     la, qa, lva = out[0]
     for lb, qb, lvb in out[1:]:
         assert np.array_equal(la, lb) and list(qa) == list(qb) and list(lva) == list(lvb)
+
+
+# ------------------------------------------------------------------ colouring rounds inside one workgroup
+def _tail_handoff_graph(seed, m=8000, chain=20):
+    """A chain of `chain` nodes in descending priority ending at a star centre
+    of m lower-priority leaves: the frontiers hold one node for chain + 1
+    rounds (the one-workgroup tail takes over after the first grid rounds),
+    then all m leaves at once (more than the tail keeps, so the grid takes the
+    rounds back).  The centre's row is long enough for the multi-workgroup
+    chunk path inside the tail."""
+    n = chain + 1 + m
+    order = sorted(range(n), key=lambda u: (oracle.priority(seed, 0, u), u), reverse=True)
+    path, centre, leaves = order[:chain], order[chain], order[chain + 1:]
+    edges = [tuple(sorted((path[i], path[i + 1]))) for i in range(chain - 1)]
+    edges += [tuple(sorted((path[-1], centre)))] + [tuple(sorted((centre, x))) for x in leaves]
+    return graphgen.from_edges(n, sorted(edges))
+
+
+@pytest.mark.parametrize("tail", [0, 1])
+def test_colour_tail_matches_oracle(P, tail):
+    """colour_tail = 1 runs small frontiers as back-to-back rounds in one
+    workgroup, 0 launches every round on the grid: both give the oracle's
+    colouring (and hence its results), including a hand-over from the tail
+    back to the grid and long rows coloured inside the tail."""
+    _say(f"colour tail={tail}")
+    cases = [(_tail_handoff_graph(3), 3), (graphgen.rmat(13, 16, seed=21, weighted=True), 1),
+             (graphgen.rmat(14, 8, seed=22, weighted=False), 2), (graphgen.planted_partition_1000(seed=5), 0)]
+    for g, seed in cases:
+        colours, C = oracle.colour(g.off.astype(np.int64), g.col.astype(np.int32), seed, 0, 0)
+        with P.Context(g.off, g.col, g.w, colour_seed=seed, colour_tail=tail) as ctx:
+            assert np.array_equal(ctx.state()[2], colours) and ctx.level_info().colours == C
+        full_run(P, g, seed=seed, colour_tail=tail)
+    stepwise(P, graphgen.rmat(12, 16, seed=23, weighted=True), seed=4, per_class=False, colour_tail=tail)
