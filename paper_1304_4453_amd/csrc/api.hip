@@ -183,9 +183,10 @@ struct plm_ctx {
     hipGraphExec_t sweep_exec = nullptr;
     // capture stream of the partitioned-hub branch of a captured sweep
     // (hub_stream), and a ring of fork/join events
-    hipStream_t hub_cap_st = nullptr;
+    static constexpr int kAux = 4;  // branches beside the capture stream
+    hipStream_t hub_cap_st[kAux] = {};
     static constexpr int kForkRing = 16;
-    hipEvent_t fork_ev[kForkRing] = {}, join_ev[kForkRing] = {};
+    hipEvent_t fork_ev[kForkRing] = {}, join_ev[kAux][kForkRing] = {};
 
     ~plm_ctx() {
         for (auto &l : levels) l.release();
@@ -199,10 +200,12 @@ struct plm_ctx {
         for (auto e : events) (void)hipEventDestroy(e);
         drop_graph();
         if (cap_st) (void)hipStreamDestroy(cap_st);
-        if (hub_cap_st) (void)hipStreamDestroy(hub_cap_st);
+        for (int a = 0; a < kAux; ++a)
+            if (hub_cap_st[a]) (void)hipStreamDestroy(hub_cap_st[a]);
         for (int i = 0; i < kForkRing; ++i) {
             if (fork_ev[i]) (void)hipEventDestroy(fork_ev[i]);
-            if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+            for (int a = 0; a < kAux; ++a)
+                if (join_ev[a][i]) (void)hipEventDestroy(join_ev[a][i]);
         }
     }
     void drop_graph() {
@@ -496,23 +499,42 @@ struct plm_ctx {
 
     // ---------------------------------------------------------------- sweeps
     // The class steps of classes [c0, c1) on stream s (decide launches, apply).
-    // With aux, a class's partitioned-hub kernels go to aux after a fork event
-    // and the apply waits for them through a join event; they only read the
-    // state the class starts from and write their own class positions, like
-    // the other decide kernels.
+    // With aux (kAux streams; branches 1: the partitioned-hub kernels, 2: every
+    // kernel group), a class's kernel groups split into branches: after a fork
+    // event on s, each branch but the first runs on an aux stream, and the
+    // apply waits for all of them through join events.  The decide kernels
+    // only read the state the class starts from and write their own class
+    // positions, so their order does not matter.
     void launch_classes(int32_t c0, int32_t c1, const MoveState &ms, const HubArrays &ha, const GraphView &g,
-                        bool fw, bool timing, unsigned mask, hipStream_t s, hipStream_t aux = nullptr) {
+                        bool fw, bool timing, unsigned mask, hipStream_t s, const hipStream_t *aux = nullptr,
+                        int branches = 0) {
         for (int32_t c = c0; c < c1; ++c) {
             const ClassRange &cr = classes[c];
             const hipEvent_t *ev = timing ? &events[kEv * (size_t)c] : nullptr;
-            if (aux && cr.red_count > 0) {
+            unsigned part[5];
+            int np = 0;
+            if (aux) {
+                const unsigned present = (cr.count[0] > 0 ? 1u : 0u) | (cr.count[1] > 0 ? 2u : 0u) |
+                                         (cr.count[2] > 0 ? 4u : 0u) | (cr.sgl_count > 0 ? 8u : 0u) |
+                                         (cr.red_count > 0 ? 16u : 0u);
+                if (branches == 2) {
+                    for (int b = 0; b < 5; ++b)
+                        if ((present >> b) & 1u) part[np++] = 1u << b;
+                } else {
+                    if (present & 15u) part[np++] = present & 15u;
+                    if (present & 16u) part[np++] = 16u;
+                }
+            }
+            if (np >= 2) {
                 const int k = c % kForkRing;
                 HIPCHK(hipEventRecord(fork_ev[k], s));
-                HIPCHK(hipStreamWaitEvent(aux, fork_ev[k], 0));
-                launch_class_step(g, ms, cr, ha, fw, ev, mask, aux, 16u);
-                HIPCHK(hipEventRecord(join_ev[k], aux));
-                launch_class_step(g, ms, cr, ha, fw, ev, mask, s, 15u);
-                HIPCHK(hipStreamWaitEvent(s, join_ev[k], 0));
+                for (int i = 1; i < np; ++i) {
+                    HIPCHK(hipStreamWaitEvent(aux[i - 1], fork_ev[k], 0));
+                    launch_class_step(g, ms, cr, ha, fw, ev, mask, aux[i - 1], part[i]);
+                    HIPCHK(hipEventRecord(join_ev[i - 1][k], aux[i - 1]));
+                }
+                launch_class_step(g, ms, cr, ha, fw, ev, mask, s, part[0]);
+                for (int i = 1; i < np; ++i) HIPCHK(hipStreamWaitEvent(s, join_ev[i - 1][k], 0));
             } else {
                 launch_class_step(g, ms, cr, ha, fw, ev, mask, s);
             }
@@ -520,11 +542,11 @@ struct plm_ctx {
         }
     }
     void ensure_hub_streams() {
-        if (hub_cap_st) return;
-        HIPCHK(hipStreamCreateWithFlags(&hub_cap_st, hipStreamNonBlocking));
+        if (hub_cap_st[0]) return;
+        for (int a = 0; a < kAux; ++a) HIPCHK(hipStreamCreateWithFlags(&hub_cap_st[a], hipStreamNonBlocking));
         for (int i = 0; i < kForkRing; ++i) {
             HIPCHK(hipEventCreateWithFlags(&fork_ev[i], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming));
+            for (int a = 0; a < kAux; ++a) HIPCHK(hipEventCreateWithFlags(&join_ev[a][i], hipEventDisableTiming));
         }
     }
 
@@ -537,7 +559,8 @@ struct plm_ctx {
         HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed));
         hipGraph_t gr = nullptr;
         try {
-            launch_classes(0, ncol, ms, ha, g, fw, false, 0, cap_st, opt.hub_stream ? hub_cap_st : nullptr);
+            launch_classes(0, ncol, ms, ha, g, fw, false, 0, cap_st, opt.hub_stream ? hub_cap_st : nullptr,
+                           opt.hub_stream);
         } catch (...) {
             (void)hipStreamEndCapture(cap_st, &gr);
             if (gr) (void)hipGraphDestroy(gr);
@@ -1117,7 +1140,7 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.timing_kernel < 0 || o.timing_kernel > 5) { msg = "timing_kernel must lie in [0, 5]"; return PLM_E_ARG; }
     if (o.refine != 0 && o.refine != 1) { msg = "refine must be 0 or 1"; return PLM_E_ARG; }
     if (o.graph_sweeps != 0 && o.graph_sweeps != 1) { msg = "graph_sweeps must be 0 or 1"; return PLM_E_ARG; }
-    if (o.hub_stream != 0 && o.hub_stream != 1) { msg = "hub_stream must be 0 or 1"; return PLM_E_ARG; }
+    if (o.hub_stream < 0 || o.hub_stream > 2) { msg = "hub_stream must be 0, 1 or 2"; return PLM_E_ARG; }
     if (o.colour_tail != 0 && o.colour_tail != 1) { msg = "colour_tail must be 0 or 1"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
@@ -1180,7 +1203,7 @@ void plm_default_options(plm_options *o) {
     o->gamma_num = 1;
     o->gamma_den = 1;
     o->graph_sweeps = 1;
-    o->hub_stream = 1;
+    o->hub_stream = 2;
     o->colour_tail = 1;
 }
 

@@ -397,8 +397,9 @@ def test_sweep_cycles_fast_forward(P, max_sweeps):
 # ------------------------------------------------------------------ sweeps replayed from a HIP graph
 def test_graph_sweeps_equal_eager(P):
     """graph_sweeps: from the third sweep of a level on, a sweep is replayed
-    from a captured HIP graph; hub_stream: the partitioned-hub kernels run on a
-    second stream (also inside the captured graph, as a forked branch).
+    from a captured HIP graph; hub_stream: the partitioned-hub kernels (1) or
+    every kernel group of a class (2) run as forked branches inside the
+    captured graph.
     Replays are interleaved with eager work (counter clears, read-backs,
     re-planning); every combination must equal the plain one and the oracle."""
     _say("graph sweeps / hub stream vs eager")
@@ -407,7 +408,7 @@ def test_graph_sweeps_equal_eager(P):
              (graphgen.rmat(11, 16, seed=4, weighted=False), MID_BINS)]
     for g, bins in cases:
         res = []
-        for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1), (1, 2)):
             with P.Context(g.off, g.col, g.w, graph_sweeps=gs, hub_stream=hs, refine=1, **bins) as ctx:
                 labels, q, lv = ctx.run()
                 st = ctx.stats()
@@ -431,7 +432,7 @@ def test_graph_sweeps_batch_equal_eager(P):
          [graphgen.planted_partition_1000(seed=4)]
     node_base, off, col, w = P.pack_batch(gs)
     out = []
-    for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1)):
+    for gs, hs in ((0, 0), (1, 0), (0, 1), (1, 1), (1, 2)):
         with P.BatchContext(node_base, off, col, w, graph_sweeps=gs, hub_stream=hs, **SMALL_BINS) as bc:
             out.append(bc.run_batch())
     la, qa, lva = out[0]
