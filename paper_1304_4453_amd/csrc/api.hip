@@ -80,7 +80,7 @@ __global__ void k_export_w(GraphView g, int64_t *out) {
     int64_t r = row_of(g.off, g.n, e0);
     int64_t rend = g.off[r + 1];
     for (int64_t e = e0; e < e1; ++e) {
-        while (e >= rend) { ++r; rend = g.off[r + 1]; }
+        while (e >= rend) { r = next_row(g.off, g.n, r, e); rend = g.off[r + 1]; }
         int64_t x = g.wkind == 0 ? 1 : (g.wkind == 1 ? (int64_t)((const int32_t *)g.w)[e] : ((const int64_t *)g.w)[e]);
         if (g.col[e] == r) x *= g.diag_mult;
         out[e] = x;
@@ -972,6 +972,17 @@ struct plm_ctx {
         return descend(lab_out, 1, true);
     }
 
+    // Modularity of the current level's partition zeta, on the current graph:
+    // contraction keeps every intra-community weight (coarse self-loops hold
+    // the doubled diagonal) and every community volume, so the two integers of
+    // Equation (3.1) equal those of the input nodes' labels
+    double modularity_current() {
+        __int128 num, den;
+        if (modularity_parts(L().view(), vol, zeta, S, scr, hbuf, &num, &den, st) != 0)
+            throw Error{PLM_E_STATE, "internal: community id out of range"};
+        if (S == 0) return 0.0;
+        return (double)num / (double)den;
+    }
     double modularity_of(const int32_t *labels_dev) {
         __int128 num, den;
         if (modularity_parts(levels[0].view(), vol0, labels_dev, S, scr, hbuf, &num, &den, st) != 0)
@@ -1437,7 +1448,7 @@ plm_status plm_run(plm_ctx *ctx, int32_t *labels, double *q_out, int32_t *levels
         try {
             int32_t lv = ctx->run(canon);
             double q = 0.0;
-            if (q_out) q = ctx->modularity_of(canon);
+            if (q_out) q = ctx->modularity_current();
             if (labels) copy_out(labels, canon, (size_t)n * 4, ctx->mem_kind, ctx->st);
             HIPCHK(hipStreamSynchronize(ctx->st));
             if (q_out) *q_out = q;

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBT) void k_batch_intra(GraphView g, const int32_t 
         gcur = gid0[r];
         for (int64_t e = e0; e < e1; ++e) {
             while (e >= rend) {
-                ++r;
+                r = next_row(g.off, g.n, r, e);
                 rend = g.off[r + 1];
                 kr = key[r];
                 const int32_t gr = gid0[r];

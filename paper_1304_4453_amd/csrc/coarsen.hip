@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_
                 const int64_t e = e0 + j;
                 if (e < e1) {
                     while (e >= rend) {
-                        ++r;
+                        r = next_row(g.off, g.n, r, e);
                         rend = g.off[r + 1];
                         kept = !keep || keep[g.gid[r]];
                         pr = kept ? (uint64_t)pi[r] : 0;
@@ -188,15 +188,23 @@ __global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, cons
     }
 }
 
-// coarse offsets: coff[r] = first unique entry with row >= r
-__global__ void k_coarse_csr(const uint64_t *ukeys, int64_t m, int b, int64_t k, int64_t *coff, int32_t *ccol) {
+// coarse columns: the low b bits of each unique key
+__global__ void k_coarse_col(const uint64_t *ukeys, int64_t m, int b, int32_t *ccol) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > m) return;
-    uint64_t mask = (b >= 64) ? ~0ULL : ((1ULL << b) - 1);
-    int64_t prev = (i == 0) ? -1 : (int64_t)(ukeys[i - 1] >> b);
-    int64_t cur = (i == m) ? k : (int64_t)(ukeys[i] >> b);
-    if (i < m) ccol[i] = (int32_t)(ukeys[i] & mask);
-    for (int64_t r = prev + 1; r <= cur && r <= k; ++r) coff[r] = i;
+    if (i < m) ccol[i] = (int32_t)(ukeys[i] & ((b >= 64) ? ~0ULL : ((1ULL << b) - 1)));
+}
+// coarse offsets: coff[r] = first unique entry with row >= r (a binary search
+// per row, so runs of empty rows cost nothing extra)
+__global__ void k_coarse_off(const uint64_t *ukeys, int64_t m, int b, int64_t k, int64_t *coff) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > k) return;
+    int64_t lo = 0, hi = m;  // first i in [0, m] with (ukeys[i] >> b) >= r
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)(ukeys[mid] >> b) < r) lo = mid + 1;
+        else hi = mid;
+    }
+    coff[r] = lo;
 }
 
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff_out, int32_t **ccol_out,
@@ -269,7 +277,8 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
     HIPCHK(hipMemsetAsync(cw, 0, m * 8, st));
     hipLaunchKernelGGL(k_reduce_by_key, dim3((unsigned)cdiv(nnz, kRbkItems)), dim3(kT), 0, st, ka, va, head, excl,
                        nnz, kb, cw);
-    hipLaunchKernelGGL(k_coarse_csr, dim3((unsigned)cdiv(m + 1, kT)), dim3(kT), 0, st, kb, m, b, k, coff, ccol);
+    hipLaunchKernelGGL(k_coarse_col, dim3((unsigned)cdiv(m, kT)), dim3(kT), 0, st, kb, m, b, ccol);
+    hipLaunchKernelGGL(k_coarse_off, dim3((unsigned)cdiv(k + 1, kT)), dim3(kT), 0, st, kb, m, b, k, coff);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
@@ -387,7 +396,7 @@ __global__ __launch_bounds__(kT) void k_intra(GraphView g, const int32_t *lab, u
         int32_t lr = lab[r];
         for (int64_t e = e0; e < e1; ++e) {
             while (e >= rend) {
-                ++r;
+                r = next_row(g.off, g.n, r, e);
                 rend = g.off[r + 1];
                 lr = lab[r];
             }

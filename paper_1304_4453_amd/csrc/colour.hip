@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, 
         while (e >= rend) {
             if (cnt) atomicAdd(&pending[r], cnt);
             cnt = 0;
-            ++r;
+            r = next_row(g.off, g.n, r, e);
             rend = g.off[r + 1];
             br = node_base(g, r);
             hr = prio_hash(seed, level, r - br);

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kThreads) void k_vol(GraphView g, int64_t *vol, uns
                 else if (acc) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)acc);
                 tot += acc;
                 acc = 0;
-                ++r;
+                r = next_row(g.off, g.n, r, e);
                 rend = g.off[r + 1];
                 seg_start = e;
             }

@@ -52,6 +52,14 @@ __device__ __forceinline__ int64_t row_of(const int64_t *off, int64_t n, int64_t
     return lo;
 }
 
+// The row holding entry e, given that e lies past row r (e >= off[r + 1]):
+// one step when the next row holds e, a binary search across a run of empty
+// rows (coarse levels keep millions of isolated nodes)
+__device__ __forceinline__ int64_t next_row(const int64_t *off, int64_t n, int64_t r, int64_t e) {
+    ++r;
+    return e < off[r + 1] ? r : row_of(off, n, e);
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -139,27 +139,55 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, int
 
 // Items of a tile are taken 256 at a time in input order; within such a round
 // a lane's rank among equal digits comes from 8 ballots (one per digit bit),
-// so equal keys keep their input order (stability).
+// so equal keys keep their input order (stability).  The tile is first sorted
+// by digit in LDS (its digit starts are the exclusive scan of its histogram
+// counts), then written out in LDS order: consecutive threads write
+// consecutive positions of a digit's run, so the stores coalesce.
 template <typename K, typename V>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, const V *vin, K *kout, V *vout,
                                                                  int64_t n, int shift, const int64_t *offsets,
-                                                                 int64_t ntiles) {
+                                                                 const int32_t *counts, int64_t ntiles) {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[kRadixWaves][256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t wsum[kRadixWaves];
     __shared__ int64_t gofs[256];
+    __shared__ K sk[kRadixTile];
+    __shared__ V sv[kRadixTile];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     running[tid] = 0;
 #pragma unroll
     for (int i = 0; i < kRadixWaves; ++i) wcnt[i][tid] = 0;
     gofs[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
+    // exclusive scan of the tile's 256 digit counts (thread t holds digit t)
+    const uint32_t cnt = (uint32_t)counts[(int64_t)tid * ntiles + blockIdx.x];
+    uint32_t inc = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int j = 0; j < w; ++j) before += wsum[j];
+    lstart[tid] = before + inc - cnt;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    // the tile's items are loaded together (one memory latency per tile)
+    K kr[kRadixRounds];
+    V vr[kRadixRounds];
+#pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
-        int64_t i = base + (int64_t)r * kRadixThreads + tid;
-        bool valid = i < n;
-        K k = valid ? kin[i] : (K)0;
-        V v = valid ? vin[i] : (V)0;
+        const int64_t i = base + (int64_t)r * kRadixThreads + tid;
+        kr[r] = i < n ? kin[i] : (K)0;
+        vr[r] = i < n ? vin[i] : (V)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const bool valid = base + (int64_t)r * kRadixThreads + tid < n;
+        const K k = kr[r];
+        const V v = vr[r];
         uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -174,9 +202,9 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
         if (valid) {
             uint32_t pre = running[d];
             for (int j = 0; j < w; ++j) pre += wcnt[j][d];
-            int64_t pos = gofs[d] + pre + rank;
-            kout[pos] = k;
-            vout[pos] = v;
+            const uint32_t lp = lstart[d] + pre + rank;
+            sk[lp] = k;
+            sv[lp] = v;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -187,6 +215,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
         }
         running[tid] += add;
         __syncthreads();
+    }
+    const int64_t left = n - base;
+    const int tn = left < kRadixTile ? (int)left : (int)kRadixTile;
+    for (int j = tid; j < tn; j += kRadixThreads) {
+        const K k = sk[j];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int64_t pos = gofs[d] + (int64_t)(j - (int)lstart[d]);
+        kout[pos] = k;
+        vout[pos] = sv[j];
     }
 }
 
@@ -211,7 +248,7 @@ static void radix_impl(K **keys, V **vals, K **keys_alt, V **vals_alt, int64_t n
                            ntiles);
         exclusive_scan_i32(counts, offsets, m, nullptr, scan_tmp, st);
         hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3(ntiles), dim3(kRadixThreads), 0, st, *keys, *vals,
-                           *keys_alt, *vals_alt, n, shift, (const int64_t *)offsets, ntiles);
+                           *keys_alt, *vals_alt, n, shift, (const int64_t *)offsets, (const int32_t *)counts, ntiles);
         K *tk = *keys; *keys = *keys_alt; *keys_alt = tk;
         V *tv = *vals; *vals = *vals_alt; *vals_alt = tv;
     }
