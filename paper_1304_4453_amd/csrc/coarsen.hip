@@ -145,10 +145,10 @@ __global__ void k_head_flags(const uint64_t *keys, int64_t n, int32_t *head) {
 }
 
 // Reduce-by-key over sorted keys.  Run id of item i = incl_scan(head)[i] - 1 =
-// excl[i] + head[i] - 1.  Each thread folds its kChunk consecutive items into
-// per-run partial sums; partials are combined per block in LDS; a run that lies
-// wholly inside the block is stored, a run crossing a block edge is added
-// atomically (out_w zeroed first).
+// excl[i] + head[i] - 1.  The items of a block are read lane by lane
+// (coalesced, all loads of a thread in flight together) and added into their
+// run's LDS slot; a run that lies wholly inside the block is stored, a run
+// crossing a block edge is added atomically (out_w zeroed first).
 constexpr int kRbkItems = kT * kChunk;
 __global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, const int64_t *vals, const int32_t *head,
                                                       const int64_t *excl, int64_t n, uint64_t *out_k,
@@ -159,22 +159,15 @@ __global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, cons
     int64_t run0 = excl[blk0] + head[blk0] - 1;  // run id of the block's first item
     for (int i = threadIdx.x; i < kRbkItems; i += kT) acc[i] = 0;
     __syncthreads();
-    int64_t i0 = blk0 + (int64_t)threadIdx.x * kChunk;
-    if (i0 < blk1) {
-        int64_t i1 = i0 + kChunk < blk1 ? i0 + kChunk : blk1;
-        int64_t cur = excl[i0] + head[i0] - 1;
-        int64_t s = 0;
-        for (int64_t i = i0; i < i1; ++i) {
-            int64_t r = excl[i] + head[i] - 1;
-            if (r != cur) {
-                atomicAdd((unsigned long long *)&acc[cur - run0], (unsigned long long)s);
-                s = 0;
-                cur = r;
-            }
-            if (head[i]) out_k[r] = keys[i];
-            s += vals[i];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+        const int64_t i = blk0 + (int64_t)q * kT + threadIdx.x;
+        if (i < blk1) {
+            const int32_t h = head[i];
+            const int64_t r = excl[i] + h - 1;
+            if (h) out_k[r] = keys[i];
+            atomicAdd((unsigned long long *)&acc[r - run0], (unsigned long long)vals[i]);
         }
-        atomicAdd((unsigned long long *)&acc[cur - run0], (unsigned long long)s);
     }
     __syncthreads();
     int64_t last_run = excl[blk1 - 1] + head[blk1 - 1] - 1;

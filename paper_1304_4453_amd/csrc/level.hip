@@ -7,45 +7,90 @@
 namespace plm {
 
 constexpr int kThreads = 256;
-constexpr int kChunk = 16;  // entries per thread in entry-parallel kernels
 
 // ------------------------------------------------------------------ volumes
 // vol(u) = row sum with self-loop entries multiplied by diag_mult (section
-// III-B: a self-loop counts twice in vol).  Entry-parallel: each thread walks
-// kChunk consecutive entries and flushes one partial sum per row segment
-// (atomic when the row extends past the chunk).  Also accumulates S and the
-// largest volume.
+// III-B: a self-loop counts twice in vol); also accumulates S.  A workgroup
+// takes kVolTile consecutive entries, stages the offsets of the rows they
+// touch in LDS, and reads its entries lane by lane (coalesced, all of a
+// thread's loads in flight together); each entry
+// finds its row by a binary search in LDS and adds into that row's LDS sum.
+// Rows wholly inside the tile are stored, the edge rows added atomically.  A
+// tile touching more rows than fit (a run of empty rows) walks its entries
+// instead, one thread per kVolPer consecutive entries, flushing a partial sum
+// per row segment.
+constexpr int kVolTile = 2048;
+constexpr int kVolPer = kVolTile / kThreads;
 template <int WK>
-__global__ __launch_bounds__(kThreads) void k_vol(GraphView g, int64_t *vol, unsigned long long *S,
-                                                  unsigned long long *maxvol) {
+__global__ __launch_bounds__(kThreads) void k_vol_tile(GraphView g, int64_t *vol, unsigned long long *S) {
+    __shared__ int64_t soff[kVolTile + 1];
+    __shared__ int64_t acc[kVolTile];
+    __shared__ int64_t rr[2];
+    const int64_t E0 = (int64_t)blockIdx.x * kVolTile;
+    const int64_t E1 = E0 + kVolTile < g.nnz ? E0 + kVolTile : g.nnz;
+    if (threadIdx.x == 0) rr[0] = row_of(g.off, g.n, E0);
+    if (threadIdx.x == kWave) rr[1] = row_of(g.off, g.n, E1 - 1);
+    __syncthreads();
+    const int64_t r0 = rr[0], nr = rr[1] - r0 + 1;
     int64_t tot = 0;
-    const int64_t nchunks = cdiv_dev(g.nnz, kChunk);
-    for (int64_t ch = (int64_t)blockIdx.x * kThreads + threadIdx.x; ch < nchunks;
-         ch += (int64_t)gridDim.x * kThreads) {
-        const int64_t e0 = ch * kChunk;
-        int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
-        int64_t r = row_of(g.off, g.n, e0);
-        int64_t rend = g.off[r + 1];
-        int64_t seg_start = e0, acc = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            while (e >= rend) {  // flush row r
-                if (seg_start == g.off[r] && rend <= e1) vol[r] = acc;
-                else if (acc) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)acc);
-                tot += acc;
-                acc = 0;
-                r = next_row(g.off, g.n, r, e);
-                rend = g.off[r + 1];
-                seg_start = e;
-            }
-            int64_t x = wload<WK>(g.w, e);
-            if (g.col[e] == r) x *= g.diag_mult;
-            acc += x;
+    if (nr <= kVolTile) {  // workgroup-uniform
+        for (int64_t j = threadIdx.x; j <= nr; j += kThreads) soff[j] = g.off[r0 + j];
+        for (int64_t j = threadIdx.x; j < nr; j += kThreads) acc[j] = 0;
+        int32_t c[kVolPer];
+        int64_t x[kVolPer];
+#pragma unroll
+        for (int q = 0; q < kVolPer; ++q) {
+            const int64_t e = E0 + q * kThreads + threadIdx.x;
+            c[q] = e < E1 ? g.col[e] : -1;
+            x[q] = e < E1 ? wload<WK>(g.w, e) : 0;
         }
-        if (seg_start == g.off[r] && rend <= e1) vol[r] = acc;
-        else if (acc) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)acc);
-        tot += acc;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kVolPer; ++q) {
+            const int64_t e = E0 + q * kThreads + threadIdx.x;
+            if (e >= E1) continue;
+            int lo = 0, hi = (int)nr;  // soff[lo] <= e < soff[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (soff[mid] <= e) lo = mid; else hi = mid;
+            }
+            int64_t v = x[q];
+            if (c[q] == r0 + lo) v *= g.diag_mult;
+            atomicAdd((unsigned long long *)&acc[lo], (unsigned long long)v);
+            tot += v;
+        }
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < nr; j += kThreads) {
+            if (soff[j] >= E0 && soff[j + 1] <= E1) vol[r0 + j] = acc[j];
+            else if (acc[j]) atomicAdd((unsigned long long *)&vol[r0 + j], (unsigned long long)acc[j]);
+        }
+    } else {
+        const int64_t e0 = E0 + (int64_t)threadIdx.x * kVolPer;
+        if (e0 < E1) {
+            const int64_t e1 = e0 + kVolPer < E1 ? e0 + kVolPer : E1;
+            int64_t r = row_of(g.off, g.n, e0);
+            int64_t rend = g.off[r + 1];
+            int64_t seg_start = e0, a = 0;
+            for (int64_t e = e0; e < e1; ++e) {
+                while (e >= rend) {
+                    if (seg_start == g.off[r] && rend <= e1) vol[r] = a;
+                    else if (a) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)a);
+                    tot += a;
+                    a = 0;
+                    r = next_row(g.off, g.n, r, e);
+                    rend = g.off[r + 1];
+                    seg_start = e;
+                }
+                int64_t v = wload<WK>(g.w, e);
+                if (g.col[e] == r) v *= g.diag_mult;
+                a += v;
+            }
+            if (seg_start == g.off[r] && rend <= e1) vol[r] = a;
+            else if (a) atomicAdd((unsigned long long *)&vol[r], (unsigned long long)a);
+            tot += a;
+        }
     }
-    block_count_add(S, (unsigned long long)tot);  // S: one atomic per workgroup
+    block_count_add(S, (unsigned long long)tot);
 }
 
 __global__ void k_max_vol(const int64_t *vol, int64_t n, unsigned long long *maxvol) {
@@ -65,12 +110,11 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
     HIPCHK(hipMemsetAsync(S_dev, 0, sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(maxvol_dev, 0, sizeof(unsigned long long), st));
     if (g.nnz > 0) {
-        const int64_t vb = cdiv(cdiv(g.nnz, kChunk), kThreads);
-        dim3 grid((unsigned)(vb < 4 * kCountGrid ? vb : 4 * kCountGrid));
+        const dim3 tiles((unsigned)cdiv(g.nnz, kVolTile));
         switch (g.wkind) {
-            case 0: hipLaunchKernelGGL(k_vol<0>, grid, dim3(kThreads), 0, st, g, vol, S_dev, maxvol_dev); break;
-            case 1: hipLaunchKernelGGL(k_vol<1>, grid, dim3(kThreads), 0, st, g, vol, S_dev, maxvol_dev); break;
-            default: hipLaunchKernelGGL(k_vol<2>, grid, dim3(kThreads), 0, st, g, vol, S_dev, maxvol_dev); break;
+            case 0: hipLaunchKernelGGL(k_vol_tile<0>, tiles, dim3(kThreads), 0, st, g, vol, S_dev); break;
+            case 1: hipLaunchKernelGGL(k_vol_tile<1>, tiles, dim3(kThreads), 0, st, g, vol, S_dev); break;
+            default: hipLaunchKernelGGL(k_vol_tile<2>, tiles, dim3(kThreads), 0, st, g, vol, S_dev); break;
         }
         int64_t nb = cdiv(g.n, kThreads);
         hipLaunchKernelGGL(k_max_vol, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(kThreads), 0, st, vol, g.n,
