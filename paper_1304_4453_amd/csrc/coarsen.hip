@@ -57,85 +57,108 @@ int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t 
 // ------------------------------------------------------------------ contraction
 // key = (pi(u) << b) | pi(v), value = entry weight (self-loops times diag_mult,
 // so the coarse diagonal is again "doubled").
-// Merged before the sort: each thread turns its kChunk consecutive entries
-// into keys (pi(u) << b) | pi(v) with weights, merges equal keys in registers
-// (within a row many neighbours fall into the same coarse node), and its
-// workgroup writes the merged entries contiguously after a global cursor (one
-// atomic per workgroup step).  Their order does not matter: the sort that
-// follows orders them completely and equal keys' weights are summed.  Rows of
-// graphs that are not kept (batched runs) are left out.
+// Merged before the sort, per tile of kCTile consecutive entries: each entry
+// (read lane by lane, coalesced) finds its row through the tile's row offsets
+// staged in LDS (a binary search there; a global one when the tile spans a run
+// of empty rows), and the tile's equal keys merge in an LDS hash table (within
+// a row many neighbours fall into the same coarse node, and so do the rows of
+// one community).  The workgroup appends its merged entries after a global
+// cursor (one atomic).  Their order does not matter: the sort that follows
+// orders them completely and equal keys' weights are summed.  Rows of graphs
+// that are not kept (batched runs) are left out.
 constexpr uint64_t kNoKey = ~0ULL;  // keys are below 2^(2b) <= 2^62
+constexpr int kCTile = 1024;
+constexpr int kCPer = kCTile / kT;
+constexpr int kCBits = 11;
+constexpr int kCSlots = 1 << kCBits;  // at most kCTile keys: load <= 1/2
+static_assert(2 * kCTile <= kCSlots, "contraction merge table must never fill");
 template <int WK>
 __global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_t *pi, int b, const uint8_t *keep,
                                                        uint64_t *keys, int64_t *vals, unsigned long long *cursor) {
+    __shared__ int64_t soff[kCTile + 1];
+    __shared__ uint64_t tk[kCSlots];
+    __shared__ int64_t tv[kCSlots];
+    __shared__ int64_t rr[2];
     __shared__ int32_t wsum[kT / kWave];
     __shared__ unsigned long long sbase;
-    const int64_t nchunks = cdiv_dev(g.nnz, kChunk);
-    for (int64_t c0 = (int64_t)blockIdx.x * kT; c0 < nchunks; c0 += (int64_t)gridDim.x * kT) {  // workgroup-uniform
-        const int64_t ch = c0 + threadIdx.x;
-        uint64_t K[kChunk];
-        int64_t W[kChunk];
+    const int64_t E0 = (int64_t)blockIdx.x * kCTile;
+    const int64_t E1 = E0 + kCTile < g.nnz ? E0 + kCTile : g.nnz;
+    if (threadIdx.x == 0) rr[0] = row_of(g.off, g.n, E0);
+    if (threadIdx.x == kWave) rr[1] = row_of(g.off, g.n, E1 - 1);
+    for (int s = threadIdx.x; s < kCSlots; s += kT) { tk[s] = kNoKey; tv[s] = 0; }
+    int32_t v[kCPer];
+    int64_t x[kCPer];
 #pragma unroll
-        for (int j = 0; j < kChunk; ++j) { K[j] = kNoKey; W[j] = 0; }
-        if (ch < nchunks) {
-            const int64_t e0 = ch * kChunk, e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
-            int64_t r = row_of(g.off, g.n, e0);
-            int64_t rend = g.off[r + 1];
-            bool kept = !keep || keep[g.gid[r]];
-            uint64_t pr = kept ? (uint64_t)pi[r] : 0;
+    for (int q = 0; q < kCPer; ++q) {
+        const int64_t e = E0 + q * kT + threadIdx.x;
+        v[q] = e < E1 ? g.col[e] : 0;
+        x[q] = e < E1 ? wload<WK>(g.w, e) : 0;
+    }
+    __syncthreads();
+    const int64_t r0 = rr[0], nr = rr[1] - r0 + 1;
+    const bool staged = nr <= kCTile;  // workgroup-uniform
+    if (staged)
+        for (int64_t j = threadIdx.x; j <= nr; j += kT) soff[j] = g.off[r0 + j];
+    __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const int64_t e = e0 + j;
-                if (e < e1) {
-                    while (e >= rend) {
-                        r = next_row(g.off, g.n, r, e);
-                        rend = g.off[r + 1];
-                        kept = !keep || keep[g.gid[r]];
-                        pr = kept ? (uint64_t)pi[r] : 0;
-                    }
-                    if (kept) {
-                        int32_t v = g.col[e];
-                        int64_t x = wload<WK>(g.w, e);
-                        if (v == r) x *= g.diag_mult;
-                        K[j] = (pr << b) | (uint64_t)pi[v];
-                        W[j] = x;
-                    }
-                }
+    for (int q = 0; q < kCPer; ++q) {
+        const int64_t e = E0 + q * kT + threadIdx.x;
+        if (e >= E1) continue;
+        int64_t r;
+        if (staged) {
+            int lo = 0, hi = (int)nr;  // soff[lo] <= e < soff[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (soff[mid] <= e) lo = mid; else hi = mid;
             }
-            // equal keys into their first occurrence
-#pragma unroll
-            for (int a = 0; a < kChunk; ++a)
-#pragma unroll
-                for (int c = a + 1; c < kChunk; ++c)
-                    if (K[c] != kNoKey && K[c] == K[a]) { W[a] += W[c]; K[c] = kNoKey; }
+            r = r0 + lo;
+        } else {
+            r = row_of(g.off, g.n, e);
         }
-        int32_t cnt = 0;
-#pragma unroll
-        for (int j = 0; j < kChunk; ++j) cnt += K[j] != kNoKey;
-        // workgroup exclusive prefix of cnt
-        int32_t inc = cnt;
-        for (int d = 1; d < kWave; d <<= 1) {
-            int32_t y = __shfl_up(inc, d);
-            if (lane_id() >= d) inc += y;
-        }
-        if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = inc;
-        __syncthreads();
-        int32_t before = 0, total = 0;
-        for (int w = 0; w < kT / kWave; ++w) {
-            if (w < (int)(threadIdx.x / kWave)) before += wsum[w];
-            total += wsum[w];
-        }
-        if (threadIdx.x == 0) sbase = total ? atomicAdd(cursor, (unsigned long long)total) : 0ULL;
-        __syncthreads();
-        int64_t pos = (int64_t)sbase + before + (inc - cnt);
-#pragma unroll
-        for (int j = 0; j < kChunk; ++j)
-            if (K[j] != kNoKey) {
-                keys[pos] = K[j];
-                vals[pos] = W[j];
-                ++pos;
+        if (keep && !keep[g.gid[r]]) continue;
+        int64_t w = x[q];
+        if (v[q] == r) w *= g.diag_mult;
+        const uint64_t key = ((uint64_t)pi[r] << b) | (uint64_t)pi[v[q]];
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ULL) >> (64 - kCBits));
+        for (;;) {
+            const uint64_t old = atomicCAS((unsigned long long *)&tk[h], (unsigned long long)kNoKey,
+                                           (unsigned long long)key);
+            if (old == kNoKey || old == key) {
+                atomicAdd((unsigned long long *)&tv[h], (unsigned long long)w);
+                break;
             }
-        __syncthreads();  // wsum and sbase are reused by the next step
+            h = (h + 1) & (kCSlots - 1);
+        }
+    }
+    __syncthreads();
+    // each thread appends the keys of its kCSlots / kT slots
+    constexpr int kSP = kCSlots / kT;
+    int32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kSP; ++j) cnt += tk[threadIdx.x * kSP + j] != kNoKey;
+    int32_t inc = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+        int32_t y = __shfl_up(inc, d);
+        if (lane_id() >= d) inc += y;
+    }
+    if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = inc;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int w = 0; w < kT / kWave; ++w) {
+        if (w < (int)(threadIdx.x / kWave)) before += wsum[w];
+        total += wsum[w];
+    }
+    if (threadIdx.x == 0) sbase = total ? atomicAdd(cursor, (unsigned long long)total) : 0ULL;
+    __syncthreads();
+    int64_t pos = (int64_t)sbase + before + (inc - cnt);
+#pragma unroll
+    for (int j = 0; j < kSP; ++j) {
+        const int s = threadIdx.x * kSP + j;
+        if (tk[s] != kNoKey) {
+            keys[pos] = tk[s];
+            vals[pos] = tv[s];
+            ++pos;
+        }
     }
 }
 
@@ -235,8 +258,7 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
         *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
         return 0;
     }
-    const int64_t cb = cdiv(cdiv(nnz, kChunk), kT);
-    dim3 grid((unsigned)(cb < 8192 ? cb : 8192));
+    const dim3 grid((unsigned)cdiv(nnz, kCTile));
     unsigned long long *cursor = (unsigned long long *)total;
     HIPCHK(hipMemsetAsync(cursor, 0, 8, st));
     switch (g.wkind) {
