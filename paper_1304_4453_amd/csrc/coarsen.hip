@@ -399,32 +399,57 @@ __global__ void k_label_vol(const int32_t *lab, const int64_t *vol, int64_t n, i
     int32_t l = x ? lab[v] : 0;
     if (wave_group_sum(l, x != 0, x)) atomicAdd((unsigned long long *)&volL[l], (unsigned long long)x);
 }
-// I2 = sum of intra-label entries with self-loops times diag_mult
+// I2 = sum of intra-label entries with self-loops times diag_mult.  A
+// workgroup takes kITile consecutive entries (read lane by lane) and finds
+// each entry's row through the tile's row offsets staged in LDS (a binary
+// search; a global one when the tile spans a run of empty rows); one atomic
+// per workgroup.
+constexpr int kITile = 2048;
+constexpr int kIPer = kITile / kT;
 template <int WK>
 __global__ __launch_bounds__(kT) void k_intra(GraphView g, const int32_t *lab, unsigned long long *I2) {
-    int64_t e0 = ((int64_t)blockIdx.x * kT + threadIdx.x) * kChunk;
-    int64_t s = 0;
-    if (e0 < g.nnz) {
-        int64_t e1 = e0 + kChunk < g.nnz ? e0 + kChunk : g.nnz;
-        int64_t r = row_of(g.off, g.n, e0);
-        int64_t rend = g.off[r + 1];
-        int32_t lr = lab[r];
-        for (int64_t e = e0; e < e1; ++e) {
-            while (e >= rend) {
-                r = next_row(g.off, g.n, r, e);
-                rend = g.off[r + 1];
-                lr = lab[r];
-            }
-            int32_t v = g.col[e];
-            if (lab[v] == lr) {
-                int64_t x = wload<WK>(g.w, e);
-                if (v == r) x *= g.diag_mult;
-                s += x;
-            }
-        }
+    __shared__ int64_t soff[kITile + 1];
+    __shared__ int64_t rr[2];
+    const int64_t E0 = (int64_t)blockIdx.x * kITile;
+    const int64_t E1 = E0 + kITile < g.nnz ? E0 + kITile : g.nnz;
+    if (threadIdx.x == 0) rr[0] = row_of(g.off, g.n, E0);
+    if (threadIdx.x == kWave) rr[1] = row_of(g.off, g.n, E1 - 1);
+    int32_t v[kIPer], lv[kIPer];
+#pragma unroll
+    for (int q = 0; q < kIPer; ++q) {
+        const int64_t e = E0 + q * kT + threadIdx.x;
+        v[q] = e < E1 ? g.col[e] : 0;
     }
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    if (lane_id() == 0 && s) atomicAdd(I2, (unsigned long long)s);
+#pragma unroll
+    for (int q = 0; q < kIPer; ++q) lv[q] = lab[v[q]];
+    __syncthreads();
+    const int64_t r0 = rr[0], nr = rr[1] - r0 + 1;
+    const bool staged = nr <= kITile;  // workgroup-uniform
+    if (staged)
+        for (int64_t j = threadIdx.x; j <= nr; j += kT) soff[j] = g.off[r0 + j];
+    __syncthreads();
+    int64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kIPer; ++q) {
+        const int64_t e = E0 + q * kT + threadIdx.x;
+        if (e >= E1) continue;
+        int64_t r;
+        if (staged) {
+            int lo = 0, hi = (int)nr;  // soff[lo] <= e < soff[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (soff[mid] <= e) lo = mid; else hi = mid;
+            }
+            r = r0 + lo;
+        } else {
+            r = row_of(g.off, g.n, e);
+        }
+        if (lv[q] != lab[r]) continue;
+        int64_t x = wload<WK>(g.w, e);
+        if (v[q] == r) x *= g.diag_mult;
+        s += x;
+    }
+    block_count_add(I2, (unsigned long long)s);
 }
 // sum of volL^2 as 128-bit: per-thread squares, wave sums, two-word atomic add
 __global__ __launch_bounds__(kT) void k_sum_sq(const int64_t *volL, int64_t n, unsigned long long *acc2) {
@@ -464,7 +489,7 @@ int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *la
     if (host_i64[0] != 0) return -1;
     hipLaunchKernelGGL(k_label_vol, grid, dim3(kT), 0, st, labels, vol0, n, volL);
     if (g0.nnz > 0) {
-        dim3 eg((unsigned)cdiv(cdiv(g0.nnz, kChunk), kT));
+        dim3 eg((unsigned)cdiv(g0.nnz, kITile));
         switch (g0.wkind) {
             case 0: hipLaunchKernelGGL(k_intra<0>, eg, dim3(kT), 0, st, g0, labels, cnt); break;
             case 1: hipLaunchKernelGGL(k_intra<1>, eg, dim3(kT), 0, st, g0, labels, cnt); break;

@@ -27,7 +27,6 @@
 namespace plm {
 
 constexpr int kCT = 256;                  // threads per workgroup
-constexpr int kCChunk = 16;               // entries per thread (pending counts)
 constexpr int64_t kLaneRow = 32;          // row length handled by eight lanes
 constexpr int64_t kWaveRow = 1024;        // row length handled by one wavefront
 constexpr int kWin = 4096;                // colour window of a bitmap (bits)
@@ -53,28 +52,64 @@ struct JpQ {
     uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
 };
 
+// pending(u) = number of higher-priority non-loop neighbours.  A workgroup
+// takes kPendTile consecutive entries (read lane by lane), finds each entry's
+// row through the tile's row offsets staged in LDS (a binary search; a global
+// one when the tile spans a run of empty rows) and counts into the row's LDS
+// counter; rows wholly inside the tile are stored, the edge rows added
+// atomically (pending zeroed first).
+constexpr int kPendTile = 2048;
+constexpr int kPendPer = kPendTile / kCT;
 __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, int32_t level, int32_t *pending) {
-    int64_t e0 = ((int64_t)blockIdx.x * kCT + threadIdx.x) * kCChunk;
-    if (e0 >= g.nnz) return;
-    int64_t e1 = e0 + kCChunk < g.nnz ? e0 + kCChunk : g.nnz;
-    int64_t r = row_of(g.off, g.n, e0);
-    int64_t rend = g.off[r + 1];
-    int64_t br = node_base(g, r);
-    uint64_t hr = prio_hash(seed, level, r - br);
-    int32_t cnt = 0;
-    for (int64_t e = e0; e < e1; ++e) {
-        while (e >= rend) {
-            if (cnt) atomicAdd(&pending[r], cnt);
-            cnt = 0;
-            r = next_row(g.off, g.n, r, e);
-            rend = g.off[r + 1];
-            br = node_base(g, r);
-            hr = prio_hash(seed, level, r - br);
-        }
-        int64_t v = g.col[e];
-        if (v != r && prio_greater(prio_hash(seed, level, v - br), v, hr, r)) ++cnt;
+    __shared__ int64_t soff[kPendTile + 1];
+    __shared__ int32_t acc[kPendTile];
+    __shared__ int64_t rr[2];
+    const int64_t E0 = (int64_t)blockIdx.x * kPendTile;
+    const int64_t E1 = E0 + kPendTile < g.nnz ? E0 + kPendTile : g.nnz;
+    if (threadIdx.x == 0) rr[0] = row_of(g.off, g.n, E0);
+    if (threadIdx.x == kWave) rr[1] = row_of(g.off, g.n, E1 - 1);
+    int32_t v[kPendPer];
+#pragma unroll
+    for (int q = 0; q < kPendPer; ++q) {
+        const int64_t e = E0 + q * kCT + threadIdx.x;
+        v[q] = e < E1 ? g.col[e] : 0;
     }
-    if (cnt) atomicAdd(&pending[r], cnt);
+    __syncthreads();
+    const int64_t r0 = rr[0], nr = rr[1] - r0 + 1;
+    const bool staged = nr <= kPendTile;  // workgroup-uniform
+    if (staged) {
+        for (int64_t j = threadIdx.x; j <= nr; j += kCT) soff[j] = g.off[r0 + j];
+        for (int64_t j = threadIdx.x; j < nr; j += kCT) acc[j] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPendPer; ++q) {
+        const int64_t e = E0 + q * kCT + threadIdx.x;
+        if (e >= E1) continue;
+        int64_t r;
+        int lo = 0;
+        if (staged) {
+            int hi = (int)nr;  // soff[lo] <= e < soff[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (soff[mid] <= e) lo = mid; else hi = mid;
+            }
+            r = r0 + lo;
+        } else {
+            r = row_of(g.off, g.n, e);
+        }
+        const int64_t br = node_base(g, r);
+        const int64_t x = v[q];
+        if (x == r || !prio_greater(prio_hash(seed, level, x - br), x, prio_hash(seed, level, r - br), r)) continue;
+        if (staged) atomicAdd(&acc[lo], 1);
+        else atomicAdd(&pending[r], 1);
+    }
+    if (!staged) return;  // workgroup-uniform
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < nr; j += kCT) {
+        if (soff[j] >= E0 && soff[j + 1] <= E1) pending[r0 + j] = acc[j];
+        else if (acc[j]) atomicAdd(&pending[r0 + j], acc[j]);
+    }
 }
 
 __device__ __forceinline__ int row_kind(const int64_t *off, int32_t v) {
@@ -474,8 +509,8 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     HIPCHK(hipMemsetAsync(Q.cnt, 0, kCntWords * sizeof(int32_t), st));
     HIPCHK(hipMemsetAsync(Q.bitmap, 0, (size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4, st));
     if (g.nnz > 0)
-        hipLaunchKernelGGL(k_jp_pending, dim3((unsigned)cdiv(cdiv(g.nnz, kCChunk), kCT)), dim3(kCT), 0, st, g, seed,
-                           level, pending);
+        hipLaunchKernelGGL(k_jp_pending, dim3((unsigned)cdiv(g.nnz, kPendTile)), dim3(kCT), 0, st, g, seed, level,
+                           pending);
     hipLaunchKernelGGL(k_jp_seed, dim3((unsigned)cdiv(n, kCT)), dim3(kCT), 0, st, g, pending, colour, Q);
     HIPCHK(hipGetLastError());
     // grid rounds while frontiers are large, the one-workgroup tail once the
