@@ -471,3 +471,36 @@ def test_colour_tail_matches_oracle(P, tail):
             assert np.array_equal(ctx.state()[2], colours) and ctx.level_info().colours == C
         full_run(P, g, seed=seed, colour_tail=tail)
     stepwise(P, graphgen.rmat(12, 16, seed=23, weighted=True), seed=4, per_class=False, colour_tail=tail)
+
+
+# ------------------------------------------------------------------ runs of empty rows
+def _islands(seed, gap=200000, block=1000, weighted=True):
+    """Two random blocks of `block` nodes separated by `gap` isolated nodes:
+    the entry tiles that cross the gap span far more rows than they can stage
+    (the per-entry fallback of the tiled kernels), the others stage theirs."""
+    rng = np.random.default_rng(seed)
+    n = 2 * block + gap
+    edges = set()
+    for base in (0, block + gap):
+        for _ in range(12 * block):
+            a, b = (int(x) for x in rng.integers(0, block, 2))
+            if a != b:
+                edges.add((base + min(a, b), base + max(a, b)))
+    edges = sorted(edges)
+    w = rng.integers(1, 50, len(edges)) if weighted else None
+    loops = {int(x): int(rng.integers(1, 9)) for x in rng.integers(0, block, 20)} if weighted else None
+    return graphgen.from_edges(n, edges, w, loops=loops)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_runs_of_isolated_nodes(P, seed):
+    _say(f"islands seed={seed}")
+    g = _islands(seed, weighted=seed == 0)
+    full_run(P, g, seed=seed)
+    full_run(P, g, seed=seed, refine=True)
+    r = oracle.plp(g.off, g.col, g.w, seed=seed)
+    with P.Context(g.off, g.col, g.w, colour_seed=seed) as ctx:
+        labels, q, it, upd = ctx.plp()
+        assert np.array_equal(labels, r.labels) and q == r.q and upd == r.updates
+        assert ctx.modularity(r.labels) == r.q
+    stepwise(P, g, seed=seed, per_class=False)
