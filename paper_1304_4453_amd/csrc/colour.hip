@@ -13,9 +13,11 @@
 // clears set (r+2)%3), so the host only checks for an empty frontier every few
 // rounds.  Frontier nodes are split by row length: eight lanes per node (<= 32
 // entries), one wavefront per node (<= 1024), and several workgroups per node
-// above that; the latter OR the colours they see into a block-local LDS bitmap,
-// merge it into a per-node global bitmap, and a second launch per round picks
-// the smallest free colour.  A round is bound by latency (its frontier is
+// above that; the latter OR the colours they see into a block-local LDS bitmap
+// and merge it into a per-node global bitmap, from which the workgroup that
+// finishes the row's last chunk picks the smallest free colour.  Small
+// frontiers run as back-to-back rounds inside one workgroup (the tail).  A
+// round is bound by latency (its frontier is
 // often small), so every lane loads a batch of entries before it gathers their
 // colours, instead of walking a row one dependent load after another.
 #include <hip/hip_runtime.h>
@@ -50,6 +52,7 @@ struct JpQ {
     int64_t *cq[3];    // [set]: chunks of the multi-workgroup rows, (slot << 32) | chunk
     int32_t *cnt;      // kCntWords counters (above)
     uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
+    int32_t *done;     // per multi-workgroup queue slot: chunks finished (0 between uses)
 };
 
 // pending(u) = number of higher-priority non-loop neighbours.  A workgroup
@@ -313,7 +316,11 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     }
     // several workgroups per node: each work item is kHubChunk entries of one
     // long row; its colours go into an LDS bitmap that is OR-ed into the row's
-    // global bitmap (the finishing launch picks the smallest free colour)
+    // global bitmap, and the workgroup that finishes the row's last chunk
+    // (counted after a device fence) picks the smallest free colour from it.
+    // The nodes this round releases read that colour only in the next round.
+    __shared__ int32_t last_chunk;
+    __shared__ uint32_t or_sink[NT];
     for (int64_t it = bid; it < nc; it += nblk) {
         const int64_t item = Q.cq[set][it];
         const int32_t j = (int32_t)(item >> 32);
@@ -346,43 +353,40 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
             if (c[q] < kWin) atomicOr(&bbm[c[q] >> 5], 1u << (c[q] & 31));
         wave_push<kQ>(Q, nxt, v, rel, g.off);
         __syncthreads();
+        // the bitmap words change only through device atomics, which every XCD
+        // sees; each OR returns (and its result is consumed) before the barrier,
+        // so it has been performed before thread 0 counts the chunk
+        uint32_t *bm = Q.bitmap + (int64_t)j * kWinWords;
+        uint32_t seen = 0;
         for (int i = threadIdx.x; i < kWinWords; i += NT)
-            if (bbm[i]) atomicOr(&Q.bitmap[(int64_t)j * kWinWords + i], bbm[i]);
+            if (bbm[i]) seen |= atomicOr(&bm[i], bbm[i]);
+        or_sink[threadIdx.x] = seen;
         __syncthreads();
+        if (threadIdx.x == 0) {
+            const int32_t nch = (int32_t)((e1 - g.off[u] + kHubChunk - 1) / kHubChunk);
+            last_chunk = atomicAdd(&Q.done[j], 1) == nch - 1 ? 1 : 0;
+        }
+        __syncthreads();
+        if (last_chunk && threadIdx.x < kWave) {  // workgroup-uniform flag; the first wavefront
+            for (int i = lane_id(); i < kWinWords; i += kWave)
+                bbm[i] = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wave_sync();
+            int32_t cu = wave_first_free(bbm, 0);
+            wave_sync();
+            for (int i = lane_id(); i < kWinWords; i += kWave) bm[i] = 0;
+            if (cu < 0) cu = wave_colour_scan(g, seed, level, u, hu, colour, bbm, kWin);
+            if (lane_id() == 0) {
+                colour[u] = cu;
+                Q.done[j] = 0;
+            }
+        }
+        __syncthreads();  // bbm and last_chunk are reused by the next item
     }
 }
 
 __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, int32_t level, int32_t r,
                                                   int32_t *colour, int32_t *pending, JpQ Q) {
     jp_round_body<kCT>(g, seed, level, r, colour, pending, Q, blockIdx.x, gridDim.x);
-}
-
-// smallest free colour of each multi-workgroup node of round r (the bitmap
-// words were OR-ed at the device's L2 and are read from there)
-template <int NT>
-__device__ __forceinline__ void jp_finish_body(const GraphView &g, uint64_t seed, int32_t level, int32_t r,
-                                               int32_t *colour, const JpQ &Q, int64_t bid, int64_t nblk) {
-    __shared__ uint32_t wbm[NT / kWave][kWinWords];
-    const int set = r % 3, w = threadIdx.x / kWave;
-    const int32_t nh = Q.cnt[cidx(set, 2)];
-    for (int64_t j = bid * (NT / kWave) + w; j < nh; j += nblk * (NT / kWave)) {
-        uint32_t *bm = Q.bitmap + j * kWinWords;
-        for (int i = lane_id(); i < kWinWords; i += kWave)
-            wbm[w][i] = __hip_atomic_load(&bm[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wave_sync();
-        int32_t c = wave_first_free(wbm[w], 0);
-        wave_sync();
-        for (int i = lane_id(); i < kWinWords; i += kWave) bm[i] = 0;
-        int32_t u = Q.q[set][2][j];
-        if (c < 0)
-            c = wave_colour_scan(g, seed, level, u, prio_hash(seed, level, u - node_base(g, u)), colour, wbm[w], kWin);
-        if (lane_id() == 0) colour[u] = c;
-    }
-}
-
-__global__ __launch_bounds__(kCT) void k_jp_finish(GraphView g, uint64_t seed, int32_t level, int32_t r,
-                                                   int32_t *colour, JpQ Q) {
-    jp_finish_body<kCT>(g, seed, level, r, colour, Q, blockIdx.x, gridDim.x);
 }
 
 // Tail of the colouring: once frontiers are small, rounds [r0, r_end) run back
@@ -416,8 +420,6 @@ __global__ __launch_bounds__(kTailThreads) void k_jp_tail(GraphView g, uint64_t 
         // uniform: set r's counters do not change during round r
         if (ns + nm + nh == 0 || tail_passes(ns, nm, nc) > kTailExit) break;
         jp_round_body<kTailThreads>(g, seed, level, r, colour, pending, Q, 0, 1);
-        tail_barrier();
-        jp_finish_body<kTailThreads>(g, seed, level, r, colour, Q, 0, 1);
         tail_barrier();
     }
     if (threadIdx.x == 0) Q.cnt[kCntTail] = r;
@@ -495,19 +497,21 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     // pending counts, 9 queues, counters, hub bitmaps
     // work items of long rows in one set: at most nnz / kHubChunk + nhub
     const int64_t ncap = g.nnz / kHubChunk + nhub + 1;
-    scr.reserve(align_up(n * 4) * 10 + align_up(kCntWords * sizeof(int32_t)) +
-                align_up((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4) +
-                3 * align_up(ncap * 8));
+    const size_t nslot = (size_t)(nhub > 0 ? nhub : 1);
+    scr.reserve(align_up(n * 4) * 10 + align_up(kCntWords * sizeof(int32_t)) + align_up(nslot * kWinWords * 4) +
+                align_up(nslot * 4) + 3 * align_up(ncap * 8));
     int32_t *pending = (int32_t *)scr.get(n * 4);
     JpQ Q;
     for (int s = 0; s < 3; ++s)
         for (int k = 0; k < 3; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
     Q.cnt = (int32_t *)scr.get(kCntWords * sizeof(int32_t));
-    Q.bitmap = (uint32_t *)scr.get((size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4);
+    Q.bitmap = (uint32_t *)scr.get(nslot * kWinWords * 4);
+    Q.done = (int32_t *)scr.get(nslot * 4);
     for (int s = 0; s < 3; ++s) Q.cq[s] = (int64_t *)scr.get(ncap * 8);
     HIPCHK(hipMemsetAsync(pending, 0, n * 4, st));
     HIPCHK(hipMemsetAsync(Q.cnt, 0, kCntWords * sizeof(int32_t), st));
-    HIPCHK(hipMemsetAsync(Q.bitmap, 0, (size_t)(nhub > 0 ? nhub : 1) * kWinWords * 4, st));
+    HIPCHK(hipMemsetAsync(Q.bitmap, 0, nslot * kWinWords * 4, st));
+    HIPCHK(hipMemsetAsync(Q.done, 0, nslot * 4, st));
     if (g.nnz > 0)
         hipLaunchKernelGGL(k_jp_pending, dim3((unsigned)cdiv(g.nnz, kPendTile)), dim3(kCT), 0, st, g, seed, level,
                            pending);
@@ -527,7 +531,6 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
             for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
                 hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour,
                                    pending, Q);
-                hipLaunchKernelGGL(k_jp_finish, dim3(256), dim3(kCT), 0, st, g, seed, level, r, colour, Q);
             }
         }
         HIPCHK(hipGetLastError());
