@@ -397,6 +397,7 @@ struct plm_ctx {
                 cr.count[b] = bs(c, b + 1) - bs(c, b);
             }
             cr.quad = bstart[8 * c + 3] - bstart[8 * c + 2];
+            cr.blk_short = bstart[8 * c + 5] - bstart[8 * c + 4];
             cr.hub_first = hg;
             cr.hub_count = cr.count[3];
             cr.sgl_base = (int64_t)shub.size();

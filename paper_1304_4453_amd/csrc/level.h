@@ -15,7 +15,8 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
                         Scratch &scr, int32_t *host_counters, int32_t *jp_rounds, hipStream_t st, bool use_tail);
 // Sorts nodes by (colour, degree bin, short row first) into class_nodes;
 // bstart_dev[8*ncol+2] receives bucket starts (bucket 8c+2b+s = bin b of class
-// c, s = 1 for the wavefront-bin rows longer than kQuadRow; bucket 8*ncol holds
+// c, s = 1 for the wavefront-bin rows longer than kQuadRow and the
+// workgroup-bin rows longer than kBlockShortRow; bucket 8*ncol holds
 // nodes that cannot move).
 // bin_entries[4]: CSR entries of the movable nodes of each bin (added to).
 // Nodes of the wave and block bins whose vol(u) does not fit 32 bits go to the
@@ -28,6 +29,9 @@ void build_buckets(const GraphView &g, const int64_t *vol, const int32_t *colour
 // wavefront-bin rows up to this length take 16 lanes per node (four nodes per
 // wavefront) instead of a whole wavefront
 constexpr int64_t kQuadRow = 64;
+// workgroup-bin rows up to this length take a 256-thread workgroup and a
+// smaller table
+constexpr int64_t kBlockShortRow = 2048;
 
 // ---- move.hip
 struct MoveState {
@@ -65,6 +69,7 @@ __device__ __forceinline__ int64_t node_wl(const MoveState &ms, int32_t u) {
 struct ClassRange {
     int64_t begin[4], count[4];  // per bin
     int64_t quad = 0;            // the first quad nodes of the wavefront bin have rows of at most kQuadRow
+    int64_t blk_short = 0;       // the first blk_short nodes of the workgroup bin have rows of at most kBlockShortRow
     // hubs of this class in the level's hub arrays
     int64_t hub_first = 0, hub_count = 0;
     int64_t ins_blocks = 0, agg_blocks = 0;

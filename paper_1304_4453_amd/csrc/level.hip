@@ -125,8 +125,8 @@ void launch_volumes(const GraphView &g, int64_t *vol, unsigned long long *S_dev,
 
 // ------------------------------------------------------------------ bucketing
 // key(u) = (colour(u) * 4 + bin(u)) * 2 + sub(u), sub = 1 for wavefront-bin
-// rows longer than kQuadRow (so that the short ones come first in their
-// bucket); nodes without a non-loop neighbour get the sentinel key ncol * 8
+// rows longer than kQuadRow and workgroup-bin rows longer than kBlockShortRow
+// (so that the short ones come first in their bucket); nodes without a non-loop neighbour get the sentinel key ncol * 8
 // (they can never move).
 // Grid-stride, with the per-bin entry counts summed per workgroup: one atomic
 // per (workgroup, bin) instead of one per wavefront, on four counters.
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_keys(GraphView g, const int
         bool active = (d > 1 || (d == 1 && g.col[e0] != u)) && (!keep || keep[g.gid[u]]);
         uint32_t bin = d <= b0 ? 0u : (d <= b1 ? 1u : (d <= b2 ? 2u : 3u));
         if ((bin == 1u || bin == 2u) && vol[u] > (int64_t)INT32_MAX) bin = 3u;
-        const uint32_t sub = (bin == 1u && d > kQuadRow) ? 1u : 0u;
+        const uint32_t sub = ((bin == 1u && d > kQuadRow) || (bin == 2u && d > kBlockShortRow)) ? 1u : 0u;
         keys[u] = active ? ((uint32_t)colour[u] * 4u + bin) * 2u + sub : (uint32_t)ncol * 8u;
         vals[u] = (int32_t)u;
         if (active) cnt[bin] += d;

@@ -428,8 +428,13 @@ __global__ __launch_bounds__(256) void k_decide_quad(GraphView g, MoveState ms, 
 }
 
 // ------------------------------------------------------------------ workgroup per node
+// rows up to kBlockShortRow entries: 256 threads and a 4096-slot table (32 KB:
+// four workgroups per CU); longer rows: 512 threads and 8192 slots (64 KB: two)
 constexpr int kBlockThreads = 512;
 constexpr int kBlockCap = 8192;  // rows up to 4096 entries
+constexpr int kBlockShortThreads = 256;
+constexpr int kBlockShortCap = 4096;
+static_assert(2 * kBlockShortRow <= kBlockShortCap, "short workgroup-bin table too small");
 
 // leaves the decision (community or -1) in *out (LDS), written by thread 0
 template <typename G, int NT, bool LP>
@@ -460,14 +465,15 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     }
 }
 
-// (two workgroups per CU: 64 KB of LDS each, at most 128 VGPRs)
-template <int WK, bool LP>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_block(GraphView g, MoveState ms, int64_t begin,
-                                                                int64_t count, int force_wide) {
-    __shared__ int32_t tk[kBlockCap];
-    __shared__ int32_t tv[kBlockCap];
+// (NT threads, a CAP-slot table; at most 128 VGPRs)
+template <int WK, bool LP, int NT, int CAP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_block(GraphView g, MoveState ms,
+                                                                                          int64_t begin, int64_t count,
+                                                                                          int force_wide) {
+    __shared__ int32_t tk[CAP];
+    __shared__ int32_t tv[CAP];
     __shared__ int32_t dec;
-    for (int s = threadIdx.x; s < kBlockCap; s += kBlockThreads) { tk[s] = kEmpty; tv[s] = 0; }
+    for (int s = threadIdx.x; s < CAP; s += NT) { tk[s] = kEmpty; tv[s] = 0; }
     __syncthreads();
     int64_t ncand = 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
@@ -481,23 +487,23 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
-        int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kBlockThreads, tk, tv, bits);
+        int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, NT, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
         int64_t base = LP ? 0 : ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         if (force_wide || vu > node_wl(ms, u))
-            block_eval<i128, kBlockThreads, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
+            block_eval<i128, NT, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
                                                 ms.volC, &dec, ncand, hv);
         else
-            block_eval<int64_t, kBlockThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
+            block_eval<int64_t, NT, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
                                                    &dec, ncand, hv);
         __syncthreads();
         const int32_t x = dec;
         if (threadIdx.x == 0) ms.move_to[pos] = x;
         if (LP) {
-            if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, kBlockThreads);
+            if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, NT);
             else if (threadIdx.x == 0) ms.active[u] = 0;
         }
     }
@@ -1072,9 +1078,17 @@ static void class_step_wk(const GraphView &g, const MoveState &ms, const ClassRa
         }
     }
     if (cr.count[2] > 0 && (groups & 4u)) {
-        int64_t blocks = cr.count[2];
-        dispatch(k_decide_block<WK, LP>, dim3((unsigned)(blocks < 2048 ? blocks : 2048)), dim3(kBlockThreads), st,
-                 t0(2), t1(2), g, ms, cr.begin[2], cr.count[2], fw);
+        // rows of at most kBlockShortRow entries first; the group's start event
+        // goes on its first launch, the stop on its last
+        const int64_t ns = cr.blk_short, nl = cr.count[2] - cr.blk_short;
+        if (ns > 0)
+            dispatch(k_decide_block<WK, LP, kBlockShortThreads, kBlockShortCap>,
+                     dim3((unsigned)(ns < 4096 ? ns : 4096)), dim3(kBlockShortThreads), st, t0(2),
+                     nl > 0 ? (hipEvent_t) nullptr : t1(2), g, ms, cr.begin[2], ns, fw);
+        if (nl > 0)
+            dispatch(k_decide_block<WK, LP, kBlockThreads, kBlockCap>, dim3((unsigned)(nl < 2048 ? nl : 2048)),
+                     dim3(kBlockThreads), st, ns > 0 ? (hipEvent_t) nullptr : t0(2), t1(2), g, ms,
+                     cr.begin[2] + ns, nl, fw);
     }
     if (cr.sgl_count > 0 && (groups & 8u))
         dispatch(k_hub_single<WK, LP>, dim3((unsigned)cr.sgl_count), dim3(kSingleThreads), st, t0(3), t1(3), g, ms,
