@@ -100,7 +100,7 @@ struct HubArrays {
     unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, pad
 };
 
-constexpr int64_t kHubInsChunk = 2048;  // entries per hub chunk workgroup
+constexpr int64_t kHubInsChunk = 1024;  // entries per hub chunk workgroup
 constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
 constexpr int64_t kHubBucketTarget = 1024;  // entries per hash bucket (one agg workgroup each)
 constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol < 2^31) take one workgroup

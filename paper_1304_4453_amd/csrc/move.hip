@@ -595,7 +595,7 @@ __device__ __forceinline__ uint32_t agg_subpart(int32_t x, int qbits) {
     return qbits == 0 ? 0u : ((uint32_t)x * 0xC2B2AE35u) >> (32 - qbits);
 }
 
-constexpr int kMergeBits = 12;
+constexpr int kMergeBits = 11;
 constexpr int kMergeSlots = 1 << kMergeBits;  // a chunk's merge table: at most kHubInsChunk keys, load <= 1/2
 static_assert(2 * kHubInsChunk <= kMergeSlots, "merge table must never fill");
 __device__ __forceinline__ uint32_t merge_slot(int32_t x) {
