@@ -118,12 +118,12 @@ typedef struct {
                               a capture runs (on private non-blocking streams), HIP
                               refuses synchronous copies on the legacy default
                               stream from other host threads of the process. */
-    int32_t hub_stream;    /* branches of a captured sweep: 2 (default): each kernel
-                              group of a class (lane, wavefront, workgroup,
-                              one-workgroup hub, partitioned hub) forms a branch of
-                              its own, all joined before the class's moves apply;
-                              1: only the partitioned-hub kernels branch off; 0: one
-                              chain.  Same results. */
+    int32_t hub_stream;    /* branches of a captured sweep: 2 (default): a class's
+                              kernel groups run as three branches (lane, wavefront
+                              and one-workgroup hub; workgroup; partitioned hub),
+                              joined before the class's moves apply; 1: only the
+                              partitioned-hub kernels branch off; 0: one chain.
+                              Same results. */
     int32_t colour_tail;   /* 1 (default): once a colouring round's frontier is
                               small, the following rounds run back to back inside
                               one workgroup (one launch for many rounds); 0: every

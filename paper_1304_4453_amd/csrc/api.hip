@@ -184,6 +184,10 @@ struct plm_ctx {
     // capture stream of the partitioned-hub branch of a captured sweep
     // (hub_stream), and a ring of fork/join events
     static constexpr int kAux = 4;  // branches beside the capture stream
+    // kernel groups per branch with hub_stream = 2 (bit i: group i = lane,
+    // wavefront, workgroup, one-workgroup hub, partitioned hub); measured on
+    // R-MAT 26 against one branch per group and two other groupings
+    static constexpr unsigned kBranchGroups[3] = {1u | 2u | 8u, 4u, 16u};
     hipStream_t hub_cap_st[kAux] = {};
     static constexpr int kForkRing = 16;
     hipEvent_t fork_ev[kForkRing] = {}, join_ev[kAux][kForkRing] = {};
@@ -519,8 +523,8 @@ struct plm_ctx {
                                          (cr.count[2] > 0 ? 4u : 0u) | (cr.sgl_count > 0 ? 8u : 0u) |
                                          (cr.red_count > 0 ? 16u : 0u);
                 if (branches == 2) {
-                    for (int b = 0; b < 5; ++b)
-                        if ((present >> b) & 1u) part[np++] = 1u << b;
+                    for (const unsigned grp : kBranchGroups)
+                        if (present & grp) part[np++] = present & grp;
                 } else {
                     if (present & 15u) part[np++] = present & 15u;
                     if (present & 16u) part[np++] = 16u;
