@@ -61,6 +61,10 @@ struct LevelData {
     // the first node of each graph (count + 1 entries)
     int32_t *gid = nullptr;
     int64_t *gbase = nullptr;
+    // colouring of this level kept by a descent that refines on its way back
+    // up (the refinement's colouring is the same: same graph, seed and level)
+    int32_t *colour_kept = nullptr;
+    int32_t ncol_kept = 0;
 
     GraphView view() const {
         GraphView g;
@@ -70,6 +74,7 @@ struct LevelData {
     }
     void release() {
         dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase);
+        dev_free(colour_kept);
     }
 };
 
@@ -801,6 +806,12 @@ struct plm_ctx {
         for (;;) {
             double t0 = now_ms();
             build_schedule();
+            if (refine) {  // refine_up below reuses it
+                LevelData &l = L();
+                if (!l.colour_kept && l.n > 0) l.colour_kept = dev_alloc<int32_t>(l.n);
+                if (l.n > 0) HIPCHK(hipMemcpyAsync(l.colour_kept, colour, l.n * 4, hipMemcpyDeviceToDevice, st));
+                l.ncol_kept = ncol;
+            }
             double t1 = now_ms();
             int64_t skipped = 0;
             int64_t moves = move_phase(&skipped);
@@ -862,7 +873,10 @@ struct plm_ctx {
             launch_comm_vol(zeta, vol, nl, volC, st);
             sched = false;
             sweeps = 0;
-            build_schedule();
+            // the colouring this level had on the way down (kept by descend)
+            if (nl > 0) HIPCHK(hipMemcpyAsync(colour, lv.colour_kept, nl * 4, hipMemcpyDeviceToDevice, st));
+            ncol = lv.ncol_kept;
+            build_plan(nullptr);
             int64_t skipped = 0;
             int64_t moves = move_phase(&skipped);
             if (l < PLM_MAX_LEVELS) {
