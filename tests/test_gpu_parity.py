@@ -441,7 +441,7 @@ def test_graph_sweeps_batch_equal_eager(P):
 
 
 # ------------------------------------------------------------------ colouring rounds inside one workgroup
-def _tail_handoff_graph(seed, m=8000, chain=20):
+def _tail_handoff_graph(seed, m=20000, chain=20):
     """A chain of `chain` nodes in descending priority ending at a star centre
     of m lower-priority leaves: the frontiers hold one node for chain + 1
     rounds (the one-workgroup tail takes over after the first grid rounds),
