@@ -13,8 +13,10 @@
 // otherwise the node takes the 128-bit path.  Ties go to the lowest X.
 //
 // Degree bins: rows up to 16 entries are handled one lane per node (register
-// arrays), up to the wave limit one wavefront per node (LDS hash table), up to
-// the block limit one workgroup per node (LDS hash table), and longer rows
+// arrays), up to the wave limit one wavefront per node (LDS hash table; rows
+// of at most kQuadRow entries 16 lanes per node), up to the block limit one
+// workgroup per node (LDS hash table; 256 threads for rows of at most
+// kBlockShortRow entries, 512 above), and longer rows
 // ("hubs") by one 1024-thread workgroup with a 16384-slot LDS table when the
 // row has at most kSingleMaxRow entries, else by several workgroups per node
 // through hash-partitioned staging.  The LDS tables sum weights in 32 bits:
