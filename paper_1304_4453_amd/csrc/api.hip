@@ -671,7 +671,8 @@ struct plm_ctx {
 
     // one sweep; from the third of a move phase on, replayed from the sweep graph
     int64_t sweep(bool allow_graph = false) {
-        int64_t mv = run_classes(0, ncol_or_build(), allow_graph && sweeps >= 2);
+        // every sweep of a plan replays the graph captured at its first sweep
+        int64_t mv = run_classes(0, ncol_or_build(), allow_graph);
         ++sweeps;
         return mv;
     }
