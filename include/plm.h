@@ -110,9 +110,9 @@ typedef struct {
      * The reported Q stays the plain modularity (gamma = 1). */
     int32_t gamma_num;
     int32_t gamma_den;
-    int32_t graph_sweeps;  /* 1 (default): the sweeps of a level's move phase (from
-                              the third iteration of label propagation on) replay
-                              their launches from a HIP graph captured once per plan;
+    int32_t graph_sweeps;  /* 1 (default): the sweeps of a level's move phase and
+                              the iterations of label propagation replay their
+                              launches from a HIP graph captured once per plan;
                               0: every launch is issued one by one.  Same results.
                               Timed runs (timing = 1) always launch one by one.  While
                               a capture runs (on private non-blocking streams), HIP

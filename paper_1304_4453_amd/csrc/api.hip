@@ -911,7 +911,7 @@ struct plm_ctx {
         int32_t it = 0;
         try {
             while (updated * 100000 > l.n && it < max_iters) {
-                updated = run_classes(0, ncol, it >= 2);
+                updated = run_classes(0, ncol, true);
                 if (upd) upd[it] = updated;
                 if (opt.timing) {
                     stats.lp_decide_ms += last_ms;

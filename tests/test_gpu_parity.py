@@ -396,10 +396,10 @@ def test_sweep_cycles_fast_forward(P, max_sweeps):
 
 # ------------------------------------------------------------------ sweeps replayed from a HIP graph
 def test_graph_sweeps_equal_eager(P):
-    """graph_sweeps: from the third sweep of a level on, a sweep is replayed
-    from a captured HIP graph; hub_stream: the partitioned-hub kernels (1) or
-    every kernel group of a class (2) run as forked branches inside the
-    captured graph.
+    """graph_sweeps: every sweep of a move phase (and every label-propagation
+    iteration) is replayed from a HIP graph captured once per plan;
+    hub_stream: the partitioned-hub kernels (1) or a class's kernel groups in
+    three branches (2) run as forked branches inside the captured graph.
     Replays are interleaved with eager work (counter clears, read-backs,
     re-planning); every combination must equal the plain one and the oracle."""
     _say("graph sweeps / hub stream vs eager")
