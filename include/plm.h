@@ -128,6 +128,18 @@ typedef struct {
                               small, the following rounds run back to back inside
                               one workgroup (one launch for many rounds); 0: every
                               round is a grid launch.  Same colours. */
+    /* Limits of the partitioned hub path (section III-B's per-node community
+     * accumulation spread over several workgroups), lowered only to exercise
+     * its rarely reached branches on small graphs; same results, slower.
+     * 0 = the default of each. */
+    int32_t hub_row_max;   /* hub-bin rows longer than this (default 12288, else
+                              1..12288) take the partitioned path instead of one
+                              1024-thread workgroup */
+    int32_t agg_max_keys;  /* distinct communities one bucket workgroup takes in a
+                              pass before it splits the bucket into sub-partition
+                              passes (default 1536, else 32..1536) */
+    int32_t agg_tile;      /* chunks whose bucket segments a bucket workgroup
+                              flattens at once (default 512, else 1..512) */
 } plm_options;
 
 /* Fills *opt with the defaults above. */

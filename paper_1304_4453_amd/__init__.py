@@ -41,7 +41,8 @@ class plm_options(ctypes.Structure):
                 ("bin_lane", ctypes.c_int32), ("bin_wave", ctypes.c_int32), ("bin_block", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32),
-                ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32)]
+                ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32), ("hub_row_max", ctypes.c_int32),
+                ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32)]
 
 
 class plm_level_info_t(ctypes.Structure):

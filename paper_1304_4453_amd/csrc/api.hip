@@ -246,6 +246,7 @@ struct plm_ctx {
     int64_t bin_lane() const { return opt.bin_lane > 0 ? opt.bin_lane : 16; }
     int64_t bin_wave() const { return opt.bin_wave > 0 ? opt.bin_wave : 512; }
     int64_t bin_block() const { return opt.bin_block > 0 ? opt.bin_block : 4096; }
+    int64_t single_max_row() const { return opt.hub_row_max > 0 ? opt.hub_row_max : kSingleMaxRow; }
 
     // ---------------------------------------------------------------- level set-up
     void init_level() {
@@ -417,7 +418,7 @@ struct plm_ctx {
             for (int64_t i = 0; i < cr.hub_count; ++i, ++hg) {
                 hpos[hg] = (int32_t)pos[hg];
                 int64_t d = deg[hg] < 0 ? -deg[hg] : deg[hg];
-                if (deg[hg] > 0 && d <= kSingleMaxRow) {
+                if (deg[hg] > 0 && d <= single_max_row()) {
                     shub.push_back((int32_t)hg);
                     ++sgl_nodes;
                     sgl_entries += d;
@@ -504,6 +505,8 @@ struct plm_ctx {
         ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
         ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
         ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part; ha.hub_base = hub_base;
+        ha.agg_max_keys = opt.agg_max_keys > 0 ? opt.agg_max_keys : 0;
+        ha.agg_tile = opt.agg_tile > 0 ? opt.agg_tile : 0;
         return ha;
     }
 
@@ -1173,6 +1176,15 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.graph_sweeps != 0 && o.graph_sweeps != 1) { msg = "graph_sweeps must be 0 or 1"; return PLM_E_ARG; }
     if (o.hub_stream < 0 || o.hub_stream > 2) { msg = "hub_stream must be 0, 1 or 2"; return PLM_E_ARG; }
     if (o.colour_tail != 0 && o.colour_tail != 1) { msg = "colour_tail must be 0 or 1"; return PLM_E_ARG; }
+    if (o.hub_row_max < 0 || o.hub_row_max > kSingleMaxRow) {
+        msg = "hub_row_max must be 0 or lie in [1, 12288]";
+        return PLM_E_ARG;
+    }
+    if (o.agg_max_keys != 0 && (o.agg_max_keys < 32 || o.agg_max_keys > 1536)) {
+        msg = "agg_max_keys must be 0 or lie in [32, 1536]";
+        return PLM_E_ARG;
+    }
+    if (o.agg_tile < 0 || o.agg_tile > 512) { msg = "agg_tile must be 0 or lie in [1, 512]"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";

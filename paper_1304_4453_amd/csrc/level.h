@@ -98,6 +98,9 @@ struct HubArrays {
     int64_t *wd_part;          // per chunk workgroup: its share of w(u, D \ u)
     int64_t *hub_base;         // per hub: vol(D \ u) at the start of its class
     unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, pad
+    // lowered limits of the bucket workgroups (0 = the compiled ones): new
+    // communities per pass, and chunks flattened at once
+    int32_t agg_max_keys = 0, agg_tile = 0;
 };
 
 constexpr int64_t kHubInsChunk = 1024;  // entries per hub chunk workgroup

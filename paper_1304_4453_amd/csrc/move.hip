@@ -765,6 +765,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     const int32_t *sx = ha.stg_x + ha.stg_off[hg];
     const int64_t *sw = ha.stg_w + ha.stg_off[hg];
     constexpr int kPer = kAggTile / kHubThreads;
+    const int32_t max_keys = ha.agg_max_keys > 0 ? ha.agg_max_keys : kAggMaxKeys;
+    const int32_t tile = ha.agg_tile > 0 ? ha.agg_tile : kAggTile;
     for (int qbits = 0;; ++qbits) {
         G pbs = neg_inf<G>();
         int32_t pbx = kNone;
@@ -775,8 +777,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
             if (threadIdx.x == 0) { *nkeys = 0; *overflow = 0; }
             __syncthreads();
             bool stop = false;
-            for (int32_t t0 = 0; t0 < nch; t0 += kAggTile) {
-                const int32_t tn = nch - t0 < kAggTile ? nch - t0 : kAggTile;
+            for (int32_t t0 = 0; t0 < nch; t0 += tile) {
+                const int32_t tn = nch - t0 < tile ? nch - t0 : tile;
                 // segment lengths of this tile's chunks, exclusive prefix into cpre
                 int32_t cnt[kPer], loc = 0;
 #pragma unroll
@@ -831,7 +833,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                         uint32_t h = agg_slot(X[b]);
                         for (;;) {
                             int32_t kk = atomicCAS(&tk[h], kEmpty, X[b]);
-                            if (kk == kEmpty && atomicAdd(nkeys, 1) >= kAggMaxKeys) {
+                            if (kk == kEmpty && atomicAdd(nkeys, 1) >= max_keys) {
                                 *overflow = 1;
                                 stop = true;
                                 break;
