@@ -39,9 +39,9 @@ class _Trace(ctypes.Structure):
 
 
 def build(force: bool = True) -> None:
-    """Compile the oracle (gcc, single-threaded, -O2)."""
+    """Compile the oracle (gcc -O2; OpenMP only for the optional threads of orc_sweep_mt)."""
     if force or not os.path.exists(_SO):
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", _SRC, "-o", _SO])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", _SO])
 
 
 _lib = None
@@ -72,6 +72,8 @@ def lib():
         L.orc_class_step.restype = i64
         L.orc_sweep.argtypes = [i64, P64, P32, P64, P64, i64, i64, i64, P32, i64, P32, P64]
         L.orc_sweep.restype = i64
+        L.orc_sweep_mt.argtypes = [i64, P64, P32, P64, P64, i64, i64, i64, P32, i64, P32, P64, i32]
+        L.orc_sweep_mt.restype = i64
         L.orc_relabel.argtypes = [i64, P32, P32]; L.orc_relabel.restype = i64
         L.orc_contract.argtypes = [i64, P64, P32, P64, P32, i64, P64, P32, P64]; L.orc_contract.restype = i64
         L.orc_modularity.argtypes = [i64, P64, P32, P64, P32, P64, PU64, P64, PU64]
@@ -188,6 +190,16 @@ def sweep(off, col, w2, vol, S, colours, ncol, zeta, volC, gamma=(1, 1)) -> int:
                                _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S, gamma[0], gamma[1],
                                _p(colours, ctypes.c_int32),
                                ncol, _p(zeta, ctypes.c_int32), _p(volC, ctypes.c_int64)))
+
+
+def sweep_mt(off, col, w2, vol, S, colours, ncol, zeta, volC, threads: int, gamma=(1, 1)) -> int:
+    """sweep() with each class's decisions spread over `threads` threads (same result)."""
+    off, col, w2, vol, colours = _i64(off), _i32(col), _i64(w2), _i64(vol), _i32(colours)
+    assert zeta.dtype == np.int32 and volC.dtype == np.int64
+    return int(lib().orc_sweep_mt(off.shape[0] - 1, _p(off, ctypes.c_int64), _p(col, ctypes.c_int32),
+                                  _p(w2, ctypes.c_int64), _p(vol, ctypes.c_int64), S, gamma[0], gamma[1],
+                                  _p(colours, ctypes.c_int32), ncol, _p(zeta, ctypes.c_int32),
+                                  _p(volC, ctypes.c_int64), threads))
 
 
 def relabel(zeta):

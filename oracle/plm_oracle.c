@@ -43,6 +43,13 @@
 
 typedef __int128 i128;
 
+#ifdef _OPENMP
+#include <omp.h>
+static int orc_thread(void) { return omp_get_thread_num(); }
+#else
+static int orc_thread(void) { return 0; }
+#endif
+
 /* ------------------------------------------------------------------ hashing */
 /* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): one step from state x. */
 uint64_t orc_splitmix64(uint64_t x) {
@@ -227,6 +234,9 @@ void orc_decide_many(int64_t n, int64_t count, const int32_t *nodes, const int64
 /* One class step: every node of class c decides against the volumes at the
  * start of the class, then all moves are applied.  Returns the move count.
  * `members`/`count` list the class; decisions[] is scratch of size count. */
+static int64_t orc_apply_class(const int32_t *members, int64_t count, const int32_t *decisions, const int64_t *vol,
+                               int32_t *zeta, int64_t *volC);
+
 static int64_t orc_class_step_m(const int32_t *members, int64_t count, const int64_t *off, const int32_t *col,
                                 const int64_t *w2, const int64_t *vol, int64_t S, int64_t gp, int64_t gq,
                                 int32_t *zeta, int64_t *volC, int32_t *decisions, orc_map *m) {
@@ -234,6 +244,12 @@ static int64_t orc_class_step_m(const int32_t *members, int64_t count, const int
         i128 g;
         decisions[i] = orc_decide_m(members[i], off, col, w2, zeta, volC, vol, S, gp, gq, m, &g);
     }
+    return orc_apply_class(members, count, decisions, vol, zeta, volC);
+}
+
+/* The moves of a class, applied after all its decisions were taken. */
+static int64_t orc_apply_class(const int32_t *members, int64_t count, const int32_t *decisions, const int64_t *vol,
+                               int32_t *zeta, int64_t *volC) {
     int64_t moves = 0;
     for (int64_t i = 0; i < count; ++i) {
         int32_t X = decisions[i];
@@ -295,6 +311,39 @@ int64_t orc_sweep(int64_t n, const int64_t *off, const int32_t *col, const int64
                                   zeta, volC, dec, &m);
     orc_map_free(&m);
     free(cls_off); free(cls_nodes); free(dec);
+    return moves;
+}
+
+/* One sweep whose class decisions are spread over `threads` threads (for
+ * writing stored expected values of very large graphs in reasonable time).
+ * The members of a class are pairwise non-adjacent and every one of them
+ * decides against the state at the class start, so the decisions do not
+ * depend on each other or on the order in which they are taken; they are then
+ * applied exactly as in orc_sweep.  The result equals orc_sweep's for any
+ * thread count.  Returns the move count, or -1 if threads < 1. */
+int64_t orc_sweep_mt(int64_t n, const int64_t *off, const int32_t *col, const int64_t *w2, const int64_t *vol,
+                     int64_t S, int64_t gp, int64_t gq, const int32_t *colour, int64_t ncol, int32_t *zeta,
+                     int64_t *volC, int32_t threads) {
+    if (threads < 1) return -1;
+    int64_t *cls_off = (int64_t *)malloc((size_t)(ncol + 1) * sizeof(int64_t));
+    int32_t *cls_nodes = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *dec = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    orc_classes(n, colour, ncol, cls_off, cls_nodes);
+    orc_map *maps = (orc_map *)malloc((size_t)threads * sizeof(orc_map));
+    for (int32_t t = 0; t < threads; ++t) orc_map_init(&maps[t], n);
+    int64_t moves = 0;
+    for (int64_t c = 0; c < ncol; ++c) {
+        const int32_t *mem = cls_nodes + cls_off[c];
+        const int64_t count = cls_off[c + 1] - cls_off[c];
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 64) if (threads > 1 && count >= 1024)
+        for (int64_t i = 0; i < count; ++i) {
+            i128 g;
+            dec[i] = orc_decide_m(mem[i], off, col, w2, zeta, volC, vol, S, gp, gq, &maps[orc_thread()], &g);
+        }
+        moves += orc_apply_class(mem, count, dec, vol, zeta, volC);
+    }
+    for (int32_t t = 0; t < threads; ++t) orc_map_free(&maps[t]);
+    free(maps); free(cls_off); free(cls_nodes); free(dec);
     return moves;
 }
 

@@ -14,10 +14,12 @@ The run follows the oracle's full run (orc_run) step for step, through the
 oracle's exported steps: volumes, colouring, sweeps until one moves nothing or
 32 have run, relabel, contraction while communities merged, composition of the
 fine-to-coarse maps, canonical labels, modularity on the input graph.  It
-needs about 55 GB of host memory at the level-0 contraction and a few hours of
-one core.
+needs about 55 GB of host memory at the level-0 contraction.  The decisions
+of each colour class may be spread over threads (orc_sweep_mt: same result as
+the oracle's plain sweep); single-threaded, one level-0 sweep takes about half
+an hour.
 
-    python tests/golden/make_rmat26_golden.py [--ckpt DIR]
+    python tests/golden/make_rmat26_golden.py [--ckpt DIR] [--threads T]
 
 --ckpt DIR keeps each finished level's state on disk and resumes from it.
 """
@@ -72,7 +74,7 @@ def host():
                 break
     except OSError:
         pass
-    return {"cpu": cpu, "logical_cores": os.cpu_count(), "threads_used": 1}
+    return {"cpu": cpu, "logical_cores": os.cpu_count()}
 
 
 def generate():
@@ -97,6 +99,7 @@ def main():
     ap.add_argument("--ckpt", default=None, help="directory for per-level checkpoints (resume)")
     ap.add_argument("--scale", type=int, default=26, help="smaller scales write rmat<scale>_oracle.json (trial runs)")
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--threads", type=int, default=1, help="threads of the class decisions (same result)")
     args = ap.parse_args()
     global SCALE, SEED, OUT
     SCALE, SEED = args.scale, args.seed
@@ -105,7 +108,7 @@ def main():
     rec = {"workload": f"R-MAT scale {SCALE}, edge factor 16, a=.57 b=.19 c=.19 d=.05, symmetrised, loops and "
                        f"duplicates removed, integer weights uniform in [1,100], seed {SEED}",
            "options": {"max_sweeps": MAX_SWEEPS, "max_levels": 0, "schedule": 0, "colour_seed": 0, "gamma": [1, 1]},
-           "host": host(), "complete": False, "levels": []}
+           "host": dict(host(), decision_threads=args.threads), "complete": False, "levels": []}
     t0 = time.time()
     say("generate")
     g, w2 = generate()
@@ -130,34 +133,49 @@ def main():
             zeta = z["zeta"]
             say(f"level {level}: resumed from checkpoint")
         else:
-            lv = {"level": level, "n": ln, "nnz": lnnz}
-            if level > 0:
-                lv.update(off_sha256=sha(off), col_sha256=sha(col), w_sha256=sha(lw))
             vol = np.empty(max(ln, 1), np.int64)
             t = time.time()
             S = int(L.orc_volumes(ln, p(off, P64), p(lw, P64), p(vol, P64)))
-            lv["S"] = S
-            lv["vol_sha256"] = sha(vol[:ln])
-            colour = np.empty(max(ln, 1), np.int32)
-            ncol = int(L.orc_colour(ln, p(off, P64), p(col, P32), 0, level, 0, p(colour, P32)))
-            lv["colour_seconds"] = time.time() - t
-            lv["colours"] = ncol
-            lv["colour_sha256"] = sha(colour[:ln])
-            lv["class_sizes_sha256"] = sha(np.bincount(colour[:ln], minlength=ncol).astype(np.int64))
-            say(f"level {level}: n={ln} nnz={lnnz} S={S} colours={ncol} ({lv['colour_seconds']:.0f} s)")
-            zeta = np.arange(max(ln, 1), dtype=np.int32)
-            volC = vol.copy()
-            lv["sweeps"] = []
-            for s in range(MAX_SWEEPS):
+            cks = os.path.join(ck, f"level{level}_sweeps.npz") if ck else None
+            if cks and os.path.exists(cks) and os.path.exists(cks + ".json"):
+                # resume inside the level: colouring and the state after the last finished sweep
+                lv = json.load(open(cks + ".json"))
+                z = np.load(cks)
+                colour, zeta, volC = z["colour"], z["zeta"], z["volC"]
+                ncol = lv["colours"]
+                say(f"level {level}: resumed after sweep {len(lv['sweeps'])}")
+            else:
+                lv = {"level": level, "n": ln, "nnz": lnnz}
+                if level > 0:
+                    lv.update(off_sha256=sha(off), col_sha256=sha(col), w_sha256=sha(lw))
+                lv["S"] = S
+                lv["vol_sha256"] = sha(vol[:ln])
+                colour = np.empty(max(ln, 1), np.int32)
+                ncol = int(L.orc_colour(ln, p(off, P64), p(col, P32), 0, level, 0, p(colour, P32)))
+                lv["colour_seconds"] = time.time() - t
+                lv["colours"] = ncol
+                lv["colour_sha256"] = sha(colour[:ln])
+                lv["class_sizes_sha256"] = sha(np.bincount(colour[:ln], minlength=ncol).astype(np.int64))
+                say(f"level {level}: n={ln} nnz={lnnz} S={S} colours={ncol} ({lv['colour_seconds']:.0f} s)")
+                zeta = np.arange(max(ln, 1), dtype=np.int32)
+                volC = vol.copy()
+                lv["sweeps"] = []
+            for s in range(len(lv["sweeps"]), MAX_SWEEPS):
+                if lv["sweeps"] and lv["sweeps"][-1]["moves"] == 0:
+                    break
                 t = time.time()
-                mv = int(L.orc_sweep(ln, p(off, P64), p(col, P32), p(lw, P64), p(vol, P64), S, 1, 1,
-                                     p(colour, P32), ncol, p(zeta, P32), p(volC, P64)))
+                mv = int(L.orc_sweep_mt(ln, p(off, P64), p(col, P32), p(lw, P64), p(vol, P64), S, 1, 1,
+                                        p(colour, P32), ncol, p(zeta, P32), p(volC, P64), args.threads))
                 dt = time.time() - t
                 lv["sweeps"].append({"moves": mv, "zeta_sha256": sha(zeta[:ln]), "volc_sha256": sha(volC[:ln]),
                                      "seconds": dt})
                 say(f"level {level} sweep {s + 1}: moves={mv} ({dt:.0f} s)")
                 rec["levels_partial"] = rec["levels"] + [lv]
                 save(rec)
+                if cks and ln > (1 << 20):
+                    np.savez(cks + ".tmp.npz", colour=colour, zeta=zeta, volC=volC)
+                    os.replace(cks + ".tmp.npz", cks)
+                    json.dump(lv, open(cks + ".json", "w"))
                 if mv == 0:
                     break
             del vol, volC, colour

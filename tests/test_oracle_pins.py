@@ -242,6 +242,28 @@ def test_converged_sweep_is_locally_optimal(seed):
             assert _N(g, w2, z2) - N0 <= 0
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+def test_threaded_sweep_equals_plain_sweep(threads):
+    """orc_sweep_mt (class decisions spread over threads, for writing stored
+    values of very large graphs) leaves the same communities, volumes and move
+    counts as orc_sweep, sweep after sweep, on graphs with classes large enough
+    to be split."""
+    for g, seed in ((graphgen.rmat(13, 16, seed=41, weighted=True), 1),
+                    (graphgen.random_graph(400, 0.05, seed=42, weighted=True, loops=0.1), 2),
+                    (graphgen.planted_partition_1000(seed=3), 3)):
+        w2 = oracle.double_diagonal(g.off, g.col, g.w)
+        vol, S = oracle.volumes(g.off, w2)
+        colours, C = oracle.colour(g.off, g.col, seed=seed)
+        z1 = np.arange(g.n, dtype=np.int32); v1 = vol.copy()
+        z2 = z1.copy(); v2 = vol.copy()
+        for _ in range(6):
+            m1 = oracle.sweep(g.off, g.col, w2, vol, S, colours, C, z1, v1)
+            m2 = oracle.sweep_mt(g.off, g.col, w2, vol, S, colours, C, z2, v2, threads)
+            assert m1 == m2 and np.array_equal(z1, z2) and np.array_equal(v1, v2)
+            if m1 == 0:
+                break
+
+
 # ------------------------------------------------------------------ coarsening
 @pytest.mark.parametrize("seed", range(8))
 def test_contraction_invariants(seed):
