@@ -212,6 +212,21 @@ plm_status plm_epp(plm_ctx *ctx, int32_t ensemble_size, int32_t plp_iters, int32
  * divided.  PLM_E_ARG for labels out of range. */
 plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind, double *q_out);
 
+/* plm_modularity without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same value as plm_modularity, bit for bit.
+ * labels: device memory (n int32, values in [0, n)).  Its workspace (the
+ * volume of every label and four counters) is a static device array of
+ * PLM_NOALLOC_MAX_NODES * 8 + 256 bytes (64 MiB + 256 B) per device, held
+ * until the process ends and whose address is taken at plm_create; so the
+ * input graph may have at most PLM_NOALLOC_MAX_NODES nodes (else PLM_E_ARG)
+ * and a batched context is PLM_E_STATE.  Every call on a device shares that
+ * device's workspace (each call clears what it uses, with kernels): calls that
+ * overlap on one device race, so callers serialise them.  PLM_E_ARG for labels
+ * out of range or NULL. */
+#define PLM_NOALLOC_MAX_NODES (1LL << 23)
+plm_status plm_modularity_noalloc(plm_ctx *ctx, const int32_t *labels, double *q_out);
+
 /* ---------------------------------------------------------------- batches
  * Many independent graphs run Algorithm 3 together, each with the result of a
  * separate plm_run on it (same labels, modularity and number of levels): the

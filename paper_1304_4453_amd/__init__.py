@@ -6,7 +6,8 @@ HIP kernels of ``libplm.so``.  There is no CPU fallback; importing the binding
 without a built library raises.
 
 Low level: ``plm_create``, ``plm_move_sweep``, ``plm_move_class``,
-``plm_coarsen``, ``plm_run``, ``plm_plp``, ``plm_epp``, ``plm_modularity``, ``plm_reset``,
+``plm_coarsen``, ``plm_run``, ``plm_plp``, ``plm_epp``, ``plm_modularity``,
+``plm_modularity_noalloc``, ``plm_reset``,
 ``plm_destroy``, ``plm_last_error``, ``plm_level_info``, ``plm_get_state``,
 ``plm_get_graph``, ``plm_get_stats``, ``plm_default_options`` (ctypes functions
 with the C signatures).  ``Context`` wraps them for numpy (host) and torch
@@ -103,6 +104,7 @@ def _load():
     lib.plm_plp.argtypes = [vp, i32, vp, P(dbl), P(i32), P(i64)]
     lib.plm_epp.argtypes = [vp, i32, i32, vp, P(dbl), P(i32), P(i64)]
     lib.plm_modularity.argtypes = [vp, vp, i32, P(dbl)]
+    lib.plm_modularity_noalloc.argtypes = [vp, vp, P(dbl)]
     lib.plm_reset.argtypes = [vp]
     lib.plm_destroy.argtypes = [vp]
     lib.plm_destroy.restype = None
@@ -126,6 +128,7 @@ def _load():
     lib.plm_server_last_error.restype = ctypes.c_char_p
     for f in ("plm_create", "plm_batch_create", "plm_batch_run", "plm_server_create", "plm_server_submit",
               "plm_server_step", "plm_server_wait", "plm_server_result", "plm_server_info", "plm_move_sweep", "plm_move_class", "plm_coarsen", "plm_run", "plm_plp", "plm_epp", "plm_modularity",
+              "plm_modularity_noalloc",
               "plm_reset", "plm_level_info", "plm_get_state", "plm_get_graph", "plm_get_stats"):
         getattr(lib, f).restype = i32
     return lib
@@ -142,6 +145,8 @@ plm_run = _lib.plm_run
 plm_plp = _lib.plm_plp
 plm_epp = _lib.plm_epp
 plm_modularity = _lib.plm_modularity
+plm_modularity_noalloc = _lib.plm_modularity_noalloc
+PLM_NOALLOC_MAX_NODES = 1 << 23
 plm_reset = _lib.plm_reset
 plm_destroy = _lib.plm_destroy
 plm_last_error = _lib.plm_last_error
@@ -282,6 +287,13 @@ class Context:
             labels = np.ascontiguousarray(labels, dtype=np.int32)
         q = ctypes.c_double()
         self._check(plm_modularity(self._c, _ptr(labels), mem_kind, ctypes.byref(q)))
+        return q.value
+
+    def modularity_noalloc(self, labels) -> float:
+        """plm_modularity_noalloc: labels in device memory (torch int32 tensor
+        or address); no device allocation inside the call."""
+        q = ctypes.c_double()
+        self._check(plm_modularity_noalloc(self._c, _ptr(labels), ctypes.byref(q)))
         return q.value
 
     def reset(self):

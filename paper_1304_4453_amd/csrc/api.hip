@@ -5,6 +5,7 @@
 
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,17 @@ using namespace plm;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Workspace of plm_modularity_noalloc: the volume of every label (int64) and
+// four counters.  One copy per device, held until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns on that
+// device (noalloc_workspace), never through the array's name.
+constexpr int64_t kNoAllocMaxNodes = PLM_NOALLOC_MAX_NODES;
+constexpr size_t kNoAllocBytes = (size_t)kNoAllocMaxNodes * 8 + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kNoAllocDevices = 64;
+void *g_noalloc_ptr[kNoAllocDevices] = {};
+std::mutex g_noalloc_mu;
 
 // batched runs: rebuild the class buckets when the graphs still sweeping hold
 // less than this fraction of the planned entries
@@ -154,6 +166,7 @@ struct plm_ctx {
     int64_t sgl_nodes = 0, sgl_entries = 0;  // hubs of the one-workgroup path
     int64_t loops = 0;  // self-loop entries of the current level
     int64_t *hbuf = nullptr;             // pinned host scratch (kHostWords int64)
+    void *noalloc_ws = nullptr;          // this device's plm_modularity_noalloc workspace
     Scratch scr;
     plm_stats_t stats;
     std::vector<hipEvent_t> events;
@@ -1226,6 +1239,26 @@ void copy_out(void *dst, const void *src, size_t bytes, int mem_kind, hipStream_
                           st));
 }
 
+// Address of the current device's static workspace, looked up once per device
+// (with that device current) at context creation.
+void *noalloc_workspace() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) throw Error{PLM_E_DEVICE, "device index beyond the workspace table"};
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw Error{PLM_E_DEVICE, std::string("hipGetSymbolAddress of the static workspace failed: ") +
+                                          hipGetErrorString(e)};
+        }
+        g_noalloc_ptr[dev] = p;
+    }
+    return g_noalloc_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1313,6 +1346,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c->mem_kind = mem_kind;
         c->n0 = n;
         HIPCHK(hipHostMalloc((void **)&c->hbuf, kHostWords * sizeof(int64_t), hipHostMallocDefault));
+        c->noalloc_ws = noalloc_workspace();
         LevelData l0;
         l0.n = n;
         l0.nnz = nnz;
@@ -1568,6 +1602,29 @@ plm_status plm_modularity(plm_ctx *ctx, const int32_t *labels, int32_t mem_kind,
             throw;
         }
         dev_free(tmp);
+    });
+}
+
+plm_status plm_modularity_noalloc(plm_ctx *ctx, const int32_t *labels, double *q_out) {
+    return guarded(ctx, [&] {
+        reject_batch(ctx, "plm_modularity_noalloc");
+        if (!labels && ctx->n0 > 0) throw Error{PLM_E_ARG, "labels is NULL"};
+        if (ctx->n0 > kNoAllocMaxNodes)
+            throw Error{PLM_E_ARG, "plm_modularity_noalloc takes at most 2^23 nodes (its static workspace)"};
+        if (!ctx->noalloc_ws) throw Error{PLM_E_STATE, "no workspace address for this context's device"};
+        if (modularity_ws_bytes(ctx->n0) > kNoAllocBytes) throw Error{PLM_E_STATE, "internal: workspace too small"};
+        if (ctx->n0 > 0) {
+            hipPointerAttribute_t at;
+            hipError_t e = hipPointerGetAttributes(&at, labels);
+            if (e != hipSuccess) (void)hipGetLastError();
+            if (e != hipSuccess || at.type != hipMemoryTypeDevice)
+                throw Error{PLM_E_ARG, "labels must be device memory"};
+        }
+        __int128 num, den;
+        if (modularity_parts_ws(ctx->levels[0].view(), ctx->vol0, labels, ctx->S, ctx->noalloc_ws, ctx->hbuf, &num,
+                                &den, ctx->st) != 0)
+            throw Error{PLM_E_ARG, "labels must lie in [0, n)"};
+        if (q_out) *q_out = ctx->S == 0 ? 0.0 : (double)num / (double)den;
     });
 }
 

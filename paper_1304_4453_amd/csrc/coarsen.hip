@@ -472,17 +472,25 @@ __global__ __launch_bounds__(kT) void k_sum_sq(const int64_t *volL, int64_t n, u
     }
 }
 
-int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, Scratch &scr,
-                     int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st) {
+// zero fill of n int64 words (a kernel rather than a memset node, so a caller
+// may capture it)
+__global__ void k_zero_i64(int64_t *a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) a[i] = 0;
+}
+
+size_t modularity_ws_bytes(int64_t n) { return align_up((size_t)(n > 0 ? n : 1) * 8) + 4 * 8; }
+
+int modularity_parts_ws(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, void *ws,
+                        int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st) {
     int64_t n = g0.n;
     *den = (__int128)S * (__int128)S;
     if (n == 0) { *num = 0; return 0; }
-    scr.reserve(align_up(n * 8) + 4 * 256);
-    int64_t *volL = (int64_t *)scr.get(n * 8);
-    unsigned long long *cnt = (unsigned long long *)scr.get(4 * 8);  // [I2, sq lo, sq hi, bad]
-    HIPCHK(hipMemsetAsync(cnt, 0, 4 * 8, st));
-    HIPCHK(hipMemsetAsync(volL, 0, n * 8, st));
-    dim3 grid((unsigned)cdiv(n, kT));
+    int64_t *volL = (int64_t *)ws;
+    unsigned long long *cnt = (unsigned long long *)((char *)ws + align_up((size_t)n * 8));  // [I2, sq lo, sq hi, bad]
+    const int64_t nb = cdiv(n, kT);
+    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(kT), 0, st, volL, n);
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kT), 0, st, (int64_t *)cnt, (int64_t)4);
+    dim3 grid((unsigned)nb);
     hipLaunchKernelGGL(k_label_check, grid, dim3(kT), 0, st, labels, n, (int32_t *)(cnt + 3));
     HIPCHK(hipMemcpyAsync(host_i64, cnt + 3, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -496,7 +504,6 @@ int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *la
             default: hipLaunchKernelGGL(k_intra<2>, eg, dim3(kT), 0, st, g0, labels, cnt); break;
         }
     }
-    int64_t nb = cdiv(n, kT);
     hipLaunchKernelGGL(k_sum_sq, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(kT), 0, st, volL, n, cnt + 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(host_i64, cnt, 3 * 8, hipMemcpyDeviceToHost, st));
@@ -504,6 +511,14 @@ int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *la
     unsigned __int128 sq = ((unsigned __int128)(uint64_t)host_i64[2] << 64) | (uint64_t)host_i64[1];
     *num = (__int128)S * (__int128)host_i64[0] - (__int128)sq;
     return 0;
+}
+
+int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, Scratch &scr,
+                     int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st) {
+    if (g0.n == 0) return modularity_parts_ws(g0, vol0, labels, S, nullptr, host_i64, num, den, st);
+    scr.reserve(modularity_ws_bytes(g0.n));
+    void *ws = scr.get(modularity_ws_bytes(g0.n));
+    return modularity_parts_ws(g0, vol0, labels, S, ws, host_i64, num, den, st);
 }
 
 // ------------------------------------------------------------------ validation

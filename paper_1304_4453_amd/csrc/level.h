@@ -152,6 +152,11 @@ void build_canonical(const int32_t *lab, int64_t n, int32_t *out, Scratch &scr, 
 // status 0, or -1 when a label is out of range
 int modularity_parts(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, Scratch &scr,
                      int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st);
+// The same with caller workspace ws of modularity_ws_bytes(g0.n) bytes (no
+// allocation; its counters are cleared by kernels, not memset nodes).
+size_t modularity_ws_bytes(int64_t n);
+int modularity_parts_ws(const GraphView &g0, const int64_t *vol0, const int32_t *labels, int64_t S, void *ws,
+                        int64_t *host_i64, __int128 *num, __int128 *den, hipStream_t st);
 // counts distinct values of zeta
 int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t *host_i64, hipStream_t st);
 // validation of an input CSR; returns 0 or an error code bit set
