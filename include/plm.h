@@ -140,6 +140,13 @@ typedef struct {
                               passes (default 1536, else 32..1536) */
     int32_t agg_tile;      /* chunks whose bucket segments a bucket workgroup
                               flattens at once (default 512, else 1..512) */
+    int32_t settle;        /* settled nodes (single-graph move phases): a node none
+                              of whose neighbours moved since it last stayed, with
+                              a margin its gains cannot have lost to the community
+                              volumes that changed meanwhile, keeps its community
+                              without a new scan of its row.  0 (default): enabled
+                              once a sweep of the phase moved at most n/16 nodes;
+                              1: from the first sweep; -1: never.  Same results. */
 } plm_options;
 
 /* Fills *opt with the defaults above. */
@@ -407,6 +414,14 @@ typedef struct {
      * counts are those of running them) */
     int64_t cycle_sweeps[PLM_MAX_LEVELS];
     int64_t ref_cycle_sweeps[PLM_MAX_LEVELS];
+    /* settled nodes (opt.settle): sweeps of the level's move phase run with the
+     * skip armed; with opt.timing, over all sweeps of the level: node decisions
+     * taken (rows scanned), their row entries, and decisions skipped because
+     * the node was settled */
+    int64_t settle_sweeps[PLM_MAX_LEVELS];
+    int64_t decided_nodes[PLM_MAX_LEVELS];
+    int64_t decided_entries[PLM_MAX_LEVELS];
+    int64_t settled_nodes[PLM_MAX_LEVELS];
 } plm_stats_t;
 
 plm_status plm_get_stats(plm_ctx *ctx, plm_stats_t *out);

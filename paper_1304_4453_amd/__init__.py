@@ -43,7 +43,7 @@ class plm_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32),
                 ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32), ("hub_row_max", ctypes.c_int32),
-                ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32)]
+                ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32), ("settle", ctypes.c_int32)]
 
 
 class plm_level_info_t(ctypes.Structure):
@@ -73,7 +73,9 @@ class plm_stats_t(ctypes.Structure):
                 ("lp_runs", ctypes.c_int64), ("lp_iterations", ctypes.c_int64), ("lp_updates", ctypes.c_int64),
                 ("lp_ms", ctypes.c_double), ("lp_decide_ms", ctypes.c_double), ("lp_first_ms", ctypes.c_double),
                 ("lp_first_bytes", ctypes.c_double), ("ens_ms", ctypes.c_double), ("ens_cores", ctypes.c_int64),
-                ("cycle_sweeps", ctypes.c_int64 * _L), ("ref_cycle_sweeps", ctypes.c_int64 * _L)]
+                ("cycle_sweeps", ctypes.c_int64 * _L), ("ref_cycle_sweeps", ctypes.c_int64 * _L),
+                ("settle_sweeps", ctypes.c_int64 * _L), ("decided_nodes", ctypes.c_int64 * _L),
+                ("decided_entries", ctypes.c_int64 * _L), ("settled_nodes", ctypes.c_int64 * _L)]
 
 
 class plm_server_info_t(ctypes.Structure):

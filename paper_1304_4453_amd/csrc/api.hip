@@ -35,6 +35,8 @@ constexpr double kReplanFraction = 0.7;
 // timing events per class step: start and stop of the 5 kernel groups (the
 // partitioned group's part launch), then start and stop of the agg launch
 constexpr size_t kEv = 12;
+// settled nodes: a move phase arms after a sweep that moved at most n / this
+constexpr int64_t kSettleDiv = 16;
 // pinned host scratch of a context, in int64 words (the colouring's counter
 // read-back takes 480 int32)
 constexpr size_t kHostWords = 512;
@@ -186,6 +188,19 @@ struct plm_ctx {
     int32_t *bgmoved = nullptr;  // per graph of the level: moved in the current sweep
     unsigned long long *bI2 = nullptr, *bsq = nullptr;
 
+    // settled nodes (see move.hip): per node the moved neighbour weight since
+    // its last decision, the slacks of its last stay and the moved-volume clock
+    // it was taken at; sctl = [on, clock].  Armed for a move phase once its
+    // sweeps move few nodes (opt.settle).
+    uint64_t *dw = nullptr;
+    int64_t *slack = nullptr, *kslack = nullptr;
+    uint64_t *tstamp = nullptr;
+    unsigned long long *sctl = nullptr;
+    bool skip_armed = false;
+    int64_t armed_sweeps = 0;
+    int32_t *hub_skip = nullptr;
+    uint64_t *hub_clk = nullptr;
+
     // label propagation (Algorithm 1): active flag of each node; lp_mode turns
     // the class steps into label-propagation steps with tie keys of lp_seed
     uint8_t *active = nullptr;
@@ -217,6 +232,7 @@ struct plm_ctx {
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
         dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active); dev_free(snap[0]); dev_free(snap[1]);
+        dev_free(dw); dev_free(slack); dev_free(kslack); dev_free(tstamp); dev_free(sctl);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
         for (auto e : events) (void)hipEventDestroy(e);
@@ -238,7 +254,7 @@ struct plm_ctx {
         dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(stg_x); dev_free(ins_first);
         dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part); dev_free(hub_base);
         dev_free(bkt); dev_free(part); dev_free(hub_u); dev_free(ins_hub); dev_free(agg_hub); dev_free(sgl_hub);
-        dev_free(red_hub);
+        dev_free(red_hub); dev_free(hub_skip); dev_free(hub_clk);
         cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = cap_hubu = cap_ihub = cap_ahub = cap_shub = cap_rhub = 0;
     }
 
@@ -308,6 +324,27 @@ struct plm_ctx {
         sched = false;
         ncol = 0;
         sweeps = 0;
+        disarm();
+    }
+
+    // ---------------------------------------------------------------- settled nodes
+    // Armed: every node's moved weight at 0x8080... >= 2^63 (so the next class
+    // steps decide them all and record their slacks; what moves add before
+    // then stays below 2^64), clock at 0.  The kernels of a captured sweep
+    // read sctl, so the same graph serves armed and unarmed sweeps.
+    bool settle_usable() { return sctl != nullptr && opt.settle >= 0 && L().n > 0; }
+    void arm() {
+        HIPCHK(hipMemsetAsync(dw, 0x80, (size_t)L().n * 8, st));
+        const unsigned long long on[2] = {1ULL, 0ULL};
+        HIPCHK(hipMemcpyAsync(sctl, on, sizeof(on), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        skip_armed = true;
+        armed_sweeps = 0;
+    }
+    void disarm() {
+        if (!sctl || !skip_armed) return;
+        HIPCHK(hipMemsetAsync(sctl, 0, 8, st));
+        skip_armed = false;
     }
 
     // grow-only device arrays of the hub plan
@@ -318,8 +355,10 @@ struct plm_ctx {
                              int64_t agg_tot, int64_t sgl_tot, int64_t red_tot) {
         if (hubs > cap_hubs) {
             dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
-            dev_free(stg_off); dev_free(bkt_off); dev_free(hub_base);
+            dev_free(stg_off); dev_free(bkt_off); dev_free(hub_base); dev_free(hub_skip); dev_free(hub_clk);
             hub_base = dev_alloc<int64_t>(hubs);
+            hub_skip = dev_alloc<int32_t>(hubs);
+            hub_clk = dev_alloc<uint64_t>(hubs);
             hub_pos = dev_alloc<int32_t>(hubs); nchunk = dev_alloc<int32_t>(hubs); pbits = dev_alloc<int32_t>(hubs);
             ins_first = dev_alloc<int64_t>(hubs); agg_first = dev_alloc<int64_t>(hubs);
             stg_off = dev_alloc<int64_t>(hubs); bkt_off = dev_alloc<int64_t>(hubs);
@@ -495,9 +534,13 @@ struct plm_ctx {
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
         ms.cand_sgl = count_cand ? dcnt + 13 : nullptr;
+        ms.dec_dev = count_cand ? dcnt + 16 : nullptr;
         ms.gp = gp();
         ms.gq = gq();
         if (batch) { ms.gid = L().gid; ms.gS = gS; ms.gwl = gwl; ms.gmoved = bgmoved; }
+        if (!lp_mode && sctl) {
+            ms.dw = dw; ms.slack = slack; ms.kslack = kslack; ms.tstamp = tstamp; ms.sctl = sctl;
+        }
         if (lp_mode) {
             // scores (w(u,X) << 32) + t(u,X): S = 2^32, no vol(u) term, 64-bit
             // while vol(u) (>= every w(u,X)) is below 2^31
@@ -518,6 +561,7 @@ struct plm_ctx {
         ha.ins_first = ins_first; ha.agg_first = agg_first; ha.nchunk = nchunk;
         ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
         ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part; ha.hub_base = hub_base;
+        ha.hub_skip = hub_skip; ha.hub_clk = hub_clk;
         ha.agg_max_keys = opt.agg_max_keys > 0 ? opt.agg_max_keys : 0;
         ha.agg_tile = opt.agg_tile > 0 ? opt.agg_tile : 0;
         return ha;
@@ -605,6 +649,7 @@ struct plm_ctx {
         if (!sched) build_schedule();
         HIPCHK(hipMemsetAsync(dcnt, 0, 5 * 8, st));
         HIPCHK(hipMemsetAsync(dcnt + 13, 0, 8, st));
+        HIPCHK(hipMemsetAsync(dcnt + 16, 0, 10 * 8, st));
         bool timing = opt.timing != 0;
         MoveState ms = move_state(timing);
         HubArrays ha = hub_arrays();
@@ -623,6 +668,7 @@ struct plm_ctx {
         }
         HIPCHK(hipMemcpyAsync(hbuf, dcnt, 5 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(hbuf + 5, dcnt + 13, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hbuf + 32, dcnt + 16, 10 * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         int64_t moves = hbuf[0];
         if (timing && cur < PLM_MAX_LEVELS) {
@@ -661,11 +707,17 @@ struct plm_ctx {
             int wb = L().wkind == 0 ? 0 : (L().wkind == 1 ? 4 : 8);
             bool whole = c0 == 0 && c1 == ncol;
             const double per_cand = lp_mode ? 0.0 : 8.0;
+            // PLM counts the rows actually scanned: a settled node costs its
+            // class entry, moved weight, slack, clock stamp and vol(u) (36 bytes)
+            const int64_t *dec = hbuf + 32;
             last_ms = last_bytes = 0;
             for (int b = 0; b < 4; ++b) {
-                double bytes = whole ? (double)bin_entries[b] * (8.0 + wb) + per_cand * (double)hbuf[1 + b] +
-                                           32.0 * (double)bin_nodes[b]
-                                     : 0.0;
+                double bytes = 0.0;
+                if (whole && lp_mode)
+                    bytes = (double)bin_entries[b] * (8.0 + wb) + 32.0 * (double)bin_nodes[b];
+                else if (whole)
+                    bytes = (double)dec[4 + b] * (8.0 + wb) + per_cand * (double)hbuf[1 + b] + 32.0 * (double)dec[b] +
+                            36.0 * (double)(bin_nodes[b] - dec[b]);
                 last_ms += bin_t[b];
                 last_bytes += bytes;
                 if (lp_mode) continue;
@@ -676,9 +728,15 @@ struct plm_ctx {
             }
             if (!lp_mode) {
                 stats.hub_single_ms[cur] += sgl_t;
-                if (whole)
-                    stats.hub_single_bytes[cur] += (double)sgl_entries * (8.0 + wb) + 8.0 * (double)hbuf[5] +
-                                                   32.0 * (double)sgl_nodes;
+                if (whole) {
+                    stats.hub_single_bytes[cur] += (double)dec[9] * (8.0 + wb) + 8.0 * (double)hbuf[5] +
+                                                   32.0 * (double)dec[8] + 36.0 * (double)(sgl_nodes - dec[8]);
+                    for (int b = 0; b < 4; ++b) {
+                        stats.decided_nodes[cur] += dec[b];
+                        stats.decided_entries[cur] += dec[4 + b];
+                        stats.settled_nodes[cur] += bin_nodes[b] - dec[b];
+                    }
+                }
                 stats.decide_launches[cur] += launches;
             }
         }
@@ -687,10 +745,26 @@ struct plm_ctx {
 
     // one sweep; from the third of a move phase on, replayed from the sweep graph
     int64_t sweep(bool allow_graph = false) {
+        settle_before();
         // every sweep of a plan replays the graph captured at its first sweep
         int64_t mv = run_classes(0, ncol_or_build(), allow_graph);
         ++sweeps;
+        if (skip_armed && cur < PLM_MAX_LEVELS) ++stats.settle_sweeps[cur];
+        settle_after(mv);
         return mv;
+    }
+    // before class steps (a sweep, or one class): arm when opt.settle = 1, and
+    // re-arm (clock back to 0) before the clock could wrap (at most 2S per
+    // sweep; a single class step counts as a sweep here)
+    void settle_before() {
+        if (!settle_usable()) return;
+        const unsigned __int128 next = (unsigned __int128)(armed_sweeps + 1) * 2u * (uint64_t)S;
+        if ((!skip_armed && opt.settle == 1) || (skip_armed && (next >> 63))) arm();
+    }
+    // after them: arm once a sweep moved at most n / kSettleDiv nodes (opt.settle = 0)
+    void settle_after(int64_t moved) {
+        if (skip_armed) ++armed_sweeps;
+        else if (settle_usable() && opt.settle == 0 && moved * kSettleDiv <= L().n) arm();
     }
 
     // Move phase of the current level: sweeps until one moves nothing, at
@@ -704,6 +778,7 @@ struct plm_ctx {
     int64_t move_phase(int64_t *skipped) {
         const int64_t n = L().n;
         *skipped = 0;
+        disarm();
         std::vector<int64_t> mv;
         int64_t moves = 0;
         for (int32_t s = 0; s < opt.max_sweeps; ++s) {
@@ -731,6 +806,7 @@ struct plm_ctx {
                         launch_comm_vol(zeta, vol, n, volC, st);
                         HIPCHK(hipStreamSynchronize(st));
                     }
+                    disarm();  // the recorded slacks belong to the other state
                     sweeps += (int32_t)rest;
                     *skipped = rest;
                     break;
@@ -1198,6 +1274,7 @@ int check_options(const plm_options &o, std::string &msg) {
         return PLM_E_ARG;
     }
     if (o.agg_tile < 0 || o.agg_tile > 512) { msg = "agg_tile must be 0 or lie in [1, 512]"; return PLM_E_ARG; }
+    if (o.settle < -1 || o.settle > 1) { msg = "settle must be -1, 0 or 1"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
@@ -1412,8 +1489,16 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c->class_nodes = dev_alloc<int32_t>(n);
         c->move_to = dev_alloc<int32_t>(n);
         c->lab = dev_alloc<int32_t>(n);
-        c->dcnt = dev_alloc<unsigned long long>(16);
-        HIPCHK(hipMemsetAsync(c->dcnt, 0, 16 * 8, c->st));
+        c->dcnt = dev_alloc<unsigned long long>(32);
+        HIPCHK(hipMemsetAsync(c->dcnt, 0, 32 * 8, c->st));
+        if (!c->batch && o.settle >= 0 && n > 0) {
+            c->dw = dev_alloc<uint64_t>(n);
+            c->slack = dev_alloc<int64_t>(n);
+            c->kslack = dev_alloc<int64_t>(n);
+            c->tstamp = dev_alloc<uint64_t>(n);
+            c->sctl = dev_alloc<unsigned long long>(2);
+            HIPCHK(hipMemsetAsync(c->sctl, 0, 16, c->st));
+        }
         if (c->batch) c->set_active_all();
         c->init_level();
     } catch (const Error &e) {
@@ -1493,7 +1578,9 @@ plm_status plm_move_class(plm_ctx *ctx, int32_t c, int64_t *moves_out) {
     return guarded(ctx, [&] {
         int32_t nc = ctx->ncol_or_build();
         if (c < 0 || c >= nc) throw Error{PLM_E_ARG, "class index out of range"};
+        if (ctx->skip_armed || ctx->opt.settle == 1) ctx->settle_before();
         int64_t mv = ctx->run_classes(c, c + 1);
+        if (ctx->skip_armed) ++ctx->armed_sweeps;
         if (moves_out) *moves_out = mv;
     });
 }

@@ -45,6 +45,9 @@ struct MoveState {
     unsigned long long *moves_dev;  // move counter
     unsigned long long *cand_dev;   // distinct candidates evaluated per bin [4] (may be null)
     unsigned long long *cand_sgl;   // of those in the hub bin, the one-workgroup hubs' (may be null)
+    // nodes decided (not settled) and their row entries: [bin], [4 + bin], and
+    // of the hub bin the one-workgroup hubs' [8], [9] (may be null)
+    unsigned long long *dec_dev = nullptr;
     // batched runs: graph of each node, and per graph S and the 64-bit limit
     const int32_t *gid = nullptr;
     const int64_t *gS = nullptr;
@@ -57,6 +60,17 @@ struct MoveState {
     uint8_t *active = nullptr;
     uint64_t lp_seed = 0;
     int32_t lp_level = 0;
+    // settled nodes (move phases of single-graph PLM; null otherwise; the
+    // bound is in move.hip).  While sctl[0] != 0: node u last stayed when the
+    // moved-volume clock sctl[1] (+= 2 vol(m) per move m) read tstamp[u], with
+    // every gain at most -slack[u] and kslack[u] = min(slack, score of
+    // staying) (-1 if negative); dw[u] is the edge weight to neighbours that
+    // moved since (>= 2^63: u must be decided).
+    uint64_t *dw = nullptr;
+    int64_t *slack = nullptr;
+    int64_t *kslack = nullptr;
+    uint64_t *tstamp = nullptr;
+    unsigned long long *sctl = nullptr;  // [0] on, [1] moved-volume clock (wraps mod 2^64)
 };
 
 __device__ __forceinline__ int64_t node_S(const MoveState &ms, int32_t u) { return ms.gid ? ms.gS[ms.gid[u]] : ms.S; }
@@ -97,7 +111,9 @@ struct HubArrays {
     uint32_t *bkt;             // (start << 16 | count) per (bucket, chunk), bucket-major
     int64_t *wd_part;          // per chunk workgroup: its share of w(u, D \ u)
     int64_t *hub_base;         // per hub: vol(D \ u) at the start of its class
-    unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, pad
+    unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, slack of the bucket
+    int32_t *hub_skip;         // per hub: 1 = settled in its current class step (written by agg)
+    uint64_t *hub_clk;         // per hub: the moved-volume clock at the start of its class step
     // lowered limits of the bucket workgroups (0 = the compiled ones): new
     // communities per pass, and chunks flattened at once
     int32_t agg_max_keys = 0, agg_tile = 0;

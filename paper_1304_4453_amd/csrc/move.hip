@@ -84,6 +84,80 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
     return v;
 }
 
+template <typename G>
+__device__ __forceinline__ G wave_max(G x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        G o = shfl_xor_g<G>(x, d);
+        if (o > x) x = o;
+    }
+    return x;
+}
+
+// ------------------------------------------------------------------ settled nodes
+// Node u (community D) scores each candidate X by the gain
+//   q S (w(u,X) - w(u,D\u)) - p vol(u) (vol(X) - vol(D\u)).
+// Say u last stayed at clock t0 with every gain at most -slack, and with the
+// score of staying K = q S w(u,D\u) - p vol(u) vol(D\u).  Since then:
+//  - community volumes changed by at most V in total, V summing 2 vol(m)
+//    over the moves m applied meanwhile (the moved-volume clock);
+//  - neighbours of u of total edge weight dw moved (u itself did not), which
+//    changed w(u,X) - w(u,D\u) by at most 2 dw for any X, and can have made
+//    new communities candidates, whose score q S w(u,X) - p vol(u) vol(X) is
+//    at most q S dw.
+// So every gain of an old candidate is now at most -slack + 2 q S dw + p vol(u) V,
+// and that of a new one at most -K + 2 q S dw + p vol(u) V.  When these bounds
+// are <= 0, u stays without a scan of its row: exactly the decision a full
+// scan would take.  kslack = min(slack, K) (-1 when K < 0) covers both cases.
+constexpr uint64_t kStaleDw = 1ULL << 63;  // dw at or above: must be decided
+struct Settle {
+    bool on;
+    uint64_t now;  // the moved-volume clock at the start of the class step
+};
+__device__ __forceinline__ Settle settle_state(const MoveState &ms) {
+    Settle st{false, 0};
+    if (ms.sctl && ms.sctl[0]) {
+        st.on = true;
+        st.now = ms.sctl[1];
+    }
+    return st;
+}
+__device__ __forceinline__ bool settled(const MoveState &ms, const Settle &st, int32_t u) {
+    if (!st.on) return false;
+    const uint64_t dw = ms.dw[u];
+    if (dw >= kStaleDw) return false;
+    const int64_t room = dw == 0 ? ms.slack[u] : ms.kslack[u];
+    if (room < 0) return false;
+    uint64_t rem = (uint64_t)room;
+    if (ms.gp > 0) {  // p vol(u) V <= room, then what is left of it
+        const unsigned __int128 vv = (unsigned __int128)(uint64_t)ms.vol[u] * (st.now - ms.tstamp[u]);
+        if (vv > (unsigned __int128)(rem / (uint64_t)ms.gp)) return false;
+        rem -= (uint64_t)ms.gp * (uint64_t)vv;
+    }
+    if (dw == 0) return true;
+    const unsigned __int128 per = (unsigned __int128)2u * (uint64_t)ms.gq * (uint64_t)node_S(ms, u);
+    return (unsigned __int128)dw <= (unsigned __int128)rem / per;
+}
+__device__ __forceinline__ void record_stay(const MoveState &ms, const Settle &st, int32_t u, int64_t slack,
+                                            int64_t kslack) {
+    ms.dw[u] = 0;
+    ms.slack[u] = slack;
+    ms.kslack[u] = kslack;
+    ms.tstamp[u] = st.now;
+}
+template <typename G>
+__device__ __forceinline__ int64_t clamp_i64(G x) {
+    return x <= 0 ? 0 : (x >= (G)INT64_MAX ? INT64_MAX : (int64_t)x);
+}
+// slack = K - ub as int64, where ub bounds every candidate's score from above
+// (neg_inf: no candidate), clamped to [0, INT64_MAX] (a lower bound of the
+// true slack); kslack = min(slack, K), or -1 when K < 0
+template <typename G>
+__device__ __forceinline__ void slack_of(G K, G ub, int64_t &slack, int64_t &kslack) {
+    slack = ub == neg_inf<G>() ? INT64_MAX : clamp_i64<G>(K - ub);
+    kslack = K < 0 ? -1 : (clamp_i64<G>(K) < slack ? clamp_i64<G>(K) : slack);
+}
+
 // tie key of label x for the node with priority hash hv: upper half of
 // SplitMix64(hv ^ x), so that each node breaks ties in its own random order
 __device__ __forceinline__ uint32_t lp_tie(uint64_t hv, int32_t x) {
@@ -100,34 +174,69 @@ __device__ __forceinline__ void lp_activate(const GraphView &g, uint8_t *active,
     }
 }
 
+// settled nodes: u decided to move, so u must be decided again and each
+// neighbour v gains w(u,v) of moved weight; threads first, first + step, ...
+// of the row.  Neighbours are never in u's class, so no decision of the class
+// reads these words.
+template <int WK>
+__device__ __forceinline__ void mark_moved(const GraphView &g, const MoveState &ms, int32_t u, int64_t e0, int64_t e1,
+                                           int64_t first, int64_t step) {
+    for (int64_t e = e0 + first; e < e1; e += step) {
+        const int32_t v = g.col[e];
+        if (v != u) atomicAdd((unsigned long long *)&ms.dw[v], (unsigned long long)wload<WK>(g.w, e));
+    }
+    if (first == 0) ms.dw[u] = kStaleDw;
+}
+
 __device__ __forceinline__ void count_candidates(unsigned long long *cand, int64_t c) {
     if (!cand) return;
     c = wave_sum(c);
     if (lane_id() == 0 && c) atomicAdd(cand, (unsigned long long)c);
 }
+// nodes decided (scanned) and their entries, into dec[i] and dec[i + 4 or 1]
+__device__ __forceinline__ void count_decided(unsigned long long *dec, int i, int j, int64_t nodes, int64_t entries) {
+    if (!dec) return;
+    nodes = wave_sum(nodes);
+    entries = wave_sum(entries);
+    if (lane_id() == 0) {
+        if (nodes) atomicAdd(dec + i, (unsigned long long)nodes);
+        if (entries) atomicAdd(dec + j, (unsigned long long)entries);
+    }
+}
 
 // ------------------------------------------------------------------ lane per node
 constexpr int kLaneMax = 16;
 
+// *slack: when u stays, a lower bound of minus its best gain (see slack_of)
 template <int WK, bool LP, typename G>
 __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const int64_t (&W)[kLaneMax], int32_t D,
-                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC, uint64_t hv) {
-    G bg = 0;
+                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC, uint64_t hv,
+                                             int64_t *slack, int64_t *kslack) {
+    G bg = 0, mg = neg_inf<G>();
     int32_t bx = kNone;
     const G vb = (G)vu * (G)base;
 #pragma unroll
     for (int j = 0; j < kLaneMax; ++j) {
         // vol(X) >= 0 bounds the gain by S (w(u,X) - w(u,D\u)) + vol(u) vol(D\u):
         // a candidate that cannot reach a positive gain is not gathered
-        if (X[j] >= 0 && X[j] != D && (G)S * (G)(W[j] - wD) + vb > 0) {
-            G g;
-            if constexpr (LP)
-                g = (G)S * (G)(W[j] - wD) + (G)lp_tie(hv, X[j]) - (G)kLpTieMax;
-            else
-                g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
-            if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
+        if (X[j] >= 0 && X[j] != D) {
+            const G bound = (G)S * (G)(W[j] - wD) + vb;
+            if (bound > 0) {
+                G g;
+                if constexpr (LP)
+                    g = (G)S * (G)(W[j] - wD) + (G)lp_tie(hv, X[j]) - (G)kLpTieMax;
+                else
+                    g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
+                if (g > mg) mg = g;
+                if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
+            } else if (bound > mg) {
+                mg = bound;
+            }
         }
     }
+    // gains here are scores minus K = S w(u,D\u) - vol(u) vol(D\u)
+    const G K = (G)S * (G)wD - vb;
+    slack_of<G>(K, mg == neg_inf<G>() ? mg : mg + K, *slack, *kslack);
     return bx;
 }
 
@@ -138,13 +247,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                                                            int64_t begin, int64_t count,
                                                                                            int force_wide) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t ncand = 0;
+    int64_t ncand = 0, nd = 0, ne = 0;
     int32_t u = 0;
+    const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     if (i < count) {
         u = ms.class_nodes[(int64_t)begin + i];
-        if (LP && !ms.active[u]) {
+        if ((LP && !ms.active[u]) || settled(ms, st, u)) {
             ms.move_to[begin + i] = -1;
-            i = count;  // inactive: nothing to decide
+            i = count;  // inactive or settled: nothing to decide
         }
     }
     if (i < count) {
@@ -182,16 +292,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         int64_t base = LP ? 0 : ms.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
+        int64_t slack, kslack;
         int32_t bx = (force_wide || vu > node_wl(ms, u))
-                         ? lane_pick<WK, LP, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, hv)
-                         : lane_pick<WK, LP, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, hv);
+                         ? lane_pick<WK, LP, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, hv,
+                                                   &slack, &kslack)
+                         : lane_pick<WK, LP, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, hv, &slack,
+                                                      &kslack);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
+        if (st.on) {
+            if (bx == kNone) record_stay(ms, st, u, slack, kslack);
+            else mark_moved<WK>(g, ms, u, e0, e0 + d, 0, 1);
+        }
+        nd = 1;
+        ne = d;
         if (LP) {
             if (bx == kNone) ms.active[u] = 0;
             else lp_activate(g, ms.active, u, e0, e0 + d, 0, 1);
         }
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 0 : nullptr, ncand);
+    count_decided(ms.dec_dev, 0, 4, nd, ne);
 }
 
 // ------------------------------------------------------------------ wavefront per node
@@ -209,9 +329,11 @@ constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 // and whether it beats K, are exactly those of a full scan.
 constexpr int kEvalBatch = 8;
 
+// ub: raised to an upper bound of every slot's score (a pruned slot's score is
+// at most S w(u,X)), from which a node that stays gets its slack
 template <typename G, typename V, bool LP>
 __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, G vu, G S, G K,
-                                           const int64_t *volC, bool clear, G &bs, int32_t &bx,
+                                           const int64_t *volC, bool clear, G &bs, int32_t &bx, G &ub,
                                            int64_t &ncand, uint64_t hv) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
@@ -233,9 +355,15 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
 #pragma unroll
         for (int j = 0; j < kEvalBatch; ++j) {
             ncand += X[j] >= 0;
-            if (!c[j]) continue;
+            if (X[j] < 0) continue;
+            if (!c[j]) {
+                const G b = (G)S * (G)a[j];
+                if (b > ub) ub = b;
+                continue;
+            }
             G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
             if constexpr (LP) sc += (G)lp_tie(hv, X[j]);
+            if (sc > ub) ub = sc;
             if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
         }
     }
@@ -244,14 +372,15 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
 template <typename G, bool LP>
 __device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
                                           const int64_t *volC, int32_t &best_x, bool &move,
-                                          int64_t &ncand, uint64_t hv) {
-    G bs = neg_inf<G>();
+                                          int64_t &ncand, uint64_t hv, int64_t &slack, int64_t &kslack) {
+    G bs = neg_inf<G>(), ub = neg_inf<G>();
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ub, ncand, hv);
     wave_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
+    slack_of<G>(K, wave_max<G>(ub), slack, kslack);
 }
 
 // folds the (X, w) entries of u into a hash table (LDS) except X == D; returns
@@ -309,11 +438,12 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
     const int w = threadIdx.x / kWave, lane = lane_id();
     for (int s = lane; s < kWaveCap; s += kWave) { tk[w][s] = kEmpty; tv[w][s] = 0; }
     wave_sync();
-    int64_t ncand = 0;
+    int64_t ncand = 0, nd = 0, ne = 0;
+    const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < count; i += (int64_t)gridDim.x * 4) {
         int64_t pos = begin + i;
         int32_t u = ms.class_nodes[pos];
-        if (LP && !ms.active[u]) {  // wave-uniform
+        if ((LP && !ms.active[u]) || settled(ms, st, u)) {  // wave-uniform
             if (lane == 0) ms.move_to[pos] = -1;
             continue;
         }
@@ -330,20 +460,29 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
         bool mv;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
+        int64_t slack, kslack;
         if (force_wide || vu > node_wl(ms, u))
             wave_eval<i128, LP>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, bx,
-                                mv, ncand, hv);
+                                mv, ncand, hv, slack, kslack);
         else
             wave_eval<int64_t, LP>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv, ncand,
-                                   hv);
-        if (lane == 0) ms.move_to[pos] = mv ? bx : -1;
+                                   hv, slack, kslack);
+        if (lane == 0) {
+            ms.move_to[pos] = mv ? bx : -1;
+            if (st.on && !mv) record_stay(ms, st, u, slack, kslack);
+            nd += 1;
+            ne += e1 - e0;
+        }
         if (LP) {
             if (mv) lp_activate(g, ms.active, u, e0, e1, lane, kWave);
             else if (lane == 0) ms.active[u] = 0;
+        } else if (st.on && mv) {
+            mark_moved<WK>(g, ms, u, e0, e1, lane, kWave);
         }
         wave_sync();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
+    count_decided(ms.dec_dev, 1, 5, nd, ne);
 }
 
 // ------------------------------------------------------------------ 16 lanes per node
@@ -355,6 +494,15 @@ __global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, 
 constexpr int kQuadLanes = 16;
 constexpr int kQuadCap = 2 * (int)kQuadRow;
 
+template <typename G>
+__device__ __forceinline__ G quad_max(G x) {
+#pragma unroll
+    for (int d = kQuadLanes / 2; d >= 1; d >>= 1) {
+        G o = shfl_xor_g<G>(x, d);
+        if (o > x) x = o;
+    }
+    return x;
+}
 template <typename G>
 __device__ __forceinline__ void quad_argmax(G &s, int32_t &x) {
 #pragma unroll
@@ -373,15 +521,16 @@ __device__ __forceinline__ int64_t quad_sum(int64_t v) {
 template <typename G, bool LP>
 __device__ __forceinline__ void quad_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
                                           const int64_t *volC, int32_t &best_x, bool &move, int64_t &ncand,
-                                          uint64_t hv) {
-    G bs = neg_inf<G>();
+                                          uint64_t hv, int64_t &slack, int64_t &kslack) {
+    G bs = neg_inf<G>(), ub = neg_inf<G>();
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
     eval_slots<G, int32_t, LP>(tk, tv, tsize, (int)(threadIdx.x % kQuadLanes), kQuadLanes, vu, S, K, volC, true, bs,
-                               bx, ncand, hv);
+                               bx, ub, ncand, hv);
     quad_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
+    slack_of<G>(K, quad_max<G>(ub), slack, kslack);
 }
 
 template <int WK, bool LP>
@@ -393,13 +542,14 @@ __global__ __launch_bounds__(256) void k_decide_quad(GraphView g, MoveState ms, 
     const int grp = threadIdx.x / kQuadLanes, l = threadIdx.x % kQuadLanes;
     for (int s = l; s < kQuadCap; s += kQuadLanes) { tk[grp][s] = kEmpty; tv[grp][s] = 0; }
     wave_sync();
-    int64_t ncand = 0;
+    int64_t ncand = 0, nd = 0, ne = 0;
+    const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     for (int64_t b0 = (int64_t)blockIdx.x * kGroups; b0 < count; b0 += (int64_t)gridDim.x * kGroups) {
         const int64_t i = b0 + grp, pos = begin + i;
         const bool has = i < count;
         const int32_t u = has ? ms.class_nodes[pos] : 0;
-        const bool act = has && (!LP || ms.active[u]);
-        if (LP && has && !act && l == 0) ms.move_to[pos] = -1;
+        const bool act = has && (!LP || ms.active[u]) && !settled(ms, st, u);
+        if (has && !act && l == 0) ms.move_to[pos] = -1;
         const int64_t e0 = act ? g.off[u] : 0, e1 = act ? g.off[u + 1] : 0;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;  // rows of at most kQuadRow entries: at most kQuadCap slots
@@ -413,20 +563,29 @@ __global__ __launch_bounds__(256) void k_decide_quad(GraphView g, MoveState ms, 
         const uint64_t hv = (LP && act) ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         int32_t bx;
         bool mv;
+        int64_t slack, kslack;
         if (act && (force_wide || vu > node_wl(ms, u)))
             quad_eval<i128, LP>(tk[grp], tv[grp], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC,
-                                bx, mv, ncand, hv);
+                                bx, mv, ncand, hv, slack, kslack);
         else
             quad_eval<int64_t, LP>(tk[grp], tv[grp], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv,
-                                   ncand, hv);
-        if (act && l == 0) ms.move_to[pos] = mv ? bx : -1;
+                                   ncand, hv, slack, kslack);
+        if (act && l == 0) {
+            ms.move_to[pos] = mv ? bx : -1;
+            if (st.on && !mv) record_stay(ms, st, u, slack, kslack);
+            nd += 1;
+            ne += e1 - e0;
+        }
         if (LP && act) {
             if (mv) lp_activate(g, ms.active, u, e0, e1, l, kQuadLanes);
             else if (l == 0) ms.active[u] = 0;
+        } else if (!LP && act && st.on && mv) {
+            mark_moved<WK>(g, ms, u, e0, e1, l, kQuadLanes);
         }
         wave_sync();
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 1 : nullptr, ncand);
+    count_decided(ms.dec_dev, 1, 5, nd, ne);
 }
 
 // ------------------------------------------------------------------ workgroup per node
@@ -438,12 +597,16 @@ constexpr int kBlockShortThreads = 256;
 constexpr int kBlockShortCap = 4096;
 static_assert(2 * kBlockShortRow <= kBlockShortCap, "short workgroup-bin table too small");
 
-// leaves the decision (community or -1) in *out (LDS), written by thread 0
+// leaves the decision (community or -1) in *out and the slack of staying in
+// *slack_out (LDS), written by thread 0
 template <typename G, int NT, bool LP>
 __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
-                                           const int64_t *volC, int32_t *out, int64_t &ncand, uint64_t hv) {
+                                           const int64_t *volC, int32_t *out, int64_t *slack_out, int64_t &ncand,
+                                           uint64_t hv) {
+    // slack_out[0], slack_out[1]: slack and kslack
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
+    __shared__ G red_u[NT / kWave];
     __shared__ int32_t red_x[NT / kWave];
     // w(u, D \ u) first (wD enters as this thread's share): the score of staying
     // bounds which slots need their community volume
@@ -454,16 +617,20 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     wD = 0;
     for (int j = 0; j < NT / kWave; ++j) wD += red_w[j];
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    G bs = neg_inf<G>();
+    G bs = neg_inf<G>(), ub = neg_inf<G>();
     int32_t bx = kNone;
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ub, ncand, hv);
     wave_argmax<G>(bs, bx);
-    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; }
+    ub = wave_max<G>(ub);
+    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; red_u[w] = ub; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int j = 1; j < NT / kWave; ++j)
+        for (int j = 1; j < NT / kWave; ++j) {
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
+            if (red_u[j] > ub) ub = red_u[j];
+        }
         *out = (bx != kNone && bs > K) ? bx : -1;
+        slack_of<G>(K, ub, slack_out[0], slack_out[1]);
     }
 }
 
@@ -475,13 +642,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ int32_t tk[CAP];
     __shared__ int32_t tv[CAP];
     __shared__ int32_t dec;
+    __shared__ int64_t slack[2];
     for (int s = threadIdx.x; s < CAP; s += NT) { tk[s] = kEmpty; tv[s] = 0; }
     __syncthreads();
-    int64_t ncand = 0;
+    int64_t ncand = 0, nd = 0, ne = 0;
+    const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         int64_t pos = begin + i;
         int32_t u = ms.class_nodes[pos];
-        if (LP && !ms.active[u]) {  // workgroup-uniform
+        if ((LP && !ms.active[u]) || settled(ms, st, u)) {  // workgroup-uniform
             if (threadIdx.x == 0) ms.move_to[pos] = -1;
             continue;
         }
@@ -497,19 +666,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         if (force_wide || vu > node_wl(ms, u))
             block_eval<i128, NT, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
-                                                ms.volC, &dec, ncand, hv);
+                                                ms.volC, &dec, slack, ncand, hv);
         else
             block_eval<int64_t, NT, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                                   &dec, ncand, hv);
+                                                   &dec, slack, ncand, hv);
         __syncthreads();
         const int32_t x = dec;
-        if (threadIdx.x == 0) ms.move_to[pos] = x;
+        if (threadIdx.x == 0) {
+            ms.move_to[pos] = x;
+            if (st.on && x < 0) record_stay(ms, st, u, slack[0], slack[1]);
+            nd += 1;
+            ne += e1 - e0;
+        }
         if (LP) {
             if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, NT);
             else if (threadIdx.x == 0) ms.active[u] = 0;
+        } else if (st.on && x >= 0) {
+            mark_moved<WK>(g, ms, u, e0, e1, threadIdx.x, NT);
         }
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 2 : nullptr, ncand);
+    count_decided(ms.dec_dev, 2, 6, nd, ne);
 }
 
 // ------------------------------------------------------------------ hubs: one large workgroup per node
@@ -522,10 +699,12 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     __shared__ int32_t tk[1 << kSingleBits];
     __shared__ int32_t tv[1 << kSingleBits];
     __shared__ int32_t dec;
+    __shared__ int64_t slack[2];
     const int64_t hg = ha.sgl_hub[blk0 + blockIdx.x];
     const int32_t u = ha.hub_u[hg];
     const int64_t pos = ha.hub_pos[hg];
-    if (LP && !ms.active[u]) {
+    const Settle st = LP ? Settle{false, 0} : settle_state(ms);
+    if ((LP && !ms.active[u]) || settled(ms, st, u)) {
         if (threadIdx.x == 0) ms.move_to[pos] = -1;
         return;
     }
@@ -545,16 +724,27 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     int64_t ncand = 0;
     if (force_wide || vu > node_wl(ms, u))
         block_eval<i128, kSingleThreads, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
-                                             ms.volC, &dec, ncand, hv);
+                                             ms.volC, &dec, slack, ncand, hv);
     else
         block_eval<int64_t, kSingleThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                                &dec, ncand, hv);
+                                                &dec, slack, ncand, hv);
     __syncthreads();
     const int32_t x = dec;
-    if (threadIdx.x == 0) ms.move_to[pos] = x;
+    if (threadIdx.x == 0) {
+        ms.move_to[pos] = x;
+        if (st.on && x < 0) record_stay(ms, st, u, slack[0], slack[1]);
+        if (ms.dec_dev) {
+            atomicAdd(ms.dec_dev + 3, 1ULL);
+            atomicAdd(ms.dec_dev + 7, (unsigned long long)(e1 - e0));
+            atomicAdd(ms.dec_dev + 8, 1ULL);
+            atomicAdd(ms.dec_dev + 9, (unsigned long long)(e1 - e0));
+        }
+    }
     if (LP) {
         if (x >= 0) lp_activate(g, ms.active, u, e0, e1, threadIdx.x, kSingleThreads);
         else if (threadIdx.x == 0) ms.active[u] = 0;
+    } else if (st.on && x >= 0) {
+        mark_moved<WK>(g, ms, u, e0, e1, threadIdx.x, kSingleThreads);
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
     count_candidates(ms.cand_sgl, ncand);
@@ -627,9 +817,14 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     // the apply launch leaves this position to the hub's own reduce
     if (k == 0 && threadIdx.x == 0) ms.move_to[ha.hub_pos[hg]] = kHubPending;
     if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
+    if (!LP && settled(ms, settle_state(ms), u)) return;  // settled hub: nothing staged
     const int32_t D = ms.zeta[u];
     const int64_t e0 = g.off[u], e1 = g.off[u + 1];
     const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
+    if (threadIdx.x == 0 && ms.dec_dev) {
+        if (k == 0) atomicAdd(ms.dec_dev + 3, 1ULL);
+        atomicAdd(ms.dec_dev + 7, (unsigned long long)(c1 - c0));
+    }
     const int pb = ha.pbits[hg];
     const int P = 1 << pb;
     for (int i = threadIdx.x; i < kMergeSlots; i += kHubThreads) { lds.m.key[i] = kEmpty; lds.m.val[i] = 0; }
@@ -751,6 +946,20 @@ __device__ __forceinline__ void block_argmax(G &bs, int32_t &bx) {
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
 }
 
+// block-wide max; result valid in thread 0
+template <typename G>
+__device__ __forceinline__ G block_max(G x) {
+    __shared__ G red[kHubThreads / kWave];
+    x = wave_max<G>(x);
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int j = 0; j < kHubThreads / kWave; ++j)
+            if (red[j] > x) x = red[j];
+    return x;
+}
+
 // Entries of bucket p of a hub, over all its chunks, processed kAggTile chunks
 // at a time: an LDS prefix sum over the chunks' segment lengths turns the
 // bucket into one flat index space that every thread strides over (a binary
@@ -759,7 +968,7 @@ template <typename G, bool LP>
 __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, G vu, G S, G K,
                                            const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
                                            int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
-                                           int32_t &bx, int64_t &ncand, uint64_t hv) {
+                                           int32_t &bx, G &ub, int64_t &ncand, uint64_t hv) {
     const int32_t nch = ha.nchunk[hg];
     const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
     const int32_t *sx = ha.stg_x + ha.stg_off[hg];
@@ -768,7 +977,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     const int32_t max_keys = ha.agg_max_keys > 0 ? ha.agg_max_keys : kAggMaxKeys;
     const int32_t tile = ha.agg_tile > 0 ? ha.agg_tile : kAggTile;
     for (int qbits = 0;; ++qbits) {
-        G pbs = neg_inf<G>();
+        G pbs = neg_inf<G>(), pub = neg_inf<G>();
         int32_t pbx = kNone;
         int64_t pc = 0;
         bool ok = true;
@@ -854,12 +1063,13 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                 break;
             }
             eval_slots<G, int64_t, LP>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx,
-                                       pc, hv);
+                                       pub, pc, hv);
             __syncthreads();
         }
         if (ok) {
             bs = pbs;
             bx = pbx;
+            ub = pub;
             ncand += pc;
             return;
         }
@@ -879,6 +1089,17 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     const int64_t p = blockIdx.x - ha.agg_first[hg];
     const int32_t u = ha.hub_u[hg];
     if (LP && !ms.active[u]) return;
+    if (!LP) {
+        // whether the hub is settled, and the clock its decision is taken at,
+        // for the reduce (which runs while the class's moves advance the clock)
+        const Settle st = settle_state(ms);
+        const bool sk = settled(ms, st, u);
+        if (p == 0 && threadIdx.x == 0) {
+            ha.hub_skip[hg] = sk ? 1 : 0;
+            ha.hub_clk[hg] = st.now;
+        }
+        if (sk) return;
+    }
     const int64_t vu = ms.vol[u];
     // w(u, D \ u) from the chunk shares (written by the chunk launch) and the
     // score of staying, which bounds the slots worth a volume gather
@@ -897,21 +1118,29 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     int64_t ncand = 0;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
+    int64_t slack = 0;  // of this bucket's communities (thread 0)
     const int64_t S_u = node_S(ms, u);
     const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
     if (force_wide || vu > node_wl(ms, u)) {
         const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
         const i128 K = Sg * (i128)wD - vg * (i128)base + (LP ? (i128)kLpTieMax : (i128)0);
-        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
+        i128 ub = neg_inf<i128>();
+        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ub,
                              ncand, hv);
         block_argmax<i128>(bs, bx);
+        ub = block_max<i128>(ub);
+        int64_t ks;
+        slack_of<i128>(K, ub, slack, ks);
     } else {
         const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
         const int64_t K = Sg * wD - vg * base + (LP ? (int64_t)kLpTieMax : 0);
-        int64_t b64 = neg_inf<int64_t>();
+        int64_t b64 = neg_inf<int64_t>(), ub = neg_inf<int64_t>();
         agg_bucket<int64_t, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
-                                ncand, hv);
+                                ub, ncand, hv);
         block_argmax<int64_t>(b64, bx);
+        ub = block_max<int64_t>(ub);
+        int64_t ks;
+        slack_of<int64_t>(K, ub, slack, ks);
         bs = (i128)b64;
     }
     if (threadIdx.x == 0) {
@@ -919,6 +1148,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         part[0] = (unsigned long long)(uint64_t)(bs >> 64);
         part[1] = (unsigned long long)(uint64_t)bs;
         part[2] = (unsigned long long)(uint32_t)bx;
+        part[3] = (unsigned long long)slack;
     }
     count_candidates(ms.cand_dev ? ms.cand_dev + 3 : nullptr, ncand);
 }
@@ -947,15 +1177,22 @@ __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveS
     __shared__ int32_t dec;
     const int32_t u = ha.hub_u[hg];
     if (LP && !ms.active[u]) return;  // nothing decided, nothing to apply
+    // settled (decided by the bucket launch before any move of the class): stays
+    const bool sk = !LP && ms.sctl && ms.sctl[0];
+    if (sk && ha.hub_skip[hg]) return;
     const int64_t nagg = (int64_t)1 << ha.pbits[hg];
     const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
+    int64_t slack = INT64_MAX;
     for (int64_t j = threadIdx.x; j < nagg; j += kHubThreads) {
         int32_t x = (int32_t)p0[4 * j + 2];
         i128 s = (i128)(((unsigned __int128)p0[4 * j + 0] << 64) | p0[4 * j + 1]);
         if (x != kNone && (s > bs || (s == bs && x < bx))) { bs = s; bx = x; }
+        const int64_t sl = (int64_t)p0[4 * j + 3];
+        if (sl < slack) slack = sl;
     }
+    if (sk) slack = -block_max<int64_t>(-slack);  // the smallest bucket slack, in thread 0
     int64_t wD = 0;
     for (int64_t j = threadIdx.x; j < ha.nchunk[hg]; j += kHubThreads) wD += ha.wd_part[ha.ins_first[hg] + j];
     wD = wave_sum(wD);
@@ -970,11 +1207,29 @@ __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveS
                  (LP ? (i128)kLpTieMax : (i128)0);
         dec = (bx != kNone && bs > K) ? bx : -1;
         if (dec >= 0) atomicAdd(ms.moves_dev, (unsigned long long)apply_move(ms, u, dec));
+        if (sk) {
+            if (dec >= 0) {
+                atomicAdd(&ms.sctl[1], (unsigned long long)(2 * vu));
+            } else {
+                int64_t s_, k_;
+                slack_of<i128>(K, K - (i128)slack, s_, k_);  // slack = the smallest bucket slack
+                record_stay(ms, Settle{true, ha.hub_clk[hg]}, u, s_, k_);
+            }
+        }
     }
     if (LP) {
         __syncthreads();
         if (dec >= 0) lp_activate(g, ms.active, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads);
         else if (threadIdx.x == 0) ms.active[u] = 0;
+    } else if (sk) {
+        __syncthreads();
+        if (dec >= 0) {
+            switch (g.wkind) {
+                case 0: mark_moved<0>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
+                case 1: mark_moved<1>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
+                default: mark_moved<2>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
+            }
+        }
     }
 }
 
@@ -993,7 +1248,7 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
     }
     __shared__ int64_t red[kHubThreads / kWave];
     const int64_t nblk = (int64_t)gridDim.x - nred;
-    int64_t moved = 0;
+    int64_t moved = 0, mvol = 0;
     if (LP) {
         for (int64_t i = ((int64_t)blockIdx.x - nred) * kHubThreads + threadIdx.x; i < count;
              i += nblk * kHubThreads) {
@@ -1004,6 +1259,7 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
     } else {
         // wavefront-uniform trips: the volume updates of moves that leave or
         // join the same community are combined per wavefront
+        const bool sk = ms.sctl && ms.sctl[0];
         for (int64_t i0 = ((int64_t)blockIdx.x - nred) * kHubThreads + (threadIdx.x & ~(kWave - 1)); i0 < count;
              i0 += nblk * kHubThreads) {
             const int64_t i = i0 + lane_id();
@@ -1018,10 +1274,15 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
                 ms.zeta[u] = X;
                 if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
                 ++moved;
+                mvol += join;
             }
             if (wave_group_sum(X, mv, join)) atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)join);
             if (wave_group_sum(D, mv, leave))
                 atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-leave));
+        }
+        if (sk) {
+            mvol = wave_sum(mvol);
+            if (lane_id() == 0 && mvol) atomicAdd(&ms.sctl[1], (unsigned long long)(2 * mvol));
         }
     }
     moved = wave_sum(moved);
