@@ -84,11 +84,19 @@ typedef struct {
     int32_t int_mode;     /* PLM_INT_AUTO: 64-bit gains where S*vol(u) < 2^62, else
                              128-bit; PLM_INT_128: always 128-bit (same results);
                              PLM_INT_64: 64-bit only, PLM_E_STATE if unsafe */
-    int32_t bin_lane;     /* rows up to this length: one lane per node (0 = 16) */
-    int32_t bin_wave;     /* rows up to this length: one wavefront per node (0 = 512) */
-    int32_t bin_block;    /* rows up to this length: one workgroup per node (0 = 4096);
+    /* Degree bins (scheduling of the per-node community accumulation).  0
+     * (the default) takes the value of the tuned table: tuned_bins.txt beside
+     * the library (written by the package's tune.py; the environment variable
+     * PLM_TUNED_TABLE names another file), whose first row of the context's
+     * kind (batch or single graph) covering its entry count applies; without
+     * one, the compiled defaults 16 / 512 / 4096 (and 12288 for hub_row_max).
+     * Any setting gives the same results.  plm_get_options reports the values
+     * a context took. */
+    int32_t bin_lane;     /* rows up to this length: one lane per node (1..16) */
+    int32_t bin_wave;     /* rows up to this length: one wavefront per node (..512) */
+    int32_t bin_block;    /* rows up to this length: one workgroup per node (..4096);
                              longer rows ("hubs"): one 1024-thread workgroup up to
-                             12288 entries, else several workgroups per node.
+                             hub_row_max entries, else several workgroups per node.
                              Rows of the wavefront and workgroup bins whose vol(u)
                              reaches 2^31 also take the hub path. */
     int32_t timing;       /* 1: time the move-decide launches with HIP events */
@@ -129,12 +137,13 @@ typedef struct {
                               one workgroup (one launch for many rounds); 0: every
                               round is a grid launch.  Same colours. */
     /* Limits of the partitioned hub path (section III-B's per-node community
-     * accumulation spread over several workgroups), lowered only to exercise
-     * its rarely reached branches on small graphs; same results, slower.
-     * 0 = the default of each. */
-    int32_t hub_row_max;   /* hub-bin rows longer than this (default 12288, else
-                              1..12288) take the partitioned path instead of one
-                              1024-thread workgroup */
+     * accumulation spread over several workgroups).  hub_row_max is tuned like
+     * the bins above; agg_max_keys and agg_tile are lowered only to exercise
+     * rarely reached branches on small graphs (same results, slower).  0 = the
+     * tuned value / the default of each. */
+    int32_t hub_row_max;   /* hub-bin rows longer than this (1..12288; compiled
+                              default 12288) take the partitioned path instead of
+                              one 1024-thread workgroup */
     int32_t agg_max_keys;  /* distinct communities one bucket workgroup takes in a
                               pass before it splits the bucket into sub-partition
                               passes (default 1536, else 32..1536) */
@@ -151,6 +160,19 @@ typedef struct {
 
 /* Fills *opt with the defaults above. */
 void plm_default_options(plm_options *opt);
+
+/* The options a context runs with, after the tuned table filled the degree
+ * bins left at 0. */
+plm_status plm_get_options(plm_ctx *ctx, plm_options *out);
+
+/* Path of the tuned table in use ("" when none was found or none of its rows
+ * is valid).  The table is read once per process. */
+const char *plm_tuned_table(void);
+
+/* Fills the degree bins of *opt left at 0 as a context would: batched != 0
+ * for plm_batch_create, nnz its entry count.  No device work.  PLM_E_ARG for
+ * invalid options. */
+plm_status plm_resolve_options(plm_options *opt, int32_t batched, int64_t nnz);
 
 /* Creates a context holding a private copy of the graph (inputs may be freed
  * as soon as the call returns) and the level-0 state: vol(u) (section III-B),

@@ -108,6 +108,12 @@ def _load():
     lib.plm_modularity.argtypes = [vp, vp, i32, P(dbl)]
     lib.plm_modularity_noalloc.argtypes = [vp, vp, P(dbl)]
     lib.plm_reset.argtypes = [vp]
+    lib.plm_get_options.argtypes = [vp, P(plm_options)]
+    lib.plm_get_options.restype = i32
+    lib.plm_resolve_options.argtypes = [P(plm_options), i32, i64]
+    lib.plm_resolve_options.restype = i32
+    lib.plm_tuned_table.argtypes = []
+    lib.plm_tuned_table.restype = ctypes.c_char_p
     lib.plm_destroy.argtypes = [vp]
     lib.plm_destroy.restype = None
     lib.plm_last_error.argtypes = [vp]
@@ -150,6 +156,19 @@ plm_modularity = _lib.plm_modularity
 plm_modularity_noalloc = _lib.plm_modularity_noalloc
 PLM_NOALLOC_MAX_NODES = 1 << 23
 plm_reset = _lib.plm_reset
+plm_get_options = _lib.plm_get_options
+plm_tuned_table = _lib.plm_tuned_table
+plm_resolve_options = _lib.plm_resolve_options
+
+
+def resolve_options(batched: bool, nnz: int, **kw) -> plm_options:
+    """The options a context (batched or not, of nnz entries) takes for kw:
+    degree bins left at 0 filled from the tuned table or the compiled defaults."""
+    o = default_options(**kw)
+    rc = plm_resolve_options(ctypes.byref(o), int(batched), int(nnz))
+    if rc != 0:
+        raise PLMError(rc, "invalid options")
+    return o
 plm_destroy = _lib.plm_destroy
 plm_last_error = _lib.plm_last_error
 plm_level_info = _lib.plm_level_info
@@ -300,6 +319,12 @@ class Context:
 
     def reset(self):
         self._check(plm_reset(self._c))
+
+    def options(self) -> plm_options:
+        """The options the context runs with (degree bins resolved)."""
+        o = plm_options()
+        self._check(plm_get_options(self._c, ctypes.byref(o)))
+        return o
 
     # ---- inspection
     def level_info(self) -> plm_level_info_t:

@@ -3,9 +3,14 @@
 // Algorithm 3 with prolongation.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -1255,6 +1260,9 @@ struct plm_ctx {
 // ------------------------------------------------------------------ C ABI
 namespace {
 
+const char *const kBinsMsg =
+    "bins must satisfy 1 <= bin_lane <= 16, bin_lane <= bin_wave <= 512, bin_wave <= bin_block <= 4096 (0: tuned)";
+
 int check_options(const plm_options &o, std::string &msg) {
     if (o.max_sweeps < 1) { msg = "max_sweeps must be >= 1"; return PLM_E_ARG; }
     if (o.max_levels < 0) { msg = "max_levels must be >= 0"; return PLM_E_ARG; }
@@ -1280,10 +1288,18 @@ int check_options(const plm_options &o, std::string &msg) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
         return PLM_E_ARG;
     }
-    int64_t a = o.bin_lane > 0 ? o.bin_lane : 16, b = o.bin_wave > 0 ? o.bin_wave : 512,
-            c = o.bin_block > 0 ? o.bin_block : 4096;
-    if (a > 16 || b > 512 || c > 4096 || a > b || b > c) {
-        msg = "bins must satisfy bin_lane <= 16, bin_lane <= bin_wave <= 512, bin_wave <= bin_block <= 4096";
+    // each bin in range here; their order once the zeros are filled (check_bins)
+    if (o.bin_lane < 0 || o.bin_wave < 0 || o.bin_block < 0 || o.bin_lane > 16 || o.bin_wave > 512 ||
+        o.bin_block > 4096) {
+        msg = kBinsMsg;
+        return PLM_E_ARG;
+    }
+    return PLM_OK;
+}
+
+int check_bins(const plm_options &o, std::string &msg) {
+    if (o.bin_lane > o.bin_wave || o.bin_wave > o.bin_block) {
+        msg = kBinsMsg;
         return PLM_E_ARG;
     }
     return PLM_OK;
@@ -1349,9 +1365,10 @@ void plm_default_options(plm_options *o) {
     o->validate = 1;
     o->colour_seed = 0;
     o->int_mode = PLM_INT_AUTO;
-    o->bin_lane = 16;
-    o->bin_wave = 512;
-    o->bin_block = 4096;
+    o->bin_lane = 0;  // 0: the tuned table's value, else the compiled default
+    o->bin_wave = 0;
+    o->bin_block = 0;
+    o->hub_row_max = 0;
     o->timing = 0;
     o->gamma_num = 1;
     o->gamma_den = 1;
@@ -1363,6 +1380,83 @@ void plm_default_options(plm_options *o) {
 }  // extern "C"
 
 namespace {
+
+// ---------------------------------------------------------------- tuned bins
+// Degree-bin thresholds and the one-workgroup hub limit left at 0 come from
+// the table the tuner (tune.py) writes beside the library, tuned_bins.txt
+// (PLM_TUNED_TABLE names another file): rows "kind max_nnz bin_lane bin_wave
+// bin_block hub_row_max", kind batch or single, max_nnz 0 = any size; the
+// first row of the context's kind whose max_nnz covers its entries applies.
+// Without a table or a matching row, the compiled defaults 16 / 512 / 4096 /
+// 12288 apply.  Rows outside the valid ranges are ignored.
+struct TunedRow {
+    bool batch;
+    int64_t max_nnz;
+    int32_t lane, wave, block, hub_max;
+};
+std::vector<TunedRow> g_tuned;
+std::string g_tuned_source;
+std::once_flag g_tuned_once;
+
+bool bins_valid(int64_t a, int64_t b, int64_t c, int64_t h) {
+    return a >= 1 && b >= 1 && c >= 1 && h >= 1 && a <= 16 && b <= 512 && c <= 4096 && a <= b && b <= c &&
+           h <= kSingleMaxRow;
+}
+
+void load_tuned() {
+    std::string path;
+    if (const char *e = std::getenv("PLM_TUNED_TABLE")) {
+        path = e;
+    } else {
+        Dl_info info;
+        if (dladdr((void *)&load_tuned, &info) && info.dli_fname) {
+            std::string so = info.dli_fname;
+            size_t k = so.rfind('/');
+            path = (k == std::string::npos ? std::string(".") : so.substr(0, k)) + "/tuned_bins.txt";
+        }
+    }
+    std::ifstream f(path);
+    if (!f) return;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string kind;
+        TunedRow r;
+        if (!(is >> kind >> r.max_nnz >> r.lane >> r.wave >> r.block >> r.hub_max)) continue;
+        if (kind != "batch" && kind != "single") continue;
+        if (r.max_nnz < 0 || !bins_valid(r.lane, r.wave, r.block, r.hub_max)) continue;
+        r.batch = kind == "batch";
+        g_tuned.push_back(r);
+    }
+    if (!g_tuned.empty()) g_tuned_source = path;
+}
+
+// Fills the bin thresholds of o left at 0: from the tuned table's row for
+// (batch, nnz), else the compiled defaults.  A mix with the caller's own
+// values that breaks the bin order falls back to the compiled defaults for
+// the zero fields.
+void resolve_bins(plm_options &o, bool batch, int64_t nnz) {
+    if (o.bin_lane > 0 && o.bin_wave > 0 && o.bin_block > 0 && o.hub_row_max > 0) return;
+    std::call_once(g_tuned_once, load_tuned);
+    const TunedRow *row = nullptr;
+    for (const TunedRow &r : g_tuned)
+        if (r.batch == batch && (r.max_nnz == 0 || nnz <= r.max_nnz)) { row = &r; break; }
+    const int32_t dl = 16, dw = 512, db = 4096, dh = (int32_t)kSingleMaxRow;
+    plm_options t = o;
+    if (t.bin_lane <= 0) t.bin_lane = row ? row->lane : dl;
+    if (t.bin_wave <= 0) t.bin_wave = row ? row->wave : dw;
+    if (t.bin_block <= 0) t.bin_block = row ? row->block : db;
+    if (t.hub_row_max <= 0) t.hub_row_max = row ? row->hub_max : dh;
+    if (!bins_valid(t.bin_lane, t.bin_wave, t.bin_block, t.hub_row_max)) {
+        t = o;
+        if (t.bin_lane <= 0) t.bin_lane = dl;
+        if (t.bin_wave <= 0) t.bin_wave = dw;
+        if (t.bin_block <= 0) t.bin_block = db;
+        if (t.hub_row_max <= 0) t.hub_row_max = dh;
+    }
+    o = t;
+}
 
 // Shared by plm_create (G = 0) and plm_batch_create (G >= 1 graphs on the node
 // ranges node_base[0..G]).
@@ -1402,6 +1496,9 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
     int rc = check_options(o, m);
     if (rc) return fail_adopt(rc, m);
     if (o.gamma_num == 0 && o.gamma_den == 0) o.gamma_num = o.gamma_den = 1;
+    resolve_bins(o, G > 0, nnz);
+    rc = check_bins(o, m);
+    if (rc) return fail_adopt(rc, m);
     if (G > 0) {
         if (o.refine) return fail_adopt(PLM_E_ARG, "batched runs do not refine");
         if (o.schedule != PLM_SCHEDULE_COLOUR) return fail_adopt(PLM_E_ARG, "batched runs use the colour schedule");
@@ -1713,6 +1810,27 @@ plm_status plm_modularity_noalloc(plm_ctx *ctx, const int32_t *labels, double *q
             throw Error{PLM_E_ARG, "labels must lie in [0, n)"};
         if (q_out) *q_out = ctx->S == 0 ? 0.0 : (double)num / (double)den;
     });
+}
+
+plm_status plm_get_options(plm_ctx *ctx, plm_options *out) {
+    return guarded(ctx, [&] {
+        if (!out) throw Error{PLM_E_ARG, "out is NULL"};
+        *out = ctx->opt;
+    });
+}
+
+plm_status plm_resolve_options(plm_options *o, int32_t batched, int64_t nnz) {
+    if (!o || nnz < 0) return PLM_E_ARG;
+    std::string m;
+    const int rc = check_options(*o, m);
+    if (rc) return rc;
+    resolve_bins(*o, batched != 0, nnz);
+    return check_bins(*o, m);
+}
+
+const char *plm_tuned_table(void) {
+    std::call_once(g_tuned_once, load_tuned);
+    return g_tuned_source.c_str();
 }
 
 plm_status plm_reset(plm_ctx *ctx) {

@@ -66,9 +66,9 @@ def test_default_options(built):
     import paper_1304_4453_amd as P
     o = P.default_options()
     assert (o.max_sweeps, o.max_levels, o.schedule, o.validate, o.int_mode) == (32, 0, 0, 1, 0)
-    assert (o.bin_lane, o.bin_wave, o.bin_block, o.timing) == (16, 512, 4096, 0)
+    assert (o.bin_lane, o.bin_wave, o.bin_block, o.timing) == (0, 0, 0, 0)   # 0: tuned table
     assert (o.graph_sweeps, o.hub_stream, o.colour_tail) == (1, 2, 1)
-    assert (o.hub_row_max, o.agg_max_keys, o.agg_tile) == (0, 0, 0)
+    assert (o.hub_row_max, o.agg_max_keys, o.agg_tile, o.settle) == (0, 0, 0, 0)
 
 
 def test_argument_errors_need_no_gpu(built):
