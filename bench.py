@@ -41,15 +41,34 @@ WORKLOADS = {
 }
 
 
-def roofline(st, level=0):
-    """Roofline of the move-decide kernel with the most device time at a level:
-    algorithmic bytes (section 8(d) of the design: per entry column, weight and
-    neighbour community; per distinct candidate its volume; per node 32 bytes)
-    over the kernel's event-timed duration, against the HBM peak."""
+def group_times(st, level):
+    """Device ms and algorithmic bytes of the five move-decide kernel groups at a level."""
     bm, bb = st["bin_ms"][level], st["bin_bytes"][level]
     ms = [bm[0], bm[1], bm[2], st["hub_single_ms"][level], bm[3] - st["hub_single_ms"][level]]
     by = [bb[0], bb[1], bb[2], st["hub_single_bytes"][level], bb[3] - st["hub_single_bytes"][level]]
-    k = max(range(5), key=lambda i: ms[i])
+    return ms, by
+
+
+def dominant(st):
+    """(level, group) of the move-decide kernel group with the most device time over the run."""
+    best = (0, 0, -1.0)
+    for level in range(st["levels"]):
+        ms, _ = group_times(st, level)
+        for k in range(5):
+            if ms[k] > best[2]:
+                best = (level, k, ms[k])
+    return best[0], best[1]
+
+
+def roofline(st, level=0, k=None):
+    """Roofline of a move-decide kernel group (by default the one with the most
+    device time at the level): algorithmic bytes (per entry of a scanned row
+    its column, weight and neighbour community; per distinct candidate its
+    volume; per decided node 32 bytes; per settled node the 36 bytes of its
+    check) over the group's event-timed duration, against the HBM peak."""
+    ms, by = group_times(st, level)
+    if k is None:
+        k = max(range(5), key=lambda i: ms[i])
     launches = st["kernel_launches"][level][k]
     achieved = by[k] / (ms[k] * 1e6) if ms[k] > 0 else 0.0
     sweeps = max(st["sweeps"][level], 1)
@@ -63,13 +82,31 @@ def roofline(st, level=0):
             # every decide kernel of every level and executed sweep together
             "all_levels_decide_GBs": sum(st["decide_bytes"]) / (sum(st["decide_ms"]) * 1e6)
             if sum(st["decide_ms"]) else 0.0,
-            "kernels": KERNELS, "kernel_ms": ms, "kernel_bytes": by}
+            "kernels": KERNELS, "kernel_ms": ms, "kernel_bytes": by,
+            "decided_nodes": st["decided_nodes"][level], "settled_nodes": st["settled_nodes"][level],
+            "decided_entries": st["decided_entries"][level]}
 
 
-def counter_traffic(kernel):
+def level_summary(st):
+    """Per level: the dominant decide group's roofline, all decide kernels
+    together, the skipped (settled) decisions, and the colouring's rounds."""
+    out = []
+    for level in range(min(st["levels"], 4)):
+        r = roofline(st, level)
+        out.append({"level": level, "dominant_kernel": r["kernel"], "achieved_GBs": r["achieved"],
+                    "frac": r["frac"], "avg_launch_us": r["avg_launch_us"],
+                    "all_decide_GBs": r["all_decide_GBs"], "decide_ms": st["decide_ms"][level],
+                    "decided_nodes": st["decided_nodes"][level], "settled_nodes": st["settled_nodes"][level],
+                    "colour_rounds": st["schedule_rounds"][level], "colour_ms": st["colour_ms"][level],
+                    "colour_us_per_round": st["colour_ms"][level] * 1e3 / max(st["schedule_rounds"][level], 1)})
+    return out
+
+
+def counter_traffic(kernel, level=0):
     """Per-launch HBM traffic of a move-decide kernel group from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or
-    None when the kernels' source has changed since the counters were taken."""
+    None when the kernels' source has changed since the counters were taken or
+    the summary covers another level."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "decide_traffic_rmat26.md")
     src = os.path.join(ROOT, "paper_1304_4453_amd", "csrc", "move.hip")
@@ -78,12 +115,14 @@ def counter_traffic(kernel):
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
         if blob["move_hip_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
             return None
+        if blob.get("level", 0) != level:
+            return None
         for k in blob["kernels"]:
             if k["kernel"] == kernel:
                 return {"bytes_per_launch": k["traffic_bytes_per_launch"],
                         "algorithmic_bytes_per_launch_same_sweep": k["algorithmic_bytes_per_launch"],
                         "fetch_scale": blob["fetch_scale"], "write_scale": blob["write_scale"],
-                        "source": "profiles/decide_traffic_rmat26.md (level-0 sweep 1)"}
+                        "source": f"profiles/decide_traffic_rmat26.md (level-{level} sweep)"}
     except (OSError, KeyError, IndexError, ValueError):
         return None
     return None
@@ -211,6 +250,66 @@ def cpu_baseline(gr, ctx_state, budget_s=15.0):
             "seconds": dt, "host": host_info()}
 
 
+def cpu_full_run(P, torch, scale=18):
+    """The oracle's whole PLM run (all levels) on R-MAT scale `scale` (unit
+    weights, seed 2), single-threaded, phase by phase through its exported
+    steps (volumes, colouring, sweeps until one moves nothing or 32, relabel,
+    contraction), beside plm_run on the same graph on the GPU; both must give
+    the same level trace."""
+    import numpy as np
+    import graphgen
+    import oracle
+    g = graphgen.rmat(scale, 16, seed=2, weighted=False)
+    m = g.undirected_edges()
+    off, col = g.off.astype(np.int64), g.col.astype(np.int32)
+    w2 = oracle.double_diagonal(off, col, g.w)
+    phases = {"colouring_s": 0.0, "sweeps_s": 0.0, "coarsening_s": 0.0, "volumes_s": 0.0}
+    trace = []
+    t_all = time.perf_counter()
+    level = 0
+    while True:
+        t = time.perf_counter()
+        vol, S = oracle.volumes(off, w2)
+        phases["volumes_s"] += time.perf_counter() - t
+        t = time.perf_counter()
+        colours, C = oracle.colour(off, col, 0, level, 0)
+        phases["colouring_s"] += time.perf_counter() - t
+        zeta = np.arange(len(vol), dtype=np.int32)
+        volC = vol.copy()
+        t = time.perf_counter()
+        sweeps = 0
+        for _ in range(32):
+            sweeps += 1
+            if oracle.sweep(off, col, w2, vol, S, colours, C, zeta, volC) == 0:
+                break
+        phases["sweeps_s"] += time.perf_counter() - t
+        t = time.perf_counter()
+        pi, k = oracle.relabel(zeta)
+        trace.append((len(vol), int(C), sweeps, int(k)))
+        if k == len(vol):
+            break
+        off, col, w2 = oracle.contract(off, col, w2, pi, k)
+        phases["coarsening_s"] += time.perf_counter() - t
+        level += 1
+    total = time.perf_counter() - t_all
+    dev = torch.device("cuda:0")
+    with P.Context(torch.from_numpy(g.off).to(dev), torch.from_numpy(g.col).to(dev), None, n=g.n, nnz=g.nnz,
+                   mem_kind=P.PLM_MEM_DEVICE) as ctx:
+        lab = torch.empty(g.n, dtype=torch.int32, device=dev)
+        ctx.run(lab)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.run(lab)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t
+        st = ctx.stats()
+    gpu_trace = [(st["n"][i], st["colours"][i], st["sweeps"][i], st["communities"][i]) for i in range(st["levels"])]
+    return {"graph": f"R-MAT scale {scale}, edge factor 16, unit weights, seed 2 ({g.n} nodes, {m} edges)",
+            "seconds": total, "edges_per_s": m / total, "cores": 1,
+            "phases_s": phases, "levels": len(trace), "same_level_trace_as_gpu": trace == gpu_trace,
+            "gpu_plm_run_s": tg, "gpu_speedup": total / tg}
+
+
 BATCH_DESC = ("4,096 SBM graphs, n log-uniform in [100, 100000], k = max(2, n/100) near-equal blocks, "
               "p_in = 20/blocksize, p_out = 1/n, unit weights, seed 4")
 
@@ -304,14 +403,55 @@ SERVE_DESC = ("Poisson arrivals at 200 req/s of R-MAT graphs, scale uniform in [
               "a=.57 b=.19 c=.19 d=.05, unit weights, request seeds from seed 5; HBM budget 200 GB")
 
 
+def serve_replay(P, torch, np, dgs, arr, check, join, inflight):
+    """One open-loop real-time replay of the request stream against the native
+    request server; returns (latencies, results of the checked requests,
+    makespan, server info)."""
+    count = len(dgs)
+    check_lab = {i: torch.empty(dgs[i].n, dtype=torch.int32, device="cuda:0") for i in check}
+    srv = P.Server(200 * 10 ** 9, max_inflight=inflight, join=int(join))
+    ids, lat, done_q = {}, np.full(count, np.nan), {}
+    nxt, t0 = 0, time.perf_counter()
+    while len(done_q) < count:
+        now = time.perf_counter() - t0
+        while nxt < count and arr[nxt] <= now:
+            d = dgs[nxt]
+            ids[nxt] = srv.submit(d.off_ptr, d.col_ptr, None, mem_kind=P.PLM_MEM_DEVICE, n=d.n, nnz=d.nnz)
+            nxt += 1
+        if srv.info().queued > 0:
+            srv.step()  # fixed batches, one in flight: runs a batch; otherwise hands one to a free worker
+        tdone = time.perf_counter() - t0
+        progressed = False
+        for i, rid in list(ids.items()):
+            if i in done_q:
+                continue
+            ready, _, q, lv = srv.result(rid, check_lab.get(i))
+            if ready:
+                done_q[i] = (q, lv)
+                lat[i] = tdone - arr[i]
+                progressed = True
+        if not progressed:
+            pause = 0.0005
+            if srv.info().inflight == 0 and nxt < count:
+                pause = max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.01))
+            time.sleep(pause)
+    makespan = time.perf_counter() - t0
+    info = srv.info()
+    srv.close()
+    checked = {i: (check_lab[i].cpu().numpy(),) + done_q[i] for i in check}
+    return lat, checked, makespan, info
+
+
 def serve_bench(args, P, torch, np):
     """Served PLM: the request stream of the arrival window is generated on the
     GPU first (client buffers), then replayed open-loop in real time against
-    the native request server (plm_server_*): each request is submitted at its
-    arrival time; a step admits the queued requests that fit beside the batches
-    in flight as one batch and hands it to a free worker of the server (up to
-    --serve-inflight batches share the device); a request's latency is its
-    result-ready time minus its arrival time."""
+    the native request server (plm_server_*), each request submitted at its
+    arrival time; a request's latency is its result-ready time minus its
+    arrival time.  Two replays of the same stream: continuous batching (join =
+    1: a running batch takes the queued requests in at each level boundary and
+    every request completes when its own run ends), then fixed batches (a step
+    admits the queued requests that fit as one batch, which reports at its
+    end; --serve-inflight batches at once)."""
     import graphgen
     import oracle
     rate = 200.0
@@ -324,37 +464,13 @@ def serve_bench(args, P, torch, np):
     log(f"serve: {count} requests ({edges} edges) generated in {time.time() - t:.1f}s")
     # a few small requests are checked against the oracle afterwards
     check = [i for i in range(count) if scales[i] <= 13][:3]
-    check_lab = {i: torch.empty(dgs[i].n, dtype=torch.int32, device="cuda:0") for i in check}
-    srv = P.Server(200 * 10 ** 9, max_inflight=args.serve_inflight)
-    ids, lat, done_q = {}, np.full(count, np.nan), {}
-    nxt, t0 = 0, time.perf_counter()
-    while len(done_q) < count:
-        now = time.perf_counter() - t0
-        while nxt < count and arr[nxt] <= now:
-            d = dgs[nxt]
-            ids[nxt] = srv.submit(d.off_ptr, d.col_ptr, None, mem_kind=P.PLM_MEM_DEVICE, n=d.n, nnz=d.nnz)
-            nxt += 1
-        if srv.info().queued > 0:
-            srv.step()  # one inflight: runs a batch; several: hands one to a free worker
-        tdone = time.perf_counter() - t0
-        progressed = False
-        for i, rid in list(ids.items()):
-            if i in done_q:
-                continue
-            ready, _, q, lv = srv.result(rid, check_lab.get(i))
-            if ready:
-                done_q[i] = (q, lv)
-                lat[i] = tdone - arr[i]
-                dgs[i].free()
-                progressed = True
-        if not progressed:
-            pause = 0.0005
-            if srv.info().inflight == 0 and nxt < count:
-                pause = max(0.0, min(arr[nxt] - (time.perf_counter() - t0), 0.01))
-            time.sleep(pause)
-    makespan = time.perf_counter() - t0
-    info = srv.info()
-    srv.close()
+    lat, checked, makespan, info = serve_replay(P, torch, np, dgs, arr, check, True, 1)
+    log(f"serve (continuous batching): {count} requests in {makespan:.1f}s, {info.batches} batches, "
+        f"{info.joined} joined a running batch")
+    lat_f, checked_f, makespan_f, info_f = serve_replay(P, torch, np, dgs, arr, check, False, args.serve_inflight)
+    log(f"serve (fixed batches): {count} requests in {makespan_f:.1f}s over {info_f.batches} batches")
+    for d in dgs:
+        d.free()
     # the same kind of requests one by one through plm_run (random sample,
     # contexts created beforehand, inputs resident in HBM)
     rng = np.random.default_rng(5)
@@ -377,22 +493,27 @@ def serve_bench(args, P, torch, np):
     for i in check:
         g = graphgen.rmat(int(scales[i]), 16, seed=int(seeds[i]), weighted=False)
         r = oracle.run(g.off, g.col, g.w)
-        ok += int(np.array_equal(check_lab[i].cpu().numpy(), r.labels[: g.n]) and done_q[i][0] == r.q
-                  and done_q[i][1] == r.levels)
-    log(f"serve: {count} requests in {makespan:.1f}s over {info.batches} batches")
+        for res in (checked[i], checked_f[i]):
+            ok += int(np.array_equal(res[0], r.labels[: g.n]) and res[1] == r.q and res[2] == r.levels)
     return {"workload": SERVE_DESC, "arrival_window_s": float(arr[-1]), "requests": count,
             "offered_req_per_s": rate, "offered_edges_per_s": edges / float(arr[-1]),
+            "mode": "continuous batching (requests join the running batch at its level boundaries)",
             "completed": int(np.isfinite(lat).sum()), "makespan_s": makespan, "graphs_per_s": count / makespan,
             "edges_per_s": edges / makespan, "p50_latency_s": float(np.nanpercentile(lat, 50)),
             "p99_latency_s": float(np.nanpercentile(lat, 99)), "max_latency_s": float(np.nanmax(lat)),
-            "batches": int(info.batches), "mean_batch": count / max(int(info.batches), 1),
-            "max_inflight": args.serve_inflight,
+            "batches": int(info.batches), "joined": int(info.joined),
+            "fixed_batches": {"max_inflight": args.serve_inflight, "makespan_s": makespan_f,
+                              "graphs_per_s": count / makespan_f,
+                              "p50_latency_s": float(np.nanpercentile(lat_f, 50)),
+                              "p99_latency_s": float(np.nanpercentile(lat_f, 99)),
+                              "batches": int(info_f.batches)},
             "plain_graphs_per_s": len(sample) / tp, "plain_sample": int(len(sample)),
             "speedup_vs_plain": (count / makespan) / (len(sample) / tp),
             "hbm_budget_bytes": 200 * 10 ** 9,
-            "verified_vs_oracle": f"{ok}/{len(check)} small requests (labels, Q, levels)",
+            "verified_vs_oracle": f"{ok}/{2 * len(check)} small requests over both replays (labels, Q, levels)",
             "note": "the offered load exceeds one GPU's throughput, so latency grows over the window; the window "
-                    "is bounded (--serve-seconds) so that the run ends within minutes"}
+                    "is bounded (--serve-seconds, default 2 s of the 60 s stream) so that the run ends within "
+                    "minutes: the full 60 s stream is not measured"}
 
 
 def plmr_bench(gr, P, torch, q_plm, st_plm):
@@ -490,11 +611,12 @@ def gamma_bench(P, torch):
     return {"workload": "R-MAT scale 20, edge factor 16, unit weights, seed 2", "runs": out}
 
 
-def sweep_probe(P, torch):
-    """One level-0 move sweep of the R-MAT 26 workload with every move-decide
-    kernel timed, after a 1 GiB device copy that calibrates the HBM byte
-    counters; for rocprofv3 --pmc runs.  Prints the sweep's per-kernel
-    algorithmic bytes and launch counts as one JSON line."""
+def sweep_probe(P, torch, level=0):
+    """One move sweep of the R-MAT 26 workload at a level (level 1: after the
+    level-0 move phase and its contraction) with every move-decide kernel
+    timed, after a 1 GiB device copy that calibrates the HBM byte counters;
+    for rocprofv3 --pmc runs.  Prints the sweep's per-kernel algorithmic bytes
+    and launch counts as one JSON line."""
     import ctypes
     import graphgen
     wl = WORKLOADS["rmat26"]
@@ -502,18 +624,29 @@ def sweep_probe(P, torch):
     ctx = P.Context(dg.off_ptr, dg.col_ptr, dg.w_ptr, mem_kind=P.PLM_MEM_DEVICE, n=dg.n, nnz=dg.nnz, timing=1,
                     validate=0)
     dg.free()
+    if level > 0:
+        for _ in range(level):
+            while ctx.move_sweep() > 0 and ctx.level_info().sweeps < 32:
+                pass
+            ctx.coarsen()
     x = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")  # 1 GiB
     y = x.clone()                                                # copy: 1 GiB read, 1 GiB written
     torch.cuda.synchronize()
     del x, y
-    moves = ctx.move_sweep()
     st = P.plm_stats_t()
     P.plm_get_stats(ctx._c, ctypes.byref(st))
-    bb, bm = list(st.bin_bytes[0]), list(st.bin_ms[0])
-    out = {"workload": wl["desc"], "sweep": 1, "moves": moves, "kernels": KERNELS,
-           "kernel_bytes": [bb[0], bb[1], bb[2], st.hub_single_bytes[0], bb[3] - st.hub_single_bytes[0]],
-           "kernel_ms": [bm[0], bm[1], bm[2], st.hub_single_ms[0], bm[3] - st.hub_single_ms[0]],
-           "kernel_launches": list(st.kernel_launches[0]), "calibration_copy_bytes": 1 << 30}
+    b0 = (list(st.bin_bytes[level]), list(st.bin_ms[level]), st.hub_single_bytes[level], st.hub_single_ms[level],
+          list(st.kernel_launches[level]))
+    moves = ctx.move_sweep()
+    P.plm_get_stats(ctx._c, ctypes.byref(st))
+    bb = [a - b for a, b in zip(st.bin_bytes[level], b0[0])]
+    bm = [a - b for a, b in zip(st.bin_ms[level], b0[1])]
+    hb, hm = st.hub_single_bytes[level] - b0[2], st.hub_single_ms[level] - b0[3]
+    out = {"workload": wl["desc"], "level": level, "sweep": ctx.level_info().sweeps, "moves": moves,
+           "kernels": KERNELS, "kernel_bytes": [bb[0], bb[1], bb[2], hb, bb[3] - hb],
+           "kernel_ms": [bm[0], bm[1], bm[2], hm, bm[3] - hm],
+           "kernel_launches": [a - b for a, b in zip(st.kernel_launches[level], b0[4])],
+           "calibration_copy_bytes": 1 << 30}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -537,8 +670,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served workload")
     ap.add_argument("--plain-serve-sample", type=int, default=40)
     ap.add_argument("--serve-inflight", type=int, default=1, help="batches the server may run at once")
-    ap.add_argument("--sweep-probe", action="store_true",
-                    help="one instrumented level-0 sweep of R-MAT 26 for hardware-counter runs")
+    ap.add_argument("--sweep-probe", type=int, default=None, metavar="LEVEL",
+                    help="one instrumented sweep of R-MAT 26 at this level for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -550,8 +683,8 @@ def main():
     import paper_1304_4453_amd as P
 
     torch.cuda.set_device(0)
-    if args.sweep_probe:
-        sweep_probe(P, torch)
+    if args.sweep_probe is not None:
+        sweep_probe(P, torch, args.sweep_probe)
         return
     t = time.time()
     gr = make_graph(args.workload)
@@ -569,7 +702,8 @@ def main():
     t = time.time()
     ctx.run(lab)
     st_probe = ctx.stats()
-    roof = roofline(st_probe)
+    dl, dk = dominant(st_probe)
+    roof = roofline(st_probe, dl, dk)
     log(f"instrumented step {time.time() - t:.2f}s: dominant {roof['kernel']}")
     ctx.close()
     ctx = mk(timing=0)
@@ -598,8 +732,9 @@ def main():
     roof["timing"] = ("HIP events attached to each move-decide dispatch (hipExtLaunchKernelGGL) on the library's "
                       "stream, in one instrumented step before the timed steps; the timed steps run without events")
     roof["measured_copy"] = copy_peak(torch)
+    roof["per_level"] = level_summary(st_probe)
     if args.workload == "rmat26":
-        tr = counter_traffic(roof["kernel"])
+        tr = counter_traffic(roof["kernel"], roof["level"])
         if tr is not None:
             roof["traffic"] = tr["bytes_per_launch"]
             roof["traffic_detail"] = tr
@@ -631,6 +766,9 @@ def main():
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(gr, state0, args.cpu_budget)
         log(f"cpu baseline {time.time() - t:.1f}s")
+        t = time.time()
+        out["cpu_baseline"]["full_run"] = cpu_full_run(P, torch)
+        log(f"oracle full run {time.time() - t:.1f}s")
     ctx.close()
     if not args.no_plmr:
         out["plmr"] = plmr_bench(gr, P, torch, q, st)

@@ -156,6 +156,14 @@ typedef struct {
                               without a new scan of its row.  0 (default): enabled
                               once a sweep of the phase moved at most n/16 nodes;
                               1: from the first sweep; -1: never.  Same results. */
+    int32_t join;          /* request servers (plm_server_create) only: k >= 1 =
+                              continuous batching: a running batch takes queued
+                              requests in at its first k level boundaries (each starts
+                              at level 0 of its own, so its result is that of its own
+                              run) and reports every request as soon as its run ends;
+                              batches then always run on the server's worker threads.
+                              0 (default): a batch is fixed when it starts and reports
+                              at its end. */
 } plm_options;
 
 /* Fills *opt with the defaults above. */
@@ -312,6 +320,7 @@ typedef struct {
     int64_t inflight;      /* batches admitted and not finished */
     int64_t running;       /* requests in those batches */
     int64_t resident_bytes; /* their footprint, charged against the budget */
+    int64_t joined;        /* requests that joined a running batch (opt.join) */
 } plm_server_info_t;
 
 /* Errors: PLM_E_ARG (budget or entry cap <= 0, max_inflight outside [1, 16],

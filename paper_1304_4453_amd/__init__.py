@@ -43,7 +43,8 @@ class plm_options(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("timing_kernel", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32),
                 ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32), ("hub_row_max", ctypes.c_int32),
-                ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32), ("settle", ctypes.c_int32)]
+                ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32), ("settle", ctypes.c_int32),
+                ("join", ctypes.c_int32)]
 
 
 class plm_level_info_t(ctypes.Structure):
@@ -81,7 +82,7 @@ class plm_stats_t(ctypes.Structure):
 class plm_server_info_t(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("held_results", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("inflight", ctypes.c_int64),
-                ("running", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+                ("running", ctypes.c_int64), ("resident_bytes", ctypes.c_int64), ("joined", ctypes.c_int64)]
 
 
 class PLMError(RuntimeError):

@@ -80,6 +80,7 @@ struct LevelData {
     // the first node of each graph (count + 1 entries)
     int32_t *gid = nullptr;
     int64_t *gbase = nullptr;
+    int32_t *gshift = nullptr;  // batches with joined graphs: per graph, the batch level it joined at
     // colouring of this level kept by a descent that refines on its way back
     // up (the refinement's colouring is the same: same graph, seed and level)
     int32_t *colour_kept = nullptr;
@@ -88,11 +89,11 @@ struct LevelData {
     GraphView view() const {
         GraphView g;
         g.n = n; g.nnz = nnz; g.off = off; g.col = col; g.w = w; g.wkind = wkind; g.diag_mult = diag_mult;
-        g.gid = gid; g.gbase = gbase;
+        g.gid = gid; g.gbase = gbase; g.gshift = gshift;
         return g;
     }
     void release() {
-        dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase);
+        dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase); dev_free(gshift);
         dev_free(colour_kept);
     }
 };
@@ -191,6 +192,10 @@ struct plm_ctx {
     void *bscan = nullptr;
     uint8_t *bstatus = nullptr, *bkeep = nullptr, *bsweep = nullptr;
     int32_t *bgmoved = nullptr;  // per graph of the level: moved in the current sweep
+    // continuous batching (request server): per input graph the batch level it
+    // joined at, and the canonical labels of graphs reported as they finish
+    std::vector<int32_t> bshift_h;
+    int32_t *bcanon = nullptr;
     unsigned long long *bI2 = nullptr, *bsq = nullptr;
 
     // settled nodes (see move.hip): per node the moved neighbour weight since
@@ -237,6 +242,7 @@ struct plm_ctx {
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
         dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active); dev_free(snap[0]); dev_free(snap[1]);
+        dev_free(bcanon);
         dev_free(dw); dev_free(slack); dev_free(kslack); dev_free(tstamp); dev_free(sctl);
         free_hubs();
         if (hbuf) (void)hipHostFree(hbuf);
@@ -1108,6 +1114,250 @@ struct plm_ctx {
         return (double)num / (double)den;
     }
 
+    // per graph of a batch level (input graph ids act), the level it joined at;
+    // null while every graph of the level started at level 0
+    void set_shifts(LevelData &lv, const std::vector<int64_t> &act_ids) {
+        dev_free(lv.gshift);
+        std::vector<int32_t> sh(act_ids.size());
+        bool any = false;
+        for (size_t a = 0; a < act_ids.size(); ++a) {
+            sh[a] = bshift_h[act_ids[a]];
+            any = any || sh[a] != 0;
+        }
+        if (!any) return;
+        lv.gshift = dev_alloc<int32_t>((int64_t)sh.size());
+        HIPCHK(hipMemcpyAsync(lv.gshift, sh.data(), sh.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    // The graphs that finished at this level, one by one over their own input
+    // node range: canonical labels (first occurrence) and modularity from
+    // their local labels in bout; reported through hooks->done.
+    void report_finished(BatchHooks *hooks, const std::vector<int64_t> &fin, const std::vector<int32_t> &glev) {
+        const GraphView g0 = levels[0].view();
+        if (!bcanon) bcanon = dev_alloc<int32_t>(n0);
+        std::vector<int64_t> Sg(G);
+        HIPCHK(hipMemcpyAsync(Sg.data(), gS0, G * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        unsigned long long *acc = dcnt + 26;
+        for (int64_t g : fin) {
+            const int64_t a = gbase0_h[g], n = gbase0_h[g + 1] - a;
+            if (n > 0) build_canonical(bout + a, n, bcanon + a, scr, st);
+            graph_modularity_parts(g0, a, n, bout + a, vol0, bnewid + a, acc, st);
+            HIPCHK(hipMemcpyAsync(hbuf + 40, acc, 3 * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            double q = 0.0;
+            if (Sg[g] != 0) {
+                unsigned __int128 s2 = ((unsigned __int128)(uint64_t)hbuf[42] << 64) | (uint64_t)hbuf[41];
+                __int128 num = (__int128)Sg[g] * (__int128)hbuf[40] - (__int128)s2;
+                __int128 den = (__int128)Sg[g] * (__int128)Sg[g];
+                q = (double)num / (double)den;
+            }
+            hooks->done(g, bcanon + a, n, q, glev[g]);
+        }
+    }
+
+    // reallocates a device array for new_n elements, keeping its first keep
+    template <typename T>
+    void regrow(T *&p, int64_t new_n, int64_t keep) {
+        T *q = dev_alloc<T>(new_n);
+        if (p && keep > 0) HIPCHK(hipMemcpyAsync(q, p, (size_t)keep * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        dev_free(p);
+        p = q;
+    }
+
+    // Continuous batching: graphs join the batch at the level boundary just
+    // set up (cur >= 1), each at level 0 of its own.  Its input CSR is
+    // validated and appended to the input union (levels[0]); converted to the
+    // coarse format (int64 weights, self-loops doubled) it is appended to the
+    // current level, whose per-graph level shift for it is cur, so that its
+    // priorities hash its own level and it stops after its own max_levels.
+    // codes/msgs: per offered graph 0 or the reason it was refused.
+    void batch_append(const std::vector<JoinGraph> &js, std::vector<int> &codes, std::vector<std::string> &msgs) {
+        struct Tmp {
+            int64_t n = 0, nnz = 0, S = 0;
+            int64_t *off = nullptr, *vol = nullptr;
+            int32_t *col = nullptr, *w = nullptr;
+        };
+        std::vector<Tmp> ok;
+        codes.assign(js.size(), PLM_OK);
+        msgs.assign(js.size(), std::string());
+        auto free_tmp = [&](Tmp &t) { dev_free(t.off); dev_free(t.vol); dev_free(t.col); dev_free(t.w); };
+        int64_t addS = 0, addN = 0;
+        try {
+            for (size_t i = 0; i < js.size(); ++i) {
+                const JoinGraph &j = js[i];
+                Tmp t;
+                t.n = j.n;
+                t.nnz = j.nnz;
+                t.off = dev_alloc<int64_t>(j.n + 1);
+                t.col = dev_alloc<int32_t>(j.nnz);
+                if (j.w) t.w = dev_alloc<int32_t>(j.nnz);
+                t.vol = dev_alloc<int64_t>(j.n);
+                const hipMemcpyKind kind = j.mem_kind == PLM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+                HIPCHK(hipMemcpyAsync(t.off, j.off, (size_t)(j.n + 1) * 8, kind, st));
+                if (j.nnz > 0) HIPCHK(hipMemcpyAsync(t.col, j.col, (size_t)j.nnz * 4, kind, st));
+                if (j.w && j.nnz > 0) HIPCHK(hipMemcpyAsync(t.w, j.w, (size_t)j.nnz * 4, kind, st));
+                GraphView v;
+                v.n = t.n; v.nnz = t.nnz; v.off = t.off; v.col = t.col; v.w = t.w; v.wkind = t.w ? 1 : 0;
+                v.diag_mult = 2;
+                uint32_t bad = opt.validate ? validate_graph(v, scr, hbuf, st) : 0u;
+                if (!bad) {
+                    launch_volumes(v, t.vol, dcnt + 5, dcnt + 6, st);
+                    HIPCHK(hipMemcpyAsync(hbuf, dcnt + 5, 8, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    t.S = hbuf[0];
+                }
+                if (bad) {
+                    codes[i] = PLM_E_GRAPH;
+                    msgs[i] = "invalid graph";
+                } else if ((unsigned __int128)(uint64_t)S + (uint64_t)addS + (uint64_t)t.S >= ((unsigned __int128)1 << 62)) {
+                    codes[i] = PLM_E_BUDGET;
+                    msgs[i] = "the batch's total weight would reach 2^62";
+                } else if (n0 + addN + t.n >= (1LL << 31)) {
+                    codes[i] = PLM_E_BUDGET;
+                    msgs[i] = "the batch would exceed 2^31 nodes";
+                }
+                if (codes[i] != PLM_OK) {
+                    free_tmp(t);
+                    continue;
+                }
+                addS += t.S;
+                addN += t.n;
+                ok.push_back(t);
+            }
+            if (ok.empty()) return;
+            const int64_t J = (int64_t)ok.size();
+            int64_t nA = 0, eA = 0;
+            bool weighted = levels[0].wkind == 1;
+            for (auto &t : ok) {
+                nA += t.n;
+                eA += t.nnz;
+                weighted = weighted || t.w != nullptr;
+            }
+            LevelData &b0 = levels[0];
+            const int64_t n0o = n0, e0o = b0.nnz, Go = G;
+            const int64_t n1 = n0o + nA, e1 = e0o + eA, G1 = Go + J;
+            // ---- the input union
+            regrow(b0.off, n1 + 1, n0o + 1);
+            regrow(b0.col, e1, e0o);
+            if (weighted) {
+                if (b0.wkind == 1) {
+                    int32_t *w0 = (int32_t *)b0.w;
+                    regrow(w0, e1, e0o);
+                    b0.w = w0;
+                } else {
+                    int32_t *w0 = dev_alloc<int32_t>(e1);
+                    launch_fill_i32(w0, e0o, 1, st);
+                    b0.w = w0;
+                    b0.wkind = 1;
+                }
+            }
+            int64_t nb = n0o, eb = e0o;
+            for (auto &t : ok) {
+                launch_append_off(b0.off + nb, t.off, t.n, eb, st);
+                launch_append_input(b0.col + eb, weighted ? (int32_t *)b0.w + eb : nullptr, t.col, t.w, t.nnz, nb, st);
+                gbase0_h.push_back(nb + t.n);
+                nb += t.n;
+                eb += t.nnz;
+            }
+            b0.n = n1;
+            b0.nnz = e1;
+            regrow(b0.gbase, G1 + 1, 0);
+            HIPCHK(hipMemcpyAsync(b0.gbase, gbase0_h.data(), (G1 + 1) * 8, hipMemcpyHostToDevice, st));
+            regrow(b0.gid, n1, 0);
+            launch_fill_gid(b0.gbase, G1, n1, b0.gid, st);
+            // ---- per input node and per input graph
+            regrow(vol0, n1, n0o);
+            regrow(lab, n1, n0o);
+            regrow(bout, n1, n0o);
+            launch_fill_i32(bout + n0o, nA, 0, st);
+            nb = n0o;
+            for (auto &t : ok) {
+                if (t.n > 0) HIPCHK(hipMemcpyAsync(vol0 + nb, t.vol, t.n * 8, hipMemcpyDeviceToDevice, st));
+                nb += t.n;
+            }
+            regrow(gS0, G1, Go);
+            regrow(gwl0, G1, Go);
+            {
+                std::vector<int64_t> s(J), wl(J);
+                for (int64_t k = 0; k < J; ++k) {
+                    s[k] = ok[k].S;
+                    unsigned __int128 sg = (unsigned __int128)(uint64_t)s[k] * (unsigned __int128)(uint64_t)gmax();
+                    wl[k] = sg == 0 ? INT64_MAX : ((sg >> 62) ? 0 : (int64_t)(((1ULL << 62) - 1) / (uint64_t)sg));
+                }
+                HIPCHK(hipMemcpyAsync(gS0 + Go, s.data(), J * 8, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(gwl0 + Go, wl.data(), J * 8, hipMemcpyHostToDevice, st));
+            }
+            regrow(vol, n1, 0);
+            regrow(volC, n1, 0);
+            regrow(zeta, n1, 0);
+            regrow(colour, n1, 0);
+            regrow(class_nodes, n1, 0);
+            regrow(move_to, n1, 0);
+            regrow(bflag, n1, 0);
+            regrow(bnewid, n1 + 1, 0);
+            dev_free(bscan);
+            bscan = dev_alloc<uint8_t>((int64_t)scan_scratch_bytes(n1 > 0 ? n1 : 1));
+            dev_free(bcanon);
+            regrow(act, G1, 0);
+            regrow(gS, G1, 0);
+            regrow(gwl, G1, 0);
+            regrow(bstatus, G1, 0);
+            regrow(bkeep, G1, 0);
+            regrow(bsweep, G1, 0);
+            regrow(bI2, G1, 0);
+            regrow(bsq, 2 * G1, 0);
+            regrow(bgmoved, G1, 0);
+            regrow(bgath, 2 * (G1 + 1), 0);
+            // ---- the current level
+            LevelData &l = L();
+            const int64_t nc = l.n, ec = l.nnz, A = (int64_t)act_h.size();
+            std::vector<int64_t> lb(A + 1);
+            HIPCHK(hipMemcpyAsync(lb.data(), l.gbase, (A + 1) * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            regrow(l.off, nc + nA + 1, nc + 1);
+            regrow(l.col, ec + eA, ec);
+            int64_t *lw = (int64_t *)l.w;
+            regrow(lw, ec + eA, ec);
+            l.w = lw;
+            // nodes of the new graphs at this level: right after the level's own
+            nb = nc;
+            eb = ec;
+            int64_t ib = n0o;
+            for (int64_t k = 0; k < J; ++k) {
+                Tmp &t = ok[k];
+                launch_append_off(l.off + nb, t.off, t.n, eb, st);
+                launch_append_coarse(l.col + eb, lw + eb, t.off, t.n, t.col, t.w, t.nnz, nb, st);
+                launch_iota_from(lab + ib, t.n, nb, st);  // input node -> its node at this level
+                nb += t.n;
+                eb += t.nnz;
+                ib += t.n;
+                lb.push_back(nb);
+                act_h.push_back(Go + k);
+                bshift_h.push_back(cur);
+            }
+            l.n = nc + nA;
+            l.nnz = ec + eA;
+            regrow(l.gbase, A + J + 1, 0);
+            HIPCHK(hipMemcpyAsync(l.gbase, lb.data(), (A + J + 1) * 8, hipMemcpyHostToDevice, st));
+            regrow(l.gid, l.n, 0);
+            launch_fill_gid(l.gbase, A + J, l.n, l.gid, st);
+            HIPCHK(hipMemcpyAsync(act, act_h.data(), (A + J) * 8, hipMemcpyHostToDevice, st));
+            set_shifts(l, act_h);
+            n0 = n1;
+            G = G1;
+            S += addS;
+            for (auto &t : ok) free_tmp(t);
+            ok.clear();
+            init_level();  // volumes, graph weights, singletons of the grown level
+        } catch (...) {
+            for (auto &t : ok) free_tmp(t);
+            throw;
+        }
+    }
+
     // Algorithm 3 on every graph of a batch at once.  All graphs still active
     // are at the same level; a graph whose communities stop merging (or that
     // reached max_levels) gets its labels at that level and leaves the next.
@@ -1115,9 +1365,15 @@ struct plm_ctx {
     // coarse ids are all local to each graph, and once a graph's sweep makes
     // no move, further sweeps of the batch leave it unchanged.
     // canon_out (device, n0): labels canonical within each graph.
-    void run_batch(int32_t *canon_out, double *q_out, int32_t *levels_out) {
+    // With hooks (request server): at every level boundary graphs may join,
+    // each starting at level 0 of its own (batch_append), and every graph is
+    // reported through hooks->done at the level it finishes; canon_out, q_out
+    // and levels_out are then unused.
+    void run_batch(int32_t *canon_out, double *q_out, int32_t *levels_out, BatchHooks *hooks = nullptr) {
         reset();
+        bshift_h.assign(G, 0);
         int64_t n0v = n0;
+        if (hooks && n0v > 0) launch_fill_i32(bout, n0v, 0, st);  // keys of unfinished graphs stay in range
         std::vector<uint8_t> status(G, 0), keep;
         std::vector<int64_t> gath, nbase, nact;
         std::vector<int32_t> glev(G, 0);
@@ -1173,15 +1429,17 @@ struct plm_ctx {
             std::vector<int64_t> abase(A + 1);
             HIPCHK(hipMemcpyAsync(abase.data(), l.gbase, (A + 1) * 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            bool last = opt.max_levels > 0 && depth >= opt.max_levels;
             keep.assign(A, 0);
             nbase.assign(1, 0);
             nact.clear();
+            std::vector<int64_t> finished;
             for (int64_t a = 0; a < A; ++a) {
                 int64_t ka = nid[a + 1] - nid[a], na = abase[a + 1] - abase[a];
                 int64_t g = act_h[a];
-                glev[g] = depth;
+                glev[g] = depth - bshift_h[g];  // levels of g's own run so far
+                const bool last = opt.max_levels > 0 && glev[g] >= opt.max_levels;
                 if (ka == na || last) {
+                    finished.push_back(g);
                     status[g] = 1;
                 } else {
                     status[g] = 0;
@@ -1202,6 +1460,7 @@ struct plm_ctx {
             }
             launch_batch_step(n0v, levels[0].gid, bstatus, l.gid, l.gbase, zeta, l.pi, lab, bout, st);
             HIPCHK(hipStreamSynchronize(st));
+            if (hooks && !finished.empty()) report_finished(hooks, finished, glev);
             for (int64_t a = 0; a < A; ++a)
                 if (!keep[a]) status[act_h[a]] = 2;
             if (A2 == 0) break;
@@ -1216,6 +1475,7 @@ struct plm_ctx {
                 nl.gid = dev_alloc<int32_t>(k);
                 HIPCHK(hipMemcpyAsync(nl.gbase, nbase.data(), (A2 + 1) * 8, hipMemcpyHostToDevice, st));
                 launch_fill_gid(nl.gbase, A2, k, nl.gid, st);
+                set_shifts(nl, nact);
                 act_h = nact;
                 HIPCHK(hipMemcpyAsync(act, act_h.data(), A2 * 8, hipMemcpyHostToDevice, st));
                 HIPCHK(hipStreamSynchronize(st));
@@ -1231,7 +1491,20 @@ struct plm_ctx {
             int prev = cur++;
             init_level();
             if (prev < PLM_MAX_LEVELS) stats.coarsen_ms[prev] = now_ms() - t3;
+            if (hooks && depth <= opt.join) {  // joins at the first opt.join level boundaries
+                std::vector<JoinGraph> js = hooks->join();
+                if (!js.empty()) {
+                    std::vector<int> codes;
+                    std::vector<std::string> msgs;
+                    batch_append(js, codes, msgs);
+                    status.resize(G, 0);
+                    glev.resize(G, 0);
+                    n0v = n0;
+                    hooks->joined(codes, msgs);
+                }
+            }
         }
+        if (hooks) return;
         // labels canonical within each graph; per-graph modularity on the input
         const GraphView g0 = levels[0].view();
         if (n0v > 0) batch_canonical(n0v, g0.gid, g0.gbase, bout, bflag, move_to, canon_out, scr, st);
@@ -1283,6 +1556,7 @@ int check_options(const plm_options &o, std::string &msg) {
     }
     if (o.agg_tile < 0 || o.agg_tile > 512) { msg = "agg_tile must be 0 or lie in [1, 512]"; return PLM_E_ARG; }
     if (o.settle < -1 || o.settle > 1) { msg = "settle must be -1, 0 or 1"; return PLM_E_ARG; }
+    if (o.join < 0) { msg = "join must be >= 0"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
@@ -1612,6 +1886,15 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
 }
 
 }  // namespace
+
+// Batched run with hooks: graphs join at level boundaries and are reported as
+// they finish (continuous batching of the request server in serve.hip).
+plm_status plm_internal_batch_serve(plm_ctx *ctx, plm::BatchHooks *hooks) {
+    return guarded(ctx, [&] {
+        if (!ctx->batch || !hooks) throw Error{PLM_E_STATE, "internal: serving needs a batched context and hooks"};
+        ctx->run_batch(nullptr, nullptr, nullptr, hooks);
+    });
+}
 
 // Batched context over a disjoint-union CSR already in device memory (hipMalloc
 // buffers the context adopts; used by the request server in serve.hip).

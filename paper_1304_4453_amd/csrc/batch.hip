@@ -225,6 +225,158 @@ void batch_modularity_parts(const GraphView &g0, const int32_t *gid0, const int3
     HIPCHK(hipGetLastError());
 }
 
+// ------------------------------------------------------------------ one graph of a union
+// Modularity parts of graph g of the input union (nodes [a, a + n), entries
+// [ea, eb), columns global ids) for local labels lab[0..n): I2 and the
+// 128-bit sum of the label volumes squared (volL: n words of scratch).
+template <int WK>
+__global__ __launch_bounds__(kBT) void k_range_intra(const int64_t *off, const int32_t *col, const void *w,
+                                                     int diag_mult, int64_t a, int64_t n, int64_t ea, int64_t eb,
+                                                     const int32_t *lab, unsigned long long *I2) {
+    // kC consecutive entries per thread: one row search, then row by row
+    constexpr int kC = 16;
+    const int64_t e0 = ea + ((int64_t)blockIdx.x * kBT + threadIdx.x) * kC;
+    int64_t s = 0;
+    if (e0 < eb) {
+        const int64_t *loff = off + a;  // local rows: loff[r] <= e < loff[r + 1]
+        const int64_t e1 = e0 + kC < eb ? e0 + kC : eb;
+        int64_t r = row_of(loff, n, e0);
+        int64_t rend = loff[r + 1];
+        int32_t lr = lab[r];
+        for (int64_t e = e0; e < e1; ++e) {
+            while (e >= rend) {
+                r = next_row(loff, n, r, e);
+                rend = loff[r + 1];
+                lr = lab[r];
+            }
+            const int64_t v = (int64_t)col[e] - a;
+            if (lab[v] == lr) {
+                int64_t x = wload<WK>(w, e);
+                if (v == r) x *= diag_mult;
+                s += x;
+            }
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane_id() == 0 && s) atomicAdd(I2, (unsigned long long)s);
+}
+__global__ void k_range_vol(int64_t n, const int32_t *lab, const int64_t *vol, int64_t *volL) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t x = v < n ? vol[v] : 0;
+    int32_t l = x ? lab[v] : 0;
+    if (wave_group_sum(l, x != 0, x)) atomicAdd((unsigned long long *)&volL[l], (unsigned long long)x);
+}
+__global__ __launch_bounds__(kBT) void k_range_sq(const int64_t *volL, int64_t n, unsigned long long *acc2) {
+    unsigned __int128 s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBT) {
+        unsigned __int128 x = (unsigned __int128)(uint64_t)volL[i];
+        s += x * x;
+    }
+    uint64_t lo = (uint64_t)s, hi = (uint64_t)(s >> 64);
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t olo = __shfl_xor(lo, d), ohi = __shfl_xor(hi, d);
+        uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1 : 0);
+        lo = nlo;
+    }
+    if (lane_id() == 0 && (lo || hi)) {
+        unsigned long long old = atomicAdd(&acc2[0], (unsigned long long)lo);
+        uint64_t carry = (old + lo < old) ? 1 : 0;
+        if (hi + carry) atomicAdd(&acc2[1], (unsigned long long)(hi + carry));
+    }
+}
+__global__ void k_zero_words(unsigned long long *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+void graph_modularity_parts(const GraphView &g0, int64_t a, int64_t n, const int32_t *lab, const int64_t *vol0,
+                            int64_t *volL, unsigned long long *acc3, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, acc3, (int64_t)3);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, (unsigned long long *)volL, n);
+    int64_t ea = 0, eb = 0;
+    HIPCHK(hipMemcpyAsync(&ea, g0.off + a, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&eb, g0.off + a + n, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (eb > ea) {
+        dim3 eg((unsigned)cdiv(cdiv(eb - ea, 16), kBT));
+        switch (g0.wkind) {
+            case 0: hipLaunchKernelGGL(k_range_intra<0>, eg, dim3(kBT), 0, st, g0.off, g0.col, g0.w, g0.diag_mult, a, n, ea, eb, lab, acc3); break;
+            case 1: hipLaunchKernelGGL(k_range_intra<1>, eg, dim3(kBT), 0, st, g0.off, g0.col, g0.w, g0.diag_mult, a, n, ea, eb, lab, acc3); break;
+            default: hipLaunchKernelGGL(k_range_intra<2>, eg, dim3(kBT), 0, st, g0.off, g0.col, g0.w, g0.diag_mult, a, n, ea, eb, lab, acc3); break;
+        }
+    }
+    hipLaunchKernelGGL(k_range_vol, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, n, lab, vol0 + a, volL);
+    const int64_t nb = cdiv(n, kBT);
+    hipLaunchKernelGGL(k_range_sq, dim3((unsigned)(nb < 1024 ? nb : 1024)), dim3(kBT), 0, st, volL, n, acc3 + 1);
+    HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ joins
+// Appending a graph (input CSR with local ids) to a union: offsets shifted by
+// the union's entries before it, columns by its nodes before it.
+__global__ void k_append_off(int64_t *dst, const int64_t *off, int64_t n, int64_t ebase) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) dst[i] = ebase + off[i];
+}
+// input level: columns shifted, weights copied (unit weights written out when
+// the graph has none and the union has a weight array)
+__global__ void k_append_input(int32_t *col, int32_t *w, const int32_t *jcol, const int32_t *jw, int64_t nnz,
+                               int32_t nbase) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    col[e] = jcol[e] + nbase;
+    if (w) w[e] = jw ? jw[e] : 1;
+}
+// coarse-level format: int64 weights with the self-loop doubled
+__global__ void k_append_coarse(int32_t *col, int64_t *w, const int64_t *joff, int64_t n, const int32_t *jcol,
+                                const int32_t *jw, int64_t nnz, int32_t nbase) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const int64_t r = row_of(joff, n, e);
+    const int32_t v = jcol[e];
+    col[e] = v + nbase;
+    w[e] = (int64_t)(jw ? jw[e] : 1) * (v == r ? 2 : 1);
+}
+__global__ void k_iota_from(int32_t *a, int64_t n, int64_t first) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = (int32_t)(first + i);
+}
+__global__ void k_fill_i32v(int32_t *a, int64_t n, int32_t x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = x;
+}
+
+void launch_append_off(int64_t *dst, const int64_t *off, int64_t n, int64_t ebase, hipStream_t st) {
+    hipLaunchKernelGGL(k_append_off, dim3((unsigned)cdiv(n + 1, kBT)), dim3(kBT), 0, st, dst, off, n, ebase);
+    HIPCHK(hipGetLastError());
+}
+void launch_append_input(int32_t *col, int32_t *w, const int32_t *jcol, const int32_t *jw, int64_t nnz, int64_t nbase,
+                         hipStream_t st) {
+    if (nnz <= 0) return;
+    hipLaunchKernelGGL(k_append_input, dim3((unsigned)cdiv(nnz, kBT)), dim3(kBT), 0, st, col, w, jcol, jw, nnz,
+                       (int32_t)nbase);
+    HIPCHK(hipGetLastError());
+}
+void launch_append_coarse(int32_t *col, int64_t *w, const int64_t *joff, int64_t n, const int32_t *jcol,
+                          const int32_t *jw, int64_t nnz, int64_t nbase, hipStream_t st) {
+    if (nnz <= 0) return;
+    hipLaunchKernelGGL(k_append_coarse, dim3((unsigned)cdiv(nnz, kBT)), dim3(kBT), 0, st, col, w, joff, n, jcol, jw,
+                       nnz, (int32_t)nbase);
+    HIPCHK(hipGetLastError());
+}
+void launch_iota_from(int32_t *a, int64_t n, int64_t first, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota_from, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, a, n, first);
+    HIPCHK(hipGetLastError());
+}
+void launch_fill_i32(int32_t *a, int64_t n, int32_t x, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32v, dim3((unsigned)cdiv(n, kBT)), dim3(kBT), 0, st, a, n, x);
+    HIPCHK(hipGetLastError());
+}
+
 // batched validation: every column lies in its row's graph
 __global__ void k_batch_validate(const int64_t *off, const int32_t *col, int64_t n, const int32_t *gid0,
                                  const int64_t *gbase0, uint32_t *bad) {

@@ -102,8 +102,9 @@ __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, 
             r = row_of(g.off, g.n, e);
         }
         const int64_t br = node_base(g, r);
+        const int32_t lr = node_level(g, level, r);
         const int64_t x = v[q];
-        if (x == r || !prio_greater(prio_hash(seed, level, x - br), x, prio_hash(seed, level, r - br), r)) continue;
+        if (x == r || !prio_greater(prio_hash(seed, lr, x - br), x, prio_hash(seed, lr, r - br), r)) continue;
         if (staged) atomicAdd(&acc[lo], 1);
         else atomicAdd(&pending[r], 1);
     }
@@ -201,6 +202,7 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
                                                     int32_t base0) {
     int64_t e0 = g.off[u], e1 = g.off[u + 1];
     const int64_t bu = node_base(g, u);
+    const int32_t lu = node_level(g, level, u);
     for (int32_t base = base0;; base += kWin) {
         for (int j = lane_id(); j < kWinWords; j += kWave) bm[j] = 0;
         wave_sync();
@@ -212,7 +214,7 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
             for (int j = 0; j < 4; ++j) v[j] = e + j * kWave < e1 ? g.col[e + j * kWave] : u;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                c[j] = (v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u)) ? colour[v[j]] : -1;
+                c[j] = (v[j] != u && prio_greater(prio_hash(seed, lu, v[j] - bu), v[j], hu, u)) ? colour[v[j]] : -1;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 int32_t x = c[j] - base;
@@ -245,7 +247,8 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     for (int64_t i = gtid >> 3; i < ns; i += gthreads >> 3) {
         int32_t u = Q.q[set][0][i];
         const int64_t bu = node_base(g, u);
-        uint64_t hu = prio_hash(seed, level, u - bu);
+        const int32_t lu = node_level(g, level, u);
+        uint64_t hu = prio_hash(seed, lu, u - bu);
         int64_t e0 = g.off[u], e1 = g.off[u + 1];
         int32_t v[4];
         bool hi[4];
@@ -255,7 +258,7 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
             v[j] = e < e1 ? g.col[e] : u;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) hi[j] = v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u);
+        for (int j = 0; j < 4; ++j) hi[j] = v[j] != u && prio_greater(prio_hash(seed, lu, v[j] - bu), v[j], hu, u);
         int32_t c[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) c[j] = hi[j] ? colour[v[j]] : 64;
@@ -279,7 +282,8 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     for (int64_t i = bid * (NT / kWave) + w; i < nm; i += nblk * (NT / kWave)) {
         int32_t u = Q.q[set][1][i];
         const int64_t bu = node_base(g, u);
-        uint64_t hu = prio_hash(seed, level, u - bu);
+        const int32_t lu = node_level(g, level, u);
+        uint64_t hu = prio_hash(seed, lu, u - bu);
         const int64_t e0 = g.off[u], e1 = g.off[u + 1];
         constexpr int kPer = (int)(kWaveRow / kWave);
         int32_t v[kPer], c[kPer];
@@ -291,7 +295,7 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
-            if (v[j] != u && prio_greater(prio_hash(seed, level, v[j] - bu), v[j], hu, u)) hi |= 1u << j;
+            if (v[j] != u && prio_greater(prio_hash(seed, lu, v[j] - bu), v[j], hu, u)) hi |= 1u << j;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) c[j] = (hi >> j) & 1u ? colour[v[j]] : -1;
         int32_t f = -1;
@@ -327,7 +331,8 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
         const int64_t k = item & 0xffffffffLL;
         int32_t u = Q.q[set][2][j];
         const int64_t bu = node_base(g, u);
-        uint64_t hu = prio_hash(seed, level, u - bu);
+        const int32_t lu = node_level(g, level, u);
+        uint64_t hu = prio_hash(seed, lu, u - bu);
         const int64_t c0 = g.off[u] + k * kHubChunk, e1 = g.off[u + 1];
         const int64_t c1 = c0 + kHubChunk < e1 ? c0 + kHubChunk : e1;
         for (int i = threadIdx.x; i < kWinWords; i += NT) bbm[i] = 0;
@@ -342,7 +347,7 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
-            hi[q] = v[q] != u && prio_greater(prio_hash(seed, level, v[q] - bu), v[q], hu, u);
+            hi[q] = v[q] != u && prio_greater(prio_hash(seed, lu, v[q] - bu), v[q], hu, u);
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             c[q] = hi[q] ? colour[v[q]] : kWin;

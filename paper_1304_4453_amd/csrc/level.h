@@ -210,5 +210,21 @@ void batch_modularity_parts(const GraphView &g0, const int32_t *gid0, const int3
                             int64_t G, int64_t *volL, unsigned long long *I2, unsigned long long *sq, hipStream_t st);
 uint32_t batch_validate(const GraphView &g, const int32_t *gid0, const int64_t *gbase0, Scratch &scr,
                         int64_t *host_i64, hipStream_t st);
+// joins (batch.hip): offsets dst[0..n] = ebase + off[0..n]; input-level
+// entries (columns + nbase, weights or unit weights when w is not null);
+// coarse-level entries (columns + nbase, int64 weights with the self-loop
+// doubled); a[i] = first + i; a[i] = x
+void launch_append_off(int64_t *dst, const int64_t *off, int64_t n, int64_t ebase, hipStream_t st);
+void launch_append_input(int32_t *col, int32_t *w, const int32_t *jcol, const int32_t *jw, int64_t nnz, int64_t nbase,
+                         hipStream_t st);
+void launch_append_coarse(int32_t *col, int64_t *w, const int64_t *joff, int64_t n, const int32_t *jcol,
+                          const int32_t *jw, int64_t nnz, int64_t nbase, hipStream_t st);
+void launch_iota_from(int32_t *a, int64_t n, int64_t first, hipStream_t st);
+void launch_fill_i32(int32_t *a, int64_t n, int32_t x, hipStream_t st);
+// modularity parts of the graph on nodes [a, a + n) of a union (global column
+// ids) for local labels lab[0..n): acc3 = [I2, sum vol(C)^2 lo, hi]; volL: n
+// words of scratch
+void graph_modularity_parts(const GraphView &g0, int64_t a, int64_t n, const int32_t *lab, const int64_t *vol0,
+                            int64_t *volL, unsigned long long *acc3, hipStream_t st);
 
 }  // namespace plm

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
+#include <vector>
 
 namespace plm {
 
@@ -130,10 +132,40 @@ struct GraphView {
     // first node of each graph; null for a single graph
     const int32_t *gid = nullptr;
     const int64_t *gbase = nullptr;
+    // batched runs in which graphs joined later: per graph of the level, the
+    // level of the batch at which it joined (null when every graph started
+    // together), so that its own level is the batch's minus that
+    const int32_t *gshift = nullptr;
+};
+
+// A graph joining a running batch (request server): an input CSR as
+// plm_create takes it, in host or device memory (mem_kind).
+struct JoinGraph {
+    int64_t n = 0, nnz = 0;
+    const int64_t *off = nullptr;
+    const int32_t *col = nullptr;
+    const int32_t *w = nullptr;
+    int mem_kind = 0;
+};
+// Callbacks of a batched run that takes graphs in at its level boundaries and
+// reports each graph as soon as it finishes (continuous batching).
+struct BatchHooks {
+    // at a level boundary: graphs to add (may be none)
+    std::function<std::vector<JoinGraph>()> join;
+    // then, per offered graph in order: 0 (added as the next graph index) or an
+    // error status with its message
+    std::function<void(const std::vector<int> &codes, const std::vector<std::string> &msgs)> joined;
+    // graph g finished: its canonical labels (device, n int32, valid during the
+    // call, on the run's stream), Q and level count
+    std::function<void(int64_t g, const int32_t *labels, int64_t n, double q, int32_t levels)> done;
 };
 
 // first node of u's graph (priorities hash the id local to the graph)
 __device__ __forceinline__ int64_t node_base(const GraphView &g, int64_t u) { return g.gid ? g.gbase[g.gid[u]] : 0; }
+// level of u's own graph when the batch is at `level` (priorities hash it)
+__device__ __forceinline__ int32_t node_level(const GraphView &g, int32_t level, int64_t u) {
+    return g.gshift ? level - g.gshift[g.gid[u]] : level;
+}
 
 // ------------------------------------------------------------------ error type
 struct Error {

@@ -14,6 +14,12 @@
 // step hands the admitted batch to a free worker and returns, so requests that
 // arrive while batches run are admitted as soon as a worker and budget are
 // free, and the batches' kernels share the device.
+//
+// With opt.join (continuous batching) batches always run on workers, and a
+// running batch takes queued requests in at each of its level boundaries, as
+// far as the budget and the entry cap allow: each joins at level 0 of its own
+// run inside the batch's union (run_batch with hooks in api.hip), and every
+// request completes as soon as its own run ends.
 #include <hip/hip_runtime.h>
 
 #include <condition_variable>
@@ -30,17 +36,18 @@
 
 plm_status plm_internal_batch_adopt(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t nnz, int64_t *off,
                                     int32_t *col, int32_t *w, void *hip_stream, const plm_options *opt);
+plm_status plm_internal_batch_serve(plm_ctx *ctx, plm::BatchHooks *hooks);
 
 namespace {
 
 using plm::cdiv;
 using plm::Error;
 
-// Resident bytes of one graph while it runs: the CSR, per-node state of the
-// level engine and the batch bookkeeping, and the sort buffers of contraction.
-int64_t footprint(int64_t n, int64_t nnz, bool weighted) {
-    return 8 * (n + 1) + (weighted ? 8 : 4) * nnz + 128 * n + 64 * nnz;
-}
+// Resident bytes of one graph while it runs: the CSR (with a weight array:
+// the union of a batch carries one, unit weights written out, as soon as any
+// of its graphs is weighted), per-node state of the level engine and the
+// batch bookkeeping, and the sort buffers of contraction.
+int64_t footprint(int64_t n, int64_t nnz) { return 8 * (n + 1) + 8 * nnz + 128 * n + 64 * nnz; }
 
 // union fix-up of one request: rows shift by the entries before it, columns
 // by the nodes before it; unit weights are written out when the union carries
@@ -80,9 +87,10 @@ struct plm_server {
     struct Job {
         std::vector<int64_t> ids;
         std::vector<Req> in;
-        int64_t bytes = 0;
+        int64_t bytes = 0, entries = 0;
     };
     hipStream_t st = nullptr;
+    bool own_st = false;          // st created here (none given): results never touch the legacy stream
     hipStream_t io_st = nullptr;  // reads of device requests at submission (created on first use)
     plm_options opt;
     int64_t budget = 0, max_entries = 0;
@@ -94,7 +102,7 @@ struct plm_server {
     std::deque<int64_t> queue;
     std::unordered_map<int64_t, Req> reqs;
     std::deque<Job> jobs;  // admitted, waiting for a worker
-    int64_t next_id = 0, completed = 0, batches = 0, resident = 0, inflight = 0, unreported = 0;
+    int64_t next_id = 0, completed = 0, batches = 0, resident = 0, inflight = 0, unreported = 0, joined = 0;
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> wstreams;
@@ -108,6 +116,7 @@ struct plm_server {
         for (auto &t : workers) t.join();
         for (auto s : wstreams) (void)hipStreamDestroy(s);
         if (io_st) (void)hipStreamDestroy(io_st);
+        if (own_st && st) (void)hipStreamDestroy(st);
         for (auto &kv : reqs)
             if (kv.second.labels) (void)hipFree(kv.second.labels);
     }
@@ -135,6 +144,7 @@ struct plm_server {
             job.in.push_back(r);
         }
         job.bytes = bytes;
+        job.entries = entries;
         resident += bytes;
         ++inflight;
         return true;
@@ -147,16 +157,35 @@ struct plm_server {
         cv_idle.notify_all();
     }
 
-    // every request of the job fails with (code, m) (mu held)
+    // every request of the job still running fails with (code, m) (mu held)
     void fail_job(const Job &job, plm_status code, const std::string &m) {
         for (int64_t id : job.ids) {
             Req &r = reqs[id];
+            if (r.state != 3) continue;  // completed already (continuous batching)
             r.state = 2;
             r.err = code;
             r.msg = m;
+            ++unreported;
         }
-        unreported += (int64_t)job.ids.size();
         retire(job);
+    }
+
+    // Continuous batching (mu held): the queue prefix that fits beside what
+    // runs, joining job at a level boundary; those requests are marked
+    // running and charged to the job.
+    std::vector<int64_t> admit_joiners(Job &job) {
+        std::vector<int64_t> ids;
+        while (!queue.empty() && !stop) {
+            Req &r = reqs[queue.front()];
+            if (r.solo || resident + r.bytes > budget || job.entries + r.nnz > max_entries) break;
+            ids.push_back(queue.front());
+            queue.pop_front();
+            r.state = 3;
+            resident += r.bytes;
+            job.bytes += r.bytes;
+            job.entries += r.nnz;
+        }
+        return ids;
     }
 
     // Runs one admitted batch on stream s (mu not held).
@@ -233,6 +262,10 @@ struct plm_server {
             plm_destroy(ctx);
             return fail_all(PLM_E_NOMEM, "device allocation of the labels failed");
         }
+        if (opt.join) {
+            (void)hipFree(canon);
+            return serve_joining(job, ctx, s);
+        }
         std::vector<double> q(G);
         std::vector<int32_t> lv(G);
         rc = plm_batch_run(ctx, canon, q.data(), lv.data());
@@ -276,6 +309,92 @@ struct plm_server {
         retire(job);
     }
 
+    // Continuous batching: runs the batch of ctx (its first job.ids.size()
+    // graphs) with hooks that take queued requests in at level boundaries and
+    // complete every request when its run ends (mu not held).
+    void serve_joining(Job &job, plm_ctx *ctx, hipStream_t s) {
+        std::vector<int64_t> offered;
+        plm::BatchHooks hooks;
+        hooks.join = [&]() {
+            std::vector<plm::JoinGraph> js;
+            std::lock_guard<std::mutex> lk(mu);
+            offered = admit_joiners(job);
+            for (int64_t id : offered) {
+                const Req &r = reqs[id];
+                plm::JoinGraph j;
+                j.n = r.n;
+                j.nnz = r.nnz;
+                j.off = r.off;
+                j.col = r.col;
+                j.w = r.w;
+                j.mem_kind = r.mem_kind;
+                js.push_back(j);
+            }
+            return js;
+        };
+        hooks.joined = [&](const std::vector<int> &codes, const std::vector<std::string> &msgs) {
+            std::lock_guard<std::mutex> lk(mu);
+            for (size_t i = 0; i < offered.size(); ++i) {
+                Req &r = reqs[offered[i]];
+                if (codes[i] == PLM_OK) {
+                    job.ids.push_back(offered[i]);
+                    job.in.push_back(r);
+                    ++joined;
+                    continue;
+                }
+                r.state = 2;
+                r.err = codes[i];
+                r.msg = msgs[i];
+                ++unreported;
+                resident -= r.bytes;
+                job.bytes -= r.bytes;
+                job.entries -= r.nnz;
+            }
+            offered.clear();
+        };
+        hooks.done = [&](int64_t g, const int32_t *labels, int64_t n, double q, int32_t levels) {
+            int32_t *buf = nullptr;
+            bool ok = hipMalloc(&buf, (size_t)(n > 0 ? n : 1) * 4) == hipSuccess &&
+                      (n == 0 || hipMemcpyAsync(buf, labels, (size_t)n * 4, hipMemcpyDeviceToDevice, s) == hipSuccess) &&
+                      hipStreamSynchronize(s) == hipSuccess;
+            if (!ok) {
+                (void)hipGetLastError();
+                if (buf) (void)hipFree(buf);
+                buf = nullptr;
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            Req &r = reqs[job.ids[g]];
+            if (!buf) {
+                r.state = 2;
+                r.err = PLM_E_NOMEM;
+                r.msg = "device allocation or copy of the result failed";
+            } else {
+                r.state = 1;
+                r.labels = buf;
+                r.q = q;
+                r.levels = levels;
+                ++completed;
+            }
+            ++unreported;
+        };
+        plm_status rc = plm_internal_batch_serve(ctx, &hooks);
+        std::string m = rc != PLM_OK ? std::string(plm_last_error(ctx)) : std::string();
+        plm_destroy(ctx);
+        std::lock_guard<std::mutex> lk(mu);
+        if (!offered.empty()) {  // taken from the queue but never handed over
+            for (int64_t id : offered) {
+                job.ids.push_back(id);
+                job.in.push_back(reqs[id]);
+            }
+        }
+        if (rc != PLM_OK) {
+            fail_job(job, rc, m);
+            return;
+        }
+        ++batches;
+        fail_job(job, PLM_E_STATE, "internal: request not reported by its batch");  // none expected; retires
+    }
+
     // run_job, with anything thrown outside its own error paths (host
     // allocation) failing the batch instead of escaping
     void run_job_safe(Job &job, hipStream_t s) {
@@ -315,7 +434,7 @@ struct plm_server {
 
     // One step; *reported = requests completed or failed since the last report.
     void step(int32_t *reported) {
-        if (max_inflight == 1) {
+        if (max_inflight == 1 && !opt.join) {
             Job job;
             bool got;
             {
@@ -374,18 +493,31 @@ plm_status plm_server_create(plm_server **out, int64_t hbm_budget_bytes, int64_t
     plm_options o;
     plm_default_options(&o);
     if (opt) o = *opt;
-    if (o.schedule != PLM_SCHEDULE_COLOUR || o.int_mode == PLM_INT_64 || o.refine) return PLM_E_ARG;
+    if (o.schedule != PLM_SCHEDULE_COLOUR || o.int_mode == PLM_INT_64 || o.refine || o.join < 0) return PLM_E_ARG;
     plm_server *s = new (std::nothrow) plm_server();
     if (!s) return PLM_E_NOMEM;
     s->st = (hipStream_t)hip_stream;
+    if (!s->st && (max_inflight > 1 || o.join)) {
+        // the result copies of the client thread go to a stream of the server's
+        // own, so that they never wait on the legacy stream while a worker
+        // captures a sweep
+        if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return PLM_E_DEVICE;
+        }
+        s->own_st = true;
+    }
     s->opt = o;
     s->budget = hbm_budget_bytes;
     s->max_entries = max_batch_entries;
     s->max_inflight = max_inflight;
-    // a stream capture in a worker would make the client thread's synchronous
-    // copies on the legacy stream fail: concurrent batches launch one by one
+    // with several workers, batches launch one by one (a capture in one worker
+    // made other threads' synchronous copies on the legacy stream fail); a
+    // single worker (continuous batching) replays its captured sweeps, and the
+    // client's result copies then go to the server's own stream
     if (max_inflight > 1) s->opt.graph_sweeps = 0;
-    if (max_inflight > 1) {
+    if (max_inflight > 1 || o.join) {
         try {
             s->start_workers();
         } catch (...) {
@@ -422,7 +554,7 @@ plm_status plm_server_submit(plm_server *s, int64_t n, int64_t nnz, const int64_
         r.col = cols;
         r.w = weights;
         r.mem_kind = mem_kind;
-        r.bytes = footprint(n, nnz, weights != nullptr);
+        r.bytes = footprint(n, nnz);
         if (r.bytes > s->budget) throw Error{PLM_E_BUDGET, "the request alone exceeds the HBM budget"};
         std::lock_guard<std::mutex> lk(s->mu);
         int64_t id = s->next_id++;
@@ -490,6 +622,7 @@ plm_status plm_server_info(plm_server *s, plm_server_info_t *out) {
         out->inflight = s->inflight;
         out->running = running;
         out->resident_bytes = s->resident;
+        out->joined = s->joined;
     });
 }
 

@@ -3,7 +3,9 @@ the oracle's run on its graph (labels, Q bit for bit, levels), whatever it was
 batched with and whatever ran beside it; admission keeps submission order under
 the HBM budget and the per-batch entry cap; an invalid graph fails alone; with
 several batches in flight, requests that arrive while a batch runs start beside
-it, within the budget."""
+it, within the budget; with continuous batching (join = 1) requests that arrive
+while a batch runs join it at its level boundaries, each with the result of its
+own run alone."""
 from __future__ import annotations
 
 import sys
@@ -78,7 +80,7 @@ def test_server_budget_keeps_order(P):
     _say("server: tight budget")
     gs = _graphs()
     # the budget holds the largest request alone, so the requests take several steps
-    fp = [8 * (g.n + 1) + (8 if g.w is not None else 4) * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
+    fp = [8 * (g.n + 1) + 8 * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
     with P.Server(max(fp) + 1) as srv:
         ids = [srv.submit(g.off, g.col, g.w) for g in gs]
         out, steps = {}, 0
@@ -176,7 +178,7 @@ def _drain_async(srv, ids, budget):
 def test_server_async_results_match_oracle(P):
     _say("server: three batches in flight")
     gs = _graphs() + [graphgen.rmat(13, 16, seed=23, weighted=False)]
-    fp = [8 * (g.n + 1) + (8 if g.w is not None else 4) * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
+    fp = [8 * (g.n + 1) + 8 * g.nnz + 128 * g.n + 64 * g.nnz for g in gs]
     budget = max(fp) + 1   # the largest request fits only alone: several batches, some waiting for memory
     assert sum(fp) > budget
     with P.Server(budget, max_inflight=3) as srv:
@@ -236,3 +238,108 @@ def test_server_async_invalid_request_and_device_inputs(P):
             lab = torch.empty(max(g.n, 1), dtype=torch.int32, device=d)
             ready, _, q, lv = srv.result(i, lab)
             _check(g, (ready, lab.cpu().numpy()[: g.n], q, lv))
+
+
+# ------------------------------------------------------------------ continuous batching (join = 1)
+def _drain_join(srv, ids, budget=None):
+    out = {}
+    for _ in range(400000):
+        srv.step()
+        if budget is not None:
+            assert srv.info().resident_bytes <= budget
+        for i in ids:
+            if i not in out:
+                res = srv.result(i)
+                if res[0]:
+                    out[i] = res
+        if len(out) == len(ids):
+            break
+        time.sleep(0.001)
+    srv.wait()
+    assert len(out) == len(ids)
+    return out
+
+
+def _check_opts(g, res, **kw):
+    ready, labels, q, lv = res
+    r = oracle.run(g.off, g.col, g.w, **kw)
+    assert ready
+    assert np.array_equal(labels, r.labels[: g.n]) and q == r.q and lv == r.levels
+
+
+def test_server_join_results_match_oracle(P):
+    """Requests submitted while a large one runs join its batch at a level
+    boundary; each result is the oracle's run of its graph alone."""
+    _say("server: continuous batching")
+    big = graphgen.rmat(18, 16, seed=24, weighted=True)
+    small = _graphs() + [graphgen.rmat(13, 16, seed=26, weighted=True), graphgen.rmat(12, 16, seed=27)]
+    with P.Server(1 << 36, join=1) as srv:
+        ids = [srv.submit(big.off, big.col, big.w)]
+        srv.step()                                    # the batch starts on the server's worker
+        ids += [srv.submit(g.off, g.col, g.w) for g in small]
+        out = _drain_join(srv, ids)
+        info = srv.info()
+        _say(f"joined {info.joined} of {len(small)}, batches {info.batches}")
+        assert info.joined >= 1 and info.completed == len(ids)
+    for g, i in zip([big] + small, ids):
+        _check(g, out[i])
+
+
+def test_server_join_level_cap_and_device_inputs(P):
+    """Joined graphs count their own levels (max_levels) and hash their own
+    level into the priorities; device inputs join too."""
+    import torch
+    _say("server: joins with a level cap")
+    d = torch.device("cuda:0")
+    big = graphgen.rmat(17, 16, seed=31, weighted=False)
+    small = [graphgen.rmat(12, 16, seed=32 + k, weighted=k % 2 == 0) for k in range(4)] + \
+        [graphgen.planted_partition_1000(seed=9)]
+    keep = []
+    with P.Server(1 << 36, join=1, max_levels=2) as srv:
+        ids = [srv.submit(big.off, big.col, big.w)]
+        srv.step()
+        for g in small:
+            t = [torch.from_numpy(x).to(d) for x in (g.off, g.col)] + \
+                [None if g.w is None else torch.from_numpy(g.w).to(d)]
+            keep.append(t)
+            ids.append(srv.submit(t[0], t[1], t[2], n=g.n, nnz=g.nnz))
+        torch.cuda.synchronize()
+        for _ in range(400000):
+            srv.step()
+            if srv.info().queued == 0 and srv.info().inflight == 0:
+                break
+            time.sleep(0.001)
+        srv.wait()
+        _say(f"joined {srv.info().joined}")
+        _check_opts(big, srv.result(ids[0]), max_levels=2)
+        for g, i in zip(small, ids[1:]):
+            lab = torch.empty(max(g.n, 1), dtype=torch.int32, device=d)
+            ready, _, q, lv = srv.result(i, lab)
+            _check_opts(g, (ready, lab.cpu().numpy()[: g.n], q, lv), max_levels=2)
+
+
+def test_server_join_budget_and_invalid_request(P):
+    """Joins stay within the budget (a request that does not fit waits for a
+    later batch) and an invalid joining graph fails alone."""
+    _say("server: joins under a budget, invalid joiner")
+    big = graphgen.rmat(17, 16, seed=41, weighted=True)
+    mid = graphgen.rmat(15, 16, seed=42, weighted=True)
+    small = [graphgen.planted_partition_1000(seed=s) for s in (11, 12)] + [graphgen.rmat(11, 16, seed=43)]
+    bad = graphgen.disjoint_cliques(2, 3)
+    bad_col = bad.col.copy()
+    bad_col[0] = 2
+    fp = lambda g: 8 * (g.n + 1) + 8 * g.nnz + 128 * g.n + 64 * g.nnz
+    budget = fp(big) + sum(fp(g) for g in small) + fp(bad) + fp(mid) // 2   # mid fits only after big is done
+    with P.Server(budget, join=1) as srv:
+        ids = [srv.submit(big.off, big.col, big.w)]
+        srv.step()
+        ids.append(srv.submit(mid.off, mid.col, mid.w))
+        bad_id = srv.submit(bad.off, bad_col, bad.w)
+        ids += [srv.submit(g.off, g.col, g.w) for g in small]
+        out = _drain_join(srv, ids, budget)
+        with pytest.raises(P.PLMError) as e:
+            srv.result(bad_id)
+        assert e.value.status == P.PLM_E_GRAPH
+        assert srv.info().resident_bytes == 0
+    for g, i in zip([big, mid] + small, ids):
+        _check(g, out[i])
