@@ -405,11 +405,12 @@ SERVE_DESC = ("Poisson arrivals at 200 req/s of R-MAT graphs, scale uniform in [
 
 def serve_replay(P, torch, np, dgs, arr, check, join, inflight):
     """One open-loop real-time replay of the request stream against the native
-    request server; returns (latencies, results of the checked requests,
-    makespan, server info)."""
+    request server (join: level boundaries of a batch at which queued requests
+    join it, 0 = fixed batches); returns (latencies, results of the checked
+    requests, makespan, server info)."""
     count = len(dgs)
     check_lab = {i: torch.empty(dgs[i].n, dtype=torch.int32, device="cuda:0") for i in check}
-    srv = P.Server(200 * 10 ** 9, max_inflight=inflight, join=int(join))
+    srv = P.Server(200 * 10 ** 9, max_inflight=inflight, join=join)
     ids, lat, done_q = {}, np.full(count, np.nan), {}
     nxt, t0 = 0, time.perf_counter()
     while len(done_q) < count:
@@ -442,6 +443,9 @@ def serve_replay(P, torch, np, dgs, arr, check, join, inflight):
     return lat, checked, makespan, info
 
 
+JOIN_DEPTH = 32  # queued requests may join a running batch at any of its level boundaries
+
+
 def serve_bench(args, P, torch, np):
     """Served PLM: the request stream of the arrival window is generated on the
     GPU first (client buffers), then replayed open-loop in real time against
@@ -464,10 +468,10 @@ def serve_bench(args, P, torch, np):
     log(f"serve: {count} requests ({edges} edges) generated in {time.time() - t:.1f}s")
     # a few small requests are checked against the oracle afterwards
     check = [i for i in range(count) if scales[i] <= 13][:3]
-    lat, checked, makespan, info = serve_replay(P, torch, np, dgs, arr, check, True, 1)
+    lat, checked, makespan, info = serve_replay(P, torch, np, dgs, arr, check, JOIN_DEPTH, 1)
     log(f"serve (continuous batching): {count} requests in {makespan:.1f}s, {info.batches} batches, "
         f"{info.joined} joined a running batch")
-    lat_f, checked_f, makespan_f, info_f = serve_replay(P, torch, np, dgs, arr, check, False, args.serve_inflight)
+    lat_f, checked_f, makespan_f, info_f = serve_replay(P, torch, np, dgs, arr, check, 0, args.serve_inflight)
     log(f"serve (fixed batches): {count} requests in {makespan_f:.1f}s over {info_f.batches} batches")
     for d in dgs:
         d.free()
@@ -498,6 +502,7 @@ def serve_bench(args, P, torch, np):
     return {"workload": SERVE_DESC, "arrival_window_s": float(arr[-1]), "requests": count,
             "offered_req_per_s": rate, "offered_edges_per_s": edges / float(arr[-1]),
             "mode": "continuous batching (requests join the running batch at its level boundaries)",
+            "join_depth": JOIN_DEPTH,
             "completed": int(np.isfinite(lat).sum()), "makespan_s": makespan, "graphs_per_s": count / makespan,
             "edges_per_s": edges / makespan, "p50_latency_s": float(np.nanpercentile(lat, 50)),
             "p99_latency_s": float(np.nanpercentile(lat, 99)), "max_latency_s": float(np.nanmax(lat)),

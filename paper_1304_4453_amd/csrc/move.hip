@@ -128,15 +128,20 @@ __device__ __forceinline__ bool settled(const MoveState &ms, const Settle &st, i
     if (dw >= kStaleDw) return false;
     const int64_t room = dw == 0 ? ms.slack[u] : ms.kslack[u];
     if (room < 0) return false;
+    // p vol(u) V <= room (< 2^63), then 2 q S dw <= what is left; products
+    // only (room < 2^63 bounds every factor that can pass)
     uint64_t rem = (uint64_t)room;
-    if (ms.gp > 0) {  // p vol(u) V <= room, then what is left of it
+    if (ms.gp > 0) {
         const unsigned __int128 vv = (unsigned __int128)(uint64_t)ms.vol[u] * (st.now - ms.tstamp[u]);
-        if (vv > (unsigned __int128)(rem / (uint64_t)ms.gp)) return false;
-        rem -= (uint64_t)ms.gp * (uint64_t)vv;
+        if (vv >> 63) return false;
+        const unsigned __int128 need = (unsigned __int128)(uint64_t)ms.gp * (uint64_t)vv;
+        if (need > rem) return false;
+        rem -= (uint64_t)need;
     }
     if (dw == 0) return true;
     const unsigned __int128 per = (unsigned __int128)2u * (uint64_t)ms.gq * (uint64_t)node_S(ms, u);
-    return (unsigned __int128)dw <= (unsigned __int128)rem / per;
+    if (per >> 63) return false;
+    return (unsigned __int128)dw * (uint64_t)per <= rem;
 }
 __device__ __forceinline__ void record_stay(const MoveState &ms, const Settle &st, int32_t u, int64_t slack,
                                             int64_t kslack) {
@@ -156,6 +161,35 @@ template <typename G>
 __device__ __forceinline__ void slack_of(G K, G ub, int64_t &slack, int64_t &kslack) {
     slack = ub == neg_inf<G>() ? INT64_MAX : clamp_i64<G>(K - ub);
     kslack = K < 0 ? -1 : (clamp_i64<G>(K) < slack ? clamp_i64<G>(K) : slack);
+}
+// The same from the best evaluated score bs and the largest weight maxpa of a
+// pruned candidate (-1: none), whose score is at most S maxpa: the bound ub is
+// max(bs, S maxpa)
+template <typename G>
+__device__ __forceinline__ void slack_from(G K, G S, G bs, int64_t maxpa, int64_t &slack, int64_t &kslack) {
+    G ub = bs;
+    if (maxpa >= 0 && (G)S * (G)maxpa > ub) ub = (G)S * (G)maxpa;
+    slack_of<G>(K, ub, slack, kslack);
+}
+// In the per-node kernels the 128-bit gains (vol(u) S >= 2^62, rare) record
+// the lower bound 0 as slack, which keeps those kernels within their register
+// budget: such a node is settled only while nothing moved at all.
+template <typename G>
+__device__ __forceinline__ void slack_lean(G K, G S, G bs, int64_t maxpa, int64_t &slack, int64_t &kslack) {
+    if constexpr (sizeof(G) > 8) {
+        slack = 0;
+        kslack = K < 0 ? -1 : 0;
+    } else {
+        slack_from<G>(K, S, bs, maxpa, slack, kslack);
+    }
+}
+__device__ __forceinline__ int64_t wave_max_i64(int64_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        int64_t o = __shfl_xor(x, d);
+        if (o > x) x = o;
+    }
+    return x;
 }
 
 // tie key of label x for the node with priority hash hv: upper half of
@@ -329,11 +363,11 @@ constexpr int kWaveCap = 1024;  // slots per wavefront (rows up to 512 entries)
 // and whether it beats K, are exactly those of a full scan.
 constexpr int kEvalBatch = 8;
 
-// ub: raised to an upper bound of every slot's score (a pruned slot's score is
-// at most S w(u,X)), from which a node that stays gets its slack
+// maxpa: raised to the largest weight of a pruned slot (its score is at most
+// S w(u,X)), from which, with bs, a node that stays gets its slack
 template <typename G, typename V, bool LP>
 __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, G vu, G S, G K,
-                                           const int64_t *volC, bool clear, G &bs, int32_t &bx, G &ub,
+                                           const int64_t *volC, bool clear, G &bs, int32_t &bx, int64_t &maxpa,
                                            int64_t &ncand, uint64_t hv) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
@@ -357,13 +391,11 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
             ncand += X[j] >= 0;
             if (X[j] < 0) continue;
             if (!c[j]) {
-                const G b = (G)S * (G)a[j];
-                if (b > ub) ub = b;
+                if (a[j] > maxpa) maxpa = a[j];
                 continue;
             }
             G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
             if constexpr (LP) sc += (G)lp_tie(hv, X[j]);
-            if (sc > ub) ub = sc;
             if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
         }
     }
@@ -373,14 +405,15 @@ template <typename G, bool LP>
 __device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
                                           const int64_t *volC, int32_t &best_x, bool &move,
                                           int64_t &ncand, uint64_t hv, int64_t &slack, int64_t &kslack) {
-    G bs = neg_inf<G>(), ub = neg_inf<G>();
+    G bs = neg_inf<G>();
+    int64_t maxpa = -1;
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, ub, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, maxpa, ncand, hv);
     wave_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
-    slack_of<G>(K, wave_max<G>(ub), slack, kslack);
+    slack_lean<G>(K, S, bs, wave_max_i64(maxpa), slack, kslack);
 }
 
 // folds the (X, w) entries of u into a hash table (LDS) except X == D; returns
@@ -430,9 +463,11 @@ __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *z
     return myD;
 }
 
+// (at most 128 VGPRs: four waves per SIMD)
 template <int WK, bool LP>
-__global__ __launch_bounds__(256) void k_decide_wave(GraphView g, MoveState ms, int64_t begin, int64_t count,
-                                                     int force_wide) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_wave(GraphView g, MoveState ms,
+                                                                                           int64_t begin, int64_t count,
+                                                                                           int force_wide) {
     __shared__ int32_t tk[4][kWaveCap];
     __shared__ int32_t tv[4][kWaveCap];
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -522,20 +557,23 @@ template <typename G, bool LP>
 __device__ __forceinline__ void quad_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
                                           const int64_t *volC, int32_t &best_x, bool &move, int64_t &ncand,
                                           uint64_t hv, int64_t &slack, int64_t &kslack) {
-    G bs = neg_inf<G>(), ub = neg_inf<G>();
+    G bs = neg_inf<G>();
+    int64_t maxpa = -1;
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
     eval_slots<G, int32_t, LP>(tk, tv, tsize, (int)(threadIdx.x % kQuadLanes), kQuadLanes, vu, S, K, volC, true, bs,
-                               bx, ub, ncand, hv);
+                               bx, maxpa, ncand, hv);
     quad_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
-    slack_of<G>(K, quad_max<G>(ub), slack, kslack);
+    slack_lean<G>(K, S, bs, quad_max<int64_t>(maxpa), slack, kslack);
 }
 
+// (at most 128 VGPRs: four waves per SIMD)
 template <int WK, bool LP>
-__global__ __launch_bounds__(256) void k_decide_quad(GraphView g, MoveState ms, int64_t begin, int64_t count,
-                                                     int force_wide) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_decide_quad(GraphView g, MoveState ms,
+                                                                                           int64_t begin, int64_t count,
+                                                                                           int force_wide) {
     constexpr int kGroups = 256 / kQuadLanes;
     __shared__ int32_t tk[kGroups][kQuadCap];
     __shared__ int32_t tv[kGroups][kQuadCap];
@@ -606,7 +644,7 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     // slack_out[0], slack_out[1]: slack and kslack
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
-    __shared__ G red_u[NT / kWave];
+    __shared__ int64_t red_u[NT / kWave];
     __shared__ int32_t red_x[NT / kWave];
     // w(u, D \ u) first (wD enters as this thread's share): the score of staying
     // bounds which slots need their community volume
@@ -617,20 +655,21 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     wD = 0;
     for (int j = 0; j < NT / kWave; ++j) wD += red_w[j];
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    G bs = neg_inf<G>(), ub = neg_inf<G>();
+    G bs = neg_inf<G>();
+    int64_t maxpa = -1;
     int32_t bx = kNone;
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, ub, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, maxpa, ncand, hv);
     wave_argmax<G>(bs, bx);
-    ub = wave_max<G>(ub);
-    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; red_u[w] = ub; }
+    maxpa = wave_max_i64(maxpa);
+    if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; red_u[w] = maxpa; }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int j = 1; j < NT / kWave; ++j) {
             if (red_s[j] > bs || (red_s[j] == bs && red_x[j] < bx)) { bs = red_s[j]; bx = red_x[j]; }
-            if (red_u[j] > ub) ub = red_u[j];
+            if (red_u[j] > maxpa) maxpa = red_u[j];
         }
         *out = (bx != kNone && bs > K) ? bx : -1;
-        slack_of<G>(K, ub, slack_out[0], slack_out[1]);
+        slack_lean<G>(K, S, bs, maxpa, slack_out[0], slack_out[1]);
     }
 }
 
@@ -968,7 +1007,7 @@ template <typename G, bool LP>
 __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, G vu, G S, G K,
                                            const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
                                            int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
-                                           int32_t &bx, G &ub, int64_t &ncand, uint64_t hv) {
+                                           int32_t &bx, int64_t &maxpa, int64_t &ncand, uint64_t hv) {
     const int32_t nch = ha.nchunk[hg];
     const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
     const int32_t *sx = ha.stg_x + ha.stg_off[hg];
@@ -977,7 +1016,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
     const int32_t max_keys = ha.agg_max_keys > 0 ? ha.agg_max_keys : kAggMaxKeys;
     const int32_t tile = ha.agg_tile > 0 ? ha.agg_tile : kAggTile;
     for (int qbits = 0;; ++qbits) {
-        G pbs = neg_inf<G>(), pub = neg_inf<G>();
+        G pbs = neg_inf<G>();
+        int64_t pmaxpa = -1;
         int32_t pbx = kNone;
         int64_t pc = 0;
         bool ok = true;
@@ -1063,13 +1103,13 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
                 break;
             }
             eval_slots<G, int64_t, LP>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx,
-                                       pub, pc, hv);
+                                       pmaxpa, pc, hv);
             __syncthreads();
         }
         if (ok) {
             bs = pbs;
             bx = pbx;
-            ub = pub;
+            maxpa = pmaxpa;
             ncand += pc;
             return;
         }
@@ -1124,23 +1164,23 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     if (force_wide || vu > node_wl(ms, u)) {
         const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
         const i128 K = Sg * (i128)wD - vg * (i128)base + (LP ? (i128)kLpTieMax : (i128)0);
-        i128 ub = neg_inf<i128>();
-        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx, ub,
-                             ncand, hv);
+        int64_t maxpa = -1;
+        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
+                             maxpa, ncand, hv);
         block_argmax<i128>(bs, bx);
-        ub = block_max<i128>(ub);
+        maxpa = block_max<int64_t>(maxpa);
         int64_t ks;
-        slack_of<i128>(K, ub, slack, ks);
+        slack_from<i128>(K, Sg, bs, maxpa, slack, ks);
     } else {
         const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
         const int64_t K = Sg * wD - vg * base + (LP ? (int64_t)kLpTieMax : 0);
-        int64_t b64 = neg_inf<int64_t>(), ub = neg_inf<int64_t>();
+        int64_t b64 = neg_inf<int64_t>(), maxpa = -1;
         agg_bucket<int64_t, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
-                                ub, ncand, hv);
+                                maxpa, ncand, hv);
         block_argmax<int64_t>(b64, bx);
-        ub = block_max<int64_t>(ub);
+        maxpa = block_max<int64_t>(maxpa);
         int64_t ks;
-        slack_of<int64_t>(K, ub, slack, ks);
+        slack_from<int64_t>(K, Sg, b64, maxpa, slack, ks);
         bs = (i128)b64;
     }
     if (threadIdx.x == 0) {
