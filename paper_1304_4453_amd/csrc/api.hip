@@ -10,8 +10,10 @@
 #include <cstring>
 #include <fstream>
 #include <mutex>
+#include <exception>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/plm.h"
@@ -85,6 +87,7 @@ struct LevelData {
     // up (the refinement's colouring is the same: same graph, seed and level)
     int32_t *colour_kept = nullptr;
     int32_t ncol_kept = 0;
+    bool borrowed = false;  // off/col/w belong to another context (ensemble base runs)
 
     GraphView view() const {
         GraphView g;
@@ -93,6 +96,9 @@ struct LevelData {
         return g;
     }
     void release() {
+        if (borrowed) {
+            off = nullptr; col = nullptr; w = nullptr;
+        }
         dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase); dev_free(gshift);
         dev_free(colour_kept);
     }
@@ -754,7 +760,8 @@ struct plm_ctx {
         return moves;
     }
 
-    // one sweep; from the third of a move phase on, replayed from the sweep graph
+    // one sweep (with allow_graph, replayed from the graph captured at the
+    // plan's first sweep)
     int64_t sweep(bool allow_graph = false) {
         settle_before();
         // every sweep of a plan replays the graph captured at its first sweep
@@ -1038,62 +1045,9 @@ struct plm_ctx {
         return it;
     }
 
-    // EPP(b, PLP, PLMR) (Algorithm 5): b label-propagation runs with seeds
-    // colour_seed .. colour_seed + b - 1 on the input graph, their core groups
-    // (Equation (3.2), named by their smallest member), the graph contracted
-    // by the core groups as level 1, PLMR from there (max_levels counted from
-    // level 1; level 0 is not refined), and the communities prolonged to the
-    // input nodes (canonical labels in lab_out).  Returns the PLMR levels.
-    int32_t epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *cores_out) {
-        reset();
-        const int64_t n = n0;
-        *cores_out = 0;
-        if (n == 0) return 1;
-        EnsembleWork wk;
-        int32_t *grp = nullptr;
-        auto release = [&]() {
-            dev_free(wk.keys); dev_free(wk.keys_alt); dev_free(wk.vals); dev_free(wk.vals_alt); dev_free(wk.first);
-            dev_free(grp);
-            if (wk.scratch) (void)hipFree(wk.scratch);
-            wk.scratch = nullptr;
-        };
-        double t_ens = 0;
-        int64_t k = 0;
-        try {
-            wk.keys = dev_alloc<uint64_t>(n); wk.keys_alt = dev_alloc<uint64_t>(n);
-            wk.vals = dev_alloc<int32_t>(n); wk.vals_alt = dev_alloc<int32_t>(n); wk.first = dev_alloc<int32_t>(n);
-            wk.scratch = (void *)dev_alloc<uint8_t>((int64_t)ensemble_scratch_bytes(n));
-            grp = dev_alloc<int32_t>(n);
-            for (int32_t i = 0; i < b; ++i) {
-                plp_level(opt.colour_seed + (uint64_t)i, plp_iters, nullptr);
-                double t1 = now_ms();
-                ensemble_refine(grp, zeta, n, i == 0, wk, st);
-                HIPCHK(hipStreamSynchronize(st));
-                t_ens += now_ms() - t1;
-            }
-            double t1 = now_ms();
-            HIPCHK(hipMemcpyAsync(zeta, grp, n * 4, hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));
-            release();
-            const int32_t ncol0 = ncol;
-            const int64_t loops0 = loops;
-            k = coarsen();
-            stats.levels = 1;
-            stats.n[0] = n;
-            stats.nnz[0] = levels[0].nnz;
-            stats.loops[0] = loops0;
-            stats.colours[0] = ncol0;
-            stats.communities[0] = k;
-            stats.coarsen_ms[0] = now_ms() - t1;
-            stats.ens_ms = t_ens;
-            stats.ens_cores = k;
-        } catch (...) {
-            release();
-            throw;
-        }
-        *cores_out = k;
-        return descend(lab_out, 1, true);
-    }
+    // EPP(b, PLP, PLMR) (Algorithm 5); defined after create_impl, which it
+    // uses for the contexts of its concurrent base runs
+    int32_t epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *cores_out);
 
     // Modularity of the current level's partition zeta, on the current graph:
     // contraction keeps every intra-community weight (coarse self-loops hold
@@ -1738,7 +1692,7 @@ void resolve_bins(plm_options &o, bool batch, int64_t nnz) {
 // context takes over (freed with it, also when creation fails) instead of copying
 plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t n, int64_t nnz,
                        const int64_t *offsets, const int32_t *cols, const int32_t *weights, int32_t mem_kind,
-                       void *hip_stream, const plm_options *opt, bool adopt = false) {
+                       void *hip_stream, const plm_options *opt, bool adopt = false, bool borrow = false) {
     g_create_error.clear();
     if (out) *out = nullptr;
     auto fail = [&](int code, const std::string &m) {
@@ -1800,11 +1754,12 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         l0.nnz = nnz;
         l0.wkind = weights ? 1 : 0;
         l0.diag_mult = 2;
-        if (adopt) {
+        if (adopt || borrow) {
             l0.off = const_cast<int64_t *>(offsets);
             l0.col = const_cast<int32_t *>(cols);
             l0.w = const_cast<int32_t *>(weights);
-            adopt = false;  // owned by the level from here on
+            l0.borrowed = borrow;
+            adopt = false;  // owned by the level from here on (or by the lender)
             c->levels.push_back(l0);
         } else {
             l0.off = dev_alloc<int64_t>(n + 1);
@@ -1901,6 +1856,123 @@ plm_status plm_internal_batch_serve(plm_ctx *ctx, plm::BatchHooks *hooks) {
 plm_status plm_internal_batch_adopt(plm_ctx **out, int64_t G, const int64_t *node_base, int64_t nnz, int64_t *off,
                                     int32_t *col, int32_t *w, void *hip_stream, const plm_options *opt) {
     return create_impl(out, G, node_base, node_base[G], nnz, off, col, w, PLM_MEM_DEVICE, hip_stream, opt, true);
+}
+
+
+// EPP(b, PLP, PLMR) (Algorithm 5): b label-propagation runs with seeds
+// colour_seed .. colour_seed + b - 1 on the input graph, their core groups
+// (Equation (3.2), named by their smallest member), the graph contracted by
+// the core groups as level 1, PLMR from there (max_levels counted from level
+// 1; level 0 is not refined), and the communities prolonged to the input
+// nodes (canonical labels in lab_out).  Returns the PLMR levels.
+// The base runs are independent, so they run concurrently: each on a context
+// of its own (reading this context's input graph, with its own state, a
+// stream of its own and a host thread driving it), as the paper runs its
+// ensemble members in parallel;
+// each gives exactly the labels of a run alone, and the core groups combine
+// them in seed order.
+int32_t plm_ctx::epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *cores_out) {
+    reset();
+    const int64_t n = n0;
+    *cores_out = 0;
+    if (n == 0) return 1;
+    EnsembleWork wk;
+    int32_t *grp = nullptr;
+    std::vector<plm_ctx *> runs(b, nullptr);
+    std::vector<hipStream_t> rst(b, nullptr);
+    std::vector<int32_t *> base(b, nullptr);
+    auto release = [&]() {
+        dev_free(wk.keys); dev_free(wk.keys_alt); dev_free(wk.vals); dev_free(wk.vals_alt); dev_free(wk.first);
+        dev_free(grp);
+        if (wk.scratch) (void)hipFree(wk.scratch);
+        wk.scratch = nullptr;
+        for (int32_t i = 0; i < b; ++i) {
+            if (runs[i]) plm_destroy(runs[i]);
+            runs[i] = nullptr;
+            if (rst[i]) (void)hipStreamDestroy(rst[i]);
+            rst[i] = nullptr;
+            dev_free(base[i]);
+        }
+    };
+    double t_ens = 0;
+    int64_t k = 0;
+    try {
+        // the base runs' contexts: same graph and options, no validation, no
+        // settled-node skip (label propagation keeps its own active set)
+        plm_options o = opt;
+        o.validate = 0;
+        o.timing = 0;
+        o.settle = -1;
+        o.refine = 0;
+        o.hub_stream = 0;  // one stream per base run: the runs are the concurrency
+        const LevelData &l0 = levels[0];
+        HIPCHK(hipStreamSynchronize(st));
+        for (int32_t i = 0; i < b; ++i) {
+            HIPCHK(hipStreamCreateWithFlags(&rst[i], hipStreamNonBlocking));
+            const plm_status rc = create_impl(&runs[i], 0, nullptr, n, l0.nnz, l0.off, l0.col,
+                                              (const int32_t *)l0.w, PLM_MEM_DEVICE, rst[i], &o, false, true);
+            if (rc != PLM_OK) throw Error{rc, "base run context: " + g_create_error};
+            base[i] = dev_alloc<int32_t>(n);
+        }
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::vector<std::exception_ptr> errs(b);
+        std::vector<std::thread> ts;
+        const double t_plp = now_ms();
+        for (int32_t i = 0; i < b; ++i) {
+            ts.emplace_back([&, i] {
+                try {
+                    HIPCHK(hipSetDevice(dev));
+                    plm_ctx *c = runs[i];
+                    c->plp_level(opt.colour_seed + (uint64_t)i, plp_iters, nullptr);
+                    HIPCHK(hipMemcpyAsync(base[i], c->zeta, n * 4, hipMemcpyDeviceToDevice, c->st));
+                    HIPCHK(hipStreamSynchronize(c->st));
+                } catch (...) {
+                    errs[i] = std::current_exception();
+                }
+            });
+        }
+        for (auto &t : ts) t.join();
+        for (auto &e : errs)
+            if (e) std::rethrow_exception(e);
+        for (int32_t i = 0; i < b; ++i) {
+            stats.lp_runs += runs[i]->stats.lp_runs;
+            stats.lp_iterations += runs[i]->stats.lp_iterations;
+            stats.lp_updates += runs[i]->stats.lp_updates;
+        }
+        stats.lp_ms += now_ms() - t_plp;
+        wk.keys = dev_alloc<uint64_t>(n); wk.keys_alt = dev_alloc<uint64_t>(n);
+        wk.vals = dev_alloc<int32_t>(n); wk.vals_alt = dev_alloc<int32_t>(n); wk.first = dev_alloc<int32_t>(n);
+        wk.scratch = (void *)dev_alloc<uint8_t>((int64_t)ensemble_scratch_bytes(n));
+        grp = dev_alloc<int32_t>(n);
+        double t1 = now_ms();
+        for (int32_t i = 0; i < b; ++i) ensemble_refine(grp, base[i], n, i == 0, wk, st);
+        HIPCHK(hipStreamSynchronize(st));
+        t_ens += now_ms() - t1;
+        t1 = now_ms();
+        HIPCHK(hipMemcpyAsync(zeta, grp, n * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        // the colouring of level 0 for the statistics (the base runs coloured
+        // with their own seeds): that of the first base run
+        const int32_t ncol0 = runs[0]->ncol;
+        release();
+        const int64_t loops0 = loops;
+        k = coarsen();
+        stats.levels = 1;
+        stats.n[0] = n;
+        stats.nnz[0] = levels[0].nnz;
+        stats.loops[0] = loops0;
+        stats.colours[0] = ncol0;
+        stats.communities[0] = k;
+        stats.coarsen_ms[0] = now_ms() - t1;
+        stats.ens_ms = t_ens;
+        stats.ens_cores = k;
+    } catch (...) {
+        release();
+        throw;
+    }
+    *cores_out = k;
+    return descend(lab_out, 1, true);
 }
 
 namespace {

@@ -321,7 +321,9 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     // several workgroups per node: each work item is kHubChunk entries of one
     // long row; its colours go into an LDS bitmap that is OR-ed into the row's
     // global bitmap, and the workgroup that finishes the row's last chunk
-    // (counted after a device fence) picks the smallest free colour from it.
+    // (counted by a per-slot atomic that each workgroup increments after its
+    // returning bitmap ORs, whose results it has consumed) picks the smallest
+    // free colour from it.
     // The nodes this round releases read that colour only in the next round.
     __shared__ int32_t last_chunk;
     __shared__ uint32_t or_sink[NT];
