@@ -656,7 +656,105 @@ def sweep_probe(P, torch, level=0):
     print(json.dumps(out), flush=True)
 
 
+GROUP_OF = {"k_decide_lane": "k_decide_lane", "k_decide_quad": "k_decide_wave", "k_decide_wave": "k_decide_wave",
+            "k_decide_block": "k_decide_block", "k_hub_single": "k_hub_single", "k_hub_part": "k_hub_part+k_hub_agg",
+            "k_hub_agg": "k_hub_part+k_hub_agg"}
+
+
+def _kernel_base(name):
+    """(base name, first template argument) of a kernel name in a rocprofv3 CSV."""
+    short = name.replace("void ", "").replace("plm::", "").split("(")[0]
+    base = short.split("<")[0]
+    arg = short[len(base) + 1:].split(",")[0].split(">")[0] if "<" in short else ""
+    return base, arg
+
+
+def reduce_counters(fetch_dir, write_dir, probe_file, level):
+    """Reduces two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+    `bench.py --sweep-probe LEVEL` to the HBM traffic of each move-decide kernel
+    group in the probed sweep (the level's instantiations: weight kind 1 at
+    level 0, 2 above), scaled by what the counters read for the probe's 1 GiB
+    device copy (the dispatch that wrote 1 GiB and read the most); prints the
+    JSON that profiles/decide_traffic_rmat26.md carries."""
+    import csv
+    import glob
+    import hashlib
+
+    def per_dispatch(d, counter):
+        agg = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                        agg[k] = agg.get(k, 0.0) + float(r["Counter_Value"])
+        return agg
+
+    wk = "2" if level > 0 else "1"
+
+    def groups(agg):
+        acc = {}
+        for (_, name), v in agg.items():
+            base, arg = _kernel_base(name)
+            if base in GROUP_OF and arg == wk:
+                acc[GROUP_OF[base]] = acc.get(GROUP_OF[base], 0.0) + v
+        return acc
+
+    fd, wd = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    cands = [kv for kv in wd.items() if abs(kv[1] - (1 << 20)) < (1 << 14)]
+    cal = max(cands, key=lambda kv: fd.get(kv[0], 0.0))
+    fs, ws = (1 << 20) / fd[cal[0]], (1 << 20) / cal[1]
+    fa, wa = groups(fd), groups(wd)
+    probe = json.loads([l for l in open(probe_file) if l.startswith("{")][-1])
+    src = os.path.join(ROOT, "paper_1304_4453_amd", "csrc", "move.hip")
+    out = {"workload": probe["workload"], "level": level, "sweep": probe["sweep"], "moves": probe["moves"],
+           "calibration_kernel": cal[0][1][:60], "fetch_copy_kib": fd[cal[0]], "write_copy_kib": cal[1],
+           "fetch_scale": fs, "write_scale": ws,
+           "move_hip_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(), "kernels": []}
+    for i, k in enumerate(probe["kernels"]):
+        la = probe["kernel_launches"][min(i, 4)]
+        fb, wb = fa.get(k, 0.0) * 1024 * fs, wa.get(k, 0.0) * 1024 * ws
+        alg = probe["kernel_bytes"][i]
+        out["kernels"].append({"kernel": k, "launches": la, "fetch_bytes": fb, "write_bytes": wb,
+                               "traffic_bytes_per_launch": (fb + wb) / max(la, 1),
+                               "algorithmic_bytes_per_launch": alg / max(la, 1),
+                               "traffic_over_algorithmic": (fb + wb) / alg if alg else None})
+    print(json.dumps(out))
+
+
+def reduce_trace(trace_dir, level):
+    """Per-dispatch durations of the move-decide kernels of a level in a
+    rocprofv3 --kernel-trace of `bench.py --steps 1 --warmup 0 ...` (the
+    instrumented step, then the timed step, each with the same dispatches):
+    average duration per dispatch in each half; prints JSON."""
+    import csv
+    import glob
+    import statistics
+    wk = "2" if level > 0 else "1"
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    out = {}
+    for base in GROUP_OF:
+        ds = [(e - s) / 1000 for s, e, n in rows if _kernel_base(n) == (base, wk)]
+        if not ds:
+            continue
+        h = len(ds) // 2
+        out[base] = {"dispatches_per_step": h, "instrumented_avg_us": statistics.mean(ds[:h]) if h else None,
+                     "timed_avg_us": statistics.mean(ds[h:])}
+    print(json.dumps(out))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--reduce-counters":
+        reduce_counters(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--reduce-trace":
+        reduce_trace(sys.argv[2], int(sys.argv[3]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
