@@ -310,6 +310,7 @@ def cpu_full_run(P, torch, scale=18):
             "gpu_plm_run_s": tg, "gpu_speedup": total / tg}
 
 
+COMPILED_BINS = {"bin_lane": 16, "bin_wave": 512, "bin_block": 4096, "hub_row_max": 12288}
 BATCH_DESC = ("4,096 SBM graphs, n log-uniform in [100, 100000], k = max(2, n/100) near-equal blocks, "
               "p_in = 20/blocksize, p_out = 1/n, unit weights, seed 4")
 
@@ -347,9 +348,26 @@ def batch_bench(args, P, torch, np):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
     st = ctx.stats()
+    o = ctx.options()
+    tuned_bins = {k: int(getattr(o, k)) for k in COMPILED_BINS}
     labels = lab.cpu().numpy()
     ctx.close()
-    log(f"batch run {tb * 1e3:.1f} ms")
+    log(f"batch run {tb * 1e3:.1f} ms (bins {tuned_bins})")
+    # the same batch with the compiled bin thresholds, for the tuned table's gain
+    ctx = P.BatchContext(nb, off, col, w, **COMPILED_BINS)
+    lab_d = torch.empty_like(lab)
+    for i in range(args.warmup):
+        ctx.run_batch(lab_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, q_d, lv_d = ctx.run_batch(lab_d)
+    torch.cuda.synchronize()
+    td = (time.perf_counter() - t0) / args.steps
+    ctx.close()
+    same_d = bool(np.array_equal(lab_d.cpu().numpy(), labels) and np.array_equal(q_d, q) and np.array_equal(lv_d, lv))
+    del lab_d
+    log(f"batch run with compiled bins {td * 1e3:.1f} ms, identical: {same_d}")
     rng = np.random.default_rng(0)
     idx = np.sort(rng.choice(count, min(args.plain_sample, count), replace=False))
     ctxs = [P.Context(graphs[i].off, graphs[i].col, graphs[i].w) for i in idx]
@@ -373,6 +391,9 @@ def batch_bench(args, P, torch, np):
            "plain_graphs_per_s": len(idx) / tp, "plain_sample": int(len(idx)),
            "speedup_vs_plain": (count / tb) / (len(idx) / tp),
            "identical_partitions": f"{same}/{len(idx)}", "levels_max": int(lv.max()),
+           "tuned_bins": {"bins": tuned_bins, "source": "paper_1304_4453_amd/tuned_bins.txt (batch row)",
+                          "compiled_bins": COMPILED_BINS, "graphs_per_s_compiled_bins": count / td,
+                          "gain": td / tb, "identical_partitions": same_d},
            "roofline": roof,
            "per_level": {k: st[k] for k in ("n", "nnz", "colours", "sweeps", "sweep_ms", "colour_ms",
                                             "coarsen_ms")}}

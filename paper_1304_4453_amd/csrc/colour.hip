@@ -15,11 +15,12 @@
 // entries), one wavefront per node (<= 1024), and several workgroups per node
 // above that; the latter OR the colours they see into a block-local LDS bitmap
 // and merge it into a per-node global bitmap, from which the workgroup that
-// finishes the row's last chunk picks the smallest free colour.  Small
-// frontiers run as back-to-back rounds inside one workgroup (the tail).  A
-// round is bound by latency (its frontier is
-// often small), so every lane loads a batch of entries before it gathers their
-// colours, instead of walking a row one dependent load after another.
+// finishes the row's last chunk picks the smallest free colour.  The three
+// tiers of a round run on workgroups of their own.  Small frontiers run as
+// back-to-back rounds inside one workgroup (the tail).  A round is bound by
+// latency (its frontier is often small), so every lane loads a batch of
+// entries before it gathers their colours, instead of walking a row one
+// dependent load after another.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -228,8 +229,40 @@ __device__ __forceinline__ int32_t wave_colour_scan(const GraphView &g, uint64_t
     }
 }
 
+// Workgroups of a grid round per tier.  The three tiers of a frontier are
+// independent (the frontier is an independent set and its nodes only read
+// colours of earlier rounds), so each tier gets workgroups of its own and a
+// round lasts as long as its slowest tier's chain of dependent loads and
+// atomics, not the sum of the three.  A tier gets the workgroups it can use in
+// one pass when they fit in the grid, else a share of the grid in proportion
+// to its passes (at least one workgroup when it has work); three workgroups
+// are held back so that the shares, each rounded down and raised to at least
+// one, never exceed the grid.
+struct TierSplit {
+    int64_t first[3], count[3];
+};
+__device__ __forceinline__ TierSplit tier_split(int64_t ns, int64_t nm, int64_t nc, int64_t per_s, int64_t per_m,
+                                                int64_t nblk) {
+    const int64_t need[3] = {(ns + per_s - 1) / per_s, (nm + per_m - 1) / per_m, nc};
+    const int64_t tot = need[0] + need[1] + need[2];
+    TierSplit t;
+    int64_t at = 0;
+    for (int k = 0; k < 3; ++k) {
+        int64_t c = need[k];
+        if (tot > nblk && c > 0) {
+            c = need[k] * (nblk - 3) / tot;
+            c = c > 0 ? c : 1;
+        }
+        t.first[k] = at;
+        t.count[k] = c;
+        at += c;
+    }
+    return t;
+}
+
 // One round, run by workgroups [bid, bid + nblk) of NT threads: the grid
-// launch passes its own block index and size, the single-workgroup tail 0, 1.
+// launch passes its own block index and size (the tiers split the grid), the
+// single-workgroup tail 0, 1 (its workgroup runs the three tiers in turn).
 template <int NT>
 __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed, int32_t level, int32_t r,
                                               int32_t *colour, int32_t *pending, const JpQ &Q, int64_t bid,
@@ -239,12 +272,15 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     const int set = r % 3, nxt = (r + 1) % 3, old = (r + 2) % 3;
     if (bid == 0 && threadIdx.x < 4) Q.cnt[cidx(old, (int)threadIdx.x)] = 0;
     const int32_t ns = Q.cnt[cidx(set, 0)], nm = Q.cnt[cidx(set, 1)], nc = Q.cnt[cidx(set, 3)];
-    const int64_t gthreads = nblk * NT;
-    const int64_t gtid = bid * NT + threadIdx.x;
+    TierSplit ts;
+    for (int k = 0; k < 3; ++k) { ts.first[k] = 0; ts.count[k] = 1; }
+    if (nblk > 1) ts = tier_split(ns, nm, nc, NT / 8, NT / kWave, nblk);
     // eight lanes per node (rows of at most 32 entries: four per lane, loaded
     // together); the colours seen are OR-ed over the eight lanes
     const int sub = (int)(threadIdx.x & 7);
-    for (int64_t i = gtid >> 3; i < ns; i += gthreads >> 3) {
+    const int64_t b0 = bid - ts.first[0];
+    const bool in0 = b0 >= 0 && b0 < ts.count[0];
+    for (int64_t i = in0 ? (b0 * NT + threadIdx.x) >> 3 : ns; i < ns; i += (ts.count[0] * NT) >> 3) {
         int32_t u = Q.q[set][0][i];
         const int64_t bu = node_base(g, u);
         const int32_t lu = node_level(g, level, u);
@@ -279,7 +315,9 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     // registers (kWaveRow / 64 per lane), its colours gathered in one batch and
     // its lower-priority neighbours released from the same registers
     const int w = threadIdx.x / kWave;
-    for (int64_t i = bid * (NT / kWave) + w; i < nm; i += nblk * (NT / kWave)) {
+    const int64_t b1 = bid - ts.first[1];
+    const bool in1 = b1 >= 0 && b1 < ts.count[1];
+    for (int64_t i = in1 ? b1 * (NT / kWave) + w : nm; i < nm; i += ts.count[1] * (NT / kWave)) {
         int32_t u = Q.q[set][1][i];
         const int64_t bu = node_base(g, u);
         const int32_t lu = node_level(g, level, u);
@@ -327,7 +365,9 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     // The nodes this round releases read that colour only in the next round.
     __shared__ int32_t last_chunk;
     __shared__ uint32_t or_sink[NT];
-    for (int64_t it = bid; it < nc; it += nblk) {
+    const int64_t b2 = bid - ts.first[2];
+    const bool in2 = b2 >= 0 && b2 < ts.count[2];  // workgroup-uniform: the loop holds barriers
+    for (int64_t it = in2 ? b2 : nc; it < nc; it += ts.count[2]) {
         const int64_t item = Q.cq[set][it];
         const int32_t j = (int32_t)(item >> 32);
         const int64_t k = item & 0xffffffffLL;
