@@ -216,6 +216,13 @@ struct plm_ctx {
     int64_t armed_sweeps = 0;
     int32_t *hub_skip = nullptr;
     uint64_t *hub_clk = nullptr;
+    // launch plans of the hub kernels (one record per workgroup of the
+    // level-wide lists) and each hub's first chunk / bucket list index
+    HubSglPlan *splan = nullptr;
+    HubPartPlan *pplan = nullptr;
+    HubAggPlan *aplan = nullptr;
+    HubRedPlan *rplan = nullptr;
+    int64_t *ins_abs = nullptr, *agg_abs = nullptr;
 
     // label propagation (Algorithm 1): active flag of each node; lp_mode turns
     // the class steps into label-propagation steps with tie keys of lp_seed
@@ -272,6 +279,7 @@ struct plm_ctx {
         dev_free(agg_first); dev_free(stg_off); dev_free(bkt_off); dev_free(stg_w); dev_free(wd_part); dev_free(hub_base);
         dev_free(bkt); dev_free(part); dev_free(hub_u); dev_free(ins_hub); dev_free(agg_hub); dev_free(sgl_hub);
         dev_free(red_hub); dev_free(hub_skip); dev_free(hub_clk);
+        dev_free(splan); dev_free(pplan); dev_free(aplan); dev_free(rplan); dev_free(ins_abs); dev_free(agg_abs);
         cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = cap_hubu = cap_ihub = cap_ahub = cap_shub = cap_rhub = 0;
     }
 
@@ -373,6 +381,9 @@ struct plm_ctx {
         if (hubs > cap_hubs) {
             dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
             dev_free(stg_off); dev_free(bkt_off); dev_free(hub_base); dev_free(hub_skip); dev_free(hub_clk);
+            dev_free(ins_abs); dev_free(agg_abs);
+            ins_abs = dev_alloc<int64_t>(hubs);
+            agg_abs = dev_alloc<int64_t>(hubs);
             hub_base = dev_alloc<int64_t>(hubs);
             hub_skip = dev_alloc<int32_t>(hubs);
             hub_clk = dev_alloc<uint64_t>(hubs);
@@ -389,10 +400,26 @@ struct plm_ctx {
         if (bk > cap_bkt) { dev_free(bkt); bkt = dev_alloc<uint32_t>(bk); cap_bkt = bk; }
         if (ins > cap_ins) { dev_free(wd_part); wd_part = dev_alloc<int64_t>(ins); cap_ins = ins; }
         if (agg > cap_agg) { dev_free(part); part = dev_alloc<unsigned long long>(4 * agg); cap_agg = agg; }
-        if (ins_tot > cap_ihub) { dev_free(ins_hub); ins_hub = dev_alloc<int32_t>(ins_tot); cap_ihub = ins_tot; }
-        if (agg_tot > cap_ahub) { dev_free(agg_hub); agg_hub = dev_alloc<int32_t>(agg_tot); cap_ahub = agg_tot; }
-        if (sgl_tot > cap_shub) { dev_free(sgl_hub); sgl_hub = dev_alloc<int32_t>(sgl_tot); cap_shub = sgl_tot; }
-        if (red_tot > cap_rhub) { dev_free(red_hub); red_hub = dev_alloc<int32_t>(red_tot); cap_rhub = red_tot; }
+        if (ins_tot > cap_ihub) {
+            dev_free(ins_hub); dev_free(pplan);
+            ins_hub = dev_alloc<int32_t>(ins_tot); pplan = dev_alloc<HubPartPlan>(ins_tot);
+            cap_ihub = ins_tot;
+        }
+        if (agg_tot > cap_ahub) {
+            dev_free(agg_hub); dev_free(aplan);
+            agg_hub = dev_alloc<int32_t>(agg_tot); aplan = dev_alloc<HubAggPlan>(agg_tot);
+            cap_ahub = agg_tot;
+        }
+        if (sgl_tot > cap_shub) {
+            dev_free(sgl_hub); dev_free(splan);
+            sgl_hub = dev_alloc<int32_t>(sgl_tot); splan = dev_alloc<HubSglPlan>(sgl_tot);
+            cap_shub = sgl_tot;
+        }
+        if (red_tot > cap_rhub) {
+            dev_free(red_hub); dev_free(rplan);
+            red_hub = dev_alloc<int32_t>(red_tot); rplan = dev_alloc<HubRedPlan>(red_tot);
+            cap_rhub = red_tot;
+        }
     }
 
     void build_schedule() { build_schedule(opt.colour_seed, opt.schedule); }
@@ -466,7 +493,7 @@ struct plm_ctx {
         std::vector<int32_t> hpos(H > 0 ? H : 1), hch(H > 0 ? H : 1, 0), hpb(H > 0 ? H : 1, 0), shub, rhub, ihub,
             ahub;
         std::vector<int64_t> hins(H > 0 ? H : 1, 0), hagg(H > 0 ? H : 1, 0), hstg(H > 0 ? H : 1, 0),
-            hbk(H > 0 ? H : 1, 0);
+            hbk(H > 0 ? H : 1, 0), hins_abs(H > 0 ? H : 1, 0), hagg_abs(H > 0 ? H : 1, 0);
         int64_t max_stg = 0, max_bk = 0, max_ins = 0, max_agg = 0, hg = 0;
         sgl_nodes = sgl_entries = 0;
         for (int32_t c = 0; c < ncol; ++c) {
@@ -501,6 +528,8 @@ struct plm_ctx {
                 hpb[hg] = pb;
                 hins[hg] = ins;
                 hagg[hg] = agg;
+                hins_abs[hg] = (int64_t)ihub.size();
+                hagg_abs[hg] = (int64_t)ahub.size();
                 hstg[hg] = stg;
                 hbk[hg] = bk;
                 ihub.insert(ihub.end(), (size_t)ch, (int32_t)hg);
@@ -533,6 +562,10 @@ struct plm_ctx {
             if (!ahub.empty()) HIPCHK(hipMemcpyAsync(agg_hub, ahub.data(), ahub.size() * 4, hipMemcpyHostToDevice, st));
             if (!shub.empty()) HIPCHK(hipMemcpyAsync(sgl_hub, shub.data(), shub.size() * 4, hipMemcpyHostToDevice, st));
             if (!rhub.empty()) HIPCHK(hipMemcpyAsync(red_hub, rhub.data(), rhub.size() * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(ins_abs, hins_abs.data(), H * 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(agg_abs, hagg_abs.data(), H * 8, hipMemcpyHostToDevice, st));
+            launch_hub_plans(g, hub_arrays(), ins_abs, agg_abs, (int64_t)shub.size(), (int64_t)ihub.size(),
+                             (int64_t)ahub.size(), (int64_t)rhub.size(), splan, pplan, aplan, rplan, st);
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
@@ -579,6 +612,7 @@ struct plm_ctx {
         ha.pbits = pbits; ha.stg_off = stg_off; ha.bkt_off = bkt_off; ha.stg_x = stg_x; ha.stg_w = stg_w;
         ha.bkt = bkt; ha.wd_part = wd_part; ha.part = part; ha.hub_base = hub_base;
         ha.hub_skip = hub_skip; ha.hub_clk = hub_clk;
+        ha.splan = splan; ha.pplan = pplan; ha.aplan = aplan; ha.rplan = rplan;
         ha.agg_max_keys = opt.agg_max_keys > 0 ? opt.agg_max_keys : 0;
         ha.agg_tile = opt.agg_tile > 0 ? opt.agg_tile : 0;
         return ha;

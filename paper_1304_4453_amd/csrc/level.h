@@ -93,6 +93,32 @@ struct ClassRange {
     int64_t sgl_base = 0, sgl_count = 0, red_base = 0, red_count = 0, ins_base = 0, agg_base = 0;
 };
 
+// Launch plans of the hub kernels, one record per workgroup (filled on the
+// device from the per-hub arrays once per plan): a workgroup finds its node,
+// row slice and staging offsets with one load instead of a chain of dependent
+// ones (workgroup -> hub -> node -> row offsets).
+struct HubSglPlan {    // one-workgroup hub
+    int64_t e0, e1;    // row of u
+    int32_t u, pos;    // node, class position
+};
+struct HubPartPlan {   // chunk workgroup of a partitioned hub
+    int64_t c0;        // first entry of the chunk
+    int64_t stg;       // staging offset of the chunk (class area)
+    int64_t bkt;       // offset of the hub's (bucket, chunk) words (class area)
+    int32_t u, hg, k, len, nch, pb, pos, pad;  // node, hub, chunk, entries, chunks, log2 buckets, class position
+};
+struct HubAggPlan {    // bucket workgroup of a partitioned hub
+    int64_t bkt;       // offset of this bucket's words, one per chunk (class area)
+    int64_t stg;       // staging offset of the hub (class area)
+    int64_t wd;        // first chunk workgroup of the hub (class-relative): its w(u, D) shares
+    int32_t u, hg, p, nch;
+};
+struct HubRedPlan {    // reduce of a partitioned hub (in the apply launch)
+    int64_t agg;       // first bucket workgroup of the hub (class-relative)
+    int64_t wd;        // first chunk workgroup of the hub (class-relative)
+    int32_t u, hg, nagg, nch;
+};
+
 struct HubArrays {
     const int32_t *hub_pos;    // class position of each hub
     const int32_t *hub_u;      // node of each hub
@@ -114,6 +140,10 @@ struct HubArrays {
     unsigned long long *part;  // per bucket workgroup: score hi, score lo, X, slack of the bucket
     int32_t *hub_skip;         // per hub: 1 = settled in its current class step (written by agg)
     uint64_t *hub_clk;         // per hub: the moved-volume clock at the start of its class step
+    const HubSglPlan *splan = nullptr;   // per workgroup of the level-wide lists above
+    const HubPartPlan *pplan = nullptr;
+    const HubAggPlan *aplan = nullptr;
+    const HubRedPlan *rplan = nullptr;
     // lowered limits of the bucket workgroups (0 = the compiled ones): new
     // communities per pass, and chunks flattened at once
     int32_t agg_max_keys = 0, agg_tile = 0;
@@ -140,6 +170,11 @@ void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, 
                   hipStream_t st);
 // row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
 // positions [begin, begin + count)
+// fills the launch plans of the level-wide hub lists (ins_abs / agg_abs: first
+// list index of each hub's chunk / bucket workgroups)
+void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
+                      int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
+                      HubAggPlan *ap, HubRedPlan *rp, hipStream_t st);
 void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
                         int64_t count, int64_t *deg_out, int32_t *u_out, hipStream_t st);
 

@@ -116,32 +116,37 @@ struct Settle {
 };
 __device__ __forceinline__ Settle settle_state(const MoveState &ms) {
     Settle st{false, 0};
-    if (ms.sctl && ms.sctl[0]) {
-        st.on = true;
-        st.now = ms.sctl[1];
+    if (ms.sctl) {  // the arming word and the clock share a line: one load
+        const uint64_t a = ms.sctl[0], now = ms.sctl[1];
+        st.on = a != 0;
+        st.now = now;
     }
     return st;
 }
+// Every word the test reads is loaded up front and the test is evaluated
+// without branches: the loads are then in flight together instead of each
+// waiting for the branch on the one before (the test sits at the head of every
+// decide kernel's chain of dependent loads).
 __device__ __forceinline__ bool settled(const MoveState &ms, const Settle &st, int32_t u) {
     if (!st.on) return false;
     const uint64_t dw = ms.dw[u];
-    if (dw >= kStaleDw) return false;
-    const int64_t room = dw == 0 ? ms.slack[u] : ms.kslack[u];
-    if (room < 0) return false;
+    const int64_t sl = ms.slack[u], ks = ms.kslack[u];
+    const uint64_t ts = ms.tstamp[u];
+    const uint64_t vu = (uint64_t)ms.vol[u];
+    const uint64_t su = (uint64_t)node_S(ms, u);
+    const int64_t room = dw == 0 ? sl : ks;
+    bool ok = dw < kStaleDw && room >= 0;
     // p vol(u) V <= room (< 2^63), then 2 q S dw <= what is left; products
     // only (room < 2^63 bounds every factor that can pass)
-    uint64_t rem = (uint64_t)room;
+    uint64_t rem = ok ? (uint64_t)room : 0;
     if (ms.gp > 0) {
-        const unsigned __int128 vv = (unsigned __int128)(uint64_t)ms.vol[u] * (st.now - ms.tstamp[u]);
-        if (vv >> 63) return false;
+        const unsigned __int128 vv = (unsigned __int128)vu * (st.now - ts);
         const unsigned __int128 need = (unsigned __int128)(uint64_t)ms.gp * (uint64_t)vv;
-        if (need > rem) return false;
-        rem -= (uint64_t)need;
+        ok = ok && !(vv >> 63) && need <= rem;
+        rem = ok ? rem - (uint64_t)need : 0;
     }
-    if (dw == 0) return true;
-    const unsigned __int128 per = (unsigned __int128)2u * (uint64_t)ms.gq * (uint64_t)node_S(ms, u);
-    if (per >> 63) return false;
-    return (unsigned __int128)dw * (uint64_t)per <= rem;
+    const unsigned __int128 per = (unsigned __int128)2u * (uint64_t)ms.gq * su;
+    return ok && (dw == 0 || (!(per >> 63) && (unsigned __int128)dw * (uint64_t)per <= rem));
 }
 __device__ __forceinline__ void record_stay(const MoveState &ms, const Settle &st, int32_t u, int64_t slack,
                                             int64_t kslack) {
@@ -739,15 +744,15 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     __shared__ int32_t tv[1 << kSingleBits];
     __shared__ int32_t dec;
     __shared__ int64_t slack[2];
-    const int64_t hg = ha.sgl_hub[blk0 + blockIdx.x];
-    const int32_t u = ha.hub_u[hg];
-    const int64_t pos = ha.hub_pos[hg];
+    const HubSglPlan pl = ha.splan[blk0 + blockIdx.x];
+    const int32_t u = pl.u;
+    const int64_t pos = pl.pos;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     if ((LP && !ms.active[u]) || settled(ms, st, u)) {
         if (threadIdx.x == 0) ms.move_to[pos] = -1;
         return;
     }
-    const int64_t e0 = g.off[u], e1 = g.off[u + 1];
+    const int64_t e0 = pl.e0, e1 = pl.e1;
     // rows of at most kSingleMaxRow entries: load factor <= 0.75
     int bits = ceil_log2_dev(2 * (e1 - e0));
     bits = bits < 6 ? 6 : (bits > kSingleBits ? kSingleBits : bits);
@@ -850,32 +855,33 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     int32_t *const start = lds.b.start;
     int32_t *const fill = lds.b.fill;
     __shared__ int64_t wsum[kHubThreads / kWave];
-    const int64_t hg = ha.ins_hub[blk0 + blockIdx.x];
-    const int64_t k = blockIdx.x - ha.ins_first[hg];
-    const int32_t u = ha.hub_u[hg];
+    const HubPartPlan pl = ha.pplan[blk0 + blockIdx.x];
+    const int32_t u = pl.u;
+    const int64_t k = pl.k;
     // the apply launch leaves this position to the hub's own reduce
-    if (k == 0 && threadIdx.x == 0) ms.move_to[ha.hub_pos[hg]] = kHubPending;
-    if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
-    if (!LP && settled(ms, settle_state(ms), u)) return;  // settled hub: nothing staged
-    const int32_t D = ms.zeta[u];
-    const int64_t e0 = g.off[u], e1 = g.off[u + 1];
-    const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
-    if (threadIdx.x == 0 && ms.dec_dev) {
-        if (k == 0) atomicAdd(ms.dec_dev + 3, 1ULL);
-        atomicAdd(ms.dec_dev + 7, (unsigned long long)(c1 - c0));
-    }
-    const int pb = ha.pbits[hg];
-    const int P = 1 << pb;
-    for (int i = threadIdx.x; i < kMergeSlots; i += kHubThreads) { lds.m.key[i] = kEmpty; lds.m.val[i] = 0; }
+    if (k == 0 && threadIdx.x == 0) ms.move_to[pl.pos] = kHubPending;
+    // the chunk's entries are loaded beside the hub's own words (community,
+    // settled test), not after them
+    const int64_t c0 = pl.c0;
     int32_t v[kHubPerThread], X[kHubPerThread], bk[kHubPerThread];
     int64_t W[kHubPerThread];
 #pragma unroll
     for (int j = 0; j < kHubPerThread; ++j) {
-        int64_t e = c0 + j * kHubThreads + threadIdx.x;
-        bool ok = e < c1;
-        v[j] = ok ? g.col[e] : u;
-        W[j] = ok ? wload<WK>(g.w, e) : 0;
+        const int32_t i = j * kHubThreads + threadIdx.x;
+        const bool ok = i < pl.len;
+        v[j] = ok ? g.col[c0 + i] : u;
+        W[j] = ok ? wload<WK>(g.w, c0 + i) : 0;
     }
+    const int32_t D = ms.zeta[u];
+    if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
+    if (!LP && settled(ms, settle_state(ms), u)) return;  // settled hub: nothing staged
+    if (threadIdx.x == 0 && ms.dec_dev) {
+        if (k == 0) atomicAdd(ms.dec_dev + 3, 1ULL);
+        atomicAdd(ms.dec_dev + 7, (unsigned long long)pl.len);
+    }
+    const int pb = pl.pb;
+    const int P = 1 << pb;
+    for (int i = threadIdx.x; i < kMergeSlots; i += kHubThreads) { lds.m.key[i] = kEmpty; lds.m.val[i] = 0; }
 #pragma unroll
     for (int j = 0; j < kHubPerThread; ++j) X[j] = v[j] != u ? ms.zeta[v[j]] : -1;
     int64_t myD = 0;
@@ -939,8 +945,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     __syncthreads();
     int32_t run = inc - local;
     for (int i = 0; i < threadIdx.x / kWave; ++i) run += wtot[i];
-    const int32_t nch = ha.nchunk[hg];
-    uint32_t *bkt = ha.bkt + ha.bkt_off[hg];
+    const int32_t nch = pl.nch;
+    uint32_t *bkt = ha.bkt + pl.bkt;
 #pragma unroll
     for (int i = 0; i < (1 << kHubMaxPBits) / kHubThreads; ++i) {
         int b = threadIdx.x * per + i;
@@ -951,8 +957,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
         }
     }
     __syncthreads();
-    int32_t *sx = ha.stg_x + ha.stg_off[hg] + k * kHubInsChunk;
-    int64_t *sw = ha.stg_w + ha.stg_off[hg] + k * kHubInsChunk;
+    int32_t *sx = ha.stg_x + pl.stg;
+    int64_t *sw = ha.stg_w + pl.stg;
 #pragma unroll
     for (int j = 0; j < kHubPerThread; ++j) {
         if (bk[j] < 0) continue;
@@ -1003,16 +1009,20 @@ __device__ __forceinline__ G block_max(G x) {
 // at a time: an LDS prefix sum over the chunks' segment lengths turns the
 // bucket into one flat index space that every thread strides over (a binary
 // search finds the chunk of an index).
+constexpr int kAggPer = kAggTile / kHubThreads;  // chunk words per thread and tile
+// pre: this thread's words of the first tile, loaded at the start of the
+// kernel (tile 0 is read by every pass)
 template <typename G, bool LP>
-__device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int64_t p, G vu, G S, G K,
-                                           const int64_t *volC, int32_t *tk, int64_t *tv, int32_t *cpre,
-                                           int32_t *cbase, int32_t *wtot, int32_t *nkeys, int32_t *overflow, G &bs,
-                                           int32_t &bx, int64_t &maxpa, int64_t &ncand, uint64_t hv) {
-    const int32_t nch = ha.nchunk[hg];
-    const uint32_t *bkt = ha.bkt + ha.bkt_off[hg] + p * (int64_t)nch;
-    const int32_t *sx = ha.stg_x + ha.stg_off[hg];
-    const int64_t *sw = ha.stg_w + ha.stg_off[hg];
-    constexpr int kPer = kAggTile / kHubThreads;
+__device__ __forceinline__ void agg_bucket(const HubArrays &ha, const HubAggPlan &pl, const uint32_t (&pre)[kAggPer],
+                                           G vu, G S, G K, const int64_t *volC, int32_t *tk, int64_t *tv,
+                                           int32_t *cpre, int32_t *cbase, int32_t *wtot, int32_t *nkeys,
+                                           int32_t *overflow, G &bs, int32_t &bx, int64_t &maxpa, int64_t &ncand,
+                                           uint64_t hv) {
+    const int32_t nch = pl.nch;
+    const uint32_t *bkt = ha.bkt + pl.bkt;
+    const int32_t *sx = ha.stg_x + pl.stg;
+    const int64_t *sw = ha.stg_w + pl.stg;
+    constexpr int kPer = kAggPer;
     const int32_t max_keys = ha.agg_max_keys > 0 ? ha.agg_max_keys : kAggMaxKeys;
     const int32_t tile = ha.agg_tile > 0 ? ha.agg_tile : kAggTile;
     for (int qbits = 0;; ++qbits) {
@@ -1033,7 +1043,7 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, int64_t hg, int6
 #pragma unroll
                 for (int i = 0; i < kPer; ++i) {
                     int32_t c = threadIdx.x * kPer + i;
-                    uint32_t word = c < tn ? bkt[t0 + c] : 0u;
+                    uint32_t word = c < tn ? (t0 == 0 ? pre[i] : bkt[t0 + c]) : 0u;
                     cnt[i] = (int32_t)(word & 0xffffu);
                     if (c < tn) cbase[c] = (t0 + c) * (int32_t)kHubInsChunk + (int32_t)(word >> 16);
                     loc += cnt[i];
@@ -1125,9 +1135,25 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     __shared__ int32_t cpre[kAggTile], cbase[kAggTile], wtot[kHubThreads / kWave];
     __shared__ int32_t nkeys, overflow;
     __shared__ int64_t wred[kHubThreads / kWave];
-    const int64_t hg = ha.agg_hub[blk0 + blockIdx.x];
-    const int64_t p = blockIdx.x - ha.agg_first[hg];
-    const int32_t u = ha.hub_u[hg];
+    const HubAggPlan pl = ha.aplan[blk0 + blockIdx.x];
+    const int64_t hg = pl.hg, p = pl.p;
+    const int32_t u = pl.u;
+    // words that depend only on the plan go out together: the first tile of
+    // the bucket's chunk words, the chunk shares of w(u, D \ u), u's own words
+    uint32_t pre[kAggPer];
+    {
+        const int32_t tile = ha.agg_tile > 0 ? ha.agg_tile : kAggTile;
+        const int32_t tn = pl.nch < tile ? pl.nch : tile;
+#pragma unroll
+        for (int i = 0; i < kAggPer; ++i) {
+            const int32_t c = threadIdx.x * kAggPer + i;
+            pre[i] = c < tn ? ha.bkt[pl.bkt + c] : 0u;
+        }
+    }
+    int64_t wD = 0;
+    for (int64_t j = threadIdx.x; j < pl.nch; j += kHubThreads) wD += ha.wd_part[pl.wd + j];
+    const int64_t vu = ms.vol[u];
+    const int32_t D = ms.zeta[u];
     if (LP && !ms.active[u]) return;
     if (!LP) {
         // whether the hub is settled, and the clock its decision is taken at,
@@ -1140,17 +1166,13 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         }
         if (sk) return;
     }
-    const int64_t vu = ms.vol[u];
     // w(u, D \ u) from the chunk shares (written by the chunk launch) and the
     // score of staying, which bounds the slots worth a volume gather
-    int64_t wD = 0;
-    for (int64_t j = threadIdx.x; j < ha.nchunk[hg]; j += kHubThreads) wD += ha.wd_part[ha.ins_first[hg] + j];
     wD = wave_sum(wD);
     if (lane_id() == 0) wred[threadIdx.x / kWave] = wD;
     __syncthreads();
     wD = 0;
     for (int i = 0; i < kHubThreads / kWave; ++i) wD += wred[i];
-    const int32_t D = ms.zeta[u];
     const int64_t base = LP ? 0 : ms.volC[D] - vu;
     // vol(D \ u) at the start of the class, for the reduce (which runs while the
     // class's other moves apply)
@@ -1165,8 +1187,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
         const i128 K = Sg * (i128)wD - vg * (i128)base + (LP ? (i128)kLpTieMax : (i128)0);
         int64_t maxpa = -1;
-        agg_bucket<i128, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs, bx,
-                             maxpa, ncand, hv);
+        agg_bucket<i128, LP>(ha, pl, pre, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs,
+                             bx, maxpa, ncand, hv);
         block_argmax<i128>(bs, bx);
         maxpa = block_max<int64_t>(maxpa);
         int64_t ks;
@@ -1175,8 +1197,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
         const int64_t K = Sg * wD - vg * base + (LP ? (int64_t)kLpTieMax : 0);
         int64_t b64 = neg_inf<int64_t>(), maxpa = -1;
-        agg_bucket<int64_t, LP>(ha, hg, p, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64, bx,
-                                maxpa, ncand, hv);
+        agg_bucket<int64_t, LP>(ha, pl, pre, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64,
+                                bx, maxpa, ncand, hv);
         block_argmax<int64_t>(b64, bx);
         maxpa = block_max<int64_t>(maxpa);
         int64_t ks;
@@ -1212,16 +1234,17 @@ __device__ __forceinline__ int64_t apply_move(const MoveState &ms, int32_t u, in
 // before any move of the class applied.
 template <bool LP>
 __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha,
-                                                 int64_t hg) {
+                                                 const HubRedPlan &pl) {
     __shared__ int64_t wsum[kHubThreads / kWave];
     __shared__ int32_t dec;
-    const int32_t u = ha.hub_u[hg];
+    const int32_t u = pl.u;
+    const int64_t hg = pl.hg;
     if (LP && !ms.active[u]) return;  // nothing decided, nothing to apply
     // settled (decided by the bucket launch before any move of the class): stays
     const bool sk = !LP && ms.sctl && ms.sctl[0];
     if (sk && ha.hub_skip[hg]) return;
-    const int64_t nagg = (int64_t)1 << ha.pbits[hg];
-    const unsigned long long *p0 = ha.part + 4 * (size_t)ha.agg_first[hg];
+    const int64_t nagg = pl.nagg;
+    const unsigned long long *p0 = ha.part + 4 * (size_t)pl.agg;
     i128 bs = neg_inf<i128>();
     int32_t bx = kNone;
     int64_t slack = INT64_MAX;
@@ -1234,7 +1257,7 @@ __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveS
     }
     if (sk) slack = -block_max<int64_t>(-slack);  // the smallest bucket slack, in thread 0
     int64_t wD = 0;
-    for (int64_t j = threadIdx.x; j < ha.nchunk[hg]; j += kHubThreads) wD += ha.wd_part[ha.ins_first[hg] + j];
+    for (int64_t j = threadIdx.x; j < pl.nch; j += kHubThreads) wD += ha.wd_part[pl.wd + j];
     wD = wave_sum(wD);
     if (lane_id() == 0) wsum[threadIdx.x / kWave] = wD;
     block_argmax<i128>(bs, bx);
@@ -1283,7 +1306,7 @@ template <bool LP>
 __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveState ms, HubArrays ha, int64_t red0,
                                                               int64_t nred, int64_t begin, int64_t count) {
     if ((int64_t)blockIdx.x < nred) {  // workgroup-uniform
-        hub_reduce_apply<LP>(g, ms, ha, ha.red_hub[red0 + blockIdx.x]);
+        hub_reduce_apply<LP>(g, ms, ha, ha.rplan[red0 + blockIdx.x]);
         return;
     }
     __shared__ int64_t red[kHubThreads / kWave];
@@ -1333,6 +1356,52 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
         for (int w = 0; w < kHubThreads / kWave; ++w) m += red[w];
         if (m) atomicAdd(ms.moves_dev, (unsigned long long)m);
     }
+}
+
+// launch plans of the level-wide hub lists: one thread per workgroup record
+__global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, const int64_t *agg_abs, int64_t n_sgl,
+                            int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
+                            HubAggPlan *ap, HubRedPlan *rp) {
+    const int64_t tot = n_sgl + n_ins + n_agg + n_red;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n_sgl) {
+            const int32_t hg = ha.sgl_hub[i], u = ha.hub_u[hg];
+            sp[i] = HubSglPlan{g.off[u], g.off[u + 1], u, ha.hub_pos[hg]};
+            continue;
+        }
+        int64_t j = i - n_sgl;
+        if (j < n_ins) {
+            const int32_t hg = ha.ins_hub[j], u = ha.hub_u[hg];
+            const int64_t k = j - ins_abs[hg], e0 = g.off[u], e1 = g.off[u + 1];
+            const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
+            pp[j] = HubPartPlan{c0, ha.stg_off[hg] + k * kHubInsChunk, ha.bkt_off[hg], u, hg, (int32_t)k,
+                                (int32_t)(c1 - c0), ha.nchunk[hg], ha.pbits[hg], ha.hub_pos[hg], 0};
+            continue;
+        }
+        j -= n_ins;
+        if (j < n_agg) {
+            const int32_t hg = ha.agg_hub[j];
+            const int64_t p = j - agg_abs[hg];
+            const int32_t nch = ha.nchunk[hg];
+            ap[j] = HubAggPlan{ha.bkt_off[hg] + p * nch, ha.stg_off[hg], ha.ins_first[hg], ha.hub_u[hg], hg,
+                               (int32_t)p, nch};
+            continue;
+        }
+        j -= n_agg;
+        const int32_t hg = ha.red_hub[j];
+        rp[j] = HubRedPlan{ha.agg_first[hg], ha.ins_first[hg], ha.hub_u[hg], hg, 1 << ha.pbits[hg], ha.nchunk[hg]};
+    }
+}
+
+void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
+                      int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
+                      HubAggPlan *ap, HubRedPlan *rp, hipStream_t st) {
+    const int64_t tot = n_sgl + n_ins + n_agg + n_red;
+    if (tot <= 0) return;
+    const int64_t blocks = cdiv(tot, 256);
+    hipLaunchKernelGGL(k_hub_plans, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, g, ha, ins_abs,
+                       agg_abs, n_sgl, n_ins, n_agg, n_red, sp, pp, ap, rp);
+    HIPCHK(hipGetLastError());
 }
 
 // row length of each hub, negated when vol(u) does not fit 32 bits
