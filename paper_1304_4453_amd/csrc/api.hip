@@ -155,6 +155,7 @@ struct plm_ctx {
     // state of the current level (capacity n0)
     int64_t *vol0 = nullptr, *vol = nullptr, *volC = nullptr;
     int32_t *zeta = nullptr, *colour = nullptr, *class_nodes = nullptr, *move_to = nullptr, *lab = nullptr;
+    NodeRec *noderec = nullptr;  // per class position: node and row (with class_nodes)
     int64_t *bstart_dev = nullptr;
     int64_t max_vol = 0, wide_lim = 0;
     bool sched = false;
@@ -251,7 +252,7 @@ struct plm_ctx {
     ~plm_ctx() {
         for (auto &l : levels) l.release();
         dev_free(vol0); dev_free(vol); dev_free(volC); dev_free(zeta); dev_free(colour); dev_free(class_nodes);
-        dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
+        dev_free(noderec); dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
         dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active); dev_free(snap[0]); dev_free(snap[1]);
@@ -460,6 +461,7 @@ struct plm_ctx {
         // first position of bin b of class c (b = 4: the next class)
         auto bs = [&](int64_t c, int b) { return bstart[8 * c + 2 * b]; };
         active_nodes = l.n > 0 ? bstart[(size_t)ncol * 8] : 0;
+        launch_node_recs(g, class_nodes, active_nodes, noderec, st);
         active_entries = l.nnz - hbuf[8];
         for (int b = 0; b < 4; ++b) {
             bin_entries[b] = hbuf[9 + b];
@@ -582,6 +584,7 @@ struct plm_ctx {
     MoveState move_state(bool count_cand) {
         MoveState ms;
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
+        ms.rec = noderec;
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
         ms.cand_sgl = count_cand ? dcnt + 13 : nullptr;
         ms.dec_dev = count_cand ? dcnt + 16 : nullptr;
@@ -1283,6 +1286,7 @@ struct plm_ctx {
             regrow(zeta, n1, 0);
             regrow(colour, n1, 0);
             regrow(class_nodes, n1, 0);
+            regrow(noderec, n1, 0);
             regrow(move_to, n1, 0);
             regrow(bflag, n1, 0);
             regrow(bnewid, n1 + 1, 0);
@@ -1847,6 +1851,7 @@ plm_status create_impl(plm_ctx **out, int64_t G, const int64_t *node_base, int64
         c->zeta = dev_alloc<int32_t>(n);
         c->colour = dev_alloc<int32_t>(n);
         c->class_nodes = dev_alloc<int32_t>(n);
+        c->noderec = dev_alloc<NodeRec>(n);
         c->move_to = dev_alloc<int32_t>(n);
         c->lab = dev_alloc<int32_t>(n);
         c->dcnt = dev_alloc<unsigned long long>(32);

@@ -34,11 +34,20 @@ constexpr int64_t kQuadRow = 64;
 constexpr int64_t kBlockShortRow = 2048;
 
 // ---- move.hip
+// per class position: its node and the node's row, written with the buckets
+// and read by the per-node decide kernels in place of the node id and its two
+// row offsets (one coalesced load instead of a load and two dependent ones)
+struct NodeRec {
+    int64_t e0;
+    int32_t len, u;
+};
+
 struct MoveState {
     int32_t *zeta;         // community of each node
     int64_t *volC;         // community volumes
     const int64_t *vol;    // node volumes
     const int32_t *class_nodes;
+    const NodeRec *rec = nullptr;  // per class position (see NodeRec)
     int32_t *move_to;      // per class position: target community or -1
     int64_t S;
     int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
@@ -170,6 +179,8 @@ void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, 
                   hipStream_t st);
 // row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
 // positions [begin, begin + count)
+// rec[i] = (row start, row length, node) of class_nodes[i], i < count
+void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, hipStream_t st);
 // fills the launch plans of the level-wide hub lists (ins_abs / agg_abs: first
 // list index of each hub's chunk / bucket workgroups)
 void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,

@@ -289,8 +289,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int64_t ncand = 0, nd = 0, ne = 0;
     int32_t u = 0;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
+    int64_t e0 = 0, d = 0;
     if (i < count) {
-        u = ms.class_nodes[(int64_t)begin + i];
+        const NodeRec r = ms.rec[(int64_t)begin + i];
+        u = r.u;
+        e0 = r.e0;
+        d = r.len;
         if ((LP && !ms.active[u]) || settled(ms, st, u)) {
             ms.move_to[begin + i] = -1;
             i = count;  // inactive or settled: nothing to decide
@@ -298,8 +302,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     if (i < count) {
         int64_t pos = begin + i;
-        int64_t e0 = g.off[u];
-        int64_t d = g.off[u + 1] - e0;
         int32_t X[kLaneMax];
         int64_t W[kLaneMax];
 #pragma unroll
@@ -482,12 +484,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < count; i += (int64_t)gridDim.x * 4) {
         int64_t pos = begin + i;
-        int32_t u = ms.class_nodes[pos];
+        const NodeRec r = ms.rec[pos];
+        const int32_t u = r.u;
         if ((LP && !ms.active[u]) || settled(ms, st, u)) {  // wave-uniform
             if (lane == 0) ms.move_to[pos] = -1;
             continue;
         }
-        int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        const int64_t e0 = r.e0, e1 = r.e0 + r.len;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
@@ -590,10 +593,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int64_t b0 = (int64_t)blockIdx.x * kGroups; b0 < count; b0 += (int64_t)gridDim.x * kGroups) {
         const int64_t i = b0 + grp, pos = begin + i;
         const bool has = i < count;
-        const int32_t u = has ? ms.class_nodes[pos] : 0;
+        const NodeRec r = has ? ms.rec[pos] : NodeRec{0, 0, 0};
+        const int32_t u = r.u;
         const bool act = has && (!LP || ms.active[u]) && !settled(ms, st, u);
         if (has && !act && l == 0) ms.move_to[pos] = -1;
-        const int64_t e0 = act ? g.off[u] : 0, e1 = act ? g.off[u + 1] : 0;
+        const int64_t e0 = act ? r.e0 : 0, e1 = act ? r.e0 + r.len : 0;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;  // rows of at most kQuadRow entries: at most kQuadCap slots
         const int32_t D = act ? ms.zeta[u] : -1;
@@ -693,12 +697,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         int64_t pos = begin + i;
-        int32_t u = ms.class_nodes[pos];
+        const NodeRec r = ms.rec[pos];
+        const int32_t u = r.u;
         if ((LP && !ms.active[u]) || settled(ms, st, u)) {  // workgroup-uniform
             if (threadIdx.x == 0) ms.move_to[pos] = -1;
             continue;
         }
-        int64_t e0 = g.off[u], e1 = g.off[u + 1];
+        const int64_t e0 = r.e0, e1 = r.e0 + r.len;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
         int32_t D = ms.zeta[u];
@@ -1327,11 +1332,11 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
              i0 += nblk * kHubThreads) {
             const int64_t i = i0 + lane_id();
             const int32_t X = i < count ? ms.move_to[begin + i] : -1;
+            const int32_t u = i < count ? ms.class_nodes[begin + i] : 0;  // beside the move, not after it
             const bool mv = X >= 0;
             int32_t D = 0;
             int64_t join = 0, leave = 0;
             if (mv) {
-                const int32_t u = ms.class_nodes[begin + i];
                 D = ms.zeta[u];
                 join = leave = ms.vol[u];
                 ms.zeta[u] = X;
@@ -1356,6 +1361,22 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
         for (int w = 0; w < kHubThreads / kWave; ++w) m += red[w];
         if (m) atomicAdd(ms.moves_dev, (unsigned long long)m);
     }
+}
+
+__global__ void k_node_recs(GraphView g, const int32_t *class_nodes, int64_t count, NodeRec *rec) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t u = class_nodes[i];
+        const int64_t e0 = g.off[u];
+        rec[i] = NodeRec{e0, (int32_t)(g.off[u + 1] - e0), u};
+    }
+}
+
+void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, hipStream_t st) {
+    if (count <= 0) return;
+    const int64_t blocks = cdiv(count, 256);
+    hipLaunchKernelGGL(k_node_recs, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, g, class_nodes,
+                       count, rec);
+    HIPCHK(hipGetLastError());
 }
 
 // launch plans of the level-wide hub lists: one thread per workgroup record
