@@ -48,15 +48,24 @@ __host__ __device__ __forceinline__ int cidx(int set, int kind) { return (set * 
 constexpr int kCntNcol = 12 * kCntLine, kCntUncoloured = 13 * kCntLine, kCntTail = 14 * kCntLine;
 constexpr int kCntWords = 15 * kCntLine;
 
+// A work item of a long row: everything its workgroup indexes, so that the
+// row's entries are its first dependent load
+struct HubItem {
+    int64_t c0, c1;           // entries of the chunk
+    int32_t u, slot, nch, pad;  // node, queue slot (bitmap, chunk counter), chunks of the row
+};
+
 struct JpQ {
-    int32_t *q[3][3];  // [set][kind]: 0 lane, 1 wavefront, 2 multi-workgroup
-    int64_t *cq[3];    // [set]: chunks of the multi-workgroup rows, (slot << 32) | chunk
+    int32_t *q[3][2];  // [set][kind]: 0 lane, 1 wavefront (long rows: cq)
+    HubItem *cq[3];    // [set]: chunks of the multi-workgroup rows
     int32_t *cnt;      // kCntWords counters (above)
     uint32_t *bitmap;  // per multi-workgroup queue slot: kWinWords words
     int32_t *done;     // per multi-workgroup queue slot: chunks finished (0 between uses)
 };
 
-// pending(u) = number of higher-priority non-loop neighbours.  A workgroup
+// pending(u) = number of higher-priority non-loop neighbours (low 32 bits;
+// k_jp_seed adds u's row kind in bits 32-33, so that the release that takes
+// the count to zero knows the queue without loading u's row offsets).  A workgroup
 // takes kPendTile consecutive entries (read lane by lane), finds each entry's
 // row through the tile's row offsets staged in LDS (a binary search; a global
 // one when the tile spans a run of empty rows) and counts into the row's LDS
@@ -64,7 +73,7 @@ struct JpQ {
 // atomically (pending zeroed first).
 constexpr int kPendTile = 2048;
 constexpr int kPendPer = kPendTile / kCT;
-__global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, int32_t level, int32_t *pending) {
+__global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, int32_t level, uint64_t *pending) {
     __shared__ int64_t soff[kPendTile + 1];
     __shared__ int32_t acc[kPendTile];
     __shared__ int64_t rr[2];
@@ -107,13 +116,13 @@ __global__ __launch_bounds__(kCT) void k_jp_pending(GraphView g, uint64_t seed, 
         const int64_t x = v[q];
         if (x == r || !prio_greater(prio_hash(seed, lr, x - br), x, prio_hash(seed, lr, r - br), r)) continue;
         if (staged) atomicAdd(&acc[lo], 1);
-        else atomicAdd(&pending[r], 1);
+        else atomicAdd((unsigned long long *)&pending[r], 1ULL);
     }
     if (!staged) return;  // workgroup-uniform
     __syncthreads();
     for (int64_t j = threadIdx.x; j < nr; j += kCT) {
-        if (soff[j] >= E0 && soff[j + 1] <= E1) pending[r0 + j] = acc[j];
-        else if (acc[j]) atomicAdd(&pending[r0 + j], acc[j]);
+        if (soff[j] >= E0 && soff[j + 1] <= E1) pending[r0 + j] = (uint64_t)acc[j];
+        else if (acc[j]) atomicAdd((unsigned long long *)&pending[r0 + j], (unsigned long long)acc[j]);
     }
 }
 
@@ -123,37 +132,57 @@ __device__ __forceinline__ int row_kind(const int64_t *off, int32_t v) {
 }
 
 // A long row (rare) enters the multi-workgroup queue: a slot, and one work
-// item per kHubChunk entries.
-__device__ __forceinline__ void push_long(const JpQ &Q, int set, int32_t v, const int64_t *off) {
-    int32_t slot = atomicAdd(&Q.cnt[cidx(set, 2)], 1);
-    Q.q[set][2][slot] = v;
-    int32_t nc = (int32_t)((off[v + 1] - off[v] + kHubChunk - 1) / kHubChunk);
-    int32_t c0 = atomicAdd(&Q.cnt[cidx(set, 3)], nc);
-    for (int32_t c = 0; c < nc; ++c) Q.cq[set][c0 + c] = ((int64_t)slot << 32) | c;
+// item per kHubChunk entries, written by the active lanes of the wavefront
+// (the short-row tier leaves the lanes of groups past the frontier's end
+// inactive).  hv, e0 and e1 are uniform over the active lanes.
+__device__ __forceinline__ void push_long(const JpQ &Q, int set, int32_t hv, int64_t e0, int64_t e1) {
+    const int32_t nc = (int32_t)((e1 - e0 + kHubChunk - 1) / kHubChunk);
+    const uint64_t act = __ballot(1);
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int lane = lane_id();
+    const int32_t rank = (int32_t)__popcll(act & ((lane == 0) ? 0ULL : (~0ULL >> (64 - lane))));
+    const int32_t nact = (int32_t)__popcll(act);
+    int32_t slot = 0, c0 = 0;
+    if (lane == leader) {
+        slot = atomicAdd(&Q.cnt[cidx(set, 2)], 1);
+        c0 = atomicAdd(&Q.cnt[cidx(set, 3)], nc);
+    }
+    slot = __shfl(slot, leader);
+    c0 = __shfl(c0, leader);
+    for (int32_t c = rank; c < nc; c += nact) {
+        const int64_t a = e0 + (int64_t)c * kHubChunk;
+        Q.cq[set][c0 + c] = HubItem{a, a + kHubChunk < e1 ? a + kHubChunk : e1, hv, slot, nc, 0};
+    }
 }
 
-// Queue pushes of a wavefront: each active lane offers v[j] where want[j].
-// All of the wavefront's pushes of one queue kind are ranked by ballots and
-// take their slots with a single counter atomic (the early rounds push
-// millions of nodes, and per-push atomics on the two counters would
-// serialise).  Order within a frontier does not matter: it is an independent
-// set.  Call with every lane of the loop iteration active.
+// Queue pushes of a wavefront: each lane offers v[j] to queue kind[j] (3: no
+// push).  All of the wavefront's pushes of one short-row queue kind are ranked
+// by ballots and take their slots with a single counter atomic (the early
+// rounds push millions of nodes, and per-push atomics on the two counters would
+// serialise); long rows are pushed one at a time by all active lanes.  Order
+// within a frontier does not matter: it is an independent set.  Call with
+// every lane of the loop iteration active (lanes that left the loop may be
+// inactive).
 template <int NV>
-__device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (&v)[NV], const bool (&want)[NV],
+__device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (&v)[NV], const int (&kind)[NV],
                                           const int64_t *off) {
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ULL : (~0ULL >> (64 - lane));
-    int kind[NV];
     int32_t rank[NV];
     int32_t tot0 = 0, tot1 = 0;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        kind[j] = want[j] ? row_kind(off, v[j]) : 3;
         const uint64_t m0 = __ballot(kind[j] == 0), m1 = __ballot(kind[j] == 1);
+        uint64_t m2 = __ballot(kind[j] == 2);
         rank[j] = kind[j] == 0 ? tot0 + (int32_t)__popcll(m0 & lt) : tot1 + (int32_t)__popcll(m1 & lt);
         tot0 += (int32_t)__popcll(m0);
         tot1 += (int32_t)__popcll(m1);
-        if (kind[j] == 2) push_long(Q, set, v[j], off);
+        while (m2) {
+            const int l = __ffsll((unsigned long long)m2) - 1;
+            m2 &= m2 - 1;
+            const int32_t hv = __shfl(v[j], l);
+            push_long(Q, set, hv, off[hv], off[hv + 1]);
+        }
     }
     const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
     int32_t b0 = 0, b1 = 0;
@@ -170,12 +199,25 @@ __device__ __forceinline__ void wave_push(const JpQ &Q, int set, const int32_t (
     }
 }
 
-__global__ void k_jp_seed(GraphView g, const int32_t *pending, int32_t *colour, JpQ Q) {
+// Releases v (a lower-priority neighbour of a node coloured this round): the
+// queue kind it joins when its count reaches zero, else 3
+__device__ __forceinline__ int release(uint64_t *pending, int32_t v) {
+    const uint64_t old = atomicSub((unsigned long long *)&pending[v], 1ULL);
+    return (uint32_t)old == 1u ? (int)(old >> 32) : 3;
+}
+
+__global__ void k_jp_seed(GraphView g, uint64_t *pending, int32_t *colour, JpQ Q) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int kind[1] = {3};
+    if (u < g.n) {
+        colour[u] = -1;
+        const int kd = row_kind(g.off, (int32_t)u);
+        const uint64_t p = pending[u];
+        if (p == 0) kind[0] = kd;
+        else pending[u] = p | ((uint64_t)kd << 32);
+    }
     const int32_t v[1] = {(int32_t)(u < g.n ? u : 0)};
-    const bool want[1] = {u < g.n && pending[u] == 0};
-    if (u < g.n) colour[u] = -1;
-    wave_push<1>(Q, 0, v, want, g.off);
+    wave_push<1>(Q, 0, v, kind, g.off);
 }
 
 // smallest colour >= base not set in an LDS window bitmap, or -1 (wave-wide)
@@ -265,7 +307,7 @@ __device__ __forceinline__ TierSplit tier_split(int64_t ns, int64_t nm, int64_t 
 // single-workgroup tail 0, 1 (its workgroup runs the three tiers in turn).
 template <int NT>
 __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed, int32_t level, int32_t r,
-                                              int32_t *colour, int32_t *pending, const JpQ &Q, int64_t bid,
+                                              int32_t *colour, uint64_t *pending, const JpQ &Q, int64_t bid,
                                               int64_t nblk) {
     __shared__ uint32_t wbm[NT / kWave][kWinWords];
     __shared__ uint32_t bbm[kWinWords];
@@ -306,10 +348,10 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
         for (int d = 1; d < 8; d <<= 1) used |= __shfl_xor(used, d);
         int32_t cu = __builtin_ctzll(~used);
         if (sub == 0) colour[u] = cu;
-        bool rel[4];
+        int kd[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) rel[j] = (v[j] != u && !hi[j]) && atomicSub(&pending[v[j]], 1) == 1;
-        wave_push<4>(Q, nxt, v, rel, g.off);
+        for (int j = 0; j < 4; ++j) kd[j] = (v[j] != u && !hi[j]) ? release(pending, v[j]) : 3;
+        wave_push<4>(Q, nxt, v, kd, g.off);
     }
     // one wavefront per node: a row of up to kWaveRow entries is held in
     // registers (kWaveRow / 64 per lane), its colours gathered in one batch and
@@ -350,11 +392,10 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
             wave_sync();
         }
         if (lane_id() == 0) colour[u] = f;
-        bool rel[kPer];
+        int kd[kPer];
 #pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            rel[j] = (v[j] != u && !((hi >> j) & 1u)) && atomicSub(&pending[v[j]], 1) == 1;
-        wave_push<kPer>(Q, nxt, v, rel, g.off);
+        for (int j = 0; j < kPer; ++j) kd[j] = (v[j] != u && !((hi >> j) & 1u)) ? release(pending, v[j]) : 3;
+        wave_push<kPer>(Q, nxt, v, kd, g.off);
     }
     // several workgroups per node: each work item is kHubChunk entries of one
     // long row; its colours go into an LDS bitmap that is OR-ed into the row's
@@ -368,20 +409,18 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
     const int64_t b2 = bid - ts.first[2];
     const bool in2 = b2 >= 0 && b2 < ts.count[2];  // workgroup-uniform: the loop holds barriers
     for (int64_t it = in2 ? b2 : nc; it < nc; it += ts.count[2]) {
-        const int64_t item = Q.cq[set][it];
-        const int32_t j = (int32_t)(item >> 32);
-        const int64_t k = item & 0xffffffffLL;
-        int32_t u = Q.q[set][2][j];
+        const HubItem item = Q.cq[set][it];
+        const int32_t j = item.slot, u = item.u;
         const int64_t bu = node_base(g, u);
         const int32_t lu = node_level(g, level, u);
         uint64_t hu = prio_hash(seed, lu, u - bu);
-        const int64_t c0 = g.off[u] + k * kHubChunk, e1 = g.off[u + 1];
-        const int64_t c1 = c0 + kHubChunk < e1 ? c0 + kHubChunk : e1;
+        const int64_t c0 = item.c0, c1 = item.c1;
         for (int i = threadIdx.x; i < kWinWords; i += NT) bbm[i] = 0;
         __syncthreads();
         constexpr int kQ = (int)(kHubChunk / NT) > 0 ? (int)(kHubChunk / NT) : 1;
         int32_t v[kQ], c[kQ];
-        bool hi[kQ], rel[kQ];
+        bool hi[kQ];
+        int kd[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             int64_t e = c0 + q * NT + threadIdx.x;
@@ -393,12 +432,12 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             c[q] = hi[q] ? colour[v[q]] : kWin;
-            rel[q] = (v[q] != u && !hi[q]) && atomicSub(&pending[v[q]], 1) == 1;
+            kd[q] = (v[q] != u && !hi[q]) ? release(pending, v[q]) : 3;
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q)
             if (c[q] < kWin) atomicOr(&bbm[c[q] >> 5], 1u << (c[q] & 31));
-        wave_push<kQ>(Q, nxt, v, rel, g.off);
+        wave_push<kQ>(Q, nxt, v, kd, g.off);
         __syncthreads();
         // the bitmap words change only through device atomics, which every XCD
         // sees; each OR returns (and its result is consumed) before the barrier,
@@ -410,8 +449,7 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
         or_sink[threadIdx.x] = seen;
         __syncthreads();
         if (threadIdx.x == 0) {
-            const int32_t nch = (int32_t)((e1 - g.off[u] + kHubChunk - 1) / kHubChunk);
-            last_chunk = atomicAdd(&Q.done[j], 1) == nch - 1 ? 1 : 0;
+            last_chunk = atomicAdd(&Q.done[j], 1) == item.nch - 1 ? 1 : 0;
         }
         __syncthreads();
         if (last_chunk && threadIdx.x < kWave) {  // workgroup-uniform flag; the first wavefront
@@ -432,7 +470,7 @@ __device__ __forceinline__ void jp_round_body(const GraphView &g, uint64_t seed,
 }
 
 __global__ __launch_bounds__(kCT) void k_jp_round(GraphView g, uint64_t seed, int32_t level, int32_t r,
-                                                  int32_t *colour, int32_t *pending, JpQ Q) {
+                                                  int32_t *colour, uint64_t *pending, JpQ Q) {
     jp_round_body<kCT>(g, seed, level, r, colour, pending, Q, blockIdx.x, gridDim.x);
 }
 
@@ -457,7 +495,7 @@ __device__ __forceinline__ void tail_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 __global__ __launch_bounds__(kTailThreads) void k_jp_tail(GraphView g, uint64_t seed, int32_t level, int32_t r0,
-                                                          int32_t r_end, int32_t *colour, int32_t *pending, JpQ Q) {
+                                                          int32_t r_end, int32_t *colour, uint64_t *pending, JpQ Q) {
     int32_t r = r0;
     tail_barrier();
     for (; r < r_end; ++r) {
@@ -541,21 +579,21 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     uint64_t nhub_u = 0;
     std::memcpy(&nhub_u, host_counters, 8);
     int64_t nhub = (int64_t)nhub_u;
-    // pending counts, 9 queues, counters, hub bitmaps
+    // pending counts, 6 node queues, counters, hub bitmaps, 3 item queues
     // work items of long rows in one set: at most nnz / kHubChunk + nhub
     const int64_t ncap = g.nnz / kHubChunk + nhub + 1;
     const size_t nslot = (size_t)(nhub > 0 ? nhub : 1);
-    scr.reserve(align_up(n * 4) * 10 + align_up(kCntWords * sizeof(int32_t)) + align_up(nslot * kWinWords * 4) +
-                align_up(nslot * 4) + 3 * align_up(ncap * 8));
-    int32_t *pending = (int32_t *)scr.get(n * 4);
+    scr.reserve(align_up(n * 8) + align_up(n * 4) * 6 + align_up(kCntWords * sizeof(int32_t)) +
+                align_up(nslot * kWinWords * 4) + align_up(nslot * 4) + 3 * align_up(ncap * sizeof(HubItem)));
+    uint64_t *pending = (uint64_t *)scr.get(n * 8);
     JpQ Q;
     for (int s = 0; s < 3; ++s)
-        for (int k = 0; k < 3; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
+        for (int k = 0; k < 2; ++k) Q.q[s][k] = (int32_t *)scr.get(n * 4);
     Q.cnt = (int32_t *)scr.get(kCntWords * sizeof(int32_t));
     Q.bitmap = (uint32_t *)scr.get(nslot * kWinWords * 4);
     Q.done = (int32_t *)scr.get(nslot * 4);
-    for (int s = 0; s < 3; ++s) Q.cq[s] = (int64_t *)scr.get(ncap * 8);
-    HIPCHK(hipMemsetAsync(pending, 0, n * 4, st));
+    for (int s = 0; s < 3; ++s) Q.cq[s] = (HubItem *)scr.get(ncap * sizeof(HubItem));
+    HIPCHK(hipMemsetAsync(pending, 0, n * 8, st));
     HIPCHK(hipMemsetAsync(Q.cnt, 0, kCntWords * sizeof(int32_t), st));
     HIPCHK(hipMemsetAsync(Q.bitmap, 0, nslot * kWinWords * 4, st));
     HIPCHK(hipMemsetAsync(Q.done, 0, nslot * 4, st));
