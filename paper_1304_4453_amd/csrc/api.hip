@@ -223,7 +223,7 @@ struct plm_ctx {
     HubPartPlan *pplan = nullptr;
     HubAggPlan *aplan = nullptr;
     HubRedPlan *rplan = nullptr;
-    int64_t *ins_abs = nullptr, *agg_abs = nullptr;
+    int64_t *ins_abs = nullptr, *agg_abs = nullptr, *red_abs = nullptr;
 
     // label propagation (Algorithm 1): active flag of each node; lp_mode turns
     // the class steps into label-propagation steps with tie keys of lp_seed
@@ -281,6 +281,7 @@ struct plm_ctx {
         dev_free(bkt); dev_free(part); dev_free(hub_u); dev_free(ins_hub); dev_free(agg_hub); dev_free(sgl_hub);
         dev_free(red_hub); dev_free(hub_skip); dev_free(hub_clk);
         dev_free(splan); dev_free(pplan); dev_free(aplan); dev_free(rplan); dev_free(ins_abs); dev_free(agg_abs);
+        dev_free(red_abs);
         cap_hubs = cap_stg = cap_bkt = cap_ins = cap_agg = cap_hubu = cap_ihub = cap_ahub = cap_shub = cap_rhub = 0;
     }
 
@@ -382,9 +383,10 @@ struct plm_ctx {
         if (hubs > cap_hubs) {
             dev_free(hub_pos); dev_free(nchunk); dev_free(pbits); dev_free(ins_first); dev_free(agg_first);
             dev_free(stg_off); dev_free(bkt_off); dev_free(hub_base); dev_free(hub_skip); dev_free(hub_clk);
-            dev_free(ins_abs); dev_free(agg_abs);
+            dev_free(ins_abs); dev_free(agg_abs); dev_free(red_abs);
             ins_abs = dev_alloc<int64_t>(hubs);
             agg_abs = dev_alloc<int64_t>(hubs);
+            red_abs = dev_alloc<int64_t>(hubs);
             hub_base = dev_alloc<int64_t>(hubs);
             hub_skip = dev_alloc<int32_t>(hubs);
             hub_clk = dev_alloc<uint64_t>(hubs);
@@ -495,7 +497,8 @@ struct plm_ctx {
         std::vector<int32_t> hpos(H > 0 ? H : 1), hch(H > 0 ? H : 1, 0), hpb(H > 0 ? H : 1, 0), shub, rhub, ihub,
             ahub;
         std::vector<int64_t> hins(H > 0 ? H : 1, 0), hagg(H > 0 ? H : 1, 0), hstg(H > 0 ? H : 1, 0),
-            hbk(H > 0 ? H : 1, 0), hins_abs(H > 0 ? H : 1, 0), hagg_abs(H > 0 ? H : 1, 0);
+            hbk(H > 0 ? H : 1, 0), hins_abs(H > 0 ? H : 1, 0), hagg_abs(H > 0 ? H : 1, 0),
+            hred_abs(H > 0 ? H : 1, 0);
         int64_t max_stg = 0, max_bk = 0, max_ins = 0, max_agg = 0, hg = 0;
         sgl_nodes = sgl_entries = 0;
         for (int32_t c = 0; c < ncol; ++c) {
@@ -522,7 +525,8 @@ struct plm_ctx {
                     sgl_entries += d;
                     continue;
                 }
-                rhub.push_back((int32_t)hg);
+                hred_abs[hg] = (int64_t)rhub.size();
+                rhub.insert(rhub.end(), (size_t)cdiv(d, kHubMarkSlice), (int32_t)hg);
                 int64_t ch = cdiv(d, kHubInsChunk);
                 int pb = ceil_log2((uint64_t)cdiv(d, kHubBucketTarget));
                 if (pb > kHubMaxPBits) pb = kHubMaxPBits;
@@ -566,7 +570,8 @@ struct plm_ctx {
             if (!rhub.empty()) HIPCHK(hipMemcpyAsync(red_hub, rhub.data(), rhub.size() * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(ins_abs, hins_abs.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(agg_abs, hagg_abs.data(), H * 8, hipMemcpyHostToDevice, st));
-            launch_hub_plans(g, hub_arrays(), ins_abs, agg_abs, (int64_t)shub.size(), (int64_t)ihub.size(),
+            HIPCHK(hipMemcpyAsync(red_abs, hred_abs.data(), H * 8, hipMemcpyHostToDevice, st));
+            launch_hub_plans(g, hub_arrays(), ins_abs, agg_abs, red_abs, (int64_t)shub.size(), (int64_t)ihub.size(),
                              (int64_t)ahub.size(), (int64_t)rhub.size(), splan, pplan, aplan, rplan, st);
             HIPCHK(hipStreamSynchronize(st));
         }

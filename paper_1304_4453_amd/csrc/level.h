@@ -97,7 +97,8 @@ struct ClassRange {
     int64_t hub_first = 0, hub_count = 0;
     int64_t ins_blocks = 0, agg_blocks = 0;
     // first entries of this class in the level's per-workgroup hub lists:
-    // single-workgroup hubs, partitioned hubs (reduce), their chunk and bucket
+    // single-workgroup hubs, reduce workgroups of the partitioned hubs (one
+    // per kHubMarkSlice entries of each row), their chunk and bucket
     // workgroups
     int64_t sgl_base = 0, sgl_count = 0, red_base = 0, red_count = 0, ins_base = 0, agg_base = 0;
 };
@@ -122,10 +123,11 @@ struct HubAggPlan {    // bucket workgroup of a partitioned hub
     int64_t wd;        // first chunk workgroup of the hub (class-relative): its w(u, D) shares
     int32_t u, hg, p, nch;
 };
-struct HubRedPlan {    // reduce of a partitioned hub (in the apply launch)
+struct HubRedPlan {    // reduce of a partitioned hub (in the apply launch), one per slice of its row
     int64_t agg;       // first bucket workgroup of the hub (class-relative)
     int64_t wd;        // first chunk workgroup of the hub (class-relative)
-    int32_t u, hg, nagg, nch;
+    int64_t s0, s1;    // the slice of u's row this workgroup marks (or activates) when u moves
+    int32_t u, hg, nagg, nch, k, pad;  // k: slice (0 applies the move)
 };
 
 struct HubArrays {
@@ -161,6 +163,7 @@ struct HubArrays {
 constexpr int64_t kHubInsChunk = 1024;  // entries per hub chunk workgroup
 constexpr int kHubMaxPBits = 12;        // at most 4096 buckets per hub
 constexpr int64_t kHubBucketTarget = 1024;  // entries per hash bucket (one agg workgroup each)
+constexpr int64_t kHubMarkSlice = 16384;  // row entries per reduce workgroup of a partitioned hub
 constexpr int64_t kSingleMaxRow = 12288;  // hubs up to this row length (and vol < 2^31) take one workgroup
 
 // ev (may be null): per kernel group (lane, wavefront, workgroup, one-workgroup
@@ -181,10 +184,10 @@ void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, 
 // positions [begin, begin + count)
 // rec[i] = (row start, row length, node) of class_nodes[i], i < count
 void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, hipStream_t st);
-// fills the launch plans of the level-wide hub lists (ins_abs / agg_abs: first
-// list index of each hub's chunk / bucket workgroups)
+// fills the launch plans of the level-wide hub lists (ins_abs / agg_abs /
+// red_abs: first list index of each hub's chunk / bucket / reduce workgroups)
 void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
-                      int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
+                      const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
                       HubAggPlan *ap, HubRedPlan *rp, hipStream_t st);
 void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
                         int64_t count, int64_t *deg_out, int32_t *u_out, hipStream_t st);

@@ -1233,10 +1233,14 @@ __device__ __forceinline__ int64_t apply_move(const MoveState &ms, int32_t u, in
     return 1;
 }
 
-// A partitioned hub's reduce: one workgroup combines the bucket partials and
-// the w(u, D) shares (written by earlier launches), decides the move like any
-// other node, and applies it.  vol(D \ u) comes from the bucket launch, taken
-// before any move of the class applied.
+// A partitioned hub's reduce: a workgroup per slice of the hub's row combines
+// the bucket partials and the w(u, D) shares (written by earlier launches) and
+// decides the move like any other node (every slice reaches the same decision
+// from the same words); slice 0 applies it, and when the hub moves each slice
+// marks (or, in label propagation, activates) the neighbours in its part of
+// the row, so that a hub of millions of entries is not marked by one
+// workgroup.  vol(D \ u) comes from the bucket launch, taken before any move of
+// the class applied.
 template <bool LP>
 __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha,
                                                  const HubRedPlan &pl) {
@@ -1274,28 +1278,30 @@ __device__ __forceinline__ void hub_reduce_apply(const GraphView &g, const MoveS
         i128 K = (i128)node_S(ms, u) * ms.gq * (i128)wD - (i128)vu * ms.gp * (i128)base +
                  (LP ? (i128)kLpTieMax : (i128)0);
         dec = (bx != kNone && bs > K) ? bx : -1;
-        if (dec >= 0) atomicAdd(ms.moves_dev, (unsigned long long)apply_move(ms, u, dec));
-        if (sk) {
-            if (dec >= 0) {
-                atomicAdd(&ms.sctl[1], (unsigned long long)(2 * vu));
-            } else {
-                int64_t s_, k_;
-                slack_of<i128>(K, K - (i128)slack, s_, k_);  // slack = the smallest bucket slack
-                record_stay(ms, Settle{true, ha.hub_clk[hg]}, u, s_, k_);
+        if (pl.k == 0) {
+            if (dec >= 0) atomicAdd(ms.moves_dev, (unsigned long long)apply_move(ms, u, dec));
+            if (sk) {
+                if (dec >= 0) {
+                    atomicAdd(&ms.sctl[1], (unsigned long long)(2 * vu));
+                } else {
+                    int64_t s_, k_;
+                    slack_of<i128>(K, K - (i128)slack, s_, k_);  // slack = the smallest bucket slack
+                    record_stay(ms, Settle{true, ha.hub_clk[hg]}, u, s_, k_);
+                }
             }
         }
     }
     if (LP) {
         __syncthreads();
-        if (dec >= 0) lp_activate(g, ms.active, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads);
-        else if (threadIdx.x == 0) ms.active[u] = 0;
+        if (dec >= 0) lp_activate(g, ms.active, u, pl.s0, pl.s1, threadIdx.x, kHubThreads);
+        else if (pl.k == 0 && threadIdx.x == 0) ms.active[u] = 0;
     } else if (sk) {
         __syncthreads();
         if (dec >= 0) {
             switch (g.wkind) {
-                case 0: mark_moved<0>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
-                case 1: mark_moved<1>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
-                default: mark_moved<2>(g, ms, u, g.off[u], g.off[u + 1], threadIdx.x, kHubThreads); break;
+                case 0: mark_moved<0>(g, ms, u, pl.s0, pl.s1, threadIdx.x, kHubThreads); break;
+                case 1: mark_moved<1>(g, ms, u, pl.s0, pl.s1, threadIdx.x, kHubThreads); break;
+                default: mark_moved<2>(g, ms, u, pl.s0, pl.s1, threadIdx.x, kHubThreads); break;
             }
         }
     }
@@ -1380,9 +1386,9 @@ void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t co
 }
 
 // launch plans of the level-wide hub lists: one thread per workgroup record
-__global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, const int64_t *agg_abs, int64_t n_sgl,
-                            int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
-                            HubAggPlan *ap, HubRedPlan *rp) {
+__global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, const int64_t *agg_abs,
+                            const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red,
+                            HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap, HubRedPlan *rp) {
     const int64_t tot = n_sgl + n_ins + n_agg + n_red;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         if (i < n_sgl) {
@@ -1409,19 +1415,22 @@ __global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, c
             continue;
         }
         j -= n_agg;
-        const int32_t hg = ha.red_hub[j];
-        rp[j] = HubRedPlan{ha.agg_first[hg], ha.ins_first[hg], ha.hub_u[hg], hg, 1 << ha.pbits[hg], ha.nchunk[hg]};
+        const int32_t hg = ha.red_hub[j], u = ha.hub_u[hg];
+        const int64_t k = j - red_abs[hg], e1 = g.off[u + 1];
+        const int64_t s0 = g.off[u] + k * kHubMarkSlice, s1 = s0 + kHubMarkSlice < e1 ? s0 + kHubMarkSlice : e1;
+        rp[j] = HubRedPlan{ha.agg_first[hg], ha.ins_first[hg], s0, s1, u, hg, 1 << ha.pbits[hg], ha.nchunk[hg],
+                           (int32_t)k, 0};
     }
 }
 
 void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
-                      int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
-                      HubAggPlan *ap, HubRedPlan *rp, hipStream_t st) {
+                      const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red,
+                      HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap, HubRedPlan *rp, hipStream_t st) {
     const int64_t tot = n_sgl + n_ins + n_agg + n_red;
     if (tot <= 0) return;
     const int64_t blocks = cdiv(tot, 256);
     hipLaunchKernelGGL(k_hub_plans, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, g, ha, ins_abs,
-                       agg_abs, n_sgl, n_ins, n_agg, n_red, sp, pp, ap, rp);
+                       agg_abs, red_abs, n_sgl, n_ins, n_agg, n_red, sp, pp, ap, rp);
     HIPCHK(hipGetLastError());
 }
 
