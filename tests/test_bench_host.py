@@ -35,14 +35,17 @@ def test_traffic_follows_the_source_hash(tmp_path):
     src = open(os.path.join(ROOT, "paper_1304_4453_amd", "csrc", "move.hip"), "rb").read()
     matches = blob["move_hip_sha256"] == hashlib.sha256(src).hexdigest()
     b = _bench_at(_tree(tmp_path))
-    tr = b.counter_traffic("k_hub_part+k_hub_agg")
+    level = blob.get("level", 0)
+    tr = b.counter_traffic("k_hub_part+k_hub_agg", level)
     if matches:
         k = [k for k in blob["kernels"] if k["kernel"] == "k_hub_part+k_hub_agg"][0]
         assert tr is not None and tr["bytes_per_launch"] == k["traffic_bytes_per_launch"]
         assert tr["bytes_per_launch"] >= tr["algorithmic_bytes_per_launch_same_sweep"]
     else:
         assert tr is None
-    assert b.counter_traffic("no_such_kernel") is None
+    # counters of one level are not reported for another
+    assert b.counter_traffic("k_hub_part+k_hub_agg", level + 1) is None
+    assert b.counter_traffic("no_such_kernel", level) is None
 
 
 def test_traffic_is_null_once_the_source_changes(tmp_path):
