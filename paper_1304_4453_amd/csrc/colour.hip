@@ -604,30 +604,76 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     HIPCHK(hipGetLastError());
     // grid rounds while frontiers are large, the one-workgroup tail once the
     // frontier the host last saw is small (the seed frontier is known without
-    // a copy only for its size, so the first check decides)
-    int32_t r = 0;
+    // a copy only for its size, so the first check decides).  Grid batches are
+    // pipelined: the counters after batch k (copied into one of two host
+    // buffers) are examined while batch k + 1 runs, so the device does not
+    // idle while the host decides; rounds launched past an empty frontier
+    // find nothing to do.  A tail launch is waited for, since the launch after
+    // it needs the round it reached.
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    for (hipEvent_t &x : ev.e) HIPCHK(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    int32_t *hcb[2] = {host_counters, host_counters + kCntWords};
+    auto frontier = [&](const int32_t *c, int32_t rr, int32_t &ns, int32_t &nm, int32_t &nh, int32_t &nc) {
+        const int s = rr % 3;
+        ns = c[cidx(s, 0)]; nm = c[cidx(s, 1)]; nh = c[cidx(s, 2)]; nc = c[cidx(s, 3)];
+        return ns == 0 && nm == 0 && nh == 0;
+    };
+    int32_t r = 0, r_done = 0, r_prev = 0;
+    int prev = -1;  // host buffer of the grid batch not yet examined
     bool tail = false;
     for (;;) {
+        int32_t ns = 0, nm = 0, nh = 0, nc = 0;
         if (tail) {
             const int32_t r_end = r < INT32_MAX - kTailRounds ? r + kTailRounds : INT32_MAX;
             hipLaunchKernelGGL(k_jp_tail, dim3(1), dim3(kTailThreads), 0, st, g, seed, level, r, r_end, colour,
                                pending, Q);
-        } else {
-            for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
-                hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour,
-                                   pending, Q);
-            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(hcb[0], Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            r = hcb[0][kCntTail];
+            if (frontier(hcb[0], r, ns, nm, nh, nc)) { r_done = r; break; }
+            tail = use_tail && tail_passes(ns, nm, nc) <= kTailEnter;
+            continue;
+        }
+        for (int i = 0; i < kRoundsPerCheck; ++i, ++r) {
+            hipLaunchKernelGGL(k_jp_round, dim3(kRoundGrid), dim3(kCT), 0, st, g, seed, level, r, colour,
+                               pending, Q);
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (tail) r = host_counters[kCntTail];
-        int s = r % 3;
-        const int32_t ns = host_counters[cidx(s, 0)], nm = host_counters[cidx(s, 1)],
-                      nh = host_counters[cidx(s, 2)], nc = host_counters[cidx(s, 3)];
-        if (ns == 0 && nm == 0 && nh == 0) break;
-        if (r > n + 2 * kRoundsPerCheck) throw Error{-6, "internal: colouring did not converge"};
-        tail = use_tail && tail_passes(ns, nm, nc) <= kTailEnter;
+        const int cur = prev == 0 ? 1 : 0;
+        HIPCHK(hipMemcpyAsync(hcb[cur], Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ev.e[cur], st));
+        if (prev < 0) {  // nothing to examine yet: launch the next batch first
+            prev = cur;
+            r_prev = r;
+            continue;
+        }
+        HIPCHK(hipEventSynchronize(ev.e[prev]));
+        if (frontier(hcb[prev], r_prev, ns, nm, nh, nc)) {
+            r_done = r_prev;
+            HIPCHK(hipStreamSynchronize(st));
+            break;
+        }
+        if (r_prev > n + 2 * kRoundsPerCheck) throw Error{-6, "internal: colouring did not converge"};
+        if (use_tail && tail_passes(ns, nm, nc) <= kTailEnter) {
+            // the batch just launched has run on: decide from its counters
+            HIPCHK(hipEventSynchronize(ev.e[cur]));
+            prev = -1;
+            if (frontier(hcb[cur], r, ns, nm, nh, nc)) {
+                r_done = r;
+                break;
+            }
+            tail = tail_passes(ns, nm, nc) <= kTailEnter;
+            continue;
+        }
+        prev = cur;
+        r_prev = r;
     }
     hipLaunchKernelGGL(k_colour_stats, dim3((unsigned)(hb < kCountGrid ? hb : kCountGrid)), dim3(kCT), 0, st, colour,
                        n, Q.cnt);
@@ -635,7 +681,7 @@ int32_t build_colouring(const GraphView &g, uint64_t seed, int32_t level, int sc
     HIPCHK(hipMemcpyAsync(host_counters, Q.cnt, kCntWords * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (host_counters[kCntUncoloured] != 0) throw Error{-6, "internal: colouring did not reach every node"};
-    *jp_rounds = r;
+    *jp_rounds = r_done;
     return host_counters[kCntNcol];
 }
 
