@@ -164,6 +164,14 @@ typedef struct {
                               batches then always run on the server's worker threads.
                               0 (default): a batch is fixed when it starts and reports
                               at its end. */
+    int32_t layout;        /* sweep layout of single graphs: the move sweeps read
+                              neighbour communities and community volumes through
+                              copies ordered by descending degree (built once per
+                              level: 4 bytes per entry and 20 per node), ranking and
+                              reporting candidates by their own ids, so results are
+                              unchanged.  0 (default): graphs of more than 2^27
+                              entries; 1: every single graph; -1: never.  Batches
+                              never. */
 } plm_options;
 
 /* Fills *opt with the defaults above. */

@@ -44,6 +44,8 @@ constexpr double kReplanFraction = 0.7;
 constexpr size_t kEv = 12;
 // settled nodes: a move phase arms after a sweep that moved at most n / this
 constexpr int64_t kSettleDiv = 16;
+// single graphs with more entries take the sweep layout by default (opt.layout = 0)
+constexpr int64_t kLayoutMinEntries = (int64_t)1 << 27;
 // pinned host scratch of a context, in int64 words (the colouring's counter
 // read-back takes 480 int32)
 constexpr size_t kHostWords = 512;
@@ -88,6 +90,8 @@ struct LevelData {
     int32_t *colour_kept = nullptr;
     int32_t ncol_kept = 0;
     bool borrowed = false;  // off/col/w belong to another context (ensemble base runs)
+    // sweep layout of this level (see MoveState), built with its first plan
+    int32_t *sig = nullptr, *ord = nullptr, *colp = nullptr;
 
     GraphView view() const {
         GraphView g;
@@ -100,7 +104,7 @@ struct LevelData {
             off = nullptr; col = nullptr; w = nullptr;
         }
         dev_free(off); dev_free(col); dev_free(w); dev_free(pi); dev_free(gid); dev_free(gbase); dev_free(gshift);
-        dev_free(colour_kept);
+        dev_free(colour_kept); dev_free(sig); dev_free(ord); dev_free(colp);
     }
 };
 
@@ -156,6 +160,11 @@ struct plm_ctx {
     int64_t *vol0 = nullptr, *vol = nullptr, *volC = nullptr;
     int32_t *zeta = nullptr, *colour = nullptr, *class_nodes = nullptr, *move_to = nullptr, *lab = nullptr;
     NodeRec *noderec = nullptr;  // per class position: node and row (with class_nodes)
+    // the sweep layout's copies of zeta and volC (see MoveState), synchronised
+    // from them before a sweep whenever they changed outside the apply
+    int32_t *zetap = nullptr;
+    int64_t *volCp = nullptr;
+    bool layout_dirty = true;
     int64_t *bstart_dev = nullptr;
     int64_t max_vol = 0, wide_lim = 0;
     bool sched = false;
@@ -252,7 +261,7 @@ struct plm_ctx {
     ~plm_ctx() {
         for (auto &l : levels) l.release();
         dev_free(vol0); dev_free(vol); dev_free(volC); dev_free(zeta); dev_free(colour); dev_free(class_nodes);
-        dev_free(noderec); dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
+        dev_free(noderec); dev_free(zetap); dev_free(volCp); dev_free(move_to); dev_free(lab); dev_free(bstart_dev); dev_free(dcnt);
         dev_free(gS0); dev_free(gwl0); dev_free(act); dev_free(gS); dev_free(gwl); dev_free(bflag); dev_free(bout);
         dev_free(bnewid); dev_free(bgath); dev_free(bscan); dev_free(bstatus); dev_free(bkeep); dev_free(bI2);
         dev_free(bsq); dev_free(bsweep); dev_free(bgmoved); dev_free(active); dev_free(snap[0]); dev_free(snap[1]);
@@ -348,6 +357,7 @@ struct plm_ctx {
             throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
         launch_iota(zeta, l.n, st);
         launch_copy_vol(volC, vol, l.n, st);
+        layout_dirty = true;
         sched = false;
         ncol = 0;
         sweeps = 0;
@@ -442,8 +452,35 @@ struct plm_ctx {
     // Class buckets and hub plan of the current colouring.  keep (batched runs,
     // device, one flag per graph of the level, else null): only the nodes of
     // kept graphs enter the buckets.
+    // the sweep layout (see MoveState): large single graphs (opt.layout 0), all
+    // single graphs (1) or none (-1); batches keep their graphs' own ids
+    bool layout_wanted() const {
+        const LevelData &l = levels[cur];
+        return !batch && opt.layout >= 0 && l.n > 0 && (opt.layout == 1 || l.nnz > kLayoutMinEntries);
+    }
+    void ensure_layout() {
+        LevelData &l = L();
+        if (l.sig || !layout_wanted()) return;
+        const GraphView g = l.view();
+        l.sig = dev_alloc<int32_t>(l.n);
+        l.ord = dev_alloc<int32_t>(l.n);
+        l.colp = dev_alloc<int32_t>(l.nnz > 0 ? l.nnz : 1);
+        if (!zetap) {
+            zetap = dev_alloc<int32_t>(n0);
+            volCp = dev_alloc<int64_t>(n0);
+        }
+        scr.reserve(4 * align_up(l.n * 4) + radix_scratch_bytes(l.n));
+        uint32_t *k = (uint32_t *)scr.get(l.n * 4), *ka = (uint32_t *)scr.get(l.n * 4);
+        int32_t *v = (int32_t *)scr.get(l.n * 4), *va = (int32_t *)scr.get(l.n * 4);
+        void *rs = scr.get(radix_scratch_bytes(l.n));
+        build_layout(g, l.sig, l.ord, l.colp, k, v, ka, va, rs, st);
+        HIPCHK(hipStreamSynchronize(st));
+        layout_dirty = true;
+    }
+
     void build_plan(const uint8_t *keep) {
         drop_graph();  // the captured sweep belongs to the previous plan
+        ensure_layout();
         LevelData &l = L();
         GraphView g = l.view();
         int64_t nkeys = (int64_t)ncol * 8 + 1;
@@ -463,7 +500,7 @@ struct plm_ctx {
         // first position of bin b of class c (b = 4: the next class)
         auto bs = [&](int64_t c, int b) { return bstart[8 * c + 2 * b]; };
         active_nodes = l.n > 0 ? bstart[(size_t)ncol * 8] : 0;
-        launch_node_recs(g, class_nodes, active_nodes, noderec, st);
+        launch_node_recs(g, class_nodes, active_nodes, noderec, l.sig, st);
         active_entries = l.nnz - hbuf[8];
         for (int b = 0; b < 4; ++b) {
             bin_entries[b] = hbuf[9 + b];
@@ -571,8 +608,9 @@ struct plm_ctx {
             HIPCHK(hipMemcpyAsync(ins_abs, hins_abs.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(agg_abs, hagg_abs.data(), H * 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(red_abs, hred_abs.data(), H * 8, hipMemcpyHostToDevice, st));
-            launch_hub_plans(g, hub_arrays(), ins_abs, agg_abs, red_abs, (int64_t)shub.size(), (int64_t)ihub.size(),
-                             (int64_t)ahub.size(), (int64_t)rhub.size(), splan, pplan, aplan, rplan, st);
+            launch_hub_plans(g, hub_arrays(), l.sig, ins_abs, agg_abs, red_abs, (int64_t)shub.size(),
+                             (int64_t)ihub.size(), (int64_t)ahub.size(), (int64_t)rhub.size(), splan, pplan, aplan,
+                             rplan, st);
             HIPCHK(hipStreamSynchronize(st));
         }
         sched = true;
@@ -590,6 +628,9 @@ struct plm_ctx {
         MoveState ms;
         ms.zeta = zeta; ms.volC = volC; ms.vol = vol; ms.class_nodes = class_nodes; ms.move_to = move_to;
         ms.rec = noderec;
+        if (L().colp) {
+            ms.colp = L().colp; ms.zetap = zetap; ms.volCp = volCp; ms.sig = L().sig; ms.ord = L().ord;
+        }
         ms.S = S; ms.wide_lim = wide_lim; ms.moves_dev = dcnt; ms.cand_dev = count_cand ? dcnt + 1 : nullptr;
         ms.cand_sgl = count_cand ? dcnt + 13 : nullptr;
         ms.dec_dev = count_cand ? dcnt + 16 : nullptr;
@@ -706,6 +747,10 @@ struct plm_ctx {
     // sweep graph
     int64_t run_classes(int32_t c0, int32_t c1, bool allow_graph = false) {
         if (!sched) build_schedule();
+        if (L().colp && layout_dirty) {  // zeta or volC changed outside the apply
+            sync_layout(L().n, zeta, volC, L().sig, zetap, volCp, st);
+            layout_dirty = false;
+        }
         HIPCHK(hipMemsetAsync(dcnt, 0, 5 * 8, st));
         HIPCHK(hipMemsetAsync(dcnt + 13, 0, 8, st));
         HIPCHK(hipMemsetAsync(dcnt + 16, 0, 10 * 8, st));
@@ -864,6 +909,7 @@ struct plm_ctx {
                     if (rest & 1) {  // the last sweep leaves the state of sweep s - 1
                         HIPCHK(hipMemcpyAsync(zeta, snap[(s - 1) & 1], n * 4, hipMemcpyDeviceToDevice, st));
                         launch_comm_vol(zeta, vol, n, volC, st);
+                        layout_dirty = true;
                         HIPCHK(hipStreamSynchronize(st));
                     }
                     disarm();  // the recorded slacks belong to the other state
@@ -1024,6 +1070,7 @@ struct plm_ctx {
             if (opt.int_mode == PLM_INT_64 && max_vol > wide_lim)
                 throw Error{PLM_E_STATE, "int_mode PLM_INT_64: S * vol(u) reaches 2^62 at this level"};
             launch_comm_vol(zeta, vol, nl, volC, st);
+            layout_dirty = true;
             sched = false;
             sweeps = 0;
             // the colouring this level had on the way down (kept by descend)
@@ -1053,6 +1100,7 @@ struct plm_ctx {
         double t0 = now_ms();
         if (!active) active = dev_alloc<uint8_t>(n0 > 0 ? n0 : 1);
         launch_iota(zeta, l.n, st);
+        layout_dirty = true;
         // nodes without non-loop neighbours are outside the class buckets, so
         // marking every node active is the same as marking those with one
         if (l.n > 0) HIPCHK(hipMemsetAsync(active, 1, l.n, st));
@@ -1554,6 +1602,7 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.agg_tile < 0 || o.agg_tile > 512) { msg = "agg_tile must be 0 or lie in [1, 512]"; return PLM_E_ARG; }
     if (o.settle < -1 || o.settle > 1) { msg = "settle must be -1, 0 or 1"; return PLM_E_ARG; }
     if (o.join < 0) { msg = "join must be >= 0"; return PLM_E_ARG; }
+    if (o.layout < -1 || o.layout > 1) { msg = "layout must be -1, 0 or 1"; return PLM_E_ARG; }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";
@@ -1949,6 +1998,7 @@ int32_t plm_ctx::epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *co
         o.settle = -1;
         o.refine = 0;
         o.hub_stream = 0;  // one stream per base run: the runs are the concurrency
+        o.layout = -1;     // the runs read the input in place: no per-run copies of it
         const LevelData &l0 = levels[0];
         HIPCHK(hipStreamSynchronize(st));
         for (int32_t i = 0; i < b; ++i) {
@@ -1995,6 +2045,7 @@ int32_t plm_ctx::epp(int32_t b, int32_t plp_iters, int32_t *lab_out, int64_t *co
         t_ens += now_ms() - t1;
         t1 = now_ms();
         HIPCHK(hipMemcpyAsync(zeta, grp, n * 4, hipMemcpyDeviceToDevice, st));
+        layout_dirty = true;
         HIPCHK(hipStreamSynchronize(st));
         // the colouring of level 0 for the statistics (the base runs coloured
         // with their own seeds): that of the first base run

@@ -40,6 +40,7 @@ constexpr int64_t kBlockShortRow = 2048;
 struct NodeRec {
     int64_t e0;
     int32_t len, u;
+    int32_t s, pad;  // s: u's index in the sweep layout (u itself without one)
 };
 
 struct MoveState {
@@ -48,6 +49,17 @@ struct MoveState {
     const int64_t *vol;    // node volumes
     const int32_t *class_nodes;
     const NodeRec *rec = nullptr;  // per class position (see NodeRec)
+    // sweep layout (large single graphs; null otherwise): the per-entry
+    // community gathers and the community-volume reads of the decide kernels go
+    // through copies ordered by descending degree, so that the few nodes most
+    // entries point to share cache lines.  sig = a node's index in that order,
+    // ord its inverse; colp[e] = sig[col[e]]; zetap[sig[u]] = sig[zeta[u]];
+    // volCp[sig[c]] = volC[c].  Candidates are ranked, tie-broken and reported
+    // by their original ids (ord), so decisions are those of the graph's own ids.
+    const int32_t *colp = nullptr;
+    int32_t *zetap = nullptr;
+    int64_t *volCp = nullptr;
+    const int32_t *sig = nullptr, *ord = nullptr;
     int32_t *move_to;      // per class position: target community or -1
     int64_t S;
     int64_t wide_lim;      // vol(u) > wide_lim needs 128-bit gains
@@ -110,24 +122,27 @@ struct ClassRange {
 struct HubSglPlan {    // one-workgroup hub
     int64_t e0, e1;    // row of u
     int32_t u, pos;    // node, class position
+    int32_t s, pad;    // u's index in the sweep layout
 };
 struct HubPartPlan {   // chunk workgroup of a partitioned hub
     int64_t c0;        // first entry of the chunk
     int64_t stg;       // staging offset of the chunk (class area)
     int64_t bkt;       // offset of the hub's (bucket, chunk) words (class area)
-    int32_t u, hg, k, len, nch, pb, pos, pad;  // node, hub, chunk, entries, chunks, log2 buckets, class position
+    int32_t u, hg, k, len, nch, pb, pos, s;  // node, hub, chunk, entries, chunks, log2 buckets, class position,
+                                             // u's index in the sweep layout
 };
 struct HubAggPlan {    // bucket workgroup of a partitioned hub
     int64_t bkt;       // offset of this bucket's words, one per chunk (class area)
     int64_t stg;       // staging offset of the hub (class area)
     int64_t wd;        // first chunk workgroup of the hub (class-relative): its w(u, D) shares
     int32_t u, hg, p, nch;
+    int32_t s, pad;    // u's index in the sweep layout
 };
 struct HubRedPlan {    // reduce of a partitioned hub (in the apply launch), one per slice of its row
     int64_t agg;       // first bucket workgroup of the hub (class-relative)
     int64_t wd;        // first chunk workgroup of the hub (class-relative)
     int64_t s0, s1;    // the slice of u's row this workgroup marks (or activates) when u moves
-    int32_t u, hg, nagg, nch, k, pad;  // k: slice (0 applies the move)
+    int32_t u, hg, nagg, nch, k, s;  // k: slice (0 applies the move); s: u's index in the sweep layout
 };
 
 struct HubArrays {
@@ -183,11 +198,20 @@ void launch_apply(const GraphView &g, const MoveState &ms, const HubArrays &ha, 
 // row lengths (negated when vol(u) >= 2^31) and nodes of the hubs at class
 // positions [begin, begin + count)
 // rec[i] = (row start, row length, node) of class_nodes[i], i < count
-void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, hipStream_t st);
+void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec,
+                      const int32_t *sig, hipStream_t st);
+// sweep layout of a level: ord = nodes by descending degree (ties by id),
+// sig its inverse, colp[e] = sig[col[e]] (keys/vals/alt: 4 n-word scratch
+// arrays, rs: radix scratch for n items)
+void build_layout(const GraphView &g, int32_t *sig, int32_t *ord, int32_t *colp, uint32_t *keys, int32_t *vals,
+                  uint32_t *keys_alt, int32_t *vals_alt, void *rs, hipStream_t st);
+// zetap[sig[u]] = sig[zeta[u]], volCp[sig[u]] = volC[u] for u < n
+void sync_layout(int64_t n, const int32_t *zeta, const int64_t *volC, const int32_t *sig, int32_t *zetap,
+                 int64_t *volCp, hipStream_t st);
 // fills the launch plans of the level-wide hub lists (ins_abs / agg_abs /
 // red_abs: first list index of each hub's chunk / bucket / reduce workgroups)
-void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
-                      const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
+void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int32_t *sig, const int64_t *ins_abs,
+                      const int64_t *agg_abs, const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp,
                       HubAggPlan *ap, HubRedPlan *rp, hipStream_t st);
 void launch_hub_degrees(const GraphView &g, const int32_t *class_nodes, const int64_t *vol, int64_t begin,
                         int64_t count, int64_t *deg_out, int32_t *u_out, hipStream_t st);

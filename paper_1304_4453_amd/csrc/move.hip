@@ -202,6 +202,21 @@ __device__ __forceinline__ int64_t wave_max_i64(int64_t x) {
 __device__ __forceinline__ uint32_t lp_tie(uint64_t hv, int32_t x) {
     return (uint32_t)(splitmix64(hv ^ (uint64_t)(uint32_t)x) >> 32);
 }
+
+// The arrays the per-entry community gathers of a sweep go through: the
+// level's sweep layout when it has one (see MoveState), else the graph's own
+// ids.  Community indices of the layout are turned back into original ids
+// (orig_id) wherever candidates are compared or reported.
+struct GatherIds {
+    const int32_t *col;   // neighbour index of each entry
+    const int32_t *zeta;  // community index of each neighbour index
+    const int64_t *volC;  // volume of each community index
+    const int32_t *ord;   // original id of a community index (null: the index itself)
+};
+__device__ __forceinline__ GatherIds gather_ids(const GraphView &g, const MoveState &ms) {
+    return ms.colp ? GatherIds{ms.colp, ms.zetap, ms.volCp, ms.ord} : GatherIds{g.col, ms.zeta, ms.volC, nullptr};
+}
+__device__ __forceinline__ int32_t orig_id(const int32_t *ord, int32_t x) { return ord ? ord[x] : x; }
 constexpr uint32_t kLpTieMax = 0xFFFFFFFFu;
 
 // label propagation: u moved, so its non-loop neighbours become active
@@ -249,8 +264,8 @@ constexpr int kLaneMax = 16;
 // *slack: when u stays, a lower bound of minus its best gain (see slack_of)
 template <int WK, bool LP, typename G>
 __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const int64_t (&W)[kLaneMax], int32_t D,
-                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC, uint64_t hv,
-                                             int64_t *slack, int64_t *kslack) {
+                                             int64_t wD, G vu, int64_t base, G S, const int64_t *volC,
+                                             const int32_t *ord, uint64_t hv, int64_t *slack, int64_t *kslack) {
     G bg = 0, mg = neg_inf<G>();
     int32_t bx = kNone;
     const G vb = (G)vu * (G)base;
@@ -261,13 +276,14 @@ __device__ __forceinline__ int32_t lane_pick(const int32_t (&X)[kLaneMax], const
         if (X[j] >= 0 && X[j] != D) {
             const G bound = (G)S * (G)(W[j] - wD) + vb;
             if (bound > 0) {
+                const int32_t ox = orig_id(ord, X[j]);
                 G g;
                 if constexpr (LP)
-                    g = (G)S * (G)(W[j] - wD) + (G)lp_tie(hv, X[j]) - (G)kLpTieMax;
+                    g = (G)S * (G)(W[j] - wD) + (G)lp_tie(hv, ox) - (G)kLpTieMax;
                 else
                     g = (G)S * (G)(W[j] - wD) - (G)vu * (G)(volC[X[j]] - base);
                 if (g > mg) mg = g;
-                if (g > 0 && (g > bg || (g == bg && X[j] < bx))) { bg = g; bx = X[j]; }
+                if (g > 0 && (g > bg || (g == bg && ox < bx))) { bg = g; bx = ox; }
             } else if (bound > mg) {
                 mg = bound;
             }
@@ -290,9 +306,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     int32_t u = 0;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
     int64_t e0 = 0, d = 0;
+    int32_t su = 0;
+    const GatherIds gi = gather_ids(g, ms);
     if (i < count) {
         const NodeRec r = ms.rec[(int64_t)begin + i];
         u = r.u;
+        su = r.s;
         e0 = r.e0;
         d = r.len;
         if ((LP && !ms.active[u]) || settled(ms, st, u)) {
@@ -309,9 +328,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             X[j] = -1;
             W[j] = 0;
             if (j < d) {
-                int32_t v = g.col[e0 + j];
-                if (v != u) {
-                    X[j] = ms.zeta[v];
+                int32_t v = gi.col[e0 + j];
+                if (v != su) {
+                    X[j] = gi.zeta[v];
                     W[j] = wload<WK>(g.w, e0 + j);
                 }
             }
@@ -322,7 +341,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
             for (int b = a + 1; b < kLaneMax; ++b)
                 if (X[b] >= 0 && X[b] == X[a]) { W[a] += W[b]; X[b] = -1; }
-        int32_t D = ms.zeta[u];
+        int32_t D = gi.zeta[su];
         int64_t wD = 0;
 #pragma unroll
         for (int j = 0; j < kLaneMax; ++j) {
@@ -330,15 +349,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             ncand += (X[j] >= 0 && X[j] != D);
         }
         int64_t vu = ms.vol[u];
-        int64_t base = LP ? 0 : ms.volC[D] - vu;
+        int64_t base = LP ? 0 : gi.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         int64_t slack, kslack;
         int32_t bx = (force_wide || vu > node_wl(ms, u))
-                         ? lane_pick<WK, LP, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, hv,
-                                                   &slack, &kslack)
-                         : lane_pick<WK, LP, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, hv, &slack,
-                                                      &kslack);
+                         ? lane_pick<WK, LP, i128>(X, W, D, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, gi.volC,
+                                                   gi.ord, hv, &slack, &kslack)
+                         : lane_pick<WK, LP, int64_t>(X, W, D, wD, vu * ms.gp, base, S_u * ms.gq, gi.volC, gi.ord,
+                                                      hv, &slack, &kslack);
         ms.move_to[pos] = (bx == kNone) ? -1 : bx;
         if (st.on) {
             if (bx == kNone) record_stay(ms, st, u, slack, kslack);
@@ -374,8 +393,8 @@ constexpr int kEvalBatch = 8;
 // S w(u,X)), from which, with bs, a node that stays gets its slack
 template <typename G, typename V, bool LP>
 __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int first, int step, G vu, G S, G K,
-                                           const int64_t *volC, bool clear, G &bs, int32_t &bx, int64_t &maxpa,
-                                           int64_t &ncand, uint64_t hv) {
+                                           const int64_t *volC, const int32_t *ord, bool clear, G &bs, int32_t &bx,
+                                           int64_t &maxpa, int64_t &ncand, uint64_t hv) {
     for (int s0 = first; s0 < tsize; s0 += kEvalBatch * step) {
         int32_t X[kEvalBatch];
         int64_t a[kEvalBatch], vc[kEvalBatch];
@@ -391,8 +410,12 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
             }
             c[j] = X[j] >= 0 && (G)S * (G)a[j] > K;
         }
+        int32_t ox[kEvalBatch];
 #pragma unroll
-        for (int j = 0; j < kEvalBatch; ++j) vc[j] = (!LP && c[j]) ? volC[X[j]] : 0;
+        for (int j = 0; j < kEvalBatch; ++j) {
+            vc[j] = (!LP && c[j]) ? volC[X[j]] : 0;
+            ox[j] = c[j] ? orig_id(ord, X[j]) : X[j];
+        }
 #pragma unroll
         for (int j = 0; j < kEvalBatch; ++j) {
             ncand += X[j] >= 0;
@@ -402,21 +425,21 @@ __device__ __forceinline__ void eval_slots(int32_t *tk, V *tv, int tsize, int fi
                 continue;
             }
             G sc = (G)S * (G)a[j] - (G)vu * (G)vc[j];
-            if constexpr (LP) sc += (G)lp_tie(hv, X[j]);
-            if (sc > bs || (sc == bs && X[j] < bx)) { bs = sc; bx = X[j]; }
+            if constexpr (LP) sc += (G)lp_tie(hv, ox[j]);
+            if (sc > bs || (sc == bs && ox[j] < bx)) { bs = sc; bx = ox[j]; }
         }
     }
 }
 
 template <typename G, bool LP>
 __device__ __forceinline__ void wave_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
-                                          const int64_t *volC, int32_t &best_x, bool &move,
+                                          const int64_t *volC, const int32_t *ord, int32_t &best_x, bool &move,
                                           int64_t &ncand, uint64_t hv, int64_t &slack, int64_t &kslack) {
     G bs = neg_inf<G>();
     int64_t maxpa = -1;
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, true, bs, bx, maxpa, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, lane_id(), kWave, vu, S, K, volC, ord, true, bs, bx, maxpa, ncand, hv);
     wave_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
@@ -433,7 +456,7 @@ __device__ __forceinline__ void lds_add(int64_t *p, int64_t x) {
 }
 
 template <int WK, int B, typename V>
-__device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *zeta, int32_t u, int32_t D, int64_t e0,
+__device__ __forceinline__ int64_t fold_row(const GraphView &g, const GatherIds &gi, int32_t su, int32_t D, int64_t e0,
                                             int64_t e1, int64_t first, int64_t step, int32_t *tk, V *tv, int bits) {
     const uint32_t mask = (1u << bits) - 1;
     int64_t myD = 0;
@@ -444,11 +467,11 @@ __device__ __forceinline__ int64_t fold_row(const GraphView &g, const int32_t *z
         for (int b = 0; b < B; ++b) {
             int64_t e = base + b * step;
             bool ok = e < e1;
-            v[b] = ok ? g.col[e] : u;
+            v[b] = ok ? gi.col[e] : su;
             wt[b] = ok ? wload<WK>(g.w, e) : 0;
         }
 #pragma unroll
-        for (int b = 0; b < B; ++b) X[b] = v[b] != u ? zeta[v[b]] : -1;
+        for (int b = 0; b < B; ++b) X[b] = v[b] != su ? gi.zeta[v[b]] : -1;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             if (X[b] < 0) continue;
@@ -482,6 +505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     wave_sync();
     int64_t ncand = 0, nd = 0, ne = 0;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
+    const GatherIds gi = gather_ids(g, ms);
     for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < count; i += (int64_t)gridDim.x * 4) {
         int64_t pos = begin + i;
         const NodeRec r = ms.rec[pos];
@@ -493,23 +517,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t e0 = r.e0, e1 = r.e0 + r.len;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
-        int32_t D = ms.zeta[u];
-        int64_t wD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
+        int32_t D = gi.zeta[r.s];
+        int64_t wD = fold_row<WK, 4, int32_t>(g, gi, r.s, D, e0, e1, lane, kWave, tk[w], tv[w], bits);
         wD = wave_sum(wD);
         wave_sync();
         int64_t vu = ms.vol[u];
-        int64_t base = LP ? 0 : ms.volC[D] - vu;
+        int64_t base = LP ? 0 : gi.volC[D] - vu;
         int32_t bx;
         bool mv;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         int64_t slack, kslack;
         if (force_wide || vu > node_wl(ms, u))
-            wave_eval<i128, LP>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC, bx,
-                                mv, ncand, hv, slack, kslack);
+            wave_eval<i128, LP>(tk[w], tv[w], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, gi.volC,
+                                gi.ord, bx, mv, ncand, hv, slack, kslack);
         else
-            wave_eval<int64_t, LP>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv, ncand,
-                                   hv, slack, kslack);
+            wave_eval<int64_t, LP>(tk[w], tv[w], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, gi.volC, gi.ord, bx, mv,
+                                   ncand, hv, slack, kslack);
         if (lane == 0) {
             ms.move_to[pos] = mv ? bx : -1;
             if (st.on && !mv) record_stay(ms, st, u, slack, kslack);
@@ -563,14 +587,15 @@ __device__ __forceinline__ int64_t quad_sum(int64_t v) {
 
 template <typename G, bool LP>
 __device__ __forceinline__ void quad_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
-                                          const int64_t *volC, int32_t &best_x, bool &move, int64_t &ncand,
+                                          const int64_t *volC, const int32_t *ord, int32_t &best_x, bool &move,
+                                          int64_t &ncand,
                                           uint64_t hv, int64_t &slack, int64_t &kslack) {
     G bs = neg_inf<G>();
     int64_t maxpa = -1;
     int32_t bx = kNone;
     const G K = (G)S * (G)wD - (G)vu * (G)base + (LP ? (G)kLpTieMax : (G)0);
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, (int)(threadIdx.x % kQuadLanes), kQuadLanes, vu, S, K, volC, true, bs,
-                               bx, maxpa, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, (int)(threadIdx.x % kQuadLanes), kQuadLanes, vu, S, K, volC, ord, true,
+                               bs, bx, maxpa, ncand, hv);
     quad_argmax<G>(bs, bx);
     best_x = bx;
     move = bx != kNone && bs > K;
@@ -590,33 +615,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     wave_sync();
     int64_t ncand = 0, nd = 0, ne = 0;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
+    const GatherIds gi = gather_ids(g, ms);
     for (int64_t b0 = (int64_t)blockIdx.x * kGroups; b0 < count; b0 += (int64_t)gridDim.x * kGroups) {
         const int64_t i = b0 + grp, pos = begin + i;
         const bool has = i < count;
-        const NodeRec r = has ? ms.rec[pos] : NodeRec{0, 0, 0};
+        const NodeRec r = has ? ms.rec[pos] : NodeRec{0, 0, 0, 0, 0};
         const int32_t u = r.u;
         const bool act = has && (!LP || ms.active[u]) && !settled(ms, st, u);
         if (has && !act && l == 0) ms.move_to[pos] = -1;
         const int64_t e0 = act ? r.e0 : 0, e1 = act ? r.e0 + r.len : 0;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;  // rows of at most kQuadRow entries: at most kQuadCap slots
-        const int32_t D = act ? ms.zeta[u] : -1;
-        int64_t wD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, l, kQuadLanes, tk[grp], tv[grp], bits);
+        const int32_t D = act ? gi.zeta[r.s] : -1;
+        int64_t wD = fold_row<WK, 4, int32_t>(g, gi, r.s, D, e0, e1, l, kQuadLanes, tk[grp], tv[grp], bits);
         wD = quad_sum(wD);
         wave_sync();
         const int64_t vu = act ? ms.vol[u] : 0;
-        const int64_t base = (LP || !act) ? 0 : ms.volC[D] - vu;
+        const int64_t base = (LP || !act) ? 0 : gi.volC[D] - vu;
         const int64_t S_u = act ? node_S(ms, u) : 0;
         const uint64_t hv = (LP && act) ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         int32_t bx;
         bool mv;
         int64_t slack, kslack;
         if (act && (force_wide || vu > node_wl(ms, u)))
-            quad_eval<i128, LP>(tk[grp], tv[grp], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, ms.volC,
-                                bx, mv, ncand, hv, slack, kslack);
+            quad_eval<i128, LP>(tk[grp], tv[grp], 1 << bits, wD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, gi.volC,
+                                gi.ord, bx, mv, ncand, hv, slack, kslack);
         else
-            quad_eval<int64_t, LP>(tk[grp], tv[grp], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, ms.volC, bx, mv,
-                                   ncand, hv, slack, kslack);
+            quad_eval<int64_t, LP>(tk[grp], tv[grp], 1 << bits, wD, vu * ms.gp, base, S_u * ms.gq, gi.volC, gi.ord, bx,
+                                   mv, ncand, hv, slack, kslack);
         if (act && l == 0) {
             ms.move_to[pos] = mv ? bx : -1;
             if (st.on && !mv) record_stay(ms, st, u, slack, kslack);
@@ -648,8 +674,8 @@ static_assert(2 * kBlockShortRow <= kBlockShortCap, "short workgroup-bin table t
 // *slack_out (LDS), written by thread 0
 template <typename G, int NT, bool LP>
 __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, int64_t wD, G vu, int64_t base, G S,
-                                           const int64_t *volC, int32_t *out, int64_t *slack_out, int64_t &ncand,
-                                           uint64_t hv) {
+                                           const int64_t *volC, const int32_t *ord, int32_t *out, int64_t *slack_out,
+                                           int64_t &ncand, uint64_t hv) {
     // slack_out[0], slack_out[1]: slack and kslack
     __shared__ int64_t red_w[NT / kWave];
     __shared__ G red_s[NT / kWave];
@@ -667,7 +693,7 @@ __device__ __forceinline__ void block_eval(int32_t *tk, int32_t *tv, int tsize, 
     G bs = neg_inf<G>();
     int64_t maxpa = -1;
     int32_t bx = kNone;
-    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, true, bs, bx, maxpa, ncand, hv);
+    eval_slots<G, int32_t, LP>(tk, tv, tsize, threadIdx.x, NT, vu, S, K, volC, ord, true, bs, bx, maxpa, ncand, hv);
     wave_argmax<G>(bs, bx);
     maxpa = wave_max_i64(maxpa);
     if (lane_id() == 0) { red_s[w] = bs; red_x[w] = bx; red_u[w] = maxpa; }
@@ -695,6 +721,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __syncthreads();
     int64_t ncand = 0, nd = 0, ne = 0;
     const Settle st = LP ? Settle{false, 0} : settle_state(ms);
+    const GatherIds gi = gather_ids(g, ms);
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
         int64_t pos = begin + i;
         const NodeRec r = ms.rec[pos];
@@ -706,19 +733,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int64_t e0 = r.e0, e1 = r.e0 + r.len;
         int bits = ceil_log2_dev(2 * (e1 - e0));
         bits = bits < 6 ? 6 : bits;
-        int32_t D = ms.zeta[u];
-        int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, NT, tk, tv, bits);
+        int32_t D = gi.zeta[r.s];
+        int64_t myD = fold_row<WK, 4, int32_t>(g, gi, r.s, D, e0, e1, threadIdx.x, NT, tk, tv, bits);
         __syncthreads();
         int64_t vu = ms.vol[u];
-        int64_t base = LP ? 0 : ms.volC[D] - vu;
+        int64_t base = LP ? 0 : gi.volC[D] - vu;
         const int64_t S_u = node_S(ms, u);
         const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
         if (force_wide || vu > node_wl(ms, u))
-            block_eval<i128, NT, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
-                                                ms.volC, &dec, slack, ncand, hv);
+            block_eval<i128, NT, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq, gi.volC,
+                                     gi.ord, &dec, slack, ncand, hv);
         else
-            block_eval<int64_t, NT, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                                   &dec, slack, ncand, hv);
+            block_eval<int64_t, NT, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, gi.volC, gi.ord, &dec,
+                                        slack, ncand, hv);
         __syncthreads();
         const int32_t x = dec;
         if (threadIdx.x == 0) {
@@ -763,20 +790,21 @@ __global__ __launch_bounds__(kSingleThreads) void k_hub_single(GraphView g, Move
     bits = bits < 6 ? 6 : (bits > kSingleBits ? kSingleBits : bits);
     for (int s = threadIdx.x; s < (1 << bits); s += kSingleThreads) { tk[s] = kEmpty; tv[s] = 0; }
     __syncthreads();
-    const int32_t D = ms.zeta[u];
-    int64_t myD = fold_row<WK, 4, int32_t>(g, ms.zeta, u, D, e0, e1, threadIdx.x, kSingleThreads, tk, tv, bits);
+    const GatherIds gi = gather_ids(g, ms);
+    const int32_t D = gi.zeta[pl.s];
+    int64_t myD = fold_row<WK, 4, int32_t>(g, gi, pl.s, D, e0, e1, threadIdx.x, kSingleThreads, tk, tv, bits);
     __syncthreads();
     const int64_t vu = ms.vol[u];
-    const int64_t base = LP ? 0 : ms.volC[D] - vu;
+    const int64_t base = LP ? 0 : gi.volC[D] - vu;
     const int64_t S_u = node_S(ms, u);
     const uint64_t hv = LP ? prio_hash(ms.lp_seed, ms.lp_level, u) : 0;
     int64_t ncand = 0;
     if (force_wide || vu > node_wl(ms, u))
         block_eval<i128, kSingleThreads, LP>(tk, tv, 1 << bits, myD, (i128)vu * ms.gp, base, (i128)S_u * ms.gq,
-                                             ms.volC, &dec, slack, ncand, hv);
+                                             gi.volC, gi.ord, &dec, slack, ncand, hv);
     else
-        block_eval<int64_t, kSingleThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, ms.volC,
-                                                &dec, slack, ncand, hv);
+        block_eval<int64_t, kSingleThreads, LP>(tk, tv, 1 << bits, myD, vu * ms.gp, base, S_u * ms.gq, gi.volC,
+                                                gi.ord, &dec, slack, ncand, hv);
     __syncthreads();
     const int32_t x = dec;
     if (threadIdx.x == 0) {
@@ -868,16 +896,18 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     // the chunk's entries are loaded beside the hub's own words (community,
     // settled test), not after them
     const int64_t c0 = pl.c0;
+    const GatherIds gi = gather_ids(g, ms);
+    const int32_t su = pl.s;
     int32_t v[kHubPerThread], X[kHubPerThread], bk[kHubPerThread];
     int64_t W[kHubPerThread];
 #pragma unroll
     for (int j = 0; j < kHubPerThread; ++j) {
         const int32_t i = j * kHubThreads + threadIdx.x;
         const bool ok = i < pl.len;
-        v[j] = ok ? g.col[c0 + i] : u;
+        v[j] = ok ? gi.col[c0 + i] : su;
         W[j] = ok ? wload<WK>(g.w, c0 + i) : 0;
     }
-    const int32_t D = ms.zeta[u];
+    const int32_t D = gi.zeta[su];
     if (LP && !ms.active[u]) return;  // label propagation: inactive hub, nothing staged
     if (!LP && settled(ms, settle_state(ms), u)) return;  // settled hub: nothing staged
     if (threadIdx.x == 0 && ms.dec_dev) {
@@ -888,7 +918,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_part(GraphView g, MoveState
     const int P = 1 << pb;
     for (int i = threadIdx.x; i < kMergeSlots; i += kHubThreads) { lds.m.key[i] = kEmpty; lds.m.val[i] = 0; }
 #pragma unroll
-    for (int j = 0; j < kHubPerThread; ++j) X[j] = v[j] != u ? ms.zeta[v[j]] : -1;
+    for (int j = 0; j < kHubPerThread; ++j) X[j] = v[j] != su ? gi.zeta[v[j]] : -1;
     int64_t myD = 0;
 #pragma unroll
     for (int j = 0; j < kHubPerThread; ++j)
@@ -1019,8 +1049,8 @@ constexpr int kAggPer = kAggTile / kHubThreads;  // chunk words per thread and t
 // kernel (tile 0 is read by every pass)
 template <typename G, bool LP>
 __device__ __forceinline__ void agg_bucket(const HubArrays &ha, const HubAggPlan &pl, const uint32_t (&pre)[kAggPer],
-                                           G vu, G S, G K, const int64_t *volC, int32_t *tk, int64_t *tv,
-                                           int32_t *cpre, int32_t *cbase, int32_t *wtot, int32_t *nkeys,
+                                           G vu, G S, G K, const int64_t *volC, const int32_t *ord, int32_t *tk,
+                                           int64_t *tv, int32_t *cpre, int32_t *cbase, int32_t *wtot, int32_t *nkeys,
                                            int32_t *overflow, G &bs, int32_t &bx, int64_t &maxpa, int64_t &ncand,
                                            uint64_t hv) {
     const int32_t nch = pl.nch;
@@ -1117,8 +1147,8 @@ __device__ __forceinline__ void agg_bucket(const HubArrays &ha, const HubAggPlan
                 __syncthreads();
                 break;
             }
-            eval_slots<G, int64_t, LP>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, false, pbs, pbx,
-                                       pmaxpa, pc, hv);
+            eval_slots<G, int64_t, LP>(tk, tv, kAggSlots, threadIdx.x, kHubThreads, vu, S, K, volC, ord, false, pbs,
+                                       pbx, pmaxpa, pc, hv);
             __syncthreads();
         }
         if (ok) {
@@ -1158,7 +1188,10 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     int64_t wD = 0;
     for (int64_t j = threadIdx.x; j < pl.nch; j += kHubThreads) wD += ha.wd_part[pl.wd + j];
     const int64_t vu = ms.vol[u];
-    const int32_t D = ms.zeta[u];
+    // community ids of the sweep layout when the level has one (see MoveState)
+    const int64_t *vcs = ms.colp ? ms.volCp : ms.volC;
+    const int32_t *ord = ms.colp ? ms.ord : nullptr;
+    const int32_t D = ms.colp ? ms.zetap[pl.s] : ms.zeta[u];
     if (LP && !ms.active[u]) return;
     if (!LP) {
         // whether the hub is settled, and the clock its decision is taken at,
@@ -1178,7 +1211,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
     __syncthreads();
     wD = 0;
     for (int i = 0; i < kHubThreads / kWave; ++i) wD += wred[i];
-    const int64_t base = LP ? 0 : ms.volC[D] - vu;
+    const int64_t base = LP ? 0 : vcs[D] - vu;
     // vol(D \ u) at the start of the class, for the reduce (which runs while the
     // class's other moves apply)
     if (p == 0 && threadIdx.x == 0) ha.hub_base[hg] = base;
@@ -1192,7 +1225,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         const i128 Sg = (i128)S_u * ms.gq, vg = (i128)vu * ms.gp;
         const i128 K = Sg * (i128)wD - vg * (i128)base + (LP ? (i128)kLpTieMax : (i128)0);
         int64_t maxpa = -1;
-        agg_bucket<i128, LP>(ha, pl, pre, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs,
+        agg_bucket<i128, LP>(ha, pl, pre, vg, Sg, K, vcs, ord, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, bs,
                              bx, maxpa, ncand, hv);
         block_argmax<i128>(bs, bx);
         maxpa = block_max<int64_t>(maxpa);
@@ -1202,7 +1235,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_agg(MoveState ms, HubArrays
         const int64_t Sg = S_u * ms.gq, vg = vu * ms.gp;
         const int64_t K = Sg * wD - vg * base + (LP ? (int64_t)kLpTieMax : 0);
         int64_t b64 = neg_inf<int64_t>(), maxpa = -1;
-        agg_bucket<int64_t, LP>(ha, pl, pre, vg, Sg, K, ms.volC, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64,
+        agg_bucket<int64_t, LP>(ha, pl, pre, vg, Sg, K, vcs, ord, tk, tv, cpre, cbase, wtot, &nkeys, &overflow, b64,
                                 bx, maxpa, ncand, hv);
         block_argmax<int64_t>(b64, bx);
         maxpa = block_max<int64_t>(maxpa);
@@ -1225,9 +1258,14 @@ __device__ __forceinline__ int64_t apply_move(const MoveState &ms, int32_t u, in
     int32_t D = ms.zeta[u];
     int64_t vu = ms.vol[u];
     ms.zeta[u] = X;
+    if (ms.zetap) ms.zetap[ms.sig[u]] = ms.sig[X];  // the sweep layout's copy
     if (!ms.active) {  // label propagation keeps no community volumes
         atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-vu));
         atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)vu);
+        if (ms.volCp) {
+            atomicAdd((unsigned long long *)&ms.volCp[ms.sig[D]], (unsigned long long)(-vu));
+            atomicAdd((unsigned long long *)&ms.volCp[ms.sig[X]], (unsigned long long)vu);
+        }
     }
     if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
     return 1;
@@ -1346,13 +1384,19 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
                 D = ms.zeta[u];
                 join = leave = ms.vol[u];
                 ms.zeta[u] = X;
+                if (ms.zetap) ms.zetap[ms.sig[u]] = ms.sig[X];  // the sweep layout's copy
                 if (ms.gmoved) ms.gmoved[ms.gid[u]] = 1;
                 ++moved;
                 mvol += join;
             }
-            if (wave_group_sum(X, mv, join)) atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)join);
-            if (wave_group_sum(D, mv, leave))
+            if (wave_group_sum(X, mv, join)) {
+                atomicAdd((unsigned long long *)&ms.volC[X], (unsigned long long)join);
+                if (ms.volCp) atomicAdd((unsigned long long *)&ms.volCp[ms.sig[X]], (unsigned long long)join);
+            }
+            if (wave_group_sum(D, mv, leave)) {
                 atomicAdd((unsigned long long *)&ms.volC[D], (unsigned long long)(-leave));
+                if (ms.volCp) atomicAdd((unsigned long long *)&ms.volCp[ms.sig[D]], (unsigned long long)(-leave));
+            }
         }
         if (sk) {
             mvol = wave_sum(mvol);
@@ -1369,31 +1413,84 @@ __global__ __launch_bounds__(kHubThreads) void k_reduce_apply(GraphView g, MoveS
     }
 }
 
-__global__ void k_node_recs(GraphView g, const int32_t *class_nodes, int64_t count, NodeRec *rec) {
+__global__ void k_node_recs(GraphView g, const int32_t *class_nodes, int64_t count, NodeRec *rec, const int32_t *sig) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t u = class_nodes[i];
         const int64_t e0 = g.off[u];
-        rec[i] = NodeRec{e0, (int32_t)(g.off[u + 1] - e0), u};
+        rec[i] = NodeRec{e0, (int32_t)(g.off[u + 1] - e0), u, sig ? sig[u] : u, 0};
     }
 }
 
-void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, hipStream_t st) {
+void launch_node_recs(const GraphView &g, const int32_t *class_nodes, int64_t count, NodeRec *rec, const int32_t *sig,
+                      hipStream_t st) {
     if (count <= 0) return;
     const int64_t blocks = cdiv(count, 256);
     hipLaunchKernelGGL(k_node_recs, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, g, class_nodes,
-                       count, rec);
+                       count, rec, sig);
+    HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ sweep layout
+__global__ void k_layout_keys(GraphView g, uint32_t *keys, int32_t *vals) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = g.off[u + 1] - g.off[u];
+        keys[u] = ~(uint32_t)(d < (int64_t)UINT32_MAX ? d : (int64_t)UINT32_MAX);  // descending degree
+        vals[u] = (int32_t)u;
+    }
+}
+__global__ void k_layout_inverse(int64_t n, const int32_t *ord, int32_t *sig) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sig[ord[i]] = (int32_t)i;
+}
+__global__ void k_layout_col(const int32_t *col, int64_t nnz, const int32_t *sig, int32_t *colp) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        colp[e] = sig[col[e]];
+}
+__global__ void k_layout_sync(int64_t n, const int32_t *zeta, const int64_t *volC, const int32_t *sig, int32_t *zetap,
+                              int64_t *volCp) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = sig[u];
+        zetap[s] = sig[zeta[u]];
+        volCp[s] = volC[u];
+    }
+}
+
+void build_layout(const GraphView &g, int32_t *sig, int32_t *ord, int32_t *colp, uint32_t *keys, int32_t *vals,
+                  uint32_t *keys_alt, int32_t *vals_alt, void *rs, hipStream_t st) {
+    const int64_t n = g.n;
+    if (n <= 0) return;
+    const unsigned nb = (unsigned)(cdiv(n, 256) < 8192 ? cdiv(n, 256) : 8192);
+    hipLaunchKernelGGL(k_layout_keys, dim3(nb), dim3(256), 0, st, g, keys, vals);
+    // a stable sort: equal degrees keep ascending ids
+    radix_sort_u32_i32(&keys, &vals, &keys_alt, &vals_alt, n, 32, rs, st);
+    HIPCHK(hipMemcpyAsync(ord, vals, n * 4, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_layout_inverse, dim3(nb), dim3(256), 0, st, n, (const int32_t *)ord, sig);
+    if (g.nnz > 0) {
+        const int64_t eb = cdiv(g.nnz, 256);
+        hipLaunchKernelGGL(k_layout_col, dim3((unsigned)(eb < 16384 ? eb : 16384)), dim3(256), 0, st, g.col, g.nnz,
+                           (const int32_t *)sig, colp);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+void sync_layout(int64_t n, const int32_t *zeta, const int64_t *volC, const int32_t *sig, int32_t *zetap,
+                 int64_t *volCp, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned nb = (unsigned)(cdiv(n, 256) < 8192 ? cdiv(n, 256) : 8192);
+    hipLaunchKernelGGL(k_layout_sync, dim3(nb), dim3(256), 0, st, n, zeta, volC, sig, zetap, volCp);
     HIPCHK(hipGetLastError());
 }
 
 // launch plans of the level-wide hub lists: one thread per workgroup record
-__global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, const int64_t *agg_abs,
-                            const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red,
-                            HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap, HubRedPlan *rp) {
+__global__ void k_hub_plans(GraphView g, HubArrays ha, const int32_t *sig, const int64_t *ins_abs,
+                            const int64_t *agg_abs, const int64_t *red_abs, int64_t n_sgl, int64_t n_ins,
+                            int64_t n_agg, int64_t n_red, HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap,
+                            HubRedPlan *rp) {
     const int64_t tot = n_sgl + n_ins + n_agg + n_red;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         if (i < n_sgl) {
             const int32_t hg = ha.sgl_hub[i], u = ha.hub_u[hg];
-            sp[i] = HubSglPlan{g.off[u], g.off[u + 1], u, ha.hub_pos[hg]};
+            sp[i] = HubSglPlan{g.off[u], g.off[u + 1], u, ha.hub_pos[hg], sig ? sig[u] : u, 0};
             continue;
         }
         int64_t j = i - n_sgl;
@@ -1402,16 +1499,16 @@ __global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, c
             const int64_t k = j - ins_abs[hg], e0 = g.off[u], e1 = g.off[u + 1];
             const int64_t c0 = e0 + k * kHubInsChunk, c1 = c0 + kHubInsChunk < e1 ? c0 + kHubInsChunk : e1;
             pp[j] = HubPartPlan{c0, ha.stg_off[hg] + k * kHubInsChunk, ha.bkt_off[hg], u, hg, (int32_t)k,
-                                (int32_t)(c1 - c0), ha.nchunk[hg], ha.pbits[hg], ha.hub_pos[hg], 0};
+                                (int32_t)(c1 - c0), ha.nchunk[hg], ha.pbits[hg], ha.hub_pos[hg], sig ? sig[u] : u};
             continue;
         }
         j -= n_ins;
         if (j < n_agg) {
-            const int32_t hg = ha.agg_hub[j];
+            const int32_t hg = ha.agg_hub[j], u = ha.hub_u[hg];
             const int64_t p = j - agg_abs[hg];
             const int32_t nch = ha.nchunk[hg];
-            ap[j] = HubAggPlan{ha.bkt_off[hg] + p * nch, ha.stg_off[hg], ha.ins_first[hg], ha.hub_u[hg], hg,
-                               (int32_t)p, nch};
+            ap[j] = HubAggPlan{ha.bkt_off[hg] + p * nch, ha.stg_off[hg], ha.ins_first[hg], u, hg, (int32_t)p, nch,
+                               sig ? sig[u] : u, 0};
             continue;
         }
         j -= n_agg;
@@ -1419,18 +1516,19 @@ __global__ void k_hub_plans(GraphView g, HubArrays ha, const int64_t *ins_abs, c
         const int64_t k = j - red_abs[hg], e1 = g.off[u + 1];
         const int64_t s0 = g.off[u] + k * kHubMarkSlice, s1 = s0 + kHubMarkSlice < e1 ? s0 + kHubMarkSlice : e1;
         rp[j] = HubRedPlan{ha.agg_first[hg], ha.ins_first[hg], s0, s1, u, hg, 1 << ha.pbits[hg], ha.nchunk[hg],
-                           (int32_t)k, 0};
+                           (int32_t)k, sig ? sig[u] : u};
     }
 }
 
-void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int64_t *ins_abs, const int64_t *agg_abs,
-                      const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg, int64_t n_red,
-                      HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap, HubRedPlan *rp, hipStream_t st) {
+void launch_hub_plans(const GraphView &g, const HubArrays &ha, const int32_t *sig, const int64_t *ins_abs,
+                      const int64_t *agg_abs, const int64_t *red_abs, int64_t n_sgl, int64_t n_ins, int64_t n_agg,
+                      int64_t n_red, HubSglPlan *sp, HubPartPlan *pp, HubAggPlan *ap, HubRedPlan *rp,
+                      hipStream_t st) {
     const int64_t tot = n_sgl + n_ins + n_agg + n_red;
     if (tot <= 0) return;
     const int64_t blocks = cdiv(tot, 256);
-    hipLaunchKernelGGL(k_hub_plans, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, g, ha, ins_abs,
-                       agg_abs, red_abs, n_sgl, n_ins, n_agg, n_red, sp, pp, ap, rp);
+    hipLaunchKernelGGL(k_hub_plans, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, g, ha, sig,
+                       ins_abs, agg_abs, red_abs, n_sgl, n_ins, n_agg, n_red, sp, pp, ap, rp);
     HIPCHK(hipGetLastError());
 }
 
