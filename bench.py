@@ -783,7 +783,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -843,8 +843,9 @@ def main():
     t0 = time.perf_counter()
     q = lv = None
     for i in range(args.steps):
+        t = time.perf_counter()
         _, q, lv = ctx.run(lab)
-        log(f"step {i} done")
+        log(f"step {i}: {time.perf_counter() - t:.3f}s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = ctx.stats()  # of the last step
