@@ -172,6 +172,15 @@ typedef struct {
                               unchanged.  0 (default): graphs of more than 2^27
                               entries; 1: every single graph; -1: never.  Batches
                               never. */
+    int32_t pack_bits;     /* coarsening of levels with 32-bit or unit weights: a
+                              (coarse row, coarse column) key and its weight are
+                              sorted as one 64-bit word when every entry's weight
+                              fits the bits the two ids leave free (a merged weight
+                              too large for them is split over several words of
+                              the key).  0 (default): all free bits; k in [2, 62]:
+                              at most k of them (more splits; lowered only to
+                              exercise the split on small graphs); -1: never
+                              (key-weight pairs).  Same coarse graph. */
 } plm_options;
 
 /* Fills *opt with the defaults above. */

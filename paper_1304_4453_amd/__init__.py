@@ -44,7 +44,8 @@ class plm_options(ctypes.Structure):
                 ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32), ("graph_sweeps", ctypes.c_int32),
                 ("hub_stream", ctypes.c_int32), ("colour_tail", ctypes.c_int32), ("hub_row_max", ctypes.c_int32),
                 ("agg_max_keys", ctypes.c_int32), ("agg_tile", ctypes.c_int32), ("settle", ctypes.c_int32),
-                ("join", ctypes.c_int32), ("layout", ctypes.c_int32)]
+                ("join", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("pack_bits", ctypes.c_int32)]
 
 
 class plm_level_info_t(ctypes.Structure):

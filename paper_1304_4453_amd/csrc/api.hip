@@ -935,7 +935,8 @@ struct plm_ctx {
         int64_t k = build_relabel(zeta, l.n, l.pi, scr, hbuf, st);
         LevelData nl;
         nl.n = k;
-        nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st);
+        nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, nullptr,
+                                   opt.pack_bits);
         nl.wkind = 2;
         nl.diag_mult = 1;
         // drop any deeper levels left from an earlier run
@@ -1513,7 +1514,8 @@ struct plm_ctx {
             LevelData nl;
             nl.n = k;
             try {
-                nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, bkeep);
+                nl.nnz = build_contraction(l.view(), l.pi, k, &nl.off, &nl.col, (int64_t **)&nl.w, scr, hbuf, st, bkeep,
+                                           opt.pack_bits);
                 nl.wkind = 2;
                 nl.diag_mult = 1;
                 nl.gbase = dev_alloc<int64_t>(A2 + 1);
@@ -1603,6 +1605,10 @@ int check_options(const plm_options &o, std::string &msg) {
     if (o.settle < -1 || o.settle > 1) { msg = "settle must be -1, 0 or 1"; return PLM_E_ARG; }
     if (o.join < 0) { msg = "join must be >= 0"; return PLM_E_ARG; }
     if (o.layout < -1 || o.layout > 1) { msg = "layout must be -1, 0 or 1"; return PLM_E_ARG; }
+    if (o.pack_bits < -1 || o.pack_bits == 1 || o.pack_bits > 62) {
+        msg = "pack_bits must be -1, 0 or lie in [2, 62]";
+        return PLM_E_ARG;
+    }
     if (!(o.gamma_num == 0 && o.gamma_den == 0) &&
         (o.gamma_num < 0 || o.gamma_den < 1 || o.gamma_num >= 65536 || o.gamma_den >= 65536)) {
         msg = "gamma must satisfy 0 <= gamma_num < 2^16, 1 <= gamma_den < 2^16";

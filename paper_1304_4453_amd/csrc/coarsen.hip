@@ -57,6 +57,14 @@ int64_t count_communities(const int32_t *zeta, int64_t n, Scratch &scr, int64_t 
 // ------------------------------------------------------------------ contraction
 // key = (pi(u) << b) | pi(v), value = entry weight (self-loops times diag_mult,
 // so the coarse diagonal is again "doubled").
+//
+// Packed items: when every entry's weight (times diag_mult) fits the wb =
+// 64 - 2b bits below the key, an item is one word (key << wb) | w and the sort
+// moves keys alone (half the bytes of key-value pairs).  A merged weight W
+// above wmax = 2^wb - 1 is carried by ceil(W / wmax) items of the same key,
+// which the reduction sums again; each of the c entries merged into W weighs
+// at most wmax, so there are at most c of them and the item count stays within
+// the entry count.
 // Merged before the sort, per tile of kCTile consecutive entries: each entry
 // (read lane by lane, coalesced) finds its row through the tile's row offsets
 // staged in LDS (a binary search there; a global one when the tile spans a run
@@ -72,9 +80,10 @@ constexpr int kCPer = kCTile / kT;
 constexpr int kCBits = 11;
 constexpr int kCSlots = 1 << kCBits;  // at most kCTile keys: load <= 1/2
 static_assert(2 * kCTile <= kCSlots, "contraction merge table must never fill");
-template <int WK>
-__global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_t *pi, int b, const uint8_t *keep,
-                                                       uint64_t *keys, int64_t *vals, unsigned long long *cursor) {
+template <int WK, bool PK>
+__global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_t *pi, int b, int wb,
+                                                       const uint8_t *keep, uint64_t *keys, int64_t *vals,
+                                                       unsigned long long *cursor) {
     __shared__ int64_t soff[kCTile + 1];
     __shared__ uint64_t tk[kCSlots];
     __shared__ int64_t tv[kCSlots];
@@ -131,11 +140,22 @@ __global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_
         }
     }
     __syncthreads();
-    // each thread appends the keys of its kCSlots / kT slots
+    // each thread appends the keys of its kCSlots / kT slots (packed: a slot's
+    // ceil(W / wmax) items, at least one)
     constexpr int kSP = kCSlots / kT;
+    const uint64_t wmax = PK ? (1ULL << wb) - 1 : 0;
     int32_t cnt = 0;
 #pragma unroll
-    for (int j = 0; j < kSP; ++j) cnt += tk[threadIdx.x * kSP + j] != kNoKey;
+    for (int j = 0; j < kSP; ++j) {
+        const int s = threadIdx.x * kSP + j;
+        if (tk[s] == kNoKey) continue;
+        if (PK) {
+            const uint64_t W = (uint64_t)tv[s];
+            cnt += W > wmax ? (int32_t)((W + wmax - 1) / wmax) : 1;
+        } else {
+            ++cnt;
+        }
+    }
     int32_t inc = cnt;
     for (int d = 1; d < kWave; d <<= 1) {
         int32_t y = __shfl_up(inc, d);
@@ -154,7 +174,16 @@ __global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_
 #pragma unroll
     for (int j = 0; j < kSP; ++j) {
         const int s = threadIdx.x * kSP + j;
-        if (tk[s] != kNoKey) {
+        if (tk[s] == kNoKey) continue;
+        if (PK) {
+            const uint64_t k = tk[s] << wb;
+            uint64_t W = (uint64_t)tv[s];
+            do {
+                const uint64_t part = W < wmax ? W : wmax;
+                keys[pos++] = k | part;
+                W -= part;
+            } while (W > 0);
+        } else {
             keys[pos] = tk[s];
             vals[pos] = tv[s];
             ++pos;
@@ -162,9 +191,33 @@ __global__ __launch_bounds__(kT) void k_contract_merge(GraphView g, const int32_
     }
 }
 
-__global__ void k_head_flags(const uint64_t *keys, int64_t n, int32_t *head) {
+// the weight of every entry as uint32 (negative weights read as >= 2^31)
+__global__ __launch_bounds__(kT) void k_weight_max(const int32_t *w, int64_t nnz, unsigned int *out) {
+    uint32_t m = 0;
+    const int64_t stride = (int64_t)gridDim.x * kT;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < nnz; i += 4 * stride) {
+        uint32_t x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = i + q * stride < nnz ? (uint32_t)w[i + q * stride] : 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m = x[q] > m ? x[q] : m;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)m, d);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0 && m) atomicMax(out, m);
+}
+
+// packed items (PK) compare their keys above bit wb
+template <bool PK>
+__global__ void k_head_flags(const uint64_t *keys, int64_t n, int wb, int32_t *head) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+    if (i < n) {
+        const uint64_t k = PK ? keys[i] >> wb : keys[i];
+        head[i] = (i == 0 || k != (PK ? keys[i - 1] >> wb : keys[i - 1])) ? 1 : 0;
+    }
 }
 
 // Reduce-by-key over sorted keys.  Run id of item i = incl_scan(head)[i] - 1 =
@@ -173,8 +226,9 @@ __global__ void k_head_flags(const uint64_t *keys, int64_t n, int32_t *head) {
 // run's LDS slot; a run that lies wholly inside the block is stored, a run
 // crossing a block edge is added atomically (out_w zeroed first).
 constexpr int kRbkItems = kT * kChunk;
+template <bool PK>
 __global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, const int64_t *vals, const int32_t *head,
-                                                      const int64_t *excl, int64_t n, uint64_t *out_k,
+                                                      const int64_t *excl, int64_t n, int wb, uint64_t *out_k,
                                                       int64_t *out_w) {
     __shared__ int64_t acc[kRbkItems];
     int64_t blk0 = (int64_t)blockIdx.x * kRbkItems;
@@ -188,8 +242,10 @@ __global__ __launch_bounds__(kT) void k_reduce_by_key(const uint64_t *keys, cons
         if (i < blk1) {
             const int32_t h = head[i];
             const int64_t r = excl[i] + h - 1;
-            if (h) out_k[r] = keys[i];
-            atomicAdd((unsigned long long *)&acc[r - run0], (unsigned long long)vals[i]);
+            const uint64_t k = keys[i];
+            if (h) out_k[r] = PK ? k >> wb : k;
+            const uint64_t w = PK ? k & ((1ULL << wb) - 1) : (uint64_t)vals[i];
+            atomicAdd((unsigned long long *)&acc[r - run0], (unsigned long long)w);
         }
     }
     __syncthreads();
@@ -224,7 +280,8 @@ __global__ void k_coarse_off(const uint64_t *ukeys, int64_t m, int b, int64_t k,
 }
 
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff_out, int32_t **ccol_out,
-                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st, const uint8_t *keep) {
+                          int64_t **cw_out, Scratch &scr, int64_t *host_i64, hipStream_t st, const uint8_t *keep,
+                          int pack_bits) {
     int64_t nnz = g.nnz;
     int b = ceil_log2((uint64_t)(k > 1 ? k : 2));
     int64_t nb = nnz > 0 ? nnz : 1;
@@ -260,16 +317,38 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
     }
     const dim3 grid((unsigned)cdiv(nnz, kCTile));
     unsigned long long *cursor = (unsigned long long *)total;
-    HIPCHK(hipMemsetAsync(cursor, 0, 8, st));
-    switch (g.wkind) {
-        case 0: hipLaunchKernelGGL(k_contract_merge<0>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
-        case 1: hipLaunchKernelGGL(k_contract_merge<1>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
-        default: hipLaunchKernelGGL(k_contract_merge<2>, grid, dim3(kT), 0, st, g, pi, b, keep, ka, va, cursor); break;
+    // packed items for 32-bit (or unit) weights whose largest entry, times
+    // diag_mult, fits below the key (in at most pack_bits bits when that is set)
+    const int wb = pack_bits > 0 && pack_bits < 64 - 2 * b ? pack_bits : 64 - 2 * b;
+    bool pk = false;
+    if (pack_bits >= 0 && g.wkind <= 1 && wb >= 2) {
+        uint64_t wtop = 1;
+        if (g.wkind == 1) {
+            unsigned int *wm = (unsigned int *)cursor;
+            HIPCHK(hipMemsetAsync(wm, 0, 8, st));
+            const int64_t blocks = cdiv(nnz, 4 * kT);
+            hipLaunchKernelGGL(k_weight_max, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(kT), 0, st,
+                               (const int32_t *)g.w, nnz, wm);
+            HIPCHK(hipMemcpyAsync(host_i64, wm, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            wtop = (uint64_t)(uint32_t)host_i64[0];
+        }
+        pk = wtop <= (uint64_t)INT32_MAX && wtop * (uint64_t)(g.diag_mult > 1 ? g.diag_mult : 1) <= (1ULL << wb) - 1;
     }
+    HIPCHK(hipMemsetAsync(cursor, 0, 8, st));
+#define PLM_MERGE(WK, PK)                                                                                        \
+    hipLaunchKernelGGL((k_contract_merge<WK, PK>), grid, dim3(kT), 0, st, g, pi, b, wb, keep, ka, va, cursor)
+    switch (g.wkind) {
+        case 0: if (pk) PLM_MERGE(0, true); else PLM_MERGE(0, false); break;
+        case 1: if (pk) PLM_MERGE(1, true); else PLM_MERGE(1, false); break;
+        default: PLM_MERGE(2, false); break;
+    }
+#undef PLM_MERGE
     HIPCHK(hipMemcpyAsync(host_i64, cursor, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     nnz = host_i64[0];  // merged entries (kept rows only)
-    radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b, tmp, st);
+    if (pk) radix_sort_u64_keys(&ka, &kb, nnz, wb, 2 * b, tmp, st);
+    else radix_sort_u64_i64(&ka, &va, &kb, &vb, nnz, 2 * b, tmp, st);
     if (nnz == 0) {
         HIPCHK(hipMemsetAsync(coff, 0, (k + 1) * 8, st));
         e = hipMalloc(&ccol, 4);
@@ -279,7 +358,8 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
         *coff_out = coff; *ccol_out = ccol; *cw_out = cw;
         return 0;
     }
-    hipLaunchKernelGGL(k_head_flags, dim3((unsigned)cdiv(nnz, kT)), dim3(kT), 0, st, ka, nnz, head);
+    if (pk) hipLaunchKernelGGL(k_head_flags<true>, dim3((unsigned)cdiv(nnz, kT)), dim3(kT), 0, st, ka, nnz, wb, head);
+    else hipLaunchKernelGGL(k_head_flags<false>, dim3((unsigned)cdiv(nnz, kT)), dim3(kT), 0, st, ka, nnz, wb, head);
     exclusive_scan_i32(head, excl, nnz, total, tmp, st);
     HIPCHK(hipMemcpyAsync(host_i64, total, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -290,8 +370,12 @@ int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int6
     if (e != hipSuccess) fail(e);
     // unique keys go to kb (free after the sort), summed weights to cw
     HIPCHK(hipMemsetAsync(cw, 0, m * 8, st));
-    hipLaunchKernelGGL(k_reduce_by_key, dim3((unsigned)cdiv(nnz, kRbkItems)), dim3(kT), 0, st, ka, va, head, excl,
-                       nnz, kb, cw);
+    if (pk)
+        hipLaunchKernelGGL(k_reduce_by_key<true>, dim3((unsigned)cdiv(nnz, kRbkItems)), dim3(kT), 0, st, ka, va, head,
+                           excl, nnz, wb, kb, cw);
+    else
+        hipLaunchKernelGGL(k_reduce_by_key<false>, dim3((unsigned)cdiv(nnz, kRbkItems)), dim3(kT), 0, st, ka, va,
+                           head, excl, nnz, wb, kb, cw);
     hipLaunchKernelGGL(k_coarse_col, dim3((unsigned)cdiv(m, kT)), dim3(kT), 0, st, kb, m, b, ccol);
     hipLaunchKernelGGL(k_coarse_off, dim3((unsigned)cdiv(k + 1, kT)), dim3(kT), 0, st, kb, m, b, k, coff);
     HIPCHK(hipGetLastError());

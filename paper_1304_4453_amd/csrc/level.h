@@ -226,7 +226,7 @@ int64_t build_relabel(const int32_t *zeta, int64_t n, int32_t *pi, Scratch &scr,
 // are left out.
 int64_t build_contraction(const GraphView &g, const int32_t *pi, int64_t k, int64_t **coff, int32_t **ccol,
                           int64_t **cw, Scratch &scr, int64_t *host_i64, hipStream_t st,
-                          const uint8_t *keep = nullptr);
+                          const uint8_t *keep = nullptr, int pack_bits = 0);
 // lab[v] = map[lab[v]] for v < n
 void launch_compose(int32_t *lab, const int32_t *map, int64_t n, hipStream_t st);
 void launch_iota(int32_t *a, int64_t n, hipStream_t st);

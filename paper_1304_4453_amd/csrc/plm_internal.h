@@ -216,6 +216,10 @@ void radix_sort_u64_i32(uint64_t **keys, int32_t **vals, uint64_t **keys_alt, in
                         int bits, void *scratch, hipStream_t st);
 void radix_sort_u64_i64(uint64_t **keys, int64_t **vals, uint64_t **keys_alt, int64_t **vals_alt, int64_t n,
                         int bits, void *scratch, hipStream_t st);
+// Keys alone, on key bits [lo, lo + bits) (the bits below lo are carried, not
+// ordered).
+void radix_sort_u64_keys(uint64_t **keys, uint64_t **keys_alt, int64_t n, int lo, int bits, void *scratch,
+                         hipStream_t st);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int ceil_log2(uint64_t x) {  // smallest b with 2^b >= x

@@ -142,8 +142,10 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, int
 // so equal keys keep their input order (stability).  The tile is first sorted
 // by digit in LDS (its digit starts are the exclusive scan of its histogram
 // counts), then written out in LDS order: consecutive threads write
-// consecutive positions of a digit's run, so the stores coalesce.
-template <typename K, typename V>
+// consecutive positions of a digit's run, so the stores coalesce.  KV = false
+// sorts keys alone (vin / vout unused): half the LDS and traffic of 8-byte
+// key-value pairs.
+template <typename K, typename V, bool KV>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, const V *vin, K *kout, V *vout,
                                                                  int64_t n, int shift, const int64_t *offsets,
                                                                  const int32_t *counts, int64_t ntiles) {
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
     __shared__ uint32_t wsum[kRadixWaves];
     __shared__ int64_t gofs[256];
     __shared__ K sk[kRadixTile];
-    __shared__ V sv[kRadixTile];
+    __shared__ V sv[KV ? kRadixTile : 1];
     const int tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     running[tid] = 0;
 #pragma unroll
@@ -176,18 +178,17 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     // the tile's items are loaded together (one memory latency per tile)
     K kr[kRadixRounds];
-    V vr[kRadixRounds];
+    V vr[KV ? kRadixRounds : 1];
 #pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
         const int64_t i = base + (int64_t)r * kRadixThreads + tid;
         kr[r] = i < n ? kin[i] : (K)0;
-        vr[r] = i < n ? vin[i] : (V)0;
+        if constexpr (KV) vr[r] = i < n ? vin[i] : (V)0;
     }
 #pragma unroll
     for (int r = 0; r < kRadixRounds; ++r) {
         const bool valid = base + (int64_t)r * kRadixThreads + tid < n;
         const K k = kr[r];
-        const V v = vr[r];
         uint32_t d = (uint32_t)(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
             for (int j = 0; j < w; ++j) pre += wcnt[j][d];
             const uint32_t lp = lstart[d] + pre + rank;
             sk[lp] = k;
-            sv[lp] = v;
+            if constexpr (KV) sv[lp] = vr[r];
         }
         __syncthreads();
         uint32_t add = 0;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *kin, c
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         const int64_t pos = gofs[d] + (int64_t)(j - (int)lstart[d]);
         kout[pos] = k;
-        vout[pos] = sv[j];
+        if constexpr (KV) vout[pos] = sv[j];
     }
 }
 
@@ -233,8 +234,10 @@ size_t radix_scratch_bytes(int64_t n) {
     return align_up((size_t)m * sizeof(int32_t)) + align_up((size_t)m * sizeof(int64_t)) + scan_scratch_bytes(m);
 }
 
-template <typename K, typename V>
-static void radix_impl(K **keys, V **vals, K **keys_alt, V **vals_alt, int64_t n, int bits, void *scratch,
+// LSD passes over key bits [lo, lo + bits), 8 at a time (lo + bits <= 8 *
+// sizeof(K) + 7: bits above the key read as zero)
+template <typename K, typename V, bool KV>
+static void radix_impl(K **keys, V **vals, K **keys_alt, V **vals_alt, int64_t n, int lo, int bits, void *scratch,
                        hipStream_t st) {
     if (n <= 1 || bits <= 0) return;
     int64_t ntiles = cdiv(n, kRadixTile);
@@ -243,11 +246,11 @@ static void radix_impl(K **keys, V **vals, K **keys_alt, V **vals_alt, int64_t n
     int32_t *counts = (int32_t *)s;
     int64_t *offsets = (int64_t *)(s + align_up((size_t)m * sizeof(int32_t)));
     char *scan_tmp = s + align_up((size_t)m * sizeof(int32_t)) + align_up((size_t)m * sizeof(int64_t));
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo; shift < lo + bits; shift += 8) {
         hipLaunchKernelGGL((k_radix_hist<K>), dim3(ntiles), dim3(kRadixThreads), 0, st, *keys, n, shift, counts,
                            ntiles);
         exclusive_scan_i32(counts, offsets, m, nullptr, scan_tmp, st);
-        hipLaunchKernelGGL((k_radix_scatter<K, V>), dim3(ntiles), dim3(kRadixThreads), 0, st, *keys, *vals,
+        hipLaunchKernelGGL((k_radix_scatter<K, V, KV>), dim3(ntiles), dim3(kRadixThreads), 0, st, *keys, *vals,
                            *keys_alt, *vals_alt, n, shift, (const int64_t *)offsets, (const int32_t *)counts, ntiles);
         K *tk = *keys; *keys = *keys_alt; *keys_alt = tk;
         V *tv = *vals; *vals = *vals_alt; *vals_alt = tv;
@@ -257,15 +260,19 @@ static void radix_impl(K **keys, V **vals, K **keys_alt, V **vals_alt, int64_t n
 
 void radix_sort_u32_i32(uint32_t **k, int32_t **v, uint32_t **ka, int32_t **va, int64_t n, int bits, void *s,
                         hipStream_t st) {
-    radix_impl<uint32_t, int32_t>(k, v, ka, va, n, bits, s, st);
+    radix_impl<uint32_t, int32_t, true>(k, v, ka, va, n, 0, bits, s, st);
 }
 void radix_sort_u64_i32(uint64_t **k, int32_t **v, uint64_t **ka, int32_t **va, int64_t n, int bits, void *s,
                         hipStream_t st) {
-    radix_impl<uint64_t, int32_t>(k, v, ka, va, n, bits, s, st);
+    radix_impl<uint64_t, int32_t, true>(k, v, ka, va, n, 0, bits, s, st);
 }
 void radix_sort_u64_i64(uint64_t **k, int64_t **v, uint64_t **ka, int64_t **va, int64_t n, int bits, void *s,
                         hipStream_t st) {
-    radix_impl<uint64_t, int64_t>(k, v, ka, va, n, bits, s, st);
+    radix_impl<uint64_t, int64_t, true>(k, v, ka, va, n, 0, bits, s, st);
+}
+void radix_sort_u64_keys(uint64_t **k, uint64_t **ka, int64_t n, int lo, int bits, void *s, hipStream_t st) {
+    int32_t *nv = nullptr, *nva = nullptr;  // no values
+    radix_impl<uint64_t, int32_t, false>(k, &nv, ka, &nva, n, lo, bits, s, st);
 }
 
 // ------------------------------------------------------------------ host helpers

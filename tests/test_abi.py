@@ -69,6 +69,7 @@ def test_default_options(built):
     assert (o.bin_lane, o.bin_wave, o.bin_block, o.timing) == (0, 0, 0, 0)   # 0: tuned table
     assert (o.graph_sweeps, o.hub_stream, o.colour_tail) == (1, 2, 1)
     assert (o.hub_row_max, o.agg_max_keys, o.agg_tile, o.settle) == (0, 0, 0, 0)
+    assert (o.join, o.layout, o.pack_bits) == (0, 0, 0)
 
 
 def test_argument_errors_need_no_gpu(built):
@@ -87,7 +88,8 @@ def test_argument_errors_need_no_gpu(built):
                         ctypes.byref(bad)) == P.PLM_E_ARG
     for kw in (dict(max_sweeps=0), dict(graph_sweeps=2), dict(hub_stream=-1), dict(hub_stream=3), dict(colour_tail=2),
                dict(hub_row_max=-1), dict(hub_row_max=12289), dict(agg_max_keys=31), dict(agg_max_keys=1537),
-               dict(agg_tile=-1), dict(agg_tile=513)):
+               dict(agg_tile=-1), dict(agg_tile=513), dict(layout=2), dict(pack_bits=1), dict(pack_bits=63),
+               dict(pack_bits=-2)):
         bad = P.default_options(**kw)
         assert P.plm_create(ctypes.byref(c), 1, 0, off.ctypes.data, col.ctypes.data, None, 0, None,
                             ctypes.byref(bad)) == P.PLM_E_ARG, kw
