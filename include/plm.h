@@ -154,8 +154,9 @@ typedef struct {
                               a margin its gains cannot have lost to the community
                               volumes that changed meanwhile, keeps its community
                               without a new scan of its row.  0 (default): enabled
-                              once a sweep of the phase moved at most n/16 nodes;
-                              1: from the first sweep; -1: never.  Same results. */
+                              once a sweep of the phase moved at most n/16 nodes
+                              (n/64 on coarse levels); 1: from the first sweep;
+                              -1: never.  Same results. */
     int32_t join;          /* request servers (plm_server_create) only: k >= 1 =
                               continuous batching: a running batch takes queued
                               requests in at its first k level boundaries (each starts

@@ -43,7 +43,10 @@ constexpr double kReplanFraction = 0.7;
 // partitioned group's part launch), then start and stop of the agg launch
 constexpr size_t kEv = 12;
 // settled nodes: a move phase arms after a sweep that moved at most n / this
+// (input level, coarse levels); measured on R-MAT 26, arming at n / 64 on the
+// input level and at n / 16 on coarse levels each cost 40 ms more sweep time
 constexpr int64_t kSettleDiv = 16;
+constexpr int64_t kSettleDivCoarse = 64;
 // single graphs with more entries take the sweep layout by default (opt.layout = 0)
 constexpr int64_t kLayoutMinEntries = (int64_t)1 << 27;
 // pinned host scratch of a context, in int64 words (the colouring's counter
@@ -866,10 +869,12 @@ struct plm_ctx {
         const unsigned __int128 next = (unsigned __int128)(armed_sweeps + 1) * 2u * (uint64_t)S;
         if ((!skip_armed && opt.settle == 1) || (skip_armed && (next >> 63))) arm();
     }
-    // after them: arm once a sweep moved at most n / kSettleDiv nodes (opt.settle = 0)
+    // after them: arm once a sweep moved at most n / kSettleDiv nodes on the
+    // input level, n / kSettleDivCoarse on coarse levels (opt.settle = 0)
     void settle_after(int64_t moved) {
+        const int64_t div = cur == 0 ? kSettleDiv : kSettleDivCoarse;
         if (skip_armed) ++armed_sweeps;
-        else if (settle_usable() && opt.settle == 0 && moved * kSettleDiv <= L().n) arm();
+        else if (settle_usable() && opt.settle == 0 && moved * div <= L().n) arm();
     }
 
     // Move phase of the current level: sweeps until one moves nothing, at
