@@ -155,7 +155,7 @@ typedef struct {
                               volumes that changed meanwhile, keeps its community
                               without a new scan of its row.  0 (default): enabled
                               once a sweep of the phase moved at most n/16 nodes
-                              (n/64 on coarse levels); 1: from the first sweep;
+                              (n/1024 on coarse levels); 1: from the first sweep;
                               -1: never.  Same results. */
     int32_t join;          /* request servers (plm_server_create) only: k >= 1 =
                               continuous batching: a running batch takes queued

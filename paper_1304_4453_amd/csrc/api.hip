@@ -43,10 +43,11 @@ constexpr double kReplanFraction = 0.7;
 // partitioned group's part launch), then start and stop of the agg launch
 constexpr size_t kEv = 12;
 // settled nodes: a move phase arms after a sweep that moved at most n / this
-// (input level, coarse levels); measured on R-MAT 26, arming at n / 64 on the
-// input level and at n / 16 on coarse levels each cost 40 ms more sweep time
+// (input level, coarse levels); measured on R-MAT 26: arming at n / 64 on the
+// input level costs 45 ms more sweep time, and the coarse level's sweeps take
+// 1,675 / 1,625 / 1,601 / 1,575 ms arming at n / 16, 64, 256, 1024
 constexpr int64_t kSettleDiv = 16;
-constexpr int64_t kSettleDivCoarse = 64;
+constexpr int64_t kSettleDivCoarse = 1024;
 // single graphs with more entries take the sweep layout by default (opt.layout = 0)
 constexpr int64_t kLayoutMinEntries = (int64_t)1 << 27;
 // pinned host scratch of a context, in int64 words (the colouring's counter

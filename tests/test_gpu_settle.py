@@ -61,7 +61,7 @@ def test_stepwise_sweeps_planted_partition_settle(P):
 
 
 def test_stepwise_default_arming(P):
-    """settle = 0 arms after a sweep that moved at most n/16 nodes (n/64 on coarse levels)."""
+    """settle = 0 arms after a sweep that moved at most n/16 nodes (n/1024 on coarse levels)."""
     g = graphgen.rmat(13, 16, seed=4, weighted=True)
     stepwise(P, g, seed=1, per_class=False, settle=0, bin_lane=4, bin_wave=32, bin_block=256)
 
